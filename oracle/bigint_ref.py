@@ -1,0 +1,237 @@
+"""Pure-Python big-integer CKKS checker for tiny rings — TEST INFRASTRUCTURE ONLY.
+
+Referee for the C oracle.  Every operation is written directly over the big
+integers modulo Q = q_0 ... q_l (times P where the definition needs it), with
+schoolbook negacyclic products in Z[X]/(X^N + 1) — no NTT, no residue
+decomposition.  Limb residues only appear at the boundary (sampling and
+comparison).  Only usable for N <= 2^8 or so.
+
+SplitMix64 is implemented here a second time from its published definition
+(Steele, Lea and Flood, OOPSLA 2014): output i of the generator seeded with x
+is mix(x + (i + 1) * 0x9E3779B97F4A7C15 mod 2^64).
+"""
+from __future__ import annotations
+
+from typing import List, Sequence
+
+MASK64 = (1 << 64) - 1
+GAMMA = 0x9E3779B97F4A7C15
+
+
+def sm_mix(z: int) -> int:
+    z &= MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def splitmix_out(x: int, i: int) -> int:
+    return sm_mix((x + (i + 1) * GAMMA) & MASK64)
+
+
+def stream(seed: int, sid: int):
+    st = splitmix_out(seed, sid)
+    return lambda c: splitmix_out(st, c)
+
+
+def sample_ternary(seed: int, sid: int, N: int) -> List[int]:
+    w = stream(seed, sid)
+    return [w(i) % 3 - 1 for i in range(N)]
+
+
+def sample_hwt(seed: int, sid: int, N: int, h: int) -> List[int]:
+    w = stream(seed, sid)
+    out = [0] * N
+    got, c = 0, 0
+    while got < h:
+        x = w(c)
+        c += 1
+        pos = x % N
+        if out[pos]:
+            continue
+        out[pos] = -1 if x >> 63 else 1
+        got += 1
+    return out
+
+
+def sample_cbd(seed: int, sid: int, N: int) -> List[int]:
+    w = stream(seed, sid)
+    out = []
+    for i in range(N):
+        x = w(i)
+        out.append(bin(x & 0x1FFFFF).count("1") - bin((x >> 21) & 0x1FFFFF).count("1"))
+    return out
+
+
+def sample_uniform_residues(seed: int, sid: int, mi: int, q: int, N: int) -> List[int]:
+    w = stream(seed, sid)
+    return [((w(2 * (mi * N + i)) << 64) | w(2 * (mi * N + i) + 1)) % q for i in range(N)]
+
+
+# ---------------------------------------------------------------- big-int polynomials
+
+def crt(residues: Sequence[Sequence[int]], mods: Sequence[int]) -> List[int]:
+    """Combine limb residues into integers in [0, prod(mods))."""
+    Q = 1
+    for q in mods:
+        Q *= q
+    N = len(residues[0])
+    out = [0] * N
+    for r, q in zip(residues, mods):
+        Mi = Q // q
+        y = Mi * pow(Mi, -1, q)
+        for k in range(N):
+            out[k] += r[k] * y
+    return [v % Q for v in out]
+
+
+def to_residues(poly: Sequence[int], mods: Sequence[int]) -> List[List[int]]:
+    return [[v % q for v in poly] for q in mods]
+
+
+def polymul(a: Sequence[int], b: Sequence[int], mod: int) -> List[int]:
+    """Schoolbook negacyclic product in Z_mod[X]/(X^N + 1)."""
+    N = len(a)
+    out = [0] * N
+    for i in range(N):
+        ai = a[i]
+        if ai == 0:
+            continue
+        for j in range(N):
+            k = i + j
+            if k < N:
+                out[k] += ai * b[j]
+            else:
+                out[k - N] -= ai * b[j]
+    return [v % mod for v in out]
+
+
+def polyadd(a, b, mod):
+    return [(x + y) % mod for x, y in zip(a, b)]
+
+
+def centred(v: int, mod: int) -> int:
+    v %= mod
+    return v - mod if v > mod // 2 else v
+
+
+def round_div(c: Sequence[int], big: int, d: int, small: int) -> List[int]:
+    """round(c / d) for c taken centred mod `big`, reduced mod `small` (= big / d)."""
+    out = []
+    for v in c:
+        cv = centred(v, big)
+        # nearest integer to cv / d (d odd, no ties)
+        qd, r = divmod(cv, d)
+        if 2 * r > d:
+            qd += 1
+        out.append(qd % small)
+    return out
+
+
+def automorph(a: Sequence[int], g: int, mod: int) -> List[int]:
+    N = len(a)
+    out = [0] * N
+    for i, v in enumerate(a):
+        e = (i * g) % (2 * N)
+        if e < N:
+            out[e] = (out[e] + v) % mod
+        else:
+            out[e - N] = (out[e - N] - v) % mod
+    return out
+
+
+class BigCKKS:
+    """Tiny-ring CKKS over big integers with the same definitions as the oracle."""
+
+    def __init__(self, N: int, q: Sequence[int], P: int):
+        self.N = N
+        self.q = list(q)     # q_0 .. q_L
+        self.P = P
+        self.L = len(q) - 1
+
+    def Q(self, l: int) -> int:
+        out = 1
+        for i in range(l):
+            out *= self.q[i]
+        return out
+
+    def mods_qp(self) -> List[int]:
+        return self.q + [self.P]
+
+    # ---- keys
+    def secret(self, seed: int, h: int) -> List[int]:
+        return sample_hwt(seed, 1, self.N, h)
+
+    def uniform_poly_qp(self, seed: int, sid: int) -> List[int]:
+        """Uniform element of Z_{QP}[X] whose residue mod q_t (t <= L) and mod P (index L+1) is sampled."""
+        res = [sample_uniform_residues(seed, sid, t, m, self.N) for t, m in enumerate(self.mods_qp())]
+        return crt(res, self.mods_qp())
+
+    def uniform_poly_q(self, seed: int, sid: int) -> List[int]:
+        res = [sample_uniform_residues(seed, sid, t, m, self.N) for t, m in enumerate(self.q)]
+        return crt(res, self.q)
+
+    def public_key(self, s, seed: int):
+        QL = self.Q(self.L + 1)
+        a = self.uniform_poly_q(seed, 2)
+        e = sample_cbd(seed, 3, self.N)
+        b = polyadd([-v for v in polymul(a, s, QL)], e, QL)
+        return b, a
+
+    def switching_key(self, s, s_prime, seed: int, sid_base: int):
+        """ksk_j = (-a_j s + e_j + P * g_j * s', a_j) mod Q_L P with g_j the CRT indicator of q_j."""
+        QL = self.Q(self.L + 1)
+        QP = QL * self.P
+        keys = []
+        for j in range(self.L + 1):
+            a = self.uniform_poly_qp(seed, sid_base + 2 * j)
+            e = sample_cbd(seed, sid_base + 2 * j + 1, self.N)
+            Mj = QL // self.q[j]
+            gj = Mj * pow(Mj, -1, self.q[j])
+            t = polymul(a, s, QP)
+            b = [(-t[k] + e[k] + self.P * gj * s_prime[k]) % QP for k in range(self.N)]
+            keys.append((b, a))
+        return keys
+
+    # ---- encryption
+    def encrypt(self, pk, m: Sequence[int], l: int, seed: int):
+        Ql = self.Q(l)
+        v = sample_ternary(seed, 1, self.N)
+        e0 = sample_cbd(seed, 2, self.N)
+        e1 = sample_cbd(seed, 3, self.N)
+        c0 = [(x + y + z) % Ql for x, y, z in zip(polymul(v, pk[0], Ql), m, e0)]
+        c1 = [(x + y) % Ql for x, y in zip(polymul(v, pk[1], Ql), e1)]
+        return c0, c1
+
+    def decrypt(self, ct, s, l: int) -> List[int]:
+        Ql = self.Q(l)
+        m = polyadd(ct[0], polymul(ct[1], s, Ql), Ql)
+        return [centred(v, Ql) for v in m]
+
+    # ---- evaluation
+    def tensor(self, a, b, l: int):
+        Ql = self.Q(l)
+        d0 = polymul(a[0], b[0], Ql)
+        d1 = polyadd(polymul(a[0], b[1], Ql), polymul(a[1], b[0], Ql), Ql)
+        d2 = polymul(a[1], b[1], Ql)
+        return d0, d1, d2
+
+    def keyswitch(self, d: Sequence[int], keys, l: int):
+        """round( sum_{j < l} [d]_{q_j} * ksk_j / P ) mod Q_l, with the key restricted to Q_l P."""
+        Ql = self.Q(l)
+        QP = Ql * self.P
+        acc0 = [0] * self.N
+        acc1 = [0] * self.N
+        for j in range(l):
+            dj = [v % self.q[j] for v in d]
+            b, a = keys[j]
+            t0 = polymul(dj, [v % QP for v in b], QP)
+            t1 = polymul(dj, [v % QP for v in a], QP)
+            acc0 = polyadd(acc0, t0, QP)
+            acc1 = polyadd(acc1, t1, QP)
+        return round_div(acc0, QP, self.P, Ql), round_div(acc1, QP, self.P, Ql)
+
+    def rescale(self, ct, l: int):
+        Ql = self.Q(l)
+        ql = self.q[l - 1]
+        return tuple(round_div(c, Ql, ql, Ql // ql) for c in ct)

@@ -1,0 +1,343 @@
+"""Encrypted modified semi-parallel GWAS on the CPU oracle — TEST INFRASTRUCTURE ONLY.
+
+Follows Alg. "Semi Parallel GWAS" (with Alg. "Homomorphic LogReg" and
+Alg. "inverseSlots") step by step on oracle ciphertexts.  Layouts:
+
+* R = PO2(n) rows per block, B = N / (2R) blocks per ciphertext (N/2 slots).
+* Per-sample vectors (covariate columns x_j, y) are R-periodic: slot s holds
+  v[s mod R] when s mod R < n, else 0 — a CP column (Methods, "Column-Packed
+  Matrices") already duplicated into every block (Alg. Duplicate done by the
+  client).  On such data the rotate-and-sum of Alg. DotProd over log2(R) left
+  rotations leaves the full dot product in every slot.
+* Entries of A = (X^T X)^-1 are replicated scalars (the same value in every slot).
+* A SNP batch is a CCP matrix (Methods, "Column-Compact-Packed Matrices") with
+  two SNPs per complex slot (Methods, "Complex Space of CKKS ciphertext"):
+  slot c R + r holds S[r, 2c] + i S[r, 2c+1] of that batch, tau = N / R SNPs per
+  ciphertext (eq. numSNPinBatch read as 2 (N/2) / R).
+
+The projection M S = S - X (A (X^T S)) is evaluated through associativity
+(eqs. M, Sprime) as S' = S - sum_j x_j (.) bcast(mask (.) colSum(r_j (.) S)) with
+r_j = sum_l A_jl x_l, so that M is never materialised.
+
+Depth plan (kappa >= 2; D_p = 7 (kappa - 1)): beta^(1) at 2, each further
+Newton pass adds 7 levels (eta, 4 for sigma7, g, beta); w at D_p + 1,
+w^-1 at D_p + 5, z at D_p + 6, z' at D_p + 9, u = w z' at D_p + 10; SNP batches
+are encrypted at D_S = D_p + 7, S' at D_S + 3, num at D_S + 4 and the two
+denominators at D_S + 5 = 7 kappa + 5 = L.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import ckks as C
+from .gwas_fp64 import SIGMA7_C1, SIGMA7_C3, SIGMA7_C5, SIGMA7_C7, xtx_inverse
+
+
+def circuit_depth(kappa: int) -> int:
+    """Number of rescales (L) the circuit consumes for kappa Newton passes."""
+    if kappa < 2:
+        raise ValueError("the encrypted circuit needs kappa >= 2 (kappa = 1 leaves p = 1/2 public)")
+    return 7 * kappa + 5
+
+
+def snp_depth(kappa: int) -> int:
+    return 7 * (kappa - 1) + 7
+
+
+@dataclass
+class Layout:
+    N: int
+    n: int
+    k: int
+    m: int
+    R: int
+
+    @property
+    def blocks(self) -> int:
+        return self.N // (2 * self.R)
+
+    @property
+    def tau(self) -> int:
+        return 2 * self.blocks
+
+    @property
+    def n_batches(self) -> int:
+        return -(-self.m // self.tau)
+
+    @property
+    def log_r(self) -> int:
+        return self.R.bit_length() - 1
+
+
+def make_layout(N: int, n: int, k: int, m: int) -> Layout:
+    R = 1
+    while R < n:
+        R *= 2
+    if 2 * R > N:
+        raise ValueError("n too large for the ring: need PO2(n) <= N/2")
+    return Layout(N=N, n=n, k=k, m=m, R=R)
+
+
+def periodic_slots(v: np.ndarray, lay: Layout) -> np.ndarray:
+    z = np.zeros(lay.N // 2, dtype=np.complex128)
+    s = np.arange(lay.N // 2)
+    r = s % lay.R
+    ok = r < lay.n
+    z[ok] = v[r[ok]]
+    return z
+
+
+def snp_batch_slots(S: np.ndarray, lay: Layout, b: int) -> np.ndarray:
+    z = np.zeros(lay.N // 2, dtype=np.complex128)
+    for c in range(lay.blocks):
+        j0 = b * lay.tau + 2 * c
+        base = c * lay.R
+        if j0 < lay.m:
+            z[base:base + lay.n] += S[:, j0].astype(np.float64)
+        if j0 + 1 < lay.m:
+            z[base:base + lay.n] += 1j * S[:, j0 + 1].astype(np.float64)
+    return z
+
+
+def a_pairs(k: int):
+    return [(j, l) for j in range(k) for l in range(j, k)]
+
+
+def constant_poly(c: float, N: int, scale: float) -> np.ndarray:
+    """Exact encoding of a replicated real scalar: round_half_away(c * scale) at X^0."""
+    m = np.zeros(N, dtype=np.int64)
+    m[0] = C.round_half_away(c * scale)
+    return m
+
+
+@dataclass
+class EncInput:
+    lay: Layout
+    kappa: int
+    x: List[C.Ct]
+    y: C.Ct
+    A: Dict[tuple, C.Ct]
+    S: List[C.Ct]
+
+    def a(self, j: int, l: int) -> C.Ct:
+        return self.A[(j, l) if j <= l else (l, j)]
+
+
+@dataclass
+class Plaintexts:
+    """Integer plaintext polynomials of every input ciphertext, in encryption order."""
+    polys: List[np.ndarray]
+    depths: List[int]
+
+
+def encode_inputs(params: C.Params, X: np.ndarray, y: np.ndarray, S: np.ndarray, kappa: int) -> Plaintexts:
+    """Client-side encoding (oracle encoder, FP64) of x_j, y, A_jl and the SNP batches."""
+    n, k = X.shape
+    lay = make_layout(params.N, n, k, S.shape[1])
+    A = xtx_inverse(X)
+    polys, depths = [], []
+    for j in range(k):
+        polys.append(C.encode(periodic_slots(X[:, j], lay), params.N, params.scales[0]))
+        depths.append(0)
+    polys.append(C.encode(periodic_slots(y, lay), params.N, params.scales[0]))
+    depths.append(0)
+    for (j, l) in a_pairs(k):
+        polys.append(constant_poly(A[j, l], params.N, a_scale(params, lay)))
+        depths.append(0)
+    ds = snp_depth(kappa)
+    for b in range(lay.n_batches):
+        polys.append(C.encode(snp_batch_slots(S, lay, b), params.N, params.scales[ds]))
+        depths.append(ds)
+    return Plaintexts(polys=polys, depths=depths)
+
+
+def a_scale(params: C.Params, lay: Layout) -> float:
+    """Entries of (X^T X)^-1 are O(1/n); they are encrypted at depth 0 with scale R * Delta_0 so that
+    their integer content stays well above the noise, and reach the canonical scale by alignment."""
+    return params.scales[0] * float(lay.R)
+
+
+def input_seed(enc_seed: int, i: int) -> int:
+    """Encryption seed of input ciphertext i: output number i of SplitMix64 seeded with enc_seed."""
+    return int(C.lib().ref_splitmix_out(enc_seed, i))
+
+
+def encrypt_inputs(o: C.Oracle, pts: Plaintexts, n: int, k: int, m: int, kappa: int, enc_seed: int) -> EncInput:
+    p = o.p
+    lay = make_layout(p.N, n, k, m)
+    scales = [p.scales[d] for d in pts.depths]
+    for i in range(k + 1, k + 1 + len(a_pairs(k))):
+        scales[i] = a_scale(p, lay)
+    cts = [o.encrypt(pt, d, s, input_seed(enc_seed, i)) for i, (pt, d, s) in enumerate(zip(pts.polys, pts.depths, scales))]
+    x = cts[:k]
+    yc = cts[k]
+    pairs = a_pairs(k)
+    A = {pr: cts[k + 1 + i] for i, pr in enumerate(pairs)}
+    S = cts[k + 1 + len(pairs):]
+    return EncInput(lay=lay, kappa=kappa, x=x, y=yc, A=A, S=S)
+
+
+def required_galois(N: int, R: int) -> List[int]:
+    """Left and right power-of-two rotations below R (Methods, power-of-two rotations) and conjugation."""
+    out = []
+    i = 1
+    while i < R:
+        out.append(C.galois_rotate(N, i))
+        out.append(C.galois_rotate(N, -i))
+        i *= 2
+    out.append(C.galois_conj(N))
+    return out
+
+
+@dataclass
+class EncOutput:
+    beta: List[C.Ct]
+    w: C.Ct
+    w_inv: C.Ct
+    z_proj: C.Ct
+    u: C.Ct
+    S_proj: List[C.Ct]
+    num: List[C.Ct]
+    den_even: List[C.Ct]
+    den_odd: List[C.Ct]
+
+
+class Circuit:
+    def __init__(self, o: C.Oracle, lay: Layout):
+        self.o = o
+        self.lay = lay
+        self.sc = o.p.scales
+
+    # canonical-scale helpers
+    def at(self, a: C.Ct, d: int, factor: float = 1.0) -> C.Ct:
+        """a brought to depth d at the canonical scale; factor scales the value (exact powers of two)."""
+        if d == a.depth and factor == 1.0:
+            return a
+        return self.o.align(a, d, self.sc[d], factor)
+
+    def rot_sum(self, a: C.Ct) -> C.Ct:
+        """a <- a + Rot(a, 2^i) for i < log2 R (Alg. colSum / Alg. DotProd)."""
+        o = self.o
+        i = 1
+        while i < self.lay.R:
+            a = o.add(a, o.rotate(a, i))
+            i *= 2
+        return a
+
+    def bcast(self, a: C.Ct) -> C.Ct:
+        """a <- a + Rot(a, -2^i) for i < log2 R: copies each block's first slot over its block."""
+        o = self.o
+        i = 1
+        while i < self.lay.R:
+            a = o.add(a, o.rotate(a, -i))
+            i *= 2
+        return a
+
+    def sigma7(self, u: C.Ct) -> C.Ct:
+        """sigma7 for u = eta / 8 at canonical scale; 4 levels (eq. sigma7, sign-corrected)."""
+        o = self.o
+        d = u.depth
+        u2 = o.mul(u, u)
+        a1 = o.add_const(o.mul_const(u2, -SIGMA7_C3), SIGMA7_C1)
+        a2 = o.add_const(o.mul_const(u2, -SIGMA7_C7), SIGMA7_C5)
+        u4 = o.mul(u2, u2)
+        b = o.mul(u4, a2)
+        cc = o.add(self.at(a1, d + 3), b)
+        return o.add_const(o.mul(self.at(u, d + 3), cc), 0.5)
+
+    def run(self, inp: EncInput) -> EncOutput:
+        o = self.o
+        lay = self.lay
+        k = lay.k
+        x, y = inp.x, inp.y
+        # ---- Alg. Homomorphic LogReg, pass 1: beta = 0 so p = sigma7(0) = 1/2 is public
+        r = o.add_const(y, -0.5)
+        g = [self.rot_sum(o.mul(x[j], r)) for j in range(k)]
+        beta = [o.mul_int(o.mul_sum([(self.at(inp.a(j, l), 1), g[l]) for l in range(k)]), 4) for j in range(k)]
+        p = None
+        for _t in range(1, inp.kappa):
+            d = beta[0].depth
+            # u = X beta / 8: the 1/8 of sigma7's argument is folded into the alignment of x_j
+            u = o.mul_sum([(self.at(x[j], d, 0.125), beta[j]) for j in range(k)])
+            p = self.sigma7(u)
+            dp = p.depth
+            r = o.sub(self.at(y, dp), p)
+            g = [self.rot_sum(o.mul(self.at(x[j], dp), r)) for j in range(k)]
+            dg = g[0].depth
+            inc = [o.mul_int(o.mul_sum([(self.at(inp.a(j, l), dg), g[l]) for l in range(k)]), 4) for j in range(k)]
+            beta = [o.add(self.at(beta[j], inc[j].depth), inc[j]) for j in range(k)]
+        # ---- w = p (1 - p) and Alg. inverseSlots (guess 3, three Newton steps; the first is 6 - 9 w)
+        dp = p.depth
+        w = o.mul(p, o.add_const(o.neg(p), 1.0))
+        gi = o.add_const(o.mul_int(w, -9), 6.0)
+        for _ in range(2):
+            wg = o.mul(self.at(w, gi.depth), gi)
+            h = o.add_const(o.neg(wg), 2.0)
+            gi = o.mul(self.at(gi, h.depth), h)
+        w_inv = gi
+        # ---- z = X beta^(kappa) + w^-1 (y - p^(kappa-1))
+        db = beta[0].depth
+        xb = o.mul_sum([(self.at(x[j], db), beta[j]) for j in range(k)])
+        t = o.mul(self.at(r, w_inv.depth), w_inv)
+        z = o.add(self.at(xb, t.depth), t)
+        # ---- z' = M z = z - X (A (X^T z))
+        h = [self.rot_sum(o.mul(self.at(x[j], z.depth), z)) for j in range(k)]
+        dh = h[0].depth
+        v = [o.mul_sum([(self.at(inp.a(j, l), dh), h[l]) for l in range(k)]) for j in range(k)]
+        dv = v[0].depth
+        xv = o.mul_sum([(self.at(x[j], dv), v[j]) for j in range(k)])
+        z_proj = o.sub(self.at(z, xv.depth), xv)
+        u = o.mul(self.at(w, z_proj.depth), z_proj)
+        # ---- r_j = (X A)_{:, j} for the projection of the SNP batches
+        rr = [o.mul_sum([(self.at(inp.a(j, l), 1), self.at(x[l], 1)) for l in range(k)]) for j in range(k)]
+        # ---- per-batch part (Alg. Semi Parallel GWAS, batch loop)
+        S_proj, nums, dens_e, dens_o = [], [], [], []
+        for S in inp.S:
+            ds = S.depth
+            cs = []
+            for j in range(k):
+                pj = o.mul(self.at(rr[j], ds), S)
+                cj = self.rot_sum(pj)                 # column sums at block starts (Alg. colSum)
+                cj = o.mul_mask(cj, lay.R)            # keep block starts only
+                cs.append(self.bcast(cj))             # (A X^T S)_{j, c} over block c
+            dc = cs[0].depth
+            xe = o.mul_sum([(self.at(x[j], dc), cs[j]) for j in range(k)])
+            sp = o.sub(self.at(S, xe.depth), xe)
+            dsp = sp.depth
+            num = self.rot_sum(o.mul(self.at(u, dsp), sp))
+            ws = o.mul(self.at(w, dsp), sp)
+            sc = o.conjugate(sp)
+            wss = o.mul(ws, self.at(sp, ws.depth))
+            wsc = o.mul(ws, self.at(sc, ws.depth))
+            de = self.rot_sum(o.set_scale(o.add(wsc, wss), 2.0))
+            do = self.rot_sum(o.set_scale(o.sub(wsc, wss), 2.0))
+            S_proj.append(sp)
+            nums.append(num)
+            dens_e.append(de)
+            dens_o.append(do)
+        return EncOutput(beta=beta, w=w, w_inv=w_inv, z_proj=z_proj, u=u, S_proj=S_proj,
+                         num=nums, den_even=dens_e, den_odd=dens_o)
+
+
+def finalize(o: C.Oracle, lay: Layout, out: EncOutput):
+    """Client side: decrypt num / den separately, b' = num / den, err' = 1 / den (Alg. Semi Parallel GWAS)."""
+    num = np.zeros(lay.n_batches * lay.tau)
+    den = np.zeros(lay.n_batches * lay.tau)
+    starts = np.arange(lay.blocks) * lay.R
+    for b in range(lay.n_batches):
+        zn = o.decrypt(out.num[b])[starts]
+        ze = o.decrypt(out.den_even[b])[starts]
+        zo = o.decrypt(out.den_odd[b])[starts]
+        base = b * lay.tau
+        num[base:base + lay.tau:2] = zn.real
+        num[base + 1:base + lay.tau:2] = zn.imag
+        den[base:base + lay.tau:2] = ze.real
+        den[base + 1:base + lay.tau:2] = zo.real
+    num, den = num[:lay.m], den[:lay.m]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        b = num / den
+        err = 1.0 / den
+    return num, den, b, err, np.sqrt(err)

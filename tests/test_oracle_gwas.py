@@ -1,0 +1,137 @@
+"""Pins of the FP64 GWAS oracle and of the encrypted circuit on the CPU oracle (no GPU)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ckks as C
+from oracle import gwas_circuit as G
+from oracle import gwas_fp64 as F
+from synth import config_seed, make_gwas_data
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _golden():
+    with open(os.path.join(ROOT, "tests", "golden", "paper_values.json")) as f:
+        return json.load(f)
+
+
+def test_sigma7_coefficients_and_sign_reading():
+    g = _golden()["sigma7_coefficients"]
+    assert (F.SIGMA7_C1, F.SIGMA7_C3, F.SIGMA7_C5, F.SIGMA7_C7) == (g["c1"], g["c3"], g["c5"], g["c7"])
+    x = np.linspace(-8, 8, 2001)
+    sig = 1 / (1 + np.exp(-x))
+    # sign-corrected polynomial approximates the sigmoid on [-8, 8]; the printed one is its mirror image
+    assert np.max(np.abs(F.sigma7(x) - sig)) < 0.033
+    assert np.allclose(F.sigma7_printed(x), F.sigma7(-x))
+    assert F.sigma7(np.array([0.0]))[0] == g["constant"]
+    # closed form at x = 8 (u = 1)
+    assert abs(F.sigma7(np.array([8.0]))[0] - (0.5 + g["c1"] - g["c3"] + g["c5"] - g["c7"])) < 1e-15
+
+
+def test_inverse_slots_closed_form():
+    g = _golden()["inverse_slots"]
+    w = np.linspace(1e-3, g["w_upper_bound"], 500)
+    got = F.inverse_slots(w, g["iterations"], g["guess"])
+    # Newton from g0 = 3: 1 - w g_k = (1 - 3 w)^(2^k)
+    assert np.allclose(got, (1 - (1 - 3 * w) ** 8) / w, rtol=1e-12, atol=0)
+    assert abs(F.inverse_slots(np.array([0.25]))[0] * 0.25 - 1) < 2e-5
+
+
+def test_complex_packing_identities():
+    rng = np.random.default_rng(0)
+    x, y = rng.standard_normal(100), rng.standard_normal(100)
+    z = x + 1j * y
+    assert np.allclose(((z * np.conj(z) + z * z) / 2).real, x * x)
+    assert np.allclose(((z * np.conj(z) - z * z) / 2).real, y * y)
+
+
+@pytest.fixture(scope="module")
+def data():
+    return make_gwas_data(245, 4, 33, seed=config_seed(1))
+
+
+def test_projection_invariants(data):
+    r = F.modified_gwas(data.X, data.y, data.S, 3)
+    X = data.X
+    scale = np.max(np.abs(X.T @ data.S.astype(float)))
+    assert np.max(np.abs(X.T @ r.S_proj)) < 1e-10 * scale
+    assert np.max(np.abs(X.T @ r.z_proj)) < 1e-10 * np.max(np.abs(X.T @ r.z))
+    A = F.xtx_inverse(X)
+    M = np.eye(X.shape[0]) - X @ A @ X.T
+    assert np.allclose(M, M.T, atol=1e-12)
+    assert np.allclose(M @ M, M, atol=1e-10)
+    assert np.allclose(A @ (X.T @ X), np.eye(X.shape[1]), atol=1e-10)
+    # the packed (two SNPs per complex slot) numerator / denominator equal the plain ones
+    num, den = F.packed_num_den(r.w, r.z_proj, r.S_proj)
+    assert np.allclose(num, r.num, rtol=1e-12, atol=1e-9)
+    assert np.allclose(den, r.den, rtol=1e-12)
+    # z' does not depend on beta (M X = 0): with beta's sign flipped it is the same
+    z2 = -X @ r.beta + r.w_inv * (data.y - r.p)
+    assert np.allclose(z2 - X @ (A @ (X.T @ z2)), r.z_proj, atol=1e-9)
+
+
+def test_fixed_hessian_newton_converges_to_mle(data):
+    X, y = data.X, data.y
+    A = F.xtx_inverse(X)
+    beta = np.zeros(X.shape[1])
+    for _ in range(300):
+        p = F.sigmoid(X @ beta)
+        beta = beta + 4 * A @ (X.T @ (y - p))
+    assert np.allclose(beta, F.irls_logreg(X, y), atol=1e-8)
+
+
+def test_sikorska_close_to_brute_force():
+    d = make_gwas_data(120, 3, 8, seed=5)
+    b_sp, err = F.sikorska_gwas(d.X, d.y, d.S)
+    b_bf, se_bf = F.per_snp_logreg(d.X, d.y, d.S)
+    # a one-step score approximation of the per-SNP fits: close, not equal
+    assert np.max(np.abs(b_sp - b_bf) / np.maximum(se_bf, 1e-9)) < 0.2
+    assert np.allclose(np.sqrt(err), se_bf, rtol=0.2)
+
+
+def test_modified_gwas_tracks_exact_semi_parallel(data):
+    r = F.modified_gwas(data.X, data.y, data.S, 3)
+    b_sp, err = F.sikorska_gwas(data.X, data.y, data.S)
+    ok = np.isfinite(r.b)
+    assert np.corrcoef(r.b[ok], b_sp[ok])[0, 1] > 0.95
+
+
+@pytest.mark.slow
+def test_encrypted_circuit_on_oracle_matches_fp64_small():
+    """The whole encrypted circuit on the oracle (N = 2^10, 40-bit scale) against the FP64 GWAS."""
+    n, k, m, kappa = 30, 4, 70, 3
+    p = C.make_params(10, G.circuit_depth(kappa), 40)
+    d = make_gwas_data(n, k, m, seed=77)
+    lay = G.make_layout(p.N, n, k, m)
+    assert lay.n_batches == 3 and m % lay.tau != 0       # ragged last batch
+    o = C.Oracle(p)
+    o.keygen(7, G.required_galois(p.N, lay.R))
+    pts = G.encode_inputs(p, d.X, d.y, d.S, kappa)
+    inp = G.encrypt_inputs(o, pts, n, k, m, kappa, 11)
+    out = G.Circuit(o, lay).run(inp)
+    assert out.den_even[0].depth == p.L and out.num[0].depth == p.L - 1
+    num, den, b, err, se = G.finalize(o, lay, out)
+    ref = F.modified_gwas(d.X, d.y, d.S, kappa)
+    tol = np.maximum(np.abs(ref.b), ref.se)
+    assert np.max(np.abs(b - ref.b) / tol) < 1e-4
+    beta = np.array([o.decrypt(c)[0].real for c in out.beta])
+    assert np.allclose(beta, ref.beta, atol=1e-5)
+
+
+@pytest.mark.slow
+def test_encrypted_circuit_on_oracle_config1_accuracy():
+    """Workload n=245, k=4, m=32, N=2^13, scale 2^30: decrypted b' within 1e-3 of the FP64 GWAS."""
+    n, k, m, kappa = 245, 4, 32, 3
+    p = C.make_params(13, G.circuit_depth(kappa), 30)
+    d = make_gwas_data(n, k, m, seed=config_seed(1))
+    lay = G.make_layout(p.N, n, k, m)
+    o = C.Oracle(p)
+    o.keygen(7, G.required_galois(p.N, lay.R))
+    inp = G.encrypt_inputs(o, G.encode_inputs(p, d.X, d.y, d.S, kappa), n, k, m, kappa, 11)
+    out = G.Circuit(o, lay).run(inp)
+    num, den, b, err, se = G.finalize(o, lay, out)
+    ref = F.modified_gwas(d.X, d.y, d.S, kappa)
+    assert np.max(np.abs(b - ref.b) / np.maximum(np.abs(ref.b), ref.se)) < 1e-3
