@@ -1,0 +1,228 @@
+/*
+ * gwas_ckks.h — C ABI of the MI355X RNS-CKKS evaluator and the encrypted
+ * modified semi-parallel GWAS of Sim, Chan, Chen, Tan and Aung, "Achieving
+ * GWAS with Homomorphic Encryption" (arXiv 1902.04303).
+ *
+ * Conventions
+ *   - Every function returns 0 (CKKS_OK) or a negative CKKS_E_* code; no
+ *     exception or abort crosses this boundary.  ckks_last_error() returns a
+ *     thread-local message for the last failure of the calling thread.
+ *   - Handles are opaque.  A context owns its tables, its device memory pool and
+ *     every key, plaintext and ciphertext created from it; destroying the
+ *     context frees all of them.  A context is not thread-safe: use one per host
+ *     thread or stream.
+ *   - Device work is enqueued on the HIP stream given to ckks_ctx_create (NULL:
+ *     the null stream).  Functions that hand data to the host synchronise that
+ *     stream; the others return with work still queued.
+ *   - Host buffers are owned by the caller.  Device memory comes from the
+ *     context's pool, which takes slabs from the allocator callbacks given at
+ *     creation (NULL: hipMalloc / hipFree).
+ *   - Polynomial data crosses the boundary in the canonical form: coefficient
+ *     domain, standard representatives in [0, q_i), laid out [poly][limb][coeff]
+ *     (a ciphertext is [2][limbs][N] uint64).
+ *   - "Depth" d counts rescales from a fresh top-level ciphertext; a ciphertext
+ *     at depth d has L + 1 - d limbs q_0 .. q_{L-d}.
+ */
+#ifndef GWAS_CKKS_H
+#define GWAS_CKKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CKKS_OK = 0,
+    CKKS_E_INVALID_ARG = -1,    /* bad pointer, size or value */
+    CKKS_E_PARAM_MISMATCH = -2, /* operands differ in context, depth or scale */
+    CKKS_E_LEVEL = -3,          /* not enough levels left for the operation or circuit */
+    CKKS_E_KEY_MISSING = -4,    /* a needed relinearisation / Galois key was not generated */
+    CKKS_E_NOMEM = -5,          /* device memory (or the pool budget) exhausted */
+    CKKS_E_HIP = -6,            /* a HIP runtime call failed */
+    CKKS_E_CANCELLED = -7,      /* a job was cancelled before it completed */
+    CKKS_E_NOT_READY = -8       /* a submitted job has not finished yet */
+};
+
+typedef struct ckks_ctx ckks_ctx;
+typedef struct ckks_ct ckks_ct;
+typedef struct gwas_enc_input gwas_enc_input;
+typedef struct gwas_enc_output gwas_enc_output;
+typedef struct gwas_server gwas_server;
+
+/* Parameters (the RNS reading of the scheme parameters of the paper's Methods,
+ * "Homomorphic Encryption": ring dimension N, levels L, scale).  The prime
+ * chain is derived from them by a fixed rule: q_0 is the largest prime below
+ * 2^60 and P the largest below 2^62 that are 1 mod 2N; the L rescale primes are
+ * chosen greedily from the 4L primes 1 mod 2N nearest 2^log2_scale so that the
+ * canonical scales Delta_{d+1} = Delta_d^2 / q_{L-d} stay near 2^log2_scale. */
+typedef struct {
+    int log_n;          /* log2 N, 10 <= log_n <= 17 */
+    int levels;         /* L >= 1: number of rescale primes */
+    int log2_scale;     /* base scale Delta_0 = 2^log2_scale, 20 <= . <= 50 */
+} ckks_params;
+
+/* Device allocator callbacks (e.g. torch's caching allocator).  alloc returns
+ * NULL on failure; user is passed back unchanged. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, size_t bytes, void *user);
+    void *user;
+} ckks_allocator;
+
+const char *ckks_last_error(void);
+
+/* Host only (no device work): the prime chain q_0..q_L, P (moduli: L + 2 entries)
+ * and the canonical scales Delta_0..Delta_L (scales: L + 1 entries). */
+int ckks_chain(const ckks_params *params, uint64_t *moduli, double *scales);
+
+/* ---------------------------------------------------------------- context */
+
+/* Build the prime chain and NTT tables and upload them.  allocator and
+ * hip_stream may be NULL.  pool_budget_bytes caps the device memory the pool
+ * may hold (0: no cap). */
+int ckks_ctx_create(const ckks_params *params, const ckks_allocator *allocator, void *hip_stream,
+                    size_t pool_budget_bytes, ckks_ctx **out);
+void ckks_ctx_destroy(ckks_ctx *ctx);
+
+/* Chain moduli: q[0..L] then P (caller array of L + 2 entries). */
+int ckks_ctx_moduli(const ckks_ctx *ctx, uint64_t *moduli, int cap);
+/* Canonical scales Delta_0..Delta_L (caller array of L + 1 entries). */
+int ckks_ctx_scales(const ckks_ctx *ctx, double *scales, int cap);
+/* Pool statistics: bytes in use, bytes cached, peak bytes, allocator calls. */
+int ckks_ctx_pool_stats(const ckks_ctx *ctx, size_t *in_use, size_t *cached, size_t *peak, size_t *n_alloc);
+/* Release cached pool slabs back to the allocator. */
+int ckks_ctx_pool_trim(ckks_ctx *ctx);
+
+/* ---------------------------------------------------------------- keys */
+
+/* KeyGen (paper: Methods, "Homomorphic Encryption", KeyGen), RNS form with one
+ * special prime P.  s has h = min(64, N/2) coefficients in {-1, 1} (HWT(h)),
+ * pk = (-a s + e, a) mod Q_L, and a switching key for s' has digits
+ * j = 0..L:  (-a_j s + e_j + [t = j] P s', a_j) mod q_t and P.
+ * A relinearisation key (s' = s^2) is always made; one Galois key is made per
+ * element of galois[] (s' = s(X^g), g odd in [3, 2N)).  seed != 0 selects the
+ * test-only deterministic generator (counter-based SplitMix64); seed == 0 draws
+ * the seed from the OS.  Keys stay resident on the device. */
+int ckks_keygen(ckks_ctx *ctx, uint64_t seed, const uint64_t *galois, int n_galois);
+/* Galois element of a left rotation by r slots (slot j <- slot j + r), 5^r mod 2N; r may be negative. */
+uint64_t ckks_galois_rotate(const ckks_ctx *ctx, int64_t r);
+/* Galois element of complex conjugation, 2N - 1. */
+uint64_t ckks_galois_conj(const ckks_ctx *ctx);
+/* Copy out a key in canonical coefficient form.  key_id 0 is the relinearisation
+ * key, otherwise a Galois element; buf holds [2][L+1][L+2][N] words (targets
+ * q_0..q_L then P). Secret: [N] int64; public key: [2][L+1][N]. */
+int ckks_export_switching_key(ckks_ctx *ctx, uint64_t key_id, uint64_t *buf, size_t cap_words);
+int ckks_export_secret(ckks_ctx *ctx, int64_t *buf, size_t cap);
+int ckks_export_public_key(ckks_ctx *ctx, uint64_t *buf, size_t cap_words);
+
+/* ---------------------------------------------------------------- encode / encrypt / decrypt */
+
+/* Encode (paper: Methods, Encode): integer polynomial round(scale * sigma^-1(z)),
+ * slot j <-> evaluation at zeta^(5^j mod 2N), zeta = exp(i pi / N).  re/im hold
+ * n <= N/2 slots (the rest are 0; im may be NULL).  FP64 on the host. */
+int ckks_encode(ckks_ctx *ctx, const double *re, const double *im, size_t n, double scale, int64_t *coeffs_out);
+/* Decode of a real polynomial given as doubles (m_i / scale already applied). */
+int ckks_decode(ckks_ctx *ctx, const double *coeffs, double *re, double *im);
+
+/* Encrypt (paper: Encrypt): ct = v pk + (m + e0, e1) at depth `depth` with tracked
+ * scale `scale`; m is an integer polynomial (N int64 coefficients).  v is
+ * ternary, e0, e1 centred binomial (eta = 21); seed as for keygen. */
+int ckks_encrypt(ckks_ctx *ctx, const int64_t *m, int depth, double scale, uint64_t seed, ckks_ct **out);
+/* Decrypt (paper: Decrypt) ciphertext `index` of a batch: c0 + c1 s, centred over
+ * q_0 q_1 (over q_0 when one limb is left), divided by the tracked scale and
+ * decoded into N/2 slots (re, im: caller arrays of N/2 doubles; im may be NULL). */
+int ckks_decrypt(ckks_ctx *ctx, const ckks_ct *ct, int index, double *re, double *im);
+/* Decrypt to the centred integer polynomial c0 + c1 s (N doubles, not scaled). */
+int ckks_decrypt_poly(ckks_ctx *ctx, const ckks_ct *ct, int index, double *coeffs);
+
+/* ---------------------------------------------------------------- ciphertexts
+ * A ckks_ct handle is a batch of `count` ciphertexts at one depth and scale,
+ * stored [count][2][limbs][N] on the device; operations on two batches pair them
+ * element-wise, and a batch of one broadcasts against a larger batch. */
+
+int ckks_ct_info(const ckks_ct *ct, int *count, int *depth, int *limbs, double *scale);
+/* Canonical export of ciphertext `index` of the batch: [2][limbs][N] words. */
+int ckks_ct_export(ckks_ctx *ctx, const ckks_ct *ct, int index, uint64_t *buf, size_t cap_words);
+/* Import of a canonical ciphertext at `depth` (limbs = L + 1 - depth). */
+int ckks_ct_import(ckks_ctx *ctx, const uint64_t *buf, int depth, double scale, ckks_ct **out);
+void ckks_ct_free(ckks_ct *ct);
+
+/* ---------------------------------------------------------------- evaluation (each a device operation) */
+
+/* Add / Sub (paper: Add): operands at equal depth and tracked scale. */
+int ckks_add(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out);
+int ckks_sub(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out);
+/* Multiply by a signed integer (no level consumed). */
+int ckks_mul_int(ckks_ctx *ctx, const ckks_ct *a, int64_t k, ckks_ct **out);
+/* Add the real constant c (the integer round_half_away(c * scale) in the constant coefficient). */
+int ckks_add_const(ckks_ctx *ctx, const ckks_ct *a, double c, ckks_ct **out);
+/* Mult (paper: Mult then Rescale): tensor, relinearise with the s^2 key, rescale
+ * by the last prime; result scale (s_a * s_b) / q. */
+int ckks_mul(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out);
+/* Multiply by the real c encoded at a's scale s (integer round_half_away(c s)), then
+ * rescale by q; result scale (s * s) / q. */
+int ckks_mul_const(ckks_ctx *ctx, const ckks_ct *a, double c, ckks_ct **out);
+/* Rescale (paper: Rescale): round(c / q_last) on the centred integer. */
+int ckks_rescale(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out);
+/* Align to a deeper depth and a target scale: mod-drop to depth - 1, multiply by
+ * round_half_away(((scale * factor) * q) / s_a), rescale, declare `scale`. */
+int ckks_align(ckks_ctx *ctx, const ckks_ct *a, int depth, double scale, double factor, ckks_ct **out);
+/* Rotate (paper: Rotate) by r slots: slot j of the result holds slot j + r. */
+int ckks_rotate(ckks_ctx *ctx, const ckks_ct *a, int64_t r, ckks_ct **out);
+/* Complex conjugation of every slot. */
+int ckks_conjugate(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out);
+/* Multiply by the block-start mask (1 at slots = 0 mod R) encoded at a's scale s,
+ * then rescale; result scale (s * s) / q. */
+int ckks_mul_mask(ckks_ctx *ctx, const ckks_ct *a, int R, ckks_ct **out);
+/* Negacyclic NTT of `count` limbs in place on device memory laid out [count][N],
+ * limb i modulo chain modulus moduli_index[i] (0..L, L+1 = P); forward (dir = 1)
+ * to this library's evaluation order or inverse (dir = -1).  Host array of indices. */
+int ckks_ntt_device(ckks_ctx *ctx, uint64_t *dev_limbs, int count, const int *moduli_index, int dir);
+
+/* ---------------------------------------------------------------- GWAS (paper: Alg. Semi Parallel GWAS) */
+
+/* Layout: R = PO2(n) rows per block, B = N / (2R) blocks, tau = N / R SNPs per
+ * SNP-batch ciphertext (two per complex slot), ceil(m / tau) batches.
+ * Circuit depth: L must equal 7 kappa + 5 (kappa >= 2 Newton passes). */
+int gwas_layout(const ckks_ctx *ctx, int n, int k, int m, int kappa, int *R, int *tau, int *n_batches,
+                int *levels_needed);
+
+/* Client side: compute A = (X^T X)^-1 in FP64, encode and encrypt x_j (R-periodic,
+ * depth 0), y (depth 0), A_jl for j <= l (replicated, depth 0, scale R Delta_0)
+ * and the SNP batches (depth 7 kappa, complex-packed).  X is n x k row-major
+ * with X[:,0] = 1; y in {0, 1}; S is n x m row-major uint8 in {0, 1, 2}.
+ * Input ciphertext i is encrypted with seed output_i(SplitMix64(enc_seed)). */
+int gwas_pack_encrypt(ckks_ctx *ctx, const double *X, const double *y, const uint8_t *S, int n, int k, int m,
+                      int kappa, uint64_t enc_seed, gwas_enc_input **out);
+/* Assemble an input from imported ciphertexts (x[k], y, A[k(k+1)/2] row-major
+ * upper triangle, S[n_batches]); the handles are copied. */
+int gwas_input_from_cts(ckks_ctx *ctx, int n, int k, int m, int kappa, ckks_ct *const *x, const ckks_ct *y,
+                        ckks_ct *const *A, ckks_ct *const *S, int n_s, gwas_enc_input **out);
+void gwas_input_free(gwas_enc_input *in);
+
+/* Server side (the hot path): the encrypted circuit.  Fails with CKKS_E_LEVEL or
+ * CKKS_E_KEY_MISSING before any launch when the chain or keys do not fit.  The SNP
+ * batches are processed `chunk` ciphertexts at a time (gwas_semiparallel: up to 64). */
+int gwas_semiparallel(ckks_ctx *ctx, const gwas_enc_input *in, gwas_enc_output **out);
+int gwas_semiparallel_chunked(ckks_ctx *ctx, const gwas_enc_input *in, int chunk, gwas_enc_output **out);
+/* Output ciphertexts: which = 0 num, 1 den_even, 2 den_odd, 3 S' (projected batches):
+ * index = chunk number, each a batch of up to `chunk` ciphertexts in SNP-batch order;
+ * 4 beta_j (index j), 5 w, 6 w^-1, 7 z', 8 u = w z'.  The handle stays owned by out. */
+int gwas_output_ct(const gwas_enc_output *out, int which, int index, const ckks_ct **ct);
+int gwas_output_batches(const gwas_enc_output *out, int *n_batches);
+void gwas_output_free(gwas_enc_output *out);
+
+/* Client side: decrypt num / den separately and divide (b' = num / den,
+ * err' = 1 / den, se = sqrt(err')), m entries each; num and den may be NULL. */
+int gwas_finalize(ckks_ctx *ctx, const gwas_enc_output *out, int m, double *b, double *err, double *se,
+                  double *num, double *den);
+
+/* Number of key switches and NTT limb transforms issued by the context so far. */
+int ckks_ctx_counters(const ckks_ctx *ctx, uint64_t *keyswitches, uint64_t *limb_ntts, uint64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GWAS_CKKS_H */

@@ -1,0 +1,435 @@
+"""ctypes binding of ``include/gwas_ckks.h`` — argument marshalling only.
+
+Every step of the computation runs in the HIP library; this module converts
+numpy arrays to pointers and error codes to exceptions.  PyTorch supplies the
+device memory (through the allocator callbacks) and the HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_build", "libgwasckks.so")
+
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_dp = ctypes.POINTER(ctypes.c_double)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_vp = ctypes.c_void_p
+_szp = ctypes.POINTER(ctypes.c_size_t)
+
+
+class CkksParams(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_int), ("levels", ctypes.c_int), ("log2_scale", ctypes.c_int)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+
+class CkksAllocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+ERRORS = {-1: "INVALID_ARG", -2: "PARAM_MISMATCH", -3: "LEVEL", -4: "KEY_MISSING", -5: "NOMEM", -6: "HIP",
+          -7: "CANCELLED", -8: "NOT_READY"}
+
+
+class CkksError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+_LIB = None
+
+# (name, restype, argtypes)
+_SIGS = [
+    ("ckks_last_error", ctypes.c_char_p, []),
+    ("ckks_chain", ctypes.c_int, [ctypes.POINTER(CkksParams), _u64p, _dp]),
+    ("ckks_ctx_create", ctypes.c_int, [ctypes.POINTER(CkksParams), ctypes.POINTER(CkksAllocator), _vp, ctypes.c_size_t,
+                                       ctypes.POINTER(_vp)]),
+    ("ckks_ctx_destroy", None, [_vp]),
+    ("ckks_ctx_moduli", ctypes.c_int, [_vp, _u64p, ctypes.c_int]),
+    ("ckks_ctx_scales", ctypes.c_int, [_vp, _dp, ctypes.c_int]),
+    ("ckks_ctx_pool_stats", ctypes.c_int, [_vp, _szp, _szp, _szp, _szp]),
+    ("ckks_ctx_pool_trim", ctypes.c_int, [_vp]),
+    ("ckks_ctx_counters", ctypes.c_int, [_vp, _u64p, _u64p, _u64p]),
+    ("ckks_keygen", ctypes.c_int, [_vp, ctypes.c_uint64, _u64p, ctypes.c_int]),
+    ("ckks_galois_rotate", ctypes.c_uint64, [_vp, ctypes.c_int64]),
+    ("ckks_galois_conj", ctypes.c_uint64, [_vp]),
+    ("ckks_export_switching_key", ctypes.c_int, [_vp, ctypes.c_uint64, _u64p, ctypes.c_size_t]),
+    ("ckks_export_secret", ctypes.c_int, [_vp, _i64p, ctypes.c_size_t]),
+    ("ckks_export_public_key", ctypes.c_int, [_vp, _u64p, ctypes.c_size_t]),
+    ("ckks_encode", ctypes.c_int, [_vp, _dp, _dp, ctypes.c_size_t, ctypes.c_double, _i64p]),
+    ("ckks_decode", ctypes.c_int, [_vp, _dp, _dp, _dp]),
+    ("ckks_encrypt", ctypes.c_int, [_vp, _i64p, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(_vp)]),
+    ("ckks_decrypt", ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _dp]),
+    ("ckks_decrypt_poly", ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp]),
+    ("ckks_ct_info", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_int), _dp]),
+    ("ckks_ct_export", ctypes.c_int, [_vp, _vp, ctypes.c_int, _u64p, ctypes.c_size_t]),
+    ("ckks_ct_import", ctypes.c_int, [_vp, _u64p, ctypes.c_int, ctypes.c_double, ctypes.POINTER(_vp)]),
+    ("ckks_ct_free", None, [_vp]),
+    ("ckks_add", ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    ("ckks_sub", ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    ("ckks_mul", ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    ("ckks_mul_int", ctypes.c_int, [_vp, _vp, ctypes.c_int64, ctypes.POINTER(_vp)]),
+    ("ckks_add_const", ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.POINTER(_vp)]),
+    ("ckks_mul_const", ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.POINTER(_vp)]),
+    ("ckks_rescale", ctypes.c_int, [_vp, _vp, ctypes.POINTER(_vp)]),
+    ("ckks_align", ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.POINTER(_vp)]),
+    ("ckks_rotate", ctypes.c_int, [_vp, _vp, ctypes.c_int64, ctypes.POINTER(_vp)]),
+    ("ckks_conjugate", ctypes.c_int, [_vp, _vp, ctypes.POINTER(_vp)]),
+    ("ckks_mul_mask", ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(_vp)]),
+    ("ckks_ntt_device", ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
+    ("gwas_layout", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    ("gwas_pack_encrypt", ctypes.c_int, [_vp, _dp, _dp, _u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_uint64, ctypes.POINTER(_vp)]),
+    ("gwas_input_from_cts", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(_vp), _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                           ctypes.c_int, ctypes.POINTER(_vp)]),
+    ("gwas_input_free", None, [_vp]),
+    ("gwas_semiparallel", ctypes.c_int, [_vp, _vp, ctypes.POINTER(_vp)]),
+    ("gwas_semiparallel_chunked", ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(_vp)]),
+    ("gwas_output_ct", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]),
+    ("gwas_output_batches", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
+    ("gwas_output_free", None, [_vp]),
+    ("gwas_finalize", ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]),
+]
+
+
+def lib():
+    """Load the built library; raises if it is missing (there is no fallback path)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP library not built: %s is missing (run paper_1902_04303_amd/build.py)" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def exported_symbols() -> List[str]:
+    return [s[0] for s in _SIGS]
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise CkksError(rc, lib().ckks_last_error().decode())
+
+
+def _u64(a: np.ndarray):
+    assert a.dtype == np.uint64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_u64p)
+
+
+def _i64(a: np.ndarray):
+    assert a.dtype == np.int64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_i64p)
+
+
+def _f64(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def chain(log_n: int, levels: int, log2_scale: int):
+    """Prime chain and canonical scales (host computation, no GPU)."""
+    p = CkksParams(log_n, levels, log2_scale)
+    q = np.zeros(levels + 2, dtype=np.uint64)
+    s = np.zeros(levels + 1, dtype=np.float64)
+    _check(lib().ckks_chain(ctypes.byref(p), _u64(q), _f64(s)))
+    return [int(v) for v in q[:-1]], int(q[-1]), [float(v) for v in s]
+
+
+class Ciphertext:
+    """A batch of ciphertexts owned by the library (freed on garbage collection)."""
+
+    def __init__(self, ctx: "Context", handle: int, owned: bool = True):
+        self.ctx = ctx
+        self.h = _vp(handle)
+        self.owned = owned
+
+    def __del__(self):
+        if getattr(self, "owned", False) and self.h and self.ctx is not None and self.ctx.h:
+            lib().ckks_ct_free(self.h)
+            self.h = None
+
+    def info(self):
+        c, d, l, s = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(lib().ckks_ct_info(self.h, ctypes.byref(c), ctypes.byref(d), ctypes.byref(l), ctypes.byref(s)))
+        return c.value, d.value, l.value, s.value
+
+    @property
+    def count(self):
+        return self.info()[0]
+
+    @property
+    def depth(self):
+        return self.info()[1]
+
+    @property
+    def limbs(self):
+        return self.info()[2]
+
+    @property
+    def scale(self):
+        return self.info()[3]
+
+
+class Context:
+    def __init__(self, log_n: int, levels: int, log2_scale: int, use_torch: bool = True, pool_budget: int = 0,
+                 stream: Optional[int] = None):
+        self.h = None
+        p = CkksParams(log_n, levels, log2_scale)
+        self._keep = []
+        alloc = None
+        if use_torch:
+            import torch
+            dev = torch.cuda.current_device()
+            st = torch.cuda.current_stream() if stream is None else None
+            s_handle = st.cuda_stream if st is not None else stream
+
+            def _alloc(nbytes, user):
+                try:
+                    return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev, s_handle))
+                except Exception:
+                    return None
+
+            def _free(ptr, nbytes, user):
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+            fa, ff = ALLOC_FN(_alloc), FREE_FN(_free)
+            self._keep += [fa, ff]
+            alloc = CkksAllocator(fa, ff, None)
+            stream_handle = s_handle
+        else:
+            stream_handle = stream
+        out = _vp()
+        _check(lib().ckks_ctx_create(ctypes.byref(p), ctypes.byref(alloc) if alloc else None,
+                                     _vp(stream_handle) if stream_handle else None, pool_budget, ctypes.byref(out)))
+        self.h = out
+        self.log_n, self.levels, self.log2_scale = log_n, levels, log2_scale
+        self.N = 1 << log_n
+
+    def close(self):
+        if self.h:
+            lib().ckks_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- parameters
+    def moduli(self) -> List[int]:
+        a = np.zeros(self.levels + 2, dtype=np.uint64)
+        _check(lib().ckks_ctx_moduli(self.h, _u64(a), len(a)))
+        return [int(v) for v in a]
+
+    def scales(self) -> List[float]:
+        a = np.zeros(self.levels + 1, dtype=np.float64)
+        _check(lib().ckks_ctx_scales(self.h, _f64(a), len(a)))
+        return [float(v) for v in a]
+
+    def pool_stats(self):
+        v = [ctypes.c_size_t() for _ in range(4)]
+        _check(lib().ckks_ctx_pool_stats(self.h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("in_use", "cached", "peak", "n_alloc"), [x.value for x in v]))
+
+    def pool_trim(self):
+        _check(lib().ckks_ctx_pool_trim(self.h))
+
+    def counters(self):
+        v = [ctypes.c_uint64() for _ in range(3)]
+        _check(lib().ckks_ctx_counters(self.h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("keyswitches", "limb_ntts", "launches"), [x.value for x in v]))
+
+    # ---- keys
+    def keygen(self, seed: int, galois: Sequence[int] = ()):
+        g = np.array(list(galois), dtype=np.uint64)
+        _check(lib().ckks_keygen(self.h, seed, _u64(g) if len(g) else None, len(g)))
+
+    def galois_rotate(self, r: int) -> int:
+        return int(lib().ckks_galois_rotate(self.h, r))
+
+    def galois_conj(self) -> int:
+        return int(lib().ckks_galois_conj(self.h))
+
+    def export_switching_key(self, key_id: int) -> np.ndarray:
+        L = self.levels
+        a = np.zeros((2, L + 1, L + 2, self.N), dtype=np.uint64)
+        _check(lib().ckks_export_switching_key(self.h, key_id, _u64(a), a.size))
+        return a
+
+    def export_secret(self) -> np.ndarray:
+        a = np.zeros(self.N, dtype=np.int64)
+        _check(lib().ckks_export_secret(self.h, _i64(a), a.size))
+        return a
+
+    def export_public_key(self) -> np.ndarray:
+        a = np.zeros((2, self.levels + 1, self.N), dtype=np.uint64)
+        _check(lib().ckks_export_public_key(self.h, _u64(a), a.size))
+        return a
+
+    # ---- encode / encrypt / decrypt
+    def encode(self, z: np.ndarray, scale: float) -> np.ndarray:
+        z = np.asarray(z, dtype=np.complex128)
+        re = np.ascontiguousarray(z.real)
+        im = np.ascontiguousarray(z.imag)
+        out = np.zeros(self.N, dtype=np.int64)
+        _check(lib().ckks_encode(self.h, _f64(re), _f64(im), len(z), scale, _i64(out)))
+        return out
+
+    def encrypt(self, m: np.ndarray, depth: int, scale: float, seed: int) -> Ciphertext:
+        m = np.ascontiguousarray(m, dtype=np.int64)
+        out = _vp()
+        _check(lib().ckks_encrypt(self.h, _i64(m), depth, scale, seed, ctypes.byref(out)))
+        return Ciphertext(self, out.value)
+
+    def decrypt(self, ct: Ciphertext, index: int = 0) -> np.ndarray:
+        re = np.zeros(self.N // 2)
+        im = np.zeros(self.N // 2)
+        _check(lib().ckks_decrypt(self.h, ct.h, index, _f64(re), _f64(im)))
+        return re + 1j * im
+
+    def decrypt_poly(self, ct: Ciphertext, index: int = 0) -> np.ndarray:
+        out = np.zeros(self.N)
+        _check(lib().ckks_decrypt_poly(self.h, ct.h, index, _f64(out)))
+        return out
+
+    def export(self, ct: Ciphertext, index: int = 0) -> np.ndarray:
+        _, _, l, _ = ct.info()
+        a = np.zeros((2, l, self.N), dtype=np.uint64)
+        _check(lib().ckks_ct_export(self.h, ct.h, index, _u64(a), a.size))
+        return a
+
+    def import_ct(self, data: np.ndarray, depth: int, scale: float) -> Ciphertext:
+        data = np.ascontiguousarray(data, dtype=np.uint64)
+        out = _vp()
+        _check(lib().ckks_ct_import(self.h, _u64(data), depth, scale, ctypes.byref(out)))
+        return Ciphertext(self, out.value)
+
+    # ---- evaluation
+    def _op(self, fn, *args) -> Ciphertext:
+        out = _vp()
+        _check(fn(self.h, *args, ctypes.byref(out)))
+        return Ciphertext(self, out.value)
+
+    def add(self, a, b):
+        return self._op(lib().ckks_add, a.h, b.h)
+
+    def sub(self, a, b):
+        return self._op(lib().ckks_sub, a.h, b.h)
+
+    def mul(self, a, b):
+        return self._op(lib().ckks_mul, a.h, b.h)
+
+    def mul_int(self, a, k: int):
+        return self._op(lib().ckks_mul_int, a.h, int(k))
+
+    def add_const(self, a, c: float):
+        return self._op(lib().ckks_add_const, a.h, float(c))
+
+    def mul_const(self, a, c: float):
+        return self._op(lib().ckks_mul_const, a.h, float(c))
+
+    def rescale(self, a):
+        return self._op(lib().ckks_rescale, a.h)
+
+    def align(self, a, depth: int, scale: float, factor: float = 1.0):
+        return self._op(lib().ckks_align, a.h, depth, scale, factor)
+
+    def rotate(self, a, r: int):
+        return self._op(lib().ckks_rotate, a.h, int(r))
+
+    def conjugate(self, a):
+        return self._op(lib().ckks_conjugate, a.h)
+
+    def mul_mask(self, a, R: int):
+        return self._op(lib().ckks_mul_mask, a.h, int(R))
+
+    def ntt_device(self, dev_ptr: int, count: int, moduli_index: Sequence[int], direction: int):
+        idx = (ctypes.c_int * count)(*moduli_index)
+        _check(lib().ckks_ntt_device(self.h, _vp(dev_ptr), count, idx, direction))
+
+    # ---- GWAS
+    def gwas_layout(self, n: int, k: int, m: int, kappa: int):
+        v = [ctypes.c_int() for _ in range(4)]
+        _check(lib().gwas_layout(self.h, n, k, m, kappa, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("R", "tau", "n_batches", "levels_needed"), [x.value for x in v]))
+
+    def gwas_pack_encrypt(self, X: np.ndarray, y: np.ndarray, S: np.ndarray, kappa: int, enc_seed: int) -> "GwasInput":
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        S = np.ascontiguousarray(S, dtype=np.uint8)
+        n, k = X.shape
+        m = S.shape[1]
+        out = _vp()
+        _check(lib().gwas_pack_encrypt(self.h, _f64(X), _f64(y), S.ctypes.data_as(_u8p), n, k, m, kappa, enc_seed,
+                                       ctypes.byref(out)))
+        return GwasInput(self, out.value, n, k, m, kappa)
+
+    def gwas_input_from_cts(self, n, k, m, kappa, x: Sequence[Ciphertext], y: Ciphertext, A: Sequence[Ciphertext],
+                            S: Sequence[Ciphertext]) -> "GwasInput":
+        xa = (_vp * len(x))(*[c.h for c in x])
+        aa = (_vp * len(A))(*[c.h for c in A])
+        sa = (_vp * len(S))(*[c.h for c in S])
+        out = _vp()
+        _check(lib().gwas_input_from_cts(self.h, n, k, m, kappa, xa, y.h, aa, sa, len(S), ctypes.byref(out)))
+        return GwasInput(self, out.value, n, k, m, kappa)
+
+    def gwas_semiparallel(self, inp: "GwasInput", chunk: Optional[int] = None) -> "GwasOutput":
+        out = _vp()
+        if chunk is None:
+            _check(lib().gwas_semiparallel(self.h, inp.h, ctypes.byref(out)))
+        else:
+            _check(lib().gwas_semiparallel_chunked(self.h, inp.h, chunk, ctypes.byref(out)))
+        return GwasOutput(self, out.value, inp.m)
+
+    def gwas_finalize(self, out: "GwasOutput"):
+        m = out.m
+        b, err, se, num, den = (np.zeros(m) for _ in range(5))
+        _check(lib().gwas_finalize(self.h, out.h, m, _f64(b), _f64(err), _f64(se), _f64(num), _f64(den)))
+        return dict(b=b, err=err, se=se, num=num, den=den)
+
+
+class GwasInput:
+    def __init__(self, ctx: Context, handle: int, n, k, m, kappa):
+        self.ctx, self.h = ctx, _vp(handle)
+        self.n, self.k, self.m, self.kappa = n, k, m, kappa
+
+    def __del__(self):
+        if self.h and self.ctx is not None and self.ctx.h:
+            lib().gwas_input_free(self.h)
+            self.h = None
+
+
+class GwasOutput:
+    NUM, DEN_EVEN, DEN_ODD, S_PROJ, BETA, W, W_INV, Z_PROJ, U = range(9)
+
+    def __init__(self, ctx: Context, handle: int, m: int):
+        self.ctx, self.h, self.m = ctx, _vp(handle), m
+
+    def __del__(self):
+        if self.h and self.ctx is not None and self.ctx.h:
+            lib().gwas_output_free(self.h)
+            self.h = None
+
+    def ct(self, which: int, index: int = 0) -> Ciphertext:
+        out = _vp()
+        _check(lib().gwas_output_ct(self.h, which, index, ctypes.byref(out)))
+        return Ciphertext(self.ctx, out.value, owned=False)

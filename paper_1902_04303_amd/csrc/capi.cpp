@@ -1,0 +1,568 @@
+// extern "C" boundary of the library (include/gwas_ckks.h).  Every entry point catches all C++
+// exceptions and turns them into a CKKS_E_* code with a thread-local message.
+#include <cmath>
+#include <cstring>
+
+#include "gwas.h"
+
+using namespace gck;
+
+struct gwas_enc_input {
+    ckks_ctx *ctx;
+    std::unique_ptr<EncInput> in;
+};
+
+struct gwas_enc_output {
+    ckks_ctx *ctx;
+    EncOutput out;
+    Layout lay;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+template <typename F>
+int guard(F &&f) {
+    try {
+        f();
+        return CKKS_OK;
+    } catch (const Error &e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_err = "host out of memory";
+        return CKKS_E_NOMEM;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        return CKKS_E_INVALID_ARG;
+    }
+}
+
+void need(bool cond, const char *msg) {
+    if (!cond) throw Error(CKKS_E_INVALID_ARG, msg);
+}
+
+u64 mont_inv64(u64 q) {
+    u64 inv = q;   // Newton iteration for q^-1 mod 2^64 (q odd)
+    for (int i = 0; i < 6; ++i) inv *= 2 - q * inv;
+    return ~inv + 1;
+}
+
+u64 shoup_of(u64 w, u64 q) { return (u64)(((u128)w << 64) / q); }
+
+int bit_reverse(int x, int bits) {
+    int r = 0;
+    for (int b = 0; b < bits; ++b)
+        if (x & (1 << b)) r |= 1 << (bits - 1 - b);
+    return r;
+}
+
+void build_tables(ckks_ctx &c) {
+    const int n = c.p.n, n_mods = c.p.levels + 2;
+    const size_t N = (size_t)n;
+    std::vector<u64> psi(N * n_mods), psi_sh(N * n_mods), ipsi(N * n_mods), ipsi_sh(N * n_mods);
+    c.h_mods.resize(n_mods);
+    for (int mi = 0; mi < n_mods; ++mi) {
+        const u64 q = c.p.mod(mi);
+        const u64 root = find_psi(q, n), iroot = invmod_host(root, q);
+        std::vector<u64> pw(N), ipw(N);
+        pw[0] = ipw[0] = 1;
+        for (size_t i = 1; i < N; ++i) {
+            pw[i] = mulmod_host(pw[i - 1], root, q);
+            ipw[i] = mulmod_host(ipw[i - 1], iroot, q);
+        }
+        for (int k = 0; k < n; ++k) {
+            int br = bit_reverse(k, c.p.log_n);
+            psi[mi * N + k] = pw[br];
+            psi_sh[mi * N + k] = shoup_of(pw[br], q);
+            ipsi[mi * N + k] = ipw[br];
+            ipsi_sh[mi * N + k] = shoup_of(ipw[br], q);
+        }
+        ModInfo &M = c.h_mods[mi];
+        M.q = q;
+        M.mont_inv = mont_inv64(q);
+        M.barrett = (u64)(((u128)1 << 64) / q);
+        M.r_mod = (u64)(((u128)1 << 64) % q);
+        M.r_mod_sh = shoup_of(M.r_mod, q);
+        M.r2_mod = mulmod_host(M.r_mod, M.r_mod, q);
+        M.ninv = invmod_host((u64)n % q, q);
+        M.ninv_sh = shoup_of(M.ninv, q);
+        M.w1ninv = mulmod_host(ipsi[mi * N + 1], M.ninv, q);
+        M.w1ninv_sh = shoup_of(M.w1ninv, q);
+    }
+    const size_t mods_bytes = ((sizeof(ModInfo) * n_mods + 255) / 256) * 256;
+    const size_t tab_bytes = N * n_mods * 8;
+    GCK_HIP(hipMalloc(&c.table_mem, mods_bytes + 4 * tab_bytes));
+    char *base = static_cast<char *>(c.table_mem);
+    c.tab.mods = reinterpret_cast<ModInfo *>(base);
+    c.tab.psi = reinterpret_cast<u64 *>(base + mods_bytes);
+    c.tab.psi_sh = reinterpret_cast<u64 *>(base + mods_bytes + tab_bytes);
+    c.tab.ipsi = reinterpret_cast<u64 *>(base + mods_bytes + 2 * tab_bytes);
+    c.tab.ipsi_sh = reinterpret_cast<u64 *>(base + mods_bytes + 3 * tab_bytes);
+    c.tab.n = n;
+    c.tab.log_n = c.p.log_n;
+    c.tab.n_mods = n_mods;
+    GCK_HIP(hipMemcpy(c.tab.mods, c.h_mods.data(), sizeof(ModInfo) * n_mods, hipMemcpyHostToDevice));
+    GCK_HIP(hipMemcpy(c.tab.psi, psi.data(), tab_bytes, hipMemcpyHostToDevice));
+    GCK_HIP(hipMemcpy(c.tab.psi_sh, psi_sh.data(), tab_bytes, hipMemcpyHostToDevice));
+    GCK_HIP(hipMemcpy(c.tab.ipsi, ipsi.data(), tab_bytes, hipMemcpyHostToDevice));
+    GCK_HIP(hipMemcpy(c.tab.ipsi_sh, ipsi_sh.data(), tab_bytes, hipMemcpyHostToDevice));
+}
+
+Ct wrap(Ct r) { return r; }
+
+ckks_ct *release(Ct r) { return r.release(); }
+
+void check_ct(const ckks_ctx *ctx, const ckks_ct *a) {
+    need(ctx && a, "null handle");
+    if (a->ctx != ctx) throw Error(CKKS_E_PARAM_MISMATCH, "ciphertext belongs to another context");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ckks_last_error(void) { return g_err.c_str(); }
+
+int ckks_chain(const ckks_params *params, uint64_t *moduli, double *scales) {
+    return guard([&] {
+        need(params && moduli && scales, "null argument");
+        Params p = make_params(params->log_n, params->levels, params->log2_scale);
+        for (int i = 0; i <= p.levels; ++i) moduli[i] = p.q[i];
+        moduli[p.levels + 1] = p.P;
+        for (int i = 0; i <= p.levels; ++i) scales[i] = p.scales[i];
+    });
+}
+
+int ckks_ctx_create(const ckks_params *params, const ckks_allocator *allocator, void *hip_stream,
+                    size_t pool_budget_bytes, ckks_ctx **out) {
+    return guard([&] {
+        need(params && out, "null argument");
+        *out = nullptr;
+        auto c = std::make_unique<ckks_ctx>();
+        c->p = make_params(params->log_n, params->levels, params->log2_scale);
+        c->stream = static_cast<hipStream_t>(hip_stream);
+        c->pool = std::make_unique<Pool>(allocator, pool_budget_bytes);
+        c->pool->stream = c->stream;
+        build_tables(*c);
+        *out = c.release();
+    });
+}
+
+void ckks_ctx_destroy(ckks_ctx *ctx) { delete ctx; }
+
+int ckks_ctx_moduli(const ckks_ctx *ctx, uint64_t *moduli, int cap) {
+    return guard([&] {
+        need(ctx && moduli && cap >= ctx->p.levels + 2, "bad buffer");
+        for (int i = 0; i <= ctx->p.levels; ++i) moduli[i] = ctx->p.q[i];
+        moduli[ctx->p.levels + 1] = ctx->p.P;
+    });
+}
+
+int ckks_ctx_scales(const ckks_ctx *ctx, double *scales, int cap) {
+    return guard([&] {
+        need(ctx && scales && cap >= ctx->p.levels + 1, "bad buffer");
+        for (int i = 0; i <= ctx->p.levels; ++i) scales[i] = ctx->p.scales[i];
+    });
+}
+
+int ckks_ctx_pool_stats(const ckks_ctx *ctx, size_t *in_use, size_t *cached, size_t *peak, size_t *n_alloc) {
+    return guard([&] {
+        need(ctx, "null context");
+        if (in_use) *in_use = ctx->pool->in_use;
+        if (cached) *cached = ctx->pool->cached;
+        if (peak) *peak = ctx->pool->peak;
+        if (n_alloc) *n_alloc = ctx->pool->n_alloc;
+    });
+}
+
+int ckks_ctx_pool_trim(ckks_ctx *ctx) {
+    return guard([&] {
+        need(ctx, "null context");
+        ctx->pool->trim();
+    });
+}
+
+int ckks_ctx_counters(const ckks_ctx *ctx, uint64_t *keyswitches, uint64_t *limb_ntts, uint64_t *launches) {
+    return guard([&] {
+        need(ctx, "null context");
+        if (keyswitches) *keyswitches = ctx->n_keyswitch;
+        if (limb_ntts) *limb_ntts = ctx->n_limb_ntt;
+        if (launches) *launches = ctx->n_launch;
+    });
+}
+
+int ckks_keygen(ckks_ctx *ctx, uint64_t seed, const uint64_t *galois, int n_galois) {
+    return guard([&] {
+        need(ctx && (n_galois == 0 || galois) && n_galois >= 0, "bad arguments");
+        keygen(*ctx, seed, std::vector<u64>(galois, galois + n_galois));
+    });
+}
+
+uint64_t ckks_galois_rotate(const ckks_ctx *ctx, int64_t r) { return ctx ? galois_rotate(*ctx, r) : 0; }
+uint64_t ckks_galois_conj(const ckks_ctx *ctx) { return ctx ? galois_conj(*ctx) : 0; }
+
+int ckks_export_switching_key(ckks_ctx *ctx, uint64_t key_id, uint64_t *buf, size_t cap_words) {
+    return guard([&] {
+        need(ctx && buf, "null argument");
+        auto it = ctx->ksk.find(key_id);
+        if (it == ctx->ksk.end()) throw Error(CKKS_E_KEY_MISSING, "no such key");
+        const int L = ctx->p.levels, nt = L + 2, nd = L + 1;
+        const size_t N = (size_t)ctx->p.n, words = (size_t)2 * nd * nt * N;
+        need(cap_words >= words, "buffer too small");
+        DBuf t(ctx->pool.get(), words);
+        GCK_HIP(hipMemcpyAsync(t.ptr, it->second.ptr, words * 8, hipMemcpyDeviceToDevice, ctx->stream));
+        const ModMap mt{nt, L + 1, L + 1};
+        k_from_mont(ctx->tab, t.ptr, 2 * nd * nt, mt, ctx->stream);
+        ntt_inv(*ctx, t.ptr, 2 * nd * nt, mt);
+        GCK_HIP(hipMemcpyAsync(buf, t.ptr, words * 8, hipMemcpyDeviceToHost, ctx->stream));
+        sync(*ctx);
+    });
+}
+
+int ckks_export_secret(ckks_ctx *ctx, int64_t *buf, size_t cap) {
+    return guard([&] {
+        need(ctx && buf && cap >= (size_t)ctx->p.n, "bad buffer");
+        if (!ctx->have_keys) throw Error(CKKS_E_KEY_MISSING, "keygen has not been run");
+        std::memcpy(buf, ctx->sk.data(), (size_t)ctx->p.n * 8);
+    });
+}
+
+int ckks_export_public_key(ckks_ctx *ctx, uint64_t *buf, size_t cap_words) {
+    return guard([&] {
+        need(ctx && buf, "null argument");
+        if (!ctx->have_keys) throw Error(CKKS_E_KEY_MISSING, "keygen has not been run");
+        const int l = ctx->p.levels + 1;
+        const size_t N = (size_t)ctx->p.n, words = (size_t)2 * l * N;
+        need(cap_words >= words, "buffer too small");
+        DBuf t(ctx->pool.get(), words);
+        GCK_HIP(hipMemcpyAsync(t.ptr, ctx->pk.ptr, words * 8, hipMemcpyDeviceToDevice, ctx->stream));
+        ntt_inv(*ctx, t.ptr, 2 * l, map_q(l));
+        GCK_HIP(hipMemcpyAsync(buf, t.ptr, words * 8, hipMemcpyDeviceToHost, ctx->stream));
+        sync(*ctx);
+    });
+}
+
+int ckks_encode(ckks_ctx *ctx, const double *re, const double *im, size_t n, double scale, int64_t *coeffs_out) {
+    return guard([&] {
+        need(ctx && coeffs_out && (re || n == 0), "null argument");
+        encode_poly(ctx->p.n, re, im, n, scale, coeffs_out);
+    });
+}
+
+int ckks_decode(ckks_ctx *ctx, const double *coeffs, double *re, double *im) {
+    return guard([&] {
+        need(ctx && coeffs, "null argument");
+        decode_poly(ctx->p.n, coeffs, re, im);
+    });
+}
+
+int ckks_encrypt(ckks_ctx *ctx, const int64_t *m, int depth, double scale, uint64_t seed, ckks_ct **out) {
+    return guard([&] {
+        need(ctx && m && out, "null argument");
+        need(scale > 0, "scale must be positive");
+        *out = release(encrypt(*ctx, m, depth, scale, seed));
+    });
+}
+
+int ckks_decrypt_poly(ckks_ctx *ctx, const ckks_ct *ct, int index, double *coeffs) {
+    return guard([&] {
+        check_ct(ctx, ct);
+        need(coeffs && index >= 0 && index < ct->count, "bad arguments");
+        auto v = decrypt_poly(*ctx, *ct, index);
+        for (size_t i = 0; i < v.size(); ++i) coeffs[i] = (double)v[i];
+    });
+}
+
+int ckks_decrypt(ckks_ctx *ctx, const ckks_ct *ct, int index, double *re, double *im) {
+    return guard([&] {
+        check_ct(ctx, ct);
+        need(index >= 0 && index < ct->count, "bad index");
+        auto v = decrypt_poly(*ctx, *ct, index);
+        std::vector<double> m(v.size());
+        for (size_t i = 0; i < v.size(); ++i) m[i] = (double)(v[i] / (long double)ct->scale);
+        decode_poly(ctx->p.n, m.data(), re, im);
+    });
+}
+
+int ckks_ct_info(const ckks_ct *ct, int *count, int *depth, int *limbs, double *scale) {
+    return guard([&] {
+        need(ct, "null handle");
+        if (count) *count = ct->count;
+        if (depth) *depth = ct->depth;
+        if (limbs) *limbs = ct->limbs;
+        if (scale) *scale = ct->scale;
+    });
+}
+
+int ckks_ct_export(ckks_ctx *ctx, const ckks_ct *ct, int index, uint64_t *buf, size_t cap_words) {
+    return guard([&] {
+        check_ct(ctx, ct);
+        need(buf && index >= 0 && index < ct->count, "bad arguments");
+        need(cap_words >= (size_t)2 * ct->limbs * ctx->p.n, "buffer too small");
+        export_ct(*ctx, *ct, index, buf);
+    });
+}
+
+int ckks_ct_import(ckks_ctx *ctx, const uint64_t *buf, int depth, double scale, ckks_ct **out) {
+    return guard([&] {
+        need(ctx && buf && out, "null argument");
+        *out = release(import_ct(*ctx, buf, depth, scale));
+    });
+}
+
+void ckks_ct_free(ckks_ct *ct) { delete ct; }
+
+#define CT_UNARY(name, expr)                                   \
+    int name(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out) { \
+        return guard([&] {                                     \
+            check_ct(ctx, a);                                  \
+            need(out, "null output");                          \
+            *out = release(expr);                              \
+        });                                                    \
+    }
+
+CT_UNARY(ckks_rescale, rescale(*ctx, *a))
+CT_UNARY(ckks_conjugate, conjugate(*ctx, *a))
+
+int ckks_add(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out) {
+    return guard([&] {
+        check_ct(ctx, a);
+        check_ct(ctx, b);
+        need(out, "null output");
+        *out = release(add(*ctx, *a, *b));
+    });
+}
+
+int ckks_sub(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out) {
+    return guard([&] {
+        check_ct(ctx, a);
+        check_ct(ctx, b);
+        need(out, "null output");
+        *out = release(sub(*ctx, *a, *b));
+    });
+}
+
+int ckks_mul(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out) {
+    return guard([&] {
+        check_ct(ctx, a);
+        check_ct(ctx, b);
+        need(out, "null output");
+        *out = release(mul(*ctx, *a, *b));
+    });
+}
+
+int ckks_mul_int(ckks_ctx *ctx, const ckks_ct *a, int64_t k, ckks_ct **out) {
+    return guard([&] {
+        check_ct(ctx, a);
+        need(out, "null output");
+        *out = release(mul_int(*ctx, *a, k));
+    });
+}
+
+int ckks_add_const(ckks_ctx *ctx, const ckks_ct *a, double v, ckks_ct **out) {
+    return guard([&] {
+        check_ct(ctx, a);
+        need(out, "null output");
+        *out = release(add_const(*ctx, *a, v));
+    });
+}
+
+int ckks_mul_const(ckks_ctx *ctx, const ckks_ct *a, double v, ckks_ct **out) {
+    return guard([&] {
+        check_ct(ctx, a);
+        need(out, "null output");
+        *out = release(mul_const(*ctx, *a, v));
+    });
+}
+
+int ckks_align(ckks_ctx *ctx, const ckks_ct *a, int depth, double scale, double factor, ckks_ct **out) {
+    return guard([&] {
+        check_ct(ctx, a);
+        need(out, "null output");
+        *out = release(align(*ctx, *a, depth, scale, factor));
+    });
+}
+
+int ckks_rotate(ckks_ctx *ctx, const ckks_ct *a, int64_t r, ckks_ct **out) {
+    return guard([&] {
+        check_ct(ctx, a);
+        need(out, "null output");
+        *out = release(rotate(*ctx, *a, r));
+    });
+}
+
+int ckks_mul_mask(ckks_ctx *ctx, const ckks_ct *a, int R, ckks_ct **out) {
+    return guard([&] {
+        check_ct(ctx, a);
+        need(out, "null output");
+        *out = release(mul_mask(*ctx, *a, R));
+    });
+}
+
+int ckks_ntt_device(ckks_ctx *ctx, uint64_t *dev_limbs, int count, const int *moduli_index, int dir) {
+    return guard([&] {
+        need(ctx && dev_limbs && moduli_index && count >= 0 && (dir == 1 || dir == -1), "bad arguments");
+        for (int i = 0; i < count; ++i) {
+            int mi = moduli_index[i];
+            need(mi >= 0 && mi <= ctx->p.levels + 1, "modulus index out of range");
+            const ModMap m{1, 0, mi};
+            if (dir == 1) ntt_fwd(*ctx, dev_limbs + (size_t)i * ctx->p.n, 1, m);
+            else ntt_inv(*ctx, dev_limbs + (size_t)i * ctx->p.n, 1, m);
+        }
+    });
+}
+
+int gwas_layout(const ckks_ctx *ctx, int n, int k, int m, int kappa, int *R, int *tau, int *n_batches,
+                int *levels_needed) {
+    return guard([&] {
+        need(ctx, "null context");
+        Layout lay = make_layout(ctx->p.n, n, k, m);
+        if (R) *R = lay.R;
+        if (tau) *tau = lay.tau;
+        if (n_batches) *n_batches = lay.n_batches;
+        if (levels_needed) *levels_needed = circuit_levels(kappa);
+    });
+}
+
+int gwas_pack_encrypt(ckks_ctx *ctx, const double *X, const double *y, const uint8_t *S, int n, int k, int m,
+                      int kappa, uint64_t enc_seed, gwas_enc_input **out) {
+    return guard([&] {
+        need(ctx && X && y && S && out, "null argument");
+        need(kappa >= 2, "kappa must be >= 2");
+        if (ctx->p.levels != circuit_levels(kappa)) throw Error(CKKS_E_LEVEL, "chain length does not match kappa");
+        auto in = pack_encrypt(*ctx, X, y, S, n, k, m, kappa, enc_seed);
+        *out = new gwas_enc_input{ctx, std::move(in)};
+    });
+}
+
+int gwas_input_from_cts(ckks_ctx *ctx, int n, int k, int m, int kappa, ckks_ct *const *x, const ckks_ct *y,
+                        ckks_ct *const *A, ckks_ct *const *S, int n_s, gwas_enc_input **out) {
+    return guard([&] {
+        need(ctx && x && y && A && S && out, "null argument");
+        need(kappa >= 2, "kappa must be >= 2");
+        auto in = std::make_unique<EncInput>();
+        in->lay = make_layout(ctx->p.n, n, k, m);
+        in->kappa = kappa;
+        need(n_s == in->lay.n_batches, "wrong number of SNP batches");
+        for (int j = 0; j < k; ++j) {
+            check_ct(ctx, x[j]);
+            in->x.push_back(clone(*ctx, *x[j]));
+        }
+        check_ct(ctx, y);
+        in->y = clone(*ctx, *y);
+        for (int i = 0; i < k * (k + 1) / 2; ++i) {
+            check_ct(ctx, A[i]);
+            in->A.push_back(clone(*ctx, *A[i]));
+        }
+        const int ds = snp_depth(kappa);
+        for (int b = 0; b < n_s; ++b) {
+            check_ct(ctx, S[b]);
+            if (S[b]->depth != ds || S[b]->count != 1) throw Error(CKKS_E_LEVEL, "SNP batch at the wrong depth");
+        }
+        in->S = new_ct(*ctx, n_s, ds, S[0]->scale);
+        const size_t per = (size_t)2 * in->S->limbs * ctx->p.n;
+        for (int b = 0; b < n_s; ++b)
+            GCK_HIP(hipMemcpyAsync(in->S->data.ptr + (size_t)b * per, S[b]->data.ptr, per * 8, hipMemcpyDeviceToDevice,
+                                   ctx->stream));
+        *out = new gwas_enc_input{ctx, std::move(in)};
+    });
+}
+
+void gwas_input_free(gwas_enc_input *in) { delete in; }
+
+int gwas_semiparallel_chunked(ckks_ctx *ctx, const gwas_enc_input *in, int chunk, gwas_enc_output **out) {
+    return guard([&] {
+        need(ctx && in && out, "null argument");
+        need(in->ctx == ctx, "input belongs to another context");
+        need(chunk >= 1, "chunk must be >= 1");
+        auto o = std::make_unique<gwas_enc_output>();
+        o->ctx = ctx;
+        o->lay = in->in->lay;
+        o->out.chunk = chunk;
+        run_circuit(*ctx, *in->in, o->out, chunk);
+        *out = o.release();
+    });
+}
+
+int gwas_semiparallel(ckks_ctx *ctx, const gwas_enc_input *in, gwas_enc_output **out) {
+    const int chunk = in && in->in ? std::max(1, in->in->S->count) : 1;
+    return gwas_semiparallel_chunked(ctx, in, chunk > 64 ? 64 : chunk, out);
+}
+
+int gwas_output_batches(const gwas_enc_output *out, int *n_batches) {
+    return guard([&] {
+        need(out && n_batches, "null argument");
+        *n_batches = out->lay.n_batches;
+    });
+}
+
+int gwas_output_ct(const gwas_enc_output *out, int which, int index, const ckks_ct **ct) {
+    return guard([&] {
+        need(out && ct, "null argument");
+        const EncOutput &o = out->out;
+        const std::vector<Ct> *vec = nullptr;
+        switch (which) {
+        case 0: vec = &o.num; break;
+        case 1: vec = &o.den_even; break;
+        case 2: vec = &o.den_odd; break;
+        case 3: vec = &o.S_proj; break;
+        case 4:
+            need(index >= 0 && index < (int)o.beta.size(), "beta index out of range");
+            *ct = o.beta[index].get();
+            return;
+        case 5: *ct = o.w.get(); return;
+        case 6: *ct = o.w_inv.get(); return;
+        case 7: *ct = o.z_proj.get(); return;
+        case 8: *ct = o.u.get(); return;
+        default: need(false, "unknown output");
+        }
+        need(index >= 0 && index < (int)vec->size(), "chunk index out of range");
+        *ct = (*vec)[index].get();
+    });
+}
+
+void gwas_output_free(gwas_enc_output *out) { delete out; }
+
+int gwas_finalize(ckks_ctx *ctx, const gwas_enc_output *out, int m, double *b, double *err, double *se, double *num,
+                  double *den) {
+    return guard([&] {
+        need(ctx && out, "null argument");
+        const Layout &lay = out->lay;
+        need(m == lay.m, "m does not match the layout");
+        const int N = ctx->p.n, slots = N / 2;
+        std::vector<double> vnum((size_t)lay.n_batches * lay.tau, 0.0), vden(vnum.size(), 0.0);
+        std::vector<double> re(slots), im(slots), coeffs(N);
+        int batch = 0;
+        for (size_t ch = 0; ch < out->out.num.size(); ++ch) {
+            const ckks_ct &cn = *out->out.num[ch], &ce = *out->out.den_even[ch], &co = *out->out.den_odd[ch];
+            for (int i = 0; i < cn.count; ++i, ++batch) {
+                auto dec = [&](const ckks_ct &ct, int idx) {
+                    auto v = decrypt_poly(*ctx, ct, idx);
+                    for (int t = 0; t < N; ++t) coeffs[t] = (double)(v[t] / (long double)ct.scale);
+                    decode_poly(N, coeffs.data(), re.data(), im.data());
+                };
+                const size_t base = (size_t)batch * lay.tau;
+                dec(cn, i);
+                for (int cb = 0; cb < lay.blocks; ++cb) {
+                    vnum[base + 2 * cb] = re[(size_t)cb * lay.R];
+                    vnum[base + 2 * cb + 1] = im[(size_t)cb * lay.R];
+                }
+                dec(ce, i);
+                for (int cb = 0; cb < lay.blocks; ++cb) vden[base + 2 * cb] = re[(size_t)cb * lay.R];
+                dec(co, i);
+                for (int cb = 0; cb < lay.blocks; ++cb) vden[base + 2 * cb + 1] = re[(size_t)cb * lay.R];
+            }
+        }
+        for (int j = 0; j < m; ++j) {
+            if (num) num[j] = vnum[j];
+            if (den) den[j] = vden[j];
+            if (b) b[j] = vnum[j] / vden[j];
+            if (err) err[j] = 1.0 / vden[j];
+            if (se) se[j] = std::sqrt(1.0 / vden[j]);
+        }
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,177 @@
+// Internal declarations of the MI355X RNS-CKKS library (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/gwas_ckks.h"
+
+namespace gck {
+
+using u64 = uint64_t;
+using i64 = int64_t;
+using u128 = unsigned __int128;
+
+constexpr int kMaxMods = 64;   // q_0..q_L and P
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+void hip_check(hipError_t e, const char *what);
+#define GCK_HIP(x) ::gck::hip_check((x), #x)
+
+// ---------------------------------------------------------------- per-modulus constants (device copy)
+struct ModInfo {
+    u64 q;
+    u64 mont_inv;      // -q^-1 mod 2^64 (Montgomery)
+    u64 barrett;       // floor(2^64 / q)
+    u64 r_mod;         // 2^64 mod q
+    u64 r_mod_sh;      // Shoup companion of r_mod
+    u64 r2_mod;        // 2^128 mod q
+    u64 ninv, ninv_sh; // N^-1
+    u64 w1ninv, w1ninv_sh;  // psi^-1 (first inverse twiddle) * N^-1
+};
+
+// ---------------------------------------------------------------- parameters and prime chain
+struct Params {
+    int log_n = 0, n = 0, levels = 0, log2_scale = 0;
+    std::vector<u64> q;        // q_0 .. q_L
+    u64 P = 0;
+    std::vector<double> scales;  // canonical Delta_0 .. Delta_L
+    int limbs_at(int depth) const { return levels + 1 - depth; }
+    u64 dropped_at(int depth) const { return q[levels - depth]; }  // prime removed by the rescale at depth
+    int p_index() const { return levels + 1; }
+    u64 mod(int idx) const { return idx <= levels ? q[idx] : P; }
+};
+Params make_params(int log_n, int levels, int log2_scale);
+u64 mulmod_host(u64 a, u64 b, u64 q);
+u64 powmod_host(u64 b, u64 e, u64 q);
+u64 invmod_host(u64 a, u64 q);
+u64 find_psi(u64 q, int n);
+i64 round_half_away(double x);
+
+// ---------------------------------------------------------------- memory pool (device)
+class Pool {
+public:
+    Pool(const ckks_allocator *alloc, size_t budget);
+    ~Pool();
+    void *get(size_t bytes);
+    void put(void *p, size_t bytes);
+    void trim();
+    size_t in_use = 0, cached = 0, peak = 0, n_alloc = 0, budget = 0;
+    hipStream_t stream = nullptr;
+
+private:
+    ckks_allocator alloc_{};
+    bool have_alloc_ = false;
+    std::multimap<size_t, void *> free_;
+    void *raw_alloc(size_t bytes);
+    void raw_free(void *p, size_t bytes);
+};
+
+// device buffer with RAII return to the pool
+struct DBuf {
+    Pool *pool = nullptr;
+    u64 *ptr = nullptr;
+    size_t words = 0;
+    DBuf() = default;
+    DBuf(Pool *p, size_t w) : pool(p), ptr(static_cast<u64 *>(p->get(w * 8))), words(w) {}
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept { *this = std::move(o); }
+    DBuf &operator=(DBuf &&o) noexcept {
+        release();
+        pool = o.pool; ptr = o.ptr; words = o.words;
+        o.ptr = nullptr; o.words = 0;
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void release() {
+        if (ptr && pool) pool->put(ptr, words * 8);
+        ptr = nullptr; words = 0;
+    }
+};
+
+// ---------------------------------------------------------------- kernels (kernels.hip)
+// Every polynomial buffer is a contiguous array of limbs of N words.  The chain
+// index (0..L for q_i, L+1 for P) of limb lam is given by a ModMap:
+//     t = lam % period;  chain = (t < nq) ? t : p_idx
+// e.g. ciphertext data [count][2][l][N] has period = nq = l; ModUp digits
+// [count][l][l+1][N] have period l+1, nq = l.
+struct ModMap {
+    int period, nq, p_idx;
+};
+inline ModMap map_q(int l) { return ModMap{l, l, 0}; }
+
+struct DevTables {
+    ModInfo *mods = nullptr;            // [n_mods]
+    u64 *psi = nullptr, *psi_sh = nullptr, *ipsi = nullptr, *ipsi_sh = nullptr;  // [n_mods][N]
+    int n = 0, log_n = 0, n_mods = 0;
+};
+
+struct ChainConst {     // one constant per chain index (value and Shoup companion), passed by value
+    u64 v[kMaxMods];
+    u64 sh[kMaxMods];
+};
+
+void k_ntt_forward(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStream_t st);
+void k_ntt_inverse(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStream_t st);
+// out = a op b over n_limbs limbs; a is read at limb (lam % na_limbs), b at (lam % nb_limbs)
+void k_add(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
+           hipStream_t st);
+void k_sub(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
+           hipStream_t st);
+void k_mul(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
+           hipStream_t st);
+// out = a * c[chain]
+void k_mul_const(const DevTables &t, u64 *out, const u64 *a, int n_limbs, ModMap m, const ChainConst &c,
+                 hipStream_t st);
+// ct data [count][2][l][N]: poly 0 limbs += c[chain]
+void k_add_const_c0(const DevTables &t, u64 *ct, int count, int l, const ChainConst &c, hipStream_t st);
+// tensor of [count][2][l] ciphertexts into [count][3][l]; a / b read at ciphertext (c % na) / (c % nb)
+void k_tensor(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int count, int l, int na, int nb,
+              bool accumulate, hipStream_t st);
+// NTT-domain automorphism X -> X^g on every limb
+void k_automorph(const DevTables &t, u64 *out, const u64 *a, int n_limbs, u64 g, hipStream_t st);
+// out[r][0:words] = in[r][0:words] with row strides (in words)
+void k_copy_rows(u64 *out, size_t out_stride, const u64 *in, size_t in_stride, int rows, size_t words,
+                 hipStream_t st);
+// basis extension of one limb per row: out[r][i] = f(in[r]) mod chain(i), i < l_out (out_map period l_out);
+// f = centred lift of residues mod chain src_mod when centred, else the plain value
+void k_extend(const DevTables &t, u64 *out, const u64 *in, int rows, int l_out, ModMap out_map, int src_mod,
+              bool centred, hipStream_t st);
+// ModUp digits: out[c][j][t] = in[c][j] mod chain(t), j < l, t <= l (t == l: P)
+void k_modup(const DevTables &t, u64 *out, const u64 *in, int count, int l, int p_idx, hipStream_t st);
+// out = (a - b) * c[chain]  (+ out when add_to_out)
+void k_sub_mul_const(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m,
+                     const ChainConst &c, bool add_to_out, hipStream_t st);
+// key-switch inner product: acc[c][comp][t] = sum_{j<l} digit[c][j][t] * key[comp][j][kt], kt = t (t<l) or L+1;
+// key words are in Montgomery form (times 2^64)
+void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, const u64 *key, int count, int l, int levels,
+                hipStream_t st);
+// samplers of the test-only SplitMix64 streams
+void k_sample_uniform(const DevTables &t, u64 *out, u64 seed, u64 sid, int n_limbs, ModMap m, int mi_of_p,
+                      hipStream_t st);
+void k_sample_cbd(i64 *out, u64 seed, u64 sid, int n, hipStream_t st);
+void k_sample_ternary(i64 *out, u64 seed, u64 sid, int n, hipStream_t st);
+// signed small coefficients -> residues for every limb of a ModMap'd buffer
+void k_signed_to_limbs(const DevTables &t, u64 *out, const i64 *in, int n_limbs, ModMap m, hipStream_t st);
+// Montgomery form conversion (x * 2^64 mod q and back)
+void k_to_mont(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t st);
+void k_from_mont(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t st);
+// out[r][i] += in[r][i] for rows of l limbs (limb i modulo q_i), row strides in words
+void k_add_rows(const DevTables &t, u64 *out, size_t out_stride, const u64 *in, size_t in_stride, int rows, int l,
+                hipStream_t st);
+// out = -out  (negation) for each limb
+void k_neg(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t st);
+
+}  // namespace gck

@@ -1,0 +1,611 @@
+// Host driver of the RNS-CKKS evaluator: context and tables, device memory pool, keys, encryption and
+// the scheme operations of the paper's Methods ("Homomorphic Encryption") in RNS form.
+#include <cmath>
+#include <cstring>
+#include <fstream>
+#include <random>
+
+#include "evaluator.h"
+
+namespace gck {
+
+void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) {
+        if (e == hipErrorOutOfMemory) throw Error(CKKS_E_NOMEM, std::string("device out of memory in ") + what);
+        throw Error(CKKS_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+// ---------------------------------------------------------------- pool
+
+Pool::Pool(const ckks_allocator *alloc, size_t b) : budget(b) {
+    if (alloc && alloc->alloc && alloc->free) {
+        alloc_ = *alloc;
+        have_alloc_ = true;
+    }
+}
+
+Pool::~Pool() {
+    if (stream) hipStreamSynchronize(stream);
+    else hipDeviceSynchronize();
+    for (auto &kv : free_) raw_free(kv.second, kv.first);
+    free_.clear();
+}
+
+void *Pool::raw_alloc(size_t bytes) {
+    void *p = nullptr;
+    if (have_alloc_) {
+        p = alloc_.alloc(bytes, alloc_.user);
+        if (!p) throw Error(CKKS_E_NOMEM, "allocator callback returned NULL");
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(CKKS_E_NOMEM, "hipMalloc failed for " + std::to_string(bytes) + " bytes");
+        }
+    }
+    ++n_alloc;
+    return p;
+}
+
+void Pool::raw_free(void *p, size_t bytes) {
+    if (have_alloc_) alloc_.free(p, bytes, alloc_.user);
+    else hipFree(p);
+}
+
+static size_t round_bytes(size_t b) { return (b + 255) & ~size_t(255); }
+
+void *Pool::get(size_t bytes) {
+    bytes = round_bytes(bytes ? bytes : 8);
+    auto it = free_.find(bytes);
+    if (it != free_.end()) {
+        void *p = it->second;
+        free_.erase(it);
+        cached -= bytes;
+        in_use += bytes;
+        peak = std::max(peak, in_use);
+        return p;
+    }
+    if (budget && in_use + cached + bytes > budget) {
+        trim();
+        if (in_use + bytes > budget)
+            throw Error(CKKS_E_NOMEM, "pool budget exceeded (" + std::to_string(in_use + bytes) + " > " +
+                                          std::to_string(budget) + " bytes)");
+    }
+    void *p;
+    try {
+        p = raw_alloc(bytes);
+    } catch (const Error &) {
+        trim();
+        p = raw_alloc(bytes);
+    }
+    in_use += bytes;
+    peak = std::max(peak, in_use);
+    return p;
+}
+
+void Pool::put(void *p, size_t bytes) {
+    bytes = round_bytes(bytes ? bytes : 8);
+    free_.emplace(bytes, p);
+    in_use -= bytes;
+    cached += bytes;
+}
+
+void Pool::trim() {
+    if (free_.empty()) return;
+    if (stream) hipStreamSynchronize(stream);
+    else hipDeviceSynchronize();
+    for (auto &kv : free_) raw_free(kv.second, kv.first);
+    free_.clear();
+    cached = 0;
+}
+
+void sync(ckks_ctx &c) { GCK_HIP(hipStreamSynchronize(c.stream)); }
+
+// ---------------------------------------------------------------- ciphertext helpers
+
+Ct new_ct(ckks_ctx &c, int count, int depth, double scale) {
+    if (depth < 0 || depth > c.p.levels) throw Error(CKKS_E_LEVEL, "depth " + std::to_string(depth) + " out of range");
+    Ct r(new ckks_ct());
+    r->ctx = &c;
+    r->count = count;
+    r->depth = depth;
+    r->limbs = c.p.limbs_at(depth);
+    r->scale = scale;
+    r->data = DBuf(c.pool.get(), (size_t)count * 2 * r->limbs * c.p.n);
+    return r;
+}
+
+Ct clone(ckks_ctx &c, const ckks_ct &a) {
+    Ct r = new_ct(c, a.count, a.depth, a.scale);
+    GCK_HIP(hipMemcpyAsync(r->data.ptr, a.data.ptr, a.data.words * 8, hipMemcpyDeviceToDevice, c.stream));
+    return r;
+}
+
+void ntt_fwd(ckks_ctx &c, u64 *buf, int n_limbs, ModMap m) {
+    k_ntt_forward(c.tab, buf, n_limbs, m, c.stream);
+    c.n_limb_ntt += n_limbs;
+    c.n_launch += 2;
+}
+void ntt_inv(ckks_ctx &c, u64 *buf, int n_limbs, ModMap m) {
+    k_ntt_inverse(c.tab, buf, n_limbs, m, c.stream);
+    c.n_limb_ntt += n_limbs;
+    c.n_launch += 2;
+}
+
+static ChainConst chain_const_of(const ckks_ctx &c, i64 k) {
+    ChainConst cc{};
+    for (int i = 0; i < c.p.levels + 2; ++i) {
+        u64 q = c.p.mod(i);
+        u64 v = k >= 0 ? (u64)k % q : q - 1 - (u64)(-(k + 1)) % q;
+        cc.v[i] = v;
+        cc.sh[i] = (u64)(((u128)v << 64) / q);
+    }
+    return cc;
+}
+
+static ChainConst chain_inv_of(const ckks_ctx &c, u64 x) {
+    ChainConst cc{};
+    for (int i = 0; i < c.p.levels + 2; ++i) {
+        u64 q = c.p.mod(i);
+        u64 v = (x % q == 0) ? 0 : invmod_host(x % q, q);
+        cc.v[i] = v;
+        cc.sh[i] = (u64)(((u128)v << 64) / q);
+    }
+    return cc;
+}
+
+static void check_same(const ckks_ct &a, const ckks_ct &b) {
+    if (a.depth != b.depth || a.scale != b.scale)
+        throw Error(CKKS_E_PARAM_MISMATCH, "operands differ in depth (" + std::to_string(a.depth) + ", " +
+                                               std::to_string(b.depth) + ") or scale");
+    if (a.count != b.count && a.count != 1 && b.count != 1)
+        throw Error(CKKS_E_PARAM_MISMATCH, "batch counts differ");
+}
+
+// ---------------------------------------------------------------- scheme operations
+
+Ct add(ckks_ctx &c, const ckks_ct &a, const ckks_ct &b) {
+    check_same(a, b);
+    int count = std::max(a.count, b.count), l = a.limbs;
+    Ct r = new_ct(c, count, a.depth, a.scale);
+    k_add(c.tab, r->data.ptr, a.data.ptr, b.data.ptr, count * 2 * l, map_q(l), a.count * 2 * l, b.count * 2 * l, c.stream);
+    ++c.n_launch;
+    return r;
+}
+
+Ct sub(ckks_ctx &c, const ckks_ct &a, const ckks_ct &b) {
+    check_same(a, b);
+    int count = std::max(a.count, b.count), l = a.limbs;
+    Ct r = new_ct(c, count, a.depth, a.scale);
+    k_sub(c.tab, r->data.ptr, a.data.ptr, b.data.ptr, count * 2 * l, map_q(l), a.count * 2 * l, b.count * 2 * l, c.stream);
+    ++c.n_launch;
+    return r;
+}
+
+Ct mul_int(ckks_ctx &c, const ckks_ct &a, i64 k) {
+    Ct r = new_ct(c, a.count, a.depth, a.scale);
+    k_mul_const(c.tab, r->data.ptr, a.data.ptr, a.count * 2 * a.limbs, map_q(a.limbs), chain_const_of(c, k), c.stream);
+    ++c.n_launch;
+    return r;
+}
+
+Ct neg(ckks_ctx &c, const ckks_ct &a) { return mul_int(c, a, -1); }
+
+Ct add_const(ckks_ctx &c, const ckks_ct &a, double v) {
+    Ct r = clone(c, a);
+    i64 k = round_half_away(v * a.scale);
+    k_add_const_c0(c.tab, r->data.ptr, a.count, a.limbs, chain_const_of(c, k), c.stream);
+    ++c.n_launch;
+    return r;
+}
+
+// Rescale: round(c / q_last) on the centred integer, per limb (c_i - [c_last]_centred) * q_last^-1 mod q_i.
+Ct rescale(ckks_ctx &c, const ckks_ct &a) {
+    const int l = a.limbs, n = c.p.n, rows = a.count * 2;
+    if (l < 2) throw Error(CKKS_E_LEVEL, "no limb left to rescale");
+    const size_t N = (size_t)n;
+    DBuf last(c.pool.get(), (size_t)rows * N);
+    k_copy_rows(last.ptr, N, a.data.ptr + (size_t)(l - 1) * N, (size_t)l * N, rows, N, c.stream);
+    ntt_inv(c, last.ptr, rows, ModMap{1, 0, l - 1});
+    DBuf t(c.pool.get(), (size_t)rows * (l - 1) * N);
+    k_extend(c.tab, t.ptr, last.ptr, rows, l - 1, map_q(l - 1), l - 1, true, c.stream);
+    ntt_fwd(c, t.ptr, rows * (l - 1), map_q(l - 1));
+    DBuf head(c.pool.get(), (size_t)rows * (l - 1) * N);
+    k_copy_rows(head.ptr, (size_t)(l - 1) * N, a.data.ptr, (size_t)l * N, rows, (size_t)(l - 1) * N, c.stream);
+    Ct r = new_ct(c, a.count, a.depth + 1, a.scale);
+    k_sub_mul_const(c.tab, r->data.ptr, head.ptr, t.ptr, rows * (l - 1), map_q(l - 1), chain_inv_of(c, c.p.q[l - 1]),
+                    false, c.stream);
+    c.n_launch += 5;
+    return r;
+}
+
+Ct mod_drop(ckks_ctx &c, const ckks_ct &a, int depth) {
+    if (depth == a.depth) return clone(c, a);
+    if (depth < a.depth) throw Error(CKKS_E_LEVEL, "mod-drop to a shallower depth");
+    Ct r = new_ct(c, a.count, depth, a.scale);
+    const size_t N = (size_t)c.p.n;
+    k_copy_rows(r->data.ptr, (size_t)r->limbs * N, a.data.ptr, (size_t)a.limbs * N, a.count * 2, (size_t)r->limbs * N,
+                c.stream);
+    ++c.n_launch;
+    return r;
+}
+
+Ct mul_const(ckks_ctx &c, const ckks_ct &a, double v) {
+    const u64 q = c.p.dropped_at(a.depth);
+    Ct t = mul_int(c, a, round_half_away(v * a.scale));
+    Ct r = rescale(c, *t);
+    r->scale = (a.scale * a.scale) / (double)q;
+    return r;
+}
+
+Ct mul_mask(ckks_ctx &c, const ckks_ct &a, int R) {
+    const u64 q = c.p.dropped_at(a.depth);
+    const int n = c.p.n, l = a.limbs;
+    std::vector<i64> h(n);
+    mask_poly(n, R, a.scale, h.data());
+    DBuf small(c.pool.get(), (size_t)n);
+    GCK_HIP(hipMemcpyAsync(small.ptr, h.data(), (size_t)n * 8, hipMemcpyHostToDevice, c.stream));
+    sync(c);   // the host vector goes out of scope
+    DBuf pt(c.pool.get(), (size_t)l * n);
+    k_signed_to_limbs(c.tab, pt.ptr, reinterpret_cast<const i64 *>(small.ptr), l, map_q(l), c.stream);
+    ntt_fwd(c, pt.ptr, l, map_q(l));
+    Ct t = new_ct(c, a.count, a.depth, a.scale);
+    k_mul(c.tab, t->data.ptr, a.data.ptr, pt.ptr, a.count * 2 * l, map_q(l), a.count * 2 * l, l, c.stream);
+    c.n_launch += 2;
+    Ct r = rescale(c, *t);
+    r->scale = (a.scale * a.scale) / (double)q;
+    return r;
+}
+
+Ct align(ckks_ctx &c, const ckks_ct &a, int depth, double scale, double factor) {
+    if (depth == a.depth && scale == a.scale && factor == 1.0) return clone(c, a);
+    if (depth <= a.depth) throw Error(CKKS_E_LEVEL, "align needs a deeper target depth");
+    Ct t = mod_drop(c, a, depth - 1);
+    const u64 q = c.p.dropped_at(depth - 1);
+    i64 k = round_half_away(((scale * factor) * (double)q) / a.scale);
+    Ct u = mul_int(c, *t, k);
+    Ct r = rescale(c, *u);
+    r->scale = scale;
+    return r;
+}
+
+Ct set_scale(ckks_ctx &, Ct a, double factor) {
+    a->scale *= factor;
+    return a;
+}
+
+bool has_key(const ckks_ctx &c, u64 id) { return c.ksk.count(id) != 0; }
+
+// Key switch of d = [count][l][N] (NTT form) with key `id`: round(sum_j [d]_{q_j} ksk_j / P).
+// Output [count][2][l][N] in NTT form.
+static DBuf keyswitch(ckks_ctx &c, const u64 *d, int count, int l, u64 id) {
+    auto it = c.ksk.find(id);
+    if (it == c.ksk.end()) throw Error(CKKS_E_KEY_MISSING, "missing switching key " + std::to_string(id));
+    const size_t N = (size_t)c.p.n;
+    const int P = c.p.p_index();
+    // ModUp: coefficient form of every digit, reduced modulo every target, back to NTT form
+    DBuf dc(c.pool.get(), (size_t)count * l * N);
+    GCK_HIP(hipMemcpyAsync(dc.ptr, d, (size_t)count * l * N * 8, hipMemcpyDeviceToDevice, c.stream));
+    ntt_inv(c, dc.ptr, count * l, map_q(l));
+    DBuf dig(c.pool.get(), (size_t)count * l * (l + 1) * N);
+    k_modup(c.tab, dig.ptr, dc.ptr, count, l, P, c.stream);
+    dc.release();
+    ntt_fwd(c, dig.ptr, count * l * (l + 1), ModMap{l + 1, l, P});
+    // inner product with the key
+    DBuf acc(c.pool.get(), (size_t)count * 2 * (l + 1) * N);
+    k_ks_inner(c.tab, acc.ptr, dig.ptr, it->second.ptr, count, l, c.p.levels, c.stream);
+    dig.release();
+    // ModDown: round(x / P) = (x - [x]_P centred) * P^-1
+    const int rows = count * 2;
+    DBuf ap(c.pool.get(), (size_t)rows * N);
+    k_copy_rows(ap.ptr, N, acc.ptr + (size_t)l * N, (size_t)(l + 1) * N, rows, N, c.stream);
+    ntt_inv(c, ap.ptr, rows, ModMap{1, 0, P});
+    DBuf t(c.pool.get(), (size_t)rows * l * N);
+    k_extend(c.tab, t.ptr, ap.ptr, rows, l, map_q(l), P, true, c.stream);
+    ntt_fwd(c, t.ptr, rows * l, map_q(l));
+    DBuf head(c.pool.get(), (size_t)rows * l * N);
+    k_copy_rows(head.ptr, (size_t)l * N, acc.ptr, (size_t)(l + 1) * N, rows, (size_t)l * N, c.stream);
+    DBuf out(c.pool.get(), (size_t)rows * l * N);
+    k_sub_mul_const(c.tab, out.ptr, head.ptr, t.ptr, rows * l, map_q(l), chain_inv_of(c, c.p.P), false, c.stream);
+    c.n_launch += 7;
+    ++c.n_keyswitch;
+    return out;
+}
+
+Ct mul_sum(ckks_ctx &c, const std::vector<std::pair<const ckks_ct *, const ckks_ct *>> &pairs) {
+    if (pairs.empty()) throw Error(CKKS_E_INVALID_ARG, "empty product sum");
+    const ckks_ct &a0 = *pairs[0].first, &b0 = *pairs[0].second;
+    const double s = a0.scale * b0.scale;
+    int count = 1;
+    for (auto &pr : pairs) {
+        if (pr.first->depth != a0.depth || pr.second->depth != a0.depth)
+            throw Error(CKKS_E_PARAM_MISMATCH, "product operands at different depths");
+        if (pr.first->scale * pr.second->scale != s)
+            throw Error(CKKS_E_PARAM_MISMATCH, "lazy sum of products with different scales");
+        count = std::max(count, std::max(pr.first->count, pr.second->count));
+    }
+    for (auto &pr : pairs)
+        if ((pr.first->count != 1 && pr.first->count != count) || (pr.second->count != 1 && pr.second->count != count))
+            throw Error(CKKS_E_PARAM_MISMATCH, "batch counts differ");
+    const int l = a0.limbs;
+    const size_t N = (size_t)c.p.n;
+    DBuf d(c.pool.get(), (size_t)count * 3 * l * N);
+    for (size_t i = 0; i < pairs.size(); ++i) {
+        k_tensor(c.tab, d.ptr, pairs[i].first->data.ptr, pairs[i].second->data.ptr, count, l, pairs[i].first->count,
+                 pairs[i].second->count, i > 0, c.stream);
+        ++c.n_launch;
+    }
+    // relinearise: (d0, d1) + KS(d2, s^2 key)
+    DBuf d2(c.pool.get(), (size_t)count * l * N);
+    k_copy_rows(d2.ptr, (size_t)l * N, d.ptr + (size_t)2 * l * N, (size_t)3 * l * N, count, (size_t)l * N, c.stream);
+    DBuf ks = keyswitch(c, d2.ptr, count, l, 0);
+    d2.release();
+    k_add_rows(c.tab, ks.ptr, (size_t)2 * l * N, d.ptr, (size_t)3 * l * N, count, l, c.stream);
+    k_add_rows(c.tab, ks.ptr + (size_t)l * N, (size_t)2 * l * N, d.ptr + (size_t)l * N, (size_t)3 * l * N, count, l,
+               c.stream);
+    c.n_launch += 3;
+    d.release();
+    ckks_ct tmp;
+    tmp.ctx = &c;
+    tmp.count = count;
+    tmp.depth = a0.depth;
+    tmp.limbs = l;
+    tmp.scale = a0.scale;
+    tmp.data = std::move(ks);
+    const u64 q = c.p.dropped_at(a0.depth);
+    Ct r = rescale(c, tmp);
+    r->scale = (a0.scale * b0.scale) / (double)q;
+    return r;
+}
+
+Ct mul(ckks_ctx &c, const ckks_ct &a, const ckks_ct &b) { return mul_sum(c, {{&a, &b}}); }
+
+u64 galois_rotate(const ckks_ctx &c, i64 r) {
+    const u64 m = 2ULL * (u64)c.p.n;
+    i64 rr = r % (c.p.n / 2);
+    if (rr < 0) rr += c.p.n / 2;   // 5 has order N/2 modulo 2N
+    return powmod_host(5, (u64)rr, m);
+}
+
+u64 galois_conj(const ckks_ctx &c) { return 2ULL * (u64)c.p.n - 1; }
+
+Ct apply_galois(ckks_ctx &c, const ckks_ct &a, u64 g) {
+    if (!has_key(c, g)) throw Error(CKKS_E_KEY_MISSING, "missing Galois key for element " + std::to_string(g));
+    const int l = a.limbs;
+    const size_t N = (size_t)c.p.n;
+    DBuf t(c.pool.get(), (size_t)a.count * 2 * l * N);
+    k_automorph(c.tab, t.ptr, a.data.ptr, a.count * 2 * l, g, c.stream);
+    DBuf c1(c.pool.get(), (size_t)a.count * l * N);
+    k_copy_rows(c1.ptr, (size_t)l * N, t.ptr + (size_t)l * N, (size_t)2 * l * N, a.count, (size_t)l * N, c.stream);
+    DBuf ks = keyswitch(c, c1.ptr, a.count, l, g);
+    k_add_rows(c.tab, ks.ptr, (size_t)2 * l * N, t.ptr, (size_t)2 * l * N, a.count, l, c.stream);
+    c.n_launch += 3;
+    Ct r(new ckks_ct());
+    r->ctx = &c;
+    r->count = a.count;
+    r->depth = a.depth;
+    r->limbs = l;
+    r->scale = a.scale;
+    r->data = std::move(ks);
+    return r;
+}
+
+Ct rotate(ckks_ctx &c, const ckks_ct &a, i64 r) { return apply_galois(c, a, galois_rotate(c, r)); }
+Ct conjugate(ckks_ctx &c, const ckks_ct &a) { return apply_galois(c, a, galois_conj(c)); }
+
+// ---------------------------------------------------------------- keys
+
+static u64 os_seed() {
+    std::random_device rd;
+    u64 s = ((u64)rd() << 32) ^ (u64)rd();
+    return s ? s : 1;
+}
+
+static u64 sm_mix_host(u64 z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+static u64 sm_out_host(u64 x, u64 i) { return sm_mix_host(x + (i + 1) * 0x9E3779B97F4A7C15ULL); }
+
+// HWT(h) secret: positions w mod N of successive stream words, sign from the top bit, repeats skipped.
+static std::vector<i64> sample_hwt_host(u64 seed, u64 sid, int n, int h) {
+    std::vector<i64> s(n, 0);
+    const u64 st = sm_out_host(seed, sid);
+    int got = 0;
+    if (h > n) h = n;
+    for (u64 cc = 0; got < h; ++cc) {
+        u64 w = sm_out_host(st, cc);
+        int pos = (int)(w % (u64)n);
+        if (s[pos]) continue;
+        s[pos] = (w >> 63) ? -1 : 1;
+        ++got;
+    }
+    return s;
+}
+
+static u64 ksk_sid_base(u64 key_id) { return (1ULL << 40) | (key_id << 20); }
+
+// switching key for target secret sp (NTT form, L+1 limbs over q_0..q_L) under key id
+static void make_switching_key(ckks_ctx &c, u64 seed, u64 key_id, const u64 *sp) {
+    const int L = c.p.levels, nt = L + 2, nd = L + 1, P = c.p.p_index();
+    const size_t N = (size_t)c.p.n;
+    const ModMap mt{nt, L + 1, P};          // targets q_0..q_L, P
+    DBuf key(c.pool.get(), (size_t)2 * nd * nt * N);
+    DBuf e_small(c.pool.get(), N);
+    DBuf as(c.pool.get(), (size_t)nt * N);
+    const u64 base = ksk_sid_base(key_id);
+    for (int j = 0; j < nd; ++j) {
+        u64 *b = key.ptr + (size_t)j * nt * N;
+        u64 *a = key.ptr + ((size_t)nd + j) * nt * N;
+        k_sample_uniform(c.tab, a, seed, base + 2ULL * j, nt, mt, P, c.stream);
+        ntt_fwd(c, a, nt, mt);
+        k_sample_cbd(reinterpret_cast<i64 *>(e_small.ptr), seed, base + 2ULL * j + 1, (int)N, c.stream);
+        k_signed_to_limbs(c.tab, b, reinterpret_cast<const i64 *>(e_small.ptr), nt, mt, c.stream);
+        ntt_fwd(c, b, nt, mt);
+        k_mul(c.tab, as.ptr, a, c.sk_ntt.ptr, nt, mt, nt, nt, c.stream);
+        k_sub(c.tab, b, b, as.ptr, nt, mt, nt, nt, c.stream);
+        // + (P mod q_j) s'_j on target j
+        ChainConst pj = chain_const_of(c, 0);
+        {
+            u64 q = c.p.q[j];
+            u64 v = c.p.P % q;
+            for (int i = 0; i < kMaxMods; ++i) { pj.v[i] = 0; pj.sh[i] = 0; }
+            pj.v[j] = v;
+            pj.sh[j] = (u64)(((u128)v << 64) / q);
+        }
+        k_mul_const(c.tab, as.ptr, sp + (size_t)j * N, 1, ModMap{1, 0, j}, pj, c.stream);
+        k_add(c.tab, b + (size_t)j * N, b + (size_t)j * N, as.ptr, 1, ModMap{1, 0, j}, 1, 1, c.stream);
+        c.n_launch += 8;
+    }
+    k_to_mont(c.tab, key.ptr, 2 * nd * nt, mt, c.stream);
+    c.ksk[key_id] = std::move(key);
+}
+
+void keygen(ckks_ctx &c, u64 seed, const std::vector<u64> &galois) {
+    if (seed == 0) seed = os_seed();
+    const int L = c.p.levels, P = c.p.p_index(), nt = L + 2;
+    const int n = c.p.n;
+    const size_t N = (size_t)n;
+    const ModMap mt{nt, L + 1, P};
+    c.ksk.clear();
+    c.sk = sample_hwt_host(seed, 1, n, std::min(64, n / 2));
+    DBuf small(c.pool.get(), N);
+    GCK_HIP(hipMemcpyAsync(small.ptr, c.sk.data(), N * 8, hipMemcpyHostToDevice, c.stream));
+    c.sk_ntt = DBuf(c.pool.get(), (size_t)nt * N);
+    k_signed_to_limbs(c.tab, c.sk_ntt.ptr, reinterpret_cast<const i64 *>(small.ptr), nt, mt, c.stream);
+    ntt_fwd(c, c.sk_ntt.ptr, nt, mt);
+    // public key over q_0..q_L
+    c.pk = DBuf(c.pool.get(), (size_t)2 * (L + 1) * N);
+    u64 *pb = c.pk.ptr, *pa = c.pk.ptr + (size_t)(L + 1) * N;
+    k_sample_uniform(c.tab, pa, seed, 2, L + 1, map_q(L + 1), P, c.stream);
+    ntt_fwd(c, pa, L + 1, map_q(L + 1));
+    k_sample_cbd(reinterpret_cast<i64 *>(small.ptr), seed, 3, n, c.stream);
+    k_signed_to_limbs(c.tab, pb, reinterpret_cast<const i64 *>(small.ptr), L + 1, map_q(L + 1), c.stream);
+    ntt_fwd(c, pb, L + 1, map_q(L + 1));
+    DBuf as(c.pool.get(), (size_t)(L + 1) * N);
+    k_mul(c.tab, as.ptr, pa, c.sk_ntt.ptr, L + 1, map_q(L + 1), L + 1, L + 1, c.stream);
+    k_sub(c.tab, pb, pb, as.ptr, L + 1, map_q(L + 1), L + 1, L + 1, c.stream);
+    // relinearisation key: s' = s^2
+    DBuf sp(c.pool.get(), (size_t)(L + 1) * N);
+    k_mul(c.tab, sp.ptr, c.sk_ntt.ptr, c.sk_ntt.ptr, L + 1, map_q(L + 1), L + 1, L + 1, c.stream);
+    make_switching_key(c, seed, 0, sp.ptr);
+    // Galois keys: s' = s(X^g), an NTT-domain permutation of s
+    for (u64 g : galois) {
+        if ((g & 1) == 0 || g >= 2ULL * N) throw Error(CKKS_E_INVALID_ARG, "Galois element must be odd and < 2N");
+        if (c.ksk.count(g)) continue;
+        k_automorph(c.tab, sp.ptr, c.sk_ntt.ptr, L + 1, g, c.stream);
+        make_switching_key(c, seed, g, sp.ptr);
+    }
+    c.have_keys = true;
+    sync(c);
+}
+
+Ct encrypt(ckks_ctx &c, const i64 *m, int depth, double scale, u64 seed) {
+    if (!c.have_keys) throw Error(CKKS_E_KEY_MISSING, "keygen has not been run");
+    if (seed == 0) seed = os_seed();
+    const int n = c.p.n;
+    const size_t N = (size_t)n;
+    Ct r = new_ct(c, 1, depth, scale);
+    const int l = r->limbs;
+    DBuf sm(c.pool.get(), 4 * N);   // m, v, e0, e1 (signed)
+    i64 *dm = reinterpret_cast<i64 *>(sm.ptr), *dv = dm + N, *de0 = dm + 2 * N, *de1 = dm + 3 * N;
+    GCK_HIP(hipMemcpyAsync(dm, m, N * 8, hipMemcpyHostToDevice, c.stream));
+    k_sample_ternary(dv, seed, 1, n, c.stream);
+    k_sample_cbd(de0, seed, 2, n, c.stream);
+    k_sample_cbd(de1, seed, 3, n, c.stream);
+    DBuf v(c.pool.get(), (size_t)l * N), t(c.pool.get(), (size_t)l * N);
+    k_signed_to_limbs(c.tab, v.ptr, dv, l, map_q(l), c.stream);
+    ntt_fwd(c, v.ptr, l, map_q(l));
+    u64 *c0 = r->data.ptr, *c1 = r->data.ptr + (size_t)l * N;
+    // c0 = v pk0 + m + e0
+    k_mul(c.tab, c0, v.ptr, c.pk.ptr, l, map_q(l), l, l, c.stream);
+    k_signed_to_limbs(c.tab, t.ptr, dm, l, map_q(l), c.stream);
+    ntt_fwd(c, t.ptr, l, map_q(l));
+    k_add(c.tab, c0, c0, t.ptr, l, map_q(l), l, l, c.stream);
+    k_signed_to_limbs(c.tab, t.ptr, de0, l, map_q(l), c.stream);
+    ntt_fwd(c, t.ptr, l, map_q(l));
+    k_add(c.tab, c0, c0, t.ptr, l, map_q(l), l, l, c.stream);
+    // c1 = v pk1 + e1
+    k_mul(c.tab, c1, v.ptr, c.pk.ptr + (size_t)(c.p.levels + 1) * N, l, map_q(l), l, l, c.stream);
+    k_signed_to_limbs(c.tab, t.ptr, de1, l, map_q(l), c.stream);
+    ntt_fwd(c, t.ptr, l, map_q(l));
+    k_add(c.tab, c1, c1, t.ptr, l, map_q(l), l, l, c.stream);
+    sync(c);   // the caller's host buffer m may be reused after return
+    return r;
+}
+
+std::vector<long double> decrypt_poly(ckks_ctx &c, const ckks_ct &a, int index) {
+    if (!c.have_keys) throw Error(CKKS_E_KEY_MISSING, "keygen has not been run");
+    const int n = c.p.n;
+    const size_t N = (size_t)n;
+    const int l = a.limbs, lu = std::min(l, 2);
+    const u64 *c0 = a.data.ptr + (size_t)index * 2 * l * N, *c1 = c0 + (size_t)l * N;
+    DBuf t(c.pool.get(), (size_t)lu * N);
+    k_mul(c.tab, t.ptr, c1, c.sk_ntt.ptr, lu, map_q(lu), lu, lu, c.stream);
+    k_add(c.tab, t.ptr, t.ptr, c0, lu, map_q(lu), lu, lu, c.stream);
+    ntt_inv(c, t.ptr, lu, map_q(lu));
+    std::vector<u64> h((size_t)lu * N);
+    GCK_HIP(hipMemcpyAsync(h.data(), t.ptr, h.size() * 8, hipMemcpyDeviceToHost, c.stream));
+    sync(c);
+    std::vector<long double> out(N);
+    const u64 q0 = c.p.q[0];
+    if (lu == 1) {
+        for (size_t k = 0; k < N; ++k) {
+            u64 x = h[k];
+            out[k] = x > q0 / 2 ? -(long double)(q0 - x) : (long double)x;
+        }
+    } else {
+        const u64 q1 = c.p.q[1];
+        const u64 inv = invmod_host(q0 % q1, q1);
+        const u128 Q = (u128)q0 * q1;
+        for (size_t k = 0; k < N; ++k) {
+            u64 x0 = h[k], x1 = h[N + k];
+            u64 d = (x1 + q1 - x0 % q1) % q1;
+            u64 tq = mulmod_host(d, inv, q1);
+            u128 x = (u128)x0 + (u128)q0 * tq;
+            out[k] = x > Q / 2 ? -(long double)(Q - x) : (long double)x;
+        }
+    }
+    return out;
+}
+
+void export_ct(ckks_ctx &c, const ckks_ct &a, int index, u64 *out) {
+    const size_t N = (size_t)c.p.n;
+    const int l = a.limbs;
+    DBuf t(c.pool.get(), (size_t)2 * l * N);
+    GCK_HIP(hipMemcpyAsync(t.ptr, a.data.ptr + (size_t)index * 2 * l * N, (size_t)2 * l * N * 8,
+                           hipMemcpyDeviceToDevice, c.stream));
+    ntt_inv(c, t.ptr, 2 * l, map_q(l));
+    GCK_HIP(hipMemcpyAsync(out, t.ptr, (size_t)2 * l * N * 8, hipMemcpyDeviceToHost, c.stream));
+    sync(c);
+}
+
+Ct import_ct(ckks_ctx &c, const u64 *in, int depth, double scale) {
+    Ct r = new_ct(c, 1, depth, scale);
+    const int l = r->limbs;
+    const size_t N = (size_t)c.p.n;
+    for (int i = 0; i < 2 * l; ++i) {
+        const u64 q = c.p.q[i % l];
+        for (size_t k = 0; k < N; ++k)
+            if (in[(size_t)i * N + k] >= q) throw Error(CKKS_E_INVALID_ARG, "imported residue out of range");
+    }
+    GCK_HIP(hipMemcpyAsync(r->data.ptr, in, (size_t)2 * l * N * 8, hipMemcpyHostToDevice, c.stream));
+    ntt_fwd(c, r->data.ptr, 2 * l, map_q(l));
+    sync(c);
+    return r;
+}
+
+}  // namespace gck
+
+// ---------------------------------------------------------------- context teardown
+ckks_ctx::~ckks_ctx() {
+    if (stream) hipStreamSynchronize(stream);
+    else hipDeviceSynchronize();
+    ksk.clear();
+    sk_ntt.release();
+    pk.release();
+    pool.reset();
+    if (table_mem) hipFree(table_mem);
+}

@@ -1,0 +1,82 @@
+// Context, ciphertext batches and the evaluation operations (host driver over the HIP kernels).
+#pragma once
+
+#include "ckks_internal.h"
+
+struct ckks_ct;
+
+struct ckks_ctx {
+    gck::Params p;
+    gck::DevTables tab;
+    std::vector<gck::ModInfo> h_mods;
+    hipStream_t stream = nullptr;
+    std::unique_ptr<gck::Pool> pool;
+    void *table_mem = nullptr;     // device tables (hipMalloc, outside the pool)
+    // keys
+    bool have_keys = false;
+    std::vector<int64_t> sk;       // secret, signed coefficients
+    gck::DBuf sk_ntt;              // [L+2][N]: s mod q_0..q_L, P in NTT form
+    gck::DBuf pk;                  // [2][L+1][N] NTT form
+    std::map<uint64_t, gck::DBuf> ksk;   // key id (0 = relinearisation, else Galois element) -> [2][L+1][L+2][N]
+    // counters
+    uint64_t n_keyswitch = 0, n_limb_ntt = 0, n_launch = 0;
+    ~ckks_ctx();
+};
+
+// A batch of `count` ciphertexts at the same depth and tracked scale, data [count][2][limbs][N] in
+// NTT form (this library's evaluation order).
+struct ckks_ct {
+    ckks_ctx *ctx = nullptr;
+    int count = 0, depth = 0, limbs = 0;
+    double scale = 0;
+    gck::DBuf data;
+};
+
+namespace gck {
+
+using Ct = std::unique_ptr<ckks_ct>;
+
+Ct new_ct(ckks_ctx &c, int count, int depth, double scale);
+Ct clone(ckks_ctx &c, const ckks_ct &a);
+
+void ntt_fwd(ckks_ctx &c, u64 *buf, int n_limbs, ModMap m);
+void ntt_inv(ckks_ctx &c, u64 *buf, int n_limbs, ModMap m);
+
+// ---- scheme operations (count-batched; operands with count 1 broadcast)
+Ct add(ckks_ctx &c, const ckks_ct &a, const ckks_ct &b);
+Ct sub(ckks_ctx &c, const ckks_ct &a, const ckks_ct &b);
+Ct neg(ckks_ctx &c, const ckks_ct &a);
+Ct mul_int(ckks_ctx &c, const ckks_ct &a, i64 k);
+Ct add_const(ckks_ctx &c, const ckks_ct &a, double v);
+Ct rescale(ckks_ctx &c, const ckks_ct &a);
+Ct mod_drop(ckks_ctx &c, const ckks_ct &a, int depth);
+Ct mul_const(ckks_ctx &c, const ckks_ct &a, double v);
+Ct mul_mask(ckks_ctx &c, const ckks_ct &a, int R);
+Ct align(ckks_ctx &c, const ckks_ct &a, int depth, double scale, double factor);
+Ct set_scale(ckks_ctx &c, Ct a, double factor);
+// sum_i a_i * b_i: one tensor per pair accumulated, one relinearisation, one rescale
+Ct mul_sum(ckks_ctx &c, const std::vector<std::pair<const ckks_ct *, const ckks_ct *>> &pairs);
+Ct mul(ckks_ctx &c, const ckks_ct &a, const ckks_ct &b);
+Ct apply_galois(ckks_ctx &c, const ckks_ct &a, u64 g);
+Ct rotate(ckks_ctx &c, const ckks_ct &a, i64 r);
+Ct conjugate(ckks_ctx &c, const ckks_ct &a);
+u64 galois_rotate(const ckks_ctx &c, i64 r);
+u64 galois_conj(const ckks_ctx &c);
+bool has_key(const ckks_ctx &c, u64 id);
+
+// ---- keys / encryption
+void keygen(ckks_ctx &c, u64 seed, const std::vector<u64> &galois);
+Ct encrypt(ckks_ctx &c, const i64 *m, int depth, double scale, u64 seed);
+// c0 + c1 s in coefficient form, centred over q_0 (q_0 q_1 when limbs >= 2), as long doubles
+std::vector<long double> decrypt_poly(ckks_ctx &c, const ckks_ct &a, int index);
+void export_ct(ckks_ctx &c, const ckks_ct &a, int index, u64 *out);
+Ct import_ct(ckks_ctx &c, const u64 *in, int depth, double scale);
+
+// ---- host math (encode.cpp)
+void encode_poly(int n, const double *re, const double *im, size_t n_slots, double scale, i64 *out);
+void decode_poly(int n, const double *coeffs, double *re, double *im);
+void mask_poly(int n, int R, double scale, i64 *out);
+
+void sync(ckks_ctx &c);
+
+}  // namespace gck

@@ -1,0 +1,344 @@
+// The encrypted modified semi-parallel GWAS (paper: Alg. Semi Parallel GWAS with Alg. Homomorphic
+// LogReg and Alg. inverseSlots) on the device evaluator.
+//
+// Layout (paper: Methods, "Homomorphic Matrix Operations" and "Batching SNPs"):
+//   R = PO2(n) rows per block, B = N / (2R) blocks, tau = 2B = N / R SNPs per ciphertext.
+//   x_j and y are R-periodic (slot s holds v[s mod R] for s mod R < n, else 0): a CP column duplicated
+//   into every block, so the log2(R)-step rotate-and-sum leaves the full dot product in every slot.
+//   A_jl = ((X^T X)^-1)_jl are replicated scalars, encrypted at depth 0 with scale R * Delta_0.
+//   SNP batch b is complex-packed CCP: slot c R + r holds S[r, b tau + 2c] + i S[r, b tau + 2c + 1].
+// The projection M S (eqs. M and Sprime) is applied as S - sum_j x_j (.) bcast(mask (.) colSum(r_j (.) S))
+// with r_j = sum_l A_jl x_l, all SNP batches of a chunk in one batched ciphertext.
+#include <algorithm>
+#include <cmath>
+
+#include "gwas.h"
+
+namespace gck {
+
+int circuit_levels(int kappa) { return 7 * kappa + 5; }
+int snp_depth(int kappa) { return 7 * kappa; }
+
+Layout make_layout(int n_ring, int n, int k, int m) {
+    if (n < 2 || k < 1 || m < 1) throw Error(CKKS_E_INVALID_ARG, "need n >= 2, k >= 1, m >= 1");
+    Layout L;
+    L.N = n_ring;
+    L.n = n;
+    L.k = k;
+    L.m = m;
+    L.R = 1;
+    while (L.R < n) L.R *= 2;
+    if (2 * L.R > n_ring) throw Error(CKKS_E_INVALID_ARG, "n too large for the ring: need PO2(n) <= N/2");
+    L.blocks = n_ring / (2 * L.R);
+    L.tau = 2 * L.blocks;
+    L.n_batches = (m + L.tau - 1) / L.tau;
+    return L;
+}
+
+std::vector<u64> required_galois(const ckks_ctx &c, int R) {
+    std::vector<u64> g;
+    for (int i = 1; i < R; i *= 2) {
+        g.push_back(galois_rotate(c, i));
+        g.push_back(galois_rotate(c, -i));
+    }
+    g.push_back(galois_conj(c));
+    return g;
+}
+
+namespace {
+
+struct Circ {
+    ckks_ctx &c;
+    const Layout &lay;
+    explicit Circ(ckks_ctx &cc, const Layout &l) : c(cc), lay(l) {}
+
+    // a at depth d and the canonical scale; factor multiplies the value
+    Ct at(const ckks_ct &a, int d, double factor = 1.0) {
+        if (d == a.depth && factor == 1.0) return clone(c, a);
+        return align(c, a, d, c.p.scales[d], factor);
+    }
+    Ct rot_sum(Ct a) {   // a <- a + Rot(a, 2^i), i < log2 R (Alg. colSum / Alg. DotProd)
+        for (int i = 1; i < lay.R; i *= 2) {
+            Ct r = rotate(c, *a, i);
+            a = add(c, *a, *r);
+        }
+        return a;
+    }
+    Ct bcast(Ct a) {     // a <- a + Rot(a, -2^i): the first slot of each block over the block
+        for (int i = 1; i < lay.R; i *= 2) {
+            Ct r = rotate(c, *a, -i);
+            a = add(c, *a, *r);
+        }
+        return a;
+    }
+    Ct msum(const std::vector<std::pair<const ckks_ct *, const ckks_ct *>> &p) { return mul_sum(c, p); }
+
+    // sigma7 of u = eta / 8 at the canonical scale (eq. sigma7, signs of the odd terms as a sigmoid)
+    Ct sigma7(const ckks_ct &u) {
+        const int d = u.depth;
+        Ct u2 = mul(c, u, u);
+        Ct a1 = add_const(c, *mul_const(c, *u2, -kSigma7C3), kSigma7C1);
+        Ct a2 = add_const(c, *mul_const(c, *u2, -kSigma7C7), kSigma7C5);
+        Ct u4 = mul(c, *u2, *u2);
+        Ct b = mul(c, *u4, *a2);
+        Ct cc = add(c, *at(*a1, d + 3), *b);
+        Ct pr = mul(c, *at(u, d + 3), *cc);
+        return add_const(c, *pr, 0.5);
+    }
+};
+
+}  // namespace
+
+void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
+    const Layout &lay = in.lay;
+    const int k = lay.k;
+    if (c.p.levels != circuit_levels(in.kappa))
+        throw Error(CKKS_E_LEVEL, "the chain has " + std::to_string(c.p.levels) + " levels, the circuit needs " +
+                                      std::to_string(circuit_levels(in.kappa)));
+    for (u64 g : required_galois(c, lay.R))
+        if (!has_key(c, g)) throw Error(CKKS_E_KEY_MISSING, "missing Galois key " + std::to_string(g));
+    if (!has_key(c, 0)) throw Error(CKKS_E_KEY_MISSING, "missing relinearisation key");
+    Circ C(c, lay);
+    auto A = [&](int j, int l) -> const ckks_ct & { return *in.A[a_index(k, std::min(j, l), std::max(j, l))]; };
+    std::vector<const ckks_ct *> x(k);
+    for (int j = 0; j < k; ++j) x[j] = in.x[j].get();
+    const ckks_ct &y = *in.y;
+
+    // ---- Alg. Homomorphic LogReg, first pass: beta = 0, so p = sigma7(0) = 1/2 is public
+    Ct r = add_const(c, y, -0.5);
+    std::vector<Ct> A1(k * k);
+    for (int j = 0; j < k; ++j)
+        for (int l = 0; l < k; ++l) A1[j * k + l] = C.at(A(j, l), 1);
+    std::vector<Ct> g(k), beta(k);
+    for (int j = 0; j < k; ++j) g[j] = C.rot_sum(mul(c, *x[j], *r));
+    for (int j = 0; j < k; ++j) {
+        std::vector<std::pair<const ckks_ct *, const ckks_ct *>> p;
+        for (int l = 0; l < k; ++l) p.push_back({A1[j * k + l].get(), g[l].get()});
+        beta[j] = mul_int(c, *C.msum(p), 4);
+    }
+    Ct pk;
+    for (int t = 1; t < in.kappa; ++t) {
+        const int d = beta[0]->depth;
+        std::vector<Ct> xs(k);
+        std::vector<std::pair<const ckks_ct *, const ckks_ct *>> p;
+        for (int j = 0; j < k; ++j) {
+            xs[j] = C.at(*x[j], d, 0.125);     // the 1/8 of sigma7's argument
+            p.push_back({xs[j].get(), beta[j].get()});
+        }
+        Ct u = C.msum(p);
+        pk = C.sigma7(*u);
+        const int dp = pk->depth;
+        r = sub(c, *C.at(y, dp), *pk);
+        for (int j = 0; j < k; ++j) g[j] = C.rot_sum(mul(c, *C.at(*x[j], dp), *r));
+        const int dg = g[0]->depth;
+        std::vector<Ct> Ag(k * k);
+        for (int j = 0; j < k; ++j)
+            for (int l = 0; l < k; ++l) Ag[j * k + l] = C.at(A(j, l), dg);
+        for (int j = 0; j < k; ++j) {
+            std::vector<std::pair<const ckks_ct *, const ckks_ct *>> q;
+            for (int l = 0; l < k; ++l) q.push_back({Ag[j * k + l].get(), g[l].get()});
+            Ct inc = mul_int(c, *C.msum(q), 4);
+            beta[j] = add(c, *C.at(*beta[j], inc->depth), *inc);
+        }
+    }
+    // ---- w = p (1 - p), Alg. inverseSlots: guess 3, the first Newton step is 6 - 9 w
+    Ct w = mul(c, *pk, *add_const(c, *neg(c, *pk), 1.0));
+    Ct gi = add_const(c, *mul_int(c, *w, -9), 6.0);
+    for (int it = 0; it < 2; ++it) {
+        Ct wg = mul(c, *C.at(*w, gi->depth), *gi);
+        Ct h = add_const(c, *neg(c, *wg), 2.0);
+        gi = mul(c, *C.at(*gi, h->depth), *h);
+    }
+    Ct w_inv = std::move(gi);
+    // ---- z = X beta^(kappa) + w^-1 (y - p^(kappa-1))
+    const int db = beta[0]->depth;
+    std::vector<Ct> xb(k);
+    std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pb;
+    for (int j = 0; j < k; ++j) {
+        xb[j] = C.at(*x[j], db);
+        pb.push_back({xb[j].get(), beta[j].get()});
+    }
+    Ct xbeta = C.msum(pb);
+    Ct tz = mul(c, *C.at(*r, w_inv->depth), *w_inv);
+    Ct z = add(c, *C.at(*xbeta, tz->depth), *tz);
+    // ---- z' = z - X (A (X^T z))
+    std::vector<Ct> h(k);
+    for (int j = 0; j < k; ++j) h[j] = C.rot_sum(mul(c, *C.at(*x[j], z->depth), *z));
+    const int dh = h[0]->depth;
+    std::vector<Ct> v(k);
+    for (int j = 0; j < k; ++j) {
+        std::vector<Ct> Ah(k);
+        std::vector<std::pair<const ckks_ct *, const ckks_ct *>> q;
+        for (int l = 0; l < k; ++l) {
+            Ah[l] = C.at(A(j, l), dh);
+            q.push_back({Ah[l].get(), h[l].get()});
+        }
+        v[j] = C.msum(q);
+    }
+    const int dv = v[0]->depth;
+    std::vector<Ct> xv(k);
+    std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pv;
+    for (int j = 0; j < k; ++j) {
+        xv[j] = C.at(*x[j], dv);
+        pv.push_back({xv[j].get(), v[j].get()});
+    }
+    Ct xvs = C.msum(pv);
+    Ct z_proj = sub(c, *C.at(*z, xvs->depth), *xvs);
+    Ct u = mul(c, *C.at(*w, z_proj->depth), *z_proj);
+    // ---- r_j = (X A)_{:, j}
+    std::vector<Ct> x1(k), rr(k);
+    for (int l = 0; l < k; ++l) x1[l] = C.at(*x[l], 1);
+    for (int j = 0; j < k; ++j) {
+        std::vector<std::pair<const ckks_ct *, const ckks_ct *>> q;
+        for (int l = 0; l < k; ++l) q.push_back({A1[j * k + l].get(), x1[l].get()});
+        rr[j] = C.msum(q);
+    }
+    for (int j = 0; j < k; ++j) out.beta.push_back(std::move(beta[j]));
+    out.w = clone(c, *w);
+    out.w_inv = std::move(w_inv);
+    out.z_proj = clone(c, *z_proj);
+    out.u = clone(c, *u);
+
+    // ---- per-batch part, chunk by chunk (Alg. Semi Parallel GWAS, batch loop)
+    const int nb = in.S->count;
+    const int ds = in.S->depth;
+    std::vector<Ct> r_s(k), x_c(k);
+    for (int j = 0; j < k; ++j) r_s[j] = C.at(*rr[j], ds);
+    for (int j = 0; j < k; ++j) x_c[j] = C.at(*x[j], ds + 2);
+    Ct u_s = C.at(*u, ds + 3), w_s = C.at(*w, ds + 3);
+    const size_t N = (size_t)c.p.n;
+    for (int b0 = 0; b0 < nb; b0 += chunk) {
+        const int cnt = std::min(chunk, nb - b0);
+        Ct S = new_ct(c, cnt, ds, in.S->scale);
+        const size_t per = (size_t)2 * S->limbs * N;
+        GCK_HIP(hipMemcpyAsync(S->data.ptr, in.S->data.ptr + (size_t)b0 * per, (size_t)cnt * per * 8,
+                               hipMemcpyDeviceToDevice, c.stream));
+        std::vector<Ct> E(k);
+        for (int j = 0; j < k; ++j) {
+            Ct pj = mul(c, *r_s[j], *S);
+            Ct cj = C.rot_sum(std::move(pj));     // column sums at block starts (Alg. colSum)
+            cj = mul_mask(c, *cj, lay.R);         // keep the block starts
+            E[j] = C.bcast(std::move(cj));        // (A X^T S)_{j, c} over block c
+        }
+        std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pe;
+        for (int j = 0; j < k; ++j) pe.push_back({x_c[j].get(), E[j].get()});
+        Ct xe = C.msum(pe);
+        Ct sp = sub(c, *C.at(*S, xe->depth), *xe);
+        Ct num = C.rot_sum(mul(c, *u_s, *sp));
+        Ct ws = mul(c, *w_s, *sp);
+        Ct sc = conjugate(c, *sp);
+        Ct wss = mul(c, *ws, *C.at(*sp, ws->depth));
+        Ct wsc = mul(c, *ws, *C.at(*sc, ws->depth));
+        Ct de = C.rot_sum(set_scale(c, add(c, *wsc, *wss), 2.0));
+        Ct dodd = C.rot_sum(set_scale(c, sub(c, *wsc, *wss), 2.0));
+        out.S_proj.push_back(std::move(sp));
+        out.num.push_back(std::move(num));
+        out.den_even.push_back(std::move(de));
+        out.den_odd.push_back(std::move(dodd));
+    }
+}
+
+// ---------------------------------------------------------------- client side
+
+static std::vector<double> xtx_inverse(const double *X, int n, int k) {
+    std::vector<double> G((size_t)k * k, 0.0);
+    for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b) {
+            double s = 0;
+            for (int i = 0; i < n; ++i) s += X[(size_t)i * k + a] * X[(size_t)i * k + b];
+            G[(size_t)a * k + b] = s;
+        }
+    // Cholesky G = L L^T, then A = L^-T L^-1
+    std::vector<double> L((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double s = G[(size_t)i * k + j];
+            for (int t = 0; t < j; ++t) s -= L[(size_t)i * k + t] * L[(size_t)j * k + t];
+            if (i == j) {
+                if (!(s > 0)) throw Error(CKKS_E_INVALID_ARG, "X^T X is not positive definite");
+                L[(size_t)i * k + i] = std::sqrt(s);
+            } else {
+                L[(size_t)i * k + j] = s / L[(size_t)j * k + j];
+            }
+        }
+    std::vector<double> Li((size_t)k * k, 0.0);
+    for (int col = 0; col < k; ++col)
+        for (int i = 0; i < k; ++i) {
+            double s = (i == col) ? 1.0 : 0.0;
+            for (int t = 0; t < i; ++t) s -= L[(size_t)i * k + t] * Li[(size_t)t * k + col];
+            Li[(size_t)i * k + col] = s / L[(size_t)i * k + i];
+        }
+    std::vector<double> A((size_t)k * k, 0.0);
+    for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b) {
+            double s = 0;
+            for (int t = 0; t < k; ++t) s += Li[(size_t)t * k + a] * Li[(size_t)t * k + b];
+            A[(size_t)a * k + b] = s;
+        }
+    return A;
+}
+
+static u64 input_seed(u64 enc_seed, u64 i) {
+    auto mix = [](u64 z) {
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        return z ^ (z >> 31);
+    };
+    return mix(enc_seed + (i + 1) * 0x9E3779B97F4A7C15ULL);
+}
+
+std::unique_ptr<EncInput> pack_encrypt(ckks_ctx &c, const double *X, const double *y, const uint8_t *S, int n, int k,
+                                       int m, int kappa, u64 enc_seed) {
+    auto in = std::make_unique<EncInput>();
+    in->lay = make_layout(c.p.n, n, k, m);
+    in->kappa = kappa;
+    const Layout &lay = in->lay;
+    const int N = c.p.n, slots = N / 2;
+    std::vector<double> re(slots), im(slots);
+    std::vector<i64> poly(N);
+    u64 idx = 0;
+    auto periodic = [&](auto get) {
+        for (int s = 0; s < slots; ++s) {
+            int r = s % lay.R;
+            re[s] = r < n ? get(r) : 0.0;
+        }
+    };
+    for (int j = 0; j < k; ++j) {
+        periodic([&](int r) { return X[(size_t)r * k + j]; });
+        encode_poly(N, re.data(), nullptr, slots, c.p.scales[0], poly.data());
+        in->x.push_back(encrypt(c, poly.data(), 0, c.p.scales[0], input_seed(enc_seed, idx++)));
+    }
+    periodic([&](int r) { return y[r]; });
+    encode_poly(N, re.data(), nullptr, slots, c.p.scales[0], poly.data());
+    in->y = encrypt(c, poly.data(), 0, c.p.scales[0], input_seed(enc_seed, idx++));
+    const std::vector<double> A = xtx_inverse(X, n, k);
+    const double a_scale = c.p.scales[0] * (double)lay.R;
+    for (int j = 0; j < k; ++j)
+        for (int l = j; l < k; ++l) {
+            std::fill(poly.begin(), poly.end(), 0);
+            poly[0] = round_half_away(A[(size_t)j * k + l] * a_scale);
+            in->A.push_back(encrypt(c, poly.data(), 0, a_scale, input_seed(enc_seed, idx++)));
+        }
+    const int ds = snp_depth(kappa);
+    in->S = new_ct(c, lay.n_batches, ds, c.p.scales[ds]);
+    const size_t per = (size_t)2 * in->S->limbs * N;
+    for (int b = 0; b < lay.n_batches; ++b) {
+        std::fill(re.begin(), re.end(), 0.0);
+        std::fill(im.begin(), im.end(), 0.0);
+        for (int cb = 0; cb < lay.blocks; ++cb) {
+            int j0 = b * lay.tau + 2 * cb;
+            for (int r = 0; r < n; ++r) {
+                if (j0 < m) re[(size_t)cb * lay.R + r] = (double)S[(size_t)r * m + j0];
+                if (j0 + 1 < m) im[(size_t)cb * lay.R + r] = (double)S[(size_t)r * m + j0 + 1];
+            }
+        }
+        encode_poly(N, re.data(), im.data(), slots, c.p.scales[ds], poly.data());
+        Ct one = encrypt(c, poly.data(), ds, c.p.scales[ds], input_seed(enc_seed, idx++));
+        GCK_HIP(hipMemcpyAsync(in->S->data.ptr + (size_t)b * per, one->data.ptr, per * 8, hipMemcpyDeviceToDevice,
+                               c.stream));
+    }
+    sync(c);
+    return in;
+}
+
+}  // namespace gck

@@ -1,0 +1,652 @@
+// HIP kernels of the RNS-CKKS evaluator for gfx950 (CDNA4).
+//
+// All arithmetic is exact modular integer arithmetic on 64-bit words, built on
+// the 32-bit integer VALU (no matrix cores: nothing here is a float
+// contraction).  Residues are kept in [0, q) with q < 2^62.
+//   - fixed-operand products (twiddles, constants): Shoup's method with a
+//     precomputed companion w' = floor(w 2^64 / q);
+//   - variable products: Montgomery reduction (REDC) of the 128-bit product;
+//   - arbitrary 64-bit words: Barrett with floor(2^64 / q).
+// Data layout: contiguous limbs of N words, limb-major; a ModMap gives the
+// chain index of each limb (see ckks_internal.h).
+#include <hip/hip_runtime.h>
+
+#include "ckks_internal.h"
+
+namespace gck {
+
+// ---------------------------------------------------------------- device arithmetic
+
+__device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) {
+    u64 s = a + b;
+    return s >= q ? s - q : s;
+}
+__device__ __forceinline__ u64 sub_mod(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
+
+// a * w mod q for fixed w with companion wsh = floor(w 2^64 / q); any a < 2^64
+__device__ __forceinline__ u64 mul_shoup(u64 a, u64 w, u64 wsh, u64 q) {
+    u64 hi = __umul64hi(a, wsh);
+    u64 r = a * w - hi * q;
+    return r >= q ? r - q : r;
+}
+
+// (hi, lo) * 2^-64 mod q, for hi < q
+__device__ __forceinline__ u64 redc(u64 hi, u64 lo, const ModInfo &M) {
+    u64 m = lo * M.mont_inv;
+    u64 mh = __umul64hi(m, M.q);
+    u64 r = hi + mh + (lo != 0 ? 1 : 0);
+    return r >= M.q ? r - M.q : r;
+}
+
+// a * b mod q for a, b < q
+__device__ __forceinline__ u64 mul_mod(u64 a, u64 b, const ModInfo &M) {
+    u64 t = redc(__umul64hi(a, b), a * b, M);
+    return mul_shoup(t, M.r_mod, M.r_mod_sh, M.q);
+}
+
+// x mod q for any 64-bit x
+__device__ __forceinline__ u64 reduce64(u64 x, const ModInfo &M) {
+    u64 qh = __umul64hi(x, M.barrett);
+    u64 r = x - qh * M.q;
+    return r >= M.q ? r - M.q : r;
+}
+
+__device__ __forceinline__ int chain_of(int lam, ModMap m) {
+    int t = lam % m.period;
+    return t < m.nq ? t : m.p_idx;
+}
+
+// ---------------------------------------------------------------- SplitMix64 (test-only randomness)
+
+__device__ __forceinline__ u64 sm_mix(u64 z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ u64 sm_out(u64 x, u64 i) { return sm_mix(x + (i + 1) * 0x9E3779B97F4A7C15ULL); }
+
+// (w1 2^64 + w2) mod q
+__device__ __forceinline__ u64 mod_u128(u64 w1, u64 w2, u64 q) {
+    u64 r = w1 % q;
+    for (int b = 63; b >= 0; --b) {
+        r = (r << 1) | ((w2 >> b) & 1ULL);
+        if (r >= q) r -= q;
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------- NTT
+//
+// Negacyclic NTT over Z_q[X]/(X^N + 1): forward maps coefficients to the
+// evaluations at psi^(2 brev(k) + 1) stored at index k (bit-reversed order),
+// psi a primitive 2N-th root of unity; inverse maps them back.  Merged
+// Cooley-Tukey (forward) / Gentleman-Sande (inverse) butterflies with the
+// bit-reversed power tables psi_rev[k] = psi^brev(k), ipsi_rev[k] = psi^-brev(k).
+//
+// N = N1 * N2 is done in two passes over HBM, each staging a 4096-word tile in
+// LDS: the first log2(N1) stages only pair words in the same column (index mod
+// N2) and the last log2(N2) stages only pair words in the same row of N2
+// contiguous words.
+
+constexpr int kTile = 4096;
+constexpr int kNttThreads = 256;
+
+struct NttGeom {
+    int n, log_n;
+    int n1, log_n1, n2, log_n2;
+    int log_cw;      // log2 columns per pass-1 tile
+    int log_rows;    // log2 rows per pass-2 tile
+    int tiles;       // tiles per limb
+};
+
+static NttGeom geom(int n, int log_n) {
+    NttGeom g;
+    g.n = n;
+    g.log_n = log_n;
+    g.log_n1 = (log_n + 1) / 2;
+    g.log_n2 = log_n - g.log_n1;
+    g.n1 = 1 << g.log_n1;
+    g.n2 = 1 << g.log_n2;
+    int tile = n < kTile ? n : kTile;
+    int log_tile = 0;
+    while ((1 << log_tile) < tile) ++log_tile;
+    g.log_cw = log_tile - g.log_n1;
+    g.log_rows = log_tile - g.log_n2;
+    g.tiles = n / tile;
+    return g;
+}
+
+__global__ void __launch_bounds__(kNttThreads) ntt_fwd_cols(u64 *buf, ModMap mm, const ModInfo *mods,
+                                                            const u64 *psi, const u64 *psi_sh, NttGeom g) {
+    __shared__ u64 sh[kTile];
+    const int limb = blockIdx.x / g.tiles, tile = blockIdx.x % g.tiles;
+    const int chain = chain_of(limb, mm);
+    const u64 q = mods[chain].q;
+    const u64 *W = psi + (size_t)chain * g.n, *Ws = psi_sh + (size_t)chain * g.n;
+    u64 *a = buf + (size_t)limb * g.n;
+    const int cw = 1 << g.log_cw, col0 = tile << g.log_cw;
+    const int total = g.n1 << g.log_cw;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        int r = e >> g.log_cw, c = e & (cw - 1);
+        sh[e] = a[((size_t)r << g.log_n2) + col0 + c];
+    }
+    __syncthreads();
+    const int nbf = total >> 1;
+    for (int m = 1, lt = g.log_n1 - 1; m < g.n1; m <<= 1, --lt) {
+        for (int b = threadIdx.x; b < nbf; b += blockDim.x) {
+            int c = b & (cw - 1), p = b >> g.log_cw;
+            int i = p >> lt, j = p & ((1 << lt) - 1);
+            int r1 = (i << (lt + 1)) + j, r2 = r1 + (1 << lt);
+            u64 U = sh[(r1 << g.log_cw) + c];
+            u64 V = mul_shoup(sh[(r2 << g.log_cw) + c], W[m + i], Ws[m + i], q);
+            sh[(r1 << g.log_cw) + c] = add_mod(U, V, q);
+            sh[(r2 << g.log_cw) + c] = sub_mod(U, V, q);
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        int r = e >> g.log_cw, c = e & (cw - 1);
+        a[((size_t)r << g.log_n2) + col0 + c] = sh[e];
+    }
+}
+
+__global__ void __launch_bounds__(kNttThreads) ntt_fwd_rows(u64 *buf, ModMap mm, const ModInfo *mods,
+                                                            const u64 *psi, const u64 *psi_sh, NttGeom g) {
+    __shared__ u64 sh[kTile];
+    const int limb = blockIdx.x / g.tiles, tile = blockIdx.x % g.tiles;
+    const int chain = chain_of(limb, mm);
+    const u64 q = mods[chain].q;
+    const u64 *W = psi + (size_t)chain * g.n, *Ws = psi_sh + (size_t)chain * g.n;
+    const int row0 = tile << g.log_rows;
+    u64 *a = buf + (size_t)limb * g.n + ((size_t)row0 << g.log_n2);
+    const int total = 1 << (g.log_rows + g.log_n2);
+    for (int e = threadIdx.x; e < total; e += blockDim.x) sh[e] = a[e];
+    __syncthreads();
+    const int nbf = total >> 1, log_half = g.log_n2 - 1;
+    for (int mp = 1, lt = g.log_n2 - 1; mp < g.n2; mp <<= 1, --lt) {
+        for (int b = threadIdx.x; b < nbf; b += blockDim.x) {
+            int rr = b >> log_half, p = b & ((1 << log_half) - 1);
+            int i = p >> lt, j = p & ((1 << lt) - 1);
+            int c1 = (i << (lt + 1)) + j, c2 = c1 + (1 << lt);
+            int widx = mp * (g.n1 + row0 + rr) + i;
+            int o = rr << g.log_n2;
+            u64 U = sh[o + c1];
+            u64 V = mul_shoup(sh[o + c2], W[widx], Ws[widx], q);
+            sh[o + c1] = add_mod(U, V, q);
+            sh[o + c2] = sub_mod(U, V, q);
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < total; e += blockDim.x) a[e] = sh[e];
+}
+
+__global__ void __launch_bounds__(kNttThreads) ntt_inv_rows(u64 *buf, ModMap mm, const ModInfo *mods,
+                                                            const u64 *ipsi, const u64 *ipsi_sh, NttGeom g) {
+    __shared__ u64 sh[kTile];
+    const int limb = blockIdx.x / g.tiles, tile = blockIdx.x % g.tiles;
+    const int chain = chain_of(limb, mm);
+    const u64 q = mods[chain].q;
+    const u64 *W = ipsi + (size_t)chain * g.n, *Ws = ipsi_sh + (size_t)chain * g.n;
+    const int row0 = tile << g.log_rows;
+    u64 *a = buf + (size_t)limb * g.n + ((size_t)row0 << g.log_n2);
+    const int total = 1 << (g.log_rows + g.log_n2);
+    for (int e = threadIdx.x; e < total; e += blockDim.x) sh[e] = a[e];
+    __syncthreads();
+    const int nbf = total >> 1, log_half = g.log_n2 - 1;
+    for (int mp = g.n2 >> 1, lt = 0; mp >= 1; mp >>= 1, ++lt) {
+        for (int b = threadIdx.x; b < nbf; b += blockDim.x) {
+            int rr = b >> log_half, p = b & ((1 << log_half) - 1);
+            int i = p >> lt, j = p & ((1 << lt) - 1);
+            int c1 = (i << (lt + 1)) + j, c2 = c1 + (1 << lt);
+            int widx = mp * (g.n1 + row0 + rr) + i;
+            int o = rr << g.log_n2;
+            u64 U = sh[o + c1], V = sh[o + c2];
+            sh[o + c1] = add_mod(U, V, q);
+            sh[o + c2] = mul_shoup(sub_mod(U, V, q), W[widx], Ws[widx], q);
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < total; e += blockDim.x) a[e] = sh[e];
+}
+
+__global__ void __launch_bounds__(kNttThreads) ntt_inv_cols(u64 *buf, ModMap mm, const ModInfo *mods,
+                                                            const u64 *ipsi, const u64 *ipsi_sh, NttGeom g) {
+    __shared__ u64 sh[kTile];
+    const int limb = blockIdx.x / g.tiles, tile = blockIdx.x % g.tiles;
+    const int chain = chain_of(limb, mm);
+    const ModInfo M = mods[chain];
+    const u64 q = M.q;
+    const u64 *W = ipsi + (size_t)chain * g.n, *Ws = ipsi_sh + (size_t)chain * g.n;
+    u64 *a = buf + (size_t)limb * g.n;
+    const int cw = 1 << g.log_cw, col0 = tile << g.log_cw;
+    const int total = g.n1 << g.log_cw;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        int r = e >> g.log_cw, c = e & (cw - 1);
+        sh[e] = a[((size_t)r << g.log_n2) + col0 + c];
+    }
+    __syncthreads();
+    const int nbf = total >> 1;
+    for (int m = g.n1 >> 1, lt = 0; m >= 1; m >>= 1, ++lt) {
+        const bool last = (m == 1);
+        for (int b = threadIdx.x; b < nbf; b += blockDim.x) {
+            int c = b & (cw - 1), p = b >> g.log_cw;
+            int i = p >> lt, j = p & ((1 << lt) - 1);
+            int r1 = (i << (lt + 1)) + j, r2 = r1 + (1 << lt);
+            u64 U = sh[(r1 << g.log_cw) + c], V = sh[(r2 << g.log_cw) + c];
+            if (!last) {
+                sh[(r1 << g.log_cw) + c] = add_mod(U, V, q);
+                sh[(r2 << g.log_cw) + c] = mul_shoup(sub_mod(U, V, q), W[m + i], Ws[m + i], q);
+            } else {
+                sh[(r1 << g.log_cw) + c] = mul_shoup(add_mod(U, V, q), M.ninv, M.ninv_sh, q);
+                sh[(r2 << g.log_cw) + c] = mul_shoup(sub_mod(U, V, q), M.w1ninv, M.w1ninv_sh, q);
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        int r = e >> g.log_cw, c = e & (cw - 1);
+        a[((size_t)r << g.log_n2) + col0 + c] = sh[e];
+    }
+}
+
+static void check_launch(const char *what) { GCK_HIP(hipGetLastError()); (void)what; }
+
+void k_ntt_forward(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStream_t st) {
+    if (n_limbs <= 0) return;
+    NttGeom g = geom(t.n, t.log_n);
+    dim3 grid((unsigned)(n_limbs * g.tiles));
+    hipLaunchKernelGGL(ntt_fwd_cols, grid, dim3(kNttThreads), 0, st, buf, m, t.mods, t.psi, t.psi_sh, g);
+    hipLaunchKernelGGL(ntt_fwd_rows, grid, dim3(kNttThreads), 0, st, buf, m, t.mods, t.psi, t.psi_sh, g);
+    check_launch("ntt_fwd");
+}
+
+void k_ntt_inverse(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStream_t st) {
+    if (n_limbs <= 0) return;
+    NttGeom g = geom(t.n, t.log_n);
+    dim3 grid((unsigned)(n_limbs * g.tiles));
+    hipLaunchKernelGGL(ntt_inv_rows, grid, dim3(kNttThreads), 0, st, buf, m, t.mods, t.ipsi, t.ipsi_sh, g);
+    hipLaunchKernelGGL(ntt_inv_cols, grid, dim3(kNttThreads), 0, st, buf, m, t.mods, t.ipsi, t.ipsi_sh, g);
+    check_launch("ntt_inv");
+}
+
+// ---------------------------------------------------------------- elementwise
+
+constexpr int kEwThreads = 256;
+
+static dim3 ew_grid(size_t total) {
+    size_t blocks = (total + kEwThreads - 1) / kEwThreads;
+    if (blocks > 65536 * 8) blocks = 65536 * 8;
+    return dim3((unsigned)blocks);
+}
+
+template <int OP>
+__global__ void ew_binary(u64 *out, const u64 *a, const u64 *b, size_t total, int log_n, ModMap mm,
+                          const ModInfo *mods, int na, int nb) {
+    const size_t n = (size_t)1 << log_n;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        int lam = (int)(idx >> log_n);
+        size_t k = idx & (n - 1);
+        const ModInfo &M = mods[chain_of(lam, mm)];
+        u64 x = a[(size_t)(lam % na) * n + k], y = b[(size_t)(lam % nb) * n + k];
+        u64 r;
+        if (OP == 0) r = add_mod(x, y, M.q);
+        else if (OP == 1) r = sub_mod(x, y, M.q);
+        else r = mul_mod(x, y, M);
+        out[idx] = r;
+    }
+}
+
+void k_add(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
+           hipStream_t st) {
+    size_t total = (size_t)n_limbs << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(ew_binary<0>, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, na, nb);
+    check_launch("add");
+}
+void k_sub(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
+           hipStream_t st) {
+    size_t total = (size_t)n_limbs << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(ew_binary<1>, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, na, nb);
+    check_launch("sub");
+}
+void k_mul(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
+           hipStream_t st) {
+    size_t total = (size_t)n_limbs << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(ew_binary<2>, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, na, nb);
+    check_launch("mul");
+}
+
+__global__ void ew_mul_const(u64 *out, const u64 *a, size_t total, int log_n, ModMap mm, const ModInfo *mods,
+                             ChainConst c) {
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        int lam = (int)(idx >> log_n);
+        int ch = chain_of(lam, mm);
+        out[idx] = mul_shoup(a[idx], c.v[ch], c.sh[ch], mods[ch].q);
+    }
+}
+void k_mul_const(const DevTables &t, u64 *out, const u64 *a, int n_limbs, ModMap m, const ChainConst &c,
+                 hipStream_t st) {
+    size_t total = (size_t)n_limbs << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(ew_mul_const, ew_grid(total), dim3(kEwThreads), 0, st, out, a, total, t.log_n, m, t.mods, c);
+    check_launch("mul_const");
+}
+
+// a constant polynomial c evaluates to c at every NTT point
+__global__ void ew_add_const_c0(u64 *ct, size_t total, int log_n, int l, const ModInfo *mods, ChainConst c) {
+    // total = count * l * N words of poly 0
+    const size_t n = (size_t)1 << log_n;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        int lam = (int)(idx >> log_n);        // over count * l
+        int ci = lam / l, i = lam % l;
+        size_t k = idx & (n - 1);
+        size_t off = ((size_t)ci * 2 * l + i) * n + k;
+        ct[off] = add_mod(ct[off], c.v[i], mods[i].q);
+    }
+}
+void k_add_const_c0(const DevTables &t, u64 *ct, int count, int l, const ChainConst &c, hipStream_t st) {
+    size_t total = ((size_t)count * l) << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(ew_add_const_c0, ew_grid(total), dim3(kEwThreads), 0, st, ct, total, t.log_n, l, t.mods, c);
+    check_launch("add_const");
+}
+
+__global__ void ew_tensor(u64 *out, const u64 *a, const u64 *b, size_t total, int log_n, int l, const ModInfo *mods,
+                          int na, int nb, int accumulate) {
+    const size_t n = (size_t)1 << log_n;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        int lam = (int)(idx >> log_n);       // over count * l
+        int ci = lam / l, i = lam % l;
+        size_t k = idx & (n - 1);
+        const ModInfo &M = mods[i];
+        const u64 *pa = a + (size_t)(ci % na) * 2 * l * n, *pb = b + (size_t)(ci % nb) * 2 * l * n;
+        u64 a0 = pa[(size_t)i * n + k], a1 = pa[(size_t)(l + i) * n + k];
+        u64 b0 = pb[(size_t)i * n + k], b1 = pb[(size_t)(l + i) * n + k];
+        u64 d0 = mul_mod(a0, b0, M);
+        // a0 b1 + a1 b0 as one 128-bit sum (< 2 q^2 < q 2^64), one reduction
+        u64 lo1 = a0 * b1, hi1 = __umul64hi(a0, b1);
+        u64 lo2 = a1 * b0, hi2 = __umul64hi(a1, b0);
+        u64 lo = lo1 + lo2, hi = hi1 + hi2 + (lo < lo1 ? 1 : 0);
+        if (hi >= M.q) hi -= M.q;
+        u64 d1 = mul_shoup(redc(hi, lo, M), M.r_mod, M.r_mod_sh, M.q);
+        u64 d2 = mul_mod(a1, b1, M);
+        u64 *po = out + (size_t)ci * 3 * l * n;
+        size_t o0 = (size_t)i * n + k, o1 = (size_t)(l + i) * n + k, o2 = (size_t)(2 * l + i) * n + k;
+        if (accumulate) {
+            po[o0] = add_mod(po[o0], d0, M.q);
+            po[o1] = add_mod(po[o1], d1, M.q);
+            po[o2] = add_mod(po[o2], d2, M.q);
+        } else {
+            po[o0] = d0; po[o1] = d1; po[o2] = d2;
+        }
+    }
+}
+void k_tensor(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int count, int l, int na, int nb,
+              bool accumulate, hipStream_t st) {
+    size_t total = ((size_t)count * l) << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(ew_tensor, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, l, t.mods, na, nb,
+                       accumulate ? 1 : 0);
+    check_launch("tensor");
+}
+
+// out[k] = a[k'] with psi^(2 brev(k') + 1) = (psi^(2 brev(k) + 1))^g
+__global__ void ew_automorph(u64 *out, const u64 *a, size_t total, int log_n, u64 g) {
+    const size_t n = (size_t)1 << log_n;
+    const u64 mask2n = 2 * n - 1;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        size_t lam = idx >> log_n;
+        u64 k = idx & (n - 1);
+        u64 e = 2 * (u64)(__brev((unsigned)k) >> (32 - log_n)) + 1;
+        u64 e2 = (e * g) & mask2n;
+        u64 k2 = __brev((unsigned)((e2 - 1) >> 1)) >> (32 - log_n);
+        out[idx] = a[lam * n + k2];
+    }
+}
+void k_automorph(const DevTables &t, u64 *out, const u64 *a, int n_limbs, u64 g, hipStream_t st) {
+    size_t total = (size_t)n_limbs << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(ew_automorph, ew_grid(total), dim3(kEwThreads), 0, st, out, a, total, t.log_n, g);
+    check_launch("automorph");
+}
+
+__global__ void ew_copy_rows(u64 *out, size_t out_stride, const u64 *in, size_t in_stride, size_t total, size_t words) {
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        size_t r = idx / words, k = idx % words;
+        out[r * out_stride + k] = in[r * in_stride + k];
+    }
+}
+void k_copy_rows(u64 *out, size_t out_stride, const u64 *in, size_t in_stride, int rows, size_t words,
+                 hipStream_t st) {
+    size_t total = (size_t)rows * words;
+    if (!total) return;
+    hipLaunchKernelGGL(ew_copy_rows, ew_grid(total), dim3(kEwThreads), 0, st, out, out_stride, in, in_stride, total, words);
+    check_launch("copy_rows");
+}
+
+__global__ void ew_extend(u64 *out, const u64 *in, size_t total, int log_n, int l_out, ModMap om, const ModInfo *mods,
+                          int src_mod, int centred) {
+    const size_t n = (size_t)1 << log_n;
+    const u64 qs = mods[src_mod].q, half = qs >> 1;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        int lam = (int)(idx >> log_n);    // over rows * l_out
+        int r = lam / l_out, i = lam % l_out;
+        size_t k = idx & (n - 1);
+        const ModInfo &M = mods[chain_of(i, om)];
+        u64 x = in[(size_t)r * n + k];
+        u64 v = reduce64(x, M);
+        if (centred && x > half) v = sub_mod(v, reduce64(qs, M), M.q);   // x - qs is negative
+        out[idx] = v;
+    }
+}
+void k_extend(const DevTables &t, u64 *out, const u64 *in, int rows, int l_out, ModMap out_map, int src_mod,
+              bool centred, hipStream_t st) {
+    size_t total = ((size_t)rows * l_out) << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(ew_extend, ew_grid(total), dim3(kEwThreads), 0, st, out, in, total, t.log_n, l_out, out_map,
+                       t.mods, src_mod, centred ? 1 : 0);
+    check_launch("extend");
+}
+
+__global__ void ew_modup(u64 *out, const u64 *in, size_t total, int log_n, int l, int p_idx, const ModInfo *mods) {
+    const size_t n = (size_t)1 << log_n;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        size_t lam = idx >> log_n;        // over count * l * (l + 1)
+        int tt = (int)(lam % (l + 1));
+        size_t cj = lam / (l + 1);        // c * l + j
+        size_t k = idx & (n - 1);
+        const ModInfo &M = mods[tt < l ? tt : p_idx];
+        out[idx] = reduce64(in[cj * n + k], M);
+    }
+}
+void k_modup(const DevTables &t, u64 *out, const u64 *in, int count, int l, int p_idx, hipStream_t st) {
+    size_t total = ((size_t)count * l * (l + 1)) << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(ew_modup, ew_grid(total), dim3(kEwThreads), 0, st, out, in, total, t.log_n, l, p_idx, t.mods);
+    check_launch("modup");
+}
+
+__global__ void ew_sub_mul_const(u64 *out, const u64 *a, const u64 *b, size_t total, int log_n, ModMap mm,
+                                 const ModInfo *mods, ChainConst c, int add_to_out) {
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        int lam = (int)(idx >> log_n);
+        int ch = chain_of(lam, mm);
+        u64 q = mods[ch].q;
+        u64 r = mul_shoup(sub_mod(a[idx], b[idx], q), c.v[ch], c.sh[ch], q);
+        out[idx] = add_to_out ? add_mod(out[idx], r, q) : r;
+    }
+}
+void k_sub_mul_const(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m,
+                     const ChainConst &c, bool add_to_out, hipStream_t st) {
+    size_t total = (size_t)n_limbs << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(ew_sub_mul_const, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, c,
+                       add_to_out ? 1 : 0);
+    check_launch("sub_mul_const");
+}
+
+// out[r][i] += in[r][i] for rows of l limbs (limb i of a row is modulo q_i)
+__global__ void ew_add_rows(u64 *out, size_t out_stride, const u64 *in, size_t in_stride, size_t total, int log_n,
+                            int l, const ModInfo *mods) {
+    const size_t n = (size_t)1 << log_n;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        size_t lam = idx >> log_n;
+        size_t r = lam / l;
+        int i = (int)(lam % l);
+        size_t k = idx & (n - 1);
+        u64 *o = out + r * out_stride + (size_t)i * n + k;
+        *o = add_mod(*o, in[r * in_stride + (size_t)i * n + k], mods[i].q);
+    }
+}
+void k_add_rows(const DevTables &t, u64 *out, size_t out_stride, const u64 *in, size_t in_stride, int rows, int l,
+                hipStream_t st) {
+    size_t total = ((size_t)rows * l) << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(ew_add_rows, ew_grid(total), dim3(kEwThreads), 0, st, out, out_stride, in, in_stride, total,
+                       t.log_n, l, t.mods);
+    check_launch("add_rows");
+}
+
+// ---------------------------------------------------------------- key-switch inner product
+//
+// acc[c][comp][t][k] = sum_j digit[c][j][t][k] * key[comp][j][kt][k] mod q_t.  The key words carry a
+// factor 2^64 (Montgomery form), so the lazily accumulated 128-bit sum needs one REDC at the end.
+// The high word is kept <= q by subtracting q (i.e. q 2^64 = 0 mod q) after each addition.
+__global__ void ks_inner(u64 *acc, const u64 *digits, const u64 *key, size_t total, int log_n, int l, int levels,
+                         const ModInfo *mods) {
+    const size_t n = (size_t)1 << log_n;
+    const int nt_key = levels + 2;
+    const size_t key_comp = (size_t)(levels + 1) * nt_key * n;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        size_t lam = idx >> log_n;       // over count * (l + 1)
+        int tt = (int)(lam % (l + 1));
+        size_t c = lam / (l + 1);
+        size_t k = idx & (n - 1);
+        int chain = tt < l ? tt : levels + 1;
+        int kt = chain;
+        const ModInfo M = mods[chain];
+        u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
+        const u64 *dg = digits + (c * l * (l + 1) + tt) * n + k;
+        for (int j = 0; j < l; ++j) {
+            u64 d = dg[(size_t)j * (l + 1) * n];
+            u64 k0 = key[((size_t)j * nt_key + kt) * n + k];
+            u64 k1 = key[key_comp + ((size_t)j * nt_key + kt) * n + k];
+            u64 p0 = d * k0, q0 = __umul64hi(d, k0);
+            u64 p1 = d * k1, q1 = __umul64hi(d, k1);
+            l0 += p0; h0 += q0 + (l0 < p0 ? 1 : 0);
+            l1 += p1; h1 += q1 + (l1 < p1 ? 1 : 0);
+            if (h0 >= M.q) h0 -= M.q;
+            if (h1 >= M.q) h1 -= M.q;
+        }
+        if (h0 >= M.q) h0 -= M.q;
+        if (h1 >= M.q) h1 -= M.q;
+        u64 *o = acc + (c * 2 * (l + 1) + tt) * n + k;
+        o[0] = redc(h0, l0, M);
+        o[(size_t)(l + 1) * n] = redc(h1, l1, M);
+    }
+}
+void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, const u64 *key, int count, int l, int levels,
+                hipStream_t st) {
+    size_t total = ((size_t)count * (l + 1)) << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(ks_inner, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, key, total, t.log_n, l, levels, t.mods);
+    check_launch("ks_inner");
+}
+
+// ---------------------------------------------------------------- samplers and conversions
+
+__global__ void sample_uniform(u64 *out, u64 seed, u64 sid, size_t total, int log_n, ModMap mm, const ModInfo *mods) {
+    const size_t n = (size_t)1 << log_n;
+    const u64 st = sm_out(seed, sid);
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        int lam = (int)(idx >> log_n);
+        u64 k = idx & (n - 1);
+        int ch = chain_of(lam, mm);
+        u64 ctr = 2 * ((u64)ch * n + k);
+        out[idx] = mod_u128(sm_out(st, ctr), sm_out(st, ctr + 1), mods[ch].q);
+    }
+}
+void k_sample_uniform(const DevTables &t, u64 *out, u64 seed, u64 sid, int n_limbs, ModMap m, int, hipStream_t st) {
+    size_t total = (size_t)n_limbs << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(sample_uniform, ew_grid(total), dim3(kEwThreads), 0, st, out, seed, sid, total, t.log_n, m, t.mods);
+    check_launch("sample_uniform");
+}
+
+__global__ void sample_small(i64 *out, u64 seed, u64 sid, int n, int kind) {
+    const u64 st = sm_out(seed, sid);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        u64 w = sm_out(st, (u64)i);
+        if (kind == 0) out[i] = (i64)__popcll(w & 0x1FFFFFULL) - (i64)__popcll((w >> 21) & 0x1FFFFFULL);
+        else out[i] = (i64)(w % 3) - 1;
+    }
+}
+void k_sample_cbd(i64 *out, u64 seed, u64 sid, int n, hipStream_t st) {
+    hipLaunchKernelGGL(sample_small, ew_grid(n), dim3(kEwThreads), 0, st, out, seed, sid, n, 0);
+    check_launch("sample_cbd");
+}
+void k_sample_ternary(i64 *out, u64 seed, u64 sid, int n, hipStream_t st) {
+    hipLaunchKernelGGL(sample_small, ew_grid(n), dim3(kEwThreads), 0, st, out, seed, sid, n, 1);
+    check_launch("sample_ternary");
+}
+
+__global__ void ew_signed_to_limbs(u64 *out, const i64 *in, size_t total, int log_n, ModMap mm, const ModInfo *mods) {
+    const size_t n = (size_t)1 << log_n;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        int lam = (int)(idx >> log_n);
+        size_t k = idx & (n - 1);
+        const ModInfo &M = mods[chain_of(lam, mm)];
+        i64 v = in[k];
+        u64 r;
+        if (v >= 0) r = reduce64((u64)v, M);
+        else {
+            r = reduce64((u64)(-(v + 1)), M);   // -(v+1) >= 0
+            r = M.q - 1 - r;
+        }
+        out[idx] = r;
+    }
+}
+void k_signed_to_limbs(const DevTables &t, u64 *out, const i64 *in, int n_limbs, ModMap m, hipStream_t st) {
+    size_t total = (size_t)n_limbs << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(ew_signed_to_limbs, ew_grid(total), dim3(kEwThreads), 0, st, out, in, total, t.log_n, m, t.mods);
+    check_launch("signed_to_limbs");
+}
+
+__global__ void ew_mont(u64 *x, size_t total, int log_n, ModMap mm, const ModInfo *mods, int to) {
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        int lam = (int)(idx >> log_n);
+        const ModInfo &M = mods[chain_of(lam, mm)];
+        x[idx] = to ? mul_shoup(x[idx], M.r_mod, M.r_mod_sh, M.q) : redc(0, x[idx], M);
+    }
+}
+void k_to_mont(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t st) {
+    size_t total = (size_t)n_limbs << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(ew_mont, ew_grid(total), dim3(kEwThreads), 0, st, x, total, t.log_n, m, t.mods, 1);
+    check_launch("to_mont");
+}
+void k_from_mont(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t st) {
+    size_t total = (size_t)n_limbs << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(ew_mont, ew_grid(total), dim3(kEwThreads), 0, st, x, total, t.log_n, m, t.mods, 0);
+    check_launch("from_mont");
+}
+
+__global__ void ew_neg(u64 *x, size_t total, int log_n, ModMap mm, const ModInfo *mods) {
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        int lam = (int)(idx >> log_n);
+        u64 q = mods[chain_of(lam, mm)].q;
+        x[idx] = x[idx] ? q - x[idx] : 0;
+    }
+}
+void k_neg(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t st) {
+    size_t total = (size_t)n_limbs << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(ew_neg, ew_grid(total), dim3(kEwThreads), 0, st, x, total, t.log_n, m, t.mods);
+    check_launch("neg");
+}
+
+}  // namespace gck

@@ -1,0 +1,224 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI.
+
+Ciphertexts, keys and every intermediate are compared bit for bit in the
+canonical form (coefficient domain, residues in [0, q)); decrypted GWAS results
+are compared with the FP64 plaintext GWAS.  Inputs of the circuit test are the
+oracle's own ciphertexts, imported into the library, so that no oracle input or
+expected value comes from the HIP path.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import paper_1902_04303_amd as P  # noqa: E402
+from oracle import ckks as C  # noqa: E402
+from oracle import gwas_circuit as G  # noqa: E402
+from oracle import gwas_fp64 as F  # noqa: E402
+from synth import config_seed, make_gwas_data  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    return torch
+
+
+def make_pair(log_n, levels, b, galois_fn, seed=7):
+    ctx = P.Context(log_n, levels, b)
+    p = C.make_params(log_n, levels, b)
+    o = C.Oracle(p)
+    g = galois_fn(p.N)
+    ctx.keygen(seed, g)
+    o.keygen(seed, g)
+    return ctx, o, p
+
+
+@pytest.fixture(scope="module")
+def small(torch_dev):
+    say("[gpu] small ring N=2^10 L=5")
+    return make_pair(10, 5, 30, lambda N: [C.galois_rotate(N, 1), C.galois_rotate(N, -2), C.galois_rotate(N, 4),
+                                           C.galois_conj(N)])
+
+
+def rand_ct(p, depth, rng):
+    l = p.limbs_at_depth(depth)
+    return np.stack([np.stack([rng.integers(0, q, size=p.N, dtype=np.uint64) for q in p.q[:l]]) for _ in range(2)])
+
+
+def test_keys_match_oracle(small):
+    ctx, o, p = small
+    assert np.array_equal(ctx.export_secret(), o.sk)
+    assert np.array_equal(ctx.export_public_key(), o.pk)
+    for K in list(o.keys):
+        assert np.array_equal(ctx.export_switching_key(K), o.keys[K]), K
+
+
+def test_encrypt_matches_oracle(small):
+    ctx, o, p = small
+    rng = np.random.default_rng(1)
+    z = rng.standard_normal(p.slots) + 1j * rng.standard_normal(p.slots)
+    m = C.encode(z, p.N, p.scales[0])
+    for depth in (0, 2):
+        ct = ctx.encrypt(m, depth, p.scales[depth], 99 + depth)
+        ref = o.encrypt(m, depth, p.scales[depth], 99 + depth)
+        assert np.array_equal(ctx.export(ct), ref.data)
+    # decrypt of the library's own ciphertext
+    ct = ctx.encrypt(m, 0, p.scales[0], 5)
+    assert np.max(np.abs(ctx.decrypt(ct) - z)) < 1e-4
+
+
+def test_encode_matches_oracle_within_one(small):
+    ctx, o, p = small
+    rng = np.random.default_rng(2)
+    z = rng.standard_normal(p.slots) + 1j * rng.standard_normal(p.slots)
+    assert np.max(np.abs(ctx.encode(z, p.scales[0]) - C.encode(z, p.N, p.scales[0]))) <= 1
+
+
+def test_import_export_roundtrip(small):
+    ctx, o, p = small
+    rng = np.random.default_rng(3)
+    for depth in (0, 3, p.L):
+        data = rand_ct(p, depth, rng)
+        ct = ctx.import_ct(data, depth, p.scales[depth])
+        assert np.array_equal(ctx.export(ct), data)
+
+
+def _both(ctx, o, p, data, depth, scale=None):
+    scale = p.scales[depth] if scale is None else scale
+    return ctx.import_ct(data, depth, scale), C.Ct(data.copy(), depth, scale)
+
+
+def test_elementwise_and_rescale_match_oracle(small):
+    ctx, o, p = small
+    rng = np.random.default_rng(4)
+    ga, oa = _both(ctx, o, p, rand_ct(p, 1, rng), 1)
+    gb, ob = _both(ctx, o, p, rand_ct(p, 1, rng), 1)
+    cases = [
+        ("add", ctx.add(ga, gb), o.add(oa, ob)),
+        ("sub", ctx.sub(ga, gb), o.sub(oa, ob)),
+        ("mul_int", ctx.mul_int(ga, -123456789), o.mul_int(oa, -123456789)),
+        ("add_const", ctx.add_const(ga, -0.7351), o.add_const(oa, -0.7351)),
+        ("rescale", ctx.rescale(ga), o.rescale(oa)),
+        ("mul_const", ctx.mul_const(ga, 0.3141), o.mul_const(oa, 0.3141)),
+        ("align", ctx.align(ga, 3, p.scales[3], 0.125), o.align(oa, 3, p.scales[3], 0.125)),
+        ("mask", ctx.mul_mask(ga, 8), o.mul_mask(oa, 8)),
+    ]
+    for name, g, r in cases:
+        say("[gpu] op", name)
+        assert g.depth == r.depth and g.scale == r.scale, name
+        assert np.array_equal(ctx.export(g), r.data), name
+
+
+def test_mul_relinearise_and_galois_match_oracle(small):
+    ctx, o, p = small
+    rng = np.random.default_rng(5)
+    for depth in (0, 2, p.L - 1):
+        ga, oa = _both(ctx, o, p, rand_ct(p, depth, rng), depth)
+        gb, ob = _both(ctx, o, p, rand_ct(p, depth, rng), depth)
+        say("[gpu] mul at depth", depth)
+        assert np.array_equal(ctx.export(ctx.mul(ga, gb)), o.mul(oa, ob).data)
+        for r in (1, -2, 4):
+            say("[gpu] rotate", r, "at depth", depth)
+            assert np.array_equal(ctx.export(ctx.rotate(ga, r)), o.rotate(oa, r).data)
+        assert np.array_equal(ctx.export(ctx.conjugate(ga)), o.conjugate(oa).data)
+
+
+def test_missing_key_and_level_errors(small):
+    ctx, o, p = small
+    rng = np.random.default_rng(6)
+    ga = ctx.import_ct(rand_ct(p, p.L, rng), p.L, p.scales[p.L])
+    with pytest.raises(P.CkksError) as e:
+        ctx.rotate(ga, 3)
+    assert e.value.code == -4
+    with pytest.raises(P.CkksError) as e:
+        ctx.rescale(ga)
+    assert e.value.code == -3
+
+
+def test_decrypted_semantics(small):
+    ctx, o, p = small
+    rng = np.random.default_rng(7)
+    z = rng.standard_normal(p.slots) + 1j * rng.standard_normal(p.slots)
+    w = rng.standard_normal(p.slots)
+    a = ctx.encrypt(ctx.encode(z, p.scales[0]), 0, p.scales[0], 1)
+    b = ctx.encrypt(ctx.encode(w, p.scales[0]), 0, p.scales[0], 2)
+    assert np.max(np.abs(ctx.decrypt(ctx.mul(a, b)) - z * w)) < 1e-3
+    assert np.max(np.abs(ctx.decrypt(ctx.rotate(a, 1)) - np.roll(z, -1))) < 1e-4
+    assert np.max(np.abs(ctx.decrypt(ctx.rotate(a, -2)) - np.roll(z, 2))) < 1e-4
+    assert np.max(np.abs(ctx.decrypt(ctx.conjugate(a)) - np.conj(z))) < 1e-4
+
+
+# ------------------------------------------------------------------ the whole circuit
+
+def _oracle_circuit(n, k, m, kappa, log_n, b, data_seed):
+    p = C.make_params(log_n, G.circuit_depth(kappa), b)
+    d = make_gwas_data(n, k, m, seed=data_seed)
+    lay = G.make_layout(p.N, n, k, m)
+    o = C.Oracle(p)
+    o.keygen(7, G.required_galois(p.N, lay.R))
+    pts = G.encode_inputs(p, d.X, d.y, d.S, kappa)
+    inp = G.encrypt_inputs(o, pts, n, k, m, kappa, 11)
+    out = G.Circuit(o, lay).run(inp)
+    return p, d, lay, o, inp, out
+
+
+@pytest.mark.parametrize("n,k,m,log_n,b,chunk", [(30, 4, 70, 10, 30, 2), (245, 4, 32, 13, 30, None)])
+def test_circuit_bit_exact_against_oracle(torch_dev, n, k, m, log_n, b, chunk):
+    kappa = 3
+    say("[gpu] circuit n=%d k=%d m=%d logN=%d" % (n, k, m, log_n))
+    p, d, lay, o, inp, ref = _oracle_circuit(n, k, m, kappa, log_n, b, config_seed(1))
+    ctx = P.Context(log_n, p.L, b)
+    ctx.keygen(7, G.required_galois(p.N, lay.R))
+    imp = lambda c: ctx.import_ct(c.data, c.depth, c.scale)  # noqa: E731
+    x = [imp(c) for c in inp.x]
+    A = [imp(inp.A[pr]) for pr in G.a_pairs(k)]
+    S = [imp(c) for c in inp.S]
+    gin = ctx.gwas_input_from_cts(n, k, m, kappa, x, imp(inp.y), A, S)
+    out = ctx.gwas_semiparallel(gin, chunk)
+    for j in range(k):
+        assert np.array_equal(ctx.export(out.ct(P.GwasOutput.BETA, j)), ref.beta[j].data)
+    for which, r in [(P.GwasOutput.W, ref.w), (P.GwasOutput.W_INV, ref.w_inv), (P.GwasOutput.Z_PROJ, ref.z_proj),
+                     (P.GwasOutput.U, ref.u)]:
+        assert np.array_equal(ctx.export(out.ct(which)), r.data), which
+    ch = chunk or lay.n_batches
+    for bi in range(lay.n_batches):
+        for which, r in [(P.GwasOutput.NUM, ref.num), (P.GwasOutput.DEN_EVEN, ref.den_even),
+                         (P.GwasOutput.DEN_ODD, ref.den_odd), (P.GwasOutput.S_PROJ, ref.S_proj)]:
+            g = out.ct(which, bi // ch)
+            assert np.array_equal(ctx.export(g, bi % ch), r[bi].data), (which, bi)
+    # the client finalisation agrees with the oracle's to FP64 rounding
+    res = ctx.gwas_finalize(out)
+    num, den, bb, err, se = G.finalize(o, lay, ref)
+    assert np.allclose(res["b"], bb, rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,k,m,log_n,b,tol", [(245, 4, 32, 13, 30, 1e-3), (245, 4, 600, 16, 40, 1e-3)])
+def test_end_to_end_accuracy_against_fp64(torch_dev, n, k, m, log_n, b, tol):
+    kappa = 3
+    say("[gpu] end-to-end n=%d m=%d logN=%d" % (n, m, log_n))
+    L = G.circuit_depth(kappa)
+    ctx = P.Context(log_n, L, b)
+    lay = ctx.gwas_layout(n, k, m, kappa)
+    N = 1 << log_n
+    ctx.keygen(7, G.required_galois(N, lay["R"]))
+    d = make_gwas_data(n, k, m, seed=config_seed(2 if log_n == 16 else 1))
+    gin = ctx.gwas_pack_encrypt(d.X, d.y, d.S, kappa, 11)
+    out = ctx.gwas_semiparallel(gin)
+    res = ctx.gwas_finalize(out)
+    ref = F.modified_gwas(d.X, d.y, d.S, kappa)
+    ok = ref.den > 1e-9 * np.max(ref.den)
+    rel = np.abs(res["b"] - ref.b) / np.maximum(np.abs(ref.b), ref.se)
+    say("[gpu] max G26 error", float(np.max(rel[ok])))
+    assert np.max(rel[ok]) < tol
+    assert np.allclose(res["se"][ok], ref.se[ok], rtol=1e-3)

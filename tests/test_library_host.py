@@ -1,0 +1,43 @@
+"""Host-side checks of the HIP library that need no GPU: it loads, exports every
+symbol the C header declares, and its prime-chain rule agrees with the oracle's."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1902_04303_amd as P
+from oracle import ckks as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "gwas_ckks.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:ckks|gwas)_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.lib()
+    names = declared_symbols()
+    assert len(names) > 40
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(P.exported_symbols()) == set(names)
+
+
+@pytest.mark.parametrize("log_n,levels,b", [(10, 4, 30), (13, 26, 30), (16, 26, 40), (16, 19, 40)])
+def test_prime_chain_matches_oracle(log_n, levels, b):
+    q, Pm, scales = P.chain(log_n, levels, b)
+    ref = C.make_params(log_n, levels, b)
+    assert q == ref.q and Pm == ref.P
+    assert scales == ref.scales
+
+
+def test_bad_parameters_are_rejected():
+    with pytest.raises(P.CkksError) as e:
+        P.chain(9, 4, 30)
+    assert e.value.code == -1
+    with pytest.raises(P.CkksError):
+        P.chain(13, 4, 60)
