@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark: encrypted semi-parallel GWAS on one MI355X.
+
+A step is one call of the hot path, ``gwas_semiparallel``, on the paper-scale
+workload: n = 245 samples, k = 4 covariates (intercept + 3 N(0,1)), m = 10643
+SNPs packed two per complex slot (42 SNP batches of 256), RNS-CKKS with
+N = 2^16, scale 2^40, q_0 of 60 bits, 26 rescale primes of 40 bits, a 62-bit
+special prime, kappa = 3 Newton passes.  Keys and encrypted inputs are resident
+in HBM before the timed region; the encrypted numerators and denominators are
+ready in HBM at its end.  Data: seeded synthetic genotypes and phenotypes with
+the shapes and distributions of the paper's workload.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_SAMPLES, K_COV, M_SNPS, KAPPA, LOG_N, LOG_SCALE = 245, 4, 10643, 3, 16, 40
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "encrypted semi-parallel GWAS n=245 k=4 m=10643, RNS-CKKS N=2^16 L=26 scale=2^40, kappa=3"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def galois_set(ctx, R):
+    g = []
+    i = 1
+    while i < R:
+        g += [ctx.galois_rotate(i), ctx.galois_rotate(-i)]
+        i *= 2
+    g.append(ctx.galois_conj())
+    return g
+
+
+def gpu_leg(args):
+    import torch
+
+    import paper_1902_04303_amd as P
+    from synth import config_seed, make_gwas_data
+
+    torch.cuda.init()
+    L = 7 * KAPPA + 5
+    ctx = P.Context(LOG_N, L, LOG_SCALE)
+    lay = ctx.gwas_layout(N_SAMPLES, K_COV, M_SNPS, KAPPA)
+    gal = galois_set(ctx, lay["R"])
+    t0 = time.time()
+    ctx.keygen(7, gal)
+    torch.cuda.synchronize()
+    log("[bench] keygen %.2fs (%d switching keys)" % (time.time() - t0, len(gal) + 1))
+    d = make_gwas_data(N_SAMPLES, K_COV, M_SNPS, seed=config_seed(2))
+    t0 = time.time()
+    gin = ctx.gwas_pack_encrypt(d.X, d.y, d.S, KAPPA, 11)
+    torch.cuda.synchronize()
+    log("[bench] client encode+encrypt %.2fs, %d SNP batches" % (time.time() - t0, lay["n_batches"]))
+    out = None
+    for w in range(args.warmup):
+        out = ctx.gwas_semiparallel(gin)
+        torch.cuda.synchronize()
+        log("[bench] warmup %d done" % w)
+    c0 = ctx.counters()
+    ctx.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = ctx.gwas_semiparallel(gin)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.kernel_timing(False)
+    c1 = ctx.counters()
+    ms = (t1 - t0) * 1e3 / args.steps
+    kt = ctx.kernel_report()
+    log("[bench] %d steps, %.1f ms/step" % (args.steps, ms))
+    # end-to-end with the host boundary (outside the timed region): finalize = D2H + decrypt + divide
+    t2 = time.perf_counter()
+    res = ctx.gwas_finalize(out)
+    t3 = time.perf_counter()
+    per_step = {k: (c1[k] - c0[k]) // args.steps for k in c0}
+    return dict(ms=ms, kernels=kt, counters=per_step, finalize_ms=(t3 - t2) * 1e3,
+                b_finite=int(np.isfinite(res["b"]).sum()), pool=ctx.pool_stats())
+
+
+def roofline(kernels, steps):
+    name, (cnt, tot_ms, by) = max(kernels.items(), key=lambda kv: kv[1][1])
+    avg_ms = tot_ms / cnt
+    achieved = (by / cnt) / (avg_ms * 1e-3) / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "launches_per_step": cnt // steps, "avg_launch_us": round(avg_ms * 1e3, 2),
+            "algorithmic_bytes_per_launch": int(by / cnt), "share_of_kernel_time": round(
+                tot_ms / sum(v[1] for v in kernels.values()), 3)}
+
+
+def cpu_baseline_leg():
+    """The CPU oracle on a bounded sample of the same workload: the per-batch part of one SNP batch
+    (256 SNPs; the fixed logistic-regression part is excluded, which favours the CPU)."""
+    from oracle import ckks as C
+    from oracle import gwas_circuit as G
+    from oracle import gwas_fp64 as F
+    from synth import config_seed, make_gwas_data
+
+    L = G.circuit_depth(KAPPA)
+    p = C.make_params(LOG_N, L, LOG_SCALE)
+    d = make_gwas_data(N_SAMPLES, K_COV, M_SNPS, seed=config_seed(2))
+    lay = G.make_layout(p.N, N_SAMPLES, K_COV, M_SNPS)
+    ds = G.snp_depth(KAPPA)
+    o = C.Oracle(p)
+    t0 = time.time()
+    o.keygen(7, G.required_galois(p.N, lay.R), max_limbs=p.limbs_at_depth(ds))
+    log("[bench] cpu oracle keygen (low-level key block) %.1fs" % (time.time() - t0))
+    ref = F.modified_gwas(d.X, d.y, d.S, KAPPA)
+    A = F.xtx_inverse(d.X)
+    enc = lambda v, depth, i: o.encrypt(C.encode(G.periodic_slots(v, lay), p.N, p.scales[depth]), depth,  # noqa
+                                        p.scales[depth], 1000 + i)
+    XA = d.X @ A
+    fx = G.FixedPart(x=[enc(d.X[:, j], ds + 2, j) for j in range(K_COV)],
+                     rr=[enc(XA[:, j], ds, 10 + j) for j in range(K_COV)],
+                     w=enc(ref.w, ds + 3, 20), u=enc(ref.w * ref.z_proj, ds + 3, 21))
+    S = o.encrypt(C.encode(G.snp_batch_slots(d.S, lay, 0), p.N, p.scales[ds]), ds, p.scales[ds], 30)
+    circ = G.Circuit(o, lay)
+    t0 = time.perf_counter()
+    circ.run_batch(S, fx)
+    t = time.perf_counter() - t0
+    cores = int(C.lib().ref_num_threads())
+    log("[bench] cpu oracle: one SNP batch (%d SNPs) in %.1fs on %d threads" % (lay.tau, t, cores))
+    return {"value": round(lay.tau / t, 3), "unit": "SNPs/s", "cores": cores, "kind": "oracle",
+            "sample": "per-batch part of one 256-SNP batch of the same workload (S' = M S, numerator, both "
+                      "denominators; %d key switches at <= 6 limbs), %.1f s; the fixed logistic-regression "
+                      "part is excluded" % (o.n_keyswitch, t)}
+
+
+def run(args) -> int:
+    g = gpu_leg(args)
+    value = M_SNPS / (g["ms"] * 1e-3)
+    rl = roofline(g["kernels"], args.steps)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_leg()
+    line = {
+        "metric": "encrypted SNPs/s at 245x4x10643",
+        "value": round(value, 1),
+        "unit": "SNPs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(g["ms"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n": N_SAMPLES, "k": K_COV, "m": M_SNPS, "kappa": KAPPA,
+                   "log_n": LOG_N, "levels": 7 * KAPPA + 5, "log2_scale": LOG_SCALE, "snp_batches": 42,
+                   "parallelism": "1 GPU"},
+        "roofline": rl,
+        "cpu_baseline": cpu,
+        "per_step": g["counters"],
+        "finalize_ms": round(g["finalize_ms"], 1),
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: this build measures the single-GPU path (the multi-GPU sharding is a "
+              "design only); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        return 2
+    return run(args)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -219,6 +219,13 @@ void gwas_output_free(gwas_enc_output *out);
 int gwas_finalize(ckks_ctx *ctx, const gwas_enc_output *out, int m, double *b, double *err, double *se,
                   double *num, double *den);
 
+/* Per-kernel timing with HIP events recorded on the context's stream around every
+ * launch of the instrumented kernels.  enable = 1 clears the counters and starts
+ * recording; 0 stops.  The report is text, one line per kernel:
+ * "name launches total_ms algorithmic_bytes". */
+int ckks_ctx_kernel_timing(ckks_ctx *ctx, int enable);
+int ckks_ctx_kernel_report(ckks_ctx *ctx, char *buf, size_t cap);
+
 /* Number of key switches and NTT limb transforms issued by the context so far. */
 int ckks_ctx_counters(const ckks_ctx *ctx, uint64_t *keyswitches, uint64_t *limb_ntts, uint64_t *launches);
 

@@ -89,8 +89,10 @@ def lib():
         L.ref_keyswitch.argtypes = [ctypes.c_void_p, ctypes.c_int, _u64p, _u64p, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_int, _u64p]
         L.ref_gen_ksk.argtypes = [ctypes.c_void_p, ctypes.c_int, _i64p, _u64p, ctypes.c_uint64, ctypes.c_uint64,
-                                  _u64p]
-        L.ref_key_to_eval.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64p, _u64p]
+                                  ctypes.c_int, _u64p]
+        L.ref_key_to_eval.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64p,
+                                      _u64p]
+        L.ref_num_threads.restype = ctypes.c_int
         L.ref_gen_pk.argtypes = [ctypes.c_void_p, ctypes.c_int, _i64p, ctypes.c_uint64, ctypes.c_uint64,
                                  ctypes.c_uint64, _u64p]
         L.ref_encrypt.argtypes = [ctypes.c_void_p, ctypes.c_int, _u64p, ctypes.c_int, _i64p, ctypes.c_uint64,
@@ -416,8 +418,11 @@ class Oracle:
             pass
 
     # ---------------- key generation ----------------
-    def keygen(self, seed: int, galois: Sequence[int], relin: bool = True) -> None:
+    def keygen(self, seed: int, galois: Sequence[int], relin: bool = True, max_limbs: Optional[int] = None) -> None:
+        """Keys of the scheme.  max_limbs restricts the switching keys to the digits and targets a
+        ciphertext of at most that many limbs uses (the entries are the same as in the full key)."""
         p = self.p
+        self._max_l = p.L + 1 if max_limbs is None else int(max_limbs)
         N, L = p.N, p.L
         s = np.zeros(N, dtype=np.int64)
         lib().ref_sample_hwt(seed, SID_SECRET, N, secret_weight(N), _p(s))
@@ -450,9 +455,9 @@ class Oracle:
         N, L = p.N, p.L
         key = np.zeros((2, L + 1, L + 2, N), dtype=np.uint64)
         lib().ref_gen_ksk(self._ctx, L, _p(self.sk), _p(np.ascontiguousarray(sp)), self._seed,
-                          ksk_sid_base(K), _p(key))
+                          ksk_sid_base(K), self._max_l, _p(key))
         kev = np.zeros_like(key)
-        lib().ref_key_to_eval(self._ctx, L + 1, L + 2, self.pidx, _p(key), _p(kev))
+        lib().ref_key_to_eval(self._ctx, L + 1, L + 2, self.pidx, self._max_l, _p(key), _p(kev))
         self.keys[K] = key
         self._kev[K] = kev
 
@@ -575,6 +580,8 @@ class Oracle:
     def keyswitch(self, d: np.ndarray, K: int) -> np.ndarray:
         """round(sum_j [d]_{q_j} * ksk_j / P) for the key with id K; d is [l][N]."""
         l = d.shape[0]
+        if l > self._max_l:
+            raise ValueError("keys were generated for at most %d limbs" % self._max_l)
         p = self.p
         out = np.zeros((2, l, p.N), dtype=np.uint64)
         lib().ref_keyswitch(self._ctx, l, _p(np.ascontiguousarray(d)), _p(self._kev[K]), p.L + 1, p.L + 2,

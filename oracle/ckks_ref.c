@@ -33,6 +33,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 typedef uint64_t u64;
 typedef int64_t i64;
@@ -447,7 +448,7 @@ void ref_keyswitch(const ref_ctx *c, int l, const u64 *d, const u64 *kev, int nd
  * Output in coefficient form: key[comp][j][t][N], comp 0 = b, 1 = a.
  */
 void ref_gen_ksk(const ref_ctx *c, int L, const i64 *s, const u64 *sp, u64 seed, u64 sid_base,
-                 u64 *key) {
+                 int max_l, u64 *key) {
     int n = c->n, nt = L + 2, nd = L + 1;
     size_t kc = (size_t)nd * nt * n;
     u64 P = c->mods[L + 1].q;
@@ -458,6 +459,8 @@ void ref_gen_ksk(const ref_ctx *c, int L, const i64 *s, const u64 *sp, u64 seed,
 #pragma omp for schedule(dynamic)
         for (int jt = 0; jt < nd * nt; ++jt) {
             int j = jt / nt, t = jt % nt;
+            /* max_l < L + 1: only the sub-block used by ciphertexts of at most max_l limbs */
+            if (j >= max_l || (t >= max_l && t != nt - 1)) continue;
             u64 q = c->mods[t].q;
             u64 *b = key + (size_t)j * nt * n + (size_t)t * n;
             u64 *a = key + kc + (size_t)j * nt * n + (size_t)t * n;
@@ -477,11 +480,12 @@ void ref_gen_ksk(const ref_ctx *c, int L, const i64 *s, const u64 *sp, u64 seed,
 }
 
 /* convert a coefficient-form key to the oracle's evaluation form (same layout) */
-void ref_key_to_eval(const ref_ctx *c, int nd, int nt, int pidx, const u64 *key, u64 *kev) {
+void ref_key_to_eval(const ref_ctx *c, int nd, int nt, int pidx, int max_l, const u64 *key, u64 *kev) {
     int n = c->n;
 #pragma omp parallel for schedule(dynamic)
     for (int x = 0; x < 2 * nd * nt; ++x) {
-        int t = x % nt;
+        int t = x % nt, j = (x / nt) % nd;
+        if (j >= max_l || (t >= max_l && t != nt - 1)) continue;
         int mi = t < nt - 1 ? t : pidx;
         ref_to_eval(c, mi, key + (size_t)x * n, kev + (size_t)x * n);
     }
@@ -557,6 +561,17 @@ void ref_decrypt(const ref_ctx *c, int l, const u64 *ct, const i64 *s, u64 *m) {
         }
         free(sr); free(t);
     }
+}
+
+/* number of OpenMP threads the oracle runs with */
+int ref_num_threads(void) {
+    int n = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        n = omp_get_num_threads();
+    }
+    return n;
 }
 
 /* s^2 mod each q_t, t < nl (the relinearisation key's target secret) */

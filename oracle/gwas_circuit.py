@@ -193,6 +193,15 @@ def required_galois(N: int, R: int) -> List[int]:
 
 
 @dataclass
+class FixedPart:
+    """What the per-batch part needs from the fixed part: x_j, r_j = (X A)_{:, j}, w and u = w z'."""
+    x: List[C.Ct]
+    rr: List[C.Ct]
+    w: C.Ct
+    u: C.Ct
+
+
+@dataclass
 class EncOutput:
     beta: List[C.Ct]
     w: C.Ct
@@ -248,6 +257,30 @@ class Circuit:
         cc = o.add(self.at(a1, d + 3), b)
         return o.add_const(o.mul(self.at(u, d + 3), cc), 0.5)
 
+    def run_batch(self, S: C.Ct, fx: "FixedPart"):
+        """Per-batch part (Alg. Semi Parallel GWAS, batch loop): S' = M S, num, denEven, denOdd."""
+        o = self.o
+        k = self.lay.k
+        ds = S.depth
+        cs = []
+        for j in range(k):
+            pj = o.mul(self.at(fx.rr[j], ds), S)
+            cj = self.rot_sum(pj)                 # column sums at block starts (Alg. colSum)
+            cj = o.mul_mask(cj, self.lay.R)       # keep block starts only
+            cs.append(self.bcast(cj))             # (A X^T S)_{j, c} over block c
+        dc = cs[0].depth
+        xe = o.mul_sum([(self.at(fx.x[j], dc), cs[j]) for j in range(k)])
+        sp = o.sub(self.at(S, xe.depth), xe)
+        dsp = sp.depth
+        num = self.rot_sum(o.mul(self.at(fx.u, dsp), sp))
+        ws = o.mul(self.at(fx.w, dsp), sp)
+        sc = o.conjugate(sp)
+        wss = o.mul(ws, self.at(sp, ws.depth))
+        wsc = o.mul(ws, self.at(sc, ws.depth))
+        de = self.rot_sum(o.set_scale(o.add(wsc, wss), 2.0))
+        do = self.rot_sum(o.set_scale(o.sub(wsc, wss), 2.0))
+        return sp, num, de, do
+
     def run(self, inp: EncInput) -> EncOutput:
         o = self.o
         lay = self.lay
@@ -293,27 +326,10 @@ class Circuit:
         u = o.mul(self.at(w, z_proj.depth), z_proj)
         # ---- r_j = (X A)_{:, j} for the projection of the SNP batches
         rr = [o.mul_sum([(self.at(inp.a(j, l), 1), self.at(x[l], 1)) for l in range(k)]) for j in range(k)]
-        # ---- per-batch part (Alg. Semi Parallel GWAS, batch loop)
+        fixed = FixedPart(x=x, rr=rr, w=w, u=u)
         S_proj, nums, dens_e, dens_o = [], [], [], []
         for S in inp.S:
-            ds = S.depth
-            cs = []
-            for j in range(k):
-                pj = o.mul(self.at(rr[j], ds), S)
-                cj = self.rot_sum(pj)                 # column sums at block starts (Alg. colSum)
-                cj = o.mul_mask(cj, lay.R)            # keep block starts only
-                cs.append(self.bcast(cj))             # (A X^T S)_{j, c} over block c
-            dc = cs[0].depth
-            xe = o.mul_sum([(self.at(x[j], dc), cs[j]) for j in range(k)])
-            sp = o.sub(self.at(S, xe.depth), xe)
-            dsp = sp.depth
-            num = self.rot_sum(o.mul(self.at(u, dsp), sp))
-            ws = o.mul(self.at(w, dsp), sp)
-            sc = o.conjugate(sp)
-            wss = o.mul(ws, self.at(sp, ws.depth))
-            wsc = o.mul(ws, self.at(sc, ws.depth))
-            de = self.rot_sum(o.set_scale(o.add(wsc, wss), 2.0))
-            do = self.rot_sum(o.set_scale(o.sub(wsc, wss), 2.0))
+            sp, num, de, do = self.run_batch(S, fixed)
             S_proj.append(sp)
             nums.append(num)
             dens_e.append(de)

@@ -6,8 +6,10 @@ device memory (through the allocator callbacks) and the HIP stream.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -46,6 +48,17 @@ class CkksError(RuntimeError):
 
 
 _LIB = None
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    """Destroy live contexts before the interpreter (and torch's allocator) shuts down."""
+    for c in list(_LIVE):
+        try:
+            c.close()
+        except Exception:
+            pass
 
 # (name, restype, argtypes)
 _SIGS = [
@@ -58,6 +71,8 @@ _SIGS = [
     ("ckks_ctx_scales", ctypes.c_int, [_vp, _dp, ctypes.c_int]),
     ("ckks_ctx_pool_stats", ctypes.c_int, [_vp, _szp, _szp, _szp, _szp]),
     ("ckks_ctx_pool_trim", ctypes.c_int, [_vp]),
+    ("ckks_ctx_kernel_timing", ctypes.c_int, [_vp, ctypes.c_int]),
+    ("ckks_ctx_kernel_report", ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     ("ckks_ctx_counters", ctypes.c_int, [_vp, _u64p, _u64p, _u64p]),
     ("ckks_keygen", ctypes.c_int, [_vp, ctypes.c_uint64, _u64p, ctypes.c_int]),
     ("ckks_galois_rotate", ctypes.c_uint64, [_vp, ctypes.c_int64]),
@@ -201,14 +216,20 @@ class Context:
             st = torch.cuda.current_stream() if stream is None else None
             s_handle = st.cuda_stream if st is not None else stream
 
+            t_alloc = torch.cuda.caching_allocator_alloc
+            t_free = torch.cuda.caching_allocator_delete
+
             def _alloc(nbytes, user):
                 try:
-                    return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev, s_handle))
+                    return int(t_alloc(int(nbytes), dev, s_handle))
                 except Exception:
                     return None
 
             def _free(ptr, nbytes, user):
-                torch.cuda.caching_allocator_delete(int(ptr))
+                try:
+                    t_free(int(ptr))
+                except Exception:
+                    pass
 
             fa, ff = ALLOC_FN(_alloc), FREE_FN(_free)
             self._keep += [fa, ff]
@@ -220,6 +241,7 @@ class Context:
         _check(lib().ckks_ctx_create(ctypes.byref(p), ctypes.byref(alloc) if alloc else None,
                                      _vp(stream_handle) if stream_handle else None, pool_budget, ctypes.byref(out)))
         self.h = out
+        _LIVE.add(self)
         self.log_n, self.levels, self.log2_scale = log_n, levels, log2_scale
         self.N = 1 << log_n
 
@@ -227,6 +249,7 @@ class Context:
         if self.h:
             lib().ckks_ctx_destroy(self.h)
             self.h = None
+        _LIVE.discard(self)
 
     def __del__(self):
         try:
@@ -257,6 +280,19 @@ class Context:
         v = [ctypes.c_uint64() for _ in range(3)]
         _check(lib().ckks_ctx_counters(self.h, *[ctypes.byref(x) for x in v]))
         return dict(zip(("keyswitches", "limb_ntts", "launches"), [x.value for x in v]))
+
+    def kernel_timing(self, enable: bool):
+        _check(lib().ckks_ctx_kernel_timing(self.h, 1 if enable else 0))
+
+    def kernel_report(self):
+        """{kernel: (launches, total_ms, algorithmic_bytes)} from the HIP-event timing."""
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().ckks_ctx_kernel_report(self.h, buf, len(buf)))
+        out = {}
+        for line in buf.value.decode().splitlines():
+            name, cnt, ms, by = line.split()
+            out[name] = (int(cnt), float(ms), float(by))
+        return out
 
     # ---- keys
     def keygen(self, seed: int, galois: Sequence[int] = ()):

@@ -146,6 +146,7 @@ int ckks_ctx_create(const ckks_params *params, const ckks_allocator *allocator, 
         c->pool = std::make_unique<Pool>(allocator, pool_budget_bytes);
         c->pool->stream = c->stream;
         build_tables(*c);
+        c->tab.timer = &c->timer;
         *out = c.release();
     });
 }
@@ -190,6 +191,32 @@ int ckks_ctx_counters(const ckks_ctx *ctx, uint64_t *keyswitches, uint64_t *limb
         if (keyswitches) *keyswitches = ctx->n_keyswitch;
         if (limb_ntts) *limb_ntts = ctx->n_limb_ntt;
         if (launches) *launches = ctx->n_launch;
+    });
+}
+
+int ckks_ctx_kernel_timing(ckks_ctx *ctx, int enable) {
+    return guard([&] {
+        need(ctx, "null context");
+        if (enable) ctx->timer.reset();
+        else ctx->timer.collect();
+        ctx->timer.on = enable != 0;
+    });
+}
+
+int ckks_ctx_kernel_report(ckks_ctx *ctx, char *buf, size_t cap) {
+    return guard([&] {
+        need(ctx && buf && cap > 0, "bad buffer");
+        ctx->timer.collect();
+        std::string s;
+        char line[256];
+        for (size_t i = 0; i < ctx->timer.names.size(); ++i) {
+            const auto &st = ctx->timer.stats[i];
+            std::snprintf(line, sizeof line, "%s %llu %.6f %.0f\n", ctx->timer.names[i].c_str(),
+                          (unsigned long long)st.count, st.ms, st.bytes);
+            s += line;
+        }
+        need(s.size() + 1 <= cap, "report buffer too small");
+        std::memcpy(buf, s.c_str(), s.size() + 1);
     });
 }
 

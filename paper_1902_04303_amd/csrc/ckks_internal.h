@@ -112,7 +112,33 @@ struct ModMap {
 };
 inline ModMap map_q(int l) { return ModMap{l, l, 0}; }
 
+// Optional per-kernel timing with HIP events on the launching stream (off by default).
+struct KTimer {
+    bool on = false;
+    struct Rec {
+        int id;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> spare;
+    std::vector<std::string> names;
+    std::map<std::string, int> ids;
+    struct Stat {
+        uint64_t count = 0;
+        double ms = 0, bytes = 0;
+    };
+    std::vector<Stat> stats;
+    hipEvent_t take();
+    int begin(const char *name, double bytes, hipStream_t st);
+    void end(int idx, hipStream_t st);
+    void collect();   // synchronises, folds recorded events into stats
+    void reset();
+    ~KTimer();
+};
+
 struct DevTables {
+    KTimer *timer = nullptr;
     ModInfo *mods = nullptr;            // [n_mods]
     u64 *psi = nullptr, *psi_sh = nullptr, *ipsi = nullptr, *ipsi_sh = nullptr;  // [n_mods][N]
     int n = 0, log_n = 0, n_mods = 0;

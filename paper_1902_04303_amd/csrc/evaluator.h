@@ -18,8 +18,9 @@ struct ckks_ctx {
     gck::DBuf sk_ntt;              // [L+2][N]: s mod q_0..q_L, P in NTT form
     gck::DBuf pk;                  // [2][L+1][N] NTT form
     std::map<uint64_t, gck::DBuf> ksk;   // key id (0 = relinearisation, else Galois element) -> [2][L+1][L+2][N]
-    // counters
+    // counters and optional per-kernel timing
     uint64_t n_keyswitch = 0, n_limb_ntt = 0, n_launch = 0;
+    gck::KTimer timer;
     ~ckks_ctx();
 };
 

@@ -15,6 +15,80 @@
 
 namespace gck {
 
+// ---------------------------------------------------------------- launch timing
+
+hipEvent_t KTimer::take() {
+    if (!spare.empty()) {
+        hipEvent_t e = spare.back();
+        spare.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    GCK_HIP(hipEventCreate(&e));
+    return e;
+}
+
+int KTimer::begin(const char *name, double bytes, hipStream_t st) {
+    auto it = ids.find(name);
+    int id;
+    if (it == ids.end()) {
+        id = (int)names.size();
+        ids[name] = id;
+        names.push_back(name);
+        stats.emplace_back();
+    } else {
+        id = it->second;
+    }
+    Rec r{id, take(), take(), bytes};
+    GCK_HIP(hipEventRecord(r.a, st));
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+}
+
+void KTimer::end(int idx, hipStream_t st) { GCK_HIP(hipEventRecord(recs[idx].b, st)); }
+
+void KTimer::collect() {
+    for (auto &r : recs) {
+        GCK_HIP(hipEventSynchronize(r.b));
+        float ms = 0;
+        GCK_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        Stat &s = stats[r.id];
+        ++s.count;
+        s.ms += ms;
+        s.bytes += r.bytes;
+        spare.push_back(r.a);
+        spare.push_back(r.b);
+    }
+    recs.clear();
+}
+
+void KTimer::reset() {
+    collect();
+    for (auto &s : stats) s = Stat{};
+}
+
+KTimer::~KTimer() {
+    for (auto &r : recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : spare) (void)hipEventDestroy(e);
+}
+
+namespace {
+struct TScope {
+    KTimer *t;
+    int idx = -1;
+    hipStream_t st;
+    TScope(const DevTables &tab, const char *name, double bytes, hipStream_t s) : t(tab.timer), st(s) {
+        if (t && t->on) idx = t->begin(name, bytes, st);
+    }
+    ~TScope() {
+        if (idx >= 0) t->end(idx, st);
+    }
+};
+}  // namespace
+
 // ---------------------------------------------------------------- device arithmetic
 
 __device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) {
@@ -255,8 +329,15 @@ void k_ntt_forward(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStrea
     if (n_limbs <= 0) return;
     NttGeom g = geom(t.n, t.log_n);
     dim3 grid((unsigned)(n_limbs * g.tiles));
-    hipLaunchKernelGGL(ntt_fwd_cols, grid, dim3(kNttThreads), 0, st, buf, m, t.mods, t.psi, t.psi_sh, g);
-    hipLaunchKernelGGL(ntt_fwd_rows, grid, dim3(kNttThreads), 0, st, buf, m, t.mods, t.psi, t.psi_sh, g);
+    const double bytes = 16.0 * (double)n_limbs * t.n;
+    {
+        TScope ts_(t, "ntt_fwd_cols", bytes, st);
+        hipLaunchKernelGGL(ntt_fwd_cols, grid, dim3(kNttThreads), 0, st, buf, m, t.mods, t.psi, t.psi_sh, g);
+    }
+    {
+        TScope ts_(t, "ntt_fwd_rows", bytes, st);
+        hipLaunchKernelGGL(ntt_fwd_rows, grid, dim3(kNttThreads), 0, st, buf, m, t.mods, t.psi, t.psi_sh, g);
+    }
     check_launch("ntt_fwd");
 }
 
@@ -264,8 +345,15 @@ void k_ntt_inverse(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStrea
     if (n_limbs <= 0) return;
     NttGeom g = geom(t.n, t.log_n);
     dim3 grid((unsigned)(n_limbs * g.tiles));
-    hipLaunchKernelGGL(ntt_inv_rows, grid, dim3(kNttThreads), 0, st, buf, m, t.mods, t.ipsi, t.ipsi_sh, g);
-    hipLaunchKernelGGL(ntt_inv_cols, grid, dim3(kNttThreads), 0, st, buf, m, t.mods, t.ipsi, t.ipsi_sh, g);
+    const double bytes = 16.0 * (double)n_limbs * t.n;
+    {
+        TScope ts_(t, "ntt_inv_rows", bytes, st);
+        hipLaunchKernelGGL(ntt_inv_rows, grid, dim3(kNttThreads), 0, st, buf, m, t.mods, t.ipsi, t.ipsi_sh, g);
+    }
+    {
+        TScope ts_(t, "ntt_inv_cols", bytes, st);
+        hipLaunchKernelGGL(ntt_inv_cols, grid, dim3(kNttThreads), 0, st, buf, m, t.mods, t.ipsi, t.ipsi_sh, g);
+    }
     check_launch("ntt_inv");
 }
 
@@ -385,6 +473,7 @@ __global__ void ew_tensor(u64 *out, const u64 *a, const u64 *b, size_t total, in
 }
 void k_tensor(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int count, int l, int na, int nb,
               bool accumulate, hipStream_t st) {
+    TScope ts_(t, "tensor", 8.0 * 7.0 * (double)((size_t)count * l) * t.n, st);
     size_t total = ((size_t)count * l) << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_tensor, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, l, t.mods, na, nb,
@@ -406,6 +495,7 @@ __global__ void ew_automorph(u64 *out, const u64 *a, size_t total, int log_n, u6
     }
 }
 void k_automorph(const DevTables &t, u64 *out, const u64 *a, int n_limbs, u64 g, hipStream_t st) {
+    TScope ts_(t, "automorph", 16.0 * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_automorph, ew_grid(total), dim3(kEwThreads), 0, st, out, a, total, t.log_n, g);
@@ -443,6 +533,7 @@ __global__ void ew_extend(u64 *out, const u64 *in, size_t total, int log_n, int 
 }
 void k_extend(const DevTables &t, u64 *out, const u64 *in, int rows, int l_out, ModMap out_map, int src_mod,
               bool centred, hipStream_t st) {
+    TScope ts_(t, "extend", 8.0 * (double)((size_t)rows * (l_out + 1)) * t.n, st);
     size_t total = ((size_t)rows * l_out) << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_extend, ew_grid(total), dim3(kEwThreads), 0, st, out, in, total, t.log_n, l_out, out_map,
@@ -462,6 +553,7 @@ __global__ void ew_modup(u64 *out, const u64 *in, size_t total, int log_n, int l
     }
 }
 void k_modup(const DevTables &t, u64 *out, const u64 *in, int count, int l, int p_idx, hipStream_t st) {
+    TScope ts_(t, "modup", 8.0 * (double)((size_t)count * l * (l + 1) + (size_t)count * l) * t.n, st);
     size_t total = ((size_t)count * l * (l + 1)) << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_modup, ew_grid(total), dim3(kEwThreads), 0, st, out, in, total, t.log_n, l, p_idx, t.mods);
@@ -480,6 +572,7 @@ __global__ void ew_sub_mul_const(u64 *out, const u64 *a, const u64 *b, size_t to
 }
 void k_sub_mul_const(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m,
                      const ChainConst &c, bool add_to_out, hipStream_t st) {
+    TScope ts_(t, "sub_mul_const", (add_to_out ? 32.0 : 24.0) * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_sub_mul_const, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, c,
@@ -502,6 +595,7 @@ __global__ void ew_add_rows(u64 *out, size_t out_stride, const u64 *in, size_t i
 }
 void k_add_rows(const DevTables &t, u64 *out, size_t out_stride, const u64 *in, size_t in_stride, int rows, int l,
                 hipStream_t st) {
+    TScope ts_(t, "add_rows", 24.0 * (double)((size_t)rows * l) * t.n, st);
     size_t total = ((size_t)rows * l) << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_add_rows, ew_grid(total), dim3(kEwThreads), 0, st, out, out_stride, in, in_stride, total,
@@ -549,6 +643,7 @@ __global__ void ks_inner(u64 *acc, const u64 *digits, const u64 *key, size_t tot
 }
 void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, const u64 *key, int count, int l, int levels,
                 hipStream_t st) {
+    TScope ts_(t, "ks_inner", 8.0 * (double)t.n * (2.0 * l * (l + 1) + (double)count * (l * (l + 1) + 2 * (l + 1))), st);
     size_t total = ((size_t)count * (l + 1)) << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ks_inner, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, key, total, t.log_n, l, levels, t.mods);
