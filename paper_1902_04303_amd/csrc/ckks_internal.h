@@ -151,6 +151,10 @@ struct ChainConst {     // one constant per chain index (value and Shoup compani
 
 void k_ntt_forward(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStream_t st);
 void k_ntt_inverse(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStream_t st);
+// forward NTT whose input limb lam is src limb lam / src_div reduced modulo limb lam's modulus
+// (ModUp: digits in coefficient form -> every target modulus, NTT form)
+void k_ntt_forward_from(const DevTables &t, u64 *buf, const u64 *src, int src_div, int n_limbs, ModMap m,
+                        hipStream_t st);
 // out = a op b over n_limbs limbs; a is read at limb (lam % na_limbs), b at (lam % nb_limbs)
 void k_add(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
            hipStream_t st);

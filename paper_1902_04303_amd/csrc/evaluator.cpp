@@ -289,9 +289,10 @@ static DBuf keyswitch(ckks_ctx &c, const u64 *d, int count, int l, u64 id) {
     GCK_HIP(hipMemcpyAsync(dc.ptr, d, (size_t)count * l * N * 8, hipMemcpyDeviceToDevice, c.stream));
     ntt_inv(c, dc.ptr, count * l, map_q(l));
     DBuf dig(c.pool.get(), (size_t)count * l * (l + 1) * N);
-    k_modup(c.tab, dig.ptr, dc.ptr, count, l, P, c.stream);
+    k_ntt_forward_from(c.tab, dig.ptr, dc.ptr, l + 1, count * l * (l + 1), ModMap{l + 1, l, P}, c.stream);
+    c.n_limb_ntt += (uint64_t)count * l * (l + 1);
+    c.n_launch += 2;
     dc.release();
-    ntt_fwd(c, dig.ptr, count * l * (l + 1), ModMap{l + 1, l, P});
     // inner product with the key
     DBuf acc(c.pool.get(), (size_t)count * 2 * (l + 1) * N);
     k_ks_inner(c.tab, acc.ptr, dig.ptr, it->second.ptr, count, l, c.p.levels, c.stream);

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include "ckks_internal.h"
+#include "modarith.h"
 
 namespace gck {
 
@@ -75,287 +76,6 @@ KTimer::~KTimer() {
     for (auto e : spare) (void)hipEventDestroy(e);
 }
 
-namespace {
-struct TScope {
-    KTimer *t;
-    int idx = -1;
-    hipStream_t st;
-    TScope(const DevTables &tab, const char *name, double bytes, hipStream_t s) : t(tab.timer), st(s) {
-        if (t && t->on) idx = t->begin(name, bytes, st);
-    }
-    ~TScope() {
-        if (idx >= 0) t->end(idx, st);
-    }
-};
-}  // namespace
-
-// ---------------------------------------------------------------- device arithmetic
-
-__device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) {
-    u64 s = a + b;
-    return s >= q ? s - q : s;
-}
-__device__ __forceinline__ u64 sub_mod(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
-
-// a * w mod q for fixed w with companion wsh = floor(w 2^64 / q); any a < 2^64
-__device__ __forceinline__ u64 mul_shoup(u64 a, u64 w, u64 wsh, u64 q) {
-    u64 hi = __umul64hi(a, wsh);
-    u64 r = a * w - hi * q;
-    return r >= q ? r - q : r;
-}
-
-// (hi, lo) * 2^-64 mod q, for hi < q
-__device__ __forceinline__ u64 redc(u64 hi, u64 lo, const ModInfo &M) {
-    u64 m = lo * M.mont_inv;
-    u64 mh = __umul64hi(m, M.q);
-    u64 r = hi + mh + (lo != 0 ? 1 : 0);
-    return r >= M.q ? r - M.q : r;
-}
-
-// a * b mod q for a, b < q
-__device__ __forceinline__ u64 mul_mod(u64 a, u64 b, const ModInfo &M) {
-    u64 t = redc(__umul64hi(a, b), a * b, M);
-    return mul_shoup(t, M.r_mod, M.r_mod_sh, M.q);
-}
-
-// x mod q for any 64-bit x
-__device__ __forceinline__ u64 reduce64(u64 x, const ModInfo &M) {
-    u64 qh = __umul64hi(x, M.barrett);
-    u64 r = x - qh * M.q;
-    return r >= M.q ? r - M.q : r;
-}
-
-__device__ __forceinline__ int chain_of(int lam, ModMap m) {
-    int t = lam % m.period;
-    return t < m.nq ? t : m.p_idx;
-}
-
-// ---------------------------------------------------------------- SplitMix64 (test-only randomness)
-
-__device__ __forceinline__ u64 sm_mix(u64 z) {
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-    return z ^ (z >> 31);
-}
-__device__ __forceinline__ u64 sm_out(u64 x, u64 i) { return sm_mix(x + (i + 1) * 0x9E3779B97F4A7C15ULL); }
-
-// (w1 2^64 + w2) mod q
-__device__ __forceinline__ u64 mod_u128(u64 w1, u64 w2, u64 q) {
-    u64 r = w1 % q;
-    for (int b = 63; b >= 0; --b) {
-        r = (r << 1) | ((w2 >> b) & 1ULL);
-        if (r >= q) r -= q;
-    }
-    return r;
-}
-
-// ---------------------------------------------------------------- NTT
-//
-// Negacyclic NTT over Z_q[X]/(X^N + 1): forward maps coefficients to the
-// evaluations at psi^(2 brev(k) + 1) stored at index k (bit-reversed order),
-// psi a primitive 2N-th root of unity; inverse maps them back.  Merged
-// Cooley-Tukey (forward) / Gentleman-Sande (inverse) butterflies with the
-// bit-reversed power tables psi_rev[k] = psi^brev(k), ipsi_rev[k] = psi^-brev(k).
-//
-// N = N1 * N2 is done in two passes over HBM, each staging a 4096-word tile in
-// LDS: the first log2(N1) stages only pair words in the same column (index mod
-// N2) and the last log2(N2) stages only pair words in the same row of N2
-// contiguous words.
-
-constexpr int kTile = 4096;
-constexpr int kNttThreads = 256;
-
-struct NttGeom {
-    int n, log_n;
-    int n1, log_n1, n2, log_n2;
-    int log_cw;      // log2 columns per pass-1 tile
-    int log_rows;    // log2 rows per pass-2 tile
-    int tiles;       // tiles per limb
-};
-
-static NttGeom geom(int n, int log_n) {
-    NttGeom g;
-    g.n = n;
-    g.log_n = log_n;
-    g.log_n1 = (log_n + 1) / 2;
-    g.log_n2 = log_n - g.log_n1;
-    g.n1 = 1 << g.log_n1;
-    g.n2 = 1 << g.log_n2;
-    int tile = n < kTile ? n : kTile;
-    int log_tile = 0;
-    while ((1 << log_tile) < tile) ++log_tile;
-    g.log_cw = log_tile - g.log_n1;
-    g.log_rows = log_tile - g.log_n2;
-    g.tiles = n / tile;
-    return g;
-}
-
-__global__ void __launch_bounds__(kNttThreads) ntt_fwd_cols(u64 *buf, ModMap mm, const ModInfo *mods,
-                                                            const u64 *psi, const u64 *psi_sh, NttGeom g) {
-    __shared__ u64 sh[kTile];
-    const int limb = blockIdx.x / g.tiles, tile = blockIdx.x % g.tiles;
-    const int chain = chain_of(limb, mm);
-    const u64 q = mods[chain].q;
-    const u64 *W = psi + (size_t)chain * g.n, *Ws = psi_sh + (size_t)chain * g.n;
-    u64 *a = buf + (size_t)limb * g.n;
-    const int cw = 1 << g.log_cw, col0 = tile << g.log_cw;
-    const int total = g.n1 << g.log_cw;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        int r = e >> g.log_cw, c = e & (cw - 1);
-        sh[e] = a[((size_t)r << g.log_n2) + col0 + c];
-    }
-    __syncthreads();
-    const int nbf = total >> 1;
-    for (int m = 1, lt = g.log_n1 - 1; m < g.n1; m <<= 1, --lt) {
-        for (int b = threadIdx.x; b < nbf; b += blockDim.x) {
-            int c = b & (cw - 1), p = b >> g.log_cw;
-            int i = p >> lt, j = p & ((1 << lt) - 1);
-            int r1 = (i << (lt + 1)) + j, r2 = r1 + (1 << lt);
-            u64 U = sh[(r1 << g.log_cw) + c];
-            u64 V = mul_shoup(sh[(r2 << g.log_cw) + c], W[m + i], Ws[m + i], q);
-            sh[(r1 << g.log_cw) + c] = add_mod(U, V, q);
-            sh[(r2 << g.log_cw) + c] = sub_mod(U, V, q);
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        int r = e >> g.log_cw, c = e & (cw - 1);
-        a[((size_t)r << g.log_n2) + col0 + c] = sh[e];
-    }
-}
-
-__global__ void __launch_bounds__(kNttThreads) ntt_fwd_rows(u64 *buf, ModMap mm, const ModInfo *mods,
-                                                            const u64 *psi, const u64 *psi_sh, NttGeom g) {
-    __shared__ u64 sh[kTile];
-    const int limb = blockIdx.x / g.tiles, tile = blockIdx.x % g.tiles;
-    const int chain = chain_of(limb, mm);
-    const u64 q = mods[chain].q;
-    const u64 *W = psi + (size_t)chain * g.n, *Ws = psi_sh + (size_t)chain * g.n;
-    const int row0 = tile << g.log_rows;
-    u64 *a = buf + (size_t)limb * g.n + ((size_t)row0 << g.log_n2);
-    const int total = 1 << (g.log_rows + g.log_n2);
-    for (int e = threadIdx.x; e < total; e += blockDim.x) sh[e] = a[e];
-    __syncthreads();
-    const int nbf = total >> 1, log_half = g.log_n2 - 1;
-    for (int mp = 1, lt = g.log_n2 - 1; mp < g.n2; mp <<= 1, --lt) {
-        for (int b = threadIdx.x; b < nbf; b += blockDim.x) {
-            int rr = b >> log_half, p = b & ((1 << log_half) - 1);
-            int i = p >> lt, j = p & ((1 << lt) - 1);
-            int c1 = (i << (lt + 1)) + j, c2 = c1 + (1 << lt);
-            int widx = mp * (g.n1 + row0 + rr) + i;
-            int o = rr << g.log_n2;
-            u64 U = sh[o + c1];
-            u64 V = mul_shoup(sh[o + c2], W[widx], Ws[widx], q);
-            sh[o + c1] = add_mod(U, V, q);
-            sh[o + c2] = sub_mod(U, V, q);
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < total; e += blockDim.x) a[e] = sh[e];
-}
-
-__global__ void __launch_bounds__(kNttThreads) ntt_inv_rows(u64 *buf, ModMap mm, const ModInfo *mods,
-                                                            const u64 *ipsi, const u64 *ipsi_sh, NttGeom g) {
-    __shared__ u64 sh[kTile];
-    const int limb = blockIdx.x / g.tiles, tile = blockIdx.x % g.tiles;
-    const int chain = chain_of(limb, mm);
-    const u64 q = mods[chain].q;
-    const u64 *W = ipsi + (size_t)chain * g.n, *Ws = ipsi_sh + (size_t)chain * g.n;
-    const int row0 = tile << g.log_rows;
-    u64 *a = buf + (size_t)limb * g.n + ((size_t)row0 << g.log_n2);
-    const int total = 1 << (g.log_rows + g.log_n2);
-    for (int e = threadIdx.x; e < total; e += blockDim.x) sh[e] = a[e];
-    __syncthreads();
-    const int nbf = total >> 1, log_half = g.log_n2 - 1;
-    for (int mp = g.n2 >> 1, lt = 0; mp >= 1; mp >>= 1, ++lt) {
-        for (int b = threadIdx.x; b < nbf; b += blockDim.x) {
-            int rr = b >> log_half, p = b & ((1 << log_half) - 1);
-            int i = p >> lt, j = p & ((1 << lt) - 1);
-            int c1 = (i << (lt + 1)) + j, c2 = c1 + (1 << lt);
-            int widx = mp * (g.n1 + row0 + rr) + i;
-            int o = rr << g.log_n2;
-            u64 U = sh[o + c1], V = sh[o + c2];
-            sh[o + c1] = add_mod(U, V, q);
-            sh[o + c2] = mul_shoup(sub_mod(U, V, q), W[widx], Ws[widx], q);
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < total; e += blockDim.x) a[e] = sh[e];
-}
-
-__global__ void __launch_bounds__(kNttThreads) ntt_inv_cols(u64 *buf, ModMap mm, const ModInfo *mods,
-                                                            const u64 *ipsi, const u64 *ipsi_sh, NttGeom g) {
-    __shared__ u64 sh[kTile];
-    const int limb = blockIdx.x / g.tiles, tile = blockIdx.x % g.tiles;
-    const int chain = chain_of(limb, mm);
-    const ModInfo M = mods[chain];
-    const u64 q = M.q;
-    const u64 *W = ipsi + (size_t)chain * g.n, *Ws = ipsi_sh + (size_t)chain * g.n;
-    u64 *a = buf + (size_t)limb * g.n;
-    const int cw = 1 << g.log_cw, col0 = tile << g.log_cw;
-    const int total = g.n1 << g.log_cw;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        int r = e >> g.log_cw, c = e & (cw - 1);
-        sh[e] = a[((size_t)r << g.log_n2) + col0 + c];
-    }
-    __syncthreads();
-    const int nbf = total >> 1;
-    for (int m = g.n1 >> 1, lt = 0; m >= 1; m >>= 1, ++lt) {
-        const bool last = (m == 1);
-        for (int b = threadIdx.x; b < nbf; b += blockDim.x) {
-            int c = b & (cw - 1), p = b >> g.log_cw;
-            int i = p >> lt, j = p & ((1 << lt) - 1);
-            int r1 = (i << (lt + 1)) + j, r2 = r1 + (1 << lt);
-            u64 U = sh[(r1 << g.log_cw) + c], V = sh[(r2 << g.log_cw) + c];
-            if (!last) {
-                sh[(r1 << g.log_cw) + c] = add_mod(U, V, q);
-                sh[(r2 << g.log_cw) + c] = mul_shoup(sub_mod(U, V, q), W[m + i], Ws[m + i], q);
-            } else {
-                sh[(r1 << g.log_cw) + c] = mul_shoup(add_mod(U, V, q), M.ninv, M.ninv_sh, q);
-                sh[(r2 << g.log_cw) + c] = mul_shoup(sub_mod(U, V, q), M.w1ninv, M.w1ninv_sh, q);
-            }
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        int r = e >> g.log_cw, c = e & (cw - 1);
-        a[((size_t)r << g.log_n2) + col0 + c] = sh[e];
-    }
-}
-
-static void check_launch(const char *what) { GCK_HIP(hipGetLastError()); (void)what; }
-
-void k_ntt_forward(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStream_t st) {
-    if (n_limbs <= 0) return;
-    NttGeom g = geom(t.n, t.log_n);
-    dim3 grid((unsigned)(n_limbs * g.tiles));
-    const double bytes = 16.0 * (double)n_limbs * t.n;
-    {
-        TScope ts_(t, "ntt_fwd_cols", bytes, st);
-        hipLaunchKernelGGL(ntt_fwd_cols, grid, dim3(kNttThreads), 0, st, buf, m, t.mods, t.psi, t.psi_sh, g);
-    }
-    {
-        TScope ts_(t, "ntt_fwd_rows", bytes, st);
-        hipLaunchKernelGGL(ntt_fwd_rows, grid, dim3(kNttThreads), 0, st, buf, m, t.mods, t.psi, t.psi_sh, g);
-    }
-    check_launch("ntt_fwd");
-}
-
-void k_ntt_inverse(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStream_t st) {
-    if (n_limbs <= 0) return;
-    NttGeom g = geom(t.n, t.log_n);
-    dim3 grid((unsigned)(n_limbs * g.tiles));
-    const double bytes = 16.0 * (double)n_limbs * t.n;
-    {
-        TScope ts_(t, "ntt_inv_rows", bytes, st);
-        hipLaunchKernelGGL(ntt_inv_rows, grid, dim3(kNttThreads), 0, st, buf, m, t.mods, t.ipsi, t.ipsi_sh, g);
-    }
-    {
-        TScope ts_(t, "ntt_inv_cols", bytes, st);
-        hipLaunchKernelGGL(ntt_inv_cols, grid, dim3(kNttThreads), 0, st, buf, m, t.mods, t.ipsi, t.ipsi_sh, g);
-    }
-    check_launch("ntt_inv");
-}
 
 // ---------------------------------------------------------------- elementwise
 
@@ -389,21 +109,21 @@ void k_add(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_binary<0>, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, na, nb);
-    check_launch("add");
+    check_launch();
 }
 void k_sub(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
            hipStream_t st) {
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_binary<1>, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, na, nb);
-    check_launch("sub");
+    check_launch();
 }
 void k_mul(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
            hipStream_t st) {
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_binary<2>, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, na, nb);
-    check_launch("mul");
+    check_launch();
 }
 
 __global__ void ew_mul_const(u64 *out, const u64 *a, size_t total, int log_n, ModMap mm, const ModInfo *mods,
@@ -419,7 +139,7 @@ void k_mul_const(const DevTables &t, u64 *out, const u64 *a, int n_limbs, ModMap
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_mul_const, ew_grid(total), dim3(kEwThreads), 0, st, out, a, total, t.log_n, m, t.mods, c);
-    check_launch("mul_const");
+    check_launch();
 }
 
 // a constant polynomial c evaluates to c at every NTT point
@@ -438,7 +158,7 @@ void k_add_const_c0(const DevTables &t, u64 *ct, int count, int l, const ChainCo
     size_t total = ((size_t)count * l) << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_add_const_c0, ew_grid(total), dim3(kEwThreads), 0, st, ct, total, t.log_n, l, t.mods, c);
-    check_launch("add_const");
+    check_launch();
 }
 
 __global__ void ew_tensor(u64 *out, const u64 *a, const u64 *b, size_t total, int log_n, int l, const ModInfo *mods,
@@ -478,7 +198,7 @@ void k_tensor(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int coun
     if (!total) return;
     hipLaunchKernelGGL(ew_tensor, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, l, t.mods, na, nb,
                        accumulate ? 1 : 0);
-    check_launch("tensor");
+    check_launch();
 }
 
 // out[k] = a[k'] with psi^(2 brev(k') + 1) = (psi^(2 brev(k) + 1))^g
@@ -499,7 +219,7 @@ void k_automorph(const DevTables &t, u64 *out, const u64 *a, int n_limbs, u64 g,
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_automorph, ew_grid(total), dim3(kEwThreads), 0, st, out, a, total, t.log_n, g);
-    check_launch("automorph");
+    check_launch();
 }
 
 __global__ void ew_copy_rows(u64 *out, size_t out_stride, const u64 *in, size_t in_stride, size_t total, size_t words) {
@@ -513,7 +233,7 @@ void k_copy_rows(u64 *out, size_t out_stride, const u64 *in, size_t in_stride, i
     size_t total = (size_t)rows * words;
     if (!total) return;
     hipLaunchKernelGGL(ew_copy_rows, ew_grid(total), dim3(kEwThreads), 0, st, out, out_stride, in, in_stride, total, words);
-    check_launch("copy_rows");
+    check_launch();
 }
 
 __global__ void ew_extend(u64 *out, const u64 *in, size_t total, int log_n, int l_out, ModMap om, const ModInfo *mods,
@@ -538,7 +258,7 @@ void k_extend(const DevTables &t, u64 *out, const u64 *in, int rows, int l_out, 
     if (!total) return;
     hipLaunchKernelGGL(ew_extend, ew_grid(total), dim3(kEwThreads), 0, st, out, in, total, t.log_n, l_out, out_map,
                        t.mods, src_mod, centred ? 1 : 0);
-    check_launch("extend");
+    check_launch();
 }
 
 __global__ void ew_modup(u64 *out, const u64 *in, size_t total, int log_n, int l, int p_idx, const ModInfo *mods) {
@@ -557,7 +277,7 @@ void k_modup(const DevTables &t, u64 *out, const u64 *in, int count, int l, int 
     size_t total = ((size_t)count * l * (l + 1)) << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_modup, ew_grid(total), dim3(kEwThreads), 0, st, out, in, total, t.log_n, l, p_idx, t.mods);
-    check_launch("modup");
+    check_launch();
 }
 
 __global__ void ew_sub_mul_const(u64 *out, const u64 *a, const u64 *b, size_t total, int log_n, ModMap mm,
@@ -577,7 +297,7 @@ void k_sub_mul_const(const DevTables &t, u64 *out, const u64 *a, const u64 *b, i
     if (!total) return;
     hipLaunchKernelGGL(ew_sub_mul_const, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, c,
                        add_to_out ? 1 : 0);
-    check_launch("sub_mul_const");
+    check_launch();
 }
 
 // out[r][i] += in[r][i] for rows of l limbs (limb i of a row is modulo q_i)
@@ -600,7 +320,7 @@ void k_add_rows(const DevTables &t, u64 *out, size_t out_stride, const u64 *in, 
     if (!total) return;
     hipLaunchKernelGGL(ew_add_rows, ew_grid(total), dim3(kEwThreads), 0, st, out, out_stride, in, in_stride, total,
                        t.log_n, l, t.mods);
-    check_launch("add_rows");
+    check_launch();
 }
 
 // ---------------------------------------------------------------- key-switch inner product
@@ -647,7 +367,7 @@ void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, const u64 *key,
     size_t total = ((size_t)count * (l + 1)) << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ks_inner, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, key, total, t.log_n, l, levels, t.mods);
-    check_launch("ks_inner");
+    check_launch();
 }
 
 // ---------------------------------------------------------------- samplers and conversions
@@ -667,7 +387,7 @@ void k_sample_uniform(const DevTables &t, u64 *out, u64 seed, u64 sid, int n_lim
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(sample_uniform, ew_grid(total), dim3(kEwThreads), 0, st, out, seed, sid, total, t.log_n, m, t.mods);
-    check_launch("sample_uniform");
+    check_launch();
 }
 
 __global__ void sample_small(i64 *out, u64 seed, u64 sid, int n, int kind) {
@@ -680,11 +400,11 @@ __global__ void sample_small(i64 *out, u64 seed, u64 sid, int n, int kind) {
 }
 void k_sample_cbd(i64 *out, u64 seed, u64 sid, int n, hipStream_t st) {
     hipLaunchKernelGGL(sample_small, ew_grid(n), dim3(kEwThreads), 0, st, out, seed, sid, n, 0);
-    check_launch("sample_cbd");
+    check_launch();
 }
 void k_sample_ternary(i64 *out, u64 seed, u64 sid, int n, hipStream_t st) {
     hipLaunchKernelGGL(sample_small, ew_grid(n), dim3(kEwThreads), 0, st, out, seed, sid, n, 1);
-    check_launch("sample_ternary");
+    check_launch();
 }
 
 __global__ void ew_signed_to_limbs(u64 *out, const i64 *in, size_t total, int log_n, ModMap mm, const ModInfo *mods) {
@@ -707,7 +427,7 @@ void k_signed_to_limbs(const DevTables &t, u64 *out, const i64 *in, int n_limbs,
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_signed_to_limbs, ew_grid(total), dim3(kEwThreads), 0, st, out, in, total, t.log_n, m, t.mods);
-    check_launch("signed_to_limbs");
+    check_launch();
 }
 
 __global__ void ew_mont(u64 *x, size_t total, int log_n, ModMap mm, const ModInfo *mods, int to) {
@@ -721,13 +441,13 @@ void k_to_mont(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t st
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_mont, ew_grid(total), dim3(kEwThreads), 0, st, x, total, t.log_n, m, t.mods, 1);
-    check_launch("to_mont");
+    check_launch();
 }
 void k_from_mont(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t st) {
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_mont, ew_grid(total), dim3(kEwThreads), 0, st, x, total, t.log_n, m, t.mods, 0);
-    check_launch("from_mont");
+    check_launch();
 }
 
 __global__ void ew_neg(u64 *x, size_t total, int log_n, ModMap mm, const ModInfo *mods) {
@@ -741,7 +461,7 @@ void k_neg(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t st) {
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_neg, ew_grid(total), dim3(kEwThreads), 0, st, x, total, t.log_n, m, t.mods);
-    check_launch("neg");
+    check_launch();
 }
 
 }  // namespace gck

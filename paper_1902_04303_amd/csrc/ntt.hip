@@ -1,0 +1,292 @@
+// Negacyclic NTT over Z_q[X]/(X^N + 1) for gfx950.
+//
+// Forward: coefficients -> evaluations at psi^(2 brev(k) + 1) stored at index k (bit-reversed
+// order), psi a primitive 2N-th root of unity; merged Cooley-Tukey butterflies with the table
+// psi_rev[k] = psi^brev(k).  Inverse: Gentleman-Sande butterflies with psi^-brev(k), then N^-1.
+//
+// N = N1 * N2 in two passes over HBM.  The first log2(N1) stages pair words of the same column
+// (index mod N2): pass "cols" runs N1-point sub-transforms down columns; the last log2(N2) stages
+// pair words of the same row of N2 contiguous words: pass "rows".  Each block stages a tile of
+// 4096 words in LDS; each thread holds 16 words in registers and runs up to four radix-2 stages on
+// them before one LDS exchange (a 256-point sub-transform is two register phases).  Butterflies
+// are lazy (Harvey): values stay in [0, 4q) (forward) or [0, 2q) (inverse) between stages and are
+// fully reduced on the way out; q < 2^62.
+#include <hip/hip_runtime.h>
+
+#include "modarith.h"
+
+namespace gck {
+
+namespace {
+
+constexpr int kTileWords = 4096;
+constexpr int kThreads = 256;
+constexpr int kPer = 16;   // words per thread
+
+struct Geom {
+    int log_n, n2, log_n1, log_n2;
+    int log_g_cols;   // sub-transforms (columns) per cols tile
+    int log_g_rows;   // sub-transforms (rows) per rows tile
+    int tiles;        // tiles per limb (same for both passes)
+};
+
+Geom make_geom(int log_n) {
+    Geom g;
+    g.log_n = log_n;
+    g.log_n1 = (log_n + 1) / 2;
+    g.log_n2 = log_n - g.log_n1;
+    g.n2 = 1 << g.log_n2;
+    int log_tile = log_n < 12 ? log_n : 12;
+    g.log_g_cols = log_tile - g.log_n1;
+    g.log_g_rows = log_tile - g.log_n2;
+    g.tiles = 1 << (log_n - log_tile);
+    return g;
+}
+
+// LDS address of word idx of sub-transform gi; row tiles are padded (one word per 16) so that
+// threads reading 16 consecutive words of a row do not all hit one bank.
+template <bool ROWS>
+__device__ __forceinline__ int lds_addr(int gi, int idx, int log_m, int log_g) {
+    if (ROWS) {
+        const int m = 1 << log_m;
+        return gi * (m + (m >> 4)) + idx + (idx >> 4);
+    }
+    return (idx << log_g) + gi;
+}
+
+// One register phase of a sub-transform of size M = 2^LOGM: stages S0 .. S0 + R - 1.
+// The thread owns groups gam = q + j * T (T = M / 16 threads per sub-transform), each of 2^R words
+// index(k) = hi * (M >> S0) + k * tmin + lo, tmin = M >> (S0 + R), gam = hi * tmin + lo.
+// Twiddle of a butterfly at stage s, block i: table[(1 << s) * base_off + i].
+template <int LOGM, int S0, int R>
+__device__ __forceinline__ int slot_index(int e, int q) {
+    constexpr int LOG_TMIN = LOGM - S0 - R;
+    const int jg = e >> R, k = e & ((1 << R) - 1);
+    const int gam = q + (jg << (LOGM - 4));
+    const int hi = gam >> LOG_TMIN, lo = gam & ((1 << LOG_TMIN) - 1);
+    return (hi << (LOGM - S0)) + (k << LOG_TMIN) + lo;
+}
+
+template <bool INV, int LOGM, int S0, int R>
+__device__ __forceinline__ void phase(u64 (&v)[kPer], int q, int base_off, const u64 *__restrict__ W,
+                                      const u64 *__restrict__ Ws, u64 qm) {
+    constexpr int LOG_TMIN = LOGM - S0 - R;
+    constexpr int GPT = kPer >> R;
+    const u64 q2 = 2 * qm;
+#pragma unroll
+    for (int jg = 0; jg < GPT; ++jg) {
+        const int gam = q + (jg << (LOGM - 4));
+        const int hi = gam >> LOG_TMIN, lo = gam & ((1 << LOG_TMIN) - 1);
+        const int base_idx = (hi << (LOGM - S0)) + lo;
+#pragma unroll
+        for (int uu = 0; uu < R; ++uu) {
+            const int u = INV ? R - 1 - uu : uu;
+            const int s = S0 + u;
+            const int half = 1 << (R - 1 - u);
+            const int log_t = LOGM - s - 1;
+#pragma unroll
+            for (int k = 0; k < (1 << R); ++k) {
+                if (k & half) continue;
+                const int e0 = jg * (1 << R) + k, e1 = e0 + half;
+                const int idx = base_idx + (k << LOG_TMIN);
+                const int widx = (base_off << s) + (idx >> (log_t + 1));
+                const u64 w = W[widx], wsh = Ws[widx];
+                if (!INV) {
+                    u64 a = v[e0];
+                    a = a >= q2 ? a - q2 : a;
+                    const u64 t = mul_shoup_lazy(v[e1], w, wsh, qm);
+                    v[e0] = a + t;
+                    v[e1] = a - t + q2;
+                } else {
+                    const u64 a = v[e0], b = v[e1];
+                    u64 sum = a + b;
+                    v[e0] = sum >= q2 ? sum - q2 : sum;
+                    v[e1] = mul_shoup_lazy(a - b + q2, w, wsh, qm);
+                }
+            }
+        }
+    }
+}
+
+template <int LOGM, int PH>
+struct Ph {
+    static constexpr int S0 = PH * 4;
+    static constexpr int R = (LOGM - S0) < 4 ? (LOGM - S0) : 4;
+};
+
+// LDS exchange: registers laid out for phase FROM -> LDS -> registers laid out for phase TO
+template <bool ROWS, int LOGM, int FROM, int TO>
+__device__ __forceinline__ void exchange(u64 (&v)[kPer], u64 *sh, int gi, int q, int log_g) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kPer; ++e)
+        sh[lds_addr<ROWS>(gi, slot_index<LOGM, Ph<LOGM, FROM>::S0, Ph<LOGM, FROM>::R>(e, q), LOGM, log_g)] = v[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kPer; ++e)
+        v[e] = sh[lds_addr<ROWS>(gi, slot_index<LOGM, Ph<LOGM, TO>::S0, Ph<LOGM, TO>::R>(e, q), LOGM, log_g)];
+}
+
+// One pass.  ROWS selects the rows pass (sub-transforms of N2 contiguous words) or the cols pass
+// (N1-point sub-transforms down columns).  src != nullptr (forward cols pass only): the input of
+// output limb lam is limb lam / src_div of src, reduced modulo the output limb's modulus (ModUp).
+template <bool INV, bool ROWS, int LOGM>
+__global__ void __launch_bounds__(kThreads) ntt_pass(u64 *__restrict__ buf, const u64 *__restrict__ src, int src_div,
+                                                     ModMap mm, const ModInfo *__restrict__ mods,
+                                                     const u64 *__restrict__ tw, const u64 *__restrict__ tw_sh,
+                                                     Geom g) {
+    __shared__ u64 sh[kTileWords + (kTileWords >> 4)];
+    constexpr int NPH = (LOGM + 3) / 4;
+    constexpr int FIRST = INV ? NPH - 1 : 0;
+    constexpr int LAST = INV ? 0 : NPH - 1;
+    const int log_tile = g.log_n < 12 ? g.log_n : 12;
+    const int limb = blockIdx.x >> (g.log_n - log_tile);
+    const int tile = blockIdx.x & (g.tiles - 1);
+    const int chain = chain_of(limb, mm);
+    const ModInfo M = mods[chain];
+    const u64 qm = M.q;
+    const size_t n = (size_t)1 << g.log_n;
+    const u64 *W = tw + (size_t)chain * n, *Ws = tw_sh + (size_t)chain * n;
+    const int log_g = ROWS ? g.log_g_rows : g.log_g_cols;
+    constexpr int LOG_T = LOGM - 4;
+    const int tid = threadIdx.x;
+    int gi, q;
+    if (ROWS) {
+        q = tid & ((1 << LOG_T) - 1);
+        gi = tid >> LOG_T;
+    } else {
+        gi = tid & ((1 << log_g) - 1);
+        q = tid >> log_g;
+    }
+    u64 *a = buf + (size_t)limb * n;
+    const bool modup = (src != nullptr);
+    const u64 *ain = modup ? src + (size_t)(limb / src_div) * n : a;
+    size_t base;
+    int stride, base_off;
+    if (ROWS) {
+        const int row = (tile << log_g) + gi;
+        base = (size_t)row << g.log_n2;
+        stride = 1;
+        base_off = (1 << g.log_n1) + row;
+    } else {
+        base = (size_t)(tile << log_g) + gi;
+        stride = g.n2;
+        base_off = 1;
+    }
+    u64 v[kPer];
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+        const int idx = slot_index<LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(e, q);
+        u64 x = ain[base + (size_t)idx * stride];
+        if (modup) x = reduce64(x, M);
+        v[e] = x;
+    }
+    phase<INV, LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(v, q, base_off, W, Ws, qm);
+    if constexpr (NPH > 1) {
+        constexpr int P1 = INV ? NPH - 2 : 1;
+        exchange<ROWS, LOGM, FIRST, P1>(v, sh, gi, q, log_g);
+        phase<INV, LOGM, Ph<LOGM, P1>::S0, Ph<LOGM, P1>::R>(v, q, base_off, W, Ws, qm);
+        if constexpr (NPH > 2) {
+            constexpr int P2 = INV ? NPH - 3 : 2;
+            exchange<ROWS, LOGM, P1, P2>(v, sh, gi, q, log_g);
+            phase<INV, LOGM, Ph<LOGM, P2>::S0, Ph<LOGM, P2>::R>(v, q, base_off, W, Ws, qm);
+        }
+    }
+    // final scaling (inverse cols pass: N^-1) and reduction ([0, q) at the end of a transform)
+    const bool last_pass = INV ? !ROWS : ROWS;
+    const u64 q2 = 2 * qm;
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+        u64 x = v[e];
+        if (INV && !ROWS) x = mul_shoup_lazy(x, M.ninv, M.ninv_sh, qm);
+        x = x >= q2 ? x - q2 : x;
+        if (last_pass) x = x >= qm ? x - qm : x;
+        v[e] = x;
+    }
+    if (ROWS) {
+        // coalesced store through LDS, read back in the layout of the first forward phase
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < kPer; ++e)
+            sh[lds_addr<ROWS>(gi, slot_index<LOGM, Ph<LOGM, LAST>::S0, Ph<LOGM, LAST>::R>(e, q), LOGM, log_g)] = v[e];
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            const int idx = slot_index<LOGM, 0, Ph<LOGM, 0>::R>(e, q);
+            a[base + idx] = sh[lds_addr<ROWS>(gi, idx, LOGM, log_g)];
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            const int idx = slot_index<LOGM, Ph<LOGM, LAST>::S0, Ph<LOGM, LAST>::R>(e, q);
+            a[base + (size_t)idx * stride] = v[e];
+        }
+    }
+}
+
+template <bool INV, bool ROWS>
+void launch_pass(int log_m, dim3 grid, dim3 block, hipStream_t st, u64 *buf, const u64 *src, int src_div, ModMap m,
+                 const ModInfo *mods, const u64 *tw, const u64 *tws, Geom g) {
+    switch (log_m) {
+#define GCK_NTT_CASE(L)                                                                                        \
+    case L:                                                                                                    \
+        hipLaunchKernelGGL((ntt_pass<INV, ROWS, L>), grid, block, 0, st, buf, src, src_div, m, mods, tw, tws, g); \
+        break;
+        GCK_NTT_CASE(5)
+        GCK_NTT_CASE(6)
+        GCK_NTT_CASE(7)
+        GCK_NTT_CASE(8)
+        GCK_NTT_CASE(9)
+#undef GCK_NTT_CASE
+    default:
+        throw Error(CKKS_E_INVALID_ARG, "unsupported NTT sub-transform size");
+    }
+}
+
+}  // namespace
+
+static void launch(const DevTables &t, u64 *buf, const u64 *src, int src_div, int n_limbs, ModMap m, bool inv,
+                   hipStream_t st) {
+    if (n_limbs <= 0) return;
+    if (t.log_n < 10 || t.log_n > 17) throw Error(CKKS_E_INVALID_ARG, "NTT needs 2^10 <= N <= 2^17");
+    Geom g = make_geom(t.log_n);
+    const int log_tile = t.log_n < 12 ? t.log_n : 12;
+    dim3 grid((unsigned)((size_t)n_limbs * g.tiles));
+    dim3 block((unsigned)((1 << log_tile) / kPer));
+    const double bytes = 16.0 * (double)n_limbs * t.n;
+    if (!inv) {
+        {
+            TScope ts_(t, src ? "ntt_fwd_cols_modup" : "ntt_fwd_cols", bytes, st);
+            launch_pass<false, false>(g.log_n1, grid, block, st, buf, src, src_div, m, t.mods, t.psi, t.psi_sh, g);
+        }
+        {
+            TScope ts_(t, "ntt_fwd_rows", bytes, st);
+            launch_pass<false, true>(g.log_n2, grid, block, st, buf, nullptr, 1, m, t.mods, t.psi, t.psi_sh, g);
+        }
+    } else {
+        {
+            TScope ts_(t, "ntt_inv_rows", bytes, st);
+            launch_pass<true, true>(g.log_n2, grid, block, st, buf, nullptr, 1, m, t.mods, t.ipsi, t.ipsi_sh, g);
+        }
+        {
+            TScope ts_(t, "ntt_inv_cols", bytes, st);
+            launch_pass<true, false>(g.log_n1, grid, block, st, buf, nullptr, 1, m, t.mods, t.ipsi, t.ipsi_sh, g);
+        }
+    }
+    check_launch();
+}
+
+void k_ntt_forward(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStream_t st) {
+    launch(t, buf, nullptr, 1, n_limbs, m, false, st);
+}
+
+void k_ntt_inverse(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStream_t st) {
+    launch(t, buf, nullptr, 1, n_limbs, m, true, st);
+}
+
+void k_ntt_forward_from(const DevTables &t, u64 *buf, const u64 *src, int src_div, int n_limbs, ModMap m,
+                        hipStream_t st) {
+    launch(t, buf, src, src_div, n_limbs, m, false, st);
+}
+
+}  // namespace gck
