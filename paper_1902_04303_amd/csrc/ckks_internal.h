@@ -151,10 +151,24 @@ struct ChainConst {     // one constant per chain index (value and Shoup compani
 
 void k_ntt_forward(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStream_t st);
 void k_ntt_inverse(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStream_t st);
-// forward NTT whose input limb lam is src limb lam / src_div reduced modulo limb lam's modulus
-// (ModUp: digits in coefficient form -> every target modulus, NTT form)
-void k_ntt_forward_from(const DevTables &t, u64 *buf, const u64 *src, int src_div, int n_limbs, ModMap m,
-                        hipStream_t st);
+// Where the first pass of an out-of-place NTT reads output limb lam from:
+//   src limb  (lam / div) * mul + add + (lam % div) * inner
+// and how the word is brought to output limb lam's modulus: kPlain (already reduced),
+// kReduce (any word < 2^64, e.g. a digit of another modulus: ModUp), kCentred (centred lift of a
+// residue modulo chain src_chain: rescale and ModDown).
+struct Gather {
+    const u64 *ptr;
+    int div, mul, add, inner;
+    int mode, src_chain;
+};
+enum { kPlain = 0, kReduce = 1, kCentred = 2 };
+inline Gather gather_plain(const u64 *p) { return Gather{p, 1, 1, 0, 0, kPlain, 0}; }
+void k_ntt_forward_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st);
+void k_ntt_inverse_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st);
+// out = (a - b) * c[chain] (+ x): a and x are gathered (x may be null; x_even_rows: add x only on
+// rows lam / rowlen that are even, i.e. to the first polynomial of each ciphertext)
+void k_sub_mul_add(const DevTables &t, u64 *out, const Gather &a, const u64 *b, const ChainConst &c, const Gather &x,
+                   bool x_even_rows, int rowlen, int n_limbs, ModMap m, hipStream_t st);
 // out = a op b over n_limbs limbs; a is read at limb (lam % na_limbs), b at (lam % nb_limbs)
 void k_add(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
            hipStream_t st);

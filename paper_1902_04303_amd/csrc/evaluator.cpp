@@ -201,21 +201,21 @@ Ct add_const(ckks_ctx &c, const ckks_ct &a, double v) {
 }
 
 // Rescale: round(c / q_last) on the centred integer, per limb (c_i - [c_last]_centred) * q_last^-1 mod q_i.
+// The last limb of every polynomial is gathered by the inverse NTT, centred-lifted to the other limbs
+// while loading the forward NTT, and the difference is scaled in one element-wise pass.
 Ct rescale(ckks_ctx &c, const ckks_ct &a) {
-    const int l = a.limbs, n = c.p.n, rows = a.count * 2;
+    const int l = a.limbs, rows = a.count * 2;
     if (l < 2) throw Error(CKKS_E_LEVEL, "no limb left to rescale");
-    const size_t N = (size_t)n;
+    const size_t N = (size_t)c.p.n;
     DBuf last(c.pool.get(), (size_t)rows * N);
-    k_copy_rows(last.ptr, N, a.data.ptr + (size_t)(l - 1) * N, (size_t)l * N, rows, N, c.stream);
-    ntt_inv(c, last.ptr, rows, ModMap{1, 0, l - 1});
+    k_ntt_inverse_g(c.tab, last.ptr, Gather{a.data.ptr, 1, l, l - 1, 0, kPlain, 0}, rows, ModMap{1, 0, l - 1}, c.stream);
     DBuf t(c.pool.get(), (size_t)rows * (l - 1) * N);
-    k_extend(c.tab, t.ptr, last.ptr, rows, l - 1, map_q(l - 1), l - 1, true, c.stream);
-    ntt_fwd(c, t.ptr, rows * (l - 1), map_q(l - 1));
-    DBuf head(c.pool.get(), (size_t)rows * (l - 1) * N);
-    k_copy_rows(head.ptr, (size_t)(l - 1) * N, a.data.ptr, (size_t)l * N, rows, (size_t)(l - 1) * N, c.stream);
+    k_ntt_forward_g(c.tab, t.ptr, Gather{last.ptr, l - 1, 1, 0, 0, kCentred, l - 1}, rows * (l - 1), map_q(l - 1),
+                    c.stream);
     Ct r = new_ct(c, a.count, a.depth + 1, a.scale);
-    k_sub_mul_const(c.tab, r->data.ptr, head.ptr, t.ptr, rows * (l - 1), map_q(l - 1), chain_inv_of(c, c.p.q[l - 1]),
-                    false, c.stream);
+    k_sub_mul_add(c.tab, r->data.ptr, Gather{a.data.ptr, l - 1, l, 0, 1, kPlain, 0}, t.ptr, chain_inv_of(c, c.p.q[l - 1]),
+                  Gather{nullptr, 1, 1, 0, 0, kPlain, 0}, false, l - 1, rows * (l - 1), map_q(l - 1), c.stream);
+    c.n_limb_ntt += (uint64_t)rows * l;
     c.n_launch += 5;
     return r;
 }
@@ -277,21 +277,20 @@ Ct set_scale(ckks_ctx &, Ct a, double factor) {
 
 bool has_key(const ckks_ctx &c, u64 id) { return c.ksk.count(id) != 0; }
 
-// Key switch of d = [count][l][N] (NTT form) with key `id`: round(sum_j [d]_{q_j} ksk_j / P).
-// Output [count][2][l][N] in NTT form.
-static DBuf keyswitch(ckks_ctx &c, const u64 *d, int count, int l, u64 id) {
+// Key switch of the digits gathered by `d` (count ciphertexts, l limbs, NTT form) with key `id`:
+// round(sum_j [d]_{q_j} ksk_j / P), plus the gathered `add` term (on every row, or on the first
+// polynomial of each ciphertext when add_even).  Output [count][2][l][N] in NTT form.
+static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, u64 id, const Gather &add, bool add_even) {
     auto it = c.ksk.find(id);
     if (it == c.ksk.end()) throw Error(CKKS_E_KEY_MISSING, "missing switching key " + std::to_string(id));
     const size_t N = (size_t)c.p.n;
     const int P = c.p.p_index();
-    // ModUp: coefficient form of every digit, reduced modulo every target, back to NTT form
+    // ModUp: coefficient form of every digit, reduced modulo every target while loading the forward NTT
     DBuf dc(c.pool.get(), (size_t)count * l * N);
-    GCK_HIP(hipMemcpyAsync(dc.ptr, d, (size_t)count * l * N * 8, hipMemcpyDeviceToDevice, c.stream));
-    ntt_inv(c, dc.ptr, count * l, map_q(l));
+    k_ntt_inverse_g(c.tab, dc.ptr, d, count * l, map_q(l), c.stream);
     DBuf dig(c.pool.get(), (size_t)count * l * (l + 1) * N);
-    k_ntt_forward_from(c.tab, dig.ptr, dc.ptr, l + 1, count * l * (l + 1), ModMap{l + 1, l, P}, c.stream);
-    c.n_limb_ntt += (uint64_t)count * l * (l + 1);
-    c.n_launch += 2;
+    k_ntt_forward_g(c.tab, dig.ptr, Gather{dc.ptr, l + 1, 1, 0, 0, kReduce, 0}, count * l * (l + 1), ModMap{l + 1, l, P},
+                    c.stream);
     dc.release();
     // inner product with the key
     DBuf acc(c.pool.get(), (size_t)count * 2 * (l + 1) * N);
@@ -300,16 +299,14 @@ static DBuf keyswitch(ckks_ctx &c, const u64 *d, int count, int l, u64 id) {
     // ModDown: round(x / P) = (x - [x]_P centred) * P^-1
     const int rows = count * 2;
     DBuf ap(c.pool.get(), (size_t)rows * N);
-    k_copy_rows(ap.ptr, N, acc.ptr + (size_t)l * N, (size_t)(l + 1) * N, rows, N, c.stream);
-    ntt_inv(c, ap.ptr, rows, ModMap{1, 0, P});
+    k_ntt_inverse_g(c.tab, ap.ptr, Gather{acc.ptr, 1, l + 1, l, 0, kPlain, 0}, rows, ModMap{1, 0, P}, c.stream);
     DBuf t(c.pool.get(), (size_t)rows * l * N);
-    k_extend(c.tab, t.ptr, ap.ptr, rows, l, map_q(l), P, true, c.stream);
-    ntt_fwd(c, t.ptr, rows * l, map_q(l));
-    DBuf head(c.pool.get(), (size_t)rows * l * N);
-    k_copy_rows(head.ptr, (size_t)l * N, acc.ptr, (size_t)(l + 1) * N, rows, (size_t)l * N, c.stream);
+    k_ntt_forward_g(c.tab, t.ptr, Gather{ap.ptr, l, 1, 0, 0, kCentred, P}, rows * l, map_q(l), c.stream);
     DBuf out(c.pool.get(), (size_t)rows * l * N);
-    k_sub_mul_const(c.tab, out.ptr, head.ptr, t.ptr, rows * l, map_q(l), chain_inv_of(c, c.p.P), false, c.stream);
-    c.n_launch += 7;
+    k_sub_mul_add(c.tab, out.ptr, Gather{acc.ptr, l, l + 1, 0, 1, kPlain, 0}, t.ptr, chain_inv_of(c, c.p.P), add,
+                  add_even, l, rows * l, map_q(l), c.stream);
+    c.n_limb_ntt += (uint64_t)count * l * (l + 2) + (uint64_t)rows * (l + 1);
+    c.n_launch += 10;
     ++c.n_keyswitch;
     return out;
 }
@@ -338,14 +335,8 @@ Ct mul_sum(ckks_ctx &c, const std::vector<std::pair<const ckks_ct *, const ckks_
         ++c.n_launch;
     }
     // relinearise: (d0, d1) + KS(d2, s^2 key)
-    DBuf d2(c.pool.get(), (size_t)count * l * N);
-    k_copy_rows(d2.ptr, (size_t)l * N, d.ptr + (size_t)2 * l * N, (size_t)3 * l * N, count, (size_t)l * N, c.stream);
-    DBuf ks = keyswitch(c, d2.ptr, count, l, 0);
-    d2.release();
-    k_add_rows(c.tab, ks.ptr, (size_t)2 * l * N, d.ptr, (size_t)3 * l * N, count, l, c.stream);
-    k_add_rows(c.tab, ks.ptr + (size_t)l * N, (size_t)2 * l * N, d.ptr + (size_t)l * N, (size_t)3 * l * N, count, l,
-               c.stream);
-    c.n_launch += 3;
+    DBuf ks = keyswitch(c, Gather{d.ptr, l, 3 * l, 2 * l, 1, kPlain, 0}, count, l, 0,
+                        Gather{d.ptr, 2 * l, 3 * l, 0, 1, kPlain, 0}, false);
     d.release();
     ckks_ct tmp;
     tmp.ctx = &c;
@@ -377,11 +368,8 @@ Ct apply_galois(ckks_ctx &c, const ckks_ct &a, u64 g) {
     const size_t N = (size_t)c.p.n;
     DBuf t(c.pool.get(), (size_t)a.count * 2 * l * N);
     k_automorph(c.tab, t.ptr, a.data.ptr, a.count * 2 * l, g, c.stream);
-    DBuf c1(c.pool.get(), (size_t)a.count * l * N);
-    k_copy_rows(c1.ptr, (size_t)l * N, t.ptr + (size_t)l * N, (size_t)2 * l * N, a.count, (size_t)l * N, c.stream);
-    DBuf ks = keyswitch(c, c1.ptr, a.count, l, g);
-    k_add_rows(c.tab, ks.ptr, (size_t)2 * l * N, t.ptr, (size_t)2 * l * N, a.count, l, c.stream);
-    c.n_launch += 3;
+    DBuf ks = keyswitch(c, Gather{t.ptr, l, 2 * l, l, 1, kPlain, 0}, a.count, l, g, gather_plain(t.ptr), true);
+    c.n_launch += 1;
     Ct r(new ckks_ct());
     r->ctx = &c;
     r->count = a.count;

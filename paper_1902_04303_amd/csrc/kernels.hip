@@ -323,50 +323,98 @@ void k_add_rows(const DevTables &t, u64 *out, size_t out_stride, const u64 *in, 
     check_launch();
 }
 
+__device__ __forceinline__ size_t gather_limb(const Gather &g, int lam) {
+    return (size_t)((lam / g.div) * g.mul + g.add + (lam % g.div) * g.inner);
+}
+
+__global__ void ew_sub_mul_add(u64 *out, Gather a, const u64 *b, ChainConst c, Gather x, int x_even_rows, int rowlen,
+                               size_t total, int log_n, ModMap mm, const ModInfo *mods) {
+    const size_t n = (size_t)1 << log_n;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        const int lam = (int)(idx >> log_n);
+        const size_t k = idx & (n - 1);
+        const int ch = chain_of(lam, mm);
+        const u64 q = mods[ch].q;
+        u64 r = mul_shoup(sub_mod(a.ptr[gather_limb(a, lam) * n + k], b[idx], q), c.v[ch], c.sh[ch], q);
+        if (x.ptr && (!x_even_rows || ((lam / rowlen) & 1) == 0)) r = add_mod(r, x.ptr[gather_limb(x, lam) * n + k], q);
+        out[idx] = r;
+    }
+}
+void k_sub_mul_add(const DevTables &t, u64 *out, const Gather &a, const u64 *b, const ChainConst &c, const Gather &x,
+                   bool x_even_rows, int rowlen, int n_limbs, ModMap m, hipStream_t st) {
+    TScope ts_(t, "sub_mul_add", (x.ptr ? 32.0 : 24.0) * (double)n_limbs * t.n, st);
+    size_t total = (size_t)n_limbs << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(ew_sub_mul_add, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, c, x, x_even_rows ? 1 : 0,
+                       rowlen, total, t.log_n, m, t.mods);
+    check_launch();
+}
+
 // ---------------------------------------------------------------- key-switch inner product
 //
 // acc[c][comp][t][k] = sum_j digit[c][j][t][k] * key[comp][j][kt][k] mod q_t.  The key words carry a
-// factor 2^64 (Montgomery form), so the lazily accumulated 128-bit sum needs one REDC at the end.
-// The high word is kept <= q by subtracting q (i.e. q 2^64 = 0 mod q) after each addition.
+// factor 2^64 (Montgomery form), so the lazily accumulated 128-bit sum needs one REDC at the end; the
+// high word is kept <= q by subtracting q (q 2^64 = 0 mod q) after each addition.  Each thread serves CB
+// ciphertexts of the batch, so every key word it loads is used CB times.
+template <int CB>
 __global__ void ks_inner(u64 *acc, const u64 *digits, const u64 *key, size_t total, int log_n, int l, int levels,
-                         const ModInfo *mods) {
+                         int count, const ModInfo *mods) {
     const size_t n = (size_t)1 << log_n;
     const int nt_key = levels + 2;
     const size_t key_comp = (size_t)(levels + 1) * nt_key * n;
+    const size_t dig_ct = (size_t)l * (l + 1) * n;
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
-        size_t lam = idx >> log_n;       // over count * (l + 1)
-        int tt = (int)(lam % (l + 1));
-        size_t c = lam / (l + 1);
-        size_t k = idx & (n - 1);
-        int chain = tt < l ? tt : levels + 1;
-        int kt = chain;
+        const size_t lam = idx >> log_n;       // over groups * (l + 1)
+        const int tt = (int)(lam % (l + 1));
+        const int c0 = (int)(lam / (l + 1)) * CB;
+        const size_t k = idx & (n - 1);
+        const int chain = tt < l ? tt : levels + 1;
         const ModInfo M = mods[chain];
-        u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
-        const u64 *dg = digits + (c * l * (l + 1) + tt) * n + k;
+        u64 h0[CB], l0[CB], h1[CB], l1[CB];
+#pragma unroll
+        for (int b = 0; b < CB; ++b) h0[b] = l0[b] = h1[b] = l1[b] = 0;
+        const u64 *dg = digits + (size_t)c0 * dig_ct + (size_t)tt * n + k;
         for (int j = 0; j < l; ++j) {
-            u64 d = dg[(size_t)j * (l + 1) * n];
-            u64 k0 = key[((size_t)j * nt_key + kt) * n + k];
-            u64 k1 = key[key_comp + ((size_t)j * nt_key + kt) * n + k];
-            u64 p0 = d * k0, q0 = __umul64hi(d, k0);
-            u64 p1 = d * k1, q1 = __umul64hi(d, k1);
-            l0 += p0; h0 += q0 + (l0 < p0 ? 1 : 0);
-            l1 += p1; h1 += q1 + (l1 < p1 ? 1 : 0);
-            if (h0 >= M.q) h0 -= M.q;
-            if (h1 >= M.q) h1 -= M.q;
+            const u64 k0 = key[((size_t)j * nt_key + chain) * n + k];
+            const u64 k1 = key[key_comp + ((size_t)j * nt_key + chain) * n + k];
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                if (c0 + b >= count) break;
+                const u64 d = dg[(size_t)b * dig_ct + (size_t)j * (l + 1) * n];
+                const u64 p0 = d * k0, q0 = __umul64hi(d, k0);
+                const u64 p1 = d * k1, q1 = __umul64hi(d, k1);
+                l0[b] += p0;
+                h0[b] += q0 + (l0[b] < p0 ? 1 : 0);
+                l1[b] += p1;
+                h1[b] += q1 + (l1[b] < p1 ? 1 : 0);
+                if (h0[b] >= M.q) h0[b] -= M.q;
+                if (h1[b] >= M.q) h1[b] -= M.q;
+            }
         }
-        if (h0 >= M.q) h0 -= M.q;
-        if (h1 >= M.q) h1 -= M.q;
-        u64 *o = acc + (c * 2 * (l + 1) + tt) * n + k;
-        o[0] = redc(h0, l0, M);
-        o[(size_t)(l + 1) * n] = redc(h1, l1, M);
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            if (c0 + b >= count) break;
+            if (h0[b] >= M.q) h0[b] -= M.q;
+            if (h1[b] >= M.q) h1[b] -= M.q;
+            u64 *o = acc + ((size_t)(c0 + b) * 2 * (l + 1) + tt) * n + k;
+            o[0] = redc(h0[b], l0[b], M);
+            o[(size_t)(l + 1) * n] = redc(h1[b], l1[b], M);
+        }
     }
 }
 void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, const u64 *key, int count, int l, int levels,
                 hipStream_t st) {
     TScope ts_(t, "ks_inner", 8.0 * (double)t.n * (2.0 * l * (l + 1) + (double)count * (l * (l + 1) + 2 * (l + 1))), st);
-    size_t total = ((size_t)count * (l + 1)) << t.log_n;
+    const int cb = count >= 8 ? 8 : (count >= 4 ? 4 : (count >= 2 ? 2 : 1));
+    const int groups = (count + cb - 1) / cb;
+    size_t total = ((size_t)groups * (l + 1)) << t.log_n;
     if (!total) return;
-    hipLaunchKernelGGL(ks_inner, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, key, total, t.log_n, l, levels, t.mods);
+    switch (cb) {
+    case 8: hipLaunchKernelGGL(ks_inner<8>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, key, total, t.log_n, l, levels, count, t.mods); break;
+    case 4: hipLaunchKernelGGL(ks_inner<4>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, key, total, t.log_n, l, levels, count, t.mods); break;
+    case 2: hipLaunchKernelGGL(ks_inner<2>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, key, total, t.log_n, l, levels, count, t.mods); break;
+    default: hipLaunchKernelGGL(ks_inner<1>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, key, total, t.log_n, l, levels, count, t.mods); break;
+    }
     check_launch();
 }
 

@@ -131,10 +131,9 @@ __device__ __forceinline__ void exchange(u64 (&v)[kPer], u64 *sh, int gi, int q,
 // (N1-point sub-transforms down columns).  src != nullptr (forward cols pass only): the input of
 // output limb lam is limb lam / src_div of src, reduced modulo the output limb's modulus (ModUp).
 template <bool INV, bool ROWS, int LOGM>
-__global__ void __launch_bounds__(kThreads) ntt_pass(u64 *__restrict__ buf, const u64 *__restrict__ src, int src_div,
-                                                     ModMap mm, const ModInfo *__restrict__ mods,
-                                                     const u64 *__restrict__ tw, const u64 *__restrict__ tw_sh,
-                                                     Geom g) {
+__global__ void __launch_bounds__(kThreads) ntt_pass(u64 *__restrict__ buf, Gather in, ModMap mm,
+                                                     const ModInfo *__restrict__ mods, const u64 *__restrict__ tw,
+                                                     const u64 *__restrict__ tw_sh, Geom g) {
     __shared__ u64 sh[kTileWords + (kTileWords >> 4)];
     constexpr int NPH = (LOGM + 3) / 4;
     constexpr int FIRST = INV ? NPH - 1 : 0;
@@ -159,8 +158,19 @@ __global__ void __launch_bounds__(kThreads) ntt_pass(u64 *__restrict__ buf, cons
         q = tid >> log_g;
     }
     u64 *a = buf + (size_t)limb * n;
-    const bool modup = (src != nullptr);
-    const u64 *ain = modup ? src + (size_t)(limb / src_div) * n : a;
+    const u64 *ain = a;
+    int mode = kPlain;
+    u64 src_q = 0, src_half = 0, src_q_red = 0;
+    if (in.ptr) {
+        const int sl = (limb / in.div) * in.mul + in.add + (limb % in.div) * in.inner;
+        ain = in.ptr + (size_t)sl * n;
+        mode = in.mode;
+        if (mode == kCentred) {
+            src_q = mods[in.src_chain].q;
+            src_half = src_q >> 1;
+            src_q_red = reduce64(src_q, M);
+        }
+    }
     size_t base;
     int stride, base_off;
     if (ROWS) {
@@ -178,7 +188,11 @@ __global__ void __launch_bounds__(kThreads) ntt_pass(u64 *__restrict__ buf, cons
     for (int e = 0; e < kPer; ++e) {
         const int idx = slot_index<LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(e, q);
         u64 x = ain[base + (size_t)idx * stride];
-        if (modup) x = reduce64(x, M);
+        if (mode != kPlain) {
+            const bool neg = (mode == kCentred) && x > src_half;
+            x = reduce64(x, M);
+            if (neg) x = x >= src_q_red ? x - src_q_red : x + qm - src_q_red;   // x - src_q is negative
+        }
         v[e] = x;
     }
     phase<INV, LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(v, q, base_off, W, Ws, qm);
@@ -225,12 +239,12 @@ __global__ void __launch_bounds__(kThreads) ntt_pass(u64 *__restrict__ buf, cons
 }
 
 template <bool INV, bool ROWS>
-void launch_pass(int log_m, dim3 grid, dim3 block, hipStream_t st, u64 *buf, const u64 *src, int src_div, ModMap m,
+void launch_pass(int log_m, dim3 grid, dim3 block, hipStream_t st, u64 *buf, const Gather &in, ModMap m,
                  const ModInfo *mods, const u64 *tw, const u64 *tws, Geom g) {
     switch (log_m) {
-#define GCK_NTT_CASE(L)                                                                                        \
-    case L:                                                                                                    \
-        hipLaunchKernelGGL((ntt_pass<INV, ROWS, L>), grid, block, 0, st, buf, src, src_div, m, mods, tw, tws, g); \
+#define GCK_NTT_CASE(L)                                                                             \
+    case L:                                                                                         \
+        hipLaunchKernelGGL((ntt_pass<INV, ROWS, L>), grid, block, 0, st, buf, in, m, mods, tw, tws, g); \
         break;
         GCK_NTT_CASE(5)
         GCK_NTT_CASE(6)
@@ -245,8 +259,7 @@ void launch_pass(int log_m, dim3 grid, dim3 block, hipStream_t st, u64 *buf, con
 
 }  // namespace
 
-static void launch(const DevTables &t, u64 *buf, const u64 *src, int src_div, int n_limbs, ModMap m, bool inv,
-                   hipStream_t st) {
+static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, bool inv, hipStream_t st) {
     if (n_limbs <= 0) return;
     if (t.log_n < 10 || t.log_n > 17) throw Error(CKKS_E_INVALID_ARG, "NTT needs 2^10 <= N <= 2^17");
     Geom g = make_geom(t.log_n);
@@ -254,39 +267,43 @@ static void launch(const DevTables &t, u64 *buf, const u64 *src, int src_div, in
     dim3 grid((unsigned)((size_t)n_limbs * g.tiles));
     dim3 block((unsigned)((1 << log_tile) / kPer));
     const double bytes = 16.0 * (double)n_limbs * t.n;
+    const Gather none{nullptr, 1, 1, 0, 0, kPlain, 0};
     if (!inv) {
         {
-            TScope ts_(t, src ? "ntt_fwd_cols_modup" : "ntt_fwd_cols", bytes, st);
-            launch_pass<false, false>(g.log_n1, grid, block, st, buf, src, src_div, m, t.mods, t.psi, t.psi_sh, g);
+            TScope ts_(t, in.ptr ? (in.mode == kPlain ? "ntt_fwd_cols" : "ntt_fwd_cols_lift") : "ntt_fwd_cols", bytes, st);
+            launch_pass<false, false>(g.log_n1, grid, block, st, buf, in, m, t.mods, t.psi, t.psi_sh, g);
         }
         {
             TScope ts_(t, "ntt_fwd_rows", bytes, st);
-            launch_pass<false, true>(g.log_n2, grid, block, st, buf, nullptr, 1, m, t.mods, t.psi, t.psi_sh, g);
+            launch_pass<false, true>(g.log_n2, grid, block, st, buf, none, m, t.mods, t.psi, t.psi_sh, g);
         }
     } else {
         {
             TScope ts_(t, "ntt_inv_rows", bytes, st);
-            launch_pass<true, true>(g.log_n2, grid, block, st, buf, nullptr, 1, m, t.mods, t.ipsi, t.ipsi_sh, g);
+            launch_pass<true, true>(g.log_n2, grid, block, st, buf, in, m, t.mods, t.ipsi, t.ipsi_sh, g);
         }
         {
             TScope ts_(t, "ntt_inv_cols", bytes, st);
-            launch_pass<true, false>(g.log_n1, grid, block, st, buf, nullptr, 1, m, t.mods, t.ipsi, t.ipsi_sh, g);
+            launch_pass<true, false>(g.log_n1, grid, block, st, buf, none, m, t.mods, t.ipsi, t.ipsi_sh, g);
         }
     }
     check_launch();
 }
 
 void k_ntt_forward(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStream_t st) {
-    launch(t, buf, nullptr, 1, n_limbs, m, false, st);
+    launch(t, buf, Gather{nullptr, 1, 1, 0, 0, kPlain, 0}, n_limbs, m, false, st);
 }
 
 void k_ntt_inverse(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStream_t st) {
-    launch(t, buf, nullptr, 1, n_limbs, m, true, st);
+    launch(t, buf, Gather{nullptr, 1, 1, 0, 0, kPlain, 0}, n_limbs, m, true, st);
 }
 
-void k_ntt_forward_from(const DevTables &t, u64 *buf, const u64 *src, int src_div, int n_limbs, ModMap m,
-                        hipStream_t st) {
-    launch(t, buf, src, src_div, n_limbs, m, false, st);
+void k_ntt_forward_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st) {
+    launch(t, buf, in, n_limbs, m, false, st);
+}
+
+void k_ntt_inverse_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st) {
+    launch(t, buf, in, n_limbs, m, true, st);
 }
 
 }  // namespace gck
