@@ -226,6 +226,43 @@ int gwas_finalize(ckks_ctx *ctx, const gwas_enc_output *out, int m, double *b, d
 int ckks_ctx_kernel_timing(ckks_ctx *ctx, int enable);
 int ckks_ctx_kernel_report(ckks_ctx *ctx, char *buf, size_t cap);
 
+/* ---------------------------------------------------------------- batched and serving forms
+ * (additions of this library around the paper's algorithm; the arithmetic of each job is unchanged) */
+
+/* Several jobs in one call.  Jobs with the same block size R, covariate count k and kappa share every
+ * launch of the fixed part (one batch ciphertext per job) and their SNP batches run through the
+ * per-batch part together, `chunk` ciphertexts per launch, each with its own job's values.  out[i]
+ * receives job i's output (one batch per output kind, index 0).  Results are bit-identical to running
+ * each job alone. */
+int gwas_semiparallel_multi(ckks_ctx *ctx, const gwas_enc_input *const *in, int n_jobs, int chunk,
+                            gwas_enc_output **out);
+/* Device bytes a job needs while in flight (inputs, outputs and working values). */
+int gwas_input_footprint(const gwas_enc_input *in, size_t *bytes);
+/* Move a job's SNP batches to pinned host memory; they are then copied back chunk by chunk, the next
+ * chunk's copy overlapping the current chunk's compute (the stand-in for the paper's cache module,
+ * Methods: "Smart Cache Module"). */
+int gwas_input_spill(ckks_ctx *ctx, gwas_enc_input *in);
+
+/* Serving: a worker thread owns the context's device work.  Submitted jobs are admitted in arrival
+ * order while the sum of their footprints fits hbm_budget_bytes (0: no cap) and at most
+ * max_jobs_in_flight are active; a job larger than the whole budget has its SNP batches spilled to the
+ * host.  Each iteration runs the fixed parts of newly admitted jobs together, then one chunk of SNP
+ * batches drawn from all active jobs of one shape (continuous batching).  Calls on the same context
+ * from other threads are serialised with the worker. */
+int gwas_server_create(ckks_ctx *ctx, size_t hbm_budget_bytes, int max_jobs_in_flight, int chunk,
+                       gwas_server **out);
+/* Ownership of `in` passes to the server. */
+int gwas_server_submit(gwas_server *s, gwas_enc_input *in, uint64_t *job_id);
+/* CKKS_OK with *out set (ownership passes to the caller) when the job is done; CKKS_E_NOT_READY when
+ * it is not (wait = 0) ; wait = 1 blocks until it is done; CKKS_E_CANCELLED for a cancelled job. */
+int gwas_server_poll(gwas_server *s, uint64_t job_id, int wait, gwas_enc_output **out);
+int gwas_server_cancel(gwas_server *s, uint64_t job_id);
+/* Latency percentiles (completion - submission) over completed jobs, completed jobs per second
+ * (first submission to last completion), and the largest number of jobs in flight together. */
+int gwas_server_stats(gwas_server *s, double *p50_ms, double *p99_ms, double *jobs_per_s, uint64_t *completed,
+                      int *peak_jobs_in_flight);
+void gwas_server_destroy(gwas_server *s);
+
 /* Number of key switches and NTT limb transforms issued by the context so far. */
 int ckks_ctx_counters(const ckks_ctx *ctx, uint64_t *keyswitches, uint64_t *limb_ntts, uint64_t *launches);
 

@@ -10,6 +10,7 @@ from ._binding import (  # noqa: F401
     Context,
     GwasInput,
     GwasOutput,
+    GwasServer,
     LIB_PATH,
     chain,
     exported_symbols,

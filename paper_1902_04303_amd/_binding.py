@@ -117,6 +117,17 @@ _SIGS = [
     ("gwas_output_batches", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
     ("gwas_output_free", None, [_vp]),
     ("gwas_finalize", ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]),
+    ("gwas_semiparallel_multi", ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int,
+                                               ctypes.POINTER(_vp)]),
+    ("gwas_input_footprint", ctypes.c_int, [_vp, _szp]),
+    ("gwas_input_spill", ctypes.c_int, [_vp, _vp]),
+    ("gwas_server_create", ctypes.c_int, [_vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]),
+    ("gwas_server_submit", ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_uint64)]),
+    ("gwas_server_poll", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(_vp)]),
+    ("gwas_server_cancel", ctypes.c_int, [_vp, ctypes.c_uint64]),
+    ("gwas_server_stats", ctypes.c_int, [_vp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_uint64),
+                                         ctypes.POINTER(ctypes.c_int)]),
+    ("gwas_server_destroy", None, [_vp]),
 ]
 
 
@@ -436,6 +447,15 @@ class Context:
             _check(lib().gwas_semiparallel_chunked(self.h, inp.h, chunk, ctypes.byref(out)))
         return GwasOutput(self, out.value, inp.m)
 
+    def gwas_semiparallel_multi(self, inputs: Sequence["GwasInput"], chunk: int = 64) -> List["GwasOutput"]:
+        arr = (_vp * len(inputs))(*[i.h for i in inputs])
+        outs = (_vp * len(inputs))()
+        _check(lib().gwas_semiparallel_multi(self.h, arr, len(inputs), chunk, outs))
+        return [GwasOutput(self, outs[i], inputs[i].m) for i in range(len(inputs))]
+
+    def gwas_server(self, hbm_budget: int = 0, max_jobs: int = 64, chunk: int = 64) -> "GwasServer":
+        return GwasServer(self, hbm_budget, max_jobs, chunk)
+
     def gwas_finalize(self, out: "GwasOutput"):
         m = out.m
         b, err, se, num, den = (np.zeros(m) for _ in range(5))
@@ -452,6 +472,60 @@ class GwasInput:
         if self.h and self.ctx is not None and self.ctx.h:
             lib().gwas_input_free(self.h)
             self.h = None
+
+    def footprint(self) -> int:
+        v = ctypes.c_size_t()
+        _check(lib().gwas_input_footprint(self.h, ctypes.byref(v)))
+        return v.value
+
+    def spill(self):
+        _check(lib().gwas_input_spill(self.ctx.h, self.h))
+
+
+class GwasServer:
+    """Serving loop of the library (a native worker thread); submit() hands the input over."""
+
+    def __init__(self, ctx: Context, hbm_budget: int, max_jobs: int, chunk: int):
+        self.ctx = ctx
+        out = _vp()
+        _check(lib().gwas_server_create(ctx.h, hbm_budget, max_jobs, chunk, ctypes.byref(out)))
+        self.h = out
+
+    def submit(self, inp: GwasInput) -> int:
+        jid = ctypes.c_uint64()
+        _check(lib().gwas_server_submit(self.h, inp.h, ctypes.byref(jid)))
+        inp.h = None          # owned by the server now
+        return jid.value
+
+    def poll(self, job_id: int, m: int, wait: bool = False) -> Optional["GwasOutput"]:
+        out = _vp()
+        rc = lib().gwas_server_poll(self.h, job_id, 1 if wait else 0, ctypes.byref(out))
+        if rc == -8:
+            return None
+        _check(rc)
+        return GwasOutput(self.ctx, out.value, m)
+
+    def cancel(self, job_id: int):
+        _check(lib().gwas_server_cancel(self.h, job_id))
+
+    def stats(self):
+        p50, p99, tput = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        n, peak = ctypes.c_uint64(), ctypes.c_int()
+        _check(lib().gwas_server_stats(self.h, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(tput),
+                                       ctypes.byref(n), ctypes.byref(peak)))
+        return dict(p50_ms=p50.value, p99_ms=p99.value, jobs_per_s=tput.value, completed=n.value,
+                    peak_jobs_in_flight=peak.value)
+
+    def close(self):
+        if self.h:
+            lib().gwas_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class GwasOutput:

@@ -7,20 +7,17 @@
 
 using namespace gck;
 
-struct gwas_enc_input {
-    ckks_ctx *ctx;
-    std::unique_ptr<EncInput> in;
-};
-
-struct gwas_enc_output {
-    ckks_ctx *ctx;
-    EncOutput out;
-    Layout lay;
-};
-
 namespace {
 
 thread_local std::string g_err;
+
+}  // namespace
+
+namespace gck {
+void set_last_error(const std::string &s) { g_err = s; }
+}  // namespace gck
+
+namespace {
 
 template <typename F>
 int guard(F &&f) {
@@ -37,6 +34,17 @@ int guard(F &&f) {
         g_err = e.what();
         return CKKS_E_INVALID_ARG;
     }
+}
+
+// guard() for entry points that use a context: also holds the context's lock
+template <typename F>
+int guard_ctx(const ckks_ctx *ctx, F &&f) {
+    if (!ctx) {
+        g_err = "null context";
+        return CKKS_E_INVALID_ARG;
+    }
+    std::lock_guard<std::recursive_mutex> lk(const_cast<ckks_ctx *>(ctx)->mu);
+    return guard(std::forward<F>(f));
 }
 
 void need(bool cond, const char *msg) {
@@ -154,7 +162,7 @@ int ckks_ctx_create(const ckks_params *params, const ckks_allocator *allocator, 
 void ckks_ctx_destroy(ckks_ctx *ctx) { delete ctx; }
 
 int ckks_ctx_moduli(const ckks_ctx *ctx, uint64_t *moduli, int cap) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx && moduli && cap >= ctx->p.levels + 2, "bad buffer");
         for (int i = 0; i <= ctx->p.levels; ++i) moduli[i] = ctx->p.q[i];
         moduli[ctx->p.levels + 1] = ctx->p.P;
@@ -162,14 +170,14 @@ int ckks_ctx_moduli(const ckks_ctx *ctx, uint64_t *moduli, int cap) {
 }
 
 int ckks_ctx_scales(const ckks_ctx *ctx, double *scales, int cap) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx && scales && cap >= ctx->p.levels + 1, "bad buffer");
         for (int i = 0; i <= ctx->p.levels; ++i) scales[i] = ctx->p.scales[i];
     });
 }
 
 int ckks_ctx_pool_stats(const ckks_ctx *ctx, size_t *in_use, size_t *cached, size_t *peak, size_t *n_alloc) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx, "null context");
         if (in_use) *in_use = ctx->pool->in_use;
         if (cached) *cached = ctx->pool->cached;
@@ -179,14 +187,14 @@ int ckks_ctx_pool_stats(const ckks_ctx *ctx, size_t *in_use, size_t *cached, siz
 }
 
 int ckks_ctx_pool_trim(ckks_ctx *ctx) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx, "null context");
         ctx->pool->trim();
     });
 }
 
 int ckks_ctx_counters(const ckks_ctx *ctx, uint64_t *keyswitches, uint64_t *limb_ntts, uint64_t *launches) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx, "null context");
         if (keyswitches) *keyswitches = ctx->n_keyswitch;
         if (limb_ntts) *limb_ntts = ctx->n_limb_ntt;
@@ -195,7 +203,7 @@ int ckks_ctx_counters(const ckks_ctx *ctx, uint64_t *keyswitches, uint64_t *limb
 }
 
 int ckks_ctx_kernel_timing(ckks_ctx *ctx, int enable) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx, "null context");
         if (enable) ctx->timer.reset();
         else ctx->timer.collect();
@@ -204,7 +212,7 @@ int ckks_ctx_kernel_timing(ckks_ctx *ctx, int enable) {
 }
 
 int ckks_ctx_kernel_report(ckks_ctx *ctx, char *buf, size_t cap) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx && buf && cap > 0, "bad buffer");
         ctx->timer.collect();
         std::string s;
@@ -221,7 +229,7 @@ int ckks_ctx_kernel_report(ckks_ctx *ctx, char *buf, size_t cap) {
 }
 
 int ckks_keygen(ckks_ctx *ctx, uint64_t seed, const uint64_t *galois, int n_galois) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx && (n_galois == 0 || galois) && n_galois >= 0, "bad arguments");
         keygen(*ctx, seed, std::vector<u64>(galois, galois + n_galois));
     });
@@ -231,7 +239,7 @@ uint64_t ckks_galois_rotate(const ckks_ctx *ctx, int64_t r) { return ctx ? galoi
 uint64_t ckks_galois_conj(const ckks_ctx *ctx) { return ctx ? galois_conj(*ctx) : 0; }
 
 int ckks_export_switching_key(ckks_ctx *ctx, uint64_t key_id, uint64_t *buf, size_t cap_words) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx && buf, "null argument");
         auto it = ctx->ksk.find(key_id);
         if (it == ctx->ksk.end()) throw Error(CKKS_E_KEY_MISSING, "no such key");
@@ -249,7 +257,7 @@ int ckks_export_switching_key(ckks_ctx *ctx, uint64_t key_id, uint64_t *buf, siz
 }
 
 int ckks_export_secret(ckks_ctx *ctx, int64_t *buf, size_t cap) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx && buf && cap >= (size_t)ctx->p.n, "bad buffer");
         if (!ctx->have_keys) throw Error(CKKS_E_KEY_MISSING, "keygen has not been run");
         std::memcpy(buf, ctx->sk.data(), (size_t)ctx->p.n * 8);
@@ -257,7 +265,7 @@ int ckks_export_secret(ckks_ctx *ctx, int64_t *buf, size_t cap) {
 }
 
 int ckks_export_public_key(ckks_ctx *ctx, uint64_t *buf, size_t cap_words) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx && buf, "null argument");
         if (!ctx->have_keys) throw Error(CKKS_E_KEY_MISSING, "keygen has not been run");
         const int l = ctx->p.levels + 1;
@@ -272,21 +280,21 @@ int ckks_export_public_key(ckks_ctx *ctx, uint64_t *buf, size_t cap_words) {
 }
 
 int ckks_encode(ckks_ctx *ctx, const double *re, const double *im, size_t n, double scale, int64_t *coeffs_out) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx && coeffs_out && (re || n == 0), "null argument");
         encode_poly(ctx->p.n, re, im, n, scale, coeffs_out);
     });
 }
 
 int ckks_decode(ckks_ctx *ctx, const double *coeffs, double *re, double *im) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx && coeffs, "null argument");
         decode_poly(ctx->p.n, coeffs, re, im);
     });
 }
 
 int ckks_encrypt(ckks_ctx *ctx, const int64_t *m, int depth, double scale, uint64_t seed, ckks_ct **out) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx && m && out, "null argument");
         need(scale > 0, "scale must be positive");
         *out = release(encrypt(*ctx, m, depth, scale, seed));
@@ -294,7 +302,7 @@ int ckks_encrypt(ckks_ctx *ctx, const int64_t *m, int depth, double scale, uint6
 }
 
 int ckks_decrypt_poly(ckks_ctx *ctx, const ckks_ct *ct, int index, double *coeffs) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         check_ct(ctx, ct);
         need(coeffs && index >= 0 && index < ct->count, "bad arguments");
         auto v = decrypt_poly(*ctx, *ct, index);
@@ -303,7 +311,7 @@ int ckks_decrypt_poly(ckks_ctx *ctx, const ckks_ct *ct, int index, double *coeff
 }
 
 int ckks_decrypt(ckks_ctx *ctx, const ckks_ct *ct, int index, double *re, double *im) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         check_ct(ctx, ct);
         need(index >= 0 && index < ct->count, "bad index");
         auto v = decrypt_poly(*ctx, *ct, index);
@@ -324,7 +332,7 @@ int ckks_ct_info(const ckks_ct *ct, int *count, int *depth, int *limbs, double *
 }
 
 int ckks_ct_export(ckks_ctx *ctx, const ckks_ct *ct, int index, uint64_t *buf, size_t cap_words) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         check_ct(ctx, ct);
         need(buf && index >= 0 && index < ct->count, "bad arguments");
         need(cap_words >= (size_t)2 * ct->limbs * ctx->p.n, "buffer too small");
@@ -333,7 +341,7 @@ int ckks_ct_export(ckks_ctx *ctx, const ckks_ct *ct, int index, uint64_t *buf, s
 }
 
 int ckks_ct_import(ckks_ctx *ctx, const uint64_t *buf, int depth, double scale, ckks_ct **out) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx && buf && out, "null argument");
         *out = release(import_ct(*ctx, buf, depth, scale));
     });
@@ -343,7 +351,7 @@ void ckks_ct_free(ckks_ct *ct) { delete ct; }
 
 #define CT_UNARY(name, expr)                                   \
     int name(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out) { \
-        return guard([&] {                                     \
+        return guard_ctx(ctx, [&] {                                     \
             check_ct(ctx, a);                                  \
             need(out, "null output");                          \
             *out = release(expr);                              \
@@ -354,7 +362,7 @@ CT_UNARY(ckks_rescale, rescale(*ctx, *a))
 CT_UNARY(ckks_conjugate, conjugate(*ctx, *a))
 
 int ckks_add(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         check_ct(ctx, a);
         check_ct(ctx, b);
         need(out, "null output");
@@ -363,7 +371,7 @@ int ckks_add(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out) {
 }
 
 int ckks_sub(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         check_ct(ctx, a);
         check_ct(ctx, b);
         need(out, "null output");
@@ -372,7 +380,7 @@ int ckks_sub(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out) {
 }
 
 int ckks_mul(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         check_ct(ctx, a);
         check_ct(ctx, b);
         need(out, "null output");
@@ -381,7 +389,7 @@ int ckks_mul(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out) {
 }
 
 int ckks_mul_int(ckks_ctx *ctx, const ckks_ct *a, int64_t k, ckks_ct **out) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         check_ct(ctx, a);
         need(out, "null output");
         *out = release(mul_int(*ctx, *a, k));
@@ -389,7 +397,7 @@ int ckks_mul_int(ckks_ctx *ctx, const ckks_ct *a, int64_t k, ckks_ct **out) {
 }
 
 int ckks_add_const(ckks_ctx *ctx, const ckks_ct *a, double v, ckks_ct **out) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         check_ct(ctx, a);
         need(out, "null output");
         *out = release(add_const(*ctx, *a, v));
@@ -397,7 +405,7 @@ int ckks_add_const(ckks_ctx *ctx, const ckks_ct *a, double v, ckks_ct **out) {
 }
 
 int ckks_mul_const(ckks_ctx *ctx, const ckks_ct *a, double v, ckks_ct **out) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         check_ct(ctx, a);
         need(out, "null output");
         *out = release(mul_const(*ctx, *a, v));
@@ -405,7 +413,7 @@ int ckks_mul_const(ckks_ctx *ctx, const ckks_ct *a, double v, ckks_ct **out) {
 }
 
 int ckks_align(ckks_ctx *ctx, const ckks_ct *a, int depth, double scale, double factor, ckks_ct **out) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         check_ct(ctx, a);
         need(out, "null output");
         *out = release(align(*ctx, *a, depth, scale, factor));
@@ -413,7 +421,7 @@ int ckks_align(ckks_ctx *ctx, const ckks_ct *a, int depth, double scale, double 
 }
 
 int ckks_rotate(ckks_ctx *ctx, const ckks_ct *a, int64_t r, ckks_ct **out) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         check_ct(ctx, a);
         need(out, "null output");
         *out = release(rotate(*ctx, *a, r));
@@ -421,7 +429,7 @@ int ckks_rotate(ckks_ctx *ctx, const ckks_ct *a, int64_t r, ckks_ct **out) {
 }
 
 int ckks_mul_mask(ckks_ctx *ctx, const ckks_ct *a, int R, ckks_ct **out) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         check_ct(ctx, a);
         need(out, "null output");
         *out = release(mul_mask(*ctx, *a, R));
@@ -429,7 +437,7 @@ int ckks_mul_mask(ckks_ctx *ctx, const ckks_ct *a, int R, ckks_ct **out) {
 }
 
 int ckks_ntt_device(ckks_ctx *ctx, uint64_t *dev_limbs, int count, const int *moduli_index, int dir) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx && dev_limbs && moduli_index && count >= 0 && (dir == 1 || dir == -1), "bad arguments");
         for (int i = 0; i < count; ++i) {
             int mi = moduli_index[i];
@@ -443,7 +451,7 @@ int ckks_ntt_device(ckks_ctx *ctx, uint64_t *dev_limbs, int count, const int *mo
 
 int gwas_layout(const ckks_ctx *ctx, int n, int k, int m, int kappa, int *R, int *tau, int *n_batches,
                 int *levels_needed) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx, "null context");
         Layout lay = make_layout(ctx->p.n, n, k, m);
         if (R) *R = lay.R;
@@ -455,7 +463,7 @@ int gwas_layout(const ckks_ctx *ctx, int n, int k, int m, int kappa, int *R, int
 
 int gwas_pack_encrypt(ckks_ctx *ctx, const double *X, const double *y, const uint8_t *S, int n, int k, int m,
                       int kappa, uint64_t enc_seed, gwas_enc_input **out) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx && X && y && S && out, "null argument");
         need(kappa >= 2, "kappa must be >= 2");
         if (ctx->p.levels != circuit_levels(kappa)) throw Error(CKKS_E_LEVEL, "chain length does not match kappa");
@@ -466,7 +474,7 @@ int gwas_pack_encrypt(ckks_ctx *ctx, const double *X, const double *y, const uin
 
 int gwas_input_from_cts(ckks_ctx *ctx, int n, int k, int m, int kappa, ckks_ct *const *x, const ckks_ct *y,
                         ckks_ct *const *A, ckks_ct *const *S, int n_s, gwas_enc_input **out) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx && x && y && A && S && out, "null argument");
         need(kappa >= 2, "kappa must be >= 2");
         auto in = std::make_unique<EncInput>();
@@ -499,8 +507,15 @@ int gwas_input_from_cts(ckks_ctx *ctx, int n, int k, int m, int kappa, ckks_ct *
 
 void gwas_input_free(gwas_enc_input *in) { delete in; }
 
+int gwas_input_spill(ckks_ctx *ctx, gwas_enc_input *in) {
+    return guard_ctx(ctx, [&] {
+        need(in && in->ctx == ctx, "bad input");
+        spill_snp(*ctx, *in->in);
+    });
+}
+
 int gwas_semiparallel_chunked(ckks_ctx *ctx, const gwas_enc_input *in, int chunk, gwas_enc_output **out) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx && in && out, "null argument");
         need(in->ctx == ctx, "input belongs to another context");
         need(chunk >= 1, "chunk must be >= 1");
@@ -510,6 +525,28 @@ int gwas_semiparallel_chunked(ckks_ctx *ctx, const gwas_enc_input *in, int chunk
         o->out.chunk = chunk;
         run_circuit(*ctx, *in->in, o->out, chunk);
         *out = o.release();
+    });
+}
+
+int gwas_semiparallel_multi(ckks_ctx *ctx, const gwas_enc_input *const *in, int n_jobs, int chunk,
+                            gwas_enc_output **out) {
+    return guard_ctx(ctx, [&] {
+        need(in && out && n_jobs >= 1 && chunk >= 1, "bad arguments");
+        std::vector<const EncInput *> jobs;
+        for (int i = 0; i < n_jobs; ++i) {
+            need(in[i] && in[i]->ctx == ctx, "input belongs to another context");
+            jobs.push_back(in[i]->in.get());
+            out[i] = nullptr;
+        }
+        std::vector<EncOutput> outs;
+        run_multi(*ctx, jobs, outs, chunk);
+        for (int i = 0; i < n_jobs; ++i) {
+            auto o = std::make_unique<gwas_enc_output>();
+            o->ctx = ctx;
+            o->lay = jobs[i]->lay;
+            o->out = std::move(outs[i]);
+            out[i] = o.release();
+        }
     });
 }
 
@@ -554,7 +591,7 @@ void gwas_output_free(gwas_enc_output *out) { delete out; }
 
 int gwas_finalize(ckks_ctx *ctx, const gwas_enc_output *out, int m, double *b, double *err, double *se, double *num,
                   double *den) {
-    return guard([&] {
+    return guard_ctx(ctx, [&] {
         need(ctx && out, "null argument");
         const Layout &lay = out->lay;
         need(m == lay.m, "m does not match the layout");

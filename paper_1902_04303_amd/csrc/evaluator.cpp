@@ -596,5 +596,6 @@ ckks_ctx::~ckks_ctx() {
     sk_ntt.release();
     pk.release();
     pool.reset();
-    if (table_mem) hipFree(table_mem);
+    if (table_mem) (void)hipFree(table_mem);
+    if (copy_stream) (void)hipStreamDestroy(copy_stream);
 }

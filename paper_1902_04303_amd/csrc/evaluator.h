@@ -1,6 +1,8 @@
 // Context, ciphertext batches and the evaluation operations (host driver over the HIP kernels).
 #pragma once
 
+#include <mutex>
+
 #include "ckks_internal.h"
 
 struct ckks_ct;
@@ -21,6 +23,9 @@ struct ckks_ctx {
     // counters and optional per-kernel timing
     uint64_t n_keyswitch = 0, n_limb_ntt = 0, n_launch = 0;
     gck::KTimer timer;
+    // serialises use of the context between host threads (client calls and a server's worker)
+    std::recursive_mutex mu;
+    hipStream_t copy_stream = nullptr;   // second stream for host-to-device prefetch (default priority)
     ~ckks_ctx();
 };
 

@@ -89,20 +89,36 @@ struct Circ {
 
 }  // namespace
 
-void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
-    const Layout &lay = in.lay;
-    const int k = lay.k;
-    if (c.p.levels != circuit_levels(in.kappa))
-        throw Error(CKKS_E_LEVEL, "the chain has " + std::to_string(c.p.levels) + " levels, the circuit needs " +
-                                      std::to_string(circuit_levels(in.kappa)));
-    for (u64 g : required_galois(c, lay.R))
-        if (!has_key(c, g)) throw Error(CKKS_E_KEY_MISSING, "missing Galois key " + std::to_string(g));
-    if (!has_key(c, 0)) throw Error(CKKS_E_KEY_MISSING, "missing relinearisation key");
+// ---------------------------------------------------------------- batch helpers
+
+// copy ciphertext si of batch s into slot di of batch d (same depth)
+static void copy_ct(ckks_ctx &c, ckks_ct &d, int di, const ckks_ct &s, int si) {
+    const size_t per = (size_t)2 * s.limbs * c.p.n;
+    GCK_HIP(hipMemcpyAsync(d.data.ptr + (size_t)di * per, s.data.ptr + (size_t)si * per, per * 8,
+                           hipMemcpyDeviceToDevice, c.stream));
+}
+
+// a batch made of ciphertext items[i].second of batch items[i].first
+static Ct gather(ckks_ctx &c, const std::vector<std::pair<const ckks_ct *, int>> &items) {
+    const ckks_ct &f = *items[0].first;
+    Ct r = new_ct(c, (int)items.size(), f.depth, f.scale);
+    for (size_t i = 0; i < items.size(); ++i) {
+        if (items[i].first->depth != f.depth || items[i].first->scale != f.scale)
+            throw Error(CKKS_E_PARAM_MISMATCH, "gathered ciphertexts differ in depth or scale");
+        copy_ct(c, *r, (int)i, *items[i].first, items[i].second);
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------- fixed part (per job, batched over jobs)
+
+void run_fixed(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckks_ct *> &x, const ckks_ct &y,
+               const std::vector<const ckks_ct *> &Ain, int ds, FixedOut &fx, EncOutput &rep) {
+    Layout lay;
+    lay.R = R;
+    lay.k = k;
     Circ C(c, lay);
-    auto A = [&](int j, int l) -> const ckks_ct & { return *in.A[a_index(k, std::min(j, l), std::max(j, l))]; };
-    std::vector<const ckks_ct *> x(k);
-    for (int j = 0; j < k; ++j) x[j] = in.x[j].get();
-    const ckks_ct &y = *in.y;
+    auto A = [&](int j, int l) -> const ckks_ct & { return *Ain[a_index(k, std::min(j, l), std::max(j, l))]; };
 
     // ---- Alg. Homomorphic LogReg, first pass: beta = 0, so p = sigma7(0) = 1/2 is public
     Ct r = add_const(c, y, -0.5);
@@ -117,7 +133,7 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
         beta[j] = mul_int(c, *C.msum(p), 4);
     }
     Ct pk;
-    for (int t = 1; t < in.kappa; ++t) {
+    for (int t = 1; t < kappa; ++t) {
         const int d = beta[0]->depth;
         std::vector<Ct> xs(k);
         std::vector<std::pair<const ckks_ct *, const ckks_ct *>> p;
@@ -193,48 +209,256 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
         for (int l = 0; l < k; ++l) q.push_back({A1[j * k + l].get(), x1[l].get()});
         rr[j] = C.msum(q);
     }
-    for (int j = 0; j < k; ++j) out.beta.push_back(std::move(beta[j]));
-    out.w = clone(c, *w);
-    out.w_inv = std::move(w_inv);
-    out.z_proj = clone(c, *z_proj);
-    out.u = clone(c, *u);
+    // ---- what the per-batch part needs, at the depths it uses them
+    fx.r_s.resize(k);
+    fx.x_c.resize(k);
+    for (int j = 0; j < k; ++j) fx.r_s[j] = C.at(*rr[j], ds);
+    for (int j = 0; j < k; ++j) fx.x_c[j] = C.at(*x[j], ds + 2);
+    fx.u_s = C.at(*u, ds + 3);
+    fx.w_s = C.at(*w, ds + 3);
+    for (int j = 0; j < k; ++j) rep.beta.push_back(std::move(beta[j]));
+    rep.w = std::move(w);
+    rep.w_inv = std::move(w_inv);
+    rep.z_proj = std::move(z_proj);
+    rep.u = std::move(u);
+}
 
-    // ---- per-batch part, chunk by chunk (Alg. Semi Parallel GWAS, batch loop)
-    const int nb = in.S->count;
+// ---------------------------------------------------------------- per-batch part
+
+BatchOut run_batch(ckks_ctx &c, int R, int k, const FixedOut &fx, const ckks_ct &S) {
+    Layout lay;
+    lay.R = R;
+    lay.k = k;
+    Circ C(c, lay);
+    std::vector<Ct> E(k);
+    for (int j = 0; j < k; ++j) {
+        Ct pj = mul(c, *fx.r_s[j], S);
+        Ct cj = C.rot_sum(std::move(pj));     // column sums at block starts (Alg. colSum)
+        cj = mul_mask(c, *cj, R);             // keep the block starts
+        E[j] = C.bcast(std::move(cj));        // (A X^T S)_{j, c} over block c
+    }
+    std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pe;
+    for (int j = 0; j < k; ++j) pe.push_back({fx.x_c[j].get(), E[j].get()});
+    Ct xe = C.msum(pe);
+    BatchOut o;
+    o.sp = sub(c, *C.at(S, xe->depth), *xe);
+    o.num = C.rot_sum(mul(c, *fx.u_s, *o.sp));
+    Ct ws = mul(c, *fx.w_s, *o.sp);
+    Ct sc = conjugate(c, *o.sp);
+    Ct wss = mul(c, *ws, *C.at(*o.sp, ws->depth));
+    Ct wsc = mul(c, *ws, *C.at(*sc, ws->depth));
+    o.de = C.rot_sum(set_scale(c, add(c, *wsc, *wss), 2.0));
+    o.dodd = C.rot_sum(set_scale(c, sub(c, *wsc, *wss), 2.0));
+    return o;
+}
+
+static void check_keys(ckks_ctx &c, int R) {
+    for (u64 g : required_galois(c, R))
+        if (!has_key(c, g)) throw Error(CKKS_E_KEY_MISSING, "missing Galois key " + std::to_string(g));
+    if (!has_key(c, 0)) throw Error(CKKS_E_KEY_MISSING, "missing relinearisation key");
+}
+
+void fetch_snp(ckks_ctx &c, const EncInput &in, int b0, int cnt, ckks_ct &dst, int di, hipStream_t st) {
+    const size_t per = (size_t)2 * in.S->limbs * c.p.n;
+    if (in.S_host) {
+        GCK_HIP(hipMemcpyAsync(dst.data.ptr + (size_t)di * per, in.S_host + (size_t)b0 * per, (size_t)cnt * per * 8,
+                               hipMemcpyHostToDevice, st));
+    } else {
+        GCK_HIP(hipMemcpyAsync(dst.data.ptr + (size_t)di * per, in.S->data.ptr + (size_t)b0 * per, (size_t)cnt * per * 8,
+                               hipMemcpyDeviceToDevice, st));
+    }
+}
+
+void spill_snp(ckks_ctx &c, EncInput &in) {
+    if (in.S_host) return;
+    const size_t bytes = in.S->data.words * 8;
+    GCK_HIP(hipHostMalloc((void **)&in.S_host, bytes, hipHostMallocDefault));
+    GCK_HIP(hipMemcpyAsync(in.S_host, in.S->data.ptr, bytes, hipMemcpyDeviceToHost, c.stream));
+    sync(c);
+    in.S->data.release();
+}
+
+static hipStream_t copy_stream(ckks_ctx &c) {
+    if (!c.copy_stream) GCK_HIP(hipStreamCreate(&c.copy_stream));   // default priority
+    return c.copy_stream;
+}
+
+void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
+    const Layout &lay = in.lay;
+    const int k = lay.k;
+    if (c.p.levels != circuit_levels(in.kappa))
+        throw Error(CKKS_E_LEVEL, "the chain has " + std::to_string(c.p.levels) + " levels, the circuit needs " +
+                                      std::to_string(circuit_levels(in.kappa)));
+    check_keys(c, lay.R);
+    std::vector<const ckks_ct *> x, A;
+    for (auto &p : in.x) x.push_back(p.get());
+    for (auto &p : in.A) A.push_back(p.get());
+    FixedOut fx;
     const int ds = in.S->depth;
-    std::vector<Ct> r_s(k), x_c(k);
-    for (int j = 0; j < k; ++j) r_s[j] = C.at(*rr[j], ds);
-    for (int j = 0; j < k; ++j) x_c[j] = C.at(*x[j], ds + 2);
-    Ct u_s = C.at(*u, ds + 3), w_s = C.at(*w, ds + 3);
-    const size_t N = (size_t)c.p.n;
-    for (int b0 = 0; b0 < nb; b0 += chunk) {
+    run_fixed(c, lay.R, k, in.kappa, x, *in.y, A, ds, fx, out);
+    const int nb = in.S->count;
+    if (!in.S_host) {
+        for (int b0 = 0; b0 < nb; b0 += chunk) {
+            const int cnt = std::min(chunk, nb - b0);
+            Ct S = new_ct(c, cnt, ds, in.S->scale);
+            fetch_snp(c, in, b0, cnt, *S, 0, c.stream);
+            BatchOut o = run_batch(c, lay.R, k, fx, *S);
+            out.S_proj.push_back(std::move(o.sp));
+            out.num.push_back(std::move(o.num));
+            out.den_even.push_back(std::move(o.de));
+            out.den_odd.push_back(std::move(o.dodd));
+        }
+        return;
+    }
+    // spilled SNP batches: copy chunk i + 1 from pinned host memory on a second stream while chunk i
+    // computes.  Each buffer's copy waits for an event recorded on the compute stream when the buffer was
+    // taken from the pool, and chunk i's compute waits for its own copy.
+    hipStream_t cs = copy_stream(c);
+    auto start = [&](int b0, hipEvent_t &done) {
         const int cnt = std::min(chunk, nb - b0);
         Ct S = new_ct(c, cnt, ds, in.S->scale);
-        const size_t per = (size_t)2 * S->limbs * N;
-        GCK_HIP(hipMemcpyAsync(S->data.ptr, in.S->data.ptr + (size_t)b0 * per, (size_t)cnt * per * 8,
-                               hipMemcpyDeviceToDevice, c.stream));
-        std::vector<Ct> E(k);
-        for (int j = 0; j < k; ++j) {
-            Ct pj = mul(c, *r_s[j], *S);
-            Ct cj = C.rot_sum(std::move(pj));     // column sums at block starts (Alg. colSum)
-            cj = mul_mask(c, *cj, lay.R);         // keep the block starts
-            E[j] = C.bcast(std::move(cj));        // (A X^T S)_{j, c} over block c
+        hipEvent_t taken;
+        GCK_HIP(hipEventCreateWithFlags(&taken, hipEventDisableTiming));
+        GCK_HIP(hipEventRecord(taken, c.stream));
+        GCK_HIP(hipStreamWaitEvent(cs, taken, 0));
+        fetch_snp(c, in, b0, cnt, *S, 0, cs);
+        GCK_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+        GCK_HIP(hipEventRecord(done, cs));
+        (void)hipEventDestroy(taken);
+        return S;
+    };
+    hipEvent_t ev_cur, ev_next = nullptr;
+    Ct cur = start(0, ev_cur);
+    for (int b0 = 0; b0 < nb; b0 += chunk) {
+        Ct next;
+        if (b0 + chunk < nb) next = start(b0 + chunk, ev_next);
+        GCK_HIP(hipStreamWaitEvent(c.stream, ev_cur, 0));
+        BatchOut o = run_batch(c, lay.R, k, fx, *cur);
+        (void)hipEventDestroy(ev_cur);
+        out.S_proj.push_back(std::move(o.sp));
+        out.num.push_back(std::move(o.num));
+        out.den_even.push_back(std::move(o.de));
+        out.den_odd.push_back(std::move(o.dodd));
+        cur = std::move(next);
+        ev_cur = ev_next;
+    }
+}
+
+// ---------------------------------------------------------------- several jobs
+
+std::tuple<int, int, int> bucket_of(const EncInput &in) { return std::make_tuple(in.lay.R, in.lay.k, in.kappa); }
+
+// Fixed parts of several jobs with one shape (R, k, kappa): one launch sequence over a batch of one
+// ciphertext per job; the results are split back into one FixedOut (batches of one) per job.
+void fixed_for_jobs(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std::vector<FixedOut> &fxs,
+                    std::vector<EncOutput> &reps) {
+    const EncInput &j0 = *jobs[0];
+    const int R = j0.lay.R, k = j0.lay.k, kappa = j0.kappa, J = (int)jobs.size();
+    if (c.p.levels != circuit_levels(kappa)) throw Error(CKKS_E_LEVEL, "chain length does not match kappa");
+    check_keys(c, R);
+    std::vector<Ct> xs(k), As(k * (k + 1) / 2);
+    for (int j = 0; j < k; ++j) {
+        std::vector<std::pair<const ckks_ct *, int>> it;
+        for (auto *in : jobs) it.push_back({in->x[j].get(), 0});
+        xs[j] = gather(c, it);
+    }
+    for (int a = 0; a < k * (k + 1) / 2; ++a) {
+        std::vector<std::pair<const ckks_ct *, int>> it;
+        for (auto *in : jobs) it.push_back({in->A[a].get(), 0});
+        As[a] = gather(c, it);
+    }
+    std::vector<std::pair<const ckks_ct *, int>> yit;
+    for (auto *in : jobs) yit.push_back({in->y.get(), 0});
+    Ct ys = gather(c, yit);
+    std::vector<const ckks_ct *> xp, Ap;
+    for (auto &p : xs) xp.push_back(p.get());
+    for (auto &p : As) Ap.push_back(p.get());
+    FixedOut fx;
+    EncOutput rep;
+    run_fixed(c, R, k, kappa, xp, *ys, Ap, snp_depth(kappa), fx, rep);
+    fxs.clear();
+    fxs.resize(J);
+    reps.clear();
+    reps.resize(J);
+    for (int q = 0; q < J; ++q) {
+        FixedOut &f = fxs[q];
+        for (int j = 0; j < k; ++j) f.r_s.push_back(gather(c, {{fx.r_s[j].get(), q}}));
+        for (int j = 0; j < k; ++j) f.x_c.push_back(gather(c, {{fx.x_c[j].get(), q}}));
+        f.u_s = gather(c, {{fx.u_s.get(), q}});
+        f.w_s = gather(c, {{fx.w_s.get(), q}});
+        EncOutput &o = reps[q];
+        for (int j = 0; j < k; ++j) o.beta.push_back(gather(c, {{rep.beta[j].get(), q}}));
+        o.w = gather(c, {{rep.w.get(), q}});
+        o.w_inv = gather(c, {{rep.w_inv.get(), q}});
+        o.z_proj = gather(c, {{rep.z_proj.get(), q}});
+        o.u = gather(c, {{rep.u.get(), q}});
+    }
+}
+
+// One chunk of SNP batches drawn from several jobs of one shape: items (job, batch); every batch is
+// paired with its own job's fixed-part values; outputs land in slot `batch` of each job's outputs
+// (allocated on first use).
+void chunk_for_jobs(ckks_ctx &c, const std::vector<WorkItem> &items) {
+    const EncInput &j0 = *items[0].in;
+    const int R = j0.lay.R, k = j0.lay.k;
+    Ct S = new_ct(c, (int)items.size(), j0.S->depth, j0.S->scale);
+    for (size_t i = 0; i < items.size(); ++i) {
+        if (items[i].in->S->depth != S->depth || items[i].in->S->scale != S->scale)
+            throw Error(CKKS_E_PARAM_MISMATCH, "SNP batches of different depth or scale");
+        fetch_snp(c, *items[i].in, items[i].batch, 1, *S, (int)i, c.stream);
+    }
+    auto per_item = [&](auto get) {
+        std::vector<std::pair<const ckks_ct *, int>> it;
+        for (auto &w : items) it.push_back({get(*w.fx), 0});
+        return gather(c, it);
+    };
+    FixedOut fc;
+    for (int j = 0; j < k; ++j) fc.r_s.push_back(per_item([&](const FixedOut &f) { return f.r_s[j].get(); }));
+    for (int j = 0; j < k; ++j) fc.x_c.push_back(per_item([&](const FixedOut &f) { return f.x_c[j].get(); }));
+    fc.u_s = per_item([](const FixedOut &f) { return f.u_s.get(); });
+    fc.w_s = per_item([](const FixedOut &f) { return f.w_s.get(); });
+    BatchOut bo = run_batch(c, R, k, fc, *S);
+    for (size_t i = 0; i < items.size(); ++i) {
+        EncOutput &o = *items[i].out;
+        const int nbq = items[i].in->S->count;
+        if (o.num.empty()) {
+            o.S_proj.push_back(new_ct(c, nbq, bo.sp->depth, bo.sp->scale));
+            o.num.push_back(new_ct(c, nbq, bo.num->depth, bo.num->scale));
+            o.den_even.push_back(new_ct(c, nbq, bo.de->depth, bo.de->scale));
+            o.den_odd.push_back(new_ct(c, nbq, bo.dodd->depth, bo.dodd->scale));
+            o.chunk = nbq;
         }
-        std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pe;
-        for (int j = 0; j < k; ++j) pe.push_back({x_c[j].get(), E[j].get()});
-        Ct xe = C.msum(pe);
-        Ct sp = sub(c, *C.at(*S, xe->depth), *xe);
-        Ct num = C.rot_sum(mul(c, *u_s, *sp));
-        Ct ws = mul(c, *w_s, *sp);
-        Ct sc = conjugate(c, *sp);
-        Ct wss = mul(c, *ws, *C.at(*sp, ws->depth));
-        Ct wsc = mul(c, *ws, *C.at(*sc, ws->depth));
-        Ct de = C.rot_sum(set_scale(c, add(c, *wsc, *wss), 2.0));
-        Ct dodd = C.rot_sum(set_scale(c, sub(c, *wsc, *wss), 2.0));
-        out.S_proj.push_back(std::move(sp));
-        out.num.push_back(std::move(num));
-        out.den_even.push_back(std::move(de));
-        out.den_odd.push_back(std::move(dodd));
+        const int b = items[i].batch;
+        copy_ct(c, *o.S_proj[0], b, *bo.sp, (int)i);
+        copy_ct(c, *o.num[0], b, *bo.num, (int)i);
+        copy_ct(c, *o.den_even[0], b, *bo.de, (int)i);
+        copy_ct(c, *o.den_odd[0], b, *bo.dodd, (int)i);
+    }
+}
+
+// Several jobs at once: jobs with the same (R, k, kappa) share every launch of the fixed part and their
+// SNP batches go through the per-batch part together, `chunk` at a time.  Each job's output holds one
+// batch per output kind.
+void run_multi(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std::vector<EncOutput> &outs, int chunk) {
+    outs.clear();
+    outs.resize(jobs.size());
+    std::map<std::tuple<int, int, int>, std::vector<int>> buckets;
+    for (size_t i = 0; i < jobs.size(); ++i) buckets[bucket_of(*jobs[i])].push_back((int)i);
+    for (auto &kv : buckets) {
+        const std::vector<int> &ids = kv.second;
+        std::vector<const EncInput *> bj;
+        for (int id : ids) bj.push_back(jobs[id]);
+        std::vector<FixedOut> fxs;
+        std::vector<EncOutput> reps;
+        fixed_for_jobs(c, bj, fxs, reps);
+        for (size_t q = 0; q < ids.size(); ++q) outs[ids[q]] = std::move(reps[q]);
+        std::vector<WorkItem> work;
+        for (size_t q = 0; q < ids.size(); ++q)
+            for (int b = 0; b < bj[q]->S->count; ++b) work.push_back(WorkItem{bj[q], &fxs[q], &outs[ids[q]], b});
+        for (size_t w0 = 0; w0 < work.size(); w0 += chunk) {
+            const size_t cnt = std::min((size_t)chunk, work.size() - w0);
+            chunk_for_jobs(c, std::vector<WorkItem>(work.begin() + w0, work.begin() + w0 + cnt));
+        }
     }
 }
 

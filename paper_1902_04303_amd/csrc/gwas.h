@@ -1,6 +1,9 @@
 // Encrypted modified semi-parallel GWAS circuit (device) and client-side packing.
 #pragma once
 
+#include <map>
+#include <tuple>
+
 #include "evaluator.h"
 
 namespace gck {
@@ -27,8 +30,16 @@ struct EncInput {
     std::vector<Ct> x;   // k ciphertexts, depth 0
     Ct y;                // depth 0
     std::vector<Ct> A;   // k(k+1)/2, depth 0, scale R Delta_0
-    Ct S;                // batched: n_batches ciphertexts at depth 7 kappa
+    Ct S;                // batched: n_batches ciphertexts at depth 7 kappa (data empty when spilled)
+    u64 *S_host = nullptr;   // the SNP batches in pinned host memory after a spill
+    ~EncInput() {
+        if (S_host) (void)hipHostFree(S_host);
+    }
 };
+// copy SNP batches [b0, b0 + cnt) of `in` (device or spilled host copy) into slots di.. of dst, on stream st
+void fetch_snp(ckks_ctx &c, const EncInput &in, int b0, int cnt, ckks_ct &dst, int di, hipStream_t st);
+// move the SNP batches to pinned host memory (they are streamed back chunk by chunk when used)
+void spill_snp(ckks_ctx &c, EncInput &in);
 
 struct EncOutput {
     std::vector<Ct> beta;
@@ -37,12 +48,50 @@ struct EncOutput {
     int chunk = 0;
 };
 
+// what the per-batch part needs from the fixed part (batch of one per job, or one per SNP batch)
+struct FixedOut {
+    std::vector<Ct> r_s;   // r_j = (X A)_{:, j} at the SNP depth
+    std::vector<Ct> x_c;   // x_j at the SNP depth + 2
+    Ct u_s, w_s;           // u = w z' and w at the SNP depth + 3
+};
+struct BatchOut {
+    Ct sp, num, de, dodd;
+};
+
 int circuit_levels(int kappa);
 int snp_depth(int kappa);
 Layout make_layout(int n_ring, int n, int k, int m);
 std::vector<u64> required_galois(const ckks_ctx &c, int R);
+void run_fixed(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckks_ct *> &x, const ckks_ct &y,
+               const std::vector<const ckks_ct *> &A, int ds, FixedOut &fx, EncOutput &rep);
+BatchOut run_batch(ckks_ctx &c, int R, int k, const FixedOut &fx, const ckks_ct &S);
 void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk);
+void run_multi(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std::vector<EncOutput> &outs, int chunk);
+// building blocks shared with the server
+struct WorkItem {
+    const EncInput *in;
+    const FixedOut *fx;
+    EncOutput *out;
+    int batch;
+};
+std::tuple<int, int, int> bucket_of(const EncInput &in);
+void fixed_for_jobs(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std::vector<FixedOut> &fxs,
+                    std::vector<EncOutput> &reps);
+void chunk_for_jobs(ckks_ctx &c, const std::vector<WorkItem> &items);
 std::unique_ptr<EncInput> pack_encrypt(ckks_ctx &c, const double *X, const double *y, const uint8_t *S, int n, int k,
                                        int m, int kappa, u64 enc_seed);
 
+size_t input_footprint(const ckks_ctx &c, const EncInput &in);
+
 }  // namespace gck
+
+struct gwas_enc_input {
+    ckks_ctx *ctx;
+    std::unique_ptr<gck::EncInput> in;
+};
+
+struct gwas_enc_output {
+    ckks_ctx *ctx;
+    gck::EncOutput out;
+    gck::Layout lay;
+};
