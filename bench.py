@@ -91,6 +91,75 @@ def gpu_leg(args):
                 b_finite=int(np.isfinite(res["b"]).sum()), pool=ctx.pool_stats())
 
 
+def forms_leg(args):
+    """Batched multi-job form vs the plain one-job-at-a-time path, and the serving loop under Poisson
+    arrivals vs FIFO one job at a time, on a seeded mix of jobs with the batched configuration's size
+    distribution (n ~ U{100..2000}, k = 4, m ~ logU[1e3, 5e4] scaled by args.forms_m_scale)."""
+    import torch
+
+    import paper_1902_04303_amd as P
+    from synth import job_mix, make_gwas_data, poisson_arrivals
+
+    L = 7 * KAPPA + 5
+    ctx = P.Context(LOG_N, L, LOG_SCALE)
+    ctx.keygen(7, galois_set(ctx, 2048))
+    jobs = job_mix(args.forms_jobs, 301, args.forms_m_scale)
+    snps = sum(m for _, _, m, _ in jobs)
+
+    def pack_all():
+        ins = []
+        for n, k, m, ds in jobs:
+            d = make_gwas_data(n, k, m, seed=ds)
+            ins.append(ctx.gwas_pack_encrypt(d.X, d.y, d.S, KAPPA, ds))
+        torch.cuda.synchronize()
+        return ins
+
+    ins = pack_all()
+    # warm the pool with one job of the largest shape
+    ctx.gwas_semiparallel(ins[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in ins:
+        ctx.gwas_semiparallel(i)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ctx.gwas_semiparallel_multi(ins, chunk=64)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    log("[bench] %d jobs (%d SNPs): plain %.2fs, batched %.2fs" % (len(jobs), snps, t_plain, t_batched))
+    batched = {"jobs": len(jobs), "snps": snps, "plain_jobs_per_s": round(len(jobs) / t_plain, 3),
+               "batched_jobs_per_s": round(len(jobs) / t_batched, 3),
+               "ratio": round(t_plain / t_batched, 3), "m_scale": args.forms_m_scale}
+    del ins
+
+    def serve(max_jobs):
+        ins = pack_all()
+        arrivals = poisson_arrivals(len(ins), args.forms_rate, 302)
+        srv = ctx.gwas_server(hbm_budget=0, max_jobs=max_jobs, chunk=64)
+        t0 = time.perf_counter()
+        ids = []
+        for a, i in zip(arrivals, ins):
+            while time.perf_counter() - t0 < a:
+                time.sleep(0.001)
+            ids.append(srv.submit(i))
+        for jid, (_, _, m, _) in zip(ids, jobs):
+            srv.poll(jid, m, wait=True)
+        st = srv.stats()
+        srv.close()
+        return st
+
+    cb = serve(64)
+    fifo = serve(1)
+    log("[bench] serving: continuous p50 %.0f ms p99 %.0f ms; FIFO p50 %.0f ms p99 %.0f ms" %
+        (cb["p50_ms"], cb["p99_ms"], fifo["p50_ms"], fifo["p99_ms"]))
+    serving = {"jobs": len(jobs), "arrival_rate_per_s": args.forms_rate,
+               "continuous": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in cb.items()},
+               "fifo_one_at_a_time": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in fifo.items()}}
+    ctx.close()
+    return batched, serving
+
+
 def roofline(kernels, steps):
     name, (cnt, tot_ms, by) = max(kernels.items(), key=lambda kv: kv[1][1])
     avg_ms = tot_ms / cnt
@@ -147,6 +216,9 @@ def run(args) -> int:
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_leg()
+    batched = serving = None
+    if args.forms_jobs > 0:
+        batched, serving = forms_leg(args)
     line = {
         "metric": "encrypted SNPs/s at 245x4x10643",
         "value": round(value, 1),
@@ -165,6 +237,8 @@ def run(args) -> int:
                    "parallelism": "1 GPU"},
         "roofline": rl,
         "cpu_baseline": cpu,
+        "batched": batched,
+        "serving": serving,
         "per_step": g["counters"],
         "finalize_ms": round(g["finalize_ms"], 1),
     }
@@ -178,6 +252,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms-jobs", type=int, default=12, help="jobs in the batched / serving legs (0: skip)")
+    ap.add_argument("--forms-m-scale", type=float, default=0.1, help="scale of the job SNP counts")
+    ap.add_argument("--forms-rate", type=float, default=4.0, help="Poisson arrival rate (jobs/s)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build measures the single-GPU path (the multi-GPU sharding is a "

@@ -77,3 +77,22 @@ def make_gwas_data(n: int, k: int, m: int, seed: int, planted_frac: float = 0.0,
     p = 1.0 / (1.0 + np.exp(-logit))
     y = (rng.uniform(size=n) < p).astype(np.float64)
     return GwasData(X=X, y=y, S=S, b=b, maf=maf, planted=planted, seed=seed)
+
+
+def job_mix(count: int, seed: int, m_scale: float = 1.0):
+    """Sizes of a mix of GWAS jobs: n ~ U{100..2000}, k = 4, m = round(exp(U[ln 1e3, ln 5e4]) * m_scale).
+
+    Returns a list of (n, k, m, data_seed)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(count):
+        n = int(rng.integers(100, 2001))
+        m = max(1, int(round(np.exp(rng.uniform(np.log(1e3), np.log(5e4))) * m_scale)))
+        out.append((n, 4, m, seed * 1000 + j))
+    return out
+
+
+def poisson_arrivals(count: int, rate_per_s: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process with the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate_per_s, size=count))
