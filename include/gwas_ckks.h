@@ -140,7 +140,9 @@ int ckks_decrypt_poly(ckks_ctx *ctx, const ckks_ct *ct, int index, double *coeff
 /* ---------------------------------------------------------------- ciphertexts
  * A ckks_ct handle is a batch of `count` ciphertexts at one depth and scale,
  * stored [count][2][limbs][N] on the device; operations on two batches pair them
- * element-wise, and a batch of one broadcasts against a larger batch. */
+ * element-wise, and a smaller batch whose count divides the larger one's is read
+ * cyclically (ciphertext i pairs with ciphertext i mod count; a batch of one
+ * broadcasts); other count mismatches fail with CKKS_E_PARAM_MISMATCH. */
 
 int ckks_ct_info(const ckks_ct *ct, int *count, int *depth, int *limbs, double *scale);
 /* Canonical export of ciphertext `index` of the batch: [2][limbs][N] words. */

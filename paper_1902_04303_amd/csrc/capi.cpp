@@ -70,6 +70,7 @@ void build_tables(ckks_ctx &c) {
     const int n = c.p.n, n_mods = c.p.levels + 2;
     const size_t N = (size_t)n;
     std::vector<u64> psi(N * n_mods), psi_sh(N * n_mods), ipsi(N * n_mods), ipsi_sh(N * n_mods);
+    std::vector<double> psi_f(N * n_mods), ipsi_f(N * n_mods);
     c.h_mods.resize(n_mods);
     for (int mi = 0; mi < n_mods; ++mi) {
         const u64 q = c.p.mod(mi);
@@ -86,6 +87,8 @@ void build_tables(ckks_ctx &c) {
             psi_sh[mi * N + k] = shoup_of(pw[br], q);
             ipsi[mi * N + k] = ipw[br];
             ipsi_sh[mi * N + k] = shoup_of(ipw[br], q);
+            psi_f[mi * N + k] = (double)pw[br];
+            ipsi_f[mi * N + k] = (double)ipw[br];
         }
         ModInfo &M = c.h_mods[mi];
         M.q = q;
@@ -98,16 +101,22 @@ void build_tables(ckks_ctx &c) {
         M.ninv_sh = shoup_of(M.ninv, q);
         M.w1ninv = mulmod_host(ipsi[mi * N + 1], M.ninv, q);
         M.w1ninv_sh = shoup_of(M.w1ninv, q);
+        M.fp = q < ((u64)1 << kFpModBits) ? 1 : 0;
+        M.qd = (double)q;
+        M.qinv = 1.0 / (double)q;
+        M.ninv_d = (double)M.ninv;
     }
     const size_t mods_bytes = ((sizeof(ModInfo) * n_mods + 255) / 256) * 256;
     const size_t tab_bytes = N * n_mods * 8;
-    GCK_HIP(hipMalloc(&c.table_mem, mods_bytes + 4 * tab_bytes));
+    GCK_HIP(hipMalloc(&c.table_mem, mods_bytes + 6 * tab_bytes));
     char *base = static_cast<char *>(c.table_mem);
     c.tab.mods = reinterpret_cast<ModInfo *>(base);
     c.tab.psi = reinterpret_cast<u64 *>(base + mods_bytes);
     c.tab.psi_sh = reinterpret_cast<u64 *>(base + mods_bytes + tab_bytes);
     c.tab.ipsi = reinterpret_cast<u64 *>(base + mods_bytes + 2 * tab_bytes);
     c.tab.ipsi_sh = reinterpret_cast<u64 *>(base + mods_bytes + 3 * tab_bytes);
+    c.tab.psi_f = reinterpret_cast<double *>(base + mods_bytes + 4 * tab_bytes);
+    c.tab.ipsi_f = reinterpret_cast<double *>(base + mods_bytes + 5 * tab_bytes);
     c.tab.n = n;
     c.tab.log_n = c.p.log_n;
     c.tab.n_mods = n_mods;
@@ -116,6 +125,8 @@ void build_tables(ckks_ctx &c) {
     GCK_HIP(hipMemcpy(c.tab.psi_sh, psi_sh.data(), tab_bytes, hipMemcpyHostToDevice));
     GCK_HIP(hipMemcpy(c.tab.ipsi, ipsi.data(), tab_bytes, hipMemcpyHostToDevice));
     GCK_HIP(hipMemcpy(c.tab.ipsi_sh, ipsi_sh.data(), tab_bytes, hipMemcpyHostToDevice));
+    GCK_HIP(hipMemcpy(c.tab.psi_f, psi_f.data(), tab_bytes, hipMemcpyHostToDevice));
+    GCK_HIP(hipMemcpy(c.tab.ipsi_f, ipsi_f.data(), tab_bytes, hipMemcpyHostToDevice));
 }
 
 Ct wrap(Ct r) { return r; }

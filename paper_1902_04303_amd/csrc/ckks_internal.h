@@ -39,7 +39,11 @@ struct ModInfo {
     u64 r2_mod;        // 2^128 mod q
     u64 ninv, ninv_sh; // N^-1
     u64 w1ninv, w1ninv_sh;  // psi^-1 (first inverse twiddle) * N^-1
+    // moduli below 2^41 also run their NTT butterflies in FP64 (exact products by FMA)
+    u64 fp;            // 1 when q < 2^41
+    double qd, qinv, ninv_d;   // q, RN(1 / q), N^-1 mod q as doubles
 };
+constexpr int kFpModBits = 41;
 
 // ---------------------------------------------------------------- parameters and prime chain
 struct Params {
@@ -141,6 +145,7 @@ struct DevTables {
     KTimer *timer = nullptr;
     ModInfo *mods = nullptr;            // [n_mods]
     u64 *psi = nullptr, *psi_sh = nullptr, *ipsi = nullptr, *ipsi_sh = nullptr;  // [n_mods][N]
+    double *psi_f = nullptr, *ipsi_f = nullptr;   // [n_mods][N] the same twiddles as doubles (FP64 moduli)
     int n = 0, log_n = 0, n_mods = 0;
 };
 

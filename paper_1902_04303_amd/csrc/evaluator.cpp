@@ -122,6 +122,38 @@ Ct clone(ckks_ctx &c, const ckks_ct &a) {
     return r;
 }
 
+Ct view(const ckks_ct &a, int first, int n) {
+    if (first < 0 || n < 1 || first + n > a.count) throw Error(CKKS_E_INVALID_ARG, "view out of range");
+    const size_t per = (size_t)2 * a.limbs * a.ctx->p.n;
+    Ct r(new ckks_ct());
+    r->ctx = a.ctx;
+    r->count = n;
+    r->depth = a.depth;
+    r->limbs = a.limbs;
+    r->scale = a.scale;
+    r->data.pool = nullptr;   // not owned: nothing is returned to the pool
+    r->data.ptr = a.data.ptr + (size_t)first * per;
+    r->data.words = (size_t)n * per;
+    return r;
+}
+
+Ct stack(ckks_ctx &c, const std::vector<const ckks_ct *> &parts) {
+    if (parts.empty()) throw Error(CKKS_E_INVALID_ARG, "nothing to stack");
+    int count = 0;
+    for (auto *p : parts) {
+        if (p->depth != parts[0]->depth || p->scale != parts[0]->scale)
+            throw Error(CKKS_E_PARAM_MISMATCH, "stacked ciphertexts differ in depth or scale");
+        count += p->count;
+    }
+    Ct r = new_ct(c, count, parts[0]->depth, parts[0]->scale);
+    size_t off = 0;
+    for (auto *p : parts) {
+        GCK_HIP(hipMemcpyAsync(r->data.ptr + off, p->data.ptr, p->data.words * 8, hipMemcpyDeviceToDevice, c.stream));
+        off += p->data.words;
+    }
+    return r;
+}
+
 void ntt_fwd(ckks_ctx &c, u64 *buf, int n_limbs, ModMap m) {
     k_ntt_forward(c.tab, buf, n_limbs, m, c.stream);
     c.n_limb_ntt += n_limbs;
@@ -159,7 +191,7 @@ static void check_same(const ckks_ct &a, const ckks_ct &b) {
     if (a.depth != b.depth || a.scale != b.scale)
         throw Error(CKKS_E_PARAM_MISMATCH, "operands differ in depth (" + std::to_string(a.depth) + ", " +
                                                std::to_string(b.depth) + ") or scale");
-    if (a.count != b.count && a.count != 1 && b.count != 1)
+    if (std::max(a.count, b.count) % std::min(a.count, b.count) != 0)
         throw Error(CKKS_E_PARAM_MISMATCH, "batch counts differ");
 }
 
@@ -324,7 +356,7 @@ Ct mul_sum(ckks_ctx &c, const std::vector<std::pair<const ckks_ct *, const ckks_
         count = std::max(count, std::max(pr.first->count, pr.second->count));
     }
     for (auto &pr : pairs)
-        if ((pr.first->count != 1 && pr.first->count != count) || (pr.second->count != 1 && pr.second->count != count))
+        if (count % pr.first->count != 0 || count % pr.second->count != 0)
             throw Error(CKKS_E_PARAM_MISMATCH, "batch counts differ");
     const int l = a0.limbs;
     const size_t N = (size_t)c.p.n;

@@ -44,11 +44,16 @@ using Ct = std::unique_ptr<ckks_ct>;
 
 Ct new_ct(ckks_ctx &c, int count, int depth, double scale);
 Ct clone(ckks_ctx &c, const ckks_ct &a);
+// ciphertexts [first, first + n) of batch a, sharing its memory (valid while a lives; never freed)
+Ct view(const ckks_ct &a, int first, int n);
+// one batch holding the ciphertexts of every part in order (same depth and scale)
+Ct stack(ckks_ctx &c, const std::vector<const ckks_ct *> &parts);
 
 void ntt_fwd(ckks_ctx &c, u64 *buf, int n_limbs, ModMap m);
 void ntt_inv(ckks_ctx &c, u64 *buf, int n_limbs, ModMap m);
 
-// ---- scheme operations (count-batched; operands with count 1 broadcast)
+// ---- scheme operations (count-batched; an operand with fewer ciphertexts, a divisor of the other's
+//      count, is read cyclically: ciphertext i pairs with ciphertext i mod count)
 Ct add(ckks_ctx &c, const ckks_ct &a, const ckks_ct &b);
 Ct sub(ckks_ctx &c, const ckks_ct &a, const ckks_ct &b);
 Ct neg(ckks_ctx &c, const ckks_ct &a);

@@ -119,43 +119,55 @@ void run_fixed(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckk
     lay.k = k;
     Circ C(c, lay);
     auto A = [&](int j, int l) -> const ckks_ct & { return *Ain[a_index(k, std::min(j, l), std::max(j, l))]; };
+    const int J = x[0]->count;   // jobs in the batch
+
+    // The k columns x_j are stacked into one batch (x_j of job i at position j J + i), and so is each
+    // column of A: the k independent products, rotate-and-sums and product sums over j then run as one
+    // batched call each.  Every ciphertext goes through the same operations as in a per-j loop.
+    Ct Xs = stack(c, x);
+    std::vector<Ct> Acol(k);
+    for (int l = 0; l < k; ++l) {
+        std::vector<const ckks_ct *> col;
+        for (int j = 0; j < k; ++j) col.push_back(&A(j, l));
+        Acol[l] = stack(c, col);
+    }
+    auto parts = [&](const ckks_ct &s) {
+        std::vector<Ct> v(k);
+        for (int j = 0; j < k; ++j) v[j] = view(s, j * J, J);
+        return v;
+    };
+    // (A v)_j = sum_l A_jl v_l for every j at once, A at the depth of v
+    auto a_times = [&](const std::vector<Ct> &v) {
+        std::vector<Ct> Ad(k);
+        std::vector<std::pair<const ckks_ct *, const ckks_ct *>> q;
+        for (int l = 0; l < k; ++l) {
+            Ad[l] = C.at(*Acol[l], v[0]->depth);
+            q.push_back({Ad[l].get(), v[l].get()});
+        }
+        return C.msum(q);
+    };
+    // sum_j x_j t_j for stacked t, x at the depth of t (times factor)
+    auto x_dot = [&](const ckks_ct &t, double factor) {
+        Ct Xd = C.at(*Xs, t.depth, factor);
+        std::vector<Ct> a = parts(*Xd), b = parts(t);
+        std::vector<std::pair<const ckks_ct *, const ckks_ct *>> q;
+        for (int j = 0; j < k; ++j) q.push_back({a[j].get(), b[j].get()});
+        return C.msum(q);
+    };
 
     // ---- Alg. Homomorphic LogReg, first pass: beta = 0, so p = sigma7(0) = 1/2 is public
     Ct r = add_const(c, y, -0.5);
-    std::vector<Ct> A1(k * k);
-    for (int j = 0; j < k; ++j)
-        for (int l = 0; l < k; ++l) A1[j * k + l] = C.at(A(j, l), 1);
-    std::vector<Ct> g(k), beta(k);
-    for (int j = 0; j < k; ++j) g[j] = C.rot_sum(mul(c, *x[j], *r));
-    for (int j = 0; j < k; ++j) {
-        std::vector<std::pair<const ckks_ct *, const ckks_ct *>> p;
-        for (int l = 0; l < k; ++l) p.push_back({A1[j * k + l].get(), g[l].get()});
-        beta[j] = mul_int(c, *C.msum(p), 4);
-    }
+    Ct G = C.rot_sum(mul(c, *Xs, *r));                 // g_j = X^T (y - p), stacked over j
+    Ct beta = mul_int(c, *a_times(parts(*G)), 4);     // beta_j = 4 (A g)_j, stacked over j
     Ct pk;
     for (int t = 1; t < kappa; ++t) {
-        const int d = beta[0]->depth;
-        std::vector<Ct> xs(k);
-        std::vector<std::pair<const ckks_ct *, const ckks_ct *>> p;
-        for (int j = 0; j < k; ++j) {
-            xs[j] = C.at(*x[j], d, 0.125);     // the 1/8 of sigma7's argument
-            p.push_back({xs[j].get(), beta[j].get()});
-        }
-        Ct u = C.msum(p);
+        Ct u = x_dot(*beta, 0.125);                    // the 1/8 of sigma7's argument
         pk = C.sigma7(*u);
         const int dp = pk->depth;
         r = sub(c, *C.at(y, dp), *pk);
-        for (int j = 0; j < k; ++j) g[j] = C.rot_sum(mul(c, *C.at(*x[j], dp), *r));
-        const int dg = g[0]->depth;
-        std::vector<Ct> Ag(k * k);
-        for (int j = 0; j < k; ++j)
-            for (int l = 0; l < k; ++l) Ag[j * k + l] = C.at(A(j, l), dg);
-        for (int j = 0; j < k; ++j) {
-            std::vector<std::pair<const ckks_ct *, const ckks_ct *>> q;
-            for (int l = 0; l < k; ++l) q.push_back({Ag[j * k + l].get(), g[l].get()});
-            Ct inc = mul_int(c, *C.msum(q), 4);
-            beta[j] = add(c, *C.at(*beta[j], inc->depth), *inc);
-        }
+        G = C.rot_sum(mul(c, *C.at(*Xs, dp), *r));
+        Ct inc = mul_int(c, *a_times(parts(*G)), 4);
+        beta = add(c, *C.at(*beta, inc->depth), *inc);
     }
     // ---- w = p (1 - p), Alg. inverseSlots: guess 3, the first Newton step is 6 - 9 w
     Ct w = mul(c, *pk, *add_const(c, *neg(c, *pk), 1.0));
@@ -167,56 +179,30 @@ void run_fixed(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckk
     }
     Ct w_inv = std::move(gi);
     // ---- z = X beta^(kappa) + w^-1 (y - p^(kappa-1))
-    const int db = beta[0]->depth;
-    std::vector<Ct> xb(k);
-    std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pb;
-    for (int j = 0; j < k; ++j) {
-        xb[j] = C.at(*x[j], db);
-        pb.push_back({xb[j].get(), beta[j].get()});
-    }
-    Ct xbeta = C.msum(pb);
+    Ct xbeta = x_dot(*beta, 1.0);
     Ct tz = mul(c, *C.at(*r, w_inv->depth), *w_inv);
     Ct z = add(c, *C.at(*xbeta, tz->depth), *tz);
     // ---- z' = z - X (A (X^T z))
-    std::vector<Ct> h(k);
-    for (int j = 0; j < k; ++j) h[j] = C.rot_sum(mul(c, *C.at(*x[j], z->depth), *z));
-    const int dh = h[0]->depth;
-    std::vector<Ct> v(k);
-    for (int j = 0; j < k; ++j) {
-        std::vector<Ct> Ah(k);
-        std::vector<std::pair<const ckks_ct *, const ckks_ct *>> q;
-        for (int l = 0; l < k; ++l) {
-            Ah[l] = C.at(A(j, l), dh);
-            q.push_back({Ah[l].get(), h[l].get()});
-        }
-        v[j] = C.msum(q);
-    }
-    const int dv = v[0]->depth;
-    std::vector<Ct> xv(k);
-    std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pv;
-    for (int j = 0; j < k; ++j) {
-        xv[j] = C.at(*x[j], dv);
-        pv.push_back({xv[j].get(), v[j].get()});
-    }
-    Ct xvs = C.msum(pv);
+    Ct H = C.rot_sum(mul(c, *C.at(*Xs, z->depth), *z));
+    Ct V = a_times(parts(*H));
+    Ct xvs = x_dot(*V, 1.0);
     Ct z_proj = sub(c, *C.at(*z, xvs->depth), *xvs);
     Ct u = mul(c, *C.at(*w, z_proj->depth), *z_proj);
     // ---- r_j = (X A)_{:, j}
-    std::vector<Ct> x1(k), rr(k);
+    std::vector<Ct> x1(k);
     for (int l = 0; l < k; ++l) x1[l] = C.at(*x[l], 1);
-    for (int j = 0; j < k; ++j) {
-        std::vector<std::pair<const ckks_ct *, const ckks_ct *>> q;
-        for (int l = 0; l < k; ++l) q.push_back({A1[j * k + l].get(), x1[l].get()});
-        rr[j] = C.msum(q);
-    }
+    Ct RR = a_times(x1);
     // ---- what the per-batch part needs, at the depths it uses them
+    Ct RRs = C.at(*RR, ds), Xc = C.at(*Xs, ds + 2);
     fx.r_s.resize(k);
     fx.x_c.resize(k);
-    for (int j = 0; j < k; ++j) fx.r_s[j] = C.at(*rr[j], ds);
-    for (int j = 0; j < k; ++j) fx.x_c[j] = C.at(*x[j], ds + 2);
+    for (int j = 0; j < k; ++j) {
+        fx.r_s[j] = clone(c, *view(*RRs, j * J, J));
+        fx.x_c[j] = clone(c, *view(*Xc, j * J, J));
+        rep.beta.push_back(clone(c, *view(*beta, j * J, J)));
+    }
     fx.u_s = C.at(*u, ds + 3);
     fx.w_s = C.at(*w, ds + 3);
-    for (int j = 0; j < k; ++j) rep.beta.push_back(std::move(beta[j]));
     rep.w = std::move(w);
     rep.w_inv = std::move(w_inv);
     rep.z_proj = std::move(z_proj);

@@ -8,9 +8,19 @@
 // (index mod N2): pass "cols" runs N1-point sub-transforms down columns; the last log2(N2) stages
 // pair words of the same row of N2 contiguous words: pass "rows".  Each block stages a tile of
 // 4096 words in LDS; each thread holds 16 words in registers and runs up to four radix-2 stages on
-// them before one LDS exchange (a 256-point sub-transform is two register phases).  Butterflies
-// are lazy (Harvey): values stay in [0, 4q) (forward) or [0, 2q) (inverse) between stages and are
-// fully reduced on the way out; q < 2^62.
+// them before one LDS exchange (a 256-point sub-transform is two register phases).
+//
+// Two arithmetics, chosen per limb by its modulus:
+// * q < 2^41 (the rescale primes): FP64.  Words are integer-valued doubles with signed
+//   representatives; a product a w is split exactly into a rounded high part and its FMA error,
+//   and the quotient by q is rounded from a multiply by RN(1/q), so the remainder is exact and
+//   lies in (-1.1q, 1.1q).  Forward butterflies grow values by at most 1.1q per stage, inverse
+//   sums double per stage and are reduced once per register phase; every bound stays below 2^46
+//   so all sums and remainders are exact.  Between the two passes a limb holds the doubles' bit
+//   patterns; the last pass writes canonical residues in [0, q).
+// * otherwise (q_0, P; q < 2^62): 64-bit integers with Shoup multiplications and lazy (Harvey)
+//   butterflies: values stay in [0, 4q) (forward) or [0, 2q) (inverse) between stages and are
+//   fully reduced on the way out.
 #include <hip/hip_runtime.h>
 
 #include "modarith.h"
@@ -28,7 +38,18 @@ struct Geom {
     int log_g_cols;   // sub-transforms (columns) per cols tile
     int log_g_rows;   // sub-transforms (rows) per rows tile
     int tiles;        // tiles per limb (same for both passes)
+    int xcd_group;    // 1: place consecutive logical blocks on one XCD (see block_id)
 };
+
+// Logical block of a launch.  Workgroups are handed to the 8 XCDs round-robin (workgroup i to XCD
+// i mod 8), each with its own L2.  When several output limbs read the same source limb (ModUp,
+// rescale), xcd_group renumbers so that XCD x runs logical blocks [x nb / 8, (x + 1) nb / 8) in order:
+// the readers of one source tile then share an L2.  Needs nb divisible by 8.
+__device__ __forceinline__ int block_id(const Geom &g) {
+    const int b = blockIdx.x;
+    if (!g.xcd_group) return b;
+    return (b & 7) * (int)(gridDim.x >> 3) + (b >> 3);
+}
 
 Geom make_geom(int log_n) {
     Geom g;
@@ -40,6 +61,7 @@ Geom make_geom(int log_n) {
     g.log_g_cols = log_tile - g.log_n1;
     g.log_g_rows = log_tile - g.log_n2;
     g.tiles = 1 << (log_n - log_tile);
+    g.xcd_group = 0;
     return g;
 }
 
@@ -108,6 +130,74 @@ __device__ __forceinline__ void phase(u64 (&v)[kPer], int q, int base_off, const
     }
 }
 
+// ---------------------------------------------------------------- FP64 arithmetic (q < 2^41)
+struct FMod {
+    double q, qinv;
+};
+
+// a w mod q as a signed representative in (-1.1q, 1.1q), exact; a, w integers, |a| < 2^47, 0 <= w < q
+__device__ __forceinline__ double fmul_mod(double a, double w, FMod m) {
+#pragma clang fp contract(off)
+    const double h = a * w;
+    const double l = __builtin_fma(a, w, -h);         // a w = h + l exactly
+    const double qt = __builtin_rint(h * m.qinv);
+    const double r = __builtin_fma(-qt, m.q, h);      // integer of magnitude < q: exact
+    return r + l;
+}
+
+// signed reduction of an integer |x| < 2^52 to (-0.6q, 0.6q)
+__device__ __forceinline__ double fred(double x, FMod m) {
+#pragma clang fp contract(off)
+    const double qt = __builtin_rint(x * m.qinv);
+    return __builtin_fma(-qt, m.q, x);
+}
+
+// canonical residue in [0, q) of an integer |x| < 2^52, as a 64-bit word
+__device__ __forceinline__ u64 fcanon(double x, FMod m) {
+#pragma clang fp contract(off)
+    const double qt = __builtin_floor(x * m.qinv);
+    double r = __builtin_fma(-qt, m.q, x);
+    r = r < 0.0 ? r + m.q : r;
+    r = r >= m.q ? r - m.q : r;
+    return (u64)r;
+}
+
+template <bool INV, int LOGM, int S0, int R>
+__device__ __forceinline__ void fphase(double (&v)[kPer], int q, int base_off, const double *__restrict__ W, FMod m) {
+#pragma clang fp contract(off)
+    constexpr int LOG_TMIN = LOGM - S0 - R;
+    constexpr int GPT = kPer >> R;
+#pragma unroll
+    for (int jg = 0; jg < GPT; ++jg) {
+        const int gam = q + (jg << (LOGM - 4));
+        const int hi = gam >> LOG_TMIN, lo = gam & ((1 << LOG_TMIN) - 1);
+        const int base_idx = (hi << (LOGM - S0)) + lo;
+#pragma unroll
+        for (int uu = 0; uu < R; ++uu) {
+            const int u = INV ? R - 1 - uu : uu;
+            const int s = S0 + u;
+            const int half = 1 << (R - 1 - u);
+            const int log_t = LOGM - s - 1;
+#pragma unroll
+            for (int k = 0; k < (1 << R); ++k) {
+                if (k & half) continue;
+                const int e0 = jg * (1 << R) + k, e1 = e0 + half;
+                const int idx = base_idx + (k << LOG_TMIN);
+                const double w = W[(base_off << s) + (idx >> (log_t + 1))];
+                const double a = v[e0], b = v[e1];
+                if (!INV) {
+                    const double t = fmul_mod(b, w, m);
+                    v[e0] = a + t;
+                    v[e1] = a - t;
+                } else {
+                    v[e0] = a + b;
+                    v[e1] = fmul_mod(a - b, w, m);
+                }
+            }
+        }
+    }
+}
+
 template <int LOGM, int PH>
 struct Ph {
     static constexpr int S0 = PH * 4;
@@ -115,8 +205,8 @@ struct Ph {
 };
 
 // LDS exchange: registers laid out for phase FROM -> LDS -> registers laid out for phase TO
-template <bool ROWS, int LOGM, int FROM, int TO>
-__device__ __forceinline__ void exchange(u64 (&v)[kPer], u64 *sh, int gi, int q, int log_g) {
+template <bool ROWS, int LOGM, int FROM, int TO, typename T>
+__device__ __forceinline__ void exchange(T (&v)[kPer], T *sh, int gi, int q, int log_g) {
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < kPer; ++e)
@@ -133,14 +223,16 @@ __device__ __forceinline__ void exchange(u64 (&v)[kPer], u64 *sh, int gi, int q,
 template <bool INV, bool ROWS, int LOGM>
 __global__ void __launch_bounds__(kThreads) ntt_pass(u64 *__restrict__ buf, Gather in, ModMap mm,
                                                      const ModInfo *__restrict__ mods, const u64 *__restrict__ tw,
-                                                     const u64 *__restrict__ tw_sh, Geom g) {
+                                                     const u64 *__restrict__ tw_sh,
+                                                     const double *__restrict__ tw_f, Geom g) {
     __shared__ u64 sh[kTileWords + (kTileWords >> 4)];
     constexpr int NPH = (LOGM + 3) / 4;
     constexpr int FIRST = INV ? NPH - 1 : 0;
     constexpr int LAST = INV ? 0 : NPH - 1;
     const int log_tile = g.log_n < 12 ? g.log_n : 12;
-    const int limb = blockIdx.x >> (g.log_n - log_tile);
-    const int tile = blockIdx.x & (g.tiles - 1);
+    const int bid = block_id(g);
+    const int limb = bid >> (g.log_n - log_tile);
+    const int tile = bid & (g.tiles - 1);
     const int chain = chain_of(limb, mm);
     const ModInfo M = mods[chain];
     const u64 qm = M.q;
@@ -183,6 +275,7 @@ __global__ void __launch_bounds__(kThreads) ntt_pass(u64 *__restrict__ buf, Gath
         stride = g.n2;
         base_off = 1;
     }
+    const bool last_pass = INV ? !ROWS : ROWS;
     u64 v[kPer];
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
@@ -195,27 +288,61 @@ __global__ void __launch_bounds__(kThreads) ntt_pass(u64 *__restrict__ buf, Gath
         }
         v[e] = x;
     }
-    phase<INV, LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(v, q, base_off, W, Ws, qm);
-    if constexpr (NPH > 1) {
-        constexpr int P1 = INV ? NPH - 2 : 1;
-        exchange<ROWS, LOGM, FIRST, P1>(v, sh, gi, q, log_g);
-        phase<INV, LOGM, Ph<LOGM, P1>::S0, Ph<LOGM, P1>::R>(v, q, base_off, W, Ws, qm);
-        if constexpr (NPH > 2) {
-            constexpr int P2 = INV ? NPH - 3 : 2;
-            exchange<ROWS, LOGM, P1, P2>(v, sh, gi, q, log_g);
-            phase<INV, LOGM, Ph<LOGM, P2>::S0, Ph<LOGM, P2>::R>(v, q, base_off, W, Ws, qm);
-        }
-    }
-    // final scaling (inverse cols pass: N^-1) and reduction ([0, q) at the end of a transform)
-    const bool last_pass = INV ? !ROWS : ROWS;
-    const u64 q2 = 2 * qm;
+    if (M.fp) {
+        // FP64 butterflies; the first pass reads residues, the second the first pass's doubles
+        const FMod fm{M.qd, M.qinv};
+        const double *Wf = tw_f + (size_t)chain * n;
+        double f[kPer];
 #pragma unroll
-    for (int e = 0; e < kPer; ++e) {
-        u64 x = v[e];
-        if (INV && !ROWS) x = mul_shoup_lazy(x, M.ninv, M.ninv_sh, qm);
-        x = x >= q2 ? x - q2 : x;
-        if (last_pass) x = x >= qm ? x - qm : x;
-        v[e] = x;
+        for (int e = 0; e < kPer; ++e) f[e] = last_pass ? __longlong_as_double((long long)v[e]) : (double)v[e];
+        double *shf = reinterpret_cast<double *>(sh);
+        fphase<INV, LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(f, q, base_off, Wf, fm);
+        if constexpr (NPH > 1) {
+            constexpr int P1 = INV ? NPH - 2 : 1;
+            exchange<ROWS, LOGM, FIRST, P1>(f, shf, gi, q, log_g);
+            if (INV) {   // inverse sums double per stage: start each later phase from reduced words
+#pragma unroll
+                for (int e = 0; e < kPer; ++e) f[e] = fred(f[e], fm);
+            }
+            fphase<INV, LOGM, Ph<LOGM, P1>::S0, Ph<LOGM, P1>::R>(f, q, base_off, Wf, fm);
+            if constexpr (NPH > 2) {
+                constexpr int P2 = INV ? NPH - 3 : 2;
+                exchange<ROWS, LOGM, P1, P2>(f, shf, gi, q, log_g);
+                if (INV) {
+#pragma unroll
+                    for (int e = 0; e < kPer; ++e) f[e] = fred(f[e], fm);
+                }
+                fphase<INV, LOGM, Ph<LOGM, P2>::S0, Ph<LOGM, P2>::R>(f, q, base_off, Wf, fm);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            double x = f[e];
+            if (INV && !ROWS) x = fmul_mod(x, M.ninv_d, fm);
+            v[e] = last_pass ? fcanon(x, fm) : (u64)__double_as_longlong(fred(x, fm));
+        }
+    } else {
+        phase<INV, LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(v, q, base_off, W, Ws, qm);
+        if constexpr (NPH > 1) {
+            constexpr int P1 = INV ? NPH - 2 : 1;
+            exchange<ROWS, LOGM, FIRST, P1>(v, sh, gi, q, log_g);
+            phase<INV, LOGM, Ph<LOGM, P1>::S0, Ph<LOGM, P1>::R>(v, q, base_off, W, Ws, qm);
+            if constexpr (NPH > 2) {
+                constexpr int P2 = INV ? NPH - 3 : 2;
+                exchange<ROWS, LOGM, P1, P2>(v, sh, gi, q, log_g);
+                phase<INV, LOGM, Ph<LOGM, P2>::S0, Ph<LOGM, P2>::R>(v, q, base_off, W, Ws, qm);
+            }
+        }
+        // final scaling (inverse cols pass: N^-1) and reduction ([0, q) at the end of a transform)
+        const u64 q2 = 2 * qm;
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            u64 x = v[e];
+            if (INV && !ROWS) x = mul_shoup_lazy(x, M.ninv, M.ninv_sh, qm);
+            x = x >= q2 ? x - q2 : x;
+            if (last_pass) x = x >= qm ? x - qm : x;
+            v[e] = x;
+        }
     }
     if (ROWS) {
         // coalesced store through LDS, read back in the layout of the first forward phase
@@ -240,11 +367,11 @@ __global__ void __launch_bounds__(kThreads) ntt_pass(u64 *__restrict__ buf, Gath
 
 template <bool INV, bool ROWS>
 void launch_pass(int log_m, dim3 grid, dim3 block, hipStream_t st, u64 *buf, const Gather &in, ModMap m,
-                 const ModInfo *mods, const u64 *tw, const u64 *tws, Geom g) {
+                 const ModInfo *mods, const u64 *tw, const u64 *tws, const double *twf, Geom g) {
     switch (log_m) {
 #define GCK_NTT_CASE(L)                                                                             \
     case L:                                                                                         \
-        hipLaunchKernelGGL((ntt_pass<INV, ROWS, L>), grid, block, 0, st, buf, in, m, mods, tw, tws, g); \
+        hipLaunchKernelGGL((ntt_pass<INV, ROWS, L>), grid, block, 0, st, buf, in, m, mods, tw, tws, twf, g); \
         break;
         GCK_NTT_CASE(5)
         GCK_NTT_CASE(6)
@@ -268,23 +395,25 @@ static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, 
     dim3 block((unsigned)((1 << log_tile) / kPer));
     const double bytes = 16.0 * (double)n_limbs * t.n;
     const Gather none{nullptr, 1, 1, 0, 0, kPlain, 0};
+    Geom g1 = g;   // first pass: group the readers of a shared source limb on one XCD
+    g1.xcd_group = (in.ptr && in.div > 1 && in.inner == 0 && grid.x % 8 == 0) ? 1 : 0;
     if (!inv) {
         {
             TScope ts_(t, in.ptr ? (in.mode == kPlain ? "ntt_fwd_cols" : "ntt_fwd_cols_lift") : "ntt_fwd_cols", bytes, st);
-            launch_pass<false, false>(g.log_n1, grid, block, st, buf, in, m, t.mods, t.psi, t.psi_sh, g);
+            launch_pass<false, false>(g.log_n1, grid, block, st, buf, in, m, t.mods, t.psi, t.psi_sh, t.psi_f, g1);
         }
         {
             TScope ts_(t, "ntt_fwd_rows", bytes, st);
-            launch_pass<false, true>(g.log_n2, grid, block, st, buf, none, m, t.mods, t.psi, t.psi_sh, g);
+            launch_pass<false, true>(g.log_n2, grid, block, st, buf, none, m, t.mods, t.psi, t.psi_sh, t.psi_f, g);
         }
     } else {
         {
             TScope ts_(t, "ntt_inv_rows", bytes, st);
-            launch_pass<true, true>(g.log_n2, grid, block, st, buf, in, m, t.mods, t.ipsi, t.ipsi_sh, g);
+            launch_pass<true, true>(g.log_n2, grid, block, st, buf, in, m, t.mods, t.ipsi, t.ipsi_sh, t.ipsi_f, g1);
         }
         {
             TScope ts_(t, "ntt_inv_cols", bytes, st);
-            launch_pass<true, false>(g.log_n1, grid, block, st, buf, none, m, t.mods, t.ipsi, t.ipsi_sh, g);
+            launch_pass<true, false>(g.log_n1, grid, block, st, buf, none, m, t.mods, t.ipsi, t.ipsi_sh, t.ipsi_f, g);
         }
     }
     check_launch();

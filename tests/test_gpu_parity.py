@@ -56,6 +56,44 @@ def rand_ct(p, depth, rng):
     return np.stack([np.stack([rng.integers(0, q, size=p.N, dtype=np.uint64) for q in p.q[:l]]) for _ in range(2)])
 
 
+@pytest.mark.parametrize("log_n", [10, 11, 12, 13, 16, 17])
+def test_ntt_negacyclic_products_match_oracle(torch_dev, log_n):
+    """Forward NTT, pointwise product, inverse NTT on the GPU equals the oracle's negacyclic product,
+    for every modulus kind (q_0 of 60 bits, rescale primes of 40 bits, P of 62 bits), every sub-transform
+    size the two-pass NTT uses, random residues and the all-(q - 1) worst case; inverse(forward(a)) == a."""
+    say("[gpu] ntt log_n=%d" % log_n)
+    ctx = P.Context(log_n, 3, 40)
+    p = C.make_params(log_n, 3, 40)
+    o = C.Oracle(p)
+    N = p.N
+    rng = np.random.default_rng(log_n)
+    dev = torch_dev.device("cuda:0")
+
+    def run(x, mi, direction):
+        t = torch_dev.from_numpy(x.view(np.int64).copy()).to(dev)
+        ctx.ntt_device(t.data_ptr(), x.shape[0], [mi] * x.shape[0], direction)
+        torch_dev.cuda.synchronize()
+        return t.cpu().numpy().view(np.uint64)
+
+    for mi, q in enumerate(o.mods):
+        for case in ("random", "max"):
+            if case == "random":
+                a = rng.integers(0, q, size=N, dtype=np.uint64)
+                b = rng.integers(0, q, size=N, dtype=np.uint64)
+            else:
+                a = np.full(N, q - 1, dtype=np.uint64)
+                b = np.full(N, q - 1, dtype=np.uint64)
+            ev = run(np.stack([a, b]), mi, 1)
+            assert int(ev.max()) < q
+            assert np.array_equal(run(ev.copy(), mi, -1), np.stack([a, b])), (mi, case)
+            prod = ((ev[0].astype(object) * ev[1].astype(object)) % q).astype(np.uint64)
+            got = run(prod[None, :].copy(), mi, -1)[0]
+            want = np.zeros(N, dtype=np.uint64)
+            C.lib().ref_polymul(o._ctx, mi, C._p(a), C._p(b), C._p(want))
+            assert np.array_equal(got, want), (mi, case)
+    ctx.close()
+
+
 def test_keys_match_oracle(small):
     ctx, o, p = small
     assert np.array_equal(ctx.export_secret(), o.sk)
