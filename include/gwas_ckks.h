@@ -173,6 +173,10 @@ int ckks_rescale(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out);
 int ckks_align(ckks_ctx *ctx, const ckks_ct *a, int depth, double scale, double factor, ckks_ct **out);
 /* Rotate (paper: Rotate) by r slots: slot j of the result holds slot j + r. */
 int ckks_rotate(ckks_ctx *ctx, const ckks_ct *a, int64_t r, ckks_ct **out);
+/* a + sum_i Rotate(a, rots[i]) for 1 <= n <= 8 rotations sharing one key switch: one decomposition of
+ * c1 (each digit permuted by its rotation after the basis extension) and one division by P for the sum
+ * (a grouped step of Alg. colSum).  Needs the Galois key of every rotation. */
+int ckks_rotate_sum(ckks_ctx *ctx, const ckks_ct *a, const int64_t *rots, int n, ckks_ct **out);
 /* Complex conjugation of every slot. */
 int ckks_conjugate(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out);
 /* Multiply by the block-start mask (1 at slots = 0 mod R) encoded at a's scale s,
@@ -190,6 +194,11 @@ int ckks_ntt_device(ckks_ctx *ctx, uint64_t *dev_limbs, int count, const int *mo
  * Circuit depth: L must equal 7 kappa + 5 (kappa >= 2 Newton passes). */
 int gwas_layout(const ckks_ctx *ctx, int n, int k, int m, int kappa, int *R, int *tau, int *n_batches,
                 int *levels_needed);
+
+/* Host only: the Galois elements whose keys the circuit needs for block size R at ring degree 2^log_n
+ * (the rotations of the grouped rotate-and-sum in both directions, then conjugation).  Writes at most
+ * cap elements to out and the number needed to *count. */
+int gwas_galois_elements(int log_n, int R, uint64_t *out, int cap, int *count);
 
 /* Client side: compute A = (X^T X)^-1 in FP64, encode and encrypt x_j (R-periodic,
  * depth 0), y (depth 0), A_jl for j <= l (replicated, depth 0, scale R Delta_0)
@@ -226,6 +235,9 @@ int gwas_finalize(ckks_ctx *ctx, const gwas_enc_output *out, int m, double *b, d
  * recording; 0 stops.  The report is text, one line per kernel:
  * "name launches total_ms algorithmic_bytes". */
 int ckks_ctx_kernel_timing(ckks_ctx *ctx, int enable);
+/* Restrict recording to launches of one kernel name (as it appears in the report), so that timing a
+ * single kernel adds two event records per launch of that kernel only; NULL or "" records all. */
+int ckks_ctx_kernel_timing_only(ckks_ctx *ctx, const char *name);
 int ckks_ctx_kernel_report(ckks_ctx *ctx, char *buf, size_t cap);
 
 /* ---------------------------------------------------------------- batched and serving forms

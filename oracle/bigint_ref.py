@@ -231,6 +231,39 @@ class BigCKKS:
             acc1 = polyadd(acc1, t1, QP)
         return round_div(acc0, QP, self.P, Ql), round_div(acc1, QP, self.P, Ql)
 
+    def keyswitch_galois(self, d: Sequence[int], key_list, l: int):
+        """round( sum_i sum_{j < l} sigma_{g_i}([d]_{q_j}) * ksk_{i,j} / P ) mod Q_l for key_list = [(g_i, keys_i)]:
+        each digit, an integer polynomial with coefficients in [0, q_j), is permuted by X -> X^{g_i}
+        (g_i = 0: not permuted) before the product; one division by P for the whole sum."""
+        Ql = self.Q(l)
+        QP = Ql * self.P
+        acc0 = [0] * self.N
+        acc1 = [0] * self.N
+        for g, keys in key_list:
+            for j in range(l):
+                dj = [v % self.q[j] for v in d]
+                if g:
+                    dj = automorph(dj, g, QP)
+                b, a = keys[j]
+                acc0 = polyadd(acc0, polymul(dj, [v % QP for v in b], QP), QP)
+                acc1 = polyadd(acc1, polymul(dj, [v % QP for v in a], QP), QP)
+        return round_div(acc0, QP, self.P, Ql), round_div(acc1, QP, self.P, Ql)
+
+    def apply_galois(self, ct, g: int, keys, l: int):
+        """(sigma_g(c0), 0) + key switch of sigma_g(c1) from sigma_g(s) back to s."""
+        Ql = self.Q(l)
+        ks = self.keyswitch_galois(ct[1], [(g, keys)], l)
+        return polyadd(automorph(ct[0], g, Ql), ks[0], Ql), ks[1]
+
+    def rotate_sum(self, ct, key_list, l: int):
+        """ct + sum_i sigma_{g_i}(ct), the key switches of all g_i sharing one division by P."""
+        Ql = self.Q(l)
+        ks = self.keyswitch_galois(ct[1], key_list, l)
+        c0 = list(ct[0])
+        for g, _ in key_list:
+            c0 = polyadd(c0, automorph(ct[0], g, Ql), Ql)
+        return polyadd(c0, ks[0], Ql), polyadd(ct[1], ks[1], Ql)
+
     def rescale(self, ct, l: int):
         Ql = self.Q(l)
         ql = self.q[l - 1]

@@ -86,8 +86,8 @@ def lib():
         L.ref_tensor.argtypes = [ctypes.c_void_p, ctypes.c_int, _u64p, _u64p, _u64p, ctypes.c_int]
         L.ref_rescale.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _u64p, _u64p]
         L.ref_automorph.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _u64p, ctypes.c_uint64, _u64p]
-        L.ref_keyswitch.argtypes = [ctypes.c_void_p, ctypes.c_int, _u64p, _u64p, ctypes.c_int, ctypes.c_int,
-                                    ctypes.c_int, _u64p]
+        L.ref_keyswitch.argtypes = [ctypes.c_void_p, ctypes.c_int, _u64p, ctypes.c_int, _u64p,
+                                    ctypes.POINTER(_u64p), ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64p]
         L.ref_gen_ksk.argtypes = [ctypes.c_void_p, ctypes.c_int, _i64p, _u64p, ctypes.c_uint64, ctypes.c_uint64,
                                   ctypes.c_int, _u64p]
         L.ref_key_to_eval.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64p,
@@ -579,12 +579,22 @@ class Oracle:
 
     def keyswitch(self, d: np.ndarray, K: int) -> np.ndarray:
         """round(sum_j [d]_{q_j} * ksk_j / P) for the key with id K; d is [l][N]."""
+        return self.keyswitch_galois(d, [(0, K)])
+
+    def keyswitch_galois(self, d: np.ndarray, pairs: Sequence[Tuple[int, int]]) -> np.ndarray:
+        """round(sum_i sum_j sigma_{g_i}([d]_{q_j}) * ksk_{K_i, j} / P) for pairs (g_i, K_i); d is [l][N].
+
+        One decomposition of d serves every key: each digit is lifted to the target moduli first and
+        then permuted by its automorphism (g = 0: none), and all products are summed before the single
+        division by P."""
         l = d.shape[0]
         if l > self._max_l:
             raise ValueError("keys were generated for at most %d limbs" % self._max_l)
         p = self.p
         out = np.zeros((2, l, p.N), dtype=np.uint64)
-        lib().ref_keyswitch(self._ctx, l, _p(np.ascontiguousarray(d)), _p(self._kev[K]), p.L + 1, p.L + 2,
+        gal = np.array([g for g, _ in pairs], dtype=np.uint64)
+        kevs = (_u64p * len(pairs))(*[_p(self._kev[K]) for _, K in pairs])
+        lib().ref_keyswitch(self._ctx, l, _p(np.ascontiguousarray(d)), len(pairs), _p(gal), kevs, p.L + 1, p.L + 2,
                             self.pidx, _p(out))
         self.n_keyswitch += 1
         return out
@@ -628,12 +638,32 @@ class Oracle:
         return Ct(out, a.depth, a.scale)
 
     def apply_galois(self, a: Ct, g: int) -> Ct:
-        """Automorphism then key switch back to s (Rotate / conjugate)."""
-        t = self.automorph(a, g)
-        ks = self.keyswitch(t.data[1], g)
-        c0 = np.empty((1, t.limbs, self.p.N), dtype=np.uint64)
-        lib().ref_add(self._ctx, 1, t.limbs, _p(np.ascontiguousarray(t.data[0])), _p(np.ascontiguousarray(ks[0])), _p(c0))
-        return Ct(np.ascontiguousarray(np.stack([c0[0], ks[1]])), a.depth, a.scale)
+        """The automorphism X -> X^g switched back to s (Rotate / conjugate): c0 is permuted, and the
+        key switch of sigma_g(c1) permutes the lifted digits of c1 (keyswitch_galois)."""
+        c0 = self.automorph(a, g).data[0]
+        ks = self.keyswitch_galois(a.data[1], [(g, g)])
+        out = np.empty((1, a.limbs, self.p.N), dtype=np.uint64)
+        lib().ref_add(self._ctx, 1, a.limbs, _p(np.ascontiguousarray(c0)), _p(np.ascontiguousarray(ks[0])), _p(out))
+        return Ct(np.ascontiguousarray(np.stack([out[0], ks[1]])), a.depth, a.scale)
+
+    def rotate_sum(self, a: Ct, rots: Sequence[int]) -> Ct:
+        """a + sum_i Rot(a, r_i) with one key switch: the rotations share the decomposition of c1 and
+        the division by P (keyswitch_galois over all of them)."""
+        N, l = self.p.N, a.limbs
+        gs = [galois_rotate(N, r) for r in rots]
+        ks = self.keyswitch_galois(a.data[1], [(g, g) for g in gs])
+        c0 = np.ascontiguousarray(a.data[0:1])
+        for g in gs:
+            t = self.automorph(a, g)
+            nxt = np.empty_like(c0)
+            lib().ref_add(self._ctx, 1, l, _p(c0), _p(np.ascontiguousarray(t.data[0:1])), _p(nxt))
+            c0 = nxt
+        out = np.empty((2, l, N), dtype=np.uint64)
+        lib().ref_add(self._ctx, 1, l, _p(c0), _p(np.ascontiguousarray(ks[0:1])), _p(out[0:1]))
+        o1 = np.empty((1, l, N), dtype=np.uint64)
+        lib().ref_add(self._ctx, 1, l, _p(np.ascontiguousarray(a.data[1:2])), _p(np.ascontiguousarray(ks[1:2])), _p(o1))
+        out[1] = o1[0]
+        return Ct(out, a.depth, a.scale)
 
     def rotate(self, a: Ct, r: int) -> Ct:
         """Slot j of the result holds slot j + r of a."""

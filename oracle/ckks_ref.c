@@ -388,21 +388,35 @@ void ref_automorph(const ref_ctx *c, int npoly, int l, const u64 *in, u64 g, u64
 }
 
 /*
- * Key switching of the polynomial d (coefficient form, limbs 0..l-1) with a key
- * given in the oracle's evaluation form: kev[comp][j][t][N] for digits j < nd and
- * targets t < nt where target index t < nq is q_t and t == nq is the special prime.
- * The key stores targets 0..L and P (nt = L + 2), digits 0..L.
- * Output: out[2][l][N] = round( sum_{j<l} [d]_{q_j} * ksk_j / P ) mod q_0..q_{l-1}.
+ * Key switching of the polynomial d (coefficient form, limbs 0..l-1) with one or
+ * several keys, each given in the oracle's evaluation form: kevs[i][comp][j][t][N]
+ * for digits j < nd and targets t < nt where target index t < nq is q_t and
+ * t == nq is the special prime.  A key stores targets 0..L and P (nt = L + 2),
+ * digits 0..L.  Key i is paired with the automorphism X -> X^galois[i] of the
+ * digits (galois[i] == 0: none), applied after each digit [d]_{q_j} has been
+ * lifted to the target modulus; the products of all keys are summed before the
+ * single division by P (one decomposition of d serves every key):
+ *   out[2][l][N] = round( sum_i sum_{j<l} sigma_i([d]_{q_j}) * ksk_{i,j} / P ) mod q_0..q_{l-1}.
  */
-void ref_keyswitch(const ref_ctx *c, int l, const u64 *d, const u64 *kev, int nd, int nt,
-                   int pidx, u64 *out) {
+static void automorph_poly(int n, u64 q, const u64 *a, u64 g, u64 *o) {
+    u64 twon = 2ULL * (u64)n;
+    for (int k = 0; k < n; ++k) {
+        u64 e = ((u64)k * g) % twon;
+        if (e < (u64)n) o[e] = a[k];
+        else o[e - n] = a[k] ? q - a[k] : 0;
+    }
+}
+
+void ref_keyswitch(const ref_ctx *c, int l, const u64 *d, int n_keys, const u64 *galois, const u64 *const *kevs,
+                   int nd, int nt, int pidx, u64 *out) {
     int n = c->n;
     size_t kstride_t = (size_t)n, kstride_j = (size_t)nt * n, kstride_c = (size_t)nd * nt * n;
     /* accumulate, per target modulus, both components in evaluation form */
     u64 *acc = (u64 *)calloc((size_t)2 * (l + 1) * n, sizeof(u64));
 #pragma omp parallel
     {
-        u64 *dig = (u64 *)malloc(sizeof(u64) * n), *fe = (u64 *)malloc(sizeof(u64) * n);
+        u64 *dig = (u64 *)malloc(sizeof(u64) * n), *sg = (u64 *)malloc(sizeof(u64) * n),
+            *fe = (u64 *)malloc(sizeof(u64) * n);
 #pragma omp for schedule(dynamic)
         for (int ti = 0; ti <= l; ++ti) {
             int mi = ti < l ? ti : pidx;         /* modulus of this target */
@@ -412,18 +426,25 @@ void ref_keyswitch(const ref_ctx *c, int l, const u64 *d, const u64 *kev, int nd
             for (int j = 0; j < l; ++j) {
                 const u64 *dj = d + (size_t)j * n;
                 for (int k = 0; k < n; ++k) dig[k] = dj[k] % q;  /* [d]_{q_j} lifted to q */
-                ref_to_eval(c, mi, dig, fe);
-                const u64 *k0 = kev + 0 * kstride_c + j * kstride_j + tk * kstride_t;
-                const u64 *k1 = kev + 1 * kstride_c + j * kstride_j + tk * kstride_t;
-                for (int k = 0; k < n; ++k) {
-                    a0[k] = addmod(a0[k], mulmod(fe[k], k0[k], q), q);
-                    a1[k] = addmod(a1[k], mulmod(fe[k], k1[k], q), q);
+                for (int i = 0; i < n_keys; ++i) {
+                    if (galois[i]) {
+                        automorph_poly(n, q, dig, galois[i], sg);
+                        ref_to_eval(c, mi, sg, fe);
+                    } else {
+                        ref_to_eval(c, mi, dig, fe);
+                    }
+                    const u64 *k0 = kevs[i] + 0 * kstride_c + j * kstride_j + tk * kstride_t;
+                    const u64 *k1 = kevs[i] + 1 * kstride_c + j * kstride_j + tk * kstride_t;
+                    for (int k = 0; k < n; ++k) {
+                        a0[k] = addmod(a0[k], mulmod(fe[k], k0[k], q), q);
+                        a1[k] = addmod(a1[k], mulmod(fe[k], k1[k], q), q);
+                    }
                 }
             }
             ref_from_eval(c, mi, a0, a0);
             ref_from_eval(c, mi, a1, a1);
         }
-        free(dig); free(fe);
+        free(dig); free(sg); free(fe);
     }
     /* ModDown: round(x / P) = (x - [x]_P centred) / P */
     u64 P = c->mods[pidx].q;

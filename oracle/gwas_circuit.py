@@ -7,8 +7,12 @@ Alg. "inverseSlots") step by step on oracle ciphertexts.  Layouts:
 * Per-sample vectors (covariate columns x_j, y) are R-periodic: slot s holds
   v[s mod R] when s mod R < n, else 0 — a CP column (Methods, "Column-Packed
   Matrices") already duplicated into every block (Alg. Duplicate done by the
-  client).  On such data the rotate-and-sum of Alg. DotProd over log2(R) left
-  rotations leaves the full dot product in every slot.
+  client).  On such data the rotate-and-sum of Alg. DotProd leaves the full dot
+  product in every slot.  The rotate-and-sum adds Rot(a, i) for every i < R; it
+  is taken as groups a <- a + Rot(a, s) + Rot(a, 2s) + Rot(a, 3s), s = 1, 4, 16, ...
+  (one shared key switch per group, Oracle.rotate_sum), which sums the same
+  rotations as the log2(R) doubling steps of Alg. colSum with half the key-switch
+  decompositions.
 * Entries of A = (X^T X)^-1 are replicated scalars (the same value in every slot).
 * A SNP batch is a CCP matrix (Methods, "Column-Compact-Packed Matrices") with
   two SNPs per complex slot (Methods, "Complex Space of CKKS ciphertext"):
@@ -180,14 +184,29 @@ def encrypt_inputs(o: C.Oracle, pts: Plaintexts, n: int, k: int, m: int, kappa: 
     return EncInput(lay=lay, kappa=kappa, x=x, y=yc, A=A, S=S)
 
 
-def required_galois(N: int, R: int) -> List[int]:
-    """Left and right power-of-two rotations below R (Methods, power-of-two rotations) and conjugation."""
+def rotation_groups(R: int) -> List[List[int]]:
+    """The left rotations of a rotate-and-sum over R = 2^r slots, grouped by shared key switch: each
+    group {s, 2s, 3s} (s = 1, 4, 16, ...) replaces two doubling steps a <- a + Rot(a, s), a <- a + Rot(a, 2s)
+    of Alg. colSum by a <- a + Rot(a, s) + Rot(a, 2s) + Rot(a, 3s), and a last group {s} covers an odd r."""
     out = []
-    i = 1
-    while i < R:
-        out.append(C.galois_rotate(N, i))
-        out.append(C.galois_rotate(N, -i))
-        i *= 2
+    s = 1
+    while s < R:
+        if 4 * s <= R:
+            out.append([s, 2 * s, 3 * s])
+            s *= 4
+        else:
+            out.append([s])
+            s *= 2
+    return out
+
+
+def required_galois(N: int, R: int) -> List[int]:
+    """Galois elements of the left and right rotations of rotation_groups(R) and of conjugation."""
+    out = []
+    for grp in rotation_groups(R):
+        for r in grp:
+            out.append(C.galois_rotate(N, r))
+            out.append(C.galois_rotate(N, -r))
     out.append(C.galois_conj(N))
     return out
 
@@ -228,21 +247,15 @@ class Circuit:
         return self.o.align(a, d, self.sc[d], factor)
 
     def rot_sum(self, a: C.Ct) -> C.Ct:
-        """a <- a + Rot(a, 2^i) for i < log2 R (Alg. colSum / Alg. DotProd)."""
-        o = self.o
-        i = 1
-        while i < self.lay.R:
-            a = o.add(a, o.rotate(a, i))
-            i *= 2
+        """sum_{i < R} Rot(a, i) (Alg. colSum / Alg. DotProd), by the groups of rotation_groups(R)."""
+        for grp in rotation_groups(self.lay.R):
+            a = self.o.rotate_sum(a, grp)
         return a
 
     def bcast(self, a: C.Ct) -> C.Ct:
-        """a <- a + Rot(a, -2^i) for i < log2 R: copies each block's first slot over its block."""
-        o = self.o
-        i = 1
-        while i < self.lay.R:
-            a = o.add(a, o.rotate(a, -i))
-            i *= 2
+        """sum_{i < R} Rot(a, -i): copies each block's first slot over its block."""
+        for grp in rotation_groups(self.lay.R):
+            a = self.o.rotate_sum(a, [-r for r in grp])
         return a
 
     def sigma7(self, u: C.Ct) -> C.Ct:

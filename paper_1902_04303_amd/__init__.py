@@ -14,5 +14,6 @@ from ._binding import (  # noqa: F401
     LIB_PATH,
     chain,
     exported_symbols,
+    gwas_galois_elements,
     lib,
 )

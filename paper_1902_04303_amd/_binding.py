@@ -73,6 +73,7 @@ _SIGS = [
     ("ckks_ctx_pool_trim", ctypes.c_int, [_vp]),
     ("ckks_ctx_kernel_timing", ctypes.c_int, [_vp, ctypes.c_int]),
     ("ckks_ctx_kernel_report", ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
+    ("ckks_ctx_kernel_timing_only", ctypes.c_int, [_vp, ctypes.c_char_p]),
     ("ckks_ctx_counters", ctypes.c_int, [_vp, _u64p, _u64p, _u64p]),
     ("ckks_keygen", ctypes.c_int, [_vp, ctypes.c_uint64, _u64p, ctypes.c_int]),
     ("ckks_galois_rotate", ctypes.c_uint64, [_vp, ctypes.c_int64]),
@@ -99,6 +100,9 @@ _SIGS = [
     ("ckks_rescale", ctypes.c_int, [_vp, _vp, ctypes.POINTER(_vp)]),
     ("ckks_align", ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.POINTER(_vp)]),
     ("ckks_rotate", ctypes.c_int, [_vp, _vp, ctypes.c_int64, ctypes.POINTER(_vp)]),
+    ("ckks_rotate_sum", ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.POINTER(_vp)]),
+    ("gwas_galois_elements", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_int)]),
     ("ckks_conjugate", ctypes.c_int, [_vp, _vp, ctypes.POINTER(_vp)]),
     ("ckks_mul_mask", ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(_vp)]),
     ("ckks_ntt_device", ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
@@ -177,6 +181,15 @@ def chain(log_n: int, levels: int, log2_scale: int):
     s = np.zeros(levels + 1, dtype=np.float64)
     _check(lib().ckks_chain(ctypes.byref(p), _u64(q), _f64(s)))
     return [int(v) for v in q[:-1]], int(q[-1]), [float(v) for v in s]
+
+
+def gwas_galois_elements(log_n: int, R: int) -> List[int]:
+    """Galois elements whose switching keys the GWAS circuit needs for block size R (host computation)."""
+    cnt = ctypes.c_int()
+    _check(lib().gwas_galois_elements(log_n, R, None, 0, ctypes.byref(cnt)))
+    out = (ctypes.c_uint64 * cnt.value)()
+    _check(lib().gwas_galois_elements(log_n, R, out, cnt.value, ctypes.byref(cnt)))
+    return [int(v) for v in out]
 
 
 class Ciphertext:
@@ -295,6 +308,9 @@ class Context:
     def kernel_timing(self, enable: bool):
         _check(lib().ckks_ctx_kernel_timing(self.h, 1 if enable else 0))
 
+    def kernel_timing_only(self, name: Optional[str]):
+        _check(lib().ckks_ctx_kernel_timing_only(self.h, name.encode() if name else None))
+
     def kernel_report(self):
         """{kernel: (launches, total_ms, algorithmic_bytes)} from the HIP-event timing."""
         buf = ctypes.create_string_buffer(1 << 16)
@@ -402,6 +418,11 @@ class Context:
 
     def rotate(self, a, r: int):
         return self._op(lib().ckks_rotate, a.h, int(r))
+
+    def rotate_sum(self, a, rots: Sequence[int]):
+        """a + sum_i rotate(a, rots[i]) with one shared key switch (1 to 8 rotations)."""
+        arr = (ctypes.c_int64 * len(rots))(*[int(r) for r in rots])
+        return self._op(lib().ckks_rotate_sum, a.h, arr, len(rots))
 
     def conjugate(self, a):
         return self._op(lib().ckks_conjugate, a.h)

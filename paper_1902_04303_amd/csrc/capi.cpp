@@ -222,6 +222,14 @@ int ckks_ctx_kernel_timing(ckks_ctx *ctx, int enable) {
     });
 }
 
+int ckks_ctx_kernel_timing_only(ckks_ctx *ctx, const char *name) {
+    return guard_ctx(ctx, [&] {
+        need(ctx, "null context");
+        ctx->timer.collect();
+        ctx->timer.only = name ? name : "";
+    });
+}
+
 int ckks_ctx_kernel_report(ckks_ctx *ctx, char *buf, size_t cap) {
     return guard_ctx(ctx, [&] {
         need(ctx && buf && cap > 0, "bad buffer");
@@ -439,6 +447,14 @@ int ckks_rotate(ckks_ctx *ctx, const ckks_ct *a, int64_t r, ckks_ct **out) {
     });
 }
 
+int ckks_rotate_sum(ckks_ctx *ctx, const ckks_ct *a, const int64_t *rots, int n, ckks_ct **out) {
+    return guard_ctx(ctx, [&] {
+        check_ct(ctx, a);
+        need(out && rots && n >= 1 && n <= kMaxKeys, "need 1 to 8 rotations and an output");
+        *out = release(rotate_sum(*ctx, *a, std::vector<i64>(rots, rots + n)));
+    });
+}
+
 int ckks_mul_mask(ckks_ctx *ctx, const ckks_ct *a, int R, ckks_ct **out) {
     return guard_ctx(ctx, [&] {
         check_ct(ctx, a);
@@ -457,6 +473,16 @@ int ckks_ntt_device(ckks_ctx *ctx, uint64_t *dev_limbs, int count, const int *mo
             if (dir == 1) ntt_fwd(*ctx, dev_limbs + (size_t)i * ctx->p.n, 1, m);
             else ntt_inv(*ctx, dev_limbs + (size_t)i * ctx->p.n, 1, m);
         }
+    });
+}
+
+int gwas_galois_elements(int log_n, int R, uint64_t *out, int cap, int *count) {
+    return guard([&] {
+        need(log_n >= 1 && log_n <= 17 && R >= 1 && 2 * R <= (1 << log_n) && count, "bad arguments");
+        const std::vector<u64> g = required_galois(1 << log_n, R);
+        *count = (int)g.size();
+        need(out || cap == 0, "null output");
+        for (int i = 0; i < cap && i < (int)g.size(); ++i) out[i] = g[i];
     });
 }
 

@@ -119,6 +119,7 @@ inline ModMap map_q(int l) { return ModMap{l, l, 0}; }
 // Optional per-kernel timing with HIP events on the launching stream (off by default).
 struct KTimer {
     bool on = false;
+    std::string only;   // when not empty, only launches of this name are recorded
     struct Rec {
         int id;
         hipEvent_t a, b;
@@ -203,10 +204,21 @@ void k_modup(const DevTables &t, u64 *out, const u64 *in, int count, int l, int 
 // out = (a - b) * c[chain]  (+ out when add_to_out)
 void k_sub_mul_const(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m,
                      const ChainConst &c, bool add_to_out, hipStream_t st);
-// key-switch inner product: acc[c][comp][t] = sum_{j<l} digit[c][j][t] * key[comp][j][kt], kt = t (t<l) or L+1;
-// key words are in Montgomery form (times 2^64)
-void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, const u64 *key, int count, int l, int levels,
+// Keys of one key-switch inner product: key i is paired with the NTT-domain automorphism X -> X^g[i] of
+// the digits (g[i] == 0: none).
+constexpr int kMaxKeys = 8;
+struct KsKeys {
+    const u64 *key[kMaxKeys];
+    u64 g[kMaxKeys];
+    int m;
+};
+// key-switch inner product: acc[c][comp][t] = sum_i sum_{j<l} sigma_i(digit[c][j][t]) * key_i[comp][j][kt],
+// kt = t (t<l) or L+1; key words are in Montgomery form (times 2^64)
+void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, const KsKeys &keys, int count, int l, int levels,
                 hipStream_t st);
+// out c0 rows = (accumulate ? out c0 : 0) + sum_i sigma_{g[i]}(a c0) for [count][2][l] batches (c1 rows untouched)
+void k_automorph_c0(const DevTables &t, u64 *out, const u64 *a, int count, int l, const KsKeys &gs, bool accumulate,
+                    hipStream_t st);
 // samplers of the test-only SplitMix64 streams
 void k_sample_uniform(const DevTables &t, u64 *out, u64 seed, u64 sid, int n_limbs, ModMap m, int mi_of_p,
                       hipStream_t st);

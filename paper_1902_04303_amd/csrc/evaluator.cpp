@@ -309,12 +309,22 @@ Ct set_scale(ckks_ctx &, Ct a, double factor) {
 
 bool has_key(const ckks_ctx &c, u64 id) { return c.ksk.count(id) != 0; }
 
-// Key switch of the digits gathered by `d` (count ciphertexts, l limbs, NTT form) with key `id`:
-// round(sum_j [d]_{q_j} ksk_j / P), plus the gathered `add` term (on every row, or on the first
-// polynomial of each ciphertext when add_even).  Output [count][2][l][N] in NTT form.
-static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, u64 id, const Gather &add, bool add_even) {
+static const u64 *key_of(const ckks_ctx &c, u64 id) {
     auto it = c.ksk.find(id);
-    if (it == c.ksk.end()) throw Error(CKKS_E_KEY_MISSING, "missing switching key " + std::to_string(id));
+    if (it == c.ksk.end()) {
+        if (id == 0) throw Error(CKKS_E_KEY_MISSING, "missing relinearisation key");
+        throw Error(CKKS_E_KEY_MISSING, "missing Galois key for element " + std::to_string(id));
+    }
+    return it->second.ptr;
+}
+
+// Key switch of the digits gathered by `d` (count ciphertexts, l limbs, NTT form) with the keys of
+// `keys`: round(sum_i sum_j sigma_i([d]_{q_j}) ksk_{i,j} / P), one decomposition (ModUp) and one
+// division by P (ModDown) for all keys, each digit permuted by its key's automorphism after the
+// basis extension; plus the gathered `add` term (on every row, or on the first polynomial of each
+// ciphertext when add_even).  Output [count][2][l][N] in NTT form.
+static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, const KsKeys &keys, const Gather &add,
+                      bool add_even) {
     const size_t N = (size_t)c.p.n;
     const int P = c.p.p_index();
     // ModUp: coefficient form of every digit, reduced modulo every target while loading the forward NTT
@@ -324,9 +334,9 @@ static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, u64 id, co
     k_ntt_forward_g(c.tab, dig.ptr, Gather{dc.ptr, l + 1, 1, 0, 0, kReduce, 0}, count * l * (l + 1), ModMap{l + 1, l, P},
                     c.stream);
     dc.release();
-    // inner product with the key
+    // inner product with the keys (digits read through each key's automorphism)
     DBuf acc(c.pool.get(), (size_t)count * 2 * (l + 1) * N);
-    k_ks_inner(c.tab, acc.ptr, dig.ptr, it->second.ptr, count, l, c.p.levels, c.stream);
+    k_ks_inner(c.tab, acc.ptr, dig.ptr, keys, count, l, c.p.levels, c.stream);
     dig.release();
     // ModDown: round(x / P) = (x - [x]_P centred) * P^-1
     const int rows = count * 2;
@@ -341,6 +351,17 @@ static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, u64 id, co
     c.n_launch += 10;
     ++c.n_keyswitch;
     return out;
+}
+
+static KsKeys ks_keys(const ckks_ctx &c, const std::vector<u64> &ids, bool permute) {
+    if (ids.empty() || ids.size() > (size_t)kMaxKeys) throw Error(CKKS_E_INVALID_ARG, "1 to 8 keys per key switch");
+    KsKeys k{};
+    k.m = (int)ids.size();
+    for (size_t i = 0; i < ids.size(); ++i) {
+        k.key[i] = key_of(c, ids[i]);
+        k.g[i] = permute ? ids[i] : 0;
+    }
+    return k;
 }
 
 Ct mul_sum(ckks_ctx &c, const std::vector<std::pair<const ckks_ct *, const ckks_ct *>> &pairs) {
@@ -367,7 +388,7 @@ Ct mul_sum(ckks_ctx &c, const std::vector<std::pair<const ckks_ct *, const ckks_
         ++c.n_launch;
     }
     // relinearise: (d0, d1) + KS(d2, s^2 key)
-    DBuf ks = keyswitch(c, Gather{d.ptr, l, 3 * l, 2 * l, 1, kPlain, 0}, count, l, 0,
+    DBuf ks = keyswitch(c, Gather{d.ptr, l, 3 * l, 2 * l, 1, kPlain, 0}, count, l, ks_keys(c, {0}, false),
                         Gather{d.ptr, 2 * l, 3 * l, 0, 1, kPlain, 0}, false);
     d.release();
     ckks_ct tmp;
@@ -385,23 +406,48 @@ Ct mul_sum(ckks_ctx &c, const std::vector<std::pair<const ckks_ct *, const ckks_
 
 Ct mul(ckks_ctx &c, const ckks_ct &a, const ckks_ct &b) { return mul_sum(c, {{&a, &b}}); }
 
-u64 galois_rotate(const ckks_ctx &c, i64 r) {
-    const u64 m = 2ULL * (u64)c.p.n;
-    i64 rr = r % (c.p.n / 2);
-    if (rr < 0) rr += c.p.n / 2;   // 5 has order N/2 modulo 2N
+u64 galois_rotate_n(int n, i64 r) {
+    const u64 m = 2ULL * (u64)n;
+    i64 rr = r % (n / 2);
+    if (rr < 0) rr += n / 2;   // 5 has order N/2 modulo 2N
     return powmod_host(5, (u64)rr, m);
 }
 
+u64 galois_rotate(const ckks_ctx &c, i64 r) { return galois_rotate_n(c.p.n, r); }
+
 u64 galois_conj(const ckks_ctx &c) { return 2ULL * (u64)c.p.n - 1; }
 
+// sigma_g(a) switched back to s: c0 permuted, and the key switch of sigma_g(c1) reads the digits of c1
+// through the automorphism after the basis extension
 Ct apply_galois(ckks_ctx &c, const ckks_ct &a, u64 g) {
-    if (!has_key(c, g)) throw Error(CKKS_E_KEY_MISSING, "missing Galois key for element " + std::to_string(g));
     const int l = a.limbs;
     const size_t N = (size_t)c.p.n;
-    DBuf t(c.pool.get(), (size_t)a.count * 2 * l * N);
-    k_automorph(c.tab, t.ptr, a.data.ptr, a.count * 2 * l, g, c.stream);
-    DBuf ks = keyswitch(c, Gather{t.ptr, l, 2 * l, l, 1, kPlain, 0}, a.count, l, g, gather_plain(t.ptr), true);
+    const KsKeys keys = ks_keys(c, {g}, true);
+    DBuf t(c.pool.get(), (size_t)a.count * 2 * l * N);   // c0 rows: sigma_g(a c0); c1 rows unused
+    k_automorph_c0(c.tab, t.ptr, a.data.ptr, a.count, l, keys, false, c.stream);
+    DBuf ks = keyswitch(c, Gather{a.data.ptr, l, 2 * l, l, 1, kPlain, 0}, a.count, l, keys, gather_plain(t.ptr), true);
     c.n_launch += 1;
+    Ct r(new ckks_ct());
+    r->ctx = &c;
+    r->count = a.count;
+    r->depth = a.depth;
+    r->limbs = l;
+    r->scale = a.scale;
+    r->data = std::move(ks);
+    return r;
+}
+
+Ct rotate_sum(ckks_ctx &c, const ckks_ct &a, const std::vector<i64> &rots) {
+    const int l = a.limbs;
+    std::vector<u64> gs;
+    for (i64 r : rots) gs.push_back(galois_rotate(c, r));
+    const KsKeys keys = ks_keys(c, gs, true);
+    // a + (sum_i sigma_i(a c0), 0): added after the division by P
+    DBuf t(c.pool.get(), a.data.words);
+    GCK_HIP(hipMemcpyAsync(t.ptr, a.data.ptr, a.data.words * 8, hipMemcpyDeviceToDevice, c.stream));
+    k_automorph_c0(c.tab, t.ptr, a.data.ptr, a.count, l, keys, true, c.stream);
+    DBuf ks = keyswitch(c, Gather{a.data.ptr, l, 2 * l, l, 1, kPlain, 0}, a.count, l, keys, gather_plain(t.ptr), false);
+    c.n_launch += 2;
     Ct r(new ckks_ct());
     r->ctx = &c;
     r->count = a.count;

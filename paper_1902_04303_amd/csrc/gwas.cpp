@@ -35,13 +35,28 @@ Layout make_layout(int n_ring, int n, int k, int m) {
     return L;
 }
 
-std::vector<u64> required_galois(const ckks_ctx &c, int R) {
-    std::vector<u64> g;
-    for (int i = 1; i < R; i *= 2) {
-        g.push_back(galois_rotate(c, i));
-        g.push_back(galois_rotate(c, -i));
+std::vector<std::vector<i64>> rotation_groups(int R) {
+    std::vector<std::vector<i64>> out;
+    for (i64 s = 1; s < R;) {
+        if (4 * s <= R) {
+            out.push_back({s, 2 * s, 3 * s});
+            s *= 4;
+        } else {
+            out.push_back({s});
+            s *= 2;
+        }
     }
-    g.push_back(galois_conj(c));
+    return out;
+}
+
+std::vector<u64> required_galois(int n, int R) {
+    std::vector<u64> g;
+    for (const auto &grp : rotation_groups(R))
+        for (i64 r : grp) {
+            g.push_back(galois_rotate_n(n, r));
+            g.push_back(galois_rotate_n(n, -r));
+        }
+    g.push_back(2ULL * (u64)n - 1);   // conjugation
     return g;
 }
 
@@ -57,17 +72,17 @@ struct Circ {
         if (d == a.depth && factor == 1.0) return clone(c, a);
         return align(c, a, d, c.p.scales[d], factor);
     }
-    Ct rot_sum(Ct a) {   // a <- a + Rot(a, 2^i), i < log2 R (Alg. colSum / Alg. DotProd)
-        for (int i = 1; i < lay.R; i *= 2) {
-            Ct r = rotate(c, *a, i);
-            a = add(c, *a, *r);
-        }
+    // sum_{i < R} Rot(a, i) (Alg. colSum / Alg. DotProd): per group {s, 2s, 3s} of rotation_groups,
+    // a <- a + Rot(a, s) + Rot(a, 2s) + Rot(a, 3s) with one shared key switch
+    Ct rot_sum(Ct a) {
+        for (const auto &grp : rotation_groups(lay.R)) a = rotate_sum(c, *a, grp);
         return a;
     }
-    Ct bcast(Ct a) {     // a <- a + Rot(a, -2^i): the first slot of each block over the block
-        for (int i = 1; i < lay.R; i *= 2) {
-            Ct r = rotate(c, *a, -i);
-            a = add(c, *a, *r);
+    Ct bcast(Ct a) {     // sum_{i < R} Rot(a, -i): the first slot of each block over the block
+        for (const auto &grp : rotation_groups(lay.R)) {
+            std::vector<i64> neg;
+            for (i64 r : grp) neg.push_back(-r);
+            a = rotate_sum(c, *a, neg);
         }
         return a;
     }
@@ -239,7 +254,7 @@ BatchOut run_batch(ckks_ctx &c, int R, int k, const FixedOut &fx, const ckks_ct 
 }
 
 static void check_keys(ckks_ctx &c, int R) {
-    for (u64 g : required_galois(c, R))
+    for (u64 g : required_galois(c.p.n, R))
         if (!has_key(c, g)) throw Error(CKKS_E_KEY_MISSING, "missing Galois key " + std::to_string(g));
     if (!has_key(c, 0)) throw Error(CKKS_E_KEY_MISSING, "missing relinearisation key");
 }

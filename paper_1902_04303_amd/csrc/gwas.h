@@ -61,7 +61,11 @@ struct BatchOut {
 int circuit_levels(int kappa);
 int snp_depth(int kappa);
 Layout make_layout(int n_ring, int n, int k, int m);
-std::vector<u64> required_galois(const ckks_ctx &c, int R);
+// rotations of the rotate-and-sum over R slots, by shared key switch: {s, 2s, 3s} for s = 1, 4, 16, ...
+// while 4s <= R, then {s} when log2 R is odd
+std::vector<std::vector<i64>> rotation_groups(int R);
+// Galois elements of the rotations of rotation_groups(R) in both directions, and conjugation
+std::vector<u64> required_galois(int n, int R);
 void run_fixed(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckks_ct *> &x, const ckks_ct &y,
                const std::vector<const ckks_ct *> &A, int ds, FixedOut &fx, EncOutput &rep);
 BatchOut run_batch(ckks_ctx &c, int R, int k, const FixedOut &fx, const ckks_ct &S);

@@ -30,6 +30,7 @@ hipEvent_t KTimer::take() {
 }
 
 int KTimer::begin(const char *name, double bytes, hipStream_t st) {
+    if (!only.empty() && only != name) return -1;
     auto it = ids.find(name);
     int id;
     if (it == ids.end()) {
@@ -201,17 +202,21 @@ void k_tensor(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int coun
     check_launch();
 }
 
-// out[k] = a[k'] with psi^(2 brev(k') + 1) = (psi^(2 brev(k) + 1))^g
+// NTT-domain automorphism X -> X^g: word k of the result is word k2 of the input, where the evaluation
+// point of k2 is that of k raised to g, psi^(2 brev(k2) + 1) = (psi^(2 brev(k) + 1))^g.  The 64 words of
+// an aligned group of 64 map into one aligned group of 64 (only the top bits of brev(k) vary).
+__device__ __forceinline__ size_t automorph_src(size_t k, int log_n, u64 g) {
+    const u64 mask2n = (2ULL << log_n) - 1;
+    const u64 e = 2 * (u64)(__brev((unsigned)k) >> (32 - log_n)) + 1;
+    const u64 e2 = (e * g) & mask2n;
+    return __brev((unsigned)((e2 - 1) >> 1)) >> (32 - log_n);
+}
+
 __global__ void ew_automorph(u64 *out, const u64 *a, size_t total, int log_n, u64 g) {
     const size_t n = (size_t)1 << log_n;
-    const u64 mask2n = 2 * n - 1;
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
         size_t lam = idx >> log_n;
-        u64 k = idx & (n - 1);
-        u64 e = 2 * (u64)(__brev((unsigned)k) >> (32 - log_n)) + 1;
-        u64 e2 = (e * g) & mask2n;
-        u64 k2 = __brev((unsigned)((e2 - 1) >> 1)) >> (32 - log_n);
-        out[idx] = a[lam * n + k2];
+        out[idx] = a[lam * n + automorph_src(idx & (n - 1), log_n, g)];
     }
 }
 void k_automorph(const DevTables &t, u64 *out, const u64 *a, int n_limbs, u64 g, hipStream_t st) {
@@ -357,7 +362,7 @@ void k_sub_mul_add(const DevTables &t, u64 *out, const Gather &a, const u64 *b, 
 // high word is kept <= q by subtracting q (q 2^64 = 0 mod q) after each addition.  Each thread serves CB
 // ciphertexts of the batch, so every key word it loads is used CB times.
 template <int CB>
-__global__ void ks_inner(u64 *acc, const u64 *digits, const u64 *key, size_t total, int log_n, int l, int levels,
+__global__ void ks_inner(u64 *acc, const u64 *digits, KsKeys keys, size_t total, int log_n, int l, int levels,
                          int count, const ModInfo *mods) {
     const size_t n = (size_t)1 << log_n;
     const int nt_key = levels + 2;
@@ -373,22 +378,26 @@ __global__ void ks_inner(u64 *acc, const u64 *digits, const u64 *key, size_t tot
         u64 h0[CB], l0[CB], h1[CB], l1[CB];
 #pragma unroll
         for (int b = 0; b < CB; ++b) h0[b] = l0[b] = h1[b] = l1[b] = 0;
-        const u64 *dg = digits + (size_t)c0 * dig_ct + (size_t)tt * n + k;
-        for (int j = 0; j < l; ++j) {
-            const u64 k0 = key[((size_t)j * nt_key + chain) * n + k];
-            const u64 k1 = key[key_comp + ((size_t)j * nt_key + chain) * n + k];
+        const u64 *dg = digits + (size_t)c0 * dig_ct + (size_t)tt * n;
+        for (int i = 0; i < keys.m; ++i) {
+            const u64 *key = keys.key[i];
+            const size_t kd = keys.g[i] ? automorph_src(k, log_n, keys.g[i]) : k;   // permuted digit word
+            for (int j = 0; j < l; ++j) {
+                const u64 k0 = key[((size_t)j * nt_key + chain) * n + k];
+                const u64 k1 = key[key_comp + ((size_t)j * nt_key + chain) * n + k];
 #pragma unroll
-            for (int b = 0; b < CB; ++b) {
-                if (c0 + b >= count) break;
-                const u64 d = dg[(size_t)b * dig_ct + (size_t)j * (l + 1) * n];
-                const u64 p0 = d * k0, q0 = __umul64hi(d, k0);
-                const u64 p1 = d * k1, q1 = __umul64hi(d, k1);
-                l0[b] += p0;
-                h0[b] += q0 + (l0[b] < p0 ? 1 : 0);
-                l1[b] += p1;
-                h1[b] += q1 + (l1[b] < p1 ? 1 : 0);
-                if (h0[b] >= M.q) h0[b] -= M.q;
-                if (h1[b] >= M.q) h1[b] -= M.q;
+                for (int b = 0; b < CB; ++b) {
+                    if (c0 + b >= count) break;
+                    const u64 d = dg[(size_t)b * dig_ct + (size_t)j * (l + 1) * n + kd];
+                    const u64 p0 = d * k0, q0 = __umul64hi(d, k0);
+                    const u64 p1 = d * k1, q1 = __umul64hi(d, k1);
+                    l0[b] += p0;
+                    h0[b] += q0 + (l0[b] < p0 ? 1 : 0);
+                    l1[b] += p1;
+                    h1[b] += q1 + (l1[b] < p1 ? 1 : 0);
+                    if (h0[b] >= M.q) h0[b] -= M.q;
+                    if (h1[b] >= M.q) h1[b] -= M.q;
+                }
             }
         }
 #pragma unroll
@@ -402,19 +411,47 @@ __global__ void ks_inner(u64 *acc, const u64 *digits, const u64 *key, size_t tot
         }
     }
 }
-void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, const u64 *key, int count, int l, int levels,
+void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, const KsKeys &keys, int count, int l, int levels,
                 hipStream_t st) {
-    TScope ts_(t, "ks_inner", 8.0 * (double)t.n * (2.0 * l * (l + 1) + (double)count * (l * (l + 1) + 2 * (l + 1))), st);
+    const double ll = (double)l * (l + 1);
+    TScope ts_(t, "ks_inner", 8.0 * (double)t.n * (keys.m * (2.0 * ll + (double)count * ll) + (double)count * 2 * (l + 1)),
+               st);
     const int cb = count >= 8 ? 8 : (count >= 4 ? 4 : (count >= 2 ? 2 : 1));
     const int groups = (count + cb - 1) / cb;
     size_t total = ((size_t)groups * (l + 1)) << t.log_n;
     if (!total) return;
     switch (cb) {
-    case 8: hipLaunchKernelGGL(ks_inner<8>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, key, total, t.log_n, l, levels, count, t.mods); break;
-    case 4: hipLaunchKernelGGL(ks_inner<4>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, key, total, t.log_n, l, levels, count, t.mods); break;
-    case 2: hipLaunchKernelGGL(ks_inner<2>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, key, total, t.log_n, l, levels, count, t.mods); break;
-    default: hipLaunchKernelGGL(ks_inner<1>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, key, total, t.log_n, l, levels, count, t.mods); break;
+    case 8: hipLaunchKernelGGL(ks_inner<8>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, keys, total, t.log_n, l, levels, count, t.mods); break;
+    case 4: hipLaunchKernelGGL(ks_inner<4>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, keys, total, t.log_n, l, levels, count, t.mods); break;
+    case 2: hipLaunchKernelGGL(ks_inner<2>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, keys, total, t.log_n, l, levels, count, t.mods); break;
+    default: hipLaunchKernelGGL(ks_inner<1>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, keys, total, t.log_n, l, levels, count, t.mods); break;
     }
+    check_launch();
+}
+
+// out c0 rows (+)= sum_i sigma_i(a c0 rows)
+__global__ void ew_automorph_c0(u64 *out, const u64 *a, KsKeys gs, size_t total, int log_n, int l, const ModInfo *mods,
+                                int accumulate) {
+    const size_t n = (size_t)1 << log_n;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        const size_t lam = idx >> log_n;        // over count * l (c0 limbs)
+        const size_t c = lam / l;
+        const int limb = (int)(lam % l);
+        const size_t k = idx & (n - 1);
+        const u64 q = mods[limb].q;
+        const size_t row = (c * 2 * l + limb) * n;   // c0 limb of ciphertext c
+        u64 s = accumulate ? out[row + k] : 0;
+        for (int i = 0; i < gs.m; ++i) s = add_mod(s, a[row + automorph_src(k, log_n, gs.g[i])], q);
+        out[row + k] = s;
+    }
+}
+void k_automorph_c0(const DevTables &t, u64 *out, const u64 *a, int count, int l, const KsKeys &gs, bool accumulate,
+                    hipStream_t st) {
+    TScope ts_(t, "automorph_c0", 8.0 * (double)((size_t)count * l) * t.n * (gs.m + (accumulate ? 2 : 1)), st);
+    size_t total = ((size_t)count * l) << t.log_n;
+    if (!total) return;
+    hipLaunchKernelGGL(ew_automorph_c0, ew_grid(total), dim3(kEwThreads), 0, st, out, a, gs, total, t.log_n, l, t.mods,
+                       accumulate ? 1 : 0);
     check_launch();
 }
 

@@ -170,6 +170,9 @@ def test_mul_relinearise_and_galois_match_oracle(small):
             say("[gpu] rotate", r, "at depth", depth)
             assert np.array_equal(ctx.export(ctx.rotate(ga, r)), o.rotate(oa, r).data)
         assert np.array_equal(ctx.export(ctx.conjugate(ga)), o.conjugate(oa).data)
+        for rots in ([1, -2, 4], [4], [-2, 1]):
+            say("[gpu] rotate_sum", rots, "at depth", depth)
+            assert np.array_equal(ctx.export(ctx.rotate_sum(ga, rots)), o.rotate_sum(oa, rots).data)
 
 
 def test_missing_key_and_level_errors(small):

@@ -35,6 +35,23 @@ def test_prime_chain_matches_oracle(log_n, levels, b):
     assert scales == ref.scales
 
 
+@pytest.mark.parametrize("log_n,R", [(10, 2), (10, 8), (10, 64), (13, 256), (16, 256), (16, 2048), (16, 32768)])
+def test_galois_elements_match_oracle(log_n, R):
+    from oracle import gwas_circuit as G
+    assert P.gwas_galois_elements(log_n, R) == G.required_galois(1 << log_n, R)
+
+
+def test_rotation_groups_cover_every_shift_once():
+    """The grouped rotate-and-sum adds Rot(a, i) for each i < R exactly once (both implementations'
+    group lists generate the same Galois elements, checked above)."""
+    from oracle import gwas_circuit as G
+    for R in (2, 4, 8, 16, 32, 256, 2048):
+        sums = {0}
+        for grp in G.rotation_groups(R):
+            sums = {a + b for a in sums for b in [0] + grp}
+        assert sorted(sums) == list(range(R)), R
+
+
 def test_bad_parameters_are_rejected():
     with pytest.raises(P.CkksError) as e:
         P.chain(9, 4, 30)

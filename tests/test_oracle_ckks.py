@@ -108,7 +108,7 @@ def test_prime_chain_rule():
 @pytest.fixture(scope="module")
 def tiny_keys():
     p, o = tiny(logN=4, L=3, b=20)
-    g = [C.galois_rotate(p.N, 1), C.galois_conj(p.N)]
+    g = [C.galois_rotate(p.N, 1), C.galois_conj(p.N), C.galois_rotate(p.N, 2), C.galois_rotate(p.N, 3)]
     o.keygen(5, g)
     bc = B.BigCKKS(p.N, p.q, p.P)
     s = bc.secret(5, C.secret_weight(p.N))
@@ -182,6 +182,24 @@ def test_encrypt_tensor_keyswitch_rescale_match_bigint(tiny_keys):
     assert _ct_big(r, p, l - 1) == br
 
 
+def test_rotation_and_grouped_rotation_sum_match_bigint(tiny_keys):
+    """Key switch of an automorphism (digits lifted, then permuted) and the grouped rotate-and-sum
+    (three rotations, one division by P) against the big-integer schoolbook implementation."""
+    p, o, bc, s, g = tiny_keys
+    QP = bc.Q(p.L + 1) * p.P
+    keys = {gg: bc.switching_key(s, B.automorph(s, gg, QP), 5, C.ksk_sid_base(gg)) for gg in g}
+    rng = np.random.default_rng(6)
+    for l in (p.L + 1, 2):
+        ct = C.Ct(np.stack([np.stack([rng.integers(0, q, size=p.N, dtype=np.uint64) for q in p.q[:l]])
+                            for _ in range(2)]).copy(), p.L + 1 - l, 1.0)
+        big = _ct_big(ct, p, l)
+        for gg in g[:2]:
+            assert _ct_big(o.apply_galois(ct, gg), p, l) == bc.apply_galois(big, gg, keys[gg], l), (l, gg)
+        got = o.rotate_sum(ct, [1, 2, 3])
+        want = bc.rotate_sum(big, [(gg, keys[gg]) for gg in (g[0], g[2], g[3])], l)
+        assert _ct_big(got, p, l) == want, l
+
+
 def test_automorphism_matches_bigint(tiny_keys):
     p, o, bc, _, g = tiny_keys
     rng = np.random.default_rng(4)
@@ -233,7 +251,8 @@ def test_r_periodic_vectors_live_in_the_subring():
 def test_rotation_conjugation_and_mult_semantics():
     p = C.make_params(10, 3, 30)
     o = C.Oracle(p)
-    o.keygen(9, [C.galois_rotate(p.N, 1), C.galois_rotate(p.N, 4), C.galois_rotate(p.N, -4), C.galois_conj(p.N)])
+    o.keygen(9, [C.galois_rotate(p.N, 1), C.galois_rotate(p.N, 4), C.galois_rotate(p.N, -4), C.galois_conj(p.N),
+                 C.galois_rotate(p.N, -8), C.galois_rotate(p.N, -12)])
     rng = np.random.default_rng(7)
     z = rng.standard_normal(p.slots) + 1j * rng.standard_normal(p.slots)
     w = rng.standard_normal(p.slots)
@@ -250,6 +269,8 @@ def test_rotation_conjugation_and_mult_semantics():
     assert np.max(np.abs(o.decrypt(pr) - z * w)) < 10 * tol
     # rotation composition: rot(rot(a, 1), 4) equals rot(a, 5) up to noise
     assert np.max(np.abs(o.decrypt(o.rotate(o.rotate(ct, 1), 4)) - np.roll(z, -5))) < tol
+    want = z + np.roll(z, 4) + np.roll(z, 8) + np.roll(z, 12)
+    assert np.max(np.abs(o.decrypt(o.rotate_sum(ct, [-4, -8, -12])) - want)) < 4 * tol
     # integer multiply and constants
     assert np.max(np.abs(o.decrypt(o.mul_int(ct, -3)) + 3 * z)) < 10 * tol
     assert np.max(np.abs(o.decrypt(o.add_const(ct, 0.75)) - (z + 0.75))) < tol
