@@ -34,6 +34,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def region_marker(tag: int):
+    """A one-element torch fill kernel on the device: the GPU path itself launches no torch kernels, so in
+    a profiler's kernel trace the dispatches between the two markers are exactly the timed steps."""
+    import torch
+    torch.full((1,), tag, dtype=torch.int64, device="cuda")
+
+
 def galois_set(R):
     import paper_1902_04303_amd as P
     return P.gwas_galois_elements(LOG_N, R)
@@ -73,12 +80,14 @@ def gpu_leg(args):
     ctx.kernel_timing_only(dominant)
     c0 = ctx.counters()
     ctx.kernel_timing(True)
+    region_marker(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         out = ctx.gwas_semiparallel(gin)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    region_marker(2)
     ctx.kernel_timing(False)
     c1 = ctx.counters()
     ms = (t1 - t0) * 1e3 / args.steps
@@ -162,6 +171,34 @@ def forms_leg(args):
     return batched, serving
 
 
+DEVICE_SOURCES = ["paper_1902_04303_amd/csrc/" + f for f in ("ntt.hip", "kernels.hip", "modarith.h", "ckks_internal.h")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def device_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in DEVICE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter runs (FETCH_SIZE and WRITE_SIZE, each
+    scaled by the same counter's reading for a device copy of known size), or None when there is no
+    record for this kernel or the device sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != device_source_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else int(k["hbm_bytes_per_launch"])
+
+
 def roofline(kernels, warm, steps):
     """The dominant kernel (largest share of kernel time in the warmup step, where every kernel is timed),
     measured with HIP events around its own launches over the timed steps."""
@@ -169,7 +206,7 @@ def roofline(kernels, warm, steps):
     avg_ms = tot_ms / cnt
     achieved = (by / cnt) / (avg_ms * 1e-3) / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name),
             "launches_per_step": cnt // steps, "avg_launch_us": round(avg_ms * 1e3, 2),
             "algorithmic_bytes_per_launch": int(by / cnt), "share_of_kernel_time": round(
                 warm[name][1] / sum(v[1] for v in warm.values()), 3)}
@@ -211,6 +248,19 @@ def cpu_baseline_leg():
             "sample": "per-batch part of one 256-SNP batch of the same workload (S' = M S, numerator, both "
                       "denominators; %d key switches at <= 6 limbs), %.1f s; the fixed logistic-regression "
                       "part is excluded" % (o.n_keyswitch, t)}
+
+
+def copy_calibration(nbytes: int) -> int:
+    """A device-to-device copy of nbytes (a fill kernel writes the source first): the known-size
+    reference that scales HBM byte counters (FETCH_SIZE, WRITE_SIZE) to bytes."""
+    import torch
+    n = nbytes // 8
+    src = torch.arange(n, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}), flush=True)
+    return 0
 
 
 def run(args) -> int:
@@ -259,7 +309,11 @@ def main():
     ap.add_argument("--forms-jobs", type=int, default=12, help="jobs in the batched / serving legs (0: skip)")
     ap.add_argument("--forms-m-scale", type=float, default=0.1, help="scale of the job SNP counts")
     ap.add_argument("--forms-rate", type=float, default=4.0, help="Poisson arrival rate (jobs/s)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run one device copy of BYTES (byte-counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration)
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build measures the single-GPU path (the multi-GPU sharding is a "
               "design only); --gpus %d is not supported" % args.gpus, file=sys.stderr)

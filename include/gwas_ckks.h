@@ -233,7 +233,8 @@ int gwas_finalize(ckks_ctx *ctx, const gwas_enc_output *out, int m, double *b, d
 /* Per-kernel timing with HIP events recorded on the context's stream around every
  * launch of the instrumented kernels.  enable = 1 clears the counters and starts
  * recording; 0 stops.  The report is text, one line per kernel:
- * "name launches total_ms algorithmic_bytes". */
+ * "name launches total_ms algorithmic_bytes" (the name, a kernel symbol such as
+ * "ntt_pass<false, true, 8>", may contain spaces; the last three fields are numbers). */
 int ckks_ctx_kernel_timing(ckks_ctx *ctx, int enable);
 /* Restrict recording to launches of one kernel name (as it appears in the report), so that timing a
  * single kernel adds two event records per launch of that kernel only; NULL or "" records all. */

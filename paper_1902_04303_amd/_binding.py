@@ -317,7 +317,7 @@ class Context:
         _check(lib().ckks_ctx_kernel_report(self.h, buf, len(buf)))
         out = {}
         for line in buf.value.decode().splitlines():
-            name, cnt, ms, by = line.split()
+            name, cnt, ms, by = line.rsplit(None, 3)   # kernel names may contain spaces
             out[name] = (int(cnt), float(ms), float(by))
         return out
 

@@ -105,6 +105,7 @@ void build_tables(ckks_ctx &c) {
         M.qd = (double)q;
         M.qinv = 1.0 / (double)q;
         M.ninv_d = (double)M.ninv;
+        M.rinv_d = (double)invmod_host(M.r_mod, q);
     }
     const size_t mods_bytes = ((sizeof(ModInfo) * n_mods + 255) / 256) * 256;
     const size_t tab_bytes = N * n_mods * 8;

@@ -42,6 +42,7 @@ struct ModInfo {
     // moduli below 2^41 also run their NTT butterflies in FP64 (exact products by FMA)
     u64 fp;            // 1 when q < 2^41
     double qd, qinv, ninv_d;   // q, RN(1 / q), N^-1 mod q as doubles
+    double rinv_d;             // 2^-64 mod q as a double (leaves the Montgomery form of key products)
 };
 constexpr int kFpModBits = 41;
 
@@ -216,8 +217,9 @@ struct KsKeys {
 // kt = t (t<l) or L+1; key words are in Montgomery form (times 2^64)
 void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, const KsKeys &keys, int count, int l, int levels,
                 hipStream_t st);
-// out c0 rows = (accumulate ? out c0 : 0) + sum_i sigma_{g[i]}(a c0) for [count][2][l] batches (c1 rows untouched)
-void k_automorph_c0(const DevTables &t, u64 *out, const u64 *a, int count, int l, const KsKeys &gs, bool accumulate,
+// [count][2][l] batches: with_self: out = (a c0 + sum_i sigma_{g[i]}(a c0), a c1); otherwise
+// out c0 rows = sum_i sigma_{g[i]}(a c0) and out c1 rows are not written
+void k_automorph_c0(const DevTables &t, u64 *out, const u64 *a, int count, int l, const KsKeys &gs, bool with_self,
                     hipStream_t st);
 // samplers of the test-only SplitMix64 streams
 void k_sample_uniform(const DevTables &t, u64 *out, u64 seed, u64 sid, int n_limbs, ModMap m, int mi_of_p,

@@ -444,7 +444,6 @@ Ct rotate_sum(ckks_ctx &c, const ckks_ct &a, const std::vector<i64> &rots) {
     const KsKeys keys = ks_keys(c, gs, true);
     // a + (sum_i sigma_i(a c0), 0): added after the division by P
     DBuf t(c.pool.get(), a.data.words);
-    GCK_HIP(hipMemcpyAsync(t.ptr, a.data.ptr, a.data.words * 8, hipMemcpyDeviceToDevice, c.stream));
     k_automorph_c0(c.tab, t.ptr, a.data.ptr, a.count, l, keys, true, c.stream);
     DBuf ks = keyswitch(c, Gather{a.data.ptr, l, 2 * l, l, 1, kPlain, 0}, a.count, l, keys, gather_plain(t.ptr), false);
     c.n_launch += 2;

@@ -107,6 +107,7 @@ __global__ void ew_binary(u64 *out, const u64 *a, const u64 *b, size_t total, in
 
 void k_add(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
            hipStream_t st) {
+    TScope ts_(t, "ew_binary<0>", 24.0 * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_binary<0>, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, na, nb);
@@ -114,6 +115,7 @@ void k_add(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs
 }
 void k_sub(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
            hipStream_t st) {
+    TScope ts_(t, "ew_binary<1>", 24.0 * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_binary<1>, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, na, nb);
@@ -121,6 +123,7 @@ void k_sub(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs
 }
 void k_mul(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
            hipStream_t st) {
+    TScope ts_(t, "ew_binary<2>", 24.0 * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_binary<2>, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, na, nb);
@@ -137,6 +140,7 @@ __global__ void ew_mul_const(u64 *out, const u64 *a, size_t total, int log_n, Mo
 }
 void k_mul_const(const DevTables &t, u64 *out, const u64 *a, int n_limbs, ModMap m, const ChainConst &c,
                  hipStream_t st) {
+    TScope ts_(t, "ew_mul_const", 16.0 * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_mul_const, ew_grid(total), dim3(kEwThreads), 0, st, out, a, total, t.log_n, m, t.mods, c);
@@ -156,6 +160,7 @@ __global__ void ew_add_const_c0(u64 *ct, size_t total, int log_n, int l, const M
     }
 }
 void k_add_const_c0(const DevTables &t, u64 *ct, int count, int l, const ChainConst &c, hipStream_t st) {
+    TScope ts_(t, "ew_add_const_c0", 16.0 * (double)((size_t)count * l) * t.n, st);
     size_t total = ((size_t)count * l) << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_add_const_c0, ew_grid(total), dim3(kEwThreads), 0, st, ct, total, t.log_n, l, t.mods, c);
@@ -194,7 +199,7 @@ __global__ void ew_tensor(u64 *out, const u64 *a, const u64 *b, size_t total, in
 }
 void k_tensor(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int count, int l, int na, int nb,
               bool accumulate, hipStream_t st) {
-    TScope ts_(t, "tensor", 8.0 * 7.0 * (double)((size_t)count * l) * t.n, st);
+    TScope ts_(t, "ew_tensor", 8.0 * 7.0 * (double)((size_t)count * l) * t.n, st);
     size_t total = ((size_t)count * l) << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_tensor, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, l, t.mods, na, nb,
@@ -220,7 +225,7 @@ __global__ void ew_automorph(u64 *out, const u64 *a, size_t total, int log_n, u6
     }
 }
 void k_automorph(const DevTables &t, u64 *out, const u64 *a, int n_limbs, u64 g, hipStream_t st) {
-    TScope ts_(t, "automorph", 16.0 * (double)n_limbs * t.n, st);
+    TScope ts_(t, "ew_automorph", 16.0 * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_automorph, ew_grid(total), dim3(kEwThreads), 0, st, out, a, total, t.log_n, g);
@@ -258,7 +263,7 @@ __global__ void ew_extend(u64 *out, const u64 *in, size_t total, int log_n, int 
 }
 void k_extend(const DevTables &t, u64 *out, const u64 *in, int rows, int l_out, ModMap out_map, int src_mod,
               bool centred, hipStream_t st) {
-    TScope ts_(t, "extend", 8.0 * (double)((size_t)rows * (l_out + 1)) * t.n, st);
+    TScope ts_(t, "ew_extend", 8.0 * (double)((size_t)rows * (l_out + 1)) * t.n, st);
     size_t total = ((size_t)rows * l_out) << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_extend, ew_grid(total), dim3(kEwThreads), 0, st, out, in, total, t.log_n, l_out, out_map,
@@ -278,7 +283,7 @@ __global__ void ew_modup(u64 *out, const u64 *in, size_t total, int log_n, int l
     }
 }
 void k_modup(const DevTables &t, u64 *out, const u64 *in, int count, int l, int p_idx, hipStream_t st) {
-    TScope ts_(t, "modup", 8.0 * (double)((size_t)count * l * (l + 1) + (size_t)count * l) * t.n, st);
+    TScope ts_(t, "ew_modup", 8.0 * (double)((size_t)count * l * (l + 1) + (size_t)count * l) * t.n, st);
     size_t total = ((size_t)count * l * (l + 1)) << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_modup, ew_grid(total), dim3(kEwThreads), 0, st, out, in, total, t.log_n, l, p_idx, t.mods);
@@ -297,7 +302,7 @@ __global__ void ew_sub_mul_const(u64 *out, const u64 *a, const u64 *b, size_t to
 }
 void k_sub_mul_const(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m,
                      const ChainConst &c, bool add_to_out, hipStream_t st) {
-    TScope ts_(t, "sub_mul_const", (add_to_out ? 32.0 : 24.0) * (double)n_limbs * t.n, st);
+    TScope ts_(t, "ew_sub_mul_const", (add_to_out ? 32.0 : 24.0) * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_sub_mul_const, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, c,
@@ -320,7 +325,7 @@ __global__ void ew_add_rows(u64 *out, size_t out_stride, const u64 *in, size_t i
 }
 void k_add_rows(const DevTables &t, u64 *out, size_t out_stride, const u64 *in, size_t in_stride, int rows, int l,
                 hipStream_t st) {
-    TScope ts_(t, "add_rows", 24.0 * (double)((size_t)rows * l) * t.n, st);
+    TScope ts_(t, "ew_add_rows", 24.0 * (double)((size_t)rows * l) * t.n, st);
     size_t total = ((size_t)rows * l) << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_add_rows, ew_grid(total), dim3(kEwThreads), 0, st, out, out_stride, in, in_stride, total,
@@ -347,7 +352,7 @@ __global__ void ew_sub_mul_add(u64 *out, Gather a, const u64 *b, ChainConst c, G
 }
 void k_sub_mul_add(const DevTables &t, u64 *out, const Gather &a, const u64 *b, const ChainConst &c, const Gather &x,
                    bool x_even_rows, int rowlen, int n_limbs, ModMap m, hipStream_t st) {
-    TScope ts_(t, "sub_mul_add", (x.ptr ? 32.0 : 24.0) * (double)n_limbs * t.n, st);
+    TScope ts_(t, "ew_sub_mul_add", (x.ptr ? 32.0 : 24.0) * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_sub_mul_add, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, c, x, x_even_rows ? 1 : 0,
@@ -361,6 +366,11 @@ void k_sub_mul_add(const DevTables &t, u64 *out, const Gather &a, const u64 *b, 
 // factor 2^64 (Montgomery form), so the lazily accumulated 128-bit sum needs one REDC at the end; the
 // high word is kept <= q by subtracting q (q 2^64 = 0 mod q) after each addition.  Each thread serves CB
 // ciphertexts of the batch, so every key word it loads is used CB times.
+// One thread per (group of CB ciphertexts, target limb tt, word k).  Consecutive 256-thread blocks hold
+// the groups of one (tt, 256-word chunk), so the key words a chunk needs are fetched from HBM once and
+// re-read from cache by the other groups.  Targets below 2^41 accumulate in FP64 (exact products,
+// signed remainders), the others in 128-bit integers; the Montgomery form of the keys is removed at
+// the end (REDC, or a multiply with 2^-64 mod q in FP64).
 template <int CB>
 __global__ void ks_inner(u64 *acc, const u64 *digits, KsKeys keys, size_t total, int log_n, int l, int levels,
                          int count, const ModInfo *mods) {
@@ -368,60 +378,104 @@ __global__ void ks_inner(u64 *acc, const u64 *digits, KsKeys keys, size_t total,
     const int nt_key = levels + 2;
     const size_t key_comp = (size_t)(levels + 1) * nt_key * n;
     const size_t dig_ct = (size_t)l * (l + 1) * n;
+    const size_t dig_j = (size_t)(l + 1) * n;
+    const int groups = (count + CB - 1) / CB;
+    const size_t chunks = n >> 8;   // 256-word chunks per limb
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
-        const size_t lam = idx >> log_n;       // over groups * (l + 1)
-        const int tt = (int)(lam % (l + 1));
-        const int c0 = (int)(lam / (l + 1)) * CB;
-        const size_t k = idx & (n - 1);
+        const size_t blk = idx >> 8;
+        const int grp = (int)(blk % groups);
+        const size_t rest = blk / groups;
+        const size_t k = ((rest % chunks) << 8) + (idx & 255);
+        const int tt = (int)(rest / chunks);
         const int chain = tt < l ? tt : levels + 1;
         const ModInfo M = mods[chain];
-        u64 h0[CB], l0[CB], h1[CB], l1[CB];
+        const u64 *dg = digits + (size_t)tt * n;
+        const size_t krow = (size_t)chain * n + k;   // key word of digit j: key[(j nt_key) n + krow]
+        {
+            const int c0 = grp * CB;
+            const int nb = count - c0 < CB ? count - c0 : CB;
+            if (M.fp) {
+                const FMod fm{M.qd, M.qinv};
+                double a0[CB], a1[CB];
 #pragma unroll
-        for (int b = 0; b < CB; ++b) h0[b] = l0[b] = h1[b] = l1[b] = 0;
-        const u64 *dg = digits + (size_t)c0 * dig_ct + (size_t)tt * n;
-        for (int i = 0; i < keys.m; ++i) {
-            const u64 *key = keys.key[i];
-            const size_t kd = keys.g[i] ? automorph_src(k, log_n, keys.g[i]) : k;   // permuted digit word
-            for (int j = 0; j < l; ++j) {
-                const u64 k0 = key[((size_t)j * nt_key + chain) * n + k];
-                const u64 k1 = key[key_comp + ((size_t)j * nt_key + chain) * n + k];
+                for (int b = 0; b < CB; ++b) a0[b] = a1[b] = 0.0;
+                // digit-major: the keys' permuted reads of one digit word group follow each other (cache hits)
+                for (int j = 0; j < l; ++j) {
+                    for (int i = 0; i < keys.m; ++i) {
+                        const u64 *key = keys.key[i];
+                        const size_t kd = keys.g[i] ? automorph_src(k, log_n, keys.g[i]) : k;   // permuted digit word
+                        const double k0 = (double)key[(size_t)j * nt_key * n + krow];
+                        const double k1 = (double)key[key_comp + (size_t)j * nt_key * n + krow];
+                        const u64 *dj = dg + (size_t)c0 * dig_ct + (size_t)j * dig_j + kd;
+#pragma unroll
+                        for (int b = 0; b < CB; ++b) {
+                            if (b >= nb) break;
+                            const double d = (double)dj[(size_t)b * dig_ct];
+                            a0[b] += fmul_mod(d, k0, fm);
+                            a1[b] += fmul_mod(d, k1, fm);
+                        }
+                    }
+#pragma unroll
+                    for (int b = 0; b < CB; ++b) {   // each term is below 0.6 q: keep the sums below 2^47
+                        a0[b] = fred(a0[b], fm);
+                        a1[b] = fred(a1[b], fm);
+                    }
+                }
 #pragma unroll
                 for (int b = 0; b < CB; ++b) {
-                    if (c0 + b >= count) break;
-                    const u64 d = dg[(size_t)b * dig_ct + (size_t)j * (l + 1) * n + kd];
-                    const u64 p0 = d * k0, q0 = __umul64hi(d, k0);
-                    const u64 p1 = d * k1, q1 = __umul64hi(d, k1);
-                    l0[b] += p0;
-                    h0[b] += q0 + (l0[b] < p0 ? 1 : 0);
-                    l1[b] += p1;
-                    h1[b] += q1 + (l1[b] < p1 ? 1 : 0);
-                    if (h0[b] >= M.q) h0[b] -= M.q;
-                    if (h1[b] >= M.q) h1[b] -= M.q;
+                    if (b >= nb) break;
+                    u64 *o = acc + ((size_t)(c0 + b) * 2 * (l + 1) + tt) * n + k;
+                    o[0] = fcanon(fmul_mod(a0[b], M.rinv_d, fm), fm);
+                    o[(size_t)(l + 1) * n] = fcanon(fmul_mod(a1[b], M.rinv_d, fm), fm);
+                }
+            } else {
+                u64 h0[CB], l0[CB], h1[CB], l1[CB];
+#pragma unroll
+                for (int b = 0; b < CB; ++b) h0[b] = l0[b] = h1[b] = l1[b] = 0;
+                for (int j = 0; j < l; ++j) {
+                    for (int i = 0; i < keys.m; ++i) {
+                        const u64 *key = keys.key[i];
+                        const size_t kd = keys.g[i] ? automorph_src(k, log_n, keys.g[i]) : k;
+                        const u64 k0 = key[(size_t)j * nt_key * n + krow];
+                        const u64 k1 = key[key_comp + (size_t)j * nt_key * n + krow];
+                        const u64 *dj = dg + (size_t)c0 * dig_ct + (size_t)j * dig_j + kd;
+#pragma unroll
+                        for (int b = 0; b < CB; ++b) {
+                            if (b >= nb) break;
+                            const u64 d = dj[(size_t)b * dig_ct];
+                            const u64 p0 = d * k0, q0 = __umul64hi(d, k0);
+                            const u64 p1 = d * k1, q1 = __umul64hi(d, k1);
+                            l0[b] += p0;
+                            h0[b] += q0 + (l0[b] < p0 ? 1 : 0);
+                            l1[b] += p1;
+                            h1[b] += q1 + (l1[b] < p1 ? 1 : 0);
+                            if (h0[b] >= M.q) h0[b] -= M.q;
+                            if (h1[b] >= M.q) h1[b] -= M.q;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    if (b >= nb) break;
+                    u64 *o = acc + ((size_t)(c0 + b) * 2 * (l + 1) + tt) * n + k;
+                    o[0] = redc(h0[b], l0[b], M);
+                    o[(size_t)(l + 1) * n] = redc(h1[b], l1[b], M);
                 }
             }
-        }
-#pragma unroll
-        for (int b = 0; b < CB; ++b) {
-            if (c0 + b >= count) break;
-            if (h0[b] >= M.q) h0[b] -= M.q;
-            if (h1[b] >= M.q) h1[b] -= M.q;
-            u64 *o = acc + ((size_t)(c0 + b) * 2 * (l + 1) + tt) * n + k;
-            o[0] = redc(h0[b], l0[b], M);
-            o[(size_t)(l + 1) * n] = redc(h1[b], l1[b], M);
         }
     }
 }
 void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, const KsKeys &keys, int count, int l, int levels,
                 hipStream_t st) {
+    // algorithmic bytes: every key word and every digit word read once, the accumulators written once
     const double ll = (double)l * (l + 1);
-    TScope ts_(t, "ks_inner", 8.0 * (double)t.n * (keys.m * (2.0 * ll + (double)count * ll) + (double)count * 2 * (l + 1)),
-               st);
-    const int cb = count >= 8 ? 8 : (count >= 4 ? 4 : (count >= 2 ? 2 : 1));
-    const int groups = (count + cb - 1) / cb;
-    size_t total = ((size_t)groups * (l + 1)) << t.log_n;
+    const int cb = count >= 4 ? 4 : (count >= 2 ? 2 : 1);   // 8 would spill registers
+    static const char *const names[5] = {"", "ks_inner<1>", "ks_inner<2>", "", "ks_inner<4>"};
+    TScope ts_(t, names[cb], 8.0 * (double)t.n * (keys.m * 2.0 * ll + (double)count * (ll + 2.0 * (l + 1))), st);
+    if (t.log_n < 8) throw Error(CKKS_E_INVALID_ARG, "key switching needs N >= 256");
+    size_t total = ((size_t)((count + cb - 1) / cb) * (l + 1)) << t.log_n;
     if (!total) return;
     switch (cb) {
-    case 8: hipLaunchKernelGGL(ks_inner<8>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, keys, total, t.log_n, l, levels, count, t.mods); break;
     case 4: hipLaunchKernelGGL(ks_inner<4>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, keys, total, t.log_n, l, levels, count, t.mods); break;
     case 2: hipLaunchKernelGGL(ks_inner<2>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, keys, total, t.log_n, l, levels, count, t.mods); break;
     default: hipLaunchKernelGGL(ks_inner<1>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, keys, total, t.log_n, l, levels, count, t.mods); break;
@@ -429,29 +483,34 @@ void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, const KsKeys &k
     check_launch();
 }
 
-// out c0 rows (+)= sum_i sigma_i(a c0 rows)
+// with_self: out = (a c0 + sum_i sigma_i(a c0), a c1); else out c0 rows = sum_i sigma_i(a c0) (c1 rows untouched)
 __global__ void ew_automorph_c0(u64 *out, const u64 *a, KsKeys gs, size_t total, int log_n, int l, const ModInfo *mods,
-                                int accumulate) {
+                                int with_self) {
     const size_t n = (size_t)1 << log_n;
+    const int rl = with_self ? 2 * l : l;   // limbs per ciphertext covered by the launch
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
-        const size_t lam = idx >> log_n;        // over count * l (c0 limbs)
-        const size_t c = lam / l;
-        const int limb = (int)(lam % l);
+        const size_t lam = idx >> log_n;
+        const size_t c = lam / rl;
+        const int r = (int)(lam % rl);      // r < l: c0 limb r; else c1 limb r - l
         const size_t k = idx & (n - 1);
-        const u64 q = mods[limb].q;
-        const size_t row = (c * 2 * l + limb) * n;   // c0 limb of ciphertext c
-        u64 s = accumulate ? out[row + k] : 0;
+        const size_t row = (c * 2 * l + r) * n;
+        if (r >= l) {
+            out[row + k] = a[row + k];
+            continue;
+        }
+        const u64 q = mods[r].q;
+        u64 s = with_self ? a[row + k] : 0;
         for (int i = 0; i < gs.m; ++i) s = add_mod(s, a[row + automorph_src(k, log_n, gs.g[i])], q);
         out[row + k] = s;
     }
 }
-void k_automorph_c0(const DevTables &t, u64 *out, const u64 *a, int count, int l, const KsKeys &gs, bool accumulate,
+void k_automorph_c0(const DevTables &t, u64 *out, const u64 *a, int count, int l, const KsKeys &gs, bool with_self,
                     hipStream_t st) {
-    TScope ts_(t, "automorph_c0", 8.0 * (double)((size_t)count * l) * t.n * (gs.m + (accumulate ? 2 : 1)), st);
-    size_t total = ((size_t)count * l) << t.log_n;
+    TScope ts_(t, "ew_automorph_c0", 8.0 * (double)((size_t)count * l) * t.n * (with_self ? gs.m + 4 : gs.m + 1), st);
+    const size_t total = ((size_t)count * (with_self ? 2 : 1) * l) << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_automorph_c0, ew_grid(total), dim3(kEwThreads), 0, st, out, a, gs, total, t.log_n, l, t.mods,
-                       accumulate ? 1 : 0);
+                       with_self ? 1 : 0);
     check_launch();
 }
 
@@ -469,6 +528,7 @@ __global__ void sample_uniform(u64 *out, u64 seed, u64 sid, size_t total, int lo
     }
 }
 void k_sample_uniform(const DevTables &t, u64 *out, u64 seed, u64 sid, int n_limbs, ModMap m, int, hipStream_t st) {
+    TScope ts_(t, "sample_uniform", 8.0 * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(sample_uniform, ew_grid(total), dim3(kEwThreads), 0, st, out, seed, sid, total, t.log_n, m, t.mods);
@@ -509,6 +569,7 @@ __global__ void ew_signed_to_limbs(u64 *out, const i64 *in, size_t total, int lo
     }
 }
 void k_signed_to_limbs(const DevTables &t, u64 *out, const i64 *in, int n_limbs, ModMap m, hipStream_t st) {
+    TScope ts_(t, "ew_signed_to_limbs", 8.0 * (double)(n_limbs + 1) * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_signed_to_limbs, ew_grid(total), dim3(kEwThreads), 0, st, out, in, total, t.log_n, m, t.mods);
@@ -523,12 +584,14 @@ __global__ void ew_mont(u64 *x, size_t total, int log_n, ModMap mm, const ModInf
     }
 }
 void k_to_mont(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t st) {
+    TScope ts_(t, "ew_mont", 16.0 * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_mont, ew_grid(total), dim3(kEwThreads), 0, st, x, total, t.log_n, m, t.mods, 1);
     check_launch();
 }
 void k_from_mont(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t st) {
+    TScope ts_(t, "ew_mont", 16.0 * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_mont, ew_grid(total), dim3(kEwThreads), 0, st, x, total, t.log_n, m, t.mods, 0);
@@ -543,6 +606,7 @@ __global__ void ew_neg(u64 *x, size_t total, int log_n, ModMap mm, const ModInfo
     }
 }
 void k_neg(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t st) {
+    TScope ts_(t, "ew_neg", 16.0 * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_neg, ew_grid(total), dim3(kEwThreads), 0, st, x, total, t.log_n, m, t.mods);

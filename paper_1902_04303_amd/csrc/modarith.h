@@ -48,6 +48,41 @@ __device__ __forceinline__ int chain_of(int lam, ModMap m) {
     return t < m.nq ? t : m.p_idx;
 }
 
+// ---------------------------------------------------------------- FP64 arithmetic (q < 2^41)
+// Residues of moduli below 2^41 as integer-valued doubles: a product a w is split exactly into its
+// rounded value and the FMA error, the quotient by q is rounded from a multiply by RN(1/q), and the
+// remainder is then exact.
+struct FMod {
+    double q, qinv;
+};
+
+// a w mod q as a signed representative in (-1.1q, 1.1q), exact; a, w integers, |a| < 2^47, 0 <= w < q
+__device__ __forceinline__ double fmul_mod(double a, double w, FMod m) {
+#pragma clang fp contract(off)
+    const double h = a * w;
+    const double l = __builtin_fma(a, w, -h);         // a w = h + l exactly
+    const double qt = __builtin_rint(h * m.qinv);
+    const double r = __builtin_fma(-qt, m.q, h);      // integer of magnitude < q: exact
+    return r + l;
+}
+
+// signed reduction of an integer |x| < 2^52 to (-0.6q, 0.6q)
+__device__ __forceinline__ double fred(double x, FMod m) {
+#pragma clang fp contract(off)
+    const double qt = __builtin_rint(x * m.qinv);
+    return __builtin_fma(-qt, m.q, x);
+}
+
+// canonical residue in [0, q) of an integer |x| < 2^52, as a 64-bit word
+__device__ __forceinline__ u64 fcanon(double x, FMod m) {
+#pragma clang fp contract(off)
+    const double qt = __builtin_floor(x * m.qinv);
+    double r = __builtin_fma(-qt, m.q, x);
+    r = r < 0.0 ? r + m.q : r;
+    r = r >= m.q ? r - m.q : r;
+    return (u64)r;
+}
+
 // ---------------------------------------------------------------- SplitMix64 (test-only randomness)
 
 __device__ __forceinline__ u64 sm_mix(u64 z) {
