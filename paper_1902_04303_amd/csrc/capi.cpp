@@ -106,6 +106,7 @@ void build_tables(ckks_ctx &c) {
         M.qinv = 1.0 / (double)q;
         M.ninv_d = (double)M.ninv;
         M.rinv_d = (double)invmod_host(M.r_mod, q);
+        M.c32_d = (double)(((u64)1 << 32) % q);
     }
     const size_t mods_bytes = ((sizeof(ModInfo) * n_mods + 255) / 256) * 256;
     const size_t tab_bytes = N * n_mods * 8;
@@ -467,12 +468,15 @@ int ckks_mul_mask(ckks_ctx *ctx, const ckks_ct *a, int R, ckks_ct **out) {
 int ckks_ntt_device(ckks_ctx *ctx, uint64_t *dev_limbs, int count, const int *moduli_index, int dir) {
     return guard_ctx(ctx, [&] {
         need(ctx && dev_limbs && moduli_index && count >= 0 && (dir == 1 || dir == -1), "bad arguments");
-        for (int i = 0; i < count; ++i) {
-            int mi = moduli_index[i];
-            need(mi >= 0 && mi <= ctx->p.levels + 1, "modulus index out of range");
-            const ModMap m{1, 0, mi};
-            if (dir == 1) ntt_fwd(*ctx, dev_limbs + (size_t)i * ctx->p.n, 1, m);
-            else ntt_inv(*ctx, dev_limbs + (size_t)i * ctx->p.n, 1, m);
+        for (int i = 0; i < count; ++i) need(moduli_index[i] >= 0 && moduli_index[i] <= ctx->p.levels + 1,
+                                             "modulus index out of range");
+        for (int i = 0; i < count;) {   // one launch per run of limbs with the same modulus
+            int e = i + 1;
+            while (e < count && moduli_index[e] == moduli_index[i]) ++e;
+            const ModMap m{1, 0, moduli_index[i]};
+            if (dir == 1) ntt_fwd(*ctx, dev_limbs + (size_t)i * ctx->p.n, e - i, m);
+            else ntt_inv(*ctx, dev_limbs + (size_t)i * ctx->p.n, e - i, m);
+            i = e;
         }
     });
 }

@@ -43,6 +43,7 @@ struct ModInfo {
     u64 fp;            // 1 when q < 2^41
     double qd, qinv, ninv_d;   // q, RN(1 / q), N^-1 mod q as doubles
     double rinv_d;             // 2^-64 mod q as a double (leaves the Montgomery form of key products)
+    double c32_d;              // 2^32 mod q as a double (reduces 64-bit words in FP64)
 };
 constexpr int kFpModBits = 41;
 

@@ -54,7 +54,7 @@ __device__ __forceinline__ int block_id(const Geom &g) {
 Geom make_geom(int log_n) {
     Geom g;
     g.log_n = log_n;
-    g.log_n1 = (log_n + 1) / 2;
+    g.log_n1 = (log_n + 1) / 2;   // 256 x 256 at N = 2^16 (128 x 512 measured slower overall)
     g.log_n2 = log_n - g.log_n1;
     g.n2 = 1 << g.log_n2;
     int log_tile = log_n < 12 ? log_n : 12;
@@ -65,15 +65,15 @@ Geom make_geom(int log_n) {
     return g;
 }
 
-// LDS address of word idx of sub-transform gi; row tiles are padded (one word per 16) so that
-// threads reading 16 consecutive words of a row do not all hit one bank.
+// LDS address of word idx of sub-transform gi, padded by one word per 16 so that the 4 rows of a
+// wave access (16 words apart within a row, or 16 column rows apart) fall in different banks.
 template <bool ROWS>
 __device__ __forceinline__ int lds_addr(int gi, int idx, int log_m, int log_g) {
     if (ROWS) {
         const int m = 1 << log_m;
         return gi * (m + (m >> 4)) + idx + (idx >> 4);
     }
-    return (idx << log_g) + gi;
+    return (idx << log_g) + gi + (idx >> 4);
 }
 
 // One register phase of a sub-transform of size M = 2^LOGM: stages S0 .. S0 + R - 1.
@@ -244,25 +244,38 @@ __global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, G
         base_off = 1;
     }
     const bool last_pass = INV ? !ROWS : ROWS;
+    // global loads in the layout of the first phase; stores of the rows pass go through LDS so that a
+    // wave instruction covers 16 consecutive words of each of 4 rows (an LDS transposition in the cols
+    // passes, loads or stores, measured slower than the strided access it replaces)
     u64 v[kPer];
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
         const int idx = slot_index<LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(e, q);
-        u64 x = ain[base + (size_t)idx * stride];
-        if (mode != kPlain) {
-            const bool neg = (mode == kCentred) && x > src_half;
-            x = reduce64(x, M);
-            if (neg) x = x >= src_q_red ? x - src_q_red : x + qm - src_q_red;   // x - src_q is negative
-        }
-        v[e] = x;
+        v[e] = ain[base + (size_t)idx * stride];
     }
     if (M.fp) {
         // FP64 butterflies; the first pass reads residues, the second the first pass's doubles
         const FMod fm{M.qd, M.qinv};
         const double *Wf = tw_f + (size_t)chain * n;
         double f[kPer];
+        if (last_pass) {
 #pragma unroll
-        for (int e = 0; e < kPer; ++e) f[e] = last_pass ? __longlong_as_double((long long)v[e]) : (double)v[e];
+            for (int e = 0; e < kPer; ++e) f[e] = __longlong_as_double((long long)v[e]);
+        } else if (mode == kPlain) {
+#pragma unroll
+            for (int e = 0; e < kPer; ++e) f[e] = (double)v[e];
+        } else {
+            // any word x < 2^64 taken mod q as (x >> 32) (2^32 mod q) + (x mod 2^32); a centred source
+            // residue above half its modulus also subtracts that modulus
+            const double sq = (double)src_q_red;
+#pragma unroll
+            for (int e = 0; e < kPer; ++e) {
+                const u64 x = v[e];
+                double y = fmul_mod((double)(x >> 32), M.c32_d, fm) + (double)(x & 0xFFFFFFFFULL);
+                if (mode == kCentred && x > src_half) y -= sq;
+                f[e] = fred(y, fm);
+            }
+        }
         double *shf = reinterpret_cast<double *>(sh);
         fphase<INV, LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(f, q, base_off, Wf, fm);
         if constexpr (NPH > 1) {
@@ -290,6 +303,16 @@ __global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, G
             v[e] = last_pass ? fcanon(x, fm) : (u64)__double_as_longlong(fred(x, fm));
         }
     } else {
+        if (!last_pass && mode != kPlain) {
+#pragma unroll
+            for (int e = 0; e < kPer; ++e) {
+                u64 x = v[e];
+                const bool neg = (mode == kCentred) && x > src_half;
+                x = reduce64(x, M);
+                if (neg) x = x >= src_q_red ? x - src_q_red : x + qm - src_q_red;   // x - src_q is negative
+                v[e] = x;
+            }
+        }
         phase<INV, LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(v, q, base_off, W, Ws, qm);
         if constexpr (NPH > 1) {
             constexpr int P1 = INV ? NPH - 2 : 1;
@@ -312,8 +335,7 @@ __global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, G
             v[e] = x;
         }
     }
-    if (ROWS) {
-        // coalesced store through LDS, read back in the layout of the first forward phase
+    if (ROWS && LAST != 0) {
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < kPer; ++e)
@@ -361,7 +383,11 @@ static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, 
     const int log_tile = t.log_n < 12 ? t.log_n : 12;
     dim3 grid((unsigned)((size_t)n_limbs * g.tiles));
     dim3 block((unsigned)((1 << log_tile) / kPer));
+    // algorithmic bytes of a pass: each word written once and each distinct input word read once (a
+    // gather whose output limbs share a source limb, inner == 0, reads n_limbs / div source limbs)
     const double bytes = 16.0 * (double)n_limbs * t.n;
+    const bool shared_src = in.ptr && in.div > 1 && in.inner == 0;
+    const double bytes1 = shared_src ? 8.0 * t.n * ((double)n_limbs + (double)n_limbs / in.div) : bytes;
     const Gather none{nullptr, 1, 1, 0, 0, kPlain, 0};
     // timing names: the kernel symbols as a profiler lists them
     static const char *const names[2][2][5] = {
@@ -375,10 +401,10 @@ static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, 
           "ntt_pass<true, true, 8>", "ntt_pass<true, true, 9>"}}};
     auto name = [&](bool i, bool rows, int log_m) { return names[i][rows][log_m - 5]; };
     Geom g1 = g;   // first pass: group the readers of a shared source limb on one XCD
-    g1.xcd_group = (in.ptr && in.div > 1 && in.inner == 0 && grid.x % 8 == 0) ? 1 : 0;
+    g1.xcd_group = (shared_src && grid.x % 8 == 0) ? 1 : 0;
     if (!inv) {
         {
-            TScope ts_(t, name(false, false, g.log_n1), bytes, st);
+            TScope ts_(t, name(false, false, g.log_n1), bytes1, st);
             launch_pass<false, false>(g.log_n1, grid, block, st, buf, in, m, t.mods, t.psi, t.psi_sh, t.psi_f, g1);
         }
         {
@@ -387,7 +413,7 @@ static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, 
         }
     } else {
         {
-            TScope ts_(t, name(true, true, g.log_n2), bytes, st);
+            TScope ts_(t, name(true, true, g.log_n2), bytes1, st);
             launch_pass<true, true>(g.log_n2, grid, block, st, buf, in, m, t.mods, t.ipsi, t.ipsi_sh, t.ipsi_f, g1);
         }
         {
