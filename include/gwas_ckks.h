@@ -54,9 +54,11 @@ typedef struct gwas_server gwas_server;
 /* Parameters (the RNS reading of the scheme parameters of the paper's Methods,
  * "Homomorphic Encryption": ring dimension N, levels L, scale).  The prime
  * chain is derived from them by a fixed rule: q_0 is the largest prime below
- * 2^60 and P the largest below 2^62 that are 1 mod 2N; the L rescale primes are
- * chosen greedily from the 4L primes 1 mod 2N nearest 2^log2_scale so that the
- * canonical scales Delta_{d+1} = Delta_d^2 / q_{L-d} stay near 2^log2_scale. */
+ * 2^60 that is 1 mod 2N; the L rescale primes are chosen greedily from the 4L
+ * primes 1 mod 2N nearest 2^log2_scale so that the canonical scales
+ * Delta_{d+1} = Delta_d^2 / q_{L-d} stay near 2^log2_scale; the key-switching
+ * modulus P = p_1 p_2 is the product of the two largest primes below 2^41 that
+ * are 1 mod 2N and not in the chain. */
 typedef struct {
     int log_n;          /* log2 N, 10 <= log_n <= 17 */
     int levels;         /* L >= 1: number of rescale primes */
@@ -73,7 +75,7 @@ typedef struct {
 
 const char *ckks_last_error(void);
 
-/* Host only (no device work): the prime chain q_0..q_L, P (moduli: L + 2 entries)
+/* Host only (no device work): the moduli q_0..q_L, p_1, p_2 (moduli: L + 3 entries)
  * and the canonical scales Delta_0..Delta_L (scales: L + 1 entries). */
 int ckks_chain(const ckks_params *params, uint64_t *moduli, double *scales);
 
@@ -86,7 +88,7 @@ int ckks_ctx_create(const ckks_params *params, const ckks_allocator *allocator, 
                     size_t pool_budget_bytes, ckks_ctx **out);
 void ckks_ctx_destroy(ckks_ctx *ctx);
 
-/* Chain moduli: q[0..L] then P (caller array of L + 2 entries). */
+/* Chain moduli: q[0..L] then p_1, p_2 (caller array of L + 3 entries). */
 int ckks_ctx_moduli(const ckks_ctx *ctx, uint64_t *moduli, int cap);
 /* Canonical scales Delta_0..Delta_L (caller array of L + 1 entries). */
 int ckks_ctx_scales(const ckks_ctx *ctx, double *scales, int cap);
@@ -97,10 +99,12 @@ int ckks_ctx_pool_trim(ckks_ctx *ctx);
 
 /* ---------------------------------------------------------------- keys */
 
-/* KeyGen (paper: Methods, "Homomorphic Encryption", KeyGen), RNS form with one
- * special prime P.  s has h = min(64, N/2) coefficients in {-1, 1} (HWT(h)),
- * pk = (-a s + e, a) mod Q_L, and a switching key for s' has digits
- * j = 0..L:  (-a_j s + e_j + [t = j] P s', a_j) mod q_t and P.
+/* KeyGen (paper: Methods, "Homomorphic Encryption", KeyGen), RNS form with the
+ * special modulus P = p_1 p_2 and a hybrid decomposition: digit groups
+ * G_0 = {q_0}, G_b = {q_{2b-1}, q_{2b}} (b = 1 .. L/2 rounded up).  s has
+ * h = min(64, N/2) coefficients in {-1, 1} (HWT(h)), pk = (-a s + e, a) mod Q_L,
+ * and a switching key for s' has one part per group b:
+ * (-a_b s + e_b + [q_t in G_b] P s', a_b) mod q_t (t = 0..L), p_1 and p_2.
  * A relinearisation key (s' = s^2) is always made; one Galois key is made per
  * element of galois[] (s' = s(X^g), g odd in [3, 2N)).  seed != 0 selects the
  * test-only deterministic generator (counter-based SplitMix64); seed == 0 draws
@@ -111,8 +115,8 @@ uint64_t ckks_galois_rotate(const ckks_ctx *ctx, int64_t r);
 /* Galois element of complex conjugation, 2N - 1. */
 uint64_t ckks_galois_conj(const ckks_ctx *ctx);
 /* Copy out a key in canonical coefficient form.  key_id 0 is the relinearisation
- * key, otherwise a Galois element; buf holds [2][L+1][L+2][N] words (targets
- * q_0..q_L then P). Secret: [N] int64; public key: [2][L+1][N]. */
+ * key, otherwise a Galois element; buf holds [2][G][L+3][N] words, G = 1 + ceil(L/2)
+ * groups, targets q_0..q_L then p_1, p_2. Secret: [N] int64; public key: [2][L+1][N]. */
 int ckks_export_switching_key(ckks_ctx *ctx, uint64_t key_id, uint64_t *buf, size_t cap_words);
 int ckks_export_secret(ckks_ctx *ctx, int64_t *buf, size_t cap);
 int ckks_export_public_key(ckks_ctx *ctx, uint64_t *buf, size_t cap_words);
@@ -183,7 +187,7 @@ int ckks_conjugate(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out);
  * then rescale; result scale (s * s) / q. */
 int ckks_mul_mask(ckks_ctx *ctx, const ckks_ct *a, int R, ckks_ct **out);
 /* Negacyclic NTT of `count` limbs in place on device memory laid out [count][N],
- * limb i modulo chain modulus moduli_index[i] (0..L, L+1 = P); forward (dir = 1)
+ * limb i modulo chain modulus moduli_index[i] (0..L, then L+1, L+2 = p_1, p_2); forward (dir = 1)
  * to this library's evaluation order or inverse (dir = -1).  Host array of indices. */
 int ckks_ntt_device(ckks_ctx *ctx, uint64_t *dev_limbs, int count, const int *moduli_index, int dir);
 

@@ -143,10 +143,13 @@ def automorph(a: Sequence[int], g: int, mod: int) -> List[int]:
 class BigCKKS:
     """Tiny-ring CKKS over big integers with the same definitions as the oracle."""
 
-    def __init__(self, N: int, q: Sequence[int], P: int):
+    def __init__(self, N: int, q: Sequence[int], P: Sequence[int]):
         self.N = N
         self.q = list(q)     # q_0 .. q_L
-        self.P = P
+        self.p = list(P)     # special primes
+        self.P = 1
+        for v in self.p:
+            self.P *= v
         self.L = len(q) - 1
 
     def Q(self, l: int) -> int:
@@ -156,14 +159,24 @@ class BigCKKS:
         return out
 
     def mods_qp(self) -> List[int]:
-        return self.q + [self.P]
+        return self.q + self.p
+
+    @staticmethod
+    def groups(l: int) -> List[List[int]]:
+        """Key-switching digit groups of l limbs: {0}, {1, 2}, {3, 4}, ... cut at l."""
+        out = [[0]]
+        i = 1
+        while i < l:
+            out.append(list(range(i, min(i + 2, l))))
+            i += 2
+        return out
 
     # ---- keys
     def secret(self, seed: int, h: int) -> List[int]:
         return sample_hwt(seed, 1, self.N, h)
 
     def uniform_poly_qp(self, seed: int, sid: int) -> List[int]:
-        """Uniform element of Z_{QP}[X] whose residue mod q_t (t <= L) and mod P (index L+1) is sampled."""
+        """Uniform element of Z_{QP}[X] whose residue modulo each q_t and p_k (indices 0..L+2) is sampled."""
         res = [sample_uniform_residues(seed, sid, t, m, self.N) for t, m in enumerate(self.mods_qp())]
         return crt(res, self.mods_qp())
 
@@ -179,18 +192,20 @@ class BigCKKS:
         return b, a
 
     def switching_key(self, s, s_prime, seed: int, sid_base: int):
-        """ksk_j = (-a_j s + e_j + P * g_j * s', a_j) mod Q_L P with g_j the CRT indicator of q_j."""
+        """ksk_b = (-a_b s + e_b + P * g_b * s', a_b) mod Q_L P, g_b the CRT idempotent of group b."""
         QL = self.Q(self.L + 1)
         QP = QL * self.P
         keys = []
-        for j in range(self.L + 1):
-            a = self.uniform_poly_qp(seed, sid_base + 2 * j)
-            e = sample_cbd(seed, sid_base + 2 * j + 1, self.N)
-            Mj = QL // self.q[j]
-            gj = Mj * pow(Mj, -1, self.q[j])
+        for b, grp in enumerate(self.groups(self.L + 1)):
+            a = self.uniform_poly_qp(seed, sid_base + 2 * b)
+            e = sample_cbd(seed, sid_base + 2 * b + 1, self.N)
+            g = 0
+            for j in grp:
+                Mj = QL // self.q[j]
+                g += Mj * pow(Mj, -1, self.q[j])
             t = polymul(a, s, QP)
-            b = [(-t[k] + e[k] + self.P * gj * s_prime[k]) % QP for k in range(self.N)]
-            keys.append((b, a))
+            kb = [(-t[k] + e[k] + self.P * g * s_prime[k]) % QP for k in range(self.N)]
+            keys.append((kb, a))
         return keys
 
     # ---- encryption
@@ -216,38 +231,57 @@ class BigCKKS:
         d2 = polymul(a[1], b[1], Ql)
         return d0, d1, d2
 
-    def keyswitch(self, d: Sequence[int], keys, l: int):
-        """round( sum_{j < l} [d]_{q_j} * ksk_j / P ) mod Q_l, with the key restricted to Q_l P."""
+    def digits(self, d: Sequence[int], l: int) -> List[List[int]]:
+        """D_b = sum_{i in G_b} [d_i (Q_G/q_i)^-1]_{q_i} (Q_G/q_i) for every group of l limbs (integers)."""
+        out = []
+        for grp in self.groups(l):
+            QG = 1
+            for i in grp:
+                QG *= self.q[i]
+            D = [0] * self.N
+            for i in grp:
+                qi, hat = self.q[i], QG // self.q[i]
+                hinv = pow(hat % qi, -1, qi)
+                for k, v in enumerate(d):
+                    D[k] += ((v % qi) * hinv % qi) * hat
+            out.append(D)
+        return out
+
+    def moddown(self, x: Sequence[int], l: int) -> List[int]:
+        """(x - C) / P mod Q_l for x mod Q_l P, C = sum_k [x (P/p_k)^-1]_{p_k} (P/p_k)."""
         Ql = self.Q(l)
-        QP = Ql * self.P
-        acc0 = [0] * self.N
-        acc1 = [0] * self.N
-        for j in range(l):
-            dj = [v % self.q[j] for v in d]
-            b, a = keys[j]
-            t0 = polymul(dj, [v % QP for v in b], QP)
-            t1 = polymul(dj, [v % QP for v in a], QP)
-            acc0 = polyadd(acc0, t0, QP)
-            acc1 = polyadd(acc1, t1, QP)
-        return round_div(acc0, QP, self.P, Ql), round_div(acc1, QP, self.P, Ql)
+        out = []
+        for v in x:
+            C = 0
+            for pk in self.p:
+                hat = self.P // pk
+                C += (v * pow(hat % pk, -1, pk) % pk) * hat
+            assert (v - C) % self.P == 0
+            out.append(((v - C) // self.P) % Ql)
+        return out
+
+    def keyswitch(self, d: Sequence[int], keys, l: int):
+        """Key switch of d (an element of Z_{Q_l}[X]) with the key `keys` (keyswitch_galois, no automorphism)."""
+        return self.keyswitch_galois(d, [(0, keys)], l)
 
     def keyswitch_galois(self, d: Sequence[int], key_list, l: int):
-        """round( sum_i sum_{j < l} sigma_{g_i}([d]_{q_j}) * ksk_{i,j} / P ) mod Q_l for key_list = [(g_i, keys_i)]:
-        each digit, an integer polynomial with coefficients in [0, q_j), is permuted by X -> X^{g_i}
-        (g_i = 0: not permuted) before the product; one division by P for the whole sum."""
+        """(x - C) / P for x = sum_i sum_b sigma_{g_i}(D_b) * ksk_{i,b} mod Q_l P, key_list = [(g_i, keys_i)]:
+        each digit D_b (an integer polynomial) is permuted by X -> X^{g_i} (g_i = 0: not permuted)
+        before the product; one division by P for the whole sum."""
         Ql = self.Q(l)
         QP = Ql * self.P
+        D = self.digits(d, l)
         acc0 = [0] * self.N
         acc1 = [0] * self.N
         for g, keys in key_list:
-            for j in range(l):
-                dj = [v % self.q[j] for v in d]
+            for b, Db in enumerate(D):
+                db = [v % QP for v in Db]
                 if g:
-                    dj = automorph(dj, g, QP)
-                b, a = keys[j]
-                acc0 = polyadd(acc0, polymul(dj, [v % QP for v in b], QP), QP)
-                acc1 = polyadd(acc1, polymul(dj, [v % QP for v in a], QP), QP)
-        return round_div(acc0, QP, self.P, Ql), round_div(acc1, QP, self.P, Ql)
+                    db = automorph(db, g, QP)
+                kb, ka = keys[b]
+                acc0 = polyadd(acc0, polymul(db, [v % QP for v in kb], QP), QP)
+                acc1 = polyadd(acc1, polymul(db, [v % QP for v in ka], QP), QP)
+        return self.moddown(acc0, l), self.moddown(acc1, l)
 
     def apply_galois(self, ct, g: int, keys, l: int):
         """(sigma_g(c0), 0) + key switch of sigma_g(c1) from sigma_g(s) back to s."""

@@ -12,9 +12,10 @@ evaluation operations with level and scale tracking.
 Readings taken where the paper is silent (the paper describes the non-RNS
 scheme with power-of-two moduli):
 
-* Prime chain.  q_0 is the largest prime below 2^60 and the special prime P the
-  largest prime below 2^62 that are 1 mod 2N (a special prime above q_0 keeps
-  the key-switching noise of the q_0 digit small).  Rescale primes come from a pool of
+* Prime chain.  q_0 is the largest prime below 2^60 that is 1 mod 2N.  The
+  special modulus P = p_1 p_2 is the product of the two largest primes below 2^41
+  that are 1 mod 2N and not in the chain (P above every digit modulus keeps the
+  key-switching noise small).  Rescale primes come from a pool of
   the 4L primes that are 1 mod 2N and nearest to 2^b; for depth d = 0..L-1 the
   unused pool prime nearest to Delta_d^2 / 2^b becomes q_{L-d} (ties to the
   smaller prime), and Delta_{d+1} = (Delta_d * Delta_d) / q_{L-d} in FP64, with
@@ -31,6 +32,14 @@ scheme with power-of-two moduli):
   q and declare the target scale (the residual is below 1 / (2 * integer)).
 * Multiplication: tensor product, relinearisation, then rescale by the last
   prime; the result scale is (s_a * s_b) / q in FP64.
+* Key switching (the paper's non-RNS KeyGen / Mult, in RNS with a hybrid
+  decomposition): digit groups {q_0}, {q_1, q_2}, {q_3, q_4}, ... (digit_groups);
+  a ciphertext with l limbs uses each group's members below l.  Digit b is the
+  integer D_b = sum_{i in G_b} [d_i (Q_G/q_i)^-1]_{q_i} (Q_G/q_i) (fast basis
+  conversion), key b is (-a_b s + e_b + P e_{G_b} s', a_b) mod Q_L P with e_G the
+  CRT idempotent of the group (1 modulo its primes, 0 modulo the other q_i), and
+  the sum of digit-key products x is divided by P as (x - C) / P with
+  C = sum_k [x (P/p_k)^-1]_{p_k} (P/p_k).
 """
 from __future__ import annotations
 
@@ -86,12 +95,11 @@ def lib():
         L.ref_tensor.argtypes = [ctypes.c_void_p, ctypes.c_int, _u64p, _u64p, _u64p, ctypes.c_int]
         L.ref_rescale.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _u64p, _u64p]
         L.ref_automorph.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _u64p, ctypes.c_uint64, _u64p]
-        L.ref_keyswitch.argtypes = [ctypes.c_void_p, ctypes.c_int, _u64p, ctypes.c_int, _u64p,
-                                    ctypes.POINTER(_u64p), ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64p]
+        L.ref_keyswitch.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _u64p, ctypes.c_int, _u64p,
+                                    ctypes.POINTER(_u64p), ctypes.c_int, _u64p]
         L.ref_gen_ksk.argtypes = [ctypes.c_void_p, ctypes.c_int, _i64p, _u64p, ctypes.c_uint64, ctypes.c_uint64,
                                   ctypes.c_int, _u64p]
-        L.ref_key_to_eval.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64p,
-                                      _u64p]
+        L.ref_key_to_eval.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _u64p, _u64p]
         L.ref_num_threads.restype = ctypes.c_int
         L.ref_gen_pk.argtypes = [ctypes.c_void_p, ctypes.c_int, _i64p, ctypes.c_uint64, ctypes.c_uint64,
                                  ctypes.c_uint64, _u64p]
@@ -170,7 +178,7 @@ class Params:
     L: int
     b: int                 # log2 of the base scale
     q: List[int]           # q_0 .. q_L
-    P: int
+    P: List[int]           # special primes p_1, p_2 (P = p_1 p_2)
     scales: List[float]    # canonical scale at depth 0..L
 
     @property
@@ -187,6 +195,24 @@ class Params:
     def q_dropped_at_depth(self, d: int) -> int:
         """Prime removed by the rescale that takes depth d to d+1."""
         return self.q[self.L - d]
+
+    @property
+    def P_prod(self) -> int:
+        out = 1
+        for p in self.P:
+            out *= p
+        return out
+
+
+def digit_groups(l: int) -> List[List[int]]:
+    """Limb indices of the key-switching digit groups of a ciphertext with l limbs: {0}, then
+    consecutive pairs {1, 2}, {3, 4}, ... cut at l."""
+    out = [[0]] if l >= 1 else []
+    i = 1
+    while i < l:
+        out.append(list(range(i, min(i + 2, l))))
+        i += 2
+    return out
 
 
 def largest_ntt_prime_below(bits: int, N: int, skip: int = 0) -> int:
@@ -206,7 +232,6 @@ def make_params(logN: int, L: int, b: int) -> Params:
     N = 1 << logN
     M = 2 * N
     q0 = largest_ntt_prime_below(60, N)
-    P = largest_ntt_prime_below(62, N)
     # pool: the 4L primes that are 1 mod 2N nearest to 2^b
     center = 1 << b
     pool: List[int] = []
@@ -243,7 +268,14 @@ def make_params(logN: int, L: int, b: int) -> Params:
         used.add(p)
         chain[L - d] = p
         scales.append((s * s) / float(p))
-    return Params(logN=logN, L=L, b=b, q=chain, P=P, scales=scales)
+    special: List[int] = []
+    skip = 0
+    while len(special) < 2:
+        p = largest_ntt_prime_below(41, N, skip)
+        skip += 1
+        if p not in chain:
+            special.append(p)
+    return Params(logN=logN, L=L, b=b, q=chain, P=special, scales=scales)
 
 
 # --------------------------------------------------------------------------
@@ -400,14 +432,15 @@ class Oracle:
     def __init__(self, params: Params):
         self.p = params
         N = params.N
-        self.mods = list(params.q) + [params.P]
-        self.pidx = params.L + 1
+        self.mods = list(params.q) + list(params.P)
+        self.pidx = params.L + 1          # modulus index of p_1 (p_2 follows)
+        self.ng = len(digit_groups(params.L + 1))
         qs = np.array(self.mods, dtype=np.uint64)
         psis = np.array([primitive_2n_root(q, N) for q in self.mods], dtype=np.uint64)
         self._ctx = lib().ref_ctx_new(N, len(self.mods), _p(qs), _p(psis))
         self.sk: Optional[np.ndarray] = None
         self.pk: Optional[np.ndarray] = None
-        self.keys: Dict[int, np.ndarray] = {}      # coefficient form [2][L+1][L+2][N]
+        self.keys: Dict[int, np.ndarray] = {}      # coefficient form [2][groups][L+3][N]
         self._kev: Dict[int, np.ndarray] = {}      # oracle evaluation form
         self.n_keyswitch = 0
 
@@ -453,11 +486,11 @@ class Oracle:
     def _add_key(self, K: int, sp: np.ndarray) -> None:
         p = self.p
         N, L = p.N, p.L
-        key = np.zeros((2, L + 1, L + 2, N), dtype=np.uint64)
+        key = np.zeros((2, self.ng, L + 3, N), dtype=np.uint64)
         lib().ref_gen_ksk(self._ctx, L, _p(self.sk), _p(np.ascontiguousarray(sp)), self._seed,
                           ksk_sid_base(K), self._max_l, _p(key))
         kev = np.zeros_like(key)
-        lib().ref_key_to_eval(self._ctx, L + 1, L + 2, self.pidx, self._max_l, _p(key), _p(kev))
+        lib().ref_key_to_eval(self._ctx, L, self._max_l, _p(key), _p(kev))
         self.keys[K] = key
         self._kev[K] = kev
 
@@ -578,15 +611,15 @@ class Oracle:
         return Ct(a.data, a.depth, a.scale * factor)
 
     def keyswitch(self, d: np.ndarray, K: int) -> np.ndarray:
-        """round(sum_j [d]_{q_j} * ksk_j / P) for the key with id K; d is [l][N]."""
+        """Key switch of d ([l][N], coefficient form) with the key of id K (keyswitch_galois, no automorphism)."""
         return self.keyswitch_galois(d, [(0, K)])
 
     def keyswitch_galois(self, d: np.ndarray, pairs: Sequence[Tuple[int, int]]) -> np.ndarray:
-        """round(sum_i sum_j sigma_{g_i}([d]_{q_j}) * ksk_{K_i, j} / P) for pairs (g_i, K_i); d is [l][N].
+        """(x - C) / P for x = sum_i sum_b sigma_{g_i}(D_b) * ksk_{K_i, b}, pairs (g_i, K_i); d is [l][N].
 
-        One decomposition of d serves every key: each digit is lifted to the target moduli first and
-        then permuted by its automorphism (g = 0: none), and all products are summed before the single
-        division by P."""
+        One decomposition of d (the digits D_b of the module docstring) serves every key: each digit
+        is taken modulo the target moduli first and then permuted by its automorphism (g = 0: none),
+        and all products are summed before the single division by P."""
         l = d.shape[0]
         if l > self._max_l:
             raise ValueError("keys were generated for at most %d limbs" % self._max_l)
@@ -594,8 +627,8 @@ class Oracle:
         out = np.zeros((2, l, p.N), dtype=np.uint64)
         gal = np.array([g for g, _ in pairs], dtype=np.uint64)
         kevs = (_u64p * len(pairs))(*[_p(self._kev[K]) for _, K in pairs])
-        lib().ref_keyswitch(self._ctx, l, _p(np.ascontiguousarray(d)), len(pairs), _p(gal), kevs, p.L + 1, p.L + 2,
-                            self.pidx, _p(out))
+        lib().ref_keyswitch(self._ctx, p.L, l, _p(np.ascontiguousarray(d)), len(pairs), _p(gal), kevs, self.ng,
+                            _p(out))
         self.n_keyswitch += 1
         return out
 

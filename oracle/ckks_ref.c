@@ -388,15 +388,31 @@ void ref_automorph(const ref_ctx *c, int npoly, int l, const u64 *in, u64 g, u64
 }
 
 /*
+ * Digit groups of the key switch (hybrid decomposition): group 0 is {q_0}, group b >= 1 is
+ * {q_{2b-1}, q_{2b}}; a ciphertext with l limbs uses the groups with a member below l, each
+ * restricted to its members below l.  Special primes: modulus indices L+1 and L+2, P = p_1 p_2.
+ */
+static int grp_first(int b) { return b == 0 ? 0 : 2 * b - 1; }
+static int grp_size(int b, int l) {
+    int f = grp_first(b), e = b == 0 ? 1 : 2 * b + 1;   /* members [f, e) */
+    if (e > l) e = l;
+    return e > f ? e - f : 0;
+}
+int ref_num_groups(int l) { return 1 + l / 2; }          /* groups with a member below l */
+
+/*
  * Key switching of the polynomial d (coefficient form, limbs 0..l-1) with one or
- * several keys, each given in the oracle's evaluation form: kevs[i][comp][j][t][N]
- * for digits j < nd and targets t < nt where target index t < nq is q_t and
- * t == nq is the special prime.  A key stores targets 0..L and P (nt = L + 2),
- * digits 0..L.  Key i is paired with the automorphism X -> X^galois[i] of the
- * digits (galois[i] == 0: none), applied after each digit [d]_{q_j} has been
- * lifted to the target modulus; the products of all keys are summed before the
- * single division by P (one decomposition of d serves every key):
- *   out[2][l][N] = round( sum_i sum_{j<l} sigma_i([d]_{q_j}) * ksk_{i,j} / P ) mod q_0..q_{l-1}.
+ * several keys, each given in the oracle's evaluation form: kevs[i][comp][b][t][N]
+ * for the ng groups b and the nt = L + 3 targets t (q_0..q_L, p_1, p_2).
+ *
+ * Digits: for group b with members G (below l), Q_G = prod q_i, y_i = [d_i (Q_G/q_i)^-1]_{q_i},
+ * and the digit is the integer D_b = sum_{i in G} y_i (Q_G/q_i) (fast basis conversion: D_b = d mod
+ * Q_G up to a multiple of Q_G, which the keys' gadget annihilates).  Key i is paired with the
+ * automorphism X -> X^galois[i] of the digits (galois[i] == 0: none), applied after the digit has been
+ * taken modulo the target; the products of all keys are summed, then divided by P once:
+ *   x = sum_i sum_b sigma_i(D_b) ksk_{i,b}  mod (q_0..q_{l-1}, p_1, p_2),
+ *   out = (x - C) / P mod q_0..q_{l-1},  C = sum_k [x (P/p_k)^-1]_{p_k} (P/p_k)  (C = x mod P up to a
+ *   multiple of P, so the division is exact).
  */
 static void automorph_poly(int n, u64 q, const u64 *a, u64 g, u64 *o) {
     u64 twon = 2ULL * (u64)n;
@@ -407,25 +423,41 @@ static void automorph_poly(int n, u64 q, const u64 *a, u64 g, u64 *o) {
     }
 }
 
-void ref_keyswitch(const ref_ctx *c, int l, const u64 *d, int n_keys, const u64 *galois, const u64 *const *kevs,
-                   int nd, int nt, int pidx, u64 *out) {
-    int n = c->n;
-    size_t kstride_t = (size_t)n, kstride_j = (size_t)nt * n, kstride_c = (size_t)nd * nt * n;
+void ref_keyswitch(const ref_ctx *c, int L, int l, const u64 *d, int n_keys, const u64 *galois,
+                   const u64 *const *kevs, int ng, u64 *out) {
+    int n = c->n, nt = L + 3, gl = ref_num_groups(l);
+    size_t kstride_t = (size_t)n, kstride_b = (size_t)nt * n, kstride_c = (size_t)ng * nt * n;
+    /* y_i of every limb: d_i times (Q_G / q_i)^-1 modulo q_i */
+    u64 *y = (u64 *)malloc(sizeof(u64) * (size_t)l * n);
+    for (int b = 0; b < gl; ++b) {
+        int f = grp_first(b), m = grp_size(b, l);
+        for (int i = f; i < f + m; ++i) {
+            u64 qi = c->mods[i].q, hat = 1;
+            for (int j = f; j < f + m; ++j) if (j != i) hat = mulmod(hat, c->mods[j].q % qi, qi);
+            u64 hinv = invmod(hat, qi);
+            for (int k = 0; k < n; ++k) y[(size_t)i * n + k] = mulmod(d[(size_t)i * n + k], hinv, qi);
+        }
+    }
     /* accumulate, per target modulus, both components in evaluation form */
-    u64 *acc = (u64 *)calloc((size_t)2 * (l + 1) * n, sizeof(u64));
+    u64 *acc = (u64 *)calloc((size_t)2 * (l + 2) * n, sizeof(u64));
 #pragma omp parallel
     {
         u64 *dig = (u64 *)malloc(sizeof(u64) * n), *sg = (u64 *)malloc(sizeof(u64) * n),
             *fe = (u64 *)malloc(sizeof(u64) * n);
 #pragma omp for schedule(dynamic)
-        for (int ti = 0; ti <= l; ++ti) {
-            int mi = ti < l ? ti : pidx;         /* modulus of this target */
-            int tk = ti < l ? ti : nt - 1;       /* key target index */
+        for (int ti = 0; ti < l + 2; ++ti) {
+            int mi = ti < l ? ti : L + 1 + (ti - l);   /* modulus (and key target) of this target */
             u64 q = c->mods[mi].q;
-            u64 *a0 = acc + (size_t)ti * n, *a1 = acc + ((size_t)(l + 1) + ti) * n;
-            for (int j = 0; j < l; ++j) {
-                const u64 *dj = d + (size_t)j * n;
-                for (int k = 0; k < n; ++k) dig[k] = dj[k] % q;  /* [d]_{q_j} lifted to q */
+            u64 *a0 = acc + (size_t)ti * n, *a1 = acc + ((size_t)(l + 2) + ti) * n;
+            for (int b = 0; b < gl; ++b) {
+                int f = grp_first(b), m = grp_size(b, l);
+                /* D_b mod q: sum_i y_i (Q_G / q_i) */
+                for (int k = 0; k < n; ++k) dig[k] = 0;
+                for (int i = f; i < f + m; ++i) {
+                    u64 hat = 1;
+                    for (int j = f; j < f + m; ++j) if (j != i) hat = mulmod(hat, c->mods[j].q % q, q);
+                    for (int k = 0; k < n; ++k) dig[k] = addmod(dig[k], mulmod(y[(size_t)i * n + k] % q, hat, q), q);
+                }
                 for (int i = 0; i < n_keys; ++i) {
                     if (galois[i]) {
                         automorph_poly(n, q, dig, galois[i], sg);
@@ -433,8 +465,8 @@ void ref_keyswitch(const ref_ctx *c, int l, const u64 *d, int n_keys, const u64 
                     } else {
                         ref_to_eval(c, mi, dig, fe);
                     }
-                    const u64 *k0 = kevs[i] + 0 * kstride_c + j * kstride_j + tk * kstride_t;
-                    const u64 *k1 = kevs[i] + 1 * kstride_c + j * kstride_j + tk * kstride_t;
+                    const u64 *k0 = kevs[i] + 0 * kstride_c + b * kstride_b + mi * kstride_t;
+                    const u64 *k1 = kevs[i] + 1 * kstride_c + b * kstride_b + mi * kstride_t;
                     for (int k = 0; k < n; ++k) {
                         a0[k] = addmod(a0[k], mulmod(fe[k], k0[k], q), q);
                         a1[k] = addmod(a1[k], mulmod(fe[k], k1[k], q), q);
@@ -446,69 +478,75 @@ void ref_keyswitch(const ref_ctx *c, int l, const u64 *d, int n_keys, const u64 
         }
         free(dig); free(sg); free(fe);
     }
-    /* ModDown: round(x / P) = (x - [x]_P centred) / P */
-    u64 P = c->mods[pidx].q;
+    /* ModDown: (x - C) / P with C = sum_k [x (P/p_k)^-1]_{p_k} (P/p_k) */
+    u64 p1 = c->mods[L + 1].q, p2 = c->mods[L + 2].q;
+    u64 h1 = invmod(p2 % p1, p1), h2 = invmod(p1 % p2, p2);   /* (P/p_k)^-1 mod p_k */
     for (int comp = 0; comp < 2; ++comp) {
-        const u64 *xp = acc + ((size_t)comp * (l + 1) + l) * n;
+        const u64 *x1 = acc + ((size_t)comp * (l + 2) + l) * n, *x2 = x1 + n;
         for (int i = 0; i < l; ++i) {
-            u64 q = c->mods[i].q, pinv = invmod(P % q, q);
-            const u64 *xi = acc + ((size_t)comp * (l + 1) + i) * n;
+            u64 q = c->mods[i].q;
+            u64 c1 = p2 % q, c2 = p1 % q, pinv = invmod(mulmod(p1 % q, p2 % q, q), q);
+            const u64 *xi = acc + ((size_t)comp * (l + 2) + i) * n;
             u64 *o = out + ((size_t)comp * l + i) * n;
-            for (int k = 0; k < n; ++k) o[k] = mulmod(submod(xi[k], centred_to(xp[k], P, q), q), pinv, q);
+            for (int k = 0; k < n; ++k) {
+                u64 yk1 = mulmod(x1[k], h1, p1), yk2 = mulmod(x2[k], h2, p2);
+                u64 cv = addmod(mulmod(yk1 % q, c1, q), mulmod(yk2 % q, c2, q), q);
+                o[k] = mulmod(submod(xi[k], cv, q), pinv, q);
+            }
         }
     }
     free(acc);
+    free(y);
 }
 
 /*
- * Switching-key generation for a target secret s' (given as residues sp[t][N]
- * for t = 0..L) under secret s (signed coefficients).  Digits j = 0..L, targets
- * t = 0..L and P (index L+1 in the modulus table and in the key).
- *   b_j[t] = -a_j[t] * s + e_j + [t == j] * (P mod q_t) * s'[t],   a_j[t] uniform.
- * a_j is stream sid_base + 2 j, e_j is stream sid_base + 2 j + 1.
- * Output in coefficient form: key[comp][j][t][N], comp 0 = b, 1 = a.
+ * Switching key for s' (given as residues sp[t][N], t <= L) in coefficient form,
+ * key[2][ng][L+3][N]: for group b and target t (q_0..q_L, p_1, p_2),
+ *   key[0][b][t] = -a_b s + e_b + [t in group b] (P mod q_t) s'_t,   key[1][b][t] = a_b,
+ * a_b uniform with stream sid_base + 2b (modulus index t), e_b centred binomial with stream
+ * sid_base + 2b + 1.  max_l < L + 1: only the groups and targets a ciphertext of at most max_l
+ * limbs uses (the entries are those of the full key).
  */
 void ref_gen_ksk(const ref_ctx *c, int L, const i64 *s, const u64 *sp, u64 seed, u64 sid_base,
                  int max_l, u64 *key) {
-    int n = c->n, nt = L + 2, nd = L + 1;
-    size_t kc = (size_t)nd * nt * n;
-    u64 P = c->mods[L + 1].q;
+    int n = c->n, nt = L + 3, ng = ref_num_groups(L + 1);
+    size_t kc = (size_t)ng * nt * n;
+    u64 p1 = c->mods[L + 1].q, p2 = c->mods[L + 2].q;
 #pragma omp parallel
     {
         i64 *e = (i64 *)malloc(sizeof(i64) * n);
         u64 *sres = (u64 *)malloc(sizeof(u64) * n), *as = (u64 *)malloc(sizeof(u64) * n);
 #pragma omp for schedule(dynamic)
-        for (int jt = 0; jt < nd * nt; ++jt) {
-            int j = jt / nt, t = jt % nt;
-            /* max_l < L + 1: only the sub-block used by ciphertexts of at most max_l limbs */
-            if (j >= max_l || (t >= max_l && t != nt - 1)) continue;
+        for (int bt = 0; bt < ng * nt; ++bt) {
+            int b = bt / nt, t = bt % nt;
+            if (grp_first(b) >= max_l || (t >= max_l && t <= L)) continue;
             u64 q = c->mods[t].q;
-            u64 *b = key + (size_t)j * nt * n + (size_t)t * n;
-            u64 *a = key + kc + (size_t)j * nt * n + (size_t)t * n;
-            ref_sample_uniform(seed, sid_base + 2ULL * j, t, q, n, a);
-            ref_sample_cbd(seed, sid_base + 2ULL * j + 1, n, e);
+            u64 *kb = key + (size_t)b * nt * n + (size_t)t * n;
+            u64 *ka = key + kc + (size_t)b * nt * n + (size_t)t * n;
+            ref_sample_uniform(seed, sid_base + 2ULL * b, t, q, n, ka);
+            ref_sample_cbd(seed, sid_base + 2ULL * b + 1, n, e);
             for (int k = 0; k < n; ++k) sres[k] = from_signed(s[k], q);
-            ref_polymul(c, t, a, sres, as);
-            for (int k = 0; k < n; ++k) b[k] = addmod(submod(0, as[k], q), from_signed(e[k], q), q);
-            if (t == j) {
-                u64 pm = P % q;
+            ref_polymul(c, t, ka, sres, as);
+            for (int k = 0; k < n; ++k) kb[k] = addmod(submod(0, as[k], q), from_signed(e[k], q), q);
+            int f = grp_first(b), m = grp_size(b, L + 1);
+            if (t <= L && t >= f && t < f + m) {
+                u64 pm = mulmod(p1 % q, p2 % q, q);
                 const u64 *spt = sp + (size_t)t * n;
-                for (int k = 0; k < n; ++k) b[k] = addmod(b[k], mulmod(pm, spt[k], q), q);
+                for (int k = 0; k < n; ++k) kb[k] = addmod(kb[k], mulmod(pm, spt[k], q), q);
             }
         }
         free(e); free(sres); free(as);
     }
 }
 
-/* convert a coefficient-form key to the oracle's evaluation form (same layout) */
-void ref_key_to_eval(const ref_ctx *c, int nd, int nt, int pidx, int max_l, const u64 *key, u64 *kev) {
-    int n = c->n;
+/* key (coefficient form, [2][ng][nt][N]) -> the oracle's evaluation form, same layout */
+void ref_key_to_eval(const ref_ctx *c, int L, int max_l, const u64 *key, u64 *kev) {
+    int n = c->n, nt = L + 3, ng = ref_num_groups(L + 1);
 #pragma omp parallel for schedule(dynamic)
-    for (int x = 0; x < 2 * nd * nt; ++x) {
-        int t = x % nt, j = (x / nt) % nd;
-        if (j >= max_l || (t >= max_l && t != nt - 1)) continue;
-        int mi = t < nt - 1 ? t : pidx;
-        ref_to_eval(c, mi, key + (size_t)x * n, kev + (size_t)x * n);
+    for (int x = 0; x < 2 * ng * nt; ++x) {
+        int t = x % nt, b = (x / nt) % ng;
+        if (grp_first(b) >= max_l || (t >= max_l && t <= L)) continue;
+        ref_to_eval(c, t, key + (size_t)x * n, kev + (size_t)x * n);
     }
 }
 

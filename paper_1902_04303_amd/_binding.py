@@ -175,12 +175,12 @@ def _f64(a: np.ndarray):
 
 
 def chain(log_n: int, levels: int, log2_scale: int):
-    """Prime chain and canonical scales (host computation, no GPU)."""
+    """(q_0..q_L, [p_1, p_2], canonical scales): the moduli and scales of the parameters (host only)."""
     p = CkksParams(log_n, levels, log2_scale)
-    q = np.zeros(levels + 2, dtype=np.uint64)
+    q = np.zeros(levels + 3, dtype=np.uint64)
     s = np.zeros(levels + 1, dtype=np.float64)
     _check(lib().ckks_chain(ctypes.byref(p), _u64(q), _f64(s)))
-    return [int(v) for v in q[:-1]], int(q[-1]), [float(v) for v in s]
+    return [int(v) for v in q[:levels + 1]], [int(v) for v in q[levels + 1:]], [float(v) for v in s]
 
 
 def gwas_galois_elements(log_n: int, R: int) -> List[int]:
@@ -283,7 +283,7 @@ class Context:
 
     # ---- parameters
     def moduli(self) -> List[int]:
-        a = np.zeros(self.levels + 2, dtype=np.uint64)
+        a = np.zeros(self.levels + 3, dtype=np.uint64)
         _check(lib().ckks_ctx_moduli(self.h, _u64(a), len(a)))
         return [int(v) for v in a]
 
@@ -334,7 +334,7 @@ class Context:
 
     def export_switching_key(self, key_id: int) -> np.ndarray:
         L = self.levels
-        a = np.zeros((2, L + 1, L + 2, self.N), dtype=np.uint64)
+        a = np.zeros((2, 1 + (L + 1) // 2, L + 3, self.N), dtype=np.uint64)
         _check(lib().ckks_export_switching_key(self.h, key_id, _u64(a), a.size))
         return a
 

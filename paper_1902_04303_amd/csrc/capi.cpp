@@ -66,8 +66,111 @@ int bit_reverse(int x, int bits) {
     return r;
 }
 
+LimbScale limb_scale(u64 w, u64 q) { return LimbScale{w, shoup_of(w, q), (double)w}; }
+
+ConvEntry conv_entry(int src, int nsrc, int chain, const u64 *cs, u64 q, const std::vector<u64> &src_mods) {
+    ConvEntry e{};
+    e.src = src;
+    e.nsrc = nsrc;
+    e.chain = chain;
+    e.big = 0;
+    for (int m = 0; m < nsrc; ++m) {
+        e.c[m] = cs[m] % q;
+        e.c_sh[m] = shoup_of(e.c[m], q);
+        e.cd[m] = (double)e.c[m];
+        if (src_mods[m] >= (1ULL << 47)) e.big = 1;
+    }
+    return e;
+}
+
+// key-switch tables (ModUp conversion per level, digit indices, inverse-NTT scales; ModDown conversion)
+void build_ks_tables(ckks_ctx &c) {
+    const Params &p = c.p;
+    const int L = p.levels, nq = L + 1;
+    std::vector<std::vector<ConvEntry>> ups(nq + 1);
+    std::vector<std::vector<int>> didx(nq + 1);
+    std::vector<std::vector<LimbScale>> scales(nq + 1);
+    for (int l = 1; l <= nq; ++l) {
+        const int gl = ks_groups(l), nt = l + kSpecial;
+        didx[l].assign((size_t)gl * nt, -1);
+        scales[l].resize(l);
+        for (int b = 0; b < gl; ++b) {
+            const int f = ks_group_first(b), m = ks_group_size(b, l);
+            std::vector<u64> mods;
+            for (int i = f; i < f + m; ++i) mods.push_back(p.q[i]);
+            // y_i = d_i (Q_G / q_i)^-1, folded with N^-1 into the inverse NTT
+            for (int i = f; i < f + m; ++i) {
+                const u64 qi = p.q[i];
+                u64 hat = 1;
+                for (int j = f; j < f + m; ++j)
+                    if (j != i) hat = mulmod_host(hat, p.q[j] % qi, qi);
+                const u64 w = mulmod_host(invmod_host((u64)p.n % qi, qi), invmod_host(hat, qi), qi);
+                scales[l][i] = limb_scale(w, qi);
+            }
+            for (int t = 0; t < nt; ++t) {
+                if (t < l && t >= f && t < f + m) continue;   // the digit's own primes: the input residue
+                const int chain = t < l ? t : L + 1 + (t - l);
+                const u64 qt = p.mod(chain);
+                u64 cs[2] = {1, 1};
+                for (int a = 0; a < m; ++a) {
+                    u64 hat = 1;
+                    for (int j = f; j < f + m; ++j)
+                        if (j != f + a) hat = mulmod_host(hat, p.q[j] % qt, qt);
+                    cs[a] = hat;
+                }
+                didx[l][(size_t)b * nt + t] = (int)ups[l].size();
+                ups[l].push_back(conv_entry(f, m, chain, cs, qt, mods));
+            }
+        }
+    }
+    std::vector<ConvEntry> down(nq);
+    for (int i = 0; i < nq; ++i) {
+        const u64 cs[2] = {p.P[1], p.P[0]};   // P / p_1, P / p_2
+        down[i] = conv_entry(0, kSpecial, i, cs, p.q[i], p.P);
+    }
+    std::vector<LimbScale> dscale(kSpecial);
+    for (int k = 0; k < kSpecial; ++k) {
+        const u64 pk = p.P[k], other = p.P[1 - k];
+        dscale[k] = limb_scale(mulmod_host(invmod_host((u64)p.n % pk, pk), invmod_host(other % pk, pk), pk), pk);
+    }
+    for (int i = 0; i < p.n_mods(); ++i) {
+        const u64 q = p.mod(i);
+        const u64 pm = mulmod_host(p.P[0] % q, p.P[1] % q, q);
+        c.p_inv.v[i] = pm ? invmod_host(pm, q) : 0;
+        c.p_inv.sh[i] = shoup_of(c.p_inv.v[i], q);
+    }
+    // one device block for everything
+    size_t bytes = 0;
+    auto room = [&](size_t b) { size_t o = bytes; bytes += (b + 255) / 256 * 256; return o; };
+    std::vector<size_t> o_up(nq + 1), o_didx(nq + 1), o_sc(nq + 1);
+    for (int l = 1; l <= nq; ++l) {
+        o_up[l] = room(ups[l].size() * sizeof(ConvEntry));
+        o_didx[l] = room(didx[l].size() * sizeof(int));
+        o_sc[l] = room(scales[l].size() * sizeof(LimbScale));
+    }
+    const size_t o_down = room(down.size() * sizeof(ConvEntry)), o_dsc = room(dscale.size() * sizeof(LimbScale));
+    GCK_HIP(hipMalloc(&c.ks_mem, bytes));
+    char *base = static_cast<char *>(c.ks_mem);
+    c.ks_levels.assign(nq + 1, ckks_ctx::KsLevel{});
+    for (int l = 1; l <= nq; ++l) {
+        auto &kl = c.ks_levels[l];
+        kl.K = (int)ups[l].size();
+        kl.up = reinterpret_cast<ConvEntry *>(base + o_up[l]);
+        kl.didx = reinterpret_cast<int *>(base + o_didx[l]);
+        kl.up_scale = reinterpret_cast<LimbScale *>(base + o_sc[l]);
+        GCK_HIP(hipMemcpy(kl.up, ups[l].data(), ups[l].size() * sizeof(ConvEntry), hipMemcpyHostToDevice));
+        GCK_HIP(hipMemcpy(kl.didx, didx[l].data(), didx[l].size() * sizeof(int), hipMemcpyHostToDevice));
+        GCK_HIP(hipMemcpy(kl.up_scale, scales[l].data(), scales[l].size() * sizeof(LimbScale), hipMemcpyHostToDevice));
+    }
+    c.down_conv = reinterpret_cast<ConvEntry *>(base + o_down);
+    c.down_scale = reinterpret_cast<LimbScale *>(base + o_dsc);
+    GCK_HIP(hipMemcpy(c.down_conv, down.data(), down.size() * sizeof(ConvEntry), hipMemcpyHostToDevice));
+    GCK_HIP(hipMemcpy(c.down_scale, dscale.data(), dscale.size() * sizeof(LimbScale), hipMemcpyHostToDevice));
+    c.ng = ks_groups(nq);
+}
+
 void build_tables(ckks_ctx &c) {
-    const int n = c.p.n, n_mods = c.p.levels + 2;
+    const int n = c.p.n, n_mods = c.p.n_mods();
     const size_t N = (size_t)n;
     std::vector<u64> psi(N * n_mods), psi_sh(N * n_mods), ipsi(N * n_mods), ipsi_sh(N * n_mods);
     std::vector<double> psi_f(N * n_mods), ipsi_f(N * n_mods);
@@ -150,8 +253,7 @@ int ckks_chain(const ckks_params *params, uint64_t *moduli, double *scales) {
     return guard([&] {
         need(params && moduli && scales, "null argument");
         Params p = make_params(params->log_n, params->levels, params->log2_scale);
-        for (int i = 0; i <= p.levels; ++i) moduli[i] = p.q[i];
-        moduli[p.levels + 1] = p.P;
+        for (int i = 0; i < p.n_mods(); ++i) moduli[i] = p.mod(i);
         for (int i = 0; i <= p.levels; ++i) scales[i] = p.scales[i];
     });
 }
@@ -167,6 +269,7 @@ int ckks_ctx_create(const ckks_params *params, const ckks_allocator *allocator, 
         c->pool = std::make_unique<Pool>(allocator, pool_budget_bytes);
         c->pool->stream = c->stream;
         build_tables(*c);
+        build_ks_tables(*c);
         c->tab.timer = &c->timer;
         *out = c.release();
     });
@@ -176,9 +279,8 @@ void ckks_ctx_destroy(ckks_ctx *ctx) { delete ctx; }
 
 int ckks_ctx_moduli(const ckks_ctx *ctx, uint64_t *moduli, int cap) {
     return guard_ctx(ctx, [&] {
-        need(ctx && moduli && cap >= ctx->p.levels + 2, "bad buffer");
-        for (int i = 0; i <= ctx->p.levels; ++i) moduli[i] = ctx->p.q[i];
-        moduli[ctx->p.levels + 1] = ctx->p.P;
+        need(ctx && moduli && cap >= ctx->p.n_mods(), "bad buffer");
+        for (int i = 0; i < ctx->p.n_mods(); ++i) moduli[i] = ctx->p.mod(i);
     });
 }
 
@@ -264,14 +366,14 @@ int ckks_export_switching_key(ckks_ctx *ctx, uint64_t key_id, uint64_t *buf, siz
         need(ctx && buf, "null argument");
         auto it = ctx->ksk.find(key_id);
         if (it == ctx->ksk.end()) throw Error(CKKS_E_KEY_MISSING, "no such key");
-        const int L = ctx->p.levels, nt = L + 2, nd = L + 1;
-        const size_t N = (size_t)ctx->p.n, words = (size_t)2 * nd * nt * N;
+        const int L = ctx->p.levels, nt = ctx->p.n_mods(), ng = ctx->ng;
+        const size_t N = (size_t)ctx->p.n, words = (size_t)2 * ng * nt * N;
         need(cap_words >= words, "buffer too small");
         DBuf t(ctx->pool.get(), words);
         GCK_HIP(hipMemcpyAsync(t.ptr, it->second.ptr, words * 8, hipMemcpyDeviceToDevice, ctx->stream));
         const ModMap mt{nt, L + 1, L + 1};
-        k_from_mont(ctx->tab, t.ptr, 2 * nd * nt, mt, ctx->stream);
-        ntt_inv(*ctx, t.ptr, 2 * nd * nt, mt);
+        k_from_mont(ctx->tab, t.ptr, 2 * ng * nt, mt, ctx->stream);
+        ntt_inv(*ctx, t.ptr, 2 * ng * nt, mt);
         GCK_HIP(hipMemcpyAsync(buf, t.ptr, words * 8, hipMemcpyDeviceToHost, ctx->stream));
         sync(*ctx);
     });
@@ -468,7 +570,7 @@ int ckks_mul_mask(ckks_ctx *ctx, const ckks_ct *a, int R, ckks_ct **out) {
 int ckks_ntt_device(ckks_ctx *ctx, uint64_t *dev_limbs, int count, const int *moduli_index, int dir) {
     return guard_ctx(ctx, [&] {
         need(ctx && dev_limbs && moduli_index && count >= 0 && (dir == 1 || dir == -1), "bad arguments");
-        for (int i = 0; i < count; ++i) need(moduli_index[i] >= 0 && moduli_index[i] <= ctx->p.levels + 1,
+        for (int i = 0; i < count; ++i) need(moduli_index[i] >= 0 && moduli_index[i] < ctx->p.n_mods(),
                                              "modulus index out of range");
         for (int i = 0; i < count;) {   // one launch per run of limbs with the same modulus
             int e = i + 1;

@@ -19,7 +19,8 @@ using u64 = uint64_t;
 using i64 = int64_t;
 using u128 = unsigned __int128;
 
-constexpr int kMaxMods = 64;   // q_0..q_L and P
+constexpr int kMaxMods = 64;   // q_0..q_L and the special primes
+constexpr int kSpecial = 2;    // special primes p_1, p_2 of the key-switching modulus P = p_1 p_2
 
 // ---------------------------------------------------------------- errors
 struct Error : std::runtime_error {
@@ -51,13 +52,22 @@ constexpr int kFpModBits = 41;
 struct Params {
     int log_n = 0, n = 0, levels = 0, log2_scale = 0;
     std::vector<u64> q;        // q_0 .. q_L
-    u64 P = 0;
+    std::vector<u64> P;        // special primes p_1 .. p_kSpecial
     std::vector<double> scales;  // canonical Delta_0 .. Delta_L
     int limbs_at(int depth) const { return levels + 1 - depth; }
     u64 dropped_at(int depth) const { return q[levels - depth]; }  // prime removed by the rescale at depth
-    int p_index() const { return levels + 1; }
-    u64 mod(int idx) const { return idx <= levels ? q[idx] : P; }
+    int p_index() const { return levels + 1; }                      // chain index of p_1
+    int n_mods() const { return levels + 1 + kSpecial; }            // chain indices q_0..q_L, p_1..
+    u64 mod(int idx) const { return idx <= levels ? q[idx] : P[idx - levels - 1]; }
 };
+// Key-switching digit groups (hybrid decomposition): group 0 is {q_0}, group b >= 1 is {q_{2b-1}, q_{2b}};
+// a ciphertext with l limbs uses the 1 + l / 2 groups with a member below l, cut at l.
+__host__ __device__ inline int ks_groups(int l) { return 1 + l / 2; }
+__host__ __device__ inline int ks_group_first(int b) { return b == 0 ? 0 : 2 * b - 1; }
+__host__ __device__ inline int ks_group_size(int b, int l) {
+    const int f = ks_group_first(b), e = b == 0 ? 1 : 2 * b + 1;
+    return (e < l ? e : l) - f;
+}
 Params make_params(int log_n, int levels, int log2_scale);
 u64 mulmod_host(u64 a, u64 b, u64 q);
 u64 powmod_host(u64 b, u64 e, u64 q);
@@ -109,10 +119,10 @@ struct DBuf {
 
 // ---------------------------------------------------------------- kernels (kernels.hip)
 // Every polynomial buffer is a contiguous array of limbs of N words.  The chain
-// index (0..L for q_i, L+1 for P) of limb lam is given by a ModMap:
-//     t = lam % period;  chain = (t < nq) ? t : p_idx
-// e.g. ciphertext data [count][2][l][N] has period = nq = l; ModUp digits
-// [count][l][l+1][N] have period l+1, nq = l.
+// index (0..L for q_i, L+1.. for the special primes) of limb lam is given by a ModMap:
+//     t = lam % period;  chain = (t < nq) ? t : p_idx + (t - nq)
+// and t >= nq is the special prime p_idx + (t - nq); e.g. ciphertext data [count][2][l][N] has
+// period = nq = l; key-switch accumulators [count][2][l + kSpecial][N] have period l + kSpecial, nq = l.
 struct ModMap {
     int period, nq, p_idx;
 };
@@ -164,15 +174,33 @@ void k_ntt_inverse(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStrea
 // and how the word is brought to output limb lam's modulus: kPlain (already reduced),
 // kReduce (any word < 2^64, e.g. a digit of another modulus: ModUp), kCentred (centred lift of a
 // residue modulo chain src_chain: rescale and ModDown).
+// kConv: basis conversion.  Output limb lam takes entry e = conv[lam % conv_period] and row
+// r = lam / conv_period; its modulus is chain e.chain and its word is sum_{m < e.nsrc} y_m c_m mod that
+// modulus, y_m = src limb r * src_stride + e.src + m (a residue of another modulus, below 2^47 unless
+// e.big), c_m = e.c[m] (with its Shoup companion and FP64 copy).
+struct ConvEntry {
+    int src, nsrc, chain, big;
+    u64 c[2], c_sh[2];
+    double cd[2];
+};
 struct Gather {
     const u64 *ptr;
     int div, mul, add, inner;
     int mode, src_chain;
+    const ConvEntry *conv;   // kConv only
+    int conv_period, src_stride;
 };
-enum { kPlain = 0, kReduce = 1, kCentred = 2 };
+enum { kPlain = 0, kReduce = 1, kCentred = 2, kConv = 3 };
+// per output limb scale of an inverse NTT (replaces N^-1): entry lam % period
+struct LimbScale {
+    u64 w, w_sh;
+    double wd;
+};
 inline Gather gather_plain(const u64 *p) { return Gather{p, 1, 1, 0, 0, kPlain, 0}; }
 void k_ntt_forward_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st);
-void k_ntt_inverse_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st);
+// scale (nullable): multiply output limb lam by scale[lam % scale_period].w instead of N^-1
+void k_ntt_inverse_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st,
+                     const LimbScale *scale = nullptr, int scale_period = 1);
 // out = (a - b) * c[chain] (+ x): a and x are gathered (x may be null; x_even_rows: add x only on
 // rows lam / rowlen that are even, i.e. to the first polynomial of each ciphertext)
 void k_sub_mul_add(const DevTables &t, u64 *out, const Gather &a, const u64 *b, const ChainConst &c, const Gather &x,
@@ -214,10 +242,13 @@ struct KsKeys {
     u64 g[kMaxKeys];
     int m;
 };
-// key-switch inner product: acc[c][comp][t] = sum_i sum_{j<l} sigma_i(digit[c][j][t]) * key_i[comp][j][kt],
-// kt = t (t<l) or L+1; key words are in Montgomery form (times 2^64)
-void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, const KsKeys &keys, int count, int l, int levels,
-                hipStream_t st);
+// key-switch inner product over the targets t < l + kSpecial (q_0..q_{l-1}, p_1, p_2):
+//   acc[c][comp][t] = sum_i sum_b sigma_i(D_b[c][t]) * key_i[comp][b][chain(t)],
+// D_b[c][t] = digits[c][didx[b (l + kSpecial) + t]] when that index is >= 0, else limb t of ciphertext c
+// gathered by `own` (the digit's residue at its own group's primes equals the input residue).  Keys are
+// [2][ng][L + 1 + kSpecial][N] in NTT and Montgomery form (times 2^64); digits hold K limbs per ciphertext.
+void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const int *didx, const Gather &own,
+                const KsKeys &keys, int ng, int count, int l, int levels, hipStream_t st);
 // [count][2][l] batches: with_self: out = (a c0 + sum_i sigma_{g[i]}(a c0), a c1); otherwise
 // out c0 rows = sum_i sigma_{g[i]}(a c0) and out c1 rows are not written
 void k_automorph_c0(const DevTables &t, u64 *out, const u64 *a, int count, int l, const KsKeys &gs, bool with_self,

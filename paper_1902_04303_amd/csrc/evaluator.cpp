@@ -167,7 +167,7 @@ void ntt_inv(ckks_ctx &c, u64 *buf, int n_limbs, ModMap m) {
 
 static ChainConst chain_const_of(const ckks_ctx &c, i64 k) {
     ChainConst cc{};
-    for (int i = 0; i < c.p.levels + 2; ++i) {
+    for (int i = 0; i < c.p.n_mods(); ++i) {
         u64 q = c.p.mod(i);
         u64 v = k >= 0 ? (u64)k % q : q - 1 - (u64)(-(k + 1)) % q;
         cc.v[i] = v;
@@ -178,7 +178,7 @@ static ChainConst chain_const_of(const ckks_ctx &c, i64 k) {
 
 static ChainConst chain_inv_of(const ckks_ctx &c, u64 x) {
     ChainConst cc{};
-    for (int i = 0; i < c.p.levels + 2; ++i) {
+    for (int i = 0; i < c.p.n_mods(); ++i) {
         u64 q = c.p.mod(i);
         u64 v = (x % q == 0) ? 0 : invmod_host(x % q, q);
         cc.v[i] = v;
@@ -318,36 +318,42 @@ static const u64 *key_of(const ckks_ctx &c, u64 id) {
     return it->second.ptr;
 }
 
-// Key switch of the digits gathered by `d` (count ciphertexts, l limbs, NTT form) with the keys of
-// `keys`: round(sum_i sum_j sigma_i([d]_{q_j}) ksk_{i,j} / P), one decomposition (ModUp) and one
-// division by P (ModDown) for all keys, each digit permuted by its key's automorphism after the
-// basis extension; plus the gathered `add` term (on every row, or on the first polynomial of each
-// ciphertext when add_even).  Output [count][2][l][N] in NTT form.
+// Key switch of the polynomial gathered by `d` (count ciphertexts, l limbs, NTT form) with the keys of
+// `keys` (hybrid decomposition, digit groups {q_0}, {q_1, q_2}, ...):
+//   ModUp    y_i = d_i (Q_G/q_i)^-1 (folded into the inverse NTT), then each group's digit
+//            D = sum_{i in G} y_i (Q_G/q_i) converted to every other target while loading the forward
+//            NTT (its residues at its own primes are the input limbs themselves);
+//   inner    x = sum_i sum_b sigma_i(D_b) ksk_{i,b} over the targets q_0..q_{l-1}, p_1, p_2, the digits
+//            read through each key's automorphism;
+//   ModDown  (x - C) / P with C = sum_k [x (P/p_k)^-1]_{p_k} (P/p_k) (the scales folded into the
+//            inverse NTT of the special limbs, the conversion into the forward NTT's load);
+// plus the gathered `add` term (on every row, or on the first polynomial of each ciphertext when
+// add_even).  Output [count][2][l][N] in NTT form.
 static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, const KsKeys &keys, const Gather &add,
                       bool add_even) {
     const size_t N = (size_t)c.p.n;
-    const int P = c.p.p_index();
-    // ModUp: coefficient form of every digit, reduced modulo every target while loading the forward NTT
+    const ckks_ctx::KsLevel &kl = c.ks_levels.at(l);
+    const int nt = l + kSpecial, P = c.p.p_index();
     DBuf dc(c.pool.get(), (size_t)count * l * N);
-    k_ntt_inverse_g(c.tab, dc.ptr, d, count * l, map_q(l), c.stream);
-    DBuf dig(c.pool.get(), (size_t)count * l * (l + 1) * N);
-    k_ntt_forward_g(c.tab, dig.ptr, Gather{dc.ptr, l + 1, 1, 0, 0, kReduce, 0}, count * l * (l + 1), ModMap{l + 1, l, P},
+    k_ntt_inverse_g(c.tab, dc.ptr, d, count * l, map_q(l), c.stream, kl.up_scale, l);
+    DBuf dig(c.pool.get(), (size_t)count * kl.K * N);
+    k_ntt_forward_g(c.tab, dig.ptr, Gather{dc.ptr, 1, 1, 0, 0, kConv, 0, kl.up, kl.K, l}, count * kl.K, map_q(l),
                     c.stream);
     dc.release();
-    // inner product with the keys (digits read through each key's automorphism)
-    DBuf acc(c.pool.get(), (size_t)count * 2 * (l + 1) * N);
-    k_ks_inner(c.tab, acc.ptr, dig.ptr, keys, count, l, c.p.levels, c.stream);
+    DBuf acc(c.pool.get(), (size_t)count * 2 * nt * N);
+    k_ks_inner(c.tab, acc.ptr, dig.ptr, kl.K, kl.didx, d, keys, c.ng, count, l, c.p.levels, c.stream);
     dig.release();
-    // ModDown: round(x / P) = (x - [x]_P centred) * P^-1
     const int rows = count * 2;
-    DBuf ap(c.pool.get(), (size_t)rows * N);
-    k_ntt_inverse_g(c.tab, ap.ptr, Gather{acc.ptr, 1, l + 1, l, 0, kPlain, 0}, rows, ModMap{1, 0, P}, c.stream);
+    DBuf ap(c.pool.get(), (size_t)rows * kSpecial * N);
+    k_ntt_inverse_g(c.tab, ap.ptr, Gather{acc.ptr, kSpecial, nt, l, 1, kPlain, 0}, rows * kSpecial,
+                    ModMap{kSpecial, 0, P}, c.stream, c.down_scale, kSpecial);
     DBuf t(c.pool.get(), (size_t)rows * l * N);
-    k_ntt_forward_g(c.tab, t.ptr, Gather{ap.ptr, l, 1, 0, 0, kCentred, P}, rows * l, map_q(l), c.stream);
+    k_ntt_forward_g(c.tab, t.ptr, Gather{ap.ptr, 1, 1, 0, 0, kConv, 0, c.down_conv, l, kSpecial}, rows * l, map_q(l),
+                    c.stream);
     DBuf out(c.pool.get(), (size_t)rows * l * N);
-    k_sub_mul_add(c.tab, out.ptr, Gather{acc.ptr, l, l + 1, 0, 1, kPlain, 0}, t.ptr, chain_inv_of(c, c.p.P), add,
-                  add_even, l, rows * l, map_q(l), c.stream);
-    c.n_limb_ntt += (uint64_t)count * l * (l + 2) + (uint64_t)rows * (l + 1);
+    k_sub_mul_add(c.tab, out.ptr, Gather{acc.ptr, l, nt, 0, 1, kPlain, 0}, t.ptr, c.p_inv, add, add_even, l, rows * l,
+                  map_q(l), c.stream);
+    c.n_limb_ntt += (uint64_t)count * (l + kl.K) + (uint64_t)rows * (kSpecial + l);
     c.n_launch += 10;
     ++c.n_keyswitch;
     return out;
@@ -493,45 +499,48 @@ static std::vector<i64> sample_hwt_host(u64 seed, u64 sid, int n, int h) {
 
 static u64 ksk_sid_base(u64 key_id) { return (1ULL << 40) | (key_id << 20); }
 
-// switching key for target secret sp (NTT form, L+1 limbs over q_0..q_L) under key id
+// switching key for target secret sp (NTT form, L+1 limbs over q_0..q_L) under key id:
+// [2][ng][L+3][N], for group b and target t (q_0..q_L, p_1, p_2)
+//   key[0][b][t] = -a_b s + e_b + [t in group b] (P mod q_t) s'_t,  key[1][b][t] = a_b,
+// a_b uniform (stream base + 2b, modulus index t), e_b centred binomial (stream base + 2b + 1); stored in
+// NTT and Montgomery form.
 static void make_switching_key(ckks_ctx &c, u64 seed, u64 key_id, const u64 *sp) {
-    const int L = c.p.levels, nt = L + 2, nd = L + 1, P = c.p.p_index();
+    const int L = c.p.levels, nt = c.p.n_mods(), ng = c.ng, P = c.p.p_index();
     const size_t N = (size_t)c.p.n;
-    const ModMap mt{nt, L + 1, P};          // targets q_0..q_L, P
-    DBuf key(c.pool.get(), (size_t)2 * nd * nt * N);
+    const ModMap mt{nt, L + 1, P};          // targets q_0..q_L, p_1, p_2
+    DBuf key(c.pool.get(), (size_t)2 * ng * nt * N);
     DBuf e_small(c.pool.get(), N);
     DBuf as(c.pool.get(), (size_t)nt * N);
     const u64 base = ksk_sid_base(key_id);
-    for (int j = 0; j < nd; ++j) {
-        u64 *b = key.ptr + (size_t)j * nt * N;
-        u64 *a = key.ptr + ((size_t)nd + j) * nt * N;
-        k_sample_uniform(c.tab, a, seed, base + 2ULL * j, nt, mt, P, c.stream);
-        ntt_fwd(c, a, nt, mt);
-        k_sample_cbd(reinterpret_cast<i64 *>(e_small.ptr), seed, base + 2ULL * j + 1, (int)N, c.stream);
-        k_signed_to_limbs(c.tab, b, reinterpret_cast<const i64 *>(e_small.ptr), nt, mt, c.stream);
-        ntt_fwd(c, b, nt, mt);
-        k_mul(c.tab, as.ptr, a, c.sk_ntt.ptr, nt, mt, nt, nt, c.stream);
-        k_sub(c.tab, b, b, as.ptr, nt, mt, nt, nt, c.stream);
-        // + (P mod q_j) s'_j on target j
-        ChainConst pj = chain_const_of(c, 0);
-        {
-            u64 q = c.p.q[j];
-            u64 v = c.p.P % q;
-            for (int i = 0; i < kMaxMods; ++i) { pj.v[i] = 0; pj.sh[i] = 0; }
-            pj.v[j] = v;
-            pj.sh[j] = (u64)(((u128)v << 64) / q);
+    for (int b = 0; b < ng; ++b) {
+        u64 *kb = key.ptr + (size_t)b * nt * N;
+        u64 *ka = key.ptr + ((size_t)ng + b) * nt * N;
+        k_sample_uniform(c.tab, ka, seed, base + 2ULL * b, nt, mt, P, c.stream);
+        ntt_fwd(c, ka, nt, mt);
+        k_sample_cbd(reinterpret_cast<i64 *>(e_small.ptr), seed, base + 2ULL * b + 1, (int)N, c.stream);
+        k_signed_to_limbs(c.tab, kb, reinterpret_cast<const i64 *>(e_small.ptr), nt, mt, c.stream);
+        ntt_fwd(c, kb, nt, mt);
+        k_mul(c.tab, as.ptr, ka, c.sk_ntt.ptr, nt, mt, nt, nt, c.stream);
+        k_sub(c.tab, kb, kb, as.ptr, nt, mt, nt, nt, c.stream);
+        const int f = ks_group_first(b), m = ks_group_size(b, L + 1);
+        for (int t = f; t < f + m; ++t) {   // + (P mod q_t) s'_t on the group's own targets
+            const u64 q = c.p.q[t];
+            const u64 v = mulmod_host(c.p.P[0] % q, c.p.P[1] % q, q);
+            ChainConst pj{};
+            pj.v[t] = v;
+            pj.sh[t] = (u64)(((u128)v << 64) / q);
+            k_mul_const(c.tab, as.ptr, sp + (size_t)t * N, 1, ModMap{1, 0, t}, pj, c.stream);
+            k_add(c.tab, kb + (size_t)t * N, kb + (size_t)t * N, as.ptr, 1, ModMap{1, 0, t}, 1, 1, c.stream);
         }
-        k_mul_const(c.tab, as.ptr, sp + (size_t)j * N, 1, ModMap{1, 0, j}, pj, c.stream);
-        k_add(c.tab, b + (size_t)j * N, b + (size_t)j * N, as.ptr, 1, ModMap{1, 0, j}, 1, 1, c.stream);
         c.n_launch += 8;
     }
-    k_to_mont(c.tab, key.ptr, 2 * nd * nt, mt, c.stream);
+    k_to_mont(c.tab, key.ptr, 2 * ng * nt, mt, c.stream);
     c.ksk[key_id] = std::move(key);
 }
 
 void keygen(ckks_ctx &c, u64 seed, const std::vector<u64> &galois) {
     if (seed == 0) seed = os_seed();
-    const int L = c.p.levels, P = c.p.p_index(), nt = L + 2;
+    const int L = c.p.levels, P = c.p.p_index(), nt = c.p.n_mods();
     const int n = c.p.n;
     const size_t N = (size_t)n;
     const ModMap mt{nt, L + 1, P};
@@ -674,5 +683,6 @@ ckks_ctx::~ckks_ctx() {
     pk.release();
     pool.reset();
     if (table_mem) (void)hipFree(table_mem);
+    if (ks_mem) (void)hipFree(ks_mem);
     if (copy_stream) (void)hipStreamDestroy(copy_stream);
 }

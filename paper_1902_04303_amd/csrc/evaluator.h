@@ -14,12 +14,26 @@ struct ckks_ctx {
     hipStream_t stream = nullptr;
     std::unique_ptr<gck::Pool> pool;
     void *table_mem = nullptr;     // device tables (hipMalloc, outside the pool)
+    void *ks_mem = nullptr;        // key-switch tables below (hipMalloc, outside the pool)
+    // key-switch tables, per level l (index l = 1..L+1): ModUp basis conversion of every digit group to
+    // the other targets (K entries per ciphertext), digit index of (group, target), inverse-NTT scales
+    struct KsLevel {
+        int K = 0;
+        gck::ConvEntry *up = nullptr;
+        int *didx = nullptr;
+        gck::LimbScale *up_scale = nullptr;
+    };
+    std::vector<KsLevel> ks_levels;
+    gck::ConvEntry *down_conv = nullptr;     // ModDown: target q_i from the special primes, i <= L
+    gck::LimbScale *down_scale = nullptr;    // ModDown inverse-NTT scales of the special primes
+    gck::ChainConst p_inv{};                 // P^-1 mod every chain modulus
+    int ng = 0;                              // digit groups of a key (at L + 1 limbs)
     // keys
     bool have_keys = false;
     std::vector<int64_t> sk;       // secret, signed coefficients
-    gck::DBuf sk_ntt;              // [L+2][N]: s mod q_0..q_L, P in NTT form
+    gck::DBuf sk_ntt;              // [L+3][N]: s mod q_0..q_L, p_1, p_2 in NTT form
     gck::DBuf pk;                  // [2][L+1][N] NTT form
-    std::map<uint64_t, gck::DBuf> ksk;   // key id (0 = relinearisation, else Galois element) -> [2][L+1][L+2][N]
+    std::map<uint64_t, gck::DBuf> ksk;   // key id (0 = relinearisation, else Galois element) -> [2][ng][L+3][N]
     // counters and optional per-kernel timing
     uint64_t n_keyswitch = 0, n_limb_ntt = 0, n_launch = 0;
     gck::KTimer timer;

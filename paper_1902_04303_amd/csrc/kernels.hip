@@ -362,23 +362,120 @@ void k_sub_mul_add(const DevTables &t, u64 *out, const Gather &a, const u64 *b, 
 
 // ---------------------------------------------------------------- key-switch inner product
 //
-// acc[c][comp][t][k] = sum_j digit[c][j][t][k] * key[comp][j][kt][k] mod q_t.  The key words carry a
-// factor 2^64 (Montgomery form), so the lazily accumulated 128-bit sum needs one REDC at the end; the
-// high word is kept <= q by subtracting q (q 2^64 = 0 mod q) after each addition.  Each thread serves CB
-// ciphertexts of the batch, so every key word it loads is used CB times.
-// One thread per (group of CB ciphertexts, target limb tt, word k).  Consecutive 256-thread blocks hold
-// the groups of one (tt, 256-word chunk), so the key words a chunk needs are fetched from HBM once and
-// re-read from cache by the other groups.  Targets below 2^41 accumulate in FP64 (exact products,
-// signed remainders), the others in 128-bit integers; the Montgomery form of the keys is removed at
-// the end (REDC, or a multiply with 2^-64 mod q in FP64).
+// acc[c][comp][t][k] = sum_i sum_b sigma_i(D_b[c][t])[k] * key_i[comp][b][chain(t)][k] mod the target's
+// modulus, over the targets t < l + kSpecial (q_0..q_{l-1}, then the special primes).  The key words
+// carry a factor 2^64 (Montgomery form).  One thread per (group of CB ciphertexts, target t, word k);
+// consecutive 256-thread blocks hold the groups of one (t, 256-word chunk), so the key words a chunk
+// needs are fetched from HBM once and re-read from cache by the other groups.  Targets below 2^41
+// accumulate in FP64 (exact products, signed remainders; the factor 2^64 removed by a multiply with
+// 2^-64 mod q), the others in 128-bit integers with the high word kept below q and one REDC.
+// Accumulators of one target word for CB ciphertexts: FP64 signed remainders (moduli below 2^41) or
+// 128-bit integer sums with the high word kept below q.
+template <int CB, bool FP>
+struct KsAcc;
 template <int CB>
-__global__ void ks_inner(u64 *acc, const u64 *digits, KsKeys keys, size_t total, int log_n, int l, int levels,
-                         int count, const ModInfo *mods) {
+struct KsAcc<CB, true> {
+    double a0[CB], a1[CB];
+    __device__ void zero() {
+#pragma unroll
+        for (int b = 0; b < CB; ++b) a0[b] = a1[b] = 0.0;
+    }
+    __device__ void mac(int b, u64 d, u64 k0, u64 k1, const ModInfo &M, const FMod &fm) {
+        const double dd = (double)d;   // a residue of this target
+        a0[b] += fmul_mod(dd, (double)k0, fm);
+        a1[b] += fmul_mod(dd, (double)k1, fm);
+    }
+    __device__ void settle(const FMod &fm) {   // each term is below 0.6 q: keep the sums below 2^47
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            a0[b] = fred(a0[b], fm);
+            a1[b] = fred(a1[b], fm);
+        }
+    }
+    __device__ void store(int b, u64 *o, size_t comp_stride, const ModInfo &M, const FMod &fm) {
+        o[0] = fcanon(fmul_mod(a0[b], M.rinv_d, fm), fm);
+        o[comp_stride] = fcanon(fmul_mod(a1[b], M.rinv_d, fm), fm);
+    }
+};
+template <int CB>
+struct KsAcc<CB, false> {
+    u64 h0[CB], l0[CB], h1[CB], l1[CB];
+    __device__ void zero() {
+#pragma unroll
+        for (int b = 0; b < CB; ++b) h0[b] = l0[b] = h1[b] = l1[b] = 0;
+    }
+    __device__ void mac(int b, u64 d, u64 k0, u64 k1, const ModInfo &M, const FMod &) {
+        const u64 p0 = d * k0, q0 = __umul64hi(d, k0);
+        const u64 p1 = d * k1, q1 = __umul64hi(d, k1);
+        l0[b] += p0;
+        h0[b] += q0 + (l0[b] < p0 ? 1 : 0);
+        l1[b] += p1;
+        h1[b] += q1 + (l1[b] < p1 ? 1 : 0);
+        if (h0[b] >= M.q) h0[b] -= M.q;
+        if (h1[b] >= M.q) h1[b] -= M.q;
+    }
+    __device__ void settle(const FMod &) {}
+    __device__ void store(int b, u64 *o, size_t comp_stride, const ModInfo &M, const FMod &) {
+        o[0] = redc(h0[b], l0[b], M);
+        o[comp_stride] = redc(h1[b], l1[b], M);
+    }
+};
+
+// one target word for CB ciphertexts.  MK > 0: exactly MK keys, their loads for one digit group issued
+// together (unrolled); MK == 0: keys.m keys in a loop.
+template <int CB, int MK, bool FP>
+__device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, const int *__restrict__ didx,
+                                        const u64 *const (&own_row)[CB], const KsKeys &keys, const size_t (&kd)[MK > 0 ? MK : 1],
+                                        int gl, int nt, int tt, size_t k, size_t krow, size_t key_grp, size_t key_comp,
+                                        int log_n, size_t n, int c0, int nb, const ModInfo &M) {
+    const FMod fm{M.qd, M.qinv};
+    KsAcc<CB, FP> A;
+    A.zero();
+    for (int gb = 0; gb < gl; ++gb) {
+        const int e = didx[gb * nt + tt];
+        const u64 *src[CB];
+#pragma unroll
+        for (int b = 0; b < CB; ++b) src[b] = e >= 0 ? digits + ((size_t)(c0 + b) * K + e) * n : own_row[b];
+        if constexpr (MK > 0) {
+            u64 kw0[MK], kw1[MK], dw[MK][CB];
+#pragma unroll
+            for (int i = 0; i < MK; ++i) {
+                kw0[i] = keys.key[i][(size_t)gb * key_grp + krow];
+                kw1[i] = keys.key[i][key_comp + (size_t)gb * key_grp + krow];
+#pragma unroll
+                for (int b = 0; b < CB; ++b) dw[i][b] = b < nb ? src[b][kd[i]] : 0;
+            }
+#pragma unroll
+            for (int i = 0; i < MK; ++i)
+#pragma unroll
+                for (int b = 0; b < CB; ++b)
+                    if (b < nb) A.mac(b, dw[i][b], kw0[i], kw1[i], M, fm);
+        } else {
+            for (int i = 0; i < keys.m; ++i) {
+                const size_t kdi = keys.g[i] ? automorph_src(k, log_n, keys.g[i]) : k;
+                const u64 k0 = keys.key[i][(size_t)gb * key_grp + krow];
+                const u64 k1 = keys.key[i][key_comp + (size_t)gb * key_grp + krow];
+#pragma unroll
+                for (int b = 0; b < CB; ++b)
+                    if (b < nb) A.mac(b, src[b][kdi], k0, k1, M, fm);
+            }
+        }
+        A.settle(fm);
+    }
+#pragma unroll
+    for (int b = 0; b < CB; ++b)
+        if (b < nb) A.store(b, acc + ((size_t)(c0 + b) * 2 * nt + tt) * n + k, (size_t)nt * n, M, fm);
+}
+
+template <int CB, int MK>
+__global__ void ks_inner(u64 *acc, const u64 *digits, int K, const int *__restrict__ didx, Gather own, KsKeys keys,
+                         int ng, size_t total, int log_n, int l, int levels, int count, const ModInfo *mods) {
     const size_t n = (size_t)1 << log_n;
-    const int nt_key = levels + 2;
-    const size_t key_comp = (size_t)(levels + 1) * nt_key * n;
-    const size_t dig_ct = (size_t)l * (l + 1) * n;
-    const size_t dig_j = (size_t)(l + 1) * n;
+    const int nt = l + kSpecial;                 // targets of this key switch
+    const int nt_key = levels + 1 + kSpecial;    // targets of a key
+    const size_t key_comp = (size_t)ng * nt_key * n;
+    const size_t key_grp = (size_t)nt_key * n;
+    const int gl = ks_groups(l);
     const int groups = (count + CB - 1) / CB;
     const size_t chunks = n >> 8;   // 256-word chunks per limb
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
@@ -387,99 +484,59 @@ __global__ void ks_inner(u64 *acc, const u64 *digits, KsKeys keys, size_t total,
         const size_t rest = blk / groups;
         const size_t k = ((rest % chunks) << 8) + (idx & 255);
         const int tt = (int)(rest / chunks);
-        const int chain = tt < l ? tt : levels + 1;
+        const int chain = tt < l ? tt : levels + 1 + (tt - l);
         const ModInfo M = mods[chain];
-        const u64 *dg = digits + (size_t)tt * n;
-        const size_t krow = (size_t)chain * n + k;   // key word of digit j: key[(j nt_key) n + krow]
-        {
-            const int c0 = grp * CB;
-            const int nb = count - c0 < CB ? count - c0 : CB;
-            if (M.fp) {
-                const FMod fm{M.qd, M.qinv};
-                double a0[CB], a1[CB];
+        const size_t krow = (size_t)chain * n + k;   // key word of group b: key[b key_grp + krow]
+        const int c0 = grp * CB;
+        const int nb = count - c0 < CB ? count - c0 : CB;
+        // the input limb tt of each ciphertext (the digit of tt's own group), when tt is a q-target
+        const u64 *own_row[CB];
 #pragma unroll
-                for (int b = 0; b < CB; ++b) a0[b] = a1[b] = 0.0;
-                // digit-major: the keys' permuted reads of one digit word group follow each other (cache hits)
-                for (int j = 0; j < l; ++j) {
-                    for (int i = 0; i < keys.m; ++i) {
-                        const u64 *key = keys.key[i];
-                        const size_t kd = keys.g[i] ? automorph_src(k, log_n, keys.g[i]) : k;   // permuted digit word
-                        const double k0 = (double)key[(size_t)j * nt_key * n + krow];
-                        const double k1 = (double)key[key_comp + (size_t)j * nt_key * n + krow];
-                        const u64 *dj = dg + (size_t)c0 * dig_ct + (size_t)j * dig_j + kd;
-#pragma unroll
-                        for (int b = 0; b < CB; ++b) {
-                            if (b >= nb) break;
-                            const double d = (double)dj[(size_t)b * dig_ct];
-                            a0[b] += fmul_mod(d, k0, fm);
-                            a1[b] += fmul_mod(d, k1, fm);
-                        }
-                    }
-#pragma unroll
-                    for (int b = 0; b < CB; ++b) {   // each term is below 0.6 q: keep the sums below 2^47
-                        a0[b] = fred(a0[b], fm);
-                        a1[b] = fred(a1[b], fm);
-                    }
-                }
-#pragma unroll
-                for (int b = 0; b < CB; ++b) {
-                    if (b >= nb) break;
-                    u64 *o = acc + ((size_t)(c0 + b) * 2 * (l + 1) + tt) * n + k;
-                    o[0] = fcanon(fmul_mod(a0[b], M.rinv_d, fm), fm);
-                    o[(size_t)(l + 1) * n] = fcanon(fmul_mod(a1[b], M.rinv_d, fm), fm);
-                }
-            } else {
-                u64 h0[CB], l0[CB], h1[CB], l1[CB];
-#pragma unroll
-                for (int b = 0; b < CB; ++b) h0[b] = l0[b] = h1[b] = l1[b] = 0;
-                for (int j = 0; j < l; ++j) {
-                    for (int i = 0; i < keys.m; ++i) {
-                        const u64 *key = keys.key[i];
-                        const size_t kd = keys.g[i] ? automorph_src(k, log_n, keys.g[i]) : k;
-                        const u64 k0 = key[(size_t)j * nt_key * n + krow];
-                        const u64 k1 = key[key_comp + (size_t)j * nt_key * n + krow];
-                        const u64 *dj = dg + (size_t)c0 * dig_ct + (size_t)j * dig_j + kd;
-#pragma unroll
-                        for (int b = 0; b < CB; ++b) {
-                            if (b >= nb) break;
-                            const u64 d = dj[(size_t)b * dig_ct];
-                            const u64 p0 = d * k0, q0 = __umul64hi(d, k0);
-                            const u64 p1 = d * k1, q1 = __umul64hi(d, k1);
-                            l0[b] += p0;
-                            h0[b] += q0 + (l0[b] < p0 ? 1 : 0);
-                            l1[b] += p1;
-                            h1[b] += q1 + (l1[b] < p1 ? 1 : 0);
-                            if (h0[b] >= M.q) h0[b] -= M.q;
-                            if (h1[b] >= M.q) h1[b] -= M.q;
-                        }
-                    }
-                }
-#pragma unroll
-                for (int b = 0; b < CB; ++b) {
-                    if (b >= nb) break;
-                    u64 *o = acc + ((size_t)(c0 + b) * 2 * (l + 1) + tt) * n + k;
-                    o[0] = redc(h0[b], l0[b], M);
-                    o[(size_t)(l + 1) * n] = redc(h1[b], l1[b], M);
-                }
-            }
+        for (int b = 0; b < CB; ++b) {
+            const int lam = (c0 + b) * l + (tt < l ? tt : 0);
+            own_row[b] = own.ptr + (size_t)((lam / own.div) * own.mul + own.add + (lam % own.div) * own.inner) * n;
         }
+        size_t kd[MK > 0 ? MK : 1];   // permuted digit word of each key (MK > 0)
+#pragma unroll
+        for (int i = 0; i < (MK > 0 ? MK : 1); ++i) kd[i] = (MK > 0 && keys.g[i]) ? automorph_src(k, log_n, keys.g[i]) : k;
+        if (M.fp)
+            ks_word<CB, MK, true>(acc, digits, K, didx, own_row, keys, kd, gl, nt, tt, k, krow, key_grp, key_comp, log_n, n,
+                                  c0, nb, M);
+        else
+            ks_word<CB, MK, false>(acc, digits, K, didx, own_row, keys, kd, gl, nt, tt, k, krow, key_grp, key_comp, log_n,
+                                   n, c0, nb, M);
     }
 }
-void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, const KsKeys &keys, int count, int l, int levels,
-                hipStream_t st) {
+void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const int *didx, const Gather &own,
+                const KsKeys &keys, int ng, int count, int l, int levels, hipStream_t st) {
+    const int nt = l + kSpecial, gl = ks_groups(l);
     // algorithmic bytes: every key word and every digit word read once, the accumulators written once
-    const double ll = (double)l * (l + 1);
     const int cb = count >= 4 ? 4 : (count >= 2 ? 2 : 1);   // 8 would spill registers
-    static const char *const names[5] = {"", "ks_inner<1>", "ks_inner<2>", "", "ks_inner<4>"};
-    TScope ts_(t, names[cb], 8.0 * (double)t.n * (keys.m * 2.0 * ll + (double)count * (ll + 2.0 * (l + 1))), st);
+    const int mk = (keys.m == 1 || keys.m == 3) ? keys.m : 0;
+    static const char *const names[3][3] = {{"ks_inner<1, 0>", "ks_inner<1, 1>", "ks_inner<1, 3>"},
+                                            {"ks_inner<2, 0>", "ks_inner<2, 1>", "ks_inner<2, 3>"},
+                                            {"ks_inner<4, 0>", "ks_inner<4, 1>", "ks_inner<4, 3>"}};
+    TScope ts_(t, names[cb == 4 ? 2 : cb - 1][mk == 3 ? 2 : mk],
+               8.0 * (double)t.n * (keys.m * 2.0 * gl * nt + (double)count * (gl * nt + 2.0 * nt)), st);
     if (t.log_n < 8) throw Error(CKKS_E_INVALID_ARG, "key switching needs N >= 256");
-    size_t total = ((size_t)((count + cb - 1) / cb) * (l + 1)) << t.log_n;
+    size_t total = ((size_t)((count + cb - 1) / cb) * nt) << t.log_n;
     if (!total) return;
-    switch (cb) {
-    case 4: hipLaunchKernelGGL(ks_inner<4>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, keys, total, t.log_n, l, levels, count, t.mods); break;
-    case 2: hipLaunchKernelGGL(ks_inner<2>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, keys, total, t.log_n, l, levels, count, t.mods); break;
-    default: hipLaunchKernelGGL(ks_inner<1>, ew_grid(total), dim3(kEwThreads), 0, st, acc, digits, keys, total, t.log_n, l, levels, count, t.mods); break;
+    const dim3 grid = ew_grid(total), block(kEwThreads);
+#define GCK_KS(CB_, MK_) \
+    hipLaunchKernelGGL((ks_inner<CB_, MK_>), grid, block, 0, st, acc, digits, K, didx, own, keys, ng, total, t.log_n, l, \
+                       levels, count, t.mods)
+    switch (cb * 10 + mk) {
+    case 41: GCK_KS(4, 1); break;
+    case 43: GCK_KS(4, 3); break;
+    case 40: GCK_KS(4, 0); break;
+    case 21: GCK_KS(2, 1); break;
+    case 23: GCK_KS(2, 3); break;
+    case 20: GCK_KS(2, 0); break;
+    case 11: GCK_KS(1, 1); break;
+    case 13: GCK_KS(1, 3); break;
+    default: GCK_KS(1, 0); break;
     }
+#undef GCK_KS
     check_launch();
 }
 

@@ -43,9 +43,10 @@ __device__ __forceinline__ u64 reduce64(u64 x, const ModInfo &M) {
     return r >= M.q ? r - M.q : r;
 }
 
+// chain index of limb lam: t = lam mod period is q_t below nq, else special prime p_idx + (t - nq)
 __device__ __forceinline__ int chain_of(int lam, ModMap m) {
     int t = lam % m.period;
-    return t < m.nq ? t : m.p_idx;
+    return t < m.nq ? t : m.p_idx + (t - m.nq);
 }
 
 // ---------------------------------------------------------------- FP64 arithmetic (q < 2^41)

@@ -39,6 +39,10 @@ struct Geom {
     int log_g_rows;   // sub-transforms (rows) per rows tile
     int tiles;        // tiles per limb (same for both passes)
     int xcd_group;    // 1: place consecutive logical blocks on one XCD (see block_id)
+    const ConvEntry *conv;     // basis-conversion launches: chain of limb lam is conv[lam % conv_period]
+    int conv_period;
+    const LimbScale *scale;    // inverse: output limb lam scaled by scale[lam % scale_period] (else N^-1)
+    int scale_period;
 };
 
 // Logical block of a launch.  Workgroups are handed to the 8 XCDs round-robin (workgroup i to XCD
@@ -62,6 +66,10 @@ Geom make_geom(int log_n) {
     g.log_g_rows = log_tile - g.log_n2;
     g.tiles = 1 << (log_n - log_tile);
     g.xcd_group = 0;
+    g.conv = nullptr;
+    g.conv_period = 1;
+    g.scale = nullptr;
+    g.scale_period = 1;
     return g;
 }
 
@@ -201,7 +209,8 @@ __global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, G
     const int bid = block_id(g);
     const int limb = bid >> (g.log_n - log_tile);
     const int tile = bid & (g.tiles - 1);
-    const int chain = chain_of(limb, mm);
+    const ConvEntry *ce = g.conv ? g.conv + limb % g.conv_period : nullptr;
+    const int chain = ce ? ce->chain : chain_of(limb, mm);
     const ModInfo M = mods[chain];
     const u64 qm = M.q;
     const size_t n = (size_t)1 << g.log_n;
@@ -221,7 +230,10 @@ __global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, G
     const u64 *ain = a;
     int mode = kPlain;
     u64 src_q = 0, src_half = 0, src_q_red = 0;
-    if (in.ptr) {
+    if (in.ptr && in.mode == kConv) {
+        mode = kConv;
+        ain = in.ptr + ((size_t)(limb / g.conv_period) * in.src_stride + ce->src) * n;
+    } else if (in.ptr) {
         const int sl = (limb / in.div) * in.mul + in.add + (limb % in.div) * in.inner;
         ain = in.ptr + (size_t)sl * n;
         mode = in.mode;
@@ -248,17 +260,45 @@ __global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, G
     // wave instruction covers 16 consecutive words of each of 4 rows (an LDS transposition in the cols
     // passes, loads or stores, measured slower than the strided access it replaces)
     u64 v[kPer];
+    if (mode == kConv) {
+        // basis conversion while loading: sum_m y_m c_m mod q (FP64 moduli: as double bits, reduced)
+        const ConvEntry E = *ce;
+        const FMod fm{M.qd, M.qinv};
 #pragma unroll
-    for (int e = 0; e < kPer; ++e) {
-        const int idx = slot_index<LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(e, q);
-        v[e] = ain[base + (size_t)idx * stride];
+        for (int e = 0; e < kPer; ++e) {
+            const size_t at = base + (size_t)slot_index<LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(e, q) * stride;
+            const u64 y0 = ain[at];
+            const u64 y1 = E.nsrc > 1 ? ain[at + n] : 0;
+            if (M.fp) {
+                const double a0 = E.big ? fred(fmul_mod((double)(y0 >> 32), M.c32_d, fm) + (double)(y0 & 0xFFFFFFFFULL), fm)
+                                        : (double)y0;
+                double x = fmul_mod(a0, E.cd[0], fm);
+                if (E.nsrc > 1) {
+                    const double a1 = E.big ? fred(fmul_mod((double)(y1 >> 32), M.c32_d, fm) +
+                                                       (double)(y1 & 0xFFFFFFFFULL), fm)
+                                            : (double)y1;
+                    x += fmul_mod(a1, E.cd[1], fm);
+                }
+                v[e] = (u64)__double_as_longlong(fred(x, fm));
+            } else {
+                u64 r = mul_shoup(y0, E.c[0], E.c_sh[0], qm);
+                if (E.nsrc > 1) r = add_mod(r, mul_shoup(y1, E.c[1], E.c_sh[1], qm), qm);
+                v[e] = r;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            const int idx = slot_index<LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(e, q);
+            v[e] = ain[base + (size_t)idx * stride];
+        }
     }
     if (M.fp) {
         // FP64 butterflies; the first pass reads residues, the second the first pass's doubles
         const FMod fm{M.qd, M.qinv};
         const double *Wf = tw_f + (size_t)chain * n;
         double f[kPer];
-        if (last_pass) {
+        if (last_pass || mode == kConv) {
 #pragma unroll
             for (int e = 0; e < kPer; ++e) f[e] = __longlong_as_double((long long)v[e]);
         } else if (mode == kPlain) {
@@ -296,14 +336,15 @@ __global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, G
                 fphase<INV, LOGM, Ph<LOGM, P2>::S0, Ph<LOGM, P2>::R>(f, q, base_off, Wf, fm);
             }
         }
+        const double sc = (INV && !ROWS && g.scale) ? g.scale[limb % g.scale_period].wd : M.ninv_d;
 #pragma unroll
         for (int e = 0; e < kPer; ++e) {
             double x = f[e];
-            if (INV && !ROWS) x = fmul_mod(x, M.ninv_d, fm);
+            if (INV && !ROWS) x = fmul_mod(x, sc, fm);
             v[e] = last_pass ? fcanon(x, fm) : (u64)__double_as_longlong(fred(x, fm));
         }
     } else {
-        if (!last_pass && mode != kPlain) {
+        if (!last_pass && mode != kPlain && mode != kConv) {
 #pragma unroll
             for (int e = 0; e < kPer; ++e) {
                 u64 x = v[e];
@@ -326,10 +367,15 @@ __global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, G
         }
         // final scaling (inverse cols pass: N^-1) and reduction ([0, q) at the end of a transform)
         const u64 q2 = 2 * qm;
+        u64 sw = M.ninv, sw_sh = M.ninv_sh;
+        if (INV && !ROWS && g.scale) {
+            sw = g.scale[limb % g.scale_period].w;
+            sw_sh = g.scale[limb % g.scale_period].w_sh;
+        }
 #pragma unroll
         for (int e = 0; e < kPer; ++e) {
             u64 x = v[e];
-            if (INV && !ROWS) x = mul_shoup_lazy(x, M.ninv, M.ninv_sh, qm);
+            if (INV && !ROWS) x = mul_shoup_lazy(x, sw, sw_sh, qm);
             x = x >= q2 ? x - q2 : x;
             if (last_pass) x = x >= qm ? x - qm : x;
             v[e] = x;
@@ -376,18 +422,31 @@ void launch_pass(int log_m, dim3 grid, dim3 block, hipStream_t st, u64 *buf, con
 
 }  // namespace
 
-static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, bool inv, hipStream_t st) {
+static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, bool inv, hipStream_t st,
+                   const LimbScale *scale = nullptr, int scale_period = 1) {
     if (n_limbs <= 0) return;
     if (t.log_n < 10 || t.log_n > 17) throw Error(CKKS_E_INVALID_ARG, "NTT needs 2^10 <= N <= 2^17");
     Geom g = make_geom(t.log_n);
+    if (in.ptr && in.mode == kConv) {
+        if (inv || !in.conv || in.conv_period < 1) throw Error(CKKS_E_INVALID_ARG, "basis conversion needs a forward NTT");
+        g.conv = in.conv;
+        g.conv_period = in.conv_period;
+    }
+    if (scale) {
+        if (!inv || scale_period < 1) throw Error(CKKS_E_INVALID_ARG, "limb scales apply to inverse NTTs");
+        g.scale = scale;
+        g.scale_period = scale_period;
+    }
     const int log_tile = t.log_n < 12 ? t.log_n : 12;
     dim3 grid((unsigned)((size_t)n_limbs * g.tiles));
     dim3 block((unsigned)((1 << log_tile) / kPer));
     // algorithmic bytes of a pass: each word written once and each distinct input word read once (a
     // gather whose output limbs share a source limb, inner == 0, reads n_limbs / div source limbs)
     const double bytes = 16.0 * (double)n_limbs * t.n;
-    const bool shared_src = in.ptr && in.div > 1 && in.inner == 0;
-    const double bytes1 = shared_src ? 8.0 * t.n * ((double)n_limbs + (double)n_limbs / in.div) : bytes;
+    const bool conv = in.ptr && in.mode == kConv;
+    const bool shared_src = conv || (in.ptr && in.div > 1 && in.inner == 0);
+    const double src_limbs = conv ? (double)(n_limbs / in.conv_period) * in.src_stride : (double)n_limbs / in.div;
+    const double bytes1 = shared_src ? 8.0 * t.n * ((double)n_limbs + src_limbs) : bytes;
     const Gather none{nullptr, 1, 1, 0, 0, kPlain, 0};
     // timing names: the kernel symbols as a profiler lists them
     static const char *const names[2][2][5] = {
@@ -436,8 +495,9 @@ void k_ntt_forward_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs
     launch(t, buf, in, n_limbs, m, false, st);
 }
 
-void k_ntt_inverse_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st) {
-    launch(t, buf, in, n_limbs, m, true, st);
+void k_ntt_inverse_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st,
+                     const LimbScale *scale, int scale_period) {
+    launch(t, buf, in, n_limbs, m, true, st, scale, scale_period);
 }
 
 }  // namespace gck

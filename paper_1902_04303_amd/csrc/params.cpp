@@ -75,7 +75,7 @@ i64 round_half_away(double x) {
 
 Params make_params(int log_n, int levels, int log2_scale) {
     if (log_n < 10 || log_n > 17) throw Error(CKKS_E_INVALID_ARG, "log_n must be in [10, 17]");
-    if (levels < 1 || levels + 2 > kMaxMods) throw Error(CKKS_E_INVALID_ARG, "levels out of range");
+    if (levels < 1 || levels + 1 + kSpecial > kMaxMods) throw Error(CKKS_E_INVALID_ARG, "levels out of range");
     if (log2_scale < 20 || log2_scale > 50) throw Error(CKKS_E_INVALID_ARG, "log2_scale must be in [20, 50]");
     Params p;
     p.log_n = log_n;
@@ -84,7 +84,6 @@ Params make_params(int log_n, int levels, int log2_scale) {
     p.log2_scale = log2_scale;
     const u64 m = 2ULL * (u64)p.n;
     const u64 q0 = largest_prime_below(60, m);
-    p.P = largest_prime_below(62, m);
     // pool of 4L primes nearest 2^b
     const u64 center = 1ULL << log2_scale;
     std::vector<u64> pool;
@@ -120,6 +119,9 @@ Params make_params(int log_n, int levels, int log2_scale) {
         p.q[levels - d] = pool[best];
         p.scales.push_back((s * s) / (double)pool[best]);
     }
+    // special primes: the largest primes below 2^41 that are 1 mod 2N and not in the chain
+    for (u64 c = ((1ULL << 41) - 1) / m * m + 1; (int)p.P.size() < kSpecial; c -= m)
+        if (is_prime_u64(c) && std::find(p.q.begin(), p.q.end(), c) == p.q.end()) p.P.push_back(c);
     return p;
 }
 

@@ -87,14 +87,15 @@ def test_prime_chain_rule():
     for logN, L, b in [(4, 3, 20), (13, 26, 30), (16, 26, 40)]:
         p = C.make_params(logN, L, b)
         N = 1 << logN
-        mods = p.q + [p.P]
+        mods = p.q + p.P
         assert len(set(mods)) == len(mods)
         for q in mods:
             assert q % (2 * N) == 1
             # independent primality evidence: no small factor and Fermat witnesses
             assert all(q % d for d in range(3, 2000, 2))
             assert all(pow(a, q - 1, q) == 1 for a in (2, 3, 5, 7, 11, 13, 101))
-        assert p.q[0].bit_length() == 60 and p.P.bit_length() == 62
+        assert p.q[0].bit_length() == 60 and all(x.bit_length() == 41 for x in p.P)
+        assert p.P[0] > p.P[1] and p.P_prod > max(p.q[0], max(a * b for a, b in zip(p.q[1::2], p.q[2::2])))
         assert all(x.bit_length() == b + (1 if x >= 1 << b else 0) for x in p.q[1:])
         # canonical scales follow Delta_{d+1} = Delta_d^2 / q_{L-d} and stay near 2^b
         for d in range(L):
@@ -133,14 +134,15 @@ def test_secret_and_public_key_match_bigint(tiny_keys):
 def test_switching_keys_match_bigint(tiny_keys):
     p, o, bc, _, g = tiny_keys
     s = o.sk.tolist()
-    QP = bc.Q(p.L + 1) * p.P
+    QP = bc.Q(p.L + 1) * bc.P
     s2 = B.polymul(s, s, QP)
     targets = {0: s2, g[0]: B.automorph(s, g[0], QP), g[1]: B.automorph(s, g[1], QP)}
     for K, sp in targets.items():
         keys = bc.switching_key(s, sp, 5, C.ksk_sid_base(K))
         key = o.keys[K]
-        for j in range(p.L + 1):
-            for t, q in enumerate(p.q + [p.P]):
+        assert key.shape[1] == len(keys) == len(C.digit_groups(p.L + 1))
+        for j in range(len(keys)):
+            for t, q in enumerate(p.q + p.P):
                 assert key[0, j, t].tolist() == _res(keys[j][0], q), (K, j, t)
                 assert key[1, j, t].tolist() == _res(keys[j][1], q), (K, j, t)
 
@@ -169,7 +171,7 @@ def test_encrypt_tensor_keyswitch_rescale_match_bigint(tiny_keys):
         assert B.crt([d[c, i].tolist() for i in range(l)], p.q[:l]) == bd[c]
     # key switch with the relinearisation key at a reduced level
     lk = l - 1
-    QP = bc.Q(p.L + 1) * p.P
+    QP = bc.Q(p.L + 1) * bc.P
     keys = bc.switching_key(s, B.polymul(s, s, QP), 5, C.ksk_sid_base(0))
     dd = np.ascontiguousarray(d[2, :lk])
     ks = o.keyswitch(dd, 0)
@@ -186,7 +188,7 @@ def test_rotation_and_grouped_rotation_sum_match_bigint(tiny_keys):
     """Key switch of an automorphism (digits lifted, then permuted) and the grouped rotate-and-sum
     (three rotations, one division by P) against the big-integer schoolbook implementation."""
     p, o, bc, s, g = tiny_keys
-    QP = bc.Q(p.L + 1) * p.P
+    QP = bc.Q(p.L + 1) * bc.P
     keys = {gg: bc.switching_key(s, B.automorph(s, gg, QP), 5, C.ksk_sid_base(gg)) for gg in g}
     rng = np.random.default_rng(6)
     for l in (p.L + 1, 2):
