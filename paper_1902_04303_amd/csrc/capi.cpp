@@ -149,6 +149,7 @@ void build_ks_tables(ckks_ctx &c) {
         o_sc[l] = room(scales[l].size() * sizeof(LimbScale));
     }
     const size_t o_down = room(down.size() * sizeof(ConvEntry)), o_dsc = room(dscale.size() * sizeof(LimbScale));
+    const size_t o_pinv = room(kMaxMods * 8), o_pinv_sh = room(kMaxMods * 8);
     GCK_HIP(hipMalloc(&c.ks_mem, bytes));
     char *base = static_cast<char *>(c.ks_mem);
     c.ks_levels.assign(nq + 1, ckks_ctx::KsLevel{});
@@ -166,6 +167,10 @@ void build_ks_tables(ckks_ctx &c) {
     c.down_scale = reinterpret_cast<LimbScale *>(base + o_dsc);
     GCK_HIP(hipMemcpy(c.down_conv, down.data(), down.size() * sizeof(ConvEntry), hipMemcpyHostToDevice));
     GCK_HIP(hipMemcpy(c.down_scale, dscale.data(), dscale.size() * sizeof(LimbScale), hipMemcpyHostToDevice));
+    c.p_inv_dev = reinterpret_cast<u64 *>(base + o_pinv);
+    c.p_inv_sh_dev = reinterpret_cast<u64 *>(base + o_pinv_sh);
+    GCK_HIP(hipMemcpy(c.p_inv_dev, c.p_inv.v, kMaxMods * 8, hipMemcpyHostToDevice));
+    GCK_HIP(hipMemcpy(c.p_inv_sh_dev, c.p_inv.sh, kMaxMods * 8, hipMemcpyHostToDevice));
     c.ng = ks_groups(nq);
 }
 

@@ -197,7 +197,17 @@ struct LimbScale {
     double wd;
 };
 inline Gather gather_plain(const u64 *p) { return Gather{p, 1, 1, 0, 0, kPlain, 0}; }
-void k_ntt_forward_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st);
+// Epilogue of the forward NTT that ends a key switch's ModDown: output limb lam becomes
+// (acc - ntt) * P^-1 (+ add) with acc and add gathered (add may be null; add_even: added only on rows
+// lam / rowlen that are even, the first polynomial of each ciphertext); pinv[chain], pinv_sh[chain]
+// (device) hold P^-1 modulo each chain modulus with Shoup companions.
+struct ModDownEpi {
+    Gather acc, add;
+    int add_even, rowlen;
+    const u64 *pinv, *pinv_sh;
+};
+void k_ntt_forward_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st,
+                     const ModDownEpi *epi = nullptr);
 // scale (nullable): multiply output limb lam by scale[lam % scale_period].w instead of N^-1
 void k_ntt_inverse_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st,
                      const LimbScale *scale = nullptr, int scale_period = 1);

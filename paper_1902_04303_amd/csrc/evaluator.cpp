@@ -326,7 +326,8 @@ static const u64 *key_of(const ckks_ctx &c, u64 id) {
 //   inner    x = sum_i sum_b sigma_i(D_b) ksk_{i,b} over the targets q_0..q_{l-1}, p_1, p_2, the digits
 //            read through each key's automorphism;
 //   ModDown  (x - C) / P with C = sum_k [x (P/p_k)^-1]_{p_k} (P/p_k) (the scales folded into the
-//            inverse NTT of the special limbs, the conversion into the forward NTT's load);
+//            inverse NTT of the special limbs, the conversion into the forward NTT's load, the
+//            subtraction, the multiply by P^-1 and the added term into its final store);
 // plus the gathered `add` term (on every row, or on the first polynomial of each ciphertext when
 // add_even).  Output [count][2][l][N] in NTT form.
 static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, const KsKeys &keys, const Gather &add,
@@ -347,14 +348,13 @@ static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, const KsKe
     DBuf ap(c.pool.get(), (size_t)rows * kSpecial * N);
     k_ntt_inverse_g(c.tab, ap.ptr, Gather{acc.ptr, kSpecial, nt, l, 1, kPlain, 0}, rows * kSpecial,
                     ModMap{kSpecial, 0, P}, c.stream, c.down_scale, kSpecial);
-    DBuf t(c.pool.get(), (size_t)rows * l * N);
-    k_ntt_forward_g(c.tab, t.ptr, Gather{ap.ptr, 1, 1, 0, 0, kConv, 0, c.down_conv, l, kSpecial}, rows * l, map_q(l),
-                    c.stream);
     DBuf out(c.pool.get(), (size_t)rows * l * N);
-    k_sub_mul_add(c.tab, out.ptr, Gather{acc.ptr, l, nt, 0, 1, kPlain, 0}, t.ptr, c.p_inv, add, add_even, l, rows * l,
-                  map_q(l), c.stream);
+    const ModDownEpi epi{Gather{acc.ptr, l, nt, 0, 1, kPlain, 0}, add, add_even ? 1 : 0, l, c.p_inv_dev,
+                         c.p_inv_sh_dev};
+    k_ntt_forward_g(c.tab, out.ptr, Gather{ap.ptr, 1, 1, 0, 0, kConv, 0, c.down_conv, l, kSpecial}, rows * l, map_q(l),
+                    c.stream, &epi);
     c.n_limb_ntt += (uint64_t)count * (l + kl.K) + (uint64_t)rows * (kSpecial + l);
-    c.n_launch += 10;
+    c.n_launch += 9;
     ++c.n_keyswitch;
     return out;
 }

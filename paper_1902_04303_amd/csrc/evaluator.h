@@ -27,6 +27,7 @@ struct ckks_ctx {
     gck::ConvEntry *down_conv = nullptr;     // ModDown: target q_i from the special primes, i <= L
     gck::LimbScale *down_scale = nullptr;    // ModDown inverse-NTT scales of the special primes
     gck::ChainConst p_inv{};                 // P^-1 mod every chain modulus
+    gck::u64 *p_inv_dev = nullptr, *p_inv_sh_dev = nullptr;   // the same on the device
     int ng = 0;                              // digit groups of a key (at L + 1 limbs)
     // keys
     bool have_keys = false;

@@ -511,7 +511,7 @@ void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const in
                 const KsKeys &keys, int ng, int count, int l, int levels, hipStream_t st) {
     const int nt = l + kSpecial, gl = ks_groups(l);
     // algorithmic bytes: every key word and every digit word read once, the accumulators written once
-    const int cb = count >= 4 ? 4 : (count >= 2 ? 2 : 1);   // 8 would spill registers
+    const int cb = count >= 4 ? 4 : (count >= 2 ? 2 : 1);   // 8 (with fewer waves, or spills) measured slower
     const int mk = (keys.m == 1 || keys.m == 3) ? keys.m : 0;
     static const char *const names[3][3] = {{"ks_inner<1, 0>", "ks_inner<1, 1>", "ks_inner<1, 3>"},
                                             {"ks_inner<2, 0>", "ks_inner<2, 1>", "ks_inner<2, 3>"},
@@ -523,8 +523,8 @@ void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const in
     if (!total) return;
     const dim3 grid = ew_grid(total), block(kEwThreads);
 #define GCK_KS(CB_, MK_) \
-    hipLaunchKernelGGL((ks_inner<CB_, MK_>), grid, block, 0, st, acc, digits, K, didx, own, keys, ng, total, t.log_n, l, \
-                       levels, count, t.mods)
+    hipLaunchKernelGGL((ks_inner<CB_, MK_>), grid, block, 0, st, acc, digits, K, didx, own, keys, ng, total, t.log_n, \
+                       l, levels, count, t.mods)
     switch (cb * 10 + mk) {
     case 41: GCK_KS(4, 1); break;
     case 43: GCK_KS(4, 3); break;

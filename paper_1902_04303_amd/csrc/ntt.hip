@@ -43,7 +43,13 @@ struct Geom {
     int conv_period;
     const LimbScale *scale;    // inverse: output limb lam scaled by scale[lam % scale_period] (else N^-1)
     int scale_period;
+    int has_epi;               // forward rows pass: apply the ModDown epilogue while storing
+    ModDownEpi epi;
 };
+
+__device__ __forceinline__ size_t gathered(const Gather &g, int lam) {
+    return (size_t)((lam / g.div) * g.mul + g.add + (lam % g.div) * g.inner);
+}
 
 // Logical block of a launch.  Workgroups are handed to the 8 XCDs round-robin (workgroup i to XCD
 // i mod 8), each with its own L2.  When several output limbs read the same source limb (ModUp,
@@ -70,6 +76,8 @@ Geom make_geom(int log_n) {
     g.conv_period = 1;
     g.scale = nullptr;
     g.scale_period = 1;
+    g.has_epi = 0;
+    g.epi = ModDownEpi{};
     return g;
 }
 
@@ -387,10 +395,27 @@ __global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, G
         for (int e = 0; e < kPer; ++e)
             sh[lds_addr<ROWS>(gi, slot_index<LOGM, Ph<LOGM, LAST>::S0, Ph<LOGM, LAST>::R>(e, q), LOGM, log_g)] = v[e];
         __syncthreads();
+        if (!INV && g.has_epi) {
+            // ModDown epilogue: (acc - t) P^-1 (+ add), t the transform just computed
+            const ModDownEpi &E = g.epi;
+            const u64 *xa = E.acc.ptr + gathered(E.acc, limb) * n;
+            const bool with_add = E.add.ptr && (!E.add_even || ((limb / E.rowlen) & 1) == 0);
+            const u64 *xd = with_add ? E.add.ptr + gathered(E.add, limb) * n : nullptr;
+            const u64 pv = E.pinv[chain], ps = E.pinv_sh[chain];
 #pragma unroll
-        for (int e = 0; e < kPer; ++e) {
-            const int idx = slot_index<LOGM, 0, Ph<LOGM, 0>::R>(e, q);
-            a[base + idx] = sh[lds_addr<ROWS>(gi, idx, LOGM, log_g)];
+            for (int e = 0; e < kPer; ++e) {
+                const int idx = slot_index<LOGM, 0, Ph<LOGM, 0>::R>(e, q);
+                const u64 t = sh[lds_addr<ROWS>(gi, idx, LOGM, log_g)];
+                u64 r = mul_shoup(sub_mod(xa[base + idx], t, qm), pv, ps, qm);
+                if (with_add) r = add_mod(r, xd[base + idx], qm);
+                a[base + idx] = r;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < kPer; ++e) {
+                const int idx = slot_index<LOGM, 0, Ph<LOGM, 0>::R>(e, q);
+                a[base + idx] = sh[lds_addr<ROWS>(gi, idx, LOGM, log_g)];
+            }
         }
     } else {
 #pragma unroll
@@ -423,7 +448,7 @@ void launch_pass(int log_m, dim3 grid, dim3 block, hipStream_t st, u64 *buf, con
 }  // namespace
 
 static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, bool inv, hipStream_t st,
-                   const LimbScale *scale = nullptr, int scale_period = 1) {
+                   const LimbScale *scale = nullptr, int scale_period = 1, const ModDownEpi *epi = nullptr) {
     if (n_limbs <= 0) return;
     if (t.log_n < 10 || t.log_n > 17) throw Error(CKKS_E_INVALID_ARG, "NTT needs 2^10 <= N <= 2^17");
     Geom g = make_geom(t.log_n);
@@ -436,6 +461,12 @@ static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, 
         if (!inv || scale_period < 1) throw Error(CKKS_E_INVALID_ARG, "limb scales apply to inverse NTTs");
         g.scale = scale;
         g.scale_period = scale_period;
+    }
+    Geom g_rows = g;   // the epilogue applies to the forward rows pass only
+    if (epi) {
+        if (inv) throw Error(CKKS_E_INVALID_ARG, "the ModDown epilogue ends a forward NTT");
+        g_rows.has_epi = 1;
+        g_rows.epi = *epi;
     }
     const int log_tile = t.log_n < 12 ? t.log_n : 12;
     dim3 grid((unsigned)((size_t)n_limbs * g.tiles));
@@ -467,8 +498,9 @@ static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, 
             launch_pass<false, false>(g.log_n1, grid, block, st, buf, in, m, t.mods, t.psi, t.psi_sh, t.psi_f, g1);
         }
         {
-            TScope ts_(t, name(false, true, g.log_n2), bytes, st);
-            launch_pass<false, true>(g.log_n2, grid, block, st, buf, none, m, t.mods, t.psi, t.psi_sh, t.psi_f, g);
+            const double epi_bytes = epi ? 8.0 * t.n * n_limbs * (1.0 + (epi->add.ptr ? (epi->add_even ? 0.5 : 1.0) : 0.0)) : 0.0;
+            TScope ts_(t, name(false, true, g.log_n2), bytes + epi_bytes, st);
+            launch_pass<false, true>(g.log_n2, grid, block, st, buf, none, m, t.mods, t.psi, t.psi_sh, t.psi_f, g_rows);
         }
     } else {
         {
@@ -491,8 +523,9 @@ void k_ntt_inverse(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStrea
     launch(t, buf, Gather{nullptr, 1, 1, 0, 0, kPlain, 0}, n_limbs, m, true, st);
 }
 
-void k_ntt_forward_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st) {
-    launch(t, buf, in, n_limbs, m, false, st);
+void k_ntt_forward_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st,
+                     const ModDownEpi *epi) {
+    launch(t, buf, in, n_limbs, m, false, st, nullptr, 1, epi);
 }
 
 void k_ntt_inverse_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st,
