@@ -18,9 +18,12 @@
  *
  * The CKKS operations follow the scheme description of the paper (Methods,
  * "Homomorphic Encryption": KeyGen, Encrypt, Decrypt, Add, Mult, Rescale, and
- * Rotate) in its residue-number-system form with one special prime P:
- *   - key switching of d with a key for s':  round( sum_j [d]_{q_j} * ksk_j / P )
- *     where ksk_j = (-a_j s + e_j + [t = j] P s', a_j) modulo each q_t and P;
+ * Rotate) in its residue-number-system form with the special modulus P = p_1 p_2
+ * and a hybrid decomposition into digit groups {q_0}, {q_1, q_2}, {q_3, q_4}, ...:
+ *   - key switching of d with a key for s': the digits D_b of d (fast basis
+ *     conversion of d modulo the group's primes), x = sum_b D_b * ksk_b and
+ *     (x - C) / P, C the fast conversion of x mod P (see ref_keyswitch), where
+ *     ksk_b = (-a_b s + e_b + [q_t in group b] P s', a_b) modulo each q_t, p_1, p_2;
  *   - rescale by the last prime q_l:  round(c / q_l)  on the centred integer;
  *   - automorphism X -> X^g as the signed coefficient permutation i -> i*g mod 2N.
  *

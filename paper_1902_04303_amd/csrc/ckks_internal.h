@@ -235,15 +235,6 @@ void k_automorph(const DevTables &t, u64 *out, const u64 *a, int n_limbs, u64 g,
 // out[r][0:words] = in[r][0:words] with row strides (in words)
 void k_copy_rows(u64 *out, size_t out_stride, const u64 *in, size_t in_stride, int rows, size_t words,
                  hipStream_t st);
-// basis extension of one limb per row: out[r][i] = f(in[r]) mod chain(i), i < l_out (out_map period l_out);
-// f = centred lift of residues mod chain src_mod when centred, else the plain value
-void k_extend(const DevTables &t, u64 *out, const u64 *in, int rows, int l_out, ModMap out_map, int src_mod,
-              bool centred, hipStream_t st);
-// ModUp digits: out[c][j][t] = in[c][j] mod chain(t), j < l, t <= l (t == l: P)
-void k_modup(const DevTables &t, u64 *out, const u64 *in, int count, int l, int p_idx, hipStream_t st);
-// out = (a - b) * c[chain]  (+ out when add_to_out)
-void k_sub_mul_const(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m,
-                     const ChainConst &c, bool add_to_out, hipStream_t st);
 // Keys of one key-switch inner product: key i is paired with the NTT-domain automorphism X -> X^g[i] of
 // the digits (g[i] == 0: none).
 constexpr int kMaxKeys = 8;
@@ -273,10 +264,5 @@ void k_signed_to_limbs(const DevTables &t, u64 *out, const i64 *in, int n_limbs,
 // Montgomery form conversion (x * 2^64 mod q and back)
 void k_to_mont(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t st);
 void k_from_mont(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t st);
-// out[r][i] += in[r][i] for rows of l limbs (limb i modulo q_i), row strides in words
-void k_add_rows(const DevTables &t, u64 *out, size_t out_stride, const u64 *in, size_t in_stride, int rows, int l,
-                hipStream_t st);
-// out = -out  (negation) for each limb
-void k_neg(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t st);
 
 }  // namespace gck

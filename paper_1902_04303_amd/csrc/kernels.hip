@@ -1,8 +1,9 @@
 // HIP kernels of the RNS-CKKS evaluator for gfx950 (CDNA4).
 //
-// All arithmetic is exact modular integer arithmetic on 64-bit words, built on
-// the 32-bit integer VALU (no matrix cores: nothing here is a float
-// contraction).  Residues are kept in [0, q) with q < 2^62.
+// All arithmetic is exact modular arithmetic on residues in [0, q), stored as
+// 64-bit words, on the vector ALU (no matrix cores: nothing here is a float
+// contraction).  Moduli below 2^41 may use the exact FP64 products of
+// modarith.h; the others use 64-bit integers:
 //   - fixed-operand products (twiddles, constants): Shoup's method with a
 //     precomputed companion w' = floor(w 2^64 / q);
 //   - variable products: Montgomery reduction (REDC) of the 128-bit product;
@@ -243,93 +244,6 @@ void k_copy_rows(u64 *out, size_t out_stride, const u64 *in, size_t in_stride, i
     size_t total = (size_t)rows * words;
     if (!total) return;
     hipLaunchKernelGGL(ew_copy_rows, ew_grid(total), dim3(kEwThreads), 0, st, out, out_stride, in, in_stride, total, words);
-    check_launch();
-}
-
-__global__ void ew_extend(u64 *out, const u64 *in, size_t total, int log_n, int l_out, ModMap om, const ModInfo *mods,
-                          int src_mod, int centred) {
-    const size_t n = (size_t)1 << log_n;
-    const u64 qs = mods[src_mod].q, half = qs >> 1;
-    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
-        int lam = (int)(idx >> log_n);    // over rows * l_out
-        int r = lam / l_out, i = lam % l_out;
-        size_t k = idx & (n - 1);
-        const ModInfo &M = mods[chain_of(i, om)];
-        u64 x = in[(size_t)r * n + k];
-        u64 v = reduce64(x, M);
-        if (centred && x > half) v = sub_mod(v, reduce64(qs, M), M.q);   // x - qs is negative
-        out[idx] = v;
-    }
-}
-void k_extend(const DevTables &t, u64 *out, const u64 *in, int rows, int l_out, ModMap out_map, int src_mod,
-              bool centred, hipStream_t st) {
-    TScope ts_(t, "ew_extend", 8.0 * (double)((size_t)rows * (l_out + 1)) * t.n, st);
-    size_t total = ((size_t)rows * l_out) << t.log_n;
-    if (!total) return;
-    hipLaunchKernelGGL(ew_extend, ew_grid(total), dim3(kEwThreads), 0, st, out, in, total, t.log_n, l_out, out_map,
-                       t.mods, src_mod, centred ? 1 : 0);
-    check_launch();
-}
-
-__global__ void ew_modup(u64 *out, const u64 *in, size_t total, int log_n, int l, int p_idx, const ModInfo *mods) {
-    const size_t n = (size_t)1 << log_n;
-    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
-        size_t lam = idx >> log_n;        // over count * l * (l + 1)
-        int tt = (int)(lam % (l + 1));
-        size_t cj = lam / (l + 1);        // c * l + j
-        size_t k = idx & (n - 1);
-        const ModInfo &M = mods[tt < l ? tt : p_idx];
-        out[idx] = reduce64(in[cj * n + k], M);
-    }
-}
-void k_modup(const DevTables &t, u64 *out, const u64 *in, int count, int l, int p_idx, hipStream_t st) {
-    TScope ts_(t, "ew_modup", 8.0 * (double)((size_t)count * l * (l + 1) + (size_t)count * l) * t.n, st);
-    size_t total = ((size_t)count * l * (l + 1)) << t.log_n;
-    if (!total) return;
-    hipLaunchKernelGGL(ew_modup, ew_grid(total), dim3(kEwThreads), 0, st, out, in, total, t.log_n, l, p_idx, t.mods);
-    check_launch();
-}
-
-__global__ void ew_sub_mul_const(u64 *out, const u64 *a, const u64 *b, size_t total, int log_n, ModMap mm,
-                                 const ModInfo *mods, ChainConst c, int add_to_out) {
-    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
-        int lam = (int)(idx >> log_n);
-        int ch = chain_of(lam, mm);
-        u64 q = mods[ch].q;
-        u64 r = mul_shoup(sub_mod(a[idx], b[idx], q), c.v[ch], c.sh[ch], q);
-        out[idx] = add_to_out ? add_mod(out[idx], r, q) : r;
-    }
-}
-void k_sub_mul_const(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m,
-                     const ChainConst &c, bool add_to_out, hipStream_t st) {
-    TScope ts_(t, "ew_sub_mul_const", (add_to_out ? 32.0 : 24.0) * (double)n_limbs * t.n, st);
-    size_t total = (size_t)n_limbs << t.log_n;
-    if (!total) return;
-    hipLaunchKernelGGL(ew_sub_mul_const, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, c,
-                       add_to_out ? 1 : 0);
-    check_launch();
-}
-
-// out[r][i] += in[r][i] for rows of l limbs (limb i of a row is modulo q_i)
-__global__ void ew_add_rows(u64 *out, size_t out_stride, const u64 *in, size_t in_stride, size_t total, int log_n,
-                            int l, const ModInfo *mods) {
-    const size_t n = (size_t)1 << log_n;
-    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
-        size_t lam = idx >> log_n;
-        size_t r = lam / l;
-        int i = (int)(lam % l);
-        size_t k = idx & (n - 1);
-        u64 *o = out + r * out_stride + (size_t)i * n + k;
-        *o = add_mod(*o, in[r * in_stride + (size_t)i * n + k], mods[i].q);
-    }
-}
-void k_add_rows(const DevTables &t, u64 *out, size_t out_stride, const u64 *in, size_t in_stride, int rows, int l,
-                hipStream_t st) {
-    TScope ts_(t, "ew_add_rows", 24.0 * (double)((size_t)rows * l) * t.n, st);
-    size_t total = ((size_t)rows * l) << t.log_n;
-    if (!total) return;
-    hipLaunchKernelGGL(ew_add_rows, ew_grid(total), dim3(kEwThreads), 0, st, out, out_stride, in, in_stride, total,
-                       t.log_n, l, t.mods);
     check_launch();
 }
 
@@ -652,21 +566,6 @@ void k_from_mont(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t 
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
     hipLaunchKernelGGL(ew_mont, ew_grid(total), dim3(kEwThreads), 0, st, x, total, t.log_n, m, t.mods, 0);
-    check_launch();
-}
-
-__global__ void ew_neg(u64 *x, size_t total, int log_n, ModMap mm, const ModInfo *mods) {
-    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
-        int lam = (int)(idx >> log_n);
-        u64 q = mods[chain_of(lam, mm)].q;
-        x[idx] = x[idx] ? q - x[idx] : 0;
-    }
-}
-void k_neg(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t st) {
-    TScope ts_(t, "ew_neg", 16.0 * (double)n_limbs * t.n, st);
-    size_t total = (size_t)n_limbs << t.log_n;
-    if (!total) return;
-    hipLaunchKernelGGL(ew_neg, ew_grid(total), dim3(kEwThreads), 0, st, x, total, t.log_n, m, t.mods);
     check_launch();
 }
 
