@@ -54,7 +54,7 @@ def gpu_leg(args):
 
     torch.cuda.init()
     L = 7 * KAPPA + 5
-    ctx = P.Context(LOG_N, L, LOG_SCALE)
+    ctx = P.Context(LOG_N, L, LOG_SCALE, alpha=args.ks_alpha)
     lay = ctx.gwas_layout(N_SAMPLES, K_COV, M_SNPS, KAPPA)
     gal = galois_set(lay["R"])
     t0 = time.time()
@@ -99,7 +99,7 @@ def gpu_leg(args):
     t3 = time.perf_counter()
     per_step = {k: (c1[k] - c0[k]) // args.steps for k in c0}
     return dict(ms=ms, kernels=kt, warm_kernels=warm, counters=per_step, finalize_ms=(t3 - t2) * 1e3,
-                b_finite=int(np.isfinite(res["b"]).sum()), pool=ctx.pool_stats())
+                b_finite=int(np.isfinite(res["b"]).sum()), pool=ctx.pool_stats(), alpha=ctx.alpha)
 
 
 def forms_leg(args):
@@ -112,7 +112,7 @@ def forms_leg(args):
     from synth import job_mix, make_gwas_data, poisson_arrivals
 
     L = 7 * KAPPA + 5
-    ctx = P.Context(LOG_N, L, LOG_SCALE)
+    ctx = P.Context(LOG_N, L, LOG_SCALE, alpha=args.ks_alpha)
     ctx.keygen(7, galois_set(2048))
     jobs = job_mix(args.forms_jobs, 301, args.forms_m_scale)
     snps = sum(m for _, _, m, _ in jobs)
@@ -212,7 +212,7 @@ def roofline(kernels, warm, steps):
                 warm[name][1] / sum(v[1] for v in warm.values()), 3)}
 
 
-def cpu_baseline_leg():
+def cpu_baseline_leg(alpha: int):
     """The CPU oracle on a bounded sample of the same workload: the per-batch part of one SNP batch
     (256 SNPs; the fixed logistic-regression part is excluded, which favours the CPU)."""
     from oracle import ckks as C
@@ -221,7 +221,7 @@ def cpu_baseline_leg():
     from synth import config_seed, make_gwas_data
 
     L = G.circuit_depth(KAPPA)
-    p = C.make_params(LOG_N, L, LOG_SCALE)
+    p = C.make_params(LOG_N, L, LOG_SCALE, alpha)
     d = make_gwas_data(N_SAMPLES, K_COV, M_SNPS, seed=config_seed(2))
     lay = G.make_layout(p.N, N_SAMPLES, K_COV, M_SNPS)
     ds = G.snp_depth(KAPPA)
@@ -269,7 +269,7 @@ def run(args) -> int:
     rl = roofline(g["kernels"], g["warm_kernels"], args.steps)
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline_leg()
+        cpu = cpu_baseline_leg(g["alpha"])
     batched = serving = None
     if args.forms_jobs > 0:
         batched, serving = forms_leg(args)
@@ -287,7 +287,8 @@ def run(args) -> int:
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "n": N_SAMPLES, "k": K_COV, "m": M_SNPS, "kappa": KAPPA,
-                   "log_n": LOG_N, "levels": 7 * KAPPA + 5, "log2_scale": LOG_SCALE, "snp_batches": 42,
+                   "log_n": LOG_N, "levels": 7 * KAPPA + 5, "log2_scale": LOG_SCALE, "ks_alpha": g["alpha"],
+                   "snp_batches": 42,
                    "parallelism": "1 GPU"},
         "roofline": rl,
         "cpu_baseline": cpu,
@@ -306,6 +307,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ks-alpha", type=int, default=0, help="digit-group size of key switching (0: library default)")
     ap.add_argument("--forms-jobs", type=int, default=12, help="jobs in the batched / serving legs (0: skip)")
     ap.add_argument("--forms-m-scale", type=float, default=0.1, help="scale of the job SNP counts")
     ap.add_argument("--forms-rate", type=float, default=4.0, help="Poisson arrival rate (jobs/s)")

@@ -57,12 +57,15 @@ typedef struct gwas_server gwas_server;
  * 2^60 that is 1 mod 2N; the L rescale primes are chosen greedily from the 4L
  * primes 1 mod 2N nearest 2^log2_scale so that the canonical scales
  * Delta_{d+1} = Delta_d^2 / q_{L-d} stay near 2^log2_scale; the key-switching
- * modulus P = p_1 p_2 is the product of the two largest primes below 2^41 that
- * are 1 mod 2N and not in the chain. */
+ * modulus P = p_1 ... p_alpha is the product of the alpha largest primes below
+ * 2^41 that are 1 mod 2N and not in the chain, alpha the digit-group size of the
+ * hybrid key switch (see ckks_keygen). */
+#define CKKS_DEFAULT_KS_ALPHA 3
 typedef struct {
     int log_n;          /* log2 N, 10 <= log_n <= 17 */
     int levels;         /* L >= 1: number of rescale primes */
     int log2_scale;     /* base scale Delta_0 = 2^log2_scale, 20 <= . <= 50 */
+    int ks_alpha;       /* digit-group size alpha of key switching, 2 <= . <= 8; 0: CKKS_DEFAULT_KS_ALPHA */
 } ckks_params;
 
 /* Device allocator callbacks (e.g. torch's caching allocator).  alloc returns
@@ -75,7 +78,10 @@ typedef struct {
 
 const char *ckks_last_error(void);
 
-/* Host only (no device work): the moduli q_0..q_L, p_1, p_2 (moduli: L + 3 entries)
+/* Host only: the digit-group size alpha the parameters select (ks_alpha, or the default for 0),
+ * or CKKS_E_INVALID_ARG when it is out of range. */
+int ckks_params_ks_alpha(const ckks_params *params);
+/* Host only (no device work): the moduli q_0..q_L, p_1..p_alpha (moduli: L + 1 + alpha entries)
  * and the canonical scales Delta_0..Delta_L (scales: L + 1 entries). */
 int ckks_chain(const ckks_params *params, uint64_t *moduli, double *scales);
 
@@ -88,7 +94,7 @@ int ckks_ctx_create(const ckks_params *params, const ckks_allocator *allocator, 
                     size_t pool_budget_bytes, ckks_ctx **out);
 void ckks_ctx_destroy(ckks_ctx *ctx);
 
-/* Chain moduli: q[0..L] then p_1, p_2 (caller array of L + 3 entries). */
+/* Chain moduli: q[0..L] then p_1..p_alpha (caller array of L + 1 + alpha entries). */
 int ckks_ctx_moduli(const ckks_ctx *ctx, uint64_t *moduli, int cap);
 /* Canonical scales Delta_0..Delta_L (caller array of L + 1 entries). */
 int ckks_ctx_scales(const ckks_ctx *ctx, double *scales, int cap);
@@ -100,11 +106,12 @@ int ckks_ctx_pool_trim(ckks_ctx *ctx);
 /* ---------------------------------------------------------------- keys */
 
 /* KeyGen (paper: Methods, "Homomorphic Encryption", KeyGen), RNS form with the
- * special modulus P = p_1 p_2 and a hybrid decomposition: digit groups
- * G_0 = {q_0}, G_b = {q_{2b-1}, q_{2b}} (b = 1 .. L/2 rounded up).  s has
- * h = min(64, N/2) coefficients in {-1, 1} (HWT(h)), pk = (-a s + e, a) mod Q_L,
+ * special modulus P = p_1 ... p_alpha and a hybrid decomposition into digit
+ * groups of alpha primes: G_0 = {q_0 .. q_{alpha-2}},
+ * G_b = {q_{alpha b - 1} .. q_{alpha b + alpha - 2}} (b = 1 .. floor((L+1)/alpha)).
+ * s has h = min(64, N/2) coefficients in {-1, 1} (HWT(h)), pk = (-a s + e, a) mod Q_L,
  * and a switching key for s' has one part per group b:
- * (-a_b s + e_b + [q_t in G_b] P s', a_b) mod q_t (t = 0..L), p_1 and p_2.
+ * (-a_b s + e_b + [q_t in G_b] P s', a_b) mod q_t (t = 0..L) and p_1..p_alpha.
  * A relinearisation key (s' = s^2) is always made; one Galois key is made per
  * element of galois[] (s' = s(X^g), g odd in [3, 2N)).  seed != 0 selects the
  * test-only deterministic generator (counter-based SplitMix64); seed == 0 draws
@@ -115,8 +122,9 @@ uint64_t ckks_galois_rotate(const ckks_ctx *ctx, int64_t r);
 /* Galois element of complex conjugation, 2N - 1. */
 uint64_t ckks_galois_conj(const ckks_ctx *ctx);
 /* Copy out a key in canonical coefficient form.  key_id 0 is the relinearisation
- * key, otherwise a Galois element; buf holds [2][G][L+3][N] words, G = 1 + ceil(L/2)
- * groups, targets q_0..q_L then p_1, p_2. Secret: [N] int64; public key: [2][L+1][N]. */
+ * key, otherwise a Galois element; buf holds [2][G][L+1+alpha][N] words,
+ * G = 1 + floor((L+1)/alpha) groups, targets q_0..q_L then p_1..p_alpha.
+ * Secret: [N] int64; public key: [2][L+1][N]. */
 int ckks_export_switching_key(ckks_ctx *ctx, uint64_t key_id, uint64_t *buf, size_t cap_words);
 int ckks_export_secret(ckks_ctx *ctx, int64_t *buf, size_t cap);
 int ckks_export_public_key(ckks_ctx *ctx, uint64_t *buf, size_t cap_words);
@@ -187,7 +195,7 @@ int ckks_conjugate(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out);
  * then rescale; result scale (s * s) / q. */
 int ckks_mul_mask(ckks_ctx *ctx, const ckks_ct *a, int R, ckks_ct **out);
 /* Negacyclic NTT of `count` limbs in place on device memory laid out [count][N],
- * limb i modulo chain modulus moduli_index[i] (0..L, then L+1, L+2 = p_1, p_2); forward (dir = 1)
+ * limb i modulo chain modulus moduli_index[i] (0..L, then L+1.. = p_1..p_alpha); forward (dir = 1)
  * to this library's evaluation order or inverse (dir = -1).  Host array of indices. */
 int ckks_ntt_device(ckks_ctx *ctx, uint64_t *dev_limbs, int count, const int *moduli_index, int dir);
 

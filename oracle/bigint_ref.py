@@ -161,22 +161,19 @@ class BigCKKS:
     def mods_qp(self) -> List[int]:
         return self.q + self.p
 
-    @staticmethod
-    def groups(l: int) -> List[List[int]]:
-        """Key-switching digit groups of l limbs: {0}, {1, 2}, {3, 4}, ... cut at l."""
-        out = [[0]]
-        i = 1
-        while i < l:
-            out.append(list(range(i, min(i + 2, l))))
-            i += 2
-        return out
+    def groups(self, l: int) -> List[List[int]]:
+        """Key-switching digit groups of l limbs, alpha = number of special primes: the first alpha - 1
+        limbs, then runs of alpha limbs, cut at l (alpha = 2: {0}, {1, 2}, {3, 4}, ...)."""
+        a = len(self.p)
+        bounds = [0] + list(range(a - 1, l, a)) + [l]
+        return [list(range(lo, hi)) for lo, hi in zip(bounds, bounds[1:]) if hi > lo]
 
     # ---- keys
     def secret(self, seed: int, h: int) -> List[int]:
         return sample_hwt(seed, 1, self.N, h)
 
     def uniform_poly_qp(self, seed: int, sid: int) -> List[int]:
-        """Uniform element of Z_{QP}[X] whose residue modulo each q_t and p_k (indices 0..L+2) is sampled."""
+        """Uniform element of Z_{QP}[X] whose residue modulo each q_t and p_k (indices 0..L+alpha) is sampled."""
         res = [sample_uniform_residues(seed, sid, t, m, self.N) for t, m in enumerate(self.mods_qp())]
         return crt(res, self.mods_qp())
 

@@ -13,9 +13,10 @@ Readings taken where the paper is silent (the paper describes the non-RNS
 scheme with power-of-two moduli):
 
 * Prime chain.  q_0 is the largest prime below 2^60 that is 1 mod 2N.  The
-  special modulus P = p_1 p_2 is the product of the two largest primes below 2^41
-  that are 1 mod 2N and not in the chain (P above every digit modulus keeps the
-  key-switching noise small).  Rescale primes come from a pool of
+  special modulus P = p_1 ... p_alpha is the product of the alpha largest primes
+  below 2^41 that are 1 mod 2N and not in the chain, alpha the digit-group size
+  of the key switch (P above every digit modulus keeps the key-switching noise
+  small).  Rescale primes come from a pool of
   the 4L primes that are 1 mod 2N and nearest to 2^b; for depth d = 0..L-1 the
   unused pool prime nearest to Delta_d^2 / 2^b becomes q_{L-d} (ties to the
   smaller prime), and Delta_{d+1} = (Delta_d * Delta_d) / q_{L-d} in FP64, with
@@ -33,7 +34,9 @@ scheme with power-of-two moduli):
 * Multiplication: tensor product, relinearisation, then rescale by the last
   prime; the result scale is (s_a * s_b) / q in FP64.
 * Key switching (the paper's non-RNS KeyGen / Mult, in RNS with a hybrid
-  decomposition): digit groups {q_0}, {q_1, q_2}, {q_3, q_4}, ... (digit_groups);
+  decomposition): digit groups of alpha primes, {q_0 .. q_{alpha-2}}, then
+  {q_{alpha-1} .. q_{2 alpha-2}}, ... (digit_groups; alpha = 2 gives {q_0},
+  {q_1, q_2}, ...);
   a ciphertext with l limbs uses each group's members below l.  Digit b is the
   integer D_b = sum_{i in G_b} [d_i (Q_G/q_i)^-1]_{q_i} (Q_G/q_i) (fast basis
   conversion), key b is (-a_b s + e_b + P e_{G_b} s', a_b) mod Q_L P with e_G the
@@ -95,11 +98,11 @@ def lib():
         L.ref_tensor.argtypes = [ctypes.c_void_p, ctypes.c_int, _u64p, _u64p, _u64p, ctypes.c_int]
         L.ref_rescale.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _u64p, _u64p]
         L.ref_automorph.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _u64p, ctypes.c_uint64, _u64p]
-        L.ref_keyswitch.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _u64p, ctypes.c_int, _u64p,
-                                    ctypes.POINTER(_u64p), ctypes.c_int, _u64p]
-        L.ref_gen_ksk.argtypes = [ctypes.c_void_p, ctypes.c_int, _i64p, _u64p, ctypes.c_uint64, ctypes.c_uint64,
-                                  ctypes.c_int, _u64p]
-        L.ref_key_to_eval.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _u64p, _u64p]
+        L.ref_keyswitch.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64p, ctypes.c_int,
+                                    _u64p, ctypes.POINTER(_u64p), ctypes.c_int, _u64p]
+        L.ref_gen_ksk.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _i64p, _u64p, ctypes.c_uint64,
+                                  ctypes.c_uint64, ctypes.c_int, _u64p]
+        L.ref_key_to_eval.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64p, _u64p]
         L.ref_num_threads.restype = ctypes.c_int
         L.ref_gen_pk.argtypes = [ctypes.c_void_p, ctypes.c_int, _i64p, ctypes.c_uint64, ctypes.c_uint64,
                                  ctypes.c_uint64, _u64p]
@@ -178,8 +181,13 @@ class Params:
     L: int
     b: int                 # log2 of the base scale
     q: List[int]           # q_0 .. q_L
-    P: List[int]           # special primes p_1, p_2 (P = p_1 p_2)
+    P: List[int]           # special primes p_1 .. p_alpha (P = their product)
     scales: List[float]    # canonical scale at depth 0..L
+
+    @property
+    def alpha(self) -> int:
+        """Digit-group size of the key switch (one special prime per group member)."""
+        return len(self.P)
 
     @property
     def N(self) -> int:
@@ -204,14 +212,14 @@ class Params:
         return out
 
 
-def digit_groups(l: int) -> List[List[int]]:
-    """Limb indices of the key-switching digit groups of a ciphertext with l limbs: {0}, then
-    consecutive pairs {1, 2}, {3, 4}, ... cut at l."""
-    out = [[0]] if l >= 1 else []
-    i = 1
+def digit_groups(l: int, alpha: int) -> List[List[int]]:
+    """Limb indices of the key-switching digit groups of a ciphertext with l limbs: {0 .. alpha-2},
+    then runs of alpha consecutive limbs, cut at l."""
+    out = [list(range(0, min(alpha - 1, l)))] if l >= 1 else []
+    i = alpha - 1
     while i < l:
-        out.append(list(range(i, min(i + 2, l))))
-        i += 2
+        out.append(list(range(i, min(i + alpha, l))))
+        i += alpha
     return out
 
 
@@ -227,8 +235,13 @@ def largest_ntt_prime_below(bits: int, N: int, skip: int = 0) -> int:
         c -= M
 
 
-def make_params(logN: int, L: int, b: int) -> Params:
-    """The prime-chain rule stated in the module docstring."""
+DEFAULT_ALPHA = 3   # digit-group size of the key switch when none is given
+
+
+def make_params(logN: int, L: int, b: int, alpha: int = DEFAULT_ALPHA) -> Params:
+    """The prime-chain rule stated in the module docstring; alpha (2..8) special primes."""
+    if not 2 <= alpha <= 8:
+        raise ValueError("alpha must be in [2, 8]")
     N = 1 << logN
     M = 2 * N
     q0 = largest_ntt_prime_below(60, N)
@@ -270,7 +283,7 @@ def make_params(logN: int, L: int, b: int) -> Params:
         scales.append((s * s) / float(p))
     special: List[int] = []
     skip = 0
-    while len(special) < 2:
+    while len(special) < alpha:
         p = largest_ntt_prime_below(41, N, skip)
         skip += 1
         if p not in chain:
@@ -433,14 +446,15 @@ class Oracle:
         self.p = params
         N = params.N
         self.mods = list(params.q) + list(params.P)
-        self.pidx = params.L + 1          # modulus index of p_1 (p_2 follows)
-        self.ng = len(digit_groups(params.L + 1))
+        self.pidx = params.L + 1          # modulus index of p_1 (the other special primes follow)
+        self.alpha = params.alpha
+        self.ng = len(digit_groups(params.L + 1, self.alpha))
         qs = np.array(self.mods, dtype=np.uint64)
         psis = np.array([primitive_2n_root(q, N) for q in self.mods], dtype=np.uint64)
         self._ctx = lib().ref_ctx_new(N, len(self.mods), _p(qs), _p(psis))
         self.sk: Optional[np.ndarray] = None
         self.pk: Optional[np.ndarray] = None
-        self.keys: Dict[int, np.ndarray] = {}      # coefficient form [2][groups][L+3][N]
+        self.keys: Dict[int, np.ndarray] = {}      # coefficient form [2][groups][L+1+alpha][N]
         self._kev: Dict[int, np.ndarray] = {}      # oracle evaluation form
         self.n_keyswitch = 0
 
@@ -486,11 +500,11 @@ class Oracle:
     def _add_key(self, K: int, sp: np.ndarray) -> None:
         p = self.p
         N, L = p.N, p.L
-        key = np.zeros((2, self.ng, L + 3, N), dtype=np.uint64)
-        lib().ref_gen_ksk(self._ctx, L, _p(self.sk), _p(np.ascontiguousarray(sp)), self._seed,
+        key = np.zeros((2, self.ng, L + 1 + self.alpha, N), dtype=np.uint64)
+        lib().ref_gen_ksk(self._ctx, L, self.alpha, _p(self.sk), _p(np.ascontiguousarray(sp)), self._seed,
                           ksk_sid_base(K), self._max_l, _p(key))
         kev = np.zeros_like(key)
-        lib().ref_key_to_eval(self._ctx, L, self._max_l, _p(key), _p(kev))
+        lib().ref_key_to_eval(self._ctx, L, self.alpha, self._max_l, _p(key), _p(kev))
         self.keys[K] = key
         self._kev[K] = kev
 
@@ -627,7 +641,8 @@ class Oracle:
         out = np.zeros((2, l, p.N), dtype=np.uint64)
         gal = np.array([g for g, _ in pairs], dtype=np.uint64)
         kevs = (_u64p * len(pairs))(*[_p(self._kev[K]) for _, K in pairs])
-        lib().ref_keyswitch(self._ctx, p.L, l, _p(np.ascontiguousarray(d)), len(pairs), _p(gal), kevs, self.ng,
+        lib().ref_keyswitch(self._ctx, p.L, self.alpha, l, _p(np.ascontiguousarray(d)), len(pairs), _p(gal), kevs,
+                            self.ng,
                             _p(out))
         self.n_keyswitch += 1
         return out

@@ -18,12 +18,13 @@
  *
  * The CKKS operations follow the scheme description of the paper (Methods,
  * "Homomorphic Encryption": KeyGen, Encrypt, Decrypt, Add, Mult, Rescale, and
- * Rotate) in its residue-number-system form with the special modulus P = p_1 p_2
- * and a hybrid decomposition into digit groups {q_0}, {q_1, q_2}, {q_3, q_4}, ...:
+ * Rotate) in its residue-number-system form with a special modulus
+ * P = p_1 ... p_alpha and a hybrid decomposition into digit groups of alpha
+ * primes, {q_0 .. q_{alpha-2}}, then {q_{alpha-1} .. q_{2 alpha-2}}, ...:
  *   - key switching of d with a key for s': the digits D_b of d (fast basis
  *     conversion of d modulo the group's primes), x = sum_b D_b * ksk_b and
  *     (x - C) / P, C the fast conversion of x mod P (see ref_keyswitch), where
- *     ksk_b = (-a_b s + e_b + [q_t in group b] P s', a_b) modulo each q_t, p_1, p_2;
+ *     ksk_b = (-a_b s + e_b + [q_t in group b] P s', a_b) modulo each q_t and p_k;
  *   - rescale by the last prime q_l:  round(c / q_l)  on the centred integer;
  *   - automorphism X -> X^g as the signed coefficient permutation i -> i*g mod 2N.
  *
@@ -250,7 +251,7 @@ void ref_polymul(const ref_ctx *c, int mi, const u64 *a, const u64 *b, u64 *out)
 
 /* ------------------------------------------------------------------ */
 /* ciphertext-level operations (coefficient form, [2][l][N])            */
-/* moduli of limb i are c->mods[i]; the special prime is c->mods[pidx]  */
+/* moduli of limb i are c->mods[i]                                      */
 /* ------------------------------------------------------------------ */
 
 /* out = a + b (count polys of l limbs) */
@@ -391,29 +392,30 @@ void ref_automorph(const ref_ctx *c, int npoly, int l, const u64 *in, u64 g, u64
 }
 
 /*
- * Digit groups of the key switch (hybrid decomposition): group 0 is {q_0}, group b >= 1 is
- * {q_{2b-1}, q_{2b}}; a ciphertext with l limbs uses the groups with a member below l, each
- * restricted to its members below l.  Special primes: modulus indices L+1 and L+2, P = p_1 p_2.
+ * Digit groups of the key switch (hybrid decomposition with group size alpha >= 2): group 0 is
+ * {q_0 .. q_{alpha-2}}, group b >= 1 is {q_{alpha b - 1} .. q_{alpha b + alpha - 2}}; a ciphertext with
+ * l limbs uses the groups with a member below l, each restricted to its members below l.  Special
+ * primes: modulus indices L+1 .. L+alpha, P = p_1 ... p_alpha.
  */
-static int grp_first(int b) { return b == 0 ? 0 : 2 * b - 1; }
-static int grp_size(int b, int l) {
-    int f = grp_first(b), e = b == 0 ? 1 : 2 * b + 1;   /* members [f, e) */
+static int grp_first(int b, int a) { return b == 0 ? 0 : a * b - 1; }
+static int grp_size(int b, int l, int a) {
+    int f = grp_first(b, a), e = a * (b + 1) - 1;   /* members [f, e) */
     if (e > l) e = l;
     return e > f ? e - f : 0;
 }
-int ref_num_groups(int l) { return 1 + l / 2; }          /* groups with a member below l */
+int ref_num_groups(int l, int a) { return 1 + l / a; }   /* groups with a member below l */
 
 /*
  * Key switching of the polynomial d (coefficient form, limbs 0..l-1) with one or
  * several keys, each given in the oracle's evaluation form: kevs[i][comp][b][t][N]
- * for the ng groups b and the nt = L + 3 targets t (q_0..q_L, p_1, p_2).
+ * for the ng groups b and the nt = L + 1 + alpha targets t (q_0..q_L, p_1..p_alpha).
  *
  * Digits: for group b with members G (below l), Q_G = prod q_i, y_i = [d_i (Q_G/q_i)^-1]_{q_i},
  * and the digit is the integer D_b = sum_{i in G} y_i (Q_G/q_i) (fast basis conversion: D_b = d mod
  * Q_G up to a multiple of Q_G, which the keys' gadget annihilates).  Key i is paired with the
  * automorphism X -> X^galois[i] of the digits (galois[i] == 0: none), applied after the digit has been
  * taken modulo the target; the products of all keys are summed, then divided by P once:
- *   x = sum_i sum_b sigma_i(D_b) ksk_{i,b}  mod (q_0..q_{l-1}, p_1, p_2),
+ *   x = sum_i sum_b sigma_i(D_b) ksk_{i,b}  mod (q_0..q_{l-1}, p_1..p_alpha),
  *   out = (x - C) / P mod q_0..q_{l-1},  C = sum_k [x (P/p_k)^-1]_{p_k} (P/p_k)  (C = x mod P up to a
  *   multiple of P, so the division is exact).
  */
@@ -426,14 +428,14 @@ static void automorph_poly(int n, u64 q, const u64 *a, u64 g, u64 *o) {
     }
 }
 
-void ref_keyswitch(const ref_ctx *c, int L, int l, const u64 *d, int n_keys, const u64 *galois,
+void ref_keyswitch(const ref_ctx *c, int L, int alpha, int l, const u64 *d, int n_keys, const u64 *galois,
                    const u64 *const *kevs, int ng, u64 *out) {
-    int n = c->n, nt = L + 3, gl = ref_num_groups(l);
+    int n = c->n, nt = L + 1 + alpha, gl = ref_num_groups(l, alpha), lt = l + alpha;
     size_t kstride_t = (size_t)n, kstride_b = (size_t)nt * n, kstride_c = (size_t)ng * nt * n;
     /* y_i of every limb: d_i times (Q_G / q_i)^-1 modulo q_i */
     u64 *y = (u64 *)malloc(sizeof(u64) * (size_t)l * n);
     for (int b = 0; b < gl; ++b) {
-        int f = grp_first(b), m = grp_size(b, l);
+        int f = grp_first(b, alpha), m = grp_size(b, l, alpha);
         for (int i = f; i < f + m; ++i) {
             u64 qi = c->mods[i].q, hat = 1;
             for (int j = f; j < f + m; ++j) if (j != i) hat = mulmod(hat, c->mods[j].q % qi, qi);
@@ -442,18 +444,18 @@ void ref_keyswitch(const ref_ctx *c, int L, int l, const u64 *d, int n_keys, con
         }
     }
     /* accumulate, per target modulus, both components in evaluation form */
-    u64 *acc = (u64 *)calloc((size_t)2 * (l + 2) * n, sizeof(u64));
+    u64 *acc = (u64 *)calloc((size_t)2 * lt * n, sizeof(u64));
 #pragma omp parallel
     {
         u64 *dig = (u64 *)malloc(sizeof(u64) * n), *sg = (u64 *)malloc(sizeof(u64) * n),
             *fe = (u64 *)malloc(sizeof(u64) * n);
 #pragma omp for schedule(dynamic)
-        for (int ti = 0; ti < l + 2; ++ti) {
+        for (int ti = 0; ti < lt; ++ti) {
             int mi = ti < l ? ti : L + 1 + (ti - l);   /* modulus (and key target) of this target */
             u64 q = c->mods[mi].q;
-            u64 *a0 = acc + (size_t)ti * n, *a1 = acc + ((size_t)(l + 2) + ti) * n;
+            u64 *a0 = acc + (size_t)ti * n, *a1 = acc + ((size_t)lt + ti) * n;
             for (int b = 0; b < gl; ++b) {
-                int f = grp_first(b), m = grp_size(b, l);
+                int f = grp_first(b, alpha), m = grp_size(b, l, alpha);
                 /* D_b mod q: sum_i y_i (Q_G / q_i) */
                 for (int k = 0; k < n; ++k) dig[k] = 0;
                 for (int i = f; i < f + m; ++i) {
@@ -482,18 +484,31 @@ void ref_keyswitch(const ref_ctx *c, int L, int l, const u64 *d, int n_keys, con
         free(dig); free(sg); free(fe);
     }
     /* ModDown: (x - C) / P with C = sum_k [x (P/p_k)^-1]_{p_k} (P/p_k) */
-    u64 p1 = c->mods[L + 1].q, p2 = c->mods[L + 2].q;
-    u64 h1 = invmod(p2 % p1, p1), h2 = invmod(p1 % p2, p2);   /* (P/p_k)^-1 mod p_k */
+    u64 pk[64], hinv[64];   /* alpha <= 8 */
+    for (int k = 0; k < alpha; ++k) pk[k] = c->mods[L + 1 + k].q;
+    for (int k = 0; k < alpha; ++k) {   /* (P/p_k)^-1 mod p_k */
+        u64 hat = 1;
+        for (int j = 0; j < alpha; ++j) if (j != k) hat = mulmod(hat, pk[j] % pk[k], pk[k]);
+        hinv[k] = invmod(hat, pk[k]);
+    }
     for (int comp = 0; comp < 2; ++comp) {
-        const u64 *x1 = acc + ((size_t)comp * (l + 2) + l) * n, *x2 = x1 + n;
+        const u64 *xs = acc + ((size_t)comp * lt + l) * n;   /* x mod p_1 .. p_alpha */
         for (int i = 0; i < l; ++i) {
-            u64 q = c->mods[i].q;
-            u64 c1 = p2 % q, c2 = p1 % q, pinv = invmod(mulmod(p1 % q, p2 % q, q), q);
-            const u64 *xi = acc + ((size_t)comp * (l + 2) + i) * n;
+            u64 q = c->mods[i].q, pm = 1, hq[64];
+            for (int k = 0; k < alpha; ++k) {
+                pm = mulmod(pm, pk[k] % q, q);
+                hq[k] = 1;   /* (P/p_k) mod q */
+                for (int j = 0; j < alpha; ++j) if (j != k) hq[k] = mulmod(hq[k], pk[j] % q, q);
+            }
+            u64 pinv = invmod(pm, q);
+            const u64 *xi = acc + ((size_t)comp * lt + i) * n;
             u64 *o = out + ((size_t)comp * l + i) * n;
             for (int k = 0; k < n; ++k) {
-                u64 yk1 = mulmod(x1[k], h1, p1), yk2 = mulmod(x2[k], h2, p2);
-                u64 cv = addmod(mulmod(yk1 % q, c1, q), mulmod(yk2 % q, c2, q), q);
+                u64 cv = 0;
+                for (int j = 0; j < alpha; ++j) {
+                    u64 yk = mulmod(xs[(size_t)j * n + k], hinv[j], pk[j]);
+                    cv = addmod(cv, mulmod(yk % q, hq[j], q), q);
+                }
                 o[k] = mulmod(submod(xi[k], cv, q), pinv, q);
             }
         }
@@ -504,17 +519,16 @@ void ref_keyswitch(const ref_ctx *c, int L, int l, const u64 *d, int n_keys, con
 
 /*
  * Switching key for s' (given as residues sp[t][N], t <= L) in coefficient form,
- * key[2][ng][L+3][N]: for group b and target t (q_0..q_L, p_1, p_2),
+ * key[2][ng][L+1+alpha][N]: for group b and target t (q_0..q_L, p_1..p_alpha),
  *   key[0][b][t] = -a_b s + e_b + [t in group b] (P mod q_t) s'_t,   key[1][b][t] = a_b,
  * a_b uniform with stream sid_base + 2b (modulus index t), e_b centred binomial with stream
  * sid_base + 2b + 1.  max_l < L + 1: only the groups and targets a ciphertext of at most max_l
  * limbs uses (the entries are those of the full key).
  */
-void ref_gen_ksk(const ref_ctx *c, int L, const i64 *s, const u64 *sp, u64 seed, u64 sid_base,
+void ref_gen_ksk(const ref_ctx *c, int L, int alpha, const i64 *s, const u64 *sp, u64 seed, u64 sid_base,
                  int max_l, u64 *key) {
-    int n = c->n, nt = L + 3, ng = ref_num_groups(L + 1);
+    int n = c->n, nt = L + 1 + alpha, ng = ref_num_groups(L + 1, alpha);
     size_t kc = (size_t)ng * nt * n;
-    u64 p1 = c->mods[L + 1].q, p2 = c->mods[L + 2].q;
 #pragma omp parallel
     {
         i64 *e = (i64 *)malloc(sizeof(i64) * n);
@@ -522,7 +536,7 @@ void ref_gen_ksk(const ref_ctx *c, int L, const i64 *s, const u64 *sp, u64 seed,
 #pragma omp for schedule(dynamic)
         for (int bt = 0; bt < ng * nt; ++bt) {
             int b = bt / nt, t = bt % nt;
-            if (grp_first(b) >= max_l || (t >= max_l && t <= L)) continue;
+            if (grp_first(b, alpha) >= max_l || (t >= max_l && t <= L)) continue;
             u64 q = c->mods[t].q;
             u64 *kb = key + (size_t)b * nt * n + (size_t)t * n;
             u64 *ka = key + kc + (size_t)b * nt * n + (size_t)t * n;
@@ -531,9 +545,10 @@ void ref_gen_ksk(const ref_ctx *c, int L, const i64 *s, const u64 *sp, u64 seed,
             for (int k = 0; k < n; ++k) sres[k] = from_signed(s[k], q);
             ref_polymul(c, t, ka, sres, as);
             for (int k = 0; k < n; ++k) kb[k] = addmod(submod(0, as[k], q), from_signed(e[k], q), q);
-            int f = grp_first(b), m = grp_size(b, L + 1);
+            int f = grp_first(b, alpha), m = grp_size(b, L + 1, alpha);
             if (t <= L && t >= f && t < f + m) {
-                u64 pm = mulmod(p1 % q, p2 % q, q);
+                u64 pm = 1;   /* P mod q_t */
+                for (int k = 0; k < alpha; ++k) pm = mulmod(pm, c->mods[L + 1 + k].q % q, q);
                 const u64 *spt = sp + (size_t)t * n;
                 for (int k = 0; k < n; ++k) kb[k] = addmod(kb[k], mulmod(pm, spt[k], q), q);
             }
@@ -543,12 +558,12 @@ void ref_gen_ksk(const ref_ctx *c, int L, const i64 *s, const u64 *sp, u64 seed,
 }
 
 /* key (coefficient form, [2][ng][nt][N]) -> the oracle's evaluation form, same layout */
-void ref_key_to_eval(const ref_ctx *c, int L, int max_l, const u64 *key, u64 *kev) {
-    int n = c->n, nt = L + 3, ng = ref_num_groups(L + 1);
+void ref_key_to_eval(const ref_ctx *c, int L, int alpha, int max_l, const u64 *key, u64 *kev) {
+    int n = c->n, nt = L + 1 + alpha, ng = ref_num_groups(L + 1, alpha);
 #pragma omp parallel for schedule(dynamic)
     for (int x = 0; x < 2 * ng * nt; ++x) {
         int t = x % nt, b = (x / nt) % ng;
-        if (grp_first(b) >= max_l || (t >= max_l && t <= L)) continue;
+        if (grp_first(b, alpha) >= max_l || (t >= max_l && t <= L)) continue;
         ref_to_eval(c, t, key + (size_t)x * n, kev + (size_t)x * n);
     }
 }

@@ -15,5 +15,6 @@ from ._binding import (  # noqa: F401
     chain,
     exported_symbols,
     gwas_galois_elements,
+    ks_alpha,
     lib,
 )

@@ -26,7 +26,8 @@ _szp = ctypes.POINTER(ctypes.c_size_t)
 
 
 class CkksParams(ctypes.Structure):
-    _fields_ = [("log_n", ctypes.c_int), ("levels", ctypes.c_int), ("log2_scale", ctypes.c_int)]
+    _fields_ = [("log_n", ctypes.c_int), ("levels", ctypes.c_int), ("log2_scale", ctypes.c_int),
+                ("ks_alpha", ctypes.c_int)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -63,6 +64,7 @@ def _close_all():
 # (name, restype, argtypes)
 _SIGS = [
     ("ckks_last_error", ctypes.c_char_p, []),
+    ("ckks_params_ks_alpha", ctypes.c_int, [ctypes.POINTER(CkksParams)]),
     ("ckks_chain", ctypes.c_int, [ctypes.POINTER(CkksParams), _u64p, _dp]),
     ("ckks_ctx_create", ctypes.c_int, [ctypes.POINTER(CkksParams), ctypes.POINTER(CkksAllocator), _vp, ctypes.c_size_t,
                                        ctypes.POINTER(_vp)]),
@@ -174,10 +176,18 @@ def _f64(a: np.ndarray):
     return a.ctypes.data_as(_dp)
 
 
-def chain(log_n: int, levels: int, log2_scale: int):
-    """(q_0..q_L, [p_1, p_2], canonical scales): the moduli and scales of the parameters (host only)."""
-    p = CkksParams(log_n, levels, log2_scale)
-    q = np.zeros(levels + 3, dtype=np.uint64)
+def ks_alpha(log_n: int, levels: int, log2_scale: int, alpha: int = 0) -> int:
+    """Digit-group size of key switching that the parameters select (alpha = 0: the library default)."""
+    a = lib().ckks_params_ks_alpha(ctypes.byref(CkksParams(log_n, levels, log2_scale, alpha)))
+    if a < 0:
+        _check(a)
+    return int(a)
+
+
+def chain(log_n: int, levels: int, log2_scale: int, alpha: int = 0):
+    """(q_0..q_L, [p_1..p_alpha], canonical scales): the moduli and scales of the parameters (host only)."""
+    p = CkksParams(log_n, levels, log2_scale, alpha)
+    q = np.zeros(levels + 1 + ks_alpha(log_n, levels, log2_scale, alpha), dtype=np.uint64)
     s = np.zeros(levels + 1, dtype=np.float64)
     _check(lib().ckks_chain(ctypes.byref(p), _u64(q), _f64(s)))
     return [int(v) for v in q[:levels + 1]], [int(v) for v in q[levels + 1:]], [float(v) for v in s]
@@ -229,9 +239,10 @@ class Ciphertext:
 
 class Context:
     def __init__(self, log_n: int, levels: int, log2_scale: int, use_torch: bool = True, pool_budget: int = 0,
-                 stream: Optional[int] = None):
+                 stream: Optional[int] = None, alpha: int = 0):
         self.h = None
-        p = CkksParams(log_n, levels, log2_scale)
+        p = CkksParams(log_n, levels, log2_scale, alpha)
+        self.alpha = ks_alpha(log_n, levels, log2_scale, alpha)   # digit-group size of key switching
         self._keep = []
         alloc = None
         if use_torch:
@@ -283,7 +294,7 @@ class Context:
 
     # ---- parameters
     def moduli(self) -> List[int]:
-        a = np.zeros(self.levels + 3, dtype=np.uint64)
+        a = np.zeros(self.levels + 1 + self.alpha, dtype=np.uint64)
         _check(lib().ckks_ctx_moduli(self.h, _u64(a), len(a)))
         return [int(v) for v in a]
 
@@ -334,7 +345,7 @@ class Context:
 
     def export_switching_key(self, key_id: int) -> np.ndarray:
         L = self.levels
-        a = np.zeros((2, 1 + (L + 1) // 2, L + 3, self.N), dtype=np.uint64)
+        a = np.zeros((2, 1 + (L + 1) // self.alpha, L + 1 + self.alpha, self.N), dtype=np.uint64)
         _check(lib().ckks_export_switching_key(self.h, key_id, _u64(a), a.size))
         return a
 

@@ -91,11 +91,11 @@ void build_ks_tables(ckks_ctx &c) {
     std::vector<std::vector<int>> didx(nq + 1);
     std::vector<std::vector<LimbScale>> scales(nq + 1);
     for (int l = 1; l <= nq; ++l) {
-        const int gl = ks_groups(l), nt = l + kSpecial;
+        const int gl = ks_groups(l, p.alpha), nt = l + p.alpha;
         didx[l].assign((size_t)gl * nt, -1);
         scales[l].resize(l);
         for (int b = 0; b < gl; ++b) {
-            const int f = ks_group_first(b), m = ks_group_size(b, l);
+            const int f = ks_group_first(b, p.alpha), m = ks_group_size(b, l, p.alpha);
             std::vector<u64> mods;
             for (int i = f; i < f + m; ++i) mods.push_back(p.q[i]);
             // y_i = d_i (Q_G / q_i)^-1, folded with N^-1 into the inverse NTT
@@ -111,7 +111,7 @@ void build_ks_tables(ckks_ctx &c) {
                 if (t < l && t >= f && t < f + m) continue;   // the digit's own primes: the input residue
                 const int chain = t < l ? t : L + 1 + (t - l);
                 const u64 qt = p.mod(chain);
-                u64 cs[2] = {1, 1};
+                u64 cs[kMaxSpecial] = {};
                 for (int a = 0; a < m; ++a) {
                     u64 hat = 1;
                     for (int j = f; j < f + m; ++j)
@@ -123,19 +123,32 @@ void build_ks_tables(ckks_ctx &c) {
             }
         }
     }
+    // ModDown: C = sum_k [x (P/p_k)^-1]_{p_k} (P/p_k); (P/p_k)^-1 and N^-1 folded into the special limbs'
+    // inverse NTT, P/p_k mod q_i into the conversion, P^-1 mod q_i into the final store
+    const int a = p.alpha;
     std::vector<ConvEntry> down(nq);
     for (int i = 0; i < nq; ++i) {
-        const u64 cs[2] = {p.P[1], p.P[0]};   // P / p_1, P / p_2
-        down[i] = conv_entry(0, kSpecial, i, cs, p.q[i], p.P);
+        u64 cs[kMaxSpecial] = {};
+        for (int k = 0; k < a; ++k) {
+            u64 hat = 1;
+            for (int j = 0; j < a; ++j)
+                if (j != k) hat = mulmod_host(hat, p.P[j] % p.q[i], p.q[i]);
+            cs[k] = hat;
+        }
+        down[i] = conv_entry(0, a, i, cs, p.q[i], p.P);
     }
-    std::vector<LimbScale> dscale(kSpecial);
-    for (int k = 0; k < kSpecial; ++k) {
-        const u64 pk = p.P[k], other = p.P[1 - k];
-        dscale[k] = limb_scale(mulmod_host(invmod_host((u64)p.n % pk, pk), invmod_host(other % pk, pk), pk), pk);
+    std::vector<LimbScale> dscale(a);
+    for (int k = 0; k < a; ++k) {
+        const u64 pk = p.P[k];
+        u64 hat = 1;
+        for (int j = 0; j < a; ++j)
+            if (j != k) hat = mulmod_host(hat, p.P[j] % pk, pk);
+        dscale[k] = limb_scale(mulmod_host(invmod_host((u64)p.n % pk, pk), invmod_host(hat, pk), pk), pk);
     }
     for (int i = 0; i < p.n_mods(); ++i) {
         const u64 q = p.mod(i);
-        const u64 pm = mulmod_host(p.P[0] % q, p.P[1] % q, q);
+        u64 pm = 1;
+        for (int k = 0; k < a; ++k) pm = mulmod_host(pm, p.P[k] % q, q);
         c.p_inv.v[i] = pm ? invmod_host(pm, q) : 0;
         c.p_inv.sh[i] = shoup_of(c.p_inv.v[i], q);
     }
@@ -171,7 +184,7 @@ void build_ks_tables(ckks_ctx &c) {
     c.p_inv_sh_dev = reinterpret_cast<u64 *>(base + o_pinv_sh);
     GCK_HIP(hipMemcpy(c.p_inv_dev, c.p_inv.v, kMaxMods * 8, hipMemcpyHostToDevice));
     GCK_HIP(hipMemcpy(c.p_inv_sh_dev, c.p_inv.sh, kMaxMods * 8, hipMemcpyHostToDevice));
-    c.ng = ks_groups(nq);
+    c.ng = ks_groups(nq, p.alpha);
 }
 
 void build_tables(ckks_ctx &c) {
@@ -254,10 +267,16 @@ extern "C" {
 
 const char *ckks_last_error(void) { return g_err.c_str(); }
 
+int ckks_params_ks_alpha(const ckks_params *params) {
+    if (!params) return CKKS_E_INVALID_ARG;
+    const int a = params->ks_alpha == 0 ? CKKS_DEFAULT_KS_ALPHA : params->ks_alpha;
+    return (a >= 2 && a <= kMaxSpecial) ? a : CKKS_E_INVALID_ARG;
+}
+
 int ckks_chain(const ckks_params *params, uint64_t *moduli, double *scales) {
     return guard([&] {
         need(params && moduli && scales, "null argument");
-        Params p = make_params(params->log_n, params->levels, params->log2_scale);
+        Params p = make_params(params->log_n, params->levels, params->log2_scale, params->ks_alpha);
         for (int i = 0; i < p.n_mods(); ++i) moduli[i] = p.mod(i);
         for (int i = 0; i <= p.levels; ++i) scales[i] = p.scales[i];
     });
@@ -269,7 +288,7 @@ int ckks_ctx_create(const ckks_params *params, const ckks_allocator *allocator, 
         need(params && out, "null argument");
         *out = nullptr;
         auto c = std::make_unique<ckks_ctx>();
-        c->p = make_params(params->log_n, params->levels, params->log2_scale);
+        c->p = make_params(params->log_n, params->levels, params->log2_scale, params->ks_alpha);
         c->stream = static_cast<hipStream_t>(hip_stream);
         c->pool = std::make_unique<Pool>(allocator, pool_budget_bytes);
         c->pool->stream = c->stream;

@@ -19,8 +19,8 @@ using u64 = uint64_t;
 using i64 = int64_t;
 using u128 = unsigned __int128;
 
-constexpr int kMaxMods = 64;   // q_0..q_L and the special primes
-constexpr int kSpecial = 2;    // special primes p_1, p_2 of the key-switching modulus P = p_1 p_2
+constexpr int kMaxMods = 64;     // q_0..q_L and the special primes
+constexpr int kMaxSpecial = 8;   // special primes p_1 .. p_alpha of the key-switching modulus P (alpha <= 8)
 
 // ---------------------------------------------------------------- errors
 struct Error : std::runtime_error {
@@ -51,24 +51,26 @@ constexpr int kFpModBits = 41;
 // ---------------------------------------------------------------- parameters and prime chain
 struct Params {
     int log_n = 0, n = 0, levels = 0, log2_scale = 0;
+    int alpha = 0;             // digit-group size of the key switch = number of special primes
     std::vector<u64> q;        // q_0 .. q_L
-    std::vector<u64> P;        // special primes p_1 .. p_kSpecial
+    std::vector<u64> P;        // special primes p_1 .. p_alpha
     std::vector<double> scales;  // canonical Delta_0 .. Delta_L
     int limbs_at(int depth) const { return levels + 1 - depth; }
     u64 dropped_at(int depth) const { return q[levels - depth]; }  // prime removed by the rescale at depth
     int p_index() const { return levels + 1; }                      // chain index of p_1
-    int n_mods() const { return levels + 1 + kSpecial; }            // chain indices q_0..q_L, p_1..
+    int n_mods() const { return levels + 1 + alpha; }               // chain indices q_0..q_L, p_1..p_alpha
     u64 mod(int idx) const { return idx <= levels ? q[idx] : P[idx - levels - 1]; }
 };
-// Key-switching digit groups (hybrid decomposition): group 0 is {q_0}, group b >= 1 is {q_{2b-1}, q_{2b}};
-// a ciphertext with l limbs uses the 1 + l / 2 groups with a member below l, cut at l.
-__host__ __device__ inline int ks_groups(int l) { return 1 + l / 2; }
-__host__ __device__ inline int ks_group_first(int b) { return b == 0 ? 0 : 2 * b - 1; }
-__host__ __device__ inline int ks_group_size(int b, int l) {
-    const int f = ks_group_first(b), e = b == 0 ? 1 : 2 * b + 1;
+// Key-switching digit groups (hybrid decomposition, group size a = alpha): group 0 is {q_0 .. q_{a-2}},
+// group b >= 1 is {q_{a b - 1} .. q_{a b + a - 2}}; a ciphertext with l limbs uses the 1 + l / a groups
+// with a member below l, cut at l.
+__host__ __device__ inline int ks_groups(int l, int a) { return 1 + l / a; }
+__host__ __device__ inline int ks_group_first(int b, int a) { return b == 0 ? 0 : a * b - 1; }
+__host__ __device__ inline int ks_group_size(int b, int l, int a) {
+    const int f = ks_group_first(b, a), e = a * (b + 1) - 1;
     return (e < l ? e : l) - f;
 }
-Params make_params(int log_n, int levels, int log2_scale);
+Params make_params(int log_n, int levels, int log2_scale, int alpha);
 u64 mulmod_host(u64 a, u64 b, u64 q);
 u64 powmod_host(u64 b, u64 e, u64 q);
 u64 invmod_host(u64 a, u64 q);
@@ -122,7 +124,7 @@ struct DBuf {
 // index (0..L for q_i, L+1.. for the special primes) of limb lam is given by a ModMap:
 //     t = lam % period;  chain = (t < nq) ? t : p_idx + (t - nq)
 // and t >= nq is the special prime p_idx + (t - nq); e.g. ciphertext data [count][2][l][N] has
-// period = nq = l; key-switch accumulators [count][2][l + kSpecial][N] have period l + kSpecial, nq = l.
+// period = nq = l; key-switch accumulators [count][2][l + alpha][N] have period l + alpha, nq = l.
 struct ModMap {
     int period, nq, p_idx;
 };
@@ -180,8 +182,8 @@ void k_ntt_inverse(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStrea
 // e.big), c_m = e.c[m] (with its Shoup companion and FP64 copy).
 struct ConvEntry {
     int src, nsrc, chain, big;
-    u64 c[2], c_sh[2];
-    double cd[2];
+    u64 c[kMaxSpecial], c_sh[kMaxSpecial];
+    double cd[kMaxSpecial];
 };
 struct Gather {
     const u64 *ptr;
@@ -243,13 +245,13 @@ struct KsKeys {
     u64 g[kMaxKeys];
     int m;
 };
-// key-switch inner product over the targets t < l + kSpecial (q_0..q_{l-1}, p_1, p_2):
+// key-switch inner product over the targets t < l + alpha (q_0..q_{l-1}, p_1..p_alpha):
 //   acc[c][comp][t] = sum_i sum_b sigma_i(D_b[c][t]) * key_i[comp][b][chain(t)],
-// D_b[c][t] = digits[c][didx[b (l + kSpecial) + t]] when that index is >= 0, else limb t of ciphertext c
+// D_b[c][t] = digits[c][didx[b (l + alpha) + t]] when that index is >= 0, else limb t of ciphertext c
 // gathered by `own` (the digit's residue at its own group's primes equals the input residue).  Keys are
-// [2][ng][L + 1 + kSpecial][N] in NTT and Montgomery form (times 2^64); digits hold K limbs per ciphertext.
+// [2][ng][L + 1 + alpha][N] in NTT and Montgomery form (times 2^64); digits hold K limbs per ciphertext.
 void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const int *didx, const Gather &own,
-                const KsKeys &keys, int ng, int count, int l, int levels, hipStream_t st);
+                const KsKeys &keys, int ng, int count, int l, int levels, int alpha, hipStream_t st);
 // [count][2][l] batches: with_self: out = (a c0 + sum_i sigma_{g[i]}(a c0), a c1); otherwise
 // out c0 rows = sum_i sigma_{g[i]}(a c0) and out c1 rows are not written
 void k_automorph_c0(const DevTables &t, u64 *out, const u64 *a, int count, int l, const KsKeys &gs, bool with_self,

@@ -319,11 +319,11 @@ static const u64 *key_of(const ckks_ctx &c, u64 id) {
 }
 
 // Key switch of the polynomial gathered by `d` (count ciphertexts, l limbs, NTT form) with the keys of
-// `keys` (hybrid decomposition, digit groups {q_0}, {q_1, q_2}, ...):
+// `keys` (hybrid decomposition, digit groups of alpha primes {q_0 .. q_{alpha-2}}, {q_{alpha-1} ..}, ...):
 //   ModUp    y_i = d_i (Q_G/q_i)^-1 (folded into the inverse NTT), then each group's digit
 //            D = sum_{i in G} y_i (Q_G/q_i) converted to every other target while loading the forward
 //            NTT (its residues at its own primes are the input limbs themselves);
-//   inner    x = sum_i sum_b sigma_i(D_b) ksk_{i,b} over the targets q_0..q_{l-1}, p_1, p_2, the digits
+//   inner    x = sum_i sum_b sigma_i(D_b) ksk_{i,b} over the targets q_0..q_{l-1}, p_1..p_alpha, the digits
 //            read through each key's automorphism;
 //   ModDown  (x - C) / P with C = sum_k [x (P/p_k)^-1]_{p_k} (P/p_k) (the scales folded into the
 //            inverse NTT of the special limbs, the conversion into the forward NTT's load, the
@@ -334,7 +334,7 @@ static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, const KsKe
                       bool add_even) {
     const size_t N = (size_t)c.p.n;
     const ckks_ctx::KsLevel &kl = c.ks_levels.at(l);
-    const int nt = l + kSpecial, P = c.p.p_index();
+    const int a = c.p.alpha, nt = l + a, P = c.p.p_index();
     DBuf dc(c.pool.get(), (size_t)count * l * N);
     k_ntt_inverse_g(c.tab, dc.ptr, d, count * l, map_q(l), c.stream, kl.up_scale, l);
     DBuf dig(c.pool.get(), (size_t)count * kl.K * N);
@@ -342,18 +342,18 @@ static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, const KsKe
                     c.stream);
     dc.release();
     DBuf acc(c.pool.get(), (size_t)count * 2 * nt * N);
-    k_ks_inner(c.tab, acc.ptr, dig.ptr, kl.K, kl.didx, d, keys, c.ng, count, l, c.p.levels, c.stream);
+    k_ks_inner(c.tab, acc.ptr, dig.ptr, kl.K, kl.didx, d, keys, c.ng, count, l, c.p.levels, a, c.stream);
     dig.release();
     const int rows = count * 2;
-    DBuf ap(c.pool.get(), (size_t)rows * kSpecial * N);
-    k_ntt_inverse_g(c.tab, ap.ptr, Gather{acc.ptr, kSpecial, nt, l, 1, kPlain, 0}, rows * kSpecial,
-                    ModMap{kSpecial, 0, P}, c.stream, c.down_scale, kSpecial);
+    DBuf ap(c.pool.get(), (size_t)rows * a * N);
+    k_ntt_inverse_g(c.tab, ap.ptr, Gather{acc.ptr, a, nt, l, 1, kPlain, 0}, rows * a, ModMap{a, 0, P}, c.stream,
+                    c.down_scale, a);
     DBuf out(c.pool.get(), (size_t)rows * l * N);
     const ModDownEpi epi{Gather{acc.ptr, l, nt, 0, 1, kPlain, 0}, add, add_even ? 1 : 0, l, c.p_inv_dev,
                          c.p_inv_sh_dev};
-    k_ntt_forward_g(c.tab, out.ptr, Gather{ap.ptr, 1, 1, 0, 0, kConv, 0, c.down_conv, l, kSpecial}, rows * l, map_q(l),
+    k_ntt_forward_g(c.tab, out.ptr, Gather{ap.ptr, 1, 1, 0, 0, kConv, 0, c.down_conv, l, a}, rows * l, map_q(l),
                     c.stream, &epi);
-    c.n_limb_ntt += (uint64_t)count * (l + kl.K) + (uint64_t)rows * (kSpecial + l);
+    c.n_limb_ntt += (uint64_t)count * (l + kl.K) + (uint64_t)rows * (a + l);
     c.n_launch += 9;
     ++c.n_keyswitch;
     return out;
@@ -500,14 +500,14 @@ static std::vector<i64> sample_hwt_host(u64 seed, u64 sid, int n, int h) {
 static u64 ksk_sid_base(u64 key_id) { return (1ULL << 40) | (key_id << 20); }
 
 // switching key for target secret sp (NTT form, L+1 limbs over q_0..q_L) under key id:
-// [2][ng][L+3][N], for group b and target t (q_0..q_L, p_1, p_2)
+// [2][ng][L+1+alpha][N], for group b and target t (q_0..q_L, p_1..p_alpha)
 //   key[0][b][t] = -a_b s + e_b + [t in group b] (P mod q_t) s'_t,  key[1][b][t] = a_b,
 // a_b uniform (stream base + 2b, modulus index t), e_b centred binomial (stream base + 2b + 1); stored in
 // NTT and Montgomery form.
 static void make_switching_key(ckks_ctx &c, u64 seed, u64 key_id, const u64 *sp) {
     const int L = c.p.levels, nt = c.p.n_mods(), ng = c.ng, P = c.p.p_index();
     const size_t N = (size_t)c.p.n;
-    const ModMap mt{nt, L + 1, P};          // targets q_0..q_L, p_1, p_2
+    const ModMap mt{nt, L + 1, P};          // targets q_0..q_L, p_1..p_alpha
     DBuf key(c.pool.get(), (size_t)2 * ng * nt * N);
     DBuf e_small(c.pool.get(), N);
     DBuf as(c.pool.get(), (size_t)nt * N);
@@ -522,10 +522,11 @@ static void make_switching_key(ckks_ctx &c, u64 seed, u64 key_id, const u64 *sp)
         ntt_fwd(c, kb, nt, mt);
         k_mul(c.tab, as.ptr, ka, c.sk_ntt.ptr, nt, mt, nt, nt, c.stream);
         k_sub(c.tab, kb, kb, as.ptr, nt, mt, nt, nt, c.stream);
-        const int f = ks_group_first(b), m = ks_group_size(b, L + 1);
+        const int f = ks_group_first(b, c.p.alpha), m = ks_group_size(b, L + 1, c.p.alpha);
         for (int t = f; t < f + m; ++t) {   // + (P mod q_t) s'_t on the group's own targets
             const u64 q = c.p.q[t];
-            const u64 v = mulmod_host(c.p.P[0] % q, c.p.P[1] % q, q);
+            u64 v = 1;
+            for (u64 pk : c.p.P) v = mulmod_host(v, pk % q, q);
             ChainConst pj{};
             pj.v[t] = v;
             pj.sh[t] = (u64)(((u128)v << 64) / q);

@@ -277,7 +277,7 @@ void k_sub_mul_add(const DevTables &t, u64 *out, const Gather &a, const u64 *b, 
 // ---------------------------------------------------------------- key-switch inner product
 //
 // acc[c][comp][t][k] = sum_i sum_b sigma_i(D_b[c][t])[k] * key_i[comp][b][chain(t)][k] mod the target's
-// modulus, over the targets t < l + kSpecial (q_0..q_{l-1}, then the special primes).  The key words
+// modulus, over the targets t < l + alpha (q_0..q_{l-1}, then the special primes).  The key words
 // carry a factor 2^64 (Montgomery form).  One thread per (group of CB ciphertexts, target t, word k);
 // consecutive 256-thread blocks hold the groups of one (t, 256-word chunk), so the key words a chunk
 // needs are fetched from HBM once and re-read from cache by the other groups.  Targets below 2^41
@@ -383,13 +383,13 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
 
 template <int CB, int MK>
 __global__ void ks_inner(u64 *acc, const u64 *digits, int K, const int *__restrict__ didx, Gather own, KsKeys keys,
-                         int ng, size_t total, int log_n, int l, int levels, int count, const ModInfo *mods) {
+                         int ng, size_t total, int log_n, int l, int levels, int alpha, int count, const ModInfo *mods) {
     const size_t n = (size_t)1 << log_n;
-    const int nt = l + kSpecial;                 // targets of this key switch
-    const int nt_key = levels + 1 + kSpecial;    // targets of a key
+    const int nt = l + alpha;                 // targets of this key switch
+    const int nt_key = levels + 1 + alpha;    // targets of a key
     const size_t key_comp = (size_t)ng * nt_key * n;
     const size_t key_grp = (size_t)nt_key * n;
-    const int gl = ks_groups(l);
+    const int gl = ks_groups(l, alpha);
     const int groups = (count + CB - 1) / CB;
     const size_t chunks = n >> 8;   // 256-word chunks per limb
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
@@ -422,8 +422,8 @@ __global__ void ks_inner(u64 *acc, const u64 *digits, int K, const int *__restri
     }
 }
 void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const int *didx, const Gather &own,
-                const KsKeys &keys, int ng, int count, int l, int levels, hipStream_t st) {
-    const int nt = l + kSpecial, gl = ks_groups(l);
+                const KsKeys &keys, int ng, int count, int l, int levels, int alpha, hipStream_t st) {
+    const int nt = l + alpha, gl = ks_groups(l, alpha);
     // algorithmic bytes: every key word and every digit word read once, the accumulators written once
     const int cb = count >= 4 ? 4 : (count >= 2 ? 2 : 1);   // 8 (with fewer waves, or spills) measured slower
     const int mk = (keys.m == 1 || keys.m == 3) ? keys.m : 0;
@@ -438,7 +438,7 @@ void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const in
     const dim3 grid = ew_grid(total), block(kEwThreads);
 #define GCK_KS(CB_, MK_) \
     hipLaunchKernelGGL((ks_inner<CB_, MK_>), grid, block, 0, st, acc, digits, K, didx, own, keys, ng, total, t.log_n, \
-                       l, levels, count, t.mods)
+                       l, levels, alpha, count, t.mods)
     switch (cb * 10 + mk) {
     case 41: GCK_KS(4, 1); break;
     case 43: GCK_KS(4, 3); break;

@@ -23,6 +23,9 @@
 //   fully reduced on the way out.
 #include <hip/hip_runtime.h>
 
+#include <string>
+#include <vector>
+
 #include "modarith.h"
 
 namespace gck {
@@ -202,9 +205,10 @@ __device__ __forceinline__ void exchange(T (&v)[kPer], T *sh, int gi, int q, int
 }
 
 // One pass.  ROWS selects the rows pass (sub-transforms of N2 contiguous words) or the cols pass
-// (N1-point sub-transforms down columns).  src != nullptr (forward cols pass only): the input of
-// output limb lam is limb lam / src_div of src, reduced modulo the output limb's modulus (ModUp).
-template <bool INV, bool ROWS, int LOGM>
+// (N1-point sub-transforms down columns).  `in` (first pass only) gathers the input from another buffer;
+// CONV (forward cols pass only) is the basis-conversion gather, a separate instantiation so that the
+// other passes do not carry its registers.
+template <bool INV, bool ROWS, int LOGM, bool CONV>
 __global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, Gather in, ModMap mm,
                                                      const ModInfo *__restrict__ mods, const u64 *__restrict__ tw,
                                                      const u64 *__restrict__ tw_sh,
@@ -217,6 +221,7 @@ __global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, G
     const int bid = block_id(g);
     const int limb = bid >> (g.log_n - log_tile);
     const int tile = bid & (g.tiles - 1);
+    // a basis-conversion NTT takes every output limb's modulus from its conversion entry, in both passes
     const ConvEntry *ce = g.conv ? g.conv + limb % g.conv_period : nullptr;
     const int chain = ce ? ce->chain : chain_of(limb, mm);
     const ModInfo M = mods[chain];
@@ -238,7 +243,7 @@ __global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, G
     const u64 *ain = a;
     int mode = kPlain;
     u64 src_q = 0, src_half = 0, src_q_red = 0;
-    if (in.ptr && in.mode == kConv) {
+    if (CONV) {
         mode = kConv;
         ain = in.ptr + ((size_t)(limb / g.conv_period) * in.src_stride + ce->src) * n;
     } else if (in.ptr) {
@@ -268,30 +273,51 @@ __global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, G
     // wave instruction covers 16 consecutive words of each of 4 rows (an LDS transposition in the cols
     // passes, loads or stores, measured slower than the strided access it replaces)
     u64 v[kPer];
-    if (mode == kConv) {
-        // basis conversion while loading: sum_m y_m c_m mod q (FP64 moduli: as double bits, reduced)
-        const ConvEntry E = *ce;
+    if constexpr (CONV) {
+        // basis conversion while loading: sum_m y_m c_m mod q, one source limb at a time (its 16 loads
+        // issued together); FP64 moduli keep the sum as a double (|sum| < 1.1 q per source, below 2^45 for
+        // up to kMaxSpecial sources) and store its bits
+        const int ns = ce->nsrc, big = ce->big;
         const FMod fm{M.qd, M.qinv};
+        if (M.fp) {
+            double x[kPer];
 #pragma unroll
-        for (int e = 0; e < kPer; ++e) {
-            const size_t at = base + (size_t)slot_index<LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(e, q) * stride;
-            const u64 y0 = ain[at];
-            const u64 y1 = E.nsrc > 1 ? ain[at + n] : 0;
-            if (M.fp) {
-                const double a0 = E.big ? fred(fmul_mod((double)(y0 >> 32), M.c32_d, fm) + (double)(y0 & 0xFFFFFFFFULL), fm)
-                                        : (double)y0;
-                double x = fmul_mod(a0, E.cd[0], fm);
-                if (E.nsrc > 1) {
-                    const double a1 = E.big ? fred(fmul_mod((double)(y1 >> 32), M.c32_d, fm) +
-                                                       (double)(y1 & 0xFFFFFFFFULL), fm)
-                                            : (double)y1;
-                    x += fmul_mod(a1, E.cd[1], fm);
+            for (int e = 0; e < kPer; ++e) x[e] = 0.0;
+            for (int m = 0; m < ns; ++m) {
+                const u64 *src = ain + (size_t)m * n + base;
+                const double w = ce->cd[m];
+#pragma unroll
+                for (int h = 0; h < kPer; h += kPer / 2) {
+                    u64 y[kPer / 2];
+#pragma unroll
+                    for (int e = 0; e < kPer / 2; ++e)
+                        y[e] = src[(size_t)slot_index<LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(h + e, q) * stride];
+#pragma unroll
+                    for (int e = 0; e < kPer / 2; ++e) {
+                        const double a = big ? fred(fmul_mod((double)(y[e] >> 32), M.c32_d, fm) +
+                                                        (double)(y[e] & 0xFFFFFFFFULL), fm)
+                                             : (double)y[e];
+                        x[h + e] += fmul_mod(a, w, fm);
+                    }
                 }
-                v[e] = (u64)__double_as_longlong(fred(x, fm));
-            } else {
-                u64 r = mul_shoup(y0, E.c[0], E.c_sh[0], qm);
-                if (E.nsrc > 1) r = add_mod(r, mul_shoup(y1, E.c[1], E.c_sh[1], qm), qm);
-                v[e] = r;
+            }
+#pragma unroll
+            for (int e = 0; e < kPer; ++e) v[e] = (u64)__double_as_longlong(fred(x[e], fm));
+        } else {
+#pragma unroll
+            for (int e = 0; e < kPer; ++e) v[e] = 0;
+            for (int m = 0; m < ns; ++m) {
+                const u64 *src = ain + (size_t)m * n + base;
+                const u64 w = ce->c[m], wsh = ce->c_sh[m];
+#pragma unroll
+                for (int h = 0; h < kPer; h += kPer / 2) {
+                    u64 y[kPer / 2];
+#pragma unroll
+                    for (int e = 0; e < kPer / 2; ++e)
+                        y[e] = src[(size_t)slot_index<LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(h + e, q) * stride];
+#pragma unroll
+                    for (int e = 0; e < kPer / 2; ++e) v[h + e] = add_mod(v[h + e], mul_shoup(y[e], w, wsh, qm), qm);
+                }
             }
         }
     } else {
@@ -306,7 +332,7 @@ __global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, G
         const FMod fm{M.qd, M.qinv};
         const double *Wf = tw_f + (size_t)chain * n;
         double f[kPer];
-        if (last_pass || mode == kConv) {
+        if (last_pass || CONV) {
 #pragma unroll
             for (int e = 0; e < kPer; ++e) f[e] = __longlong_as_double((long long)v[e]);
         } else if (mode == kPlain) {
@@ -352,7 +378,7 @@ __global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, G
             v[e] = last_pass ? fcanon(x, fm) : (u64)__double_as_longlong(fred(x, fm));
         }
     } else {
-        if (!last_pass && mode != kPlain && mode != kConv) {
+        if (!CONV && !last_pass && mode != kPlain) {
 #pragma unroll
             for (int e = 0; e < kPer; ++e) {
                 u64 x = v[e];
@@ -426,13 +452,13 @@ __global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, G
     }
 }
 
-template <bool INV, bool ROWS>
+template <bool INV, bool ROWS, bool CONV = false>
 void launch_pass(int log_m, dim3 grid, dim3 block, hipStream_t st, u64 *buf, const Gather &in, ModMap m,
                  const ModInfo *mods, const u64 *tw, const u64 *tws, const double *twf, Geom g) {
     switch (log_m) {
-#define GCK_NTT_CASE(L)                                                                             \
-    case L:                                                                                         \
-        hipLaunchKernelGGL((ntt_pass<INV, ROWS, L>), grid, block, 0, st, buf, in, m, mods, tw, tws, twf, g); \
+#define GCK_NTT_CASE(L)                                                                                   \
+    case L:                                                                                               \
+        hipLaunchKernelGGL((ntt_pass<INV, ROWS, L, CONV>), grid, block, 0, st, buf, in, m, mods, tw, tws, twf, g); \
         break;
         GCK_NTT_CASE(5)
         GCK_NTT_CASE(6)
@@ -480,22 +506,29 @@ static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, 
     const double bytes1 = shared_src ? 8.0 * t.n * ((double)n_limbs + src_limbs) : bytes;
     const Gather none{nullptr, 1, 1, 0, 0, kPlain, 0};
     // timing names: the kernel symbols as a profiler lists them
-    static const char *const names[2][2][5] = {
-        {{"ntt_pass<false, false, 5>", "ntt_pass<false, false, 6>", "ntt_pass<false, false, 7>",
-          "ntt_pass<false, false, 8>", "ntt_pass<false, false, 9>"},
-         {"ntt_pass<false, true, 5>", "ntt_pass<false, true, 6>", "ntt_pass<false, true, 7>",
-          "ntt_pass<false, true, 8>", "ntt_pass<false, true, 9>"}},
-        {{"ntt_pass<true, false, 5>", "ntt_pass<true, false, 6>", "ntt_pass<true, false, 7>",
-          "ntt_pass<true, false, 8>", "ntt_pass<true, false, 9>"},
-         {"ntt_pass<true, true, 5>", "ntt_pass<true, true, 6>", "ntt_pass<true, true, 7>",
-          "ntt_pass<true, true, 8>", "ntt_pass<true, true, 9>"}}};
-    auto name = [&](bool i, bool rows, int log_m) { return names[i][rows][log_m - 5]; };
+    static const std::vector<std::string> names = [] {   // index ((inv * 2 + rows) * 2 + conv) * 5 + log_m - 5
+        std::vector<std::string> v;
+        const char *tf[2] = {"false", "true"};
+        for (int i = 0; i < 2; ++i)
+            for (int r = 0; r < 2; ++r)
+                for (int cv = 0; cv < 2; ++cv)
+                    for (int lm = 5; lm <= 9; ++lm)
+                        v.push_back(std::string("ntt_pass<") + tf[i] + ", " + tf[r] + ", " + std::to_string(lm) + ", " +
+                                    tf[cv] + ">");
+        return v;
+    }();
+    auto name = [&](bool i, bool rows, int log_m, bool cv = false) {
+        return names[(((i ? 1 : 0) * 2 + (rows ? 1 : 0)) * 2 + (cv ? 1 : 0)) * 5 + (log_m - 5)].c_str();
+    };
     Geom g1 = g;   // first pass: group the readers of a shared source limb on one XCD
     g1.xcd_group = (shared_src && grid.x % 8 == 0) ? 1 : 0;
     if (!inv) {
         {
-            TScope ts_(t, name(false, false, g.log_n1), bytes1, st);
-            launch_pass<false, false>(g.log_n1, grid, block, st, buf, in, m, t.mods, t.psi, t.psi_sh, t.psi_f, g1);
+            TScope ts_(t, name(false, false, g.log_n1, conv), bytes1, st);
+            if (conv)
+                launch_pass<false, false, true>(g.log_n1, grid, block, st, buf, in, m, t.mods, t.psi, t.psi_sh, t.psi_f, g1);
+            else
+                launch_pass<false, false>(g.log_n1, grid, block, st, buf, in, m, t.mods, t.psi, t.psi_sh, t.psi_f, g1);
         }
         {
             const double epi_bytes = epi ? 8.0 * t.n * n_limbs * (1.0 + (epi->add.ptr ? (epi->add_even ? 0.5 : 1.0) : 0.0)) : 0.0;

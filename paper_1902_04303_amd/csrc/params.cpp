@@ -73,15 +73,18 @@ i64 round_half_away(double x) {
     return (i64)std::llround(x);
 }
 
-Params make_params(int log_n, int levels, int log2_scale) {
+Params make_params(int log_n, int levels, int log2_scale, int alpha) {
+    if (alpha == 0) alpha = CKKS_DEFAULT_KS_ALPHA;
     if (log_n < 10 || log_n > 17) throw Error(CKKS_E_INVALID_ARG, "log_n must be in [10, 17]");
-    if (levels < 1 || levels + 1 + kSpecial > kMaxMods) throw Error(CKKS_E_INVALID_ARG, "levels out of range");
+    if (alpha < 2 || alpha > kMaxSpecial) throw Error(CKKS_E_INVALID_ARG, "ks_alpha must be 0 or in [2, 8]");
+    if (levels < 1 || levels + 1 + alpha > kMaxMods) throw Error(CKKS_E_INVALID_ARG, "levels out of range");
     if (log2_scale < 20 || log2_scale > 50) throw Error(CKKS_E_INVALID_ARG, "log2_scale must be in [20, 50]");
     Params p;
     p.log_n = log_n;
     p.n = 1 << log_n;
     p.levels = levels;
     p.log2_scale = log2_scale;
+    p.alpha = alpha;
     const u64 m = 2ULL * (u64)p.n;
     const u64 q0 = largest_prime_below(60, m);
     // pool of 4L primes nearest 2^b
@@ -119,8 +122,8 @@ Params make_params(int log_n, int levels, int log2_scale) {
         p.q[levels - d] = pool[best];
         p.scales.push_back((s * s) / (double)pool[best]);
     }
-    // special primes: the largest primes below 2^41 that are 1 mod 2N and not in the chain
-    for (u64 c = ((1ULL << 41) - 1) / m * m + 1; (int)p.P.size() < kSpecial; c -= m)
+    // special primes: the alpha largest primes below 2^41 that are 1 mod 2N and not in the chain
+    for (u64 c = ((1ULL << 41) - 1) / m * m + 1; (int)p.P.size() < alpha; c -= m)
         if (is_prime_u64(c) && std::find(p.q.begin(), p.q.end(), c) == p.q.end()) p.P.push_back(c);
     return p;
 }

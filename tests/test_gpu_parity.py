@@ -34,9 +34,11 @@ def torch_dev():
     return torch
 
 
-def make_pair(log_n, levels, b, galois_fn, seed=7):
-    ctx = P.Context(log_n, levels, b)
-    p = C.make_params(log_n, levels, b)
+def make_pair(log_n, levels, b, galois_fn, seed=7, alpha=None):
+    """Library context and oracle with the same parameters (alpha None: each side's default)."""
+    ctx = P.Context(log_n, levels, b) if alpha is None else P.Context(log_n, levels, b, alpha=alpha)
+    p = C.make_params(log_n, levels, b) if alpha is None else C.make_params(log_n, levels, b, alpha)
+    assert ctx.alpha == p.alpha
     o = C.Oracle(p)
     g = galois_fn(p.N)
     ctx.keygen(seed, g)
@@ -44,11 +46,14 @@ def make_pair(log_n, levels, b, galois_fn, seed=7):
     return ctx, o, p
 
 
-@pytest.fixture(scope="module")
-def small(torch_dev):
-    say("[gpu] small ring N=2^10 L=5")
+@pytest.fixture(scope="module", params=[None, 2, 4])
+def small(torch_dev, request):
+    """N = 2^10, L = 5 with the default digit-group size (3: {q_0 q_1} {q_2 q_3 q_4} {q_5}, a cut last
+    group), alpha = 2 ({q_0} {q_1 q_2} {q_3 q_4} {q_5}) and alpha = 4 ({q_0 q_1 q_2} {q_3 q_4 q_5}); the
+    tests' deeper ciphertexts cut the groups further."""
+    say("[gpu] small ring N=2^10 L=5 alpha=%s" % request.param)
     return make_pair(10, 5, 30, lambda N: [C.galois_rotate(N, 1), C.galois_rotate(N, -2), C.galois_rotate(N, 4),
-                                           C.galois_conj(N)])
+                                           C.galois_conj(N)], alpha=request.param)
 
 
 def rand_ct(p, depth, rng):

@@ -35,6 +35,15 @@ def test_prime_chain_matches_oracle(log_n, levels, b):
     assert scales == ref.scales
 
 
+@pytest.mark.parametrize("alpha", [2, 3, 5, 8])
+def test_special_primes_follow_the_group_size(alpha):
+    q, Pm, _ = P.chain(13, 12, 30, alpha)
+    ref = C.make_params(13, 12, 30, alpha)
+    assert P.ks_alpha(13, 12, 30, alpha) == alpha == len(Pm)
+    assert q == ref.q and Pm == ref.P
+    assert P.ks_alpha(13, 12, 30) == len(C.make_params(13, 12, 30).P)   # the two defaults agree
+
+
 @pytest.mark.parametrize("log_n,R", [(10, 2), (10, 8), (10, 64), (13, 256), (16, 256), (16, 2048), (16, 32768)])
 def test_galois_elements_match_oracle(log_n, R):
     from oracle import gwas_circuit as G
@@ -58,3 +67,6 @@ def test_bad_parameters_are_rejected():
     assert e.value.code == -1
     with pytest.raises(P.CkksError):
         P.chain(13, 4, 60)
+    for bad in (1, 9, -2):
+        with pytest.raises(P.CkksError):
+            P.chain(13, 4, 30, bad)

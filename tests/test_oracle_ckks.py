@@ -84,8 +84,9 @@ def test_eval_form_roundtrip_and_linearity():
 
 
 def test_prime_chain_rule():
-    for logN, L, b in [(4, 3, 20), (13, 26, 30), (16, 26, 40)]:
-        p = C.make_params(logN, L, b)
+    for logN, L, b, alpha in [(4, 3, 20, 2), (4, 3, 20, 4), (13, 26, 30, 3), (16, 26, 40, 2), (16, 26, 40, 4),
+                              (16, 26, 40, 8)]:
+        p = C.make_params(logN, L, b, alpha)
         N = 1 << logN
         mods = p.q + p.P
         assert len(set(mods)) == len(mods)
@@ -95,7 +96,19 @@ def test_prime_chain_rule():
             assert all(q % d for d in range(3, 2000, 2))
             assert all(pow(a, q - 1, q) == 1 for a in (2, 3, 5, 7, 11, 13, 101))
         assert p.q[0].bit_length() == 60 and all(x.bit_length() == 41 for x in p.P)
-        assert p.P[0] > p.P[1] and p.P_prod > max(p.q[0], max(a * b for a, b in zip(p.q[1::2], p.q[2::2])))
+        assert len(p.P) == alpha and p.P == sorted(p.P, reverse=True)
+        # no prime 1 mod 2N lies between 2^41 and the smallest special prime outside the chain and P
+        for c in range(p.P[-1] + 2 * N, 1 << 41, 2 * N):
+            if all(pow(a, c - 1, c) == 1 for a in (2, 3, 5, 7)):
+                assert c in p.P or c in p.q
+        # P exceeds the product of every digit group's moduli (keeps the key-switching noise small)
+        groups = C.digit_groups(L + 1, alpha)
+        assert sum(len(g) for g in groups) == L + 1 and groups[0][0] == 0
+        for g in groups:
+            QG = 1
+            for i in g:
+                QG *= p.q[i]
+            assert p.P_prod > QG
         assert all(x.bit_length() == b + (1 if x >= 1 << b else 0) for x in p.q[1:])
         # canonical scales follow Delta_{d+1} = Delta_d^2 / q_{L-d} and stay near 2^b
         for d in range(L):
@@ -106,9 +119,10 @@ def test_prime_chain_rule():
 
 # ------------------------------------------------------------------ keys / encryption against big integers
 
-@pytest.fixture(scope="module")
-def tiny_keys():
-    p, o = tiny(logN=4, L=3, b=20)
+@pytest.fixture(scope="module", params=[2, 3, 4])
+def tiny_keys(request):
+    p = C.make_params(4, 3, 20, request.param)   # alpha 2: {0} {1 2} {3}; 3: {0 1} {2 3}; 4: {0 1 2} {3}
+    o = C.Oracle(p)
     g = [C.galois_rotate(p.N, 1), C.galois_conj(p.N), C.galois_rotate(p.N, 2), C.galois_rotate(p.N, 3)]
     o.keygen(5, g)
     bc = B.BigCKKS(p.N, p.q, p.P)
@@ -140,7 +154,7 @@ def test_switching_keys_match_bigint(tiny_keys):
     for K, sp in targets.items():
         keys = bc.switching_key(s, sp, 5, C.ksk_sid_base(K))
         key = o.keys[K]
-        assert key.shape[1] == len(keys) == len(C.digit_groups(p.L + 1))
+        assert key.shape[1] == len(keys) == len(C.digit_groups(p.L + 1, p.alpha))
         for j in range(len(keys)):
             for t, q in enumerate(p.q + p.P):
                 assert key[0, j, t].tolist() == _res(keys[j][0], q), (K, j, t)
