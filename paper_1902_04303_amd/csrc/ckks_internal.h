@@ -200,13 +200,20 @@ struct LimbScale {
 };
 inline Gather gather_plain(const u64 *p) { return Gather{p, 1, 1, 0, 0, kPlain, 0}; }
 // Epilogue of the forward NTT that ends a key switch's ModDown: output limb lam becomes
-// (acc - ntt) * P^-1 (+ add) with acc and add gathered (add may be null; add_even: added only on rows
-// lam / rowlen that are even, the first polynomial of each ciphertext); pinv[chain], pinv_sh[chain]
-// (device) hold P^-1 modulo each chain modulus with Shoup companions.
+// (acc - ntt) * P^-1 (+ add) (+ aut) with acc and add gathered (add may be null; add_even: added only on
+// rows lam / rowlen that are even, the first polynomial of each ciphertext); pinv[chain], pinv_sh[chain]
+// (device) hold P^-1 modulo each chain modulus with Shoup companions.  aut (may be null) is a ciphertext
+// batch laid out like the output, [count][2][rowlen][N]: even rows add aut_self * aut[lam][k] +
+// sum_i aut[lam][k_i] with k_i the source word of the NTT-domain automorphism X -> X^g[i], odd rows add
+// aut_self * aut[lam][k] (rotate-and-sum: a + sum_i sigma_i(a c0); a single Galois map: sigma(a c0)).
+constexpr int kMaxKeys = 8;
 struct ModDownEpi {
     Gather acc, add;
     int add_even, rowlen;
     const u64 *pinv, *pinv_sh;
+    const u64 *aut;
+    int aut_self, n_g;
+    u64 g[kMaxKeys];
 };
 void k_ntt_forward_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st,
                      const ModDownEpi *epi = nullptr);
@@ -239,7 +246,6 @@ void k_copy_rows(u64 *out, size_t out_stride, const u64 *in, size_t in_stride, i
                  hipStream_t st);
 // Keys of one key-switch inner product: key i is paired with the NTT-domain automorphism X -> X^g[i] of
 // the digits (g[i] == 0: none).
-constexpr int kMaxKeys = 8;
 struct KsKeys {
     const u64 *key[kMaxKeys];
     u64 g[kMaxKeys];
@@ -252,10 +258,6 @@ struct KsKeys {
 // [2][ng][L + 1 + alpha][N] in NTT and Montgomery form (times 2^64); digits hold K limbs per ciphertext.
 void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const int *didx, const Gather &own,
                 const KsKeys &keys, int ng, int count, int l, int levels, int alpha, hipStream_t st);
-// [count][2][l] batches: with_self: out = (a c0 + sum_i sigma_{g[i]}(a c0), a c1); otherwise
-// out c0 rows = sum_i sigma_{g[i]}(a c0) and out c1 rows are not written
-void k_automorph_c0(const DevTables &t, u64 *out, const u64 *a, int count, int l, const KsKeys &gs, bool with_self,
-                    hipStream_t st);
 // samplers of the test-only SplitMix64 streams
 void k_sample_uniform(const DevTables &t, u64 *out, u64 seed, u64 sid, int n_limbs, ModMap m, int mi_of_p,
                       hipStream_t st);

@@ -331,7 +331,7 @@ static const u64 *key_of(const ckks_ctx &c, u64 id) {
 // plus the gathered `add` term (on every row, or on the first polynomial of each ciphertext when
 // add_even).  Output [count][2][l][N] in NTT form.
 static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, const KsKeys &keys, const Gather &add,
-                      bool add_even) {
+                      bool add_even, const u64 *aut = nullptr, bool aut_self = false) {
     const size_t N = (size_t)c.p.n;
     const ckks_ctx::KsLevel &kl = c.ks_levels.at(l);
     const int a = c.p.alpha, nt = l + a, P = c.p.p_index();
@@ -349,8 +349,9 @@ static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, const KsKe
     k_ntt_inverse_g(c.tab, ap.ptr, Gather{acc.ptr, a, nt, l, 1, kPlain, 0}, rows * a, ModMap{a, 0, P}, c.stream,
                     c.down_scale, a);
     DBuf out(c.pool.get(), (size_t)rows * l * N);
-    const ModDownEpi epi{Gather{acc.ptr, l, nt, 0, 1, kPlain, 0}, add, add_even ? 1 : 0, l, c.p_inv_dev,
-                         c.p_inv_sh_dev};
+    ModDownEpi epi{Gather{acc.ptr, l, nt, 0, 1, kPlain, 0}, add, add_even ? 1 : 0, l, c.p_inv_dev, c.p_inv_sh_dev,
+                   aut, aut_self ? 1 : 0, aut ? keys.m : 0, {}};
+    for (int i = 0; i < keys.m; ++i) epi.g[i] = keys.g[i];
     k_ntt_forward_g(c.tab, out.ptr, Gather{ap.ptr, 1, 1, 0, 0, kConv, 0, c.down_conv, l, a}, rows * l, map_q(l),
                     c.stream, &epi);
     c.n_limb_ntt += (uint64_t)count * (l + kl.K) + (uint64_t)rows * (a + l);
@@ -427,12 +428,10 @@ u64 galois_conj(const ckks_ctx &c) { return 2ULL * (u64)c.p.n - 1; }
 // through the automorphism after the basis extension
 Ct apply_galois(ckks_ctx &c, const ckks_ct &a, u64 g) {
     const int l = a.limbs;
-    const size_t N = (size_t)c.p.n;
     const KsKeys keys = ks_keys(c, {g}, true);
-    DBuf t(c.pool.get(), (size_t)a.count * 2 * l * N);   // c0 rows: sigma_g(a c0); c1 rows unused
-    k_automorph_c0(c.tab, t.ptr, a.data.ptr, a.count, l, keys, false, c.stream);
-    DBuf ks = keyswitch(c, Gather{a.data.ptr, l, 2 * l, l, 1, kPlain, 0}, a.count, l, keys, gather_plain(t.ptr), true);
-    c.n_launch += 1;
+    // (sigma_g(a c0), 0) added by the ModDown epilogue
+    DBuf ks = keyswitch(c, Gather{a.data.ptr, l, 2 * l, l, 1, kPlain, 0}, a.count, l, keys, Gather{}, false,
+                        a.data.ptr, false);
     Ct r(new ckks_ct());
     r->ctx = &c;
     r->count = a.count;
@@ -448,11 +447,9 @@ Ct rotate_sum(ckks_ctx &c, const ckks_ct &a, const std::vector<i64> &rots) {
     std::vector<u64> gs;
     for (i64 r : rots) gs.push_back(galois_rotate(c, r));
     const KsKeys keys = ks_keys(c, gs, true);
-    // a + (sum_i sigma_i(a c0), 0): added after the division by P
-    DBuf t(c.pool.get(), a.data.words);
-    k_automorph_c0(c.tab, t.ptr, a.data.ptr, a.count, l, keys, true, c.stream);
-    DBuf ks = keyswitch(c, Gather{a.data.ptr, l, 2 * l, l, 1, kPlain, 0}, a.count, l, keys, gather_plain(t.ptr), false);
-    c.n_launch += 2;
+    // a + (sum_i sigma_i(a c0), 0), added by the ModDown epilogue
+    DBuf ks = keyswitch(c, Gather{a.data.ptr, l, 2 * l, l, 1, kPlain, 0}, a.count, l, keys, Gather{}, false,
+                        a.data.ptr, true);
     Ct r(new ckks_ct());
     r->ctx = &c;
     r->count = a.count;

@@ -208,16 +208,6 @@ void k_tensor(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int coun
     check_launch();
 }
 
-// NTT-domain automorphism X -> X^g: word k of the result is word k2 of the input, where the evaluation
-// point of k2 is that of k raised to g, psi^(2 brev(k2) + 1) = (psi^(2 brev(k) + 1))^g.  The 64 words of
-// an aligned group of 64 map into one aligned group of 64 (only the top bits of brev(k) vary).
-__device__ __forceinline__ size_t automorph_src(size_t k, int log_n, u64 g) {
-    const u64 mask2n = (2ULL << log_n) - 1;
-    const u64 e = 2 * (u64)(__brev((unsigned)k) >> (32 - log_n)) + 1;
-    const u64 e2 = (e * g) & mask2n;
-    return __brev((unsigned)((e2 - 1) >> 1)) >> (32 - log_n);
-}
-
 __global__ void ew_automorph(u64 *out, const u64 *a, size_t total, int log_n, u64 g) {
     const size_t n = (size_t)1 << log_n;
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
@@ -451,37 +441,6 @@ void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const in
     default: GCK_KS(1, 0); break;
     }
 #undef GCK_KS
-    check_launch();
-}
-
-// with_self: out = (a c0 + sum_i sigma_i(a c0), a c1); else out c0 rows = sum_i sigma_i(a c0) (c1 rows untouched)
-__global__ void ew_automorph_c0(u64 *out, const u64 *a, KsKeys gs, size_t total, int log_n, int l, const ModInfo *mods,
-                                int with_self) {
-    const size_t n = (size_t)1 << log_n;
-    const int rl = with_self ? 2 * l : l;   // limbs per ciphertext covered by the launch
-    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
-        const size_t lam = idx >> log_n;
-        const size_t c = lam / rl;
-        const int r = (int)(lam % rl);      // r < l: c0 limb r; else c1 limb r - l
-        const size_t k = idx & (n - 1);
-        const size_t row = (c * 2 * l + r) * n;
-        if (r >= l) {
-            out[row + k] = a[row + k];
-            continue;
-        }
-        const u64 q = mods[r].q;
-        u64 s = with_self ? a[row + k] : 0;
-        for (int i = 0; i < gs.m; ++i) s = add_mod(s, a[row + automorph_src(k, log_n, gs.g[i])], q);
-        out[row + k] = s;
-    }
-}
-void k_automorph_c0(const DevTables &t, u64 *out, const u64 *a, int count, int l, const KsKeys &gs, bool with_self,
-                    hipStream_t st) {
-    TScope ts_(t, "ew_automorph_c0", 8.0 * (double)((size_t)count * l) * t.n * (with_self ? gs.m + 4 : gs.m + 1), st);
-    const size_t total = ((size_t)count * (with_self ? 2 : 1) * l) << t.log_n;
-    if (!total) return;
-    hipLaunchKernelGGL(ew_automorph_c0, ew_grid(total), dim3(kEwThreads), 0, st, out, a, gs, total, t.log_n, l, t.mods,
-                       with_self ? 1 : 0);
     check_launch();
 }
 

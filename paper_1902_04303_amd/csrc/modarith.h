@@ -49,6 +49,16 @@ __device__ __forceinline__ int chain_of(int lam, ModMap m) {
     return t < m.nq ? t : m.p_idx + (t - m.nq);
 }
 
+// NTT-domain automorphism X -> X^g: word k of the result is word k2 of the input, where the evaluation
+// point of k2 is that of k raised to g, psi^(2 brev(k2) + 1) = (psi^(2 brev(k) + 1))^g.  The 64 words of
+// an aligned group of 64 map into one aligned group of 64 (only the top bits of brev(k) vary).
+__device__ __forceinline__ size_t automorph_src(size_t k, int log_n, u64 g) {
+    const u64 mask2n = (2ULL << log_n) - 1;
+    const u64 e = 2 * (u64)(__brev((unsigned)k) >> (32 - log_n)) + 1;
+    const u64 e2 = (e * g) & mask2n;
+    return __brev((unsigned)((e2 - 1) >> 1)) >> (32 - log_n);
+}
+
 // ---------------------------------------------------------------- FP64 arithmetic (q < 2^41)
 // Residues of moduli below 2^41 as integer-valued doubles: a product a w is split exactly into its
 // rounded value and the FMA error, the quotient by q is rounded from a multiply by RN(1/q), and the

@@ -32,15 +32,15 @@ namespace gck {
 
 namespace {
 
-constexpr int kTileWords = 4096;
-constexpr int kThreads = 256;
+constexpr int kLogTileRows = 12;   // rows pass: 16 rows of 256 words per block
+constexpr int kLogTileCols = 12;   // cols pass: 16 columns of 256 words per block (32 columns measured slower)
 constexpr int kPer = 16;   // words per thread
 
 struct Geom {
     int log_n, n2, log_n1, log_n2;
     int log_g_cols;   // sub-transforms (columns) per cols tile
     int log_g_rows;   // sub-transforms (rows) per rows tile
-    int tiles;        // tiles per limb (same for both passes)
+    int log_tile_cols, log_tile_rows;   // tile sizes of the two passes (log2 words)
     int xcd_group;    // 1: place consecutive logical blocks on one XCD (see block_id)
     const ConvEntry *conv;     // basis-conversion launches: chain of limb lam is conv[lam % conv_period]
     int conv_period;
@@ -70,10 +70,10 @@ Geom make_geom(int log_n) {
     g.log_n1 = (log_n + 1) / 2;   // 256 x 256 at N = 2^16 (128 x 512 measured slower overall)
     g.log_n2 = log_n - g.log_n1;
     g.n2 = 1 << g.log_n2;
-    int log_tile = log_n < 12 ? log_n : 12;
-    g.log_g_cols = log_tile - g.log_n1;
-    g.log_g_rows = log_tile - g.log_n2;
-    g.tiles = 1 << (log_n - log_tile);
+    g.log_tile_cols = log_n < kLogTileCols ? log_n : kLogTileCols;
+    g.log_tile_rows = log_n < kLogTileRows ? log_n : kLogTileRows;
+    g.log_g_cols = g.log_tile_cols - g.log_n1;
+    g.log_g_rows = g.log_tile_rows - g.log_n2;
     g.xcd_group = 0;
     g.conv = nullptr;
     g.conv_period = 1;
@@ -207,20 +207,21 @@ __device__ __forceinline__ void exchange(T (&v)[kPer], T *sh, int gi, int q, int
 // One pass.  ROWS selects the rows pass (sub-transforms of N2 contiguous words) or the cols pass
 // (N1-point sub-transforms down columns).  `in` (first pass only) gathers the input from another buffer;
 // CONV (forward cols pass only) is the basis-conversion gather, a separate instantiation so that the
-// other passes do not carry its registers.
-template <bool INV, bool ROWS, int LOGM, bool CONV>
-__global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, Gather in, ModMap mm,
+// other passes do not carry its registers.  At least 3 waves per SIMD (up to 168 VGPRs): the passes
+// then run without spills, faster than at 4 waves with spills.
+template <bool INV, bool ROWS, int LOGM, bool CONV, int LT = ROWS ? kLogTileRows : kLogTileCols>
+__global__ void __launch_bounds__((1 << LT) / kPer, 3) ntt_pass(u64 *__restrict__ buf, Gather in, ModMap mm,
                                                      const ModInfo *__restrict__ mods, const u64 *__restrict__ tw,
                                                      const u64 *__restrict__ tw_sh,
                                                      const double *__restrict__ tw_f, Geom g) {
-    __shared__ u64 sh[kTileWords + (kTileWords >> 4)];
+    __shared__ u64 sh[(1 << LT) + ((1 << LT) >> 4)];
     constexpr int NPH = (LOGM + 3) / 4;
     constexpr int FIRST = INV ? NPH - 1 : 0;
     constexpr int LAST = INV ? 0 : NPH - 1;
-    const int log_tile = g.log_n < 12 ? g.log_n : 12;
+    const int log_tile = ROWS ? g.log_tile_rows : g.log_tile_cols;
     const int bid = block_id(g);
     const int limb = bid >> (g.log_n - log_tile);
-    const int tile = bid & (g.tiles - 1);
+    const int tile = bid & ((1 << (g.log_n - log_tile)) - 1);
     // a basis-conversion NTT takes every output limb's modulus from its conversion entry, in both passes
     const ConvEntry *ce = g.conv ? g.conv + limb % g.conv_period : nullptr;
     const int chain = ce ? ce->chain : chain_of(limb, mm);
@@ -422,11 +423,15 @@ __global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, G
             sh[lds_addr<ROWS>(gi, slot_index<LOGM, Ph<LOGM, LAST>::S0, Ph<LOGM, LAST>::R>(e, q), LOGM, log_g)] = v[e];
         __syncthreads();
         if (!INV && g.has_epi) {
-            // ModDown epilogue: (acc - t) P^-1 (+ add), t the transform just computed
+            // ModDown epilogue: (acc - t) P^-1 (+ add) (+ automorphism term), t the transform just computed
             const ModDownEpi &E = g.epi;
             const u64 *xa = E.acc.ptr + gathered(E.acc, limb) * n;
-            const bool with_add = E.add.ptr && (!E.add_even || ((limb / E.rowlen) & 1) == 0);
+            const bool even = ((limb / E.rowlen) & 1) == 0;
+            const bool with_add = E.add.ptr && (!E.add_even || even);
             const u64 *xd = with_add ? E.add.ptr + gathered(E.add, limb) * n : nullptr;
+            const u64 *xs = E.aut ? E.aut + (size_t)limb * n : nullptr;
+            const int n_aut = (xs && even) ? E.n_g : 0;
+            const bool aut_self = xs && E.aut_self;
             const u64 pv = E.pinv[chain], ps = E.pinv_sh[chain];
 #pragma unroll
             for (int e = 0; e < kPer; ++e) {
@@ -434,6 +439,8 @@ __global__ void __launch_bounds__(kThreads, 4) ntt_pass(u64 *__restrict__ buf, G
                 const u64 t = sh[lds_addr<ROWS>(gi, idx, LOGM, log_g)];
                 u64 r = mul_shoup(sub_mod(xa[base + idx], t, qm), pv, ps, qm);
                 if (with_add) r = add_mod(r, xd[base + idx], qm);
+                if (aut_self) r = add_mod(r, xs[base + idx], qm);
+                for (int i = 0; i < n_aut; ++i) r = add_mod(r, xs[automorph_src(base + idx, g.log_n, E.g[i])], qm);
                 a[base + idx] = r;
             }
         } else {
@@ -494,9 +501,10 @@ static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, 
         g_rows.has_epi = 1;
         g_rows.epi = *epi;
     }
-    const int log_tile = t.log_n < 12 ? t.log_n : 12;
-    dim3 grid((unsigned)((size_t)n_limbs * g.tiles));
-    dim3 block((unsigned)((1 << log_tile) / kPer));
+    const dim3 grid_c((unsigned)((size_t)n_limbs << (t.log_n - g.log_tile_cols)));
+    const dim3 block_c((unsigned)((1 << g.log_tile_cols) / kPer));
+    const dim3 grid_r((unsigned)((size_t)n_limbs << (t.log_n - g.log_tile_rows)));
+    const dim3 block_r((unsigned)((1 << g.log_tile_rows) / kPer));
     // algorithmic bytes of a pass: each word written once and each distinct input word read once (a
     // gather whose output limbs share a source limb, inner == 0, reads n_limbs / div source limbs)
     const double bytes = 16.0 * (double)n_limbs * t.n;
@@ -521,28 +529,33 @@ static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, 
         return names[(((i ? 1 : 0) * 2 + (rows ? 1 : 0)) * 2 + (cv ? 1 : 0)) * 5 + (log_m - 5)].c_str();
     };
     Geom g1 = g;   // first pass: group the readers of a shared source limb on one XCD
-    g1.xcd_group = (shared_src && grid.x % 8 == 0) ? 1 : 0;
+    g1.xcd_group = (shared_src && (inv ? grid_r.x : grid_c.x) % 8 == 0) ? 1 : 0;
     if (!inv) {
         {
             TScope ts_(t, name(false, false, g.log_n1, conv), bytes1, st);
             if (conv)
-                launch_pass<false, false, true>(g.log_n1, grid, block, st, buf, in, m, t.mods, t.psi, t.psi_sh, t.psi_f, g1);
+                launch_pass<false, false, true>(g.log_n1, grid_c, block_c, st, buf, in, m, t.mods, t.psi, t.psi_sh, t.psi_f, g1);
             else
-                launch_pass<false, false>(g.log_n1, grid, block, st, buf, in, m, t.mods, t.psi, t.psi_sh, t.psi_f, g1);
+                launch_pass<false, false>(g.log_n1, grid_c, block_c, st, buf, in, m, t.mods, t.psi, t.psi_sh, t.psi_f, g1);
         }
         {
-            const double epi_bytes = epi ? 8.0 * t.n * n_limbs * (1.0 + (epi->add.ptr ? (epi->add_even ? 0.5 : 1.0) : 0.0)) : 0.0;
+            // epilogue reads: acc, the added term, the automorphism source (each distinct word once)
+            const double epi_bytes =
+                epi ? 8.0 * t.n * n_limbs *
+                          (1.0 + (epi->add.ptr ? (epi->add_even ? 0.5 : 1.0) : 0.0) +
+                           (epi->aut ? (epi->aut_self ? 1.0 : 0.5) : 0.0))
+                    : 0.0;
             TScope ts_(t, name(false, true, g.log_n2), bytes + epi_bytes, st);
-            launch_pass<false, true>(g.log_n2, grid, block, st, buf, none, m, t.mods, t.psi, t.psi_sh, t.psi_f, g_rows);
+            launch_pass<false, true>(g.log_n2, grid_r, block_r, st, buf, none, m, t.mods, t.psi, t.psi_sh, t.psi_f, g_rows);
         }
     } else {
         {
             TScope ts_(t, name(true, true, g.log_n2), bytes1, st);
-            launch_pass<true, true>(g.log_n2, grid, block, st, buf, in, m, t.mods, t.ipsi, t.ipsi_sh, t.ipsi_f, g1);
+            launch_pass<true, true>(g.log_n2, grid_r, block_r, st, buf, in, m, t.mods, t.ipsi, t.ipsi_sh, t.ipsi_f, g1);
         }
         {
             TScope ts_(t, name(true, false, g.log_n1), bytes, st);
-            launch_pass<true, false>(g.log_n1, grid, block, st, buf, none, m, t.mods, t.ipsi, t.ipsi_sh, t.ipsi_f, g);
+            launch_pass<true, false>(g.log_n1, grid_c, block_c, st, buf, none, m, t.mods, t.ipsi, t.ipsi_sh, t.ipsi_f, g);
         }
     }
     check_launch();
