@@ -162,7 +162,7 @@ void build_ks_tables(ckks_ctx &c) {
         o_sc[l] = room(scales[l].size() * sizeof(LimbScale));
     }
     const size_t o_down = room(down.size() * sizeof(ConvEntry)), o_dsc = room(dscale.size() * sizeof(LimbScale));
-    const size_t o_pinv = room(kMaxMods * 8), o_pinv_sh = room(kMaxMods * 8);
+    const size_t o_pinv = room(kMaxMods * 8), o_pinv_sh = room(kMaxMods * 8), o_pinv_d = room(kMaxMods * 8);
     GCK_HIP(hipMalloc(&c.ks_mem, bytes));
     char *base = static_cast<char *>(c.ks_mem);
     c.ks_levels.assign(nq + 1, ckks_ctx::KsLevel{});
@@ -184,6 +184,10 @@ void build_ks_tables(ckks_ctx &c) {
     c.p_inv_sh_dev = reinterpret_cast<u64 *>(base + o_pinv_sh);
     GCK_HIP(hipMemcpy(c.p_inv_dev, c.p_inv.v, kMaxMods * 8, hipMemcpyHostToDevice));
     GCK_HIP(hipMemcpy(c.p_inv_sh_dev, c.p_inv.sh, kMaxMods * 8, hipMemcpyHostToDevice));
+    std::vector<double> pinv_d(kMaxMods, 0.0);
+    for (int i = 0; i < p.n_mods(); ++i) pinv_d[i] = (double)c.p_inv.v[i];
+    c.p_inv_d_dev = reinterpret_cast<double *>(base + o_pinv_d);
+    GCK_HIP(hipMemcpy(c.p_inv_d_dev, pinv_d.data(), kMaxMods * 8, hipMemcpyHostToDevice));
     c.ng = ks_groups(nq, p.alpha);
 }
 

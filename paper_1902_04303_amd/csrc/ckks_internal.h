@@ -202,8 +202,9 @@ inline Gather gather_plain(const u64 *p) { return Gather{p, 1, 1, 0, 0, kPlain, 
 // Epilogue of the forward NTT that ends a key switch's ModDown: output limb lam becomes
 // (acc - ntt) * P^-1 (+ add) (+ aut) with acc and add gathered (add may be null; add_even: added only on
 // rows lam / rowlen that are even, the first polynomial of each ciphertext); pinv[chain], pinv_sh[chain]
-// (device) hold P^-1 modulo each chain modulus with Shoup companions.  aut (may be null) is a ciphertext
-// batch laid out like the output, [count][2][rowlen][N]: even rows add aut_self * aut[lam][k] +
+// and pinv_d[chain] (device) hold P^-1 modulo each chain modulus, with Shoup companions and as doubles.
+// aut (may be null) is a ciphertext batch laid out like the output, [count][2][rowlen][N]: even rows add
+// aut_self * aut[lam][k] +
 // sum_i aut[lam][k_i] with k_i the source word of the NTT-domain automorphism X -> X^g[i], odd rows add
 // aut_self * aut[lam][k] (rotate-and-sum: a + sum_i sigma_i(a c0); a single Galois map: sigma(a c0)).
 constexpr int kMaxKeys = 8;
@@ -211,6 +212,7 @@ struct ModDownEpi {
     Gather acc, add;
     int add_even, rowlen;
     const u64 *pinv, *pinv_sh;
+    const double *pinv_d;
     const u64 *aut;
     int aut_self, n_g;
     u64 g[kMaxKeys];

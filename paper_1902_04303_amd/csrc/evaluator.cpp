@@ -350,7 +350,7 @@ static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, const KsKe
                     c.down_scale, a);
     DBuf out(c.pool.get(), (size_t)rows * l * N);
     ModDownEpi epi{Gather{acc.ptr, l, nt, 0, 1, kPlain, 0}, add, add_even ? 1 : 0, l, c.p_inv_dev, c.p_inv_sh_dev,
-                   aut, aut_self ? 1 : 0, aut ? keys.m : 0, {}};
+                   c.p_inv_d_dev, aut, aut_self ? 1 : 0, aut ? keys.m : 0, {}};
     for (int i = 0; i < keys.m; ++i) epi.g[i] = keys.g[i];
     k_ntt_forward_g(c.tab, out.ptr, Gather{ap.ptr, 1, 1, 0, 0, kConv, 0, c.down_conv, l, a}, rows * l, map_q(l),
                     c.stream, &epi);

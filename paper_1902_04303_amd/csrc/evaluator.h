@@ -28,13 +28,14 @@ struct ckks_ctx {
     gck::LimbScale *down_scale = nullptr;    // ModDown inverse-NTT scales of the special primes
     gck::ChainConst p_inv{};                 // P^-1 mod every chain modulus
     gck::u64 *p_inv_dev = nullptr, *p_inv_sh_dev = nullptr;   // the same on the device
+    double *p_inv_d_dev = nullptr;                             // and as doubles (FP64 moduli)
     int ng = 0;                              // digit groups of a key (at L + 1 limbs)
     // keys
     bool have_keys = false;
     std::vector<int64_t> sk;       // secret, signed coefficients
-    gck::DBuf sk_ntt;              // [L+3][N]: s mod q_0..q_L, p_1, p_2 in NTT form
+    gck::DBuf sk_ntt;              // [L+1+alpha][N]: s mod q_0..q_L, p_1..p_alpha in NTT form
     gck::DBuf pk;                  // [2][L+1][N] NTT form
-    std::map<uint64_t, gck::DBuf> ksk;   // key id (0 = relinearisation, else Galois element) -> [2][ng][L+3][N]
+    std::map<uint64_t, gck::DBuf> ksk;   // key id (0 = relinearisation, else Galois element) -> [2][ng][L+1+alpha][N]
     // counters and optional per-kernel timing
     uint64_t n_keyswitch = 0, n_limb_ntt = 0, n_launch = 0;
     gck::KTimer timer;

@@ -32,6 +32,7 @@ namespace gck {
 
 namespace {
 
+enum { kGmPlain = 0, kGmConv = 1, kGmEpi = 2 };   // ntt_pass instantiations (see ntt_pass)
 constexpr int kLogTileRows = 12;   // rows pass: 16 rows of 256 words per block
 constexpr int kLogTileCols = 12;   // cols pass: 16 columns of 256 words per block (32 columns measured slower)
 constexpr int kPer = 16;   // words per thread
@@ -46,7 +47,6 @@ struct Geom {
     int conv_period;
     const LimbScale *scale;    // inverse: output limb lam scaled by scale[lam % scale_period] (else N^-1)
     int scale_period;
-    int has_epi;               // forward rows pass: apply the ModDown epilogue while storing
     ModDownEpi epi;
 };
 
@@ -79,7 +79,6 @@ Geom make_geom(int log_n) {
     g.conv_period = 1;
     g.scale = nullptr;
     g.scale_period = 1;
-    g.has_epi = 0;
     g.epi = ModDownEpi{};
     return g;
 }
@@ -204,16 +203,65 @@ __device__ __forceinline__ void exchange(T (&v)[kPer], T *sh, int gi, int q, int
         v[e] = sh[lds_addr<ROWS>(gi, slot_index<LOGM, Ph<LOGM, TO>::S0, Ph<LOGM, TO>::R>(e, q), LOGM, log_g)];
 }
 
+// The register phases of one pass over a tile, with the LDS exchanges between them: FP64 words (the
+// inverse reduces the doubled sums before each later phase) and 64-bit integer words (lazy reduction).
+template <bool INV, bool ROWS, int LOGM>
+__device__ __forceinline__ void fp_phases(double (&f)[kPer], double *shf, int gi, int q, int log_g, int base_off,
+                                          const double *__restrict__ Wf, FMod fm) {
+    constexpr int NPH = (LOGM + 3) / 4;
+    constexpr int FIRST = INV ? NPH - 1 : 0;
+    fphase<INV, LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(f, q, base_off, Wf, fm);
+    if constexpr (NPH > 1) {
+        constexpr int P1 = INV ? NPH - 2 : 1;
+        exchange<ROWS, LOGM, FIRST, P1>(f, shf, gi, q, log_g);
+        if (INV) {
+#pragma unroll
+            for (int e = 0; e < kPer; ++e) f[e] = fred(f[e], fm);
+        }
+        fphase<INV, LOGM, Ph<LOGM, P1>::S0, Ph<LOGM, P1>::R>(f, q, base_off, Wf, fm);
+        if constexpr (NPH > 2) {
+            constexpr int P2 = INV ? NPH - 3 : 2;
+            exchange<ROWS, LOGM, P1, P2>(f, shf, gi, q, log_g);
+            if (INV) {
+#pragma unroll
+                for (int e = 0; e < kPer; ++e) f[e] = fred(f[e], fm);
+            }
+            fphase<INV, LOGM, Ph<LOGM, P2>::S0, Ph<LOGM, P2>::R>(f, q, base_off, Wf, fm);
+        }
+    }
+}
+
+template <bool INV, bool ROWS, int LOGM>
+__device__ __forceinline__ void int_phases(u64 (&v)[kPer], u64 *sh, int gi, int q, int log_g, int base_off,
+                                           const u64 *__restrict__ W, const u64 *__restrict__ Ws, u64 qm) {
+    constexpr int NPH = (LOGM + 3) / 4;
+    constexpr int FIRST = INV ? NPH - 1 : 0;
+    phase<INV, LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(v, q, base_off, W, Ws, qm);
+    if constexpr (NPH > 1) {
+        constexpr int P1 = INV ? NPH - 2 : 1;
+        exchange<ROWS, LOGM, FIRST, P1>(v, sh, gi, q, log_g);
+        phase<INV, LOGM, Ph<LOGM, P1>::S0, Ph<LOGM, P1>::R>(v, q, base_off, W, Ws, qm);
+        if constexpr (NPH > 2) {
+            constexpr int P2 = INV ? NPH - 3 : 2;
+            exchange<ROWS, LOGM, P1, P2>(v, sh, gi, q, log_g);
+            phase<INV, LOGM, Ph<LOGM, P2>::S0, Ph<LOGM, P2>::R>(v, q, base_off, W, Ws, qm);
+        }
+    }
+}
+
 // One pass.  ROWS selects the rows pass (sub-transforms of N2 contiguous words) or the cols pass
 // (N1-point sub-transforms down columns).  `in` (first pass only) gathers the input from another buffer;
-// CONV (forward cols pass only) is the basis-conversion gather, a separate instantiation so that the
-// other passes do not carry its registers.  At least 3 waves per SIMD (up to 168 VGPRs): the passes
+// GM selects a separate instantiation for the work only some launches do, so that the other passes do
+// not carry its registers: kGmConv (forward cols pass) is the basis-conversion gather, kGmEpi (forward
+// rows pass) the ModDown epilogue.  At least 3 waves per SIMD (up to 168 VGPRs): the passes
 // then run without spills, faster than at 4 waves with spills.
-template <bool INV, bool ROWS, int LOGM, bool CONV, int LT = ROWS ? kLogTileRows : kLogTileCols>
-__global__ void __launch_bounds__((1 << LT) / kPer, 3) ntt_pass(u64 *__restrict__ buf, Gather in, ModMap mm,
+template <bool INV, bool ROWS, int LOGM, int GM>
+__global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / kPer, 3) ntt_pass(u64 *__restrict__ buf, Gather in, ModMap mm,
                                                      const ModInfo *__restrict__ mods, const u64 *__restrict__ tw,
                                                      const u64 *__restrict__ tw_sh,
                                                      const double *__restrict__ tw_f, Geom g) {
+    constexpr int LT = ROWS ? kLogTileRows : kLogTileCols;
+    constexpr bool CONV = GM == kGmConv;
     __shared__ u64 sh[(1 << LT) + ((1 << LT) >> 4)];
     constexpr int NPH = (LOGM + 3) / 4;
     constexpr int FIRST = INV ? NPH - 1 : 0;
@@ -276,8 +324,9 @@ __global__ void __launch_bounds__((1 << LT) / kPer, 3) ntt_pass(u64 *__restrict_
     u64 v[kPer];
     if constexpr (CONV) {
         // basis conversion while loading: sum_m y_m c_m mod q, one source limb at a time (its 16 loads
-        // issued together); FP64 moduli keep the sum as a double (|sum| < 1.1 q per source, below 2^45 for
-        // up to kMaxSpecial sources) and store its bits
+        // issued in two groups of 8; prefetching the next source into registers measured slower); FP64
+        // moduli keep the sum as a double (|sum| < 1.1 q per source, below 2^45 for up to kMaxSpecial
+        // sources) and store its bits
         const int ns = ce->nsrc, big = ce->big;
         const FMod fm{M.qd, M.qinv};
         if (M.fp) {
@@ -351,26 +400,7 @@ __global__ void __launch_bounds__((1 << LT) / kPer, 3) ntt_pass(u64 *__restrict_
                 f[e] = fred(y, fm);
             }
         }
-        double *shf = reinterpret_cast<double *>(sh);
-        fphase<INV, LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(f, q, base_off, Wf, fm);
-        if constexpr (NPH > 1) {
-            constexpr int P1 = INV ? NPH - 2 : 1;
-            exchange<ROWS, LOGM, FIRST, P1>(f, shf, gi, q, log_g);
-            if (INV) {   // inverse sums double per stage: start each later phase from reduced words
-#pragma unroll
-                for (int e = 0; e < kPer; ++e) f[e] = fred(f[e], fm);
-            }
-            fphase<INV, LOGM, Ph<LOGM, P1>::S0, Ph<LOGM, P1>::R>(f, q, base_off, Wf, fm);
-            if constexpr (NPH > 2) {
-                constexpr int P2 = INV ? NPH - 3 : 2;
-                exchange<ROWS, LOGM, P1, P2>(f, shf, gi, q, log_g);
-                if (INV) {
-#pragma unroll
-                    for (int e = 0; e < kPer; ++e) f[e] = fred(f[e], fm);
-                }
-                fphase<INV, LOGM, Ph<LOGM, P2>::S0, Ph<LOGM, P2>::R>(f, q, base_off, Wf, fm);
-            }
-        }
+        fp_phases<INV, ROWS, LOGM>(f, reinterpret_cast<double *>(sh), gi, q, log_g, base_off, Wf, fm);
         const double sc = (INV && !ROWS && g.scale) ? g.scale[limb % g.scale_period].wd : M.ninv_d;
 #pragma unroll
         for (int e = 0; e < kPer; ++e) {
@@ -389,17 +419,7 @@ __global__ void __launch_bounds__((1 << LT) / kPer, 3) ntt_pass(u64 *__restrict_
                 v[e] = x;
             }
         }
-        phase<INV, LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(v, q, base_off, W, Ws, qm);
-        if constexpr (NPH > 1) {
-            constexpr int P1 = INV ? NPH - 2 : 1;
-            exchange<ROWS, LOGM, FIRST, P1>(v, sh, gi, q, log_g);
-            phase<INV, LOGM, Ph<LOGM, P1>::S0, Ph<LOGM, P1>::R>(v, q, base_off, W, Ws, qm);
-            if constexpr (NPH > 2) {
-                constexpr int P2 = INV ? NPH - 3 : 2;
-                exchange<ROWS, LOGM, P1, P2>(v, sh, gi, q, log_g);
-                phase<INV, LOGM, Ph<LOGM, P2>::S0, Ph<LOGM, P2>::R>(v, q, base_off, W, Ws, qm);
-            }
-        }
+        int_phases<INV, ROWS, LOGM>(v, sh, gi, q, log_g, base_off, W, Ws, qm);
         // final scaling (inverse cols pass: N^-1) and reduction ([0, q) at the end of a transform)
         const u64 q2 = 2 * qm;
         u64 sw = M.ninv, sw_sh = M.ninv_sh;
@@ -422,7 +442,7 @@ __global__ void __launch_bounds__((1 << LT) / kPer, 3) ntt_pass(u64 *__restrict_
         for (int e = 0; e < kPer; ++e)
             sh[lds_addr<ROWS>(gi, slot_index<LOGM, Ph<LOGM, LAST>::S0, Ph<LOGM, LAST>::R>(e, q), LOGM, log_g)] = v[e];
         __syncthreads();
-        if (!INV && g.has_epi) {
+        if constexpr (!INV && GM == kGmEpi) {
             // ModDown epilogue: (acc - t) P^-1 (+ add) (+ automorphism term), t the transform just computed
             const ModDownEpi &E = g.epi;
             const u64 *xa = E.acc.ptr + gathered(E.acc, limb) * n;
@@ -432,16 +452,33 @@ __global__ void __launch_bounds__((1 << LT) / kPer, 3) ntt_pass(u64 *__restrict_
             const u64 *xs = E.aut ? E.aut + (size_t)limb * n : nullptr;
             const int n_aut = (xs && even) ? E.n_g : 0;
             const bool aut_self = xs && E.aut_self;
-            const u64 pv = E.pinv[chain], ps = E.pinv_sh[chain];
+            if (M.fp) {
+                // FP64: |acc - t| < q, the product's remainder below 1.1 q, each added residue below q: the
+                // sum stays below 12 q for up to 8 automorphism terms, well inside the exact range
+                const FMod fm{M.qd, M.qinv};
+                const double pd = E.pinv_d[chain];
 #pragma unroll
-            for (int e = 0; e < kPer; ++e) {
-                const int idx = slot_index<LOGM, 0, Ph<LOGM, 0>::R>(e, q);
-                const u64 t = sh[lds_addr<ROWS>(gi, idx, LOGM, log_g)];
-                u64 r = mul_shoup(sub_mod(xa[base + idx], t, qm), pv, ps, qm);
-                if (with_add) r = add_mod(r, xd[base + idx], qm);
-                if (aut_self) r = add_mod(r, xs[base + idx], qm);
-                for (int i = 0; i < n_aut; ++i) r = add_mod(r, xs[automorph_src(base + idx, g.log_n, E.g[i])], qm);
-                a[base + idx] = r;
+                for (int e = 0; e < kPer; ++e) {
+                    const int idx = slot_index<LOGM, 0, Ph<LOGM, 0>::R>(e, q);
+                    const u64 t = sh[lds_addr<ROWS>(gi, idx, LOGM, log_g)];
+                    double r = fmul_mod((double)xa[base + idx] - (double)t, pd, fm);
+                    if (with_add) r += (double)xd[base + idx];
+                    if (aut_self) r += (double)xs[base + idx];
+                    for (int i = 0; i < n_aut; ++i) r += (double)xs[automorph_src(base + idx, g.log_n, E.g[i])];
+                    a[base + idx] = fcanon(r, fm);
+                }
+            } else {
+                const u64 pv = E.pinv[chain], ps = E.pinv_sh[chain];
+#pragma unroll
+                for (int e = 0; e < kPer; ++e) {
+                    const int idx = slot_index<LOGM, 0, Ph<LOGM, 0>::R>(e, q);
+                    const u64 t = sh[lds_addr<ROWS>(gi, idx, LOGM, log_g)];
+                    u64 r = mul_shoup(sub_mod(xa[base + idx], t, qm), pv, ps, qm);
+                    if (with_add) r = add_mod(r, xd[base + idx], qm);
+                    if (aut_self) r = add_mod(r, xs[base + idx], qm);
+                    for (int i = 0; i < n_aut; ++i) r = add_mod(r, xs[automorph_src(base + idx, g.log_n, E.g[i])], qm);
+                    a[base + idx] = r;
+                }
             }
         } else {
 #pragma unroll
@@ -459,13 +496,13 @@ __global__ void __launch_bounds__((1 << LT) / kPer, 3) ntt_pass(u64 *__restrict_
     }
 }
 
-template <bool INV, bool ROWS, bool CONV = false>
+template <bool INV, bool ROWS, int GM = kGmPlain>
 void launch_pass(int log_m, dim3 grid, dim3 block, hipStream_t st, u64 *buf, const Gather &in, ModMap m,
                  const ModInfo *mods, const u64 *tw, const u64 *tws, const double *twf, Geom g) {
     switch (log_m) {
 #define GCK_NTT_CASE(L)                                                                                   \
     case L:                                                                                               \
-        hipLaunchKernelGGL((ntt_pass<INV, ROWS, L, CONV>), grid, block, 0, st, buf, in, m, mods, tw, tws, twf, g); \
+        hipLaunchKernelGGL((ntt_pass<INV, ROWS, L, GM>), grid, block, 0, st, buf, in, m, mods, tw, tws, twf, g); \
         break;
         GCK_NTT_CASE(5)
         GCK_NTT_CASE(6)
@@ -479,6 +516,22 @@ void launch_pass(int log_m, dim3 grid, dim3 block, hipStream_t st, u64 *buf, con
 }
 
 }  // namespace
+
+// timing names: the kernel symbols as a profiler lists them
+static const char *pass_name(bool inv, bool rows, int log_m, int gm) {
+    static const std::vector<std::string> names = [] {   // index ((inv * 2 + rows) * 3 + gm) * 5 + log_m - 5
+        std::vector<std::string> v;
+        const char *tf[2] = {"false", "true"};
+        for (int i = 0; i < 2; ++i)
+            for (int r = 0; r < 2; ++r)
+                for (int g = 0; g < 3; ++g)
+                    for (int lm = 5; lm <= 9; ++lm)
+                        v.push_back(std::string("ntt_pass<") + tf[i] + ", " + tf[r] + ", " + std::to_string(lm) + ", " +
+                                    std::to_string(g) + ">");
+        return v;
+    }();
+    return names[(((inv ? 1 : 0) * 2 + (rows ? 1 : 0)) * 3 + gm) * 5 + (log_m - 5)].c_str();
+}
 
 static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, bool inv, hipStream_t st,
                    const LimbScale *scale = nullptr, int scale_period = 1, const ModDownEpi *epi = nullptr) {
@@ -498,7 +551,6 @@ static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, 
     Geom g_rows = g;   // the epilogue applies to the forward rows pass only
     if (epi) {
         if (inv) throw Error(CKKS_E_INVALID_ARG, "the ModDown epilogue ends a forward NTT");
-        g_rows.has_epi = 1;
         g_rows.epi = *epi;
     }
     const dim3 grid_c((unsigned)((size_t)n_limbs << (t.log_n - g.log_tile_cols)));
@@ -513,28 +565,14 @@ static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, 
     const double src_limbs = conv ? (double)(n_limbs / in.conv_period) * in.src_stride : (double)n_limbs / in.div;
     const double bytes1 = shared_src ? 8.0 * t.n * ((double)n_limbs + src_limbs) : bytes;
     const Gather none{nullptr, 1, 1, 0, 0, kPlain, 0};
-    // timing names: the kernel symbols as a profiler lists them
-    static const std::vector<std::string> names = [] {   // index ((inv * 2 + rows) * 2 + conv) * 5 + log_m - 5
-        std::vector<std::string> v;
-        const char *tf[2] = {"false", "true"};
-        for (int i = 0; i < 2; ++i)
-            for (int r = 0; r < 2; ++r)
-                for (int cv = 0; cv < 2; ++cv)
-                    for (int lm = 5; lm <= 9; ++lm)
-                        v.push_back(std::string("ntt_pass<") + tf[i] + ", " + tf[r] + ", " + std::to_string(lm) + ", " +
-                                    tf[cv] + ">");
-        return v;
-    }();
-    auto name = [&](bool i, bool rows, int log_m, bool cv = false) {
-        return names[(((i ? 1 : 0) * 2 + (rows ? 1 : 0)) * 2 + (cv ? 1 : 0)) * 5 + (log_m - 5)].c_str();
-    };
+    auto name = [&](bool i, bool rows, int log_m, int gm = kGmPlain) { return pass_name(i, rows, log_m, gm); };
     Geom g1 = g;   // first pass: group the readers of a shared source limb on one XCD
     g1.xcd_group = (shared_src && (inv ? grid_r.x : grid_c.x) % 8 == 0) ? 1 : 0;
     if (!inv) {
         {
-            TScope ts_(t, name(false, false, g.log_n1, conv), bytes1, st);
+            TScope ts_(t, name(false, false, g.log_n1, conv ? kGmConv : kGmPlain), bytes1, st);
             if (conv)
-                launch_pass<false, false, true>(g.log_n1, grid_c, block_c, st, buf, in, m, t.mods, t.psi, t.psi_sh, t.psi_f, g1);
+                launch_pass<false, false, kGmConv>(g.log_n1, grid_c, block_c, st, buf, in, m, t.mods, t.psi, t.psi_sh, t.psi_f, g1);
             else
                 launch_pass<false, false>(g.log_n1, grid_c, block_c, st, buf, in, m, t.mods, t.psi, t.psi_sh, t.psi_f, g1);
         }
@@ -545,8 +583,11 @@ static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, 
                           (1.0 + (epi->add.ptr ? (epi->add_even ? 0.5 : 1.0) : 0.0) +
                            (epi->aut ? (epi->aut_self ? 1.0 : 0.5) : 0.0))
                     : 0.0;
-            TScope ts_(t, name(false, true, g.log_n2), bytes + epi_bytes, st);
-            launch_pass<false, true>(g.log_n2, grid_r, block_r, st, buf, none, m, t.mods, t.psi, t.psi_sh, t.psi_f, g_rows);
+            TScope ts_(t, name(false, true, g.log_n2, epi ? kGmEpi : kGmPlain), bytes + epi_bytes, st);
+            if (epi)
+                launch_pass<false, true, kGmEpi>(g.log_n2, grid_r, block_r, st, buf, none, m, t.mods, t.psi, t.psi_sh, t.psi_f, g_rows);
+            else
+                launch_pass<false, true>(g.log_n2, grid_r, block_r, st, buf, none, m, t.mods, t.psi, t.psi_sh, t.psi_f, g_rows);
         }
     } else {
         {
@@ -578,5 +619,6 @@ void k_ntt_inverse_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs
                      const LimbScale *scale, int scale_period) {
     launch(t, buf, in, n_limbs, m, true, st, scale, scale_period);
 }
+
 
 }  // namespace gck
