@@ -98,7 +98,8 @@ void ckks_ctx_destroy(ckks_ctx *ctx);
 int ckks_ctx_moduli(const ckks_ctx *ctx, uint64_t *moduli, int cap);
 /* Canonical scales Delta_0..Delta_L (caller array of L + 1 entries). */
 int ckks_ctx_scales(const ckks_ctx *ctx, double *scales, int cap);
-/* Pool statistics: bytes in use, bytes cached, peak bytes, allocator calls. */
+/* Pool statistics: bytes in use, bytes cached, peak bytes, allocator calls (summed over the main pool and
+ * the pool of the context's second compute stream, which the GWAS circuit uses when no budget is set). */
 int ckks_ctx_pool_stats(const ckks_ctx *ctx, size_t *in_use, size_t *cached, size_t *peak, size_t *n_alloc);
 /* Release cached pool slabs back to the allocator. */
 int ckks_ctx_pool_trim(ckks_ctx *ctx);

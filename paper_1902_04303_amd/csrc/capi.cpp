@@ -322,17 +322,20 @@ int ckks_ctx_scales(const ckks_ctx *ctx, double *scales, int cap) {
 int ckks_ctx_pool_stats(const ckks_ctx *ctx, size_t *in_use, size_t *cached, size_t *peak, size_t *n_alloc) {
     return guard_ctx(ctx, [&] {
         need(ctx, "null context");
-        if (in_use) *in_use = ctx->pool->in_use;
-        if (cached) *cached = ctx->pool->cached;
-        if (peak) *peak = ctx->pool->peak;
-        if (n_alloc) *n_alloc = ctx->pool->n_alloc;
+        const Pool *a = ctx->aux_pool.get();   // the auxiliary stream's pool, when it exists
+        if (in_use) *in_use = ctx->pool->in_use + (a ? a->in_use : 0);
+        if (cached) *cached = ctx->pool->cached + (a ? a->cached : 0);
+        if (peak) *peak = ctx->pool->peak + (a ? a->peak : 0);
+        if (n_alloc) *n_alloc = ctx->pool->n_alloc + (a ? a->n_alloc : 0);
     });
 }
 
 int ckks_ctx_pool_trim(ckks_ctx *ctx) {
     return guard_ctx(ctx, [&] {
         need(ctx, "null context");
+        if (ctx->aux_stream) GCK_HIP(hipStreamSynchronize(ctx->stream));   // main-stream readers of aux buffers
         ctx->pool->trim();
+        if (ctx->aux_pool) ctx->aux_pool->trim();
     });
 }
 

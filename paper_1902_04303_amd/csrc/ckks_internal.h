@@ -85,6 +85,7 @@ public:
     void *get(size_t bytes);
     void put(void *p, size_t bytes);
     void trim();
+    std::unique_ptr<Pool> sibling() const;   // an empty pool with the same allocator (no budget)
     size_t in_use = 0, cached = 0, peak = 0, n_alloc = 0, budget = 0;
     hipStream_t stream = nullptr;
 

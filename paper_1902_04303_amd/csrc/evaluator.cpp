@@ -91,6 +91,13 @@ void Pool::put(void *p, size_t bytes) {
     cached += bytes;
 }
 
+std::unique_ptr<Pool> Pool::sibling() const {
+    auto p = std::make_unique<Pool>(nullptr, 0);
+    p->alloc_ = alloc_;
+    p->have_alloc_ = have_alloc_;
+    return p;
+}
+
 void Pool::trim() {
     if (free_.empty()) return;
     if (stream) hipStreamSynchronize(stream);
@@ -101,6 +108,35 @@ void Pool::trim() {
 }
 
 void sync(ckks_ctx &c) { GCK_HIP(hipStreamSynchronize(c.stream)); }
+
+void ensure_aux(ckks_ctx &c) {
+    // non-blocking (default priority): no implicit ordering with a legacy default main stream; the two
+    // streams are ordered by events only
+    if (!c.aux_stream) GCK_HIP(hipStreamCreateWithFlags(&c.aux_stream, hipStreamNonBlocking));
+    if (!c.aux_pool) {
+        c.aux_pool = c.pool->sibling();
+        c.aux_pool->stream = c.aux_stream;
+    }
+}
+
+OnStream::OnStream(ckks_ctx &ctx) : c(ctx) {
+    ensure_aux(c);
+    std::swap(c.stream, c.aux_stream);
+    c.pool.swap(c.aux_pool);
+}
+
+OnStream::~OnStream() {
+    std::swap(c.stream, c.aux_stream);
+    c.pool.swap(c.aux_pool);
+}
+
+void stream_wait(hipStream_t to, hipStream_t from) {
+    hipEvent_t ev;
+    GCK_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    GCK_HIP(hipEventRecord(ev, from));
+    GCK_HIP(hipStreamWaitEvent(to, ev, 0));
+    (void)hipEventDestroy(ev);
+}
 
 // ---------------------------------------------------------------- ciphertext helpers
 
@@ -676,11 +712,14 @@ Ct import_ct(ckks_ctx &c, const u64 *in, int depth, double scale) {
 ckks_ctx::~ckks_ctx() {
     if (stream) hipStreamSynchronize(stream);
     else hipDeviceSynchronize();
-    ksk.clear();
+    if (aux_stream) hipStreamSynchronize(aux_stream);
+    aux_pool.reset();
+    ksk.clear();   // every pool-backed member goes back to the pool before the pool is destroyed
     sk_ntt.release();
     pk.release();
     pool.reset();
     if (table_mem) (void)hipFree(table_mem);
     if (ks_mem) (void)hipFree(ks_mem);
     if (copy_stream) (void)hipStreamDestroy(copy_stream);
+    if (aux_stream) (void)hipStreamDestroy(aux_stream);
 }

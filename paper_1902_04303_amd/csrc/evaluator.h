@@ -42,6 +42,10 @@ struct ckks_ctx {
     // serialises use of the context between host threads (client calls and a server's worker)
     std::recursive_mutex mu;
     hipStream_t copy_stream = nullptr;   // second stream for host-to-device prefetch (default priority)
+    // second compute stream (default priority) with its own pool: work independent of the main stream's
+    // runs there concurrently (see OnStream); buffers move between the two only across event waits
+    hipStream_t aux_stream = nullptr;
+    std::unique_ptr<gck::Pool> aux_pool;
     ~ckks_ctx();
 };
 
@@ -108,5 +112,17 @@ void decode_poly(int n, const double *coeffs, double *re, double *im);
 void mask_poly(int n, int R, double scale, i64 *out);
 
 void sync(ckks_ctx &c);
+// While alive, the context's operations run on its auxiliary stream and allocate from its auxiliary pool
+// (both made on first use).  The caller orders the two streams with events (fork_to_aux, join_from_aux).
+struct OnStream {
+    ckks_ctx &c;
+    explicit OnStream(ckks_ctx &ctx);
+    ~OnStream();
+    OnStream(const OnStream &) = delete;
+    OnStream &operator=(const OnStream &) = delete;
+};
+void ensure_aux(ckks_ctx &c);
+// make stream `to` wait for the work enqueued so far on stream `from`
+void stream_wait(hipStream_t to, hipStream_t from);
 
 }  // namespace gck

@@ -127,32 +127,41 @@ static Ct gather(ckks_ctx &c, const std::vector<std::pair<const ckks_ct *, int>>
 
 // ---------------------------------------------------------------- fixed part (per job, batched over jobs)
 
-void run_fixed(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckks_ct *> &x, const ckks_ct &y,
-               const std::vector<const ckks_ct *> &Ain, int ds, FixedOut &fx, EncOutput &rep) {
+namespace {
+// The stacked inputs of the fixed part and the batched helpers over them.  The k columns x_j are stacked
+// into one batch (x_j of job i at position j J + i), and so is each column of A: the k independent
+// products, rotate-and-sums and product sums over j then run as one batched call each.  Every ciphertext
+// goes through the same operations as in a per-j loop.
+struct Stacked {
+    ckks_ctx &c;
     Layout lay;
-    lay.R = R;
-    lay.k = k;
-    Circ C(c, lay);
-    auto A = [&](int j, int l) -> const ckks_ct & { return *Ain[a_index(k, std::min(j, l), std::max(j, l))]; };
-    const int J = x[0]->count;   // jobs in the batch
-
-    // The k columns x_j are stacked into one batch (x_j of job i at position j J + i), and so is each
-    // column of A: the k independent products, rotate-and-sums and product sums over j then run as one
-    // batched call each.  Every ciphertext goes through the same operations as in a per-j loop.
-    Ct Xs = stack(c, x);
-    std::vector<Ct> Acol(k);
-    for (int l = 0; l < k; ++l) {
-        std::vector<const ckks_ct *> col;
-        for (int j = 0; j < k; ++j) col.push_back(&A(j, l));
-        Acol[l] = stack(c, col);
+    Circ C;
+    int k, J;
+    Ct Xs;
+    std::vector<Ct> Acol;
+    Stacked(ckks_ctx &ctx, int R, int k_, const std::vector<const ckks_ct *> &x, const std::vector<const ckks_ct *> &Ain)
+        : c(ctx), lay(make_lay(R, k_)), C(ctx, lay), k(k_), J(x[0]->count) {
+        Xs = stack(c, x);
+        Acol.resize(k);
+        for (int l = 0; l < k; ++l) {
+            std::vector<const ckks_ct *> col;
+            for (int j = 0; j < k; ++j) col.push_back(Ain[a_index(k, std::min(j, l), std::max(j, l))]);
+            Acol[l] = stack(c, col);
+        }
     }
-    auto parts = [&](const ckks_ct &s) {
+    static Layout make_lay(int R, int k) {
+        Layout l;
+        l.R = R;
+        l.k = k;
+        return l;
+    }
+    std::vector<Ct> parts(const ckks_ct &s) const {
         std::vector<Ct> v(k);
         for (int j = 0; j < k; ++j) v[j] = view(s, j * J, J);
         return v;
-    };
+    }
     // (A v)_j = sum_l A_jl v_l for every j at once, A at the depth of v
-    auto a_times = [&](const std::vector<Ct> &v) {
+    Ct a_times(const std::vector<Ct> &v) {
         std::vector<Ct> Ad(k);
         std::vector<std::pair<const ckks_ct *, const ckks_ct *>> q;
         for (int l = 0; l < k; ++l) {
@@ -160,28 +169,53 @@ void run_fixed(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckk
             q.push_back({Ad[l].get(), v[l].get()});
         }
         return C.msum(q);
-    };
+    }
     // sum_j x_j t_j for stacked t, x at the depth of t (times factor)
-    auto x_dot = [&](const ckks_ct &t, double factor) {
+    Ct x_dot(const ckks_ct &t, double factor) {
         Ct Xd = C.at(*Xs, t.depth, factor);
         std::vector<Ct> a = parts(*Xd), b = parts(t);
         std::vector<std::pair<const ckks_ct *, const ckks_ct *>> q;
         for (int j = 0; j < k; ++j) q.push_back({a[j].get(), b[j].get()});
         return C.msum(q);
-    };
+    }
+};
+}  // namespace
 
+void fixed_front(ckks_ctx &c, int R, int k, const std::vector<const ckks_ct *> &x, const std::vector<const ckks_ct *> &Ain,
+                 int ds, FixedOut &fx) {
+    Stacked st(c, R, k, x, Ain);
+    const int J = st.J;
+    // ---- r_j = (X A)_{:, j}, and x_j at the depth the per-batch part uses it
+    std::vector<Ct> x1(k);
+    for (int l = 0; l < k; ++l) x1[l] = st.C.at(*x[l], 1);
+    Ct RR = st.a_times(x1);
+    Ct RRs = st.C.at(*RR, ds), Xc = st.C.at(*st.Xs, ds + 2);
+    fx.r_s.resize(k);
+    fx.x_c.resize(k);
+    for (int j = 0; j < k; ++j) {
+        fx.r_s[j] = clone(c, *view(*RRs, j * J, J));
+        fx.x_c[j] = clone(c, *view(*Xc, j * J, J));
+    }
+}
+
+void fixed_back(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckks_ct *> &x, const ckks_ct &y,
+                const std::vector<const ckks_ct *> &Ain, int ds, FixedOut &fx, EncOutput &rep) {
+    Stacked st(c, R, k, x, Ain);
+    Circ &C = st.C;
+    const int J = st.J;
+    const ckks_ct &Xs = *st.Xs;
     // ---- Alg. Homomorphic LogReg, first pass: beta = 0, so p = sigma7(0) = 1/2 is public
     Ct r = add_const(c, y, -0.5);
-    Ct G = C.rot_sum(mul(c, *Xs, *r));                 // g_j = X^T (y - p), stacked over j
-    Ct beta = mul_int(c, *a_times(parts(*G)), 4);     // beta_j = 4 (A g)_j, stacked over j
+    Ct G = C.rot_sum(mul(c, Xs, *r));                    // g_j = X^T (y - p), stacked over j
+    Ct beta = mul_int(c, *st.a_times(st.parts(*G)), 4);  // beta_j = 4 (A g)_j, stacked over j
     Ct pk;
     for (int t = 1; t < kappa; ++t) {
-        Ct u = x_dot(*beta, 0.125);                    // the 1/8 of sigma7's argument
+        Ct u = st.x_dot(*beta, 0.125);                   // the 1/8 of sigma7's argument
         pk = C.sigma7(*u);
         const int dp = pk->depth;
         r = sub(c, *C.at(y, dp), *pk);
-        G = C.rot_sum(mul(c, *C.at(*Xs, dp), *r));
-        Ct inc = mul_int(c, *a_times(parts(*G)), 4);
+        G = C.rot_sum(mul(c, *C.at(Xs, dp), *r));
+        Ct inc = mul_int(c, *st.a_times(st.parts(*G)), 4);
         beta = add(c, *C.at(*beta, inc->depth), *inc);
     }
     // ---- w = p (1 - p), Alg. inverseSlots: guess 3, the first Newton step is 6 - 9 w
@@ -194,28 +228,17 @@ void run_fixed(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckk
     }
     Ct w_inv = std::move(gi);
     // ---- z = X beta^(kappa) + w^-1 (y - p^(kappa-1))
-    Ct xbeta = x_dot(*beta, 1.0);
+    Ct xbeta = st.x_dot(*beta, 1.0);
     Ct tz = mul(c, *C.at(*r, w_inv->depth), *w_inv);
     Ct z = add(c, *C.at(*xbeta, tz->depth), *tz);
     // ---- z' = z - X (A (X^T z))
-    Ct H = C.rot_sum(mul(c, *C.at(*Xs, z->depth), *z));
-    Ct V = a_times(parts(*H));
-    Ct xvs = x_dot(*V, 1.0);
+    Ct H = C.rot_sum(mul(c, *C.at(Xs, z->depth), *z));
+    Ct V = st.a_times(st.parts(*H));
+    Ct xvs = st.x_dot(*V, 1.0);
     Ct z_proj = sub(c, *C.at(*z, xvs->depth), *xvs);
     Ct u = mul(c, *C.at(*w, z_proj->depth), *z_proj);
-    // ---- r_j = (X A)_{:, j}
-    std::vector<Ct> x1(k);
-    for (int l = 0; l < k; ++l) x1[l] = C.at(*x[l], 1);
-    Ct RR = a_times(x1);
     // ---- what the per-batch part needs, at the depths it uses them
-    Ct RRs = C.at(*RR, ds), Xc = C.at(*Xs, ds + 2);
-    fx.r_s.resize(k);
-    fx.x_c.resize(k);
-    for (int j = 0; j < k; ++j) {
-        fx.r_s[j] = clone(c, *view(*RRs, j * J, J));
-        fx.x_c[j] = clone(c, *view(*Xc, j * J, J));
-        rep.beta.push_back(clone(c, *view(*beta, j * J, J)));
-    }
+    for (int j = 0; j < k; ++j) rep.beta.push_back(clone(c, *view(*beta, j * J, J)));
     fx.u_s = C.at(*u, ds + 3);
     fx.w_s = C.at(*w, ds + 3);
     rep.w = std::move(w);
@@ -224,9 +247,16 @@ void run_fixed(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckk
     rep.u = std::move(u);
 }
 
+void run_fixed(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckks_ct *> &x, const ckks_ct &y,
+               const std::vector<const ckks_ct *> &Ain, int ds, FixedOut &fx, EncOutput &rep) {
+    fixed_front(c, R, k, x, Ain, ds, fx);
+    fixed_back(c, R, k, kappa, x, y, Ain, ds, fx, rep);
+}
+
 // ---------------------------------------------------------------- per-batch part
 
-BatchOut run_batch(ckks_ctx &c, int R, int k, const FixedOut &fx, const ckks_ct &S) {
+// S' = S - sum_j x_j E_j with E_j = bcast_R(mask(colSum(r_j S))): needs only r_j and x_j of the fixed part
+Ct batch_front(ckks_ctx &c, int R, int k, const FixedOut &fx, const ckks_ct &S) {
     Layout lay;
     lay.R = R;
     lay.k = k;
@@ -241,8 +271,17 @@ BatchOut run_batch(ckks_ctx &c, int R, int k, const FixedOut &fx, const ckks_ct 
     std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pe;
     for (int j = 0; j < k; ++j) pe.push_back({fx.x_c[j].get(), E[j].get()});
     Ct xe = C.msum(pe);
+    return sub(c, *C.at(S, xe->depth), *xe);
+}
+
+// numerator and denominators from S' (needs u and w of the fixed part)
+BatchOut batch_back(ckks_ctx &c, int R, int k, const FixedOut &fx, Ct sp) {
+    Layout lay;
+    lay.R = R;
+    lay.k = k;
+    Circ C(c, lay);
     BatchOut o;
-    o.sp = sub(c, *C.at(S, xe->depth), *xe);
+    o.sp = std::move(sp);
     o.num = C.rot_sum(mul(c, *fx.u_s, *o.sp));
     Ct ws = mul(c, *fx.w_s, *o.sp);
     Ct sc = conjugate(c, *o.sp);
@@ -251,6 +290,10 @@ BatchOut run_batch(ckks_ctx &c, int R, int k, const FixedOut &fx, const ckks_ct 
     o.de = C.rot_sum(set_scale(c, add(c, *wsc, *wss), 2.0));
     o.dodd = C.rot_sum(set_scale(c, sub(c, *wsc, *wss), 2.0));
     return o;
+}
+
+BatchOut run_batch(ckks_ctx &c, int R, int k, const FixedOut &fx, const ckks_ct &S) {
+    return batch_back(c, R, k, fx, batch_front(c, R, k, fx, S));
 }
 
 static void check_keys(ckks_ctx &c, int R) {
@@ -296,8 +339,38 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
     for (auto &p : in.A) A.push_back(p.get());
     FixedOut fx;
     const int ds = in.S->depth;
-    run_fixed(c, lay.R, k, in.kappa, x, *in.y, A, ds, fx, out);
     const int nb = in.S->count;
+    if (!in.S_host && c.pool->budget == 0) {
+        // The logistic regression (u, w) runs on the auxiliary stream while the main stream computes what
+        // needs only r_j and x_j: S' of every SNP batch.  The numerator and denominators then wait for it.
+        fixed_front(c, lay.R, k, x, A, ds, fx);
+        ensure_aux(c);
+        stream_wait(c.aux_stream, c.stream);   // inputs and this call's earlier work before the fixed part
+        {
+            OnStream on_aux(c);
+            fixed_back(c, lay.R, k, in.kappa, x, *in.y, A, ds, fx, out);
+        }
+        std::vector<Ct> sps;
+        for (int b0 = 0; b0 < nb; b0 += chunk) {
+            const int cnt = std::min(chunk, nb - b0);
+            Ct S = new_ct(c, cnt, ds, in.S->scale);
+            fetch_snp(c, in, b0, cnt, *S, 0, c.stream);
+            sps.push_back(batch_front(c, lay.R, k, fx, *S));
+        }
+        stream_wait(c.stream, c.aux_stream);   // u and w
+        for (Ct &sp : sps) {
+            BatchOut o = batch_back(c, lay.R, k, fx, std::move(sp));
+            out.S_proj.push_back(std::move(o.sp));
+            out.num.push_back(std::move(o.num));
+            out.den_even.push_back(std::move(o.de));
+            out.den_odd.push_back(std::move(o.dodd));
+        }
+        // buffers of the auxiliary pool were read on the main stream: later reuse on the auxiliary stream
+        // comes after this work
+        stream_wait(c.aux_stream, c.stream);
+        return;
+    }
+    run_fixed(c, lay.R, k, in.kappa, x, *in.y, A, ds, fx, out);
     if (!in.S_host) {
         for (int b0 = 0; b0 < nb; b0 += chunk) {
             const int cnt = std::min(chunk, nb - b0);

@@ -382,12 +382,23 @@ __global__ void ks_inner(u64 *acc, const u64 *digits, int K, const int *__restri
     const int gl = ks_groups(l, alpha);
     const int groups = (count + CB - 1) / CB;
     const size_t chunks = n >> 8;   // 256-word chunks per limb
-    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
-        const size_t blk = idx >> 8;
-        const int grp = (int)(blk % groups);
-        const size_t rest = blk / groups;
-        const size_t k = ((rest % chunks) << 8) + (idx & 255);
-        const int tt = (int)(rest / chunks);
+    // Work item: (target, 256-word chunk, group of CB ciphertexts).  Workgroup b runs on XCD b mod 8; XCD x
+    // takes the chunks [x p8, (x + 1) p8) of every target, and consecutive workgroups of an XCD (which run
+    // together) take the ciphertext groups of one chunk: they share its key words in the XCD's L2.
+    // gridDim.x is a multiple of 8 and `total` counts 8 p8 nt groups items.
+    const int p8 = chunks >= 8 ? (int)(chunks >> 3) : 1;
+    const int x = (int)(blockIdx.x & 7);
+    const int pos0 = x * p8;
+    const int npos = pos0 >= (int)chunks ? 0 : ((int)chunks - pos0 < p8 ? (int)chunks - pos0 : p8);
+    const size_t items_x = (size_t)npos * nt * groups;   // items of this XCD
+    for (size_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const size_t sl = b >> 3;                          // slot of this workgroup on its XCD
+        if (sl >= items_x) break;
+        const int grp = (int)(sl % groups);
+        const size_t rest = sl / groups;
+        const int pos = pos0 + (int)(rest % npos);
+        const int tt = (int)(rest / npos);
+        const size_t k = ((size_t)pos << 8) + threadIdx.x;
         const int chain = tt < l ? tt : levels + 1 + (tt - l);
         const ModInfo M = mods[chain];
         const size_t krow = (size_t)chain * n + k;   // key word of group b: key[b key_grp + krow]
@@ -423,9 +434,11 @@ void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const in
     TScope ts_(t, names[cb == 4 ? 2 : cb - 1][mk == 3 ? 2 : mk],
                8.0 * (double)t.n * (keys.m * 2.0 * gl * nt + (double)count * (gl * nt + 2.0 * nt)), st);
     if (t.log_n < 8) throw Error(CKKS_E_INVALID_ARG, "key switching needs N >= 256");
-    size_t total = ((size_t)((count + cb - 1) / cb) * nt) << t.log_n;
-    if (!total) return;
-    const dim3 grid = ew_grid(total), block(kEwThreads);
+    const size_t chunks = (size_t)1 << (t.log_n - 8);
+    const size_t p8 = chunks >= 8 ? chunks / 8 : 1;
+    const size_t total = 8 * p8 * nt * (size_t)((count + cb - 1) / cb);   // workgroup items
+    if (!count) return;
+    const dim3 grid((unsigned)(total < 65536 * 8 ? total : 65536 * 8)), block(kEwThreads);
 #define GCK_KS(CB_, MK_) \
     hipLaunchKernelGGL((ks_inner<CB_, MK_>), grid, block, 0, st, acc, digits, K, didx, own, keys, ng, total, t.log_n, \
                        l, levels, alpha, count, t.mods)
