@@ -243,16 +243,24 @@ void gwas_output_free(gwas_enc_output *out);
 int gwas_finalize(ckks_ctx *ctx, const gwas_enc_output *out, int m, double *b, double *err, double *se,
                   double *num, double *den);
 
-/* Per-kernel timing with HIP events recorded on the context's stream around every
- * launch of the instrumented kernels.  enable = 1 clears the counters and starts
+/* Per-kernel timing with HIP events set by the runtime at the start and the end of
+ * every launch of the instrumented kernels (hipExtLaunchKernelGGL), on the stream
+ * each kernel is launched on.  enable = 1 clears the counters and starts
  * recording; 0 stops.  The report is text, one line per kernel:
  * "name launches total_ms algorithmic_bytes" (the name, a kernel symbol such as
- * "ntt_pass<false, true, 8>", may contain spaces; the last three fields are numbers). */
+ * "ntt_pass<false, true, 8, 0>", may contain spaces; the last three fields are numbers).
+ * While two streams run at once a kernel's interval includes waiting for workgroup
+ * slots held by the other stream's kernels (see ckks_ctx_set_streams). */
 int ckks_ctx_kernel_timing(ckks_ctx *ctx, int enable);
 /* Restrict recording to launches of one kernel name (as it appears in the report), so that timing a
  * single kernel adds two event records per launch of that kernel only; NULL or "" records all. */
 int ckks_ctx_kernel_timing_only(ckks_ctx *ctx, const char *name);
 int ckks_ctx_kernel_report(ckks_ctx *ctx, char *buf, size_t cap);
+/* Number of compute streams the GWAS circuit may use: 2 (the default) runs the
+ * logistic-regression part on a second stream concurrently with the per-batch work
+ * that does not depend on it; 1 runs everything in order on the context's stream.
+ * Results are identical either way. */
+int ckks_ctx_set_streams(ckks_ctx *ctx, int n);
 
 /* ---------------------------------------------------------------- batched and serving forms
  * (additions of this library around the paper's algorithm; the arithmetic of each job is unchanged) */

@@ -76,6 +76,7 @@ _SIGS = [
     ("ckks_ctx_kernel_timing", ctypes.c_int, [_vp, ctypes.c_int]),
     ("ckks_ctx_kernel_report", ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     ("ckks_ctx_kernel_timing_only", ctypes.c_int, [_vp, ctypes.c_char_p]),
+    ("ckks_ctx_set_streams", ctypes.c_int, [_vp, ctypes.c_int]),
     ("ckks_ctx_counters", ctypes.c_int, [_vp, _u64p, _u64p, _u64p]),
     ("ckks_keygen", ctypes.c_int, [_vp, ctypes.c_uint64, _u64p, ctypes.c_int]),
     ("ckks_galois_rotate", ctypes.c_uint64, [_vp, ctypes.c_int64]),
@@ -321,6 +322,11 @@ class Context:
 
     def kernel_timing_only(self, name: Optional[str]):
         _check(lib().ckks_ctx_kernel_timing_only(self.h, name.encode() if name else None))
+
+    def set_streams(self, n: int):
+        """1: the GWAS circuit runs in order on one stream; 2 (default): the logistic-regression part
+        overlaps the independent per-batch work on a second stream."""
+        _check(lib().ckks_ctx_set_streams(self.h, int(n)))
 
     def kernel_report(self):
         """{kernel: (launches, total_ms, algorithmic_bytes)} from the HIP-event timing."""

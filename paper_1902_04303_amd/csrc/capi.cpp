@@ -365,6 +365,13 @@ int ckks_ctx_kernel_timing_only(ckks_ctx *ctx, const char *name) {
     });
 }
 
+int ckks_ctx_set_streams(ckks_ctx *ctx, int n) {
+    return guard_ctx(ctx, [&] {
+        need(ctx && (n == 1 || n == 2), "streams must be 1 or 2");
+        ctx->n_streams = n;
+    });
+}
+
 int ckks_ctx_kernel_report(ckks_ctx *ctx, char *buf, size_t cap) {
     return guard_ctx(ctx, [&] {
         need(ctx && buf && cap > 0, "bad buffer");

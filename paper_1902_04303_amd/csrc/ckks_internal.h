@@ -131,7 +131,9 @@ struct ModMap {
 };
 inline ModMap map_q(int l) { return ModMap{l, l, 0}; }
 
-// Optional per-kernel timing with HIP events on the launching stream (off by default).
+// Optional per-kernel timing (off by default).  Each timed launch carries a start and a stop event that
+// the runtime sets when the kernel itself starts and ends (hipExtLaunchKernelGGL), so the time excludes
+// waiting for workgroup slots behind kernels of another stream.
 struct KTimer {
     bool on = false;
     std::string only;   // when not empty, only launches of this name are recorded
@@ -139,6 +141,7 @@ struct KTimer {
         int id;
         hipEvent_t a, b;
         double bytes;
+        bool launched;
     };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> spare;

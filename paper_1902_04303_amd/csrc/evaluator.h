@@ -46,6 +46,7 @@ struct ckks_ctx {
     // runs there concurrently (see OnStream); buffers move between the two only across event waits
     hipStream_t aux_stream = nullptr;
     std::unique_ptr<gck::Pool> aux_pool;
+    int n_streams = 2;   // 1: the circuit runs in order on `stream` only
     ~ckks_ctx();
 };
 

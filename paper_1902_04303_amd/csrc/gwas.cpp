@@ -340,7 +340,7 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
     FixedOut fx;
     const int ds = in.S->depth;
     const int nb = in.S->count;
-    if (!in.S_host && c.pool->budget == 0) {
+    if (!in.S_host && c.pool->budget == 0 && c.n_streams == 2) {
         // The logistic regression (u, w) runs on the auxiliary stream while the main stream computes what
         // needs only r_j and x_j: S' of every SNP batch.  The numerator and denominators then wait for it.
         fixed_front(c, lay.R, k, x, A, ds, fx);

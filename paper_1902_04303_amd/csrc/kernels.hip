@@ -42,13 +42,22 @@ int KTimer::begin(const char *name, double bytes, hipStream_t st) {
     } else {
         id = it->second;
     }
-    Rec r{id, take(), take(), bytes};
-    GCK_HIP(hipEventRecord(r.a, st));
-    recs.push_back(r);
+    (void)st;
+    recs.push_back(Rec{id, take(), take(), bytes, false});
+    tl_timed_launch = &recs.back();   // the next launch on this thread fills its events
     return (int)recs.size() - 1;
 }
 
-void KTimer::end(int idx, hipStream_t st) { GCK_HIP(hipEventRecord(recs[idx].b, st)); }
+void KTimer::end(int idx, hipStream_t) {
+    tl_timed_launch = nullptr;
+    if (!recs[idx].launched && idx == (int)recs.size() - 1) {   // nothing was launched in the scope
+        spare.push_back(recs[idx].a);
+        spare.push_back(recs[idx].b);
+        recs.pop_back();
+    }
+}
+
+thread_local KTimer::Rec *tl_timed_launch = nullptr;
 
 void KTimer::collect() {
     for (auto &r : recs) {
@@ -111,7 +120,7 @@ void k_add(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs
     TScope ts_(t, "ew_binary<0>", 24.0 * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
-    hipLaunchKernelGGL(ew_binary<0>, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, na, nb);
+    gck_launch(ew_binary<0>, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, na, nb);
     check_launch();
 }
 void k_sub(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
@@ -119,7 +128,7 @@ void k_sub(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs
     TScope ts_(t, "ew_binary<1>", 24.0 * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
-    hipLaunchKernelGGL(ew_binary<1>, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, na, nb);
+    gck_launch(ew_binary<1>, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, na, nb);
     check_launch();
 }
 void k_mul(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
@@ -127,7 +136,7 @@ void k_mul(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs
     TScope ts_(t, "ew_binary<2>", 24.0 * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
-    hipLaunchKernelGGL(ew_binary<2>, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, na, nb);
+    gck_launch(ew_binary<2>, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, m, t.mods, na, nb);
     check_launch();
 }
 
@@ -144,7 +153,7 @@ void k_mul_const(const DevTables &t, u64 *out, const u64 *a, int n_limbs, ModMap
     TScope ts_(t, "ew_mul_const", 16.0 * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
-    hipLaunchKernelGGL(ew_mul_const, ew_grid(total), dim3(kEwThreads), 0, st, out, a, total, t.log_n, m, t.mods, c);
+    gck_launch(ew_mul_const, ew_grid(total), dim3(kEwThreads), 0, st, out, a, total, t.log_n, m, t.mods, c);
     check_launch();
 }
 
@@ -164,7 +173,7 @@ void k_add_const_c0(const DevTables &t, u64 *ct, int count, int l, const ChainCo
     TScope ts_(t, "ew_add_const_c0", 16.0 * (double)((size_t)count * l) * t.n, st);
     size_t total = ((size_t)count * l) << t.log_n;
     if (!total) return;
-    hipLaunchKernelGGL(ew_add_const_c0, ew_grid(total), dim3(kEwThreads), 0, st, ct, total, t.log_n, l, t.mods, c);
+    gck_launch(ew_add_const_c0, ew_grid(total), dim3(kEwThreads), 0, st, ct, total, t.log_n, l, t.mods, c);
     check_launch();
 }
 
@@ -203,7 +212,7 @@ void k_tensor(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int coun
     TScope ts_(t, "ew_tensor", 8.0 * 7.0 * (double)((size_t)count * l) * t.n, st);
     size_t total = ((size_t)count * l) << t.log_n;
     if (!total) return;
-    hipLaunchKernelGGL(ew_tensor, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, l, t.mods, na, nb,
+    gck_launch(ew_tensor, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, total, t.log_n, l, t.mods, na, nb,
                        accumulate ? 1 : 0);
     check_launch();
 }
@@ -219,7 +228,7 @@ void k_automorph(const DevTables &t, u64 *out, const u64 *a, int n_limbs, u64 g,
     TScope ts_(t, "ew_automorph", 16.0 * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
-    hipLaunchKernelGGL(ew_automorph, ew_grid(total), dim3(kEwThreads), 0, st, out, a, total, t.log_n, g);
+    gck_launch(ew_automorph, ew_grid(total), dim3(kEwThreads), 0, st, out, a, total, t.log_n, g);
     check_launch();
 }
 
@@ -233,7 +242,7 @@ void k_copy_rows(u64 *out, size_t out_stride, const u64 *in, size_t in_stride, i
                  hipStream_t st) {
     size_t total = (size_t)rows * words;
     if (!total) return;
-    hipLaunchKernelGGL(ew_copy_rows, ew_grid(total), dim3(kEwThreads), 0, st, out, out_stride, in, in_stride, total, words);
+    gck_launch(ew_copy_rows, ew_grid(total), dim3(kEwThreads), 0, st, out, out_stride, in, in_stride, total, words);
     check_launch();
 }
 
@@ -259,7 +268,7 @@ void k_sub_mul_add(const DevTables &t, u64 *out, const Gather &a, const u64 *b, 
     TScope ts_(t, "ew_sub_mul_add", (x.ptr ? 32.0 : 24.0) * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
-    hipLaunchKernelGGL(ew_sub_mul_add, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, c, x, x_even_rows ? 1 : 0,
+    gck_launch(ew_sub_mul_add, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, c, x, x_even_rows ? 1 : 0,
                        rowlen, total, t.log_n, m, t.mods);
     check_launch();
 }
@@ -440,7 +449,7 @@ void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const in
     if (!count) return;
     const dim3 grid((unsigned)(total < 65536 * 8 ? total : 65536 * 8)), block(kEwThreads);
 #define GCK_KS(CB_, MK_) \
-    hipLaunchKernelGGL((ks_inner<CB_, MK_>), grid, block, 0, st, acc, digits, K, didx, own, keys, ng, total, t.log_n, \
+    gck_launch((ks_inner<CB_, MK_>), grid, block, 0, st, acc, digits, K, didx, own, keys, ng, total, t.log_n, \
                        l, levels, alpha, count, t.mods)
     switch (cb * 10 + mk) {
     case 41: GCK_KS(4, 1); break;
@@ -474,7 +483,7 @@ void k_sample_uniform(const DevTables &t, u64 *out, u64 seed, u64 sid, int n_lim
     TScope ts_(t, "sample_uniform", 8.0 * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
-    hipLaunchKernelGGL(sample_uniform, ew_grid(total), dim3(kEwThreads), 0, st, out, seed, sid, total, t.log_n, m, t.mods);
+    gck_launch(sample_uniform, ew_grid(total), dim3(kEwThreads), 0, st, out, seed, sid, total, t.log_n, m, t.mods);
     check_launch();
 }
 
@@ -487,11 +496,11 @@ __global__ void sample_small(i64 *out, u64 seed, u64 sid, int n, int kind) {
     }
 }
 void k_sample_cbd(i64 *out, u64 seed, u64 sid, int n, hipStream_t st) {
-    hipLaunchKernelGGL(sample_small, ew_grid(n), dim3(kEwThreads), 0, st, out, seed, sid, n, 0);
+    gck_launch(sample_small, ew_grid(n), dim3(kEwThreads), 0, st, out, seed, sid, n, 0);
     check_launch();
 }
 void k_sample_ternary(i64 *out, u64 seed, u64 sid, int n, hipStream_t st) {
-    hipLaunchKernelGGL(sample_small, ew_grid(n), dim3(kEwThreads), 0, st, out, seed, sid, n, 1);
+    gck_launch(sample_small, ew_grid(n), dim3(kEwThreads), 0, st, out, seed, sid, n, 1);
     check_launch();
 }
 
@@ -515,7 +524,7 @@ void k_signed_to_limbs(const DevTables &t, u64 *out, const i64 *in, int n_limbs,
     TScope ts_(t, "ew_signed_to_limbs", 8.0 * (double)(n_limbs + 1) * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
-    hipLaunchKernelGGL(ew_signed_to_limbs, ew_grid(total), dim3(kEwThreads), 0, st, out, in, total, t.log_n, m, t.mods);
+    gck_launch(ew_signed_to_limbs, ew_grid(total), dim3(kEwThreads), 0, st, out, in, total, t.log_n, m, t.mods);
     check_launch();
 }
 
@@ -530,14 +539,14 @@ void k_to_mont(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t st
     TScope ts_(t, "ew_mont", 16.0 * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
-    hipLaunchKernelGGL(ew_mont, ew_grid(total), dim3(kEwThreads), 0, st, x, total, t.log_n, m, t.mods, 1);
+    gck_launch(ew_mont, ew_grid(total), dim3(kEwThreads), 0, st, x, total, t.log_n, m, t.mods, 1);
     check_launch();
 }
 void k_from_mont(const DevTables &t, u64 *x, int n_limbs, ModMap m, hipStream_t st) {
     TScope ts_(t, "ew_mont", 16.0 * (double)n_limbs * t.n, st);
     size_t total = (size_t)n_limbs << t.log_n;
     if (!total) return;
-    hipLaunchKernelGGL(ew_mont, ew_grid(total), dim3(kEwThreads), 0, st, x, total, t.log_n, m, t.mods, 0);
+    gck_launch(ew_mont, ew_grid(total), dim3(kEwThreads), 0, st, x, total, t.log_n, m, t.mods, 0);
     check_launch();
 }
 

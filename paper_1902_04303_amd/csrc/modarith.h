@@ -1,6 +1,7 @@
 // Device-side modular arithmetic and helpers shared by the HIP kernel files.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "ckks_internal.h"
@@ -119,7 +120,20 @@ __device__ __forceinline__ u64 mul_shoup_lazy(u64 a, u64 w, u64 wsh, u64 q) {
     return a * w - __umul64hi(a, wsh) * q;
 }
 
-// RAII timing scope around kernel launches (records HIP events when timing is on)
+// Kernel launch: plain, or with the events of the pending timing record (see KTimer) when a TScope is open.
+extern thread_local KTimer::Rec *tl_timed_launch;
+template <typename... KArgs, typename... Args>
+inline void gck_launch(void (*kernel)(KArgs...), dim3 grid, dim3 block, unsigned shmem, hipStream_t st, Args... args) {
+    if (KTimer::Rec *r = tl_timed_launch) {
+        tl_timed_launch = nullptr;
+        r->launched = true;
+        hipExtLaunchKernelGGL(kernel, grid, block, shmem, st, r->a, r->b, 0u, static_cast<KArgs>(args)...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shmem, st, static_cast<KArgs>(args)...);
+    }
+}
+
+// RAII timing scope around one kernel launch (records its events when timing is on)
 struct TScope {
     KTimer *t;
     int idx = -1;

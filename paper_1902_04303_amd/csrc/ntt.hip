@@ -502,7 +502,7 @@ void launch_pass(int log_m, dim3 grid, dim3 block, hipStream_t st, u64 *buf, con
     switch (log_m) {
 #define GCK_NTT_CASE(L)                                                                                   \
     case L:                                                                                               \
-        hipLaunchKernelGGL((ntt_pass<INV, ROWS, L, GM>), grid, block, 0, st, buf, in, m, mods, tw, tws, twf, g); \
+        gck_launch((ntt_pass<INV, ROWS, L, GM>), grid, block, 0, st, buf, in, m, mods, tw, tws, twf, g); \
         break;
         GCK_NTT_CASE(5)
         GCK_NTT_CASE(6)

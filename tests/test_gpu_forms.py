@@ -88,6 +88,24 @@ def test_multi_job_matches_single_jobs(ctx, singles):
             same(outputs(ctx, o, ctx.gwas_layout(n, k, m, KAPPA)["n_batches"]), r)
 
 
+def test_one_and_two_streams_agree(ctx, singles):
+    """The circuit with the logistic-regression part on a second stream (the default) and in order on one
+    stream give the same ciphertexts."""
+    say("[gpu] one stream vs two streams")
+    for q in (0, 2, 4):
+        n, k, m, seed = JOBS[q]
+        lay = ctx.gwas_layout(n, k, m, KAPPA)
+        ctx.set_streams(1)
+        try:
+            one = outputs(ctx, ctx.gwas_semiparallel(pack(ctx, n, k, m, seed)), lay["n_batches"])
+        finally:
+            ctx.set_streams(2)
+        same(one, singles[q])
+        for chunk in (1, 2):   # several chunks: every chunk's S' is computed before the join
+            two = outputs(ctx, ctx.gwas_semiparallel(pack(ctx, n, k, m, seed), chunk), lay["n_batches"])
+            same(two, singles[q])
+
+
 def test_spilled_snp_batches_match_resident(ctx, singles):
     say("[gpu] spill")
     n, k, m, seed = JOBS[1]
