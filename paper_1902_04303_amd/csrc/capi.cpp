@@ -78,7 +78,7 @@ ConvEntry conv_entry(int src, int nsrc, int chain, const u64 *cs, u64 q, const s
         e.c[m] = cs[m] % q;
         e.c_sh[m] = shoup_of(e.c[m], q);
         e.cd[m] = (double)e.c[m];
-        if (src_mods[m] >= (1ULL << 47)) e.big = 1;
+        if (src_mods[m] >= (1ULL << 47)) e.big |= 1 << m;   // source m's residues need splitting
     }
     return e;
 }

@@ -183,7 +183,7 @@ void k_ntt_inverse(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStrea
 // kConv: basis conversion.  Output limb lam takes entry e = conv[lam % conv_period] and row
 // r = lam / conv_period; its modulus is chain e.chain and its word is sum_{m < e.nsrc} y_m c_m mod that
 // modulus, y_m = src limb r * src_stride + e.src + m (a residue of another modulus, below 2^47 unless
-// e.big), c_m = e.c[m] (with its Shoup companion and FP64 copy).
+// bit m of e.big is set), c_m = e.c[m] (with its Shoup companion and FP64 copy).
 struct ConvEntry {
     int src, nsrc, chain, big;
     u64 c[kMaxSpecial], c_sh[kMaxSpecial];

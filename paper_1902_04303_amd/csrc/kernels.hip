@@ -435,7 +435,7 @@ void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const in
                 const KsKeys &keys, int ng, int count, int l, int levels, int alpha, hipStream_t st) {
     const int nt = l + alpha, gl = ks_groups(l, alpha);
     // algorithmic bytes: every key word and every digit word read once, the accumulators written once
-    const int cb = count >= 4 ? 4 : (count >= 2 ? 2 : 1);   // 8 (with fewer waves, or spills) measured slower
+    const int cb = count >= 4 ? 4 : (count >= 2 ? 2 : 1);   // 2 or 8 (fewer waves, or spills) measured slower
     const int mk = (keys.m == 1 || keys.m == 3) ? keys.m : 0;
     static const char *const names[3][3] = {{"ks_inner<1, 0>", "ks_inner<1, 1>", "ks_inner<1, 3>"},
                                             {"ks_inner<2, 0>", "ks_inner<2, 1>", "ks_inner<2, 3>"},

@@ -344,7 +344,7 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
                         y[e] = src[(size_t)slot_index<LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(h + e, q) * stride];
 #pragma unroll
                     for (int e = 0; e < kPer / 2; ++e) {
-                        const double a = big ? fred(fmul_mod((double)(y[e] >> 32), M.c32_d, fm) +
+                        const double a = ((big >> m) & 1) ? fred(fmul_mod((double)(y[e] >> 32), M.c32_d, fm) +
                                                         (double)(y[e] & 0xFFFFFFFFULL), fm)
                                              : (double)y[e];
                         x[h + e] += fmul_mod(a, w, fm);
