@@ -344,26 +344,46 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
     const FMod fm{M.qd, M.qinv};
     KsAcc<CB, FP> A;
     A.zero();
-    for (int gb = 0; gb < gl; ++gb) {
-        const int e = didx[gb * nt + tt];
-        const u64 *src[CB];
-#pragma unroll
-        for (int b = 0; b < CB; ++b) src[b] = e >= 0 ? digits + ((size_t)(c0 + b) * K + e) * n : own_row[b];
-        if constexpr (MK > 0) {
-            u64 kw0[MK], kw1[MK], dw[MK][CB];
+    if constexpr (MK > 0) {
+        // the loads of digit group gb + 1 are issued before the products of group gb (double buffer)
+        u64 kw0[2][MK], kw1[2][MK], dw[2][MK][CB];
+        auto load = [&](int gb, int s) {
+            const int e = didx[gb * nt + tt];
 #pragma unroll
             for (int i = 0; i < MK; ++i) {
-                kw0[i] = keys.key[i][(size_t)gb * key_grp + krow];
-                kw1[i] = keys.key[i][key_comp + (size_t)gb * key_grp + krow];
+                kw0[s][i] = keys.key[i][(size_t)gb * key_grp + krow];
+                kw1[s][i] = keys.key[i][key_comp + (size_t)gb * key_grp + krow];
 #pragma unroll
-                for (int b = 0; b < CB; ++b) dw[i][b] = b < nb ? src[b][kd[i]] : 0;
+                for (int b = 0; b < CB; ++b) {
+                    const u64 *src = e >= 0 ? digits + ((size_t)(c0 + b) * K + e) * n : own_row[b];
+                    dw[s][i][b] = b < nb ? src[kd[i]] : 0;
+                }
             }
+        };
+        load(0, 0);
+        for (int gb = 0; gb < gl; gb += 2) {
+            if (gb + 1 < gl) load(gb + 1, 1);
 #pragma unroll
             for (int i = 0; i < MK; ++i)
 #pragma unroll
                 for (int b = 0; b < CB; ++b)
-                    if (b < nb) A.mac(b, dw[i][b], kw0[i], kw1[i], M, fm);
-        } else {
+                    if (b < nb) A.mac(b, dw[0][i][b], kw0[0][i], kw1[0][i], M, fm);
+            A.settle(fm);
+            if (gb + 1 >= gl) break;
+            if (gb + 2 < gl) load(gb + 2, 0);
+#pragma unroll
+            for (int i = 0; i < MK; ++i)
+#pragma unroll
+                for (int b = 0; b < CB; ++b)
+                    if (b < nb) A.mac(b, dw[1][i][b], kw0[1][i], kw1[1][i], M, fm);
+            A.settle(fm);
+        }
+    } else {
+        for (int gb = 0; gb < gl; ++gb) {
+            const int e = didx[gb * nt + tt];
+            const u64 *src[CB];
+#pragma unroll
+            for (int b = 0; b < CB; ++b) src[b] = e >= 0 ? digits + ((size_t)(c0 + b) * K + e) * n : own_row[b];
             for (int i = 0; i < keys.m; ++i) {
                 const size_t kdi = keys.g[i] ? automorph_src(k, log_n, keys.g[i]) : k;
                 const u64 k0 = keys.key[i][(size_t)gb * key_grp + krow];
@@ -372,8 +392,8 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
                 for (int b = 0; b < CB; ++b)
                     if (b < nb) A.mac(b, src[b][kdi], k0, k1, M, fm);
             }
+            A.settle(fm);
         }
-        A.settle(fm);
     }
 #pragma unroll
     for (int b = 0; b < CB; ++b)
@@ -381,7 +401,7 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
 }
 
 template <int CB, int MK>
-__global__ void ks_inner(u64 *acc, const u64 *digits, int K, const int *__restrict__ didx, Gather own, KsKeys keys,
+__global__ void __launch_bounds__(kEwThreads, 3) ks_inner(u64 *acc, const u64 *digits, int K, const int *__restrict__ didx, Gather own, KsKeys keys,
                          int ng, size_t total, int log_n, int l, int levels, int alpha, int count, const ModInfo *mods) {
     const size_t n = (size_t)1 << log_n;
     const int nt = l + alpha;                 // targets of this key switch
