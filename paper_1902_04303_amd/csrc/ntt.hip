@@ -454,18 +454,36 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
             const bool aut_self = xs && E.aut_self;
             if (M.fp) {
                 // FP64: |acc - t| < q, the product's remainder below 1.1 q, each added residue below q: the
-                // sum stays below 12 q for up to 8 automorphism terms, well inside the exact range
+                // sum stays below 12 q for up to 8 automorphism terms, well inside the exact range (the
+                // sums of two residues below 2^42 are exact as well)
                 const FMod fm{M.qd, M.qinv};
                 const double pd = E.pinv_d[chain];
+                // every load of a group of EG words is issued before the group's stores (the stores could
+                // otherwise alias later loads for the compiler)
+                constexpr int EG = 4, AU = 3;   // words per group, automorphism terms loaded ahead
 #pragma unroll
-                for (int e = 0; e < kPer; ++e) {
-                    const int idx = slot_index<LOGM, 0, Ph<LOGM, 0>::R>(e, q);
-                    const u64 t = sh[lds_addr<ROWS>(gi, idx, LOGM, log_g)];
-                    double r = fmul_mod((double)xa[base + idx] - (double)t, pd, fm);
-                    if (with_add) r += (double)xd[base + idx];
-                    if (aut_self) r += (double)xs[base + idx];
-                    for (int i = 0; i < n_aut; ++i) r += (double)xs[automorph_src(base + idx, g.log_n, E.g[i])];
-                    a[base + idx] = fcanon(r, fm);
+                for (int e0 = 0; e0 < kPer; e0 += EG) {
+                    u64 va[EG], vt[EG], vd[EG], vs[EG], vp[AU][EG];
+#pragma unroll
+                    for (int j = 0; j < EG; ++j) {
+                        const size_t w = base + slot_index<LOGM, 0, Ph<LOGM, 0>::R>(e0 + j, q);
+                        vt[j] = sh[lds_addr<ROWS>(gi, slot_index<LOGM, 0, Ph<LOGM, 0>::R>(e0 + j, q), LOGM, log_g)];
+                        va[j] = xa[w];
+                        vd[j] = with_add ? xd[w] : 0;
+                        vs[j] = aut_self ? xs[w] : 0;
+#pragma unroll
+                        for (int i = 0; i < AU; ++i) vp[i][j] = i < n_aut ? xs[automorph_src(w, g.log_n, E.g[i])] : 0;
+                    }
+#pragma unroll
+                    for (int j = 0; j < EG; ++j) {
+                        const size_t w = base + slot_index<LOGM, 0, Ph<LOGM, 0>::R>(e0 + j, q);
+                        double r = fmul_mod((double)va[j] - (double)vt[j], pd, fm);
+                        r += (double)vd[j] + (double)vs[j];
+#pragma unroll
+                        for (int i = 0; i < AU; ++i) r += (double)vp[i][j];
+                        for (int i = AU; i < n_aut; ++i) r += (double)xs[automorph_src(w, g.log_n, E.g[i])];
+                        a[w] = fcanon(r, fm);
+                    }
                 }
             } else {
                 const u64 pv = E.pinv[chain], ps = E.pinv_sh[chain];
