@@ -323,33 +323,42 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
     // passes, loads or stores, measured slower than the strided access it replaces)
     u64 v[kPer];
     if constexpr (CONV) {
-        // basis conversion while loading: sum_m y_m c_m mod q, one source limb at a time (its 16 loads
-        // issued in two groups of 8; prefetching the next source into registers measured slower); FP64
-        // moduli keep the sum as a double (|sum| < 1.1 q per source, below 2^45 for up to kMaxSpecial
-        // sources) and store its bits
+        // basis conversion while loading: sum_m y_m c_m mod q over the source limbs, 8 words at a time with
+        // the next 8 words' loads issued before the current 8 are converted (double buffer); FP64 moduli
+        // keep the sum as a double (|sum| < 1.1 q per source, below 2^45 for up to kMaxSpecial sources)
+        // and store its bits
         const int ns = ce->nsrc, big = ce->big;
         const FMod fm{M.qd, M.qinv};
         if (M.fp) {
+            constexpr int H = kPer / 2;
             double x[kPer];
 #pragma unroll
             for (int e = 0; e < kPer; ++e) x[e] = 0.0;
-            for (int m = 0; m < ns; ++m) {
+            // buffer 0 holds words 0..H-1 of a source, buffer 1 words H..2H-1
+            u64 y0[H], y1[H];
+            auto load = [&](u64 (&yb)[H], int m, int h) {
                 const u64 *src = ain + (size_t)m * n + base;
+#pragma unroll
+                for (int e = 0; e < H; ++e)
+                    yb[e] = src[(size_t)slot_index<LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(h + e, q) * stride];
+            };
+            auto convert = [&](const u64 (&yb)[H], double *xh, int m) {
                 const double w = ce->cd[m];
+                const bool split = (big >> m) & 1;
 #pragma unroll
-                for (int h = 0; h < kPer; h += kPer / 2) {
-                    u64 y[kPer / 2];
-#pragma unroll
-                    for (int e = 0; e < kPer / 2; ++e)
-                        y[e] = src[(size_t)slot_index<LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(h + e, q) * stride];
-#pragma unroll
-                    for (int e = 0; e < kPer / 2; ++e) {
-                        const double a = ((big >> m) & 1) ? fred(fmul_mod((double)(y[e] >> 32), M.c32_d, fm) +
-                                                        (double)(y[e] & 0xFFFFFFFFULL), fm)
-                                             : (double)y[e];
-                        x[h + e] += fmul_mod(a, w, fm);
-                    }
+                for (int e = 0; e < H; ++e) {
+                    const u64 y = yb[e];
+                    const double a = split ? fred(fmul_mod((double)(y >> 32), M.c32_d, fm) + (double)(y & 0xFFFFFFFFULL), fm)
+                                           : (double)y;
+                    xh[e] += fmul_mod(a, w, fm);
                 }
+            };
+            load(y0, 0, 0);
+            for (int m = 0; m < ns; ++m) {
+                load(y1, m, H);
+                convert(y0, x, m);
+                if (m + 1 < ns) load(y0, m + 1, 0);
+                convert(y1, x + H, m);
             }
 #pragma unroll
             for (int e = 0; e < kPer; ++e) v[e] = (u64)__double_as_longlong(fred(x[e], fm));
