@@ -163,6 +163,7 @@ void build_ks_tables(ckks_ctx &c) {
     }
     const size_t o_down = room(down.size() * sizeof(ConvEntry)), o_dsc = room(dscale.size() * sizeof(LimbScale));
     const size_t o_pinv = room(kMaxMods * 8), o_pinv_sh = room(kMaxMods * 8), o_pinv_d = room(kMaxMods * 8);
+    const size_t o_qinv = room((size_t)nq * 3 * kMaxMods * 8);   // [j][v, sh, d][kMaxMods]
     GCK_HIP(hipMalloc(&c.ks_mem, bytes));
     char *base = static_cast<char *>(c.ks_mem);
     c.ks_levels.assign(nq + 1, ckks_ctx::KsLevel{});
@@ -188,6 +189,22 @@ void build_ks_tables(ckks_ctx &c) {
     for (int i = 0; i < p.n_mods(); ++i) pinv_d[i] = (double)c.p_inv.v[i];
     c.p_inv_d_dev = reinterpret_cast<double *>(base + o_pinv_d);
     GCK_HIP(hipMemcpy(c.p_inv_d_dev, pinv_d.data(), kMaxMods * 8, hipMemcpyHostToDevice));
+    // rescale constants: q_j^-1 mod q_i (j the dropped prime)
+    std::vector<u64> qinv((size_t)nq * 3 * kMaxMods, 0);
+    c.q_inv.assign(nq, ckks_ctx::QInv{});
+    for (int j = 1; j < nq; ++j) {
+        u64 *v = &qinv[(size_t)j * 3 * kMaxMods], *sh = v + kMaxMods;
+        double *d = reinterpret_cast<double *>(sh + kMaxMods);
+        for (int i = 0; i < p.n_mods(); ++i) {
+            const u64 q = p.mod(i), x = p.q[j] % q;
+            v[i] = x ? invmod_host(x, q) : 0;
+            sh[i] = shoup_of(v[i], q);
+            d[i] = (double)v[i];
+        }
+        u64 *dev = reinterpret_cast<u64 *>(base + o_qinv) + (size_t)j * 3 * kMaxMods;
+        c.q_inv[j] = ckks_ctx::QInv{dev, dev + kMaxMods, reinterpret_cast<double *>(dev + 2 * kMaxMods)};
+    }
+    GCK_HIP(hipMemcpy(base + o_qinv, qinv.data(), qinv.size() * 8, hipMemcpyHostToDevice));
     c.ng = ks_groups(nq, p.alpha);
 }
 

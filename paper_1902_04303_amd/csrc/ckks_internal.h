@@ -226,10 +226,6 @@ void k_ntt_forward_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs
 // scale (nullable): multiply output limb lam by scale[lam % scale_period].w instead of N^-1
 void k_ntt_inverse_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st,
                      const LimbScale *scale = nullptr, int scale_period = 1);
-// out = (a - b) * c[chain] (+ x): a and x are gathered (x may be null; x_even_rows: add x only on
-// rows lam / rowlen that are even, i.e. to the first polynomial of each ciphertext)
-void k_sub_mul_add(const DevTables &t, u64 *out, const Gather &a, const u64 *b, const ChainConst &c, const Gather &x,
-                   bool x_even_rows, int rowlen, int n_limbs, ModMap m, hipStream_t st);
 // out = a op b over n_limbs limbs; a is read at limb (lam % na_limbs), b at (lam % nb_limbs)
 void k_add(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
            hipStream_t st);

@@ -212,17 +212,6 @@ static ChainConst chain_const_of(const ckks_ctx &c, i64 k) {
     return cc;
 }
 
-static ChainConst chain_inv_of(const ckks_ctx &c, u64 x) {
-    ChainConst cc{};
-    for (int i = 0; i < c.p.n_mods(); ++i) {
-        u64 q = c.p.mod(i);
-        u64 v = (x % q == 0) ? 0 : invmod_host(x % q, q);
-        cc.v[i] = v;
-        cc.sh[i] = (u64)(((u128)v << 64) / q);
-    }
-    return cc;
-}
-
 static void check_same(const ckks_ct &a, const ckks_ct &b) {
     if (a.depth != b.depth || a.scale != b.scale)
         throw Error(CKKS_E_PARAM_MISMATCH, "operands differ in depth (" + std::to_string(a.depth) + ", " +
@@ -270,21 +259,22 @@ Ct add_const(ckks_ctx &c, const ckks_ct &a, double v) {
 
 // Rescale: round(c / q_last) on the centred integer, per limb (c_i - [c_last]_centred) * q_last^-1 mod q_i.
 // The last limb of every polynomial is gathered by the inverse NTT, centred-lifted to the other limbs
-// while loading the forward NTT, and the difference is scaled in one element-wise pass.
+// while loading the forward NTT, and the forward NTT's final store (the ModDown epilogue with q_last^-1
+// in place of P^-1) subtracts and scales straight into the result.
 Ct rescale(ckks_ctx &c, const ckks_ct &a) {
     const int l = a.limbs, rows = a.count * 2;
     if (l < 2) throw Error(CKKS_E_LEVEL, "no limb left to rescale");
     const size_t N = (size_t)c.p.n;
     DBuf last(c.pool.get(), (size_t)rows * N);
     k_ntt_inverse_g(c.tab, last.ptr, Gather{a.data.ptr, 1, l, l - 1, 0, kPlain, 0}, rows, ModMap{1, 0, l - 1}, c.stream);
-    DBuf t(c.pool.get(), (size_t)rows * (l - 1) * N);
-    k_ntt_forward_g(c.tab, t.ptr, Gather{last.ptr, l - 1, 1, 0, 0, kCentred, l - 1}, rows * (l - 1), map_q(l - 1),
-                    c.stream);
     Ct r = new_ct(c, a.count, a.depth + 1, a.scale);
-    k_sub_mul_add(c.tab, r->data.ptr, Gather{a.data.ptr, l - 1, l, 0, 1, kPlain, 0}, t.ptr, chain_inv_of(c, c.p.q[l - 1]),
-                  Gather{nullptr, 1, 1, 0, 0, kPlain, 0}, false, l - 1, rows * (l - 1), map_q(l - 1), c.stream);
+    const ckks_ctx::QInv &qi = c.q_inv.at(l - 1);
+    const ModDownEpi epi{Gather{a.data.ptr, l - 1, l, 0, 1, kPlain, 0}, Gather{}, 0, l - 1, qi.v, qi.sh, qi.d, nullptr,
+                         0, 0, {}};
+    k_ntt_forward_g(c.tab, r->data.ptr, Gather{last.ptr, l - 1, 1, 0, 0, kCentred, l - 1}, rows * (l - 1),
+                    map_q(l - 1), c.stream, &epi);
     c.n_limb_ntt += (uint64_t)rows * l;
-    c.n_launch += 5;
+    c.n_launch += 4;
     return r;
 }
 

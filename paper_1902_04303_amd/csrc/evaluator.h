@@ -29,6 +29,12 @@ struct ckks_ctx {
     gck::ChainConst p_inv{};                 // P^-1 mod every chain modulus
     gck::u64 *p_inv_dev = nullptr, *p_inv_sh_dev = nullptr;   // the same on the device
     double *p_inv_d_dev = nullptr;                             // and as doubles (FP64 moduli)
+    // rescale by q_j (j = 1..L): q_j^-1 mod every chain modulus, with Shoup companions and as doubles
+    struct QInv {
+        gck::u64 *v = nullptr, *sh = nullptr;
+        double *d = nullptr;
+    };
+    std::vector<QInv> q_inv;
     int ng = 0;                              // digit groups of a key (at L + 1 limbs)
     // keys
     bool have_keys = false;

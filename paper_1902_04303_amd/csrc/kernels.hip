@@ -249,30 +249,6 @@ void k_copy_rows(u64 *out, size_t out_stride, const u64 *in, size_t in_stride, i
 __device__ __forceinline__ size_t gather_limb(const Gather &g, int lam) {
     return (size_t)((lam / g.div) * g.mul + g.add + (lam % g.div) * g.inner);
 }
-
-__global__ void ew_sub_mul_add(u64 *out, Gather a, const u64 *b, ChainConst c, Gather x, int x_even_rows, int rowlen,
-                               size_t total, int log_n, ModMap mm, const ModInfo *mods) {
-    const size_t n = (size_t)1 << log_n;
-    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
-        const int lam = (int)(idx >> log_n);
-        const size_t k = idx & (n - 1);
-        const int ch = chain_of(lam, mm);
-        const u64 q = mods[ch].q;
-        u64 r = mul_shoup(sub_mod(a.ptr[gather_limb(a, lam) * n + k], b[idx], q), c.v[ch], c.sh[ch], q);
-        if (x.ptr && (!x_even_rows || ((lam / rowlen) & 1) == 0)) r = add_mod(r, x.ptr[gather_limb(x, lam) * n + k], q);
-        out[idx] = r;
-    }
-}
-void k_sub_mul_add(const DevTables &t, u64 *out, const Gather &a, const u64 *b, const ChainConst &c, const Gather &x,
-                   bool x_even_rows, int rowlen, int n_limbs, ModMap m, hipStream_t st) {
-    TScope ts_(t, "ew_sub_mul_add", (x.ptr ? 32.0 : 24.0) * (double)n_limbs * t.n, st);
-    size_t total = (size_t)n_limbs << t.log_n;
-    if (!total) return;
-    gck_launch(ew_sub_mul_add, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, c, x, x_even_rows ? 1 : 0,
-                       rowlen, total, t.log_n, m, t.mods);
-    check_launch();
-}
-
 // ---------------------------------------------------------------- key-switch inner product
 //
 // acc[c][comp][t][k] = sum_i sum_b sigma_i(D_b[c][t])[k] * key_i[comp][b][chain(t)][k] mod the target's

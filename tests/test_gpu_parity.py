@@ -180,6 +180,31 @@ def test_mul_relinearise_and_galois_match_oracle(small):
             assert np.array_equal(ctx.export(ctx.rotate_sum(ga, rots)), o.rotate_sum(oa, rots).data)
 
 
+def test_kernel_timing_report(small):
+    """Per-kernel timing: every launched kernel appears with its launches and a positive time, a timing
+    restricted to one kernel records that kernel only, and timing leaves the results unchanged."""
+    ctx, o, p = small
+    rng = np.random.default_rng(8)
+    ga, _ = _both(ctx, o, p, rand_ct(p, 1, rng), 1)
+    want = ctx.export(ctx.rotate_sum(ga, [1, -2, 4]))
+    ctx.kernel_timing(True)
+    got = ctx.export(ctx.rotate_sum(ga, [1, -2, 4]))
+    ctx.kernel_timing(False)
+    rep = ctx.kernel_report()
+    assert np.array_equal(got, want)
+    assert any(k.startswith("ks_inner<") for k in rep) and any(k.startswith("ntt_pass<") for k in rep)
+    for name, (cnt, ms, by) in rep.items():
+        assert cnt >= 1 and ms > 0 and by > 0, name
+    name = next(k for k in rep if k.startswith("ks_inner<"))
+    ctx.kernel_timing_only(name)
+    ctx.kernel_timing(True)
+    got = ctx.export(ctx.rotate_sum(ga, [1, -2, 4]))
+    ctx.kernel_timing(False)
+    ctx.kernel_timing_only(None)
+    only = {k: v for k, v in ctx.kernel_report().items() if v[0]}
+    assert list(only) == [name] and np.array_equal(got, want)
+
+
 def test_missing_key_and_level_errors(small):
     ctx, o, p = small
     rng = np.random.default_rng(6)
