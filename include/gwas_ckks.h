@@ -186,7 +186,7 @@ int ckks_rescale(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out);
 int ckks_align(ckks_ctx *ctx, const ckks_ct *a, int depth, double scale, double factor, ckks_ct **out);
 /* Rotate (paper: Rotate) by r slots: slot j of the result holds slot j + r. */
 int ckks_rotate(ckks_ctx *ctx, const ckks_ct *a, int64_t r, ckks_ct **out);
-/* a + sum_i Rotate(a, rots[i]) for 1 <= n <= 8 rotations sharing one key switch: one decomposition of
+/* a + sum_i Rotate(a, rots[i]) for 1 <= n <= 16 rotations sharing one key switch: one decomposition of
  * c1 (each digit permuted by its rotation after the basis extension) and one division by P for the sum
  * (a grouped step of Alg. colSum).  Needs the Galois key of every rotation. */
 int ckks_rotate_sum(ckks_ctx *ctx, const ckks_ct *a, const int64_t *rots, int n, ckks_ct **out);
@@ -209,8 +209,9 @@ int gwas_layout(const ckks_ctx *ctx, int n, int k, int m, int kappa, int *R, int
                 int *levels_needed);
 
 /* Host only: the Galois elements whose keys the circuit needs for block size R at ring degree 2^log_n
- * (the rotations of the grouped rotate-and-sum in both directions, then conjugation).  Writes at most
- * cap elements to out and the number needed to *count. */
+ * (the rotations of the grouped rotate-and-sum in both directions, each once: the fixed part groups
+ * them by up to 3 per key switch, {s, 2s, 3s}, the per-SNP-batch part by up to 15, {s, 2s, .., 15s};
+ * then conjugation).  Writes at most cap elements to out and the number needed to *count. */
 int gwas_galois_elements(int log_n, int R, uint64_t *out, int cap, int *count);
 
 /* Client side: compute A = (X^T X)^-1 in FP64, encode and encrypt x_j (R-periodic,
@@ -247,8 +248,9 @@ int gwas_finalize(ckks_ctx *ctx, const gwas_enc_output *out, int m, double *b, d
  * every launch of the instrumented kernels (hipExtLaunchKernelGGL), on the stream
  * each kernel is launched on.  enable = 1 clears the counters and starts
  * recording; 0 stops.  The report is text, one line per kernel:
- * "name launches total_ms algorithmic_bytes" (the name, a kernel symbol such as
- * "ntt_pass<false, true, 8, 0>", may contain spaces; the last three fields are numbers).
+ * "name launches total_ms algorithmic_bytes algorithmic_fp64_ops" (the name, a kernel symbol such as
+ * "ntt_pass<false, true, 8, 0>", may contain spaces; the last four fields are numbers; the FP64 operation
+ * count is 0 for kernels bound by memory rather than arithmetic).
  * While two streams run at once a kernel's interval includes waiting for workgroup
  * slots held by the other stream's kernels (see ckks_ctx_set_streams). */
 int ckks_ctx_kernel_timing(ckks_ctx *ctx, int enable);

@@ -184,30 +184,42 @@ def encrypt_inputs(o: C.Oracle, pts: Plaintexts, n: int, k: int, m: int, kappa: 
     return EncInput(lay=lay, kappa=kappa, x=x, y=yc, A=A, S=S)
 
 
-def rotation_groups(R: int) -> List[List[int]]:
-    """The left rotations of a rotate-and-sum over R = 2^r slots, grouped by shared key switch: each
-    group {s, 2s, 3s} (s = 1, 4, 16, ...) replaces two doubling steps a <- a + Rot(a, s), a <- a + Rot(a, 2s)
-    of Alg. colSum by a <- a + Rot(a, s) + Rot(a, 2s) + Rot(a, 3s), and a last group {s} covers an odd r."""
+# Rotations per shared key switch: up to FIXED_RADIX - 1 in the fixed part (one to a few ciphertexts per
+# call) and up to BATCH_RADIX - 1 in the per-SNP-batch part.
+FIXED_RADIX = 4
+BATCH_RADIX = 16
+
+
+def rotation_groups(R: int, radix: int = FIXED_RADIX) -> List[List[int]]:
+    """The left rotations of a rotate-and-sum over R = 2^r slots, grouped by shared key switch.
+
+    Alg. colSum doubles its partial sums: a <- a + Rot(a, s) for s = 1, 2, 4, .., R/2.  A group merges
+    log2(m) consecutive doublings starting at shift s into one step a <- a + sum_{0 < j < m} Rot(a, j s),
+    since (1 + X^s)(1 + X^2s)..(1 + X^(m/2) s) = sum_{j < m} X^(j s); here m = min(radix, R / s) and the
+    next group starts at shift m s.  Radix 4 gives {s, 2s, 3s} for s = 1, 4, 16, .. and a last {s} when
+    r is odd."""
     out = []
     s = 1
     while s < R:
-        if 4 * s <= R:
-            out.append([s, 2 * s, 3 * s])
-            s *= 4
-        else:
-            out.append([s])
-            s *= 2
+        m = min(radix, R // s)
+        out.append([j * s for j in range(1, m)])
+        s *= m
     return out
 
 
 def required_galois(N: int, R: int) -> List[int]:
-    """Galois elements of the left and right rotations of rotation_groups(R) and of conjugation."""
-    out = []
-    for grp in rotation_groups(R):
-        for r in grp:
-            out.append(C.galois_rotate(N, r))
-            out.append(C.galois_rotate(N, -r))
-    out.append(C.galois_conj(N))
+    """Galois elements of the left and right rotations of rotation_groups(R, FIXED_RADIX) and
+    rotation_groups(R, BATCH_RADIX), each once in first-seen order, then conjugation."""
+    out: List[int] = []
+    for radix in (FIXED_RADIX, BATCH_RADIX):
+        for grp in rotation_groups(R, radix):
+            for r in grp:
+                for e in (C.galois_rotate(N, r), C.galois_rotate(N, -r)):
+                    if e not in out:
+                        out.append(e)
+    e = C.galois_conj(N)
+    if e not in out:
+        out.append(e)
     return out
 
 
@@ -246,15 +258,15 @@ class Circuit:
             return a
         return self.o.align(a, d, self.sc[d], factor)
 
-    def rot_sum(self, a: C.Ct) -> C.Ct:
-        """sum_{i < R} Rot(a, i) (Alg. colSum / Alg. DotProd), by the groups of rotation_groups(R)."""
-        for grp in rotation_groups(self.lay.R):
+    def rot_sum(self, a: C.Ct, radix: int = FIXED_RADIX) -> C.Ct:
+        """sum_{i < R} Rot(a, i) (Alg. colSum / Alg. DotProd), by the groups of rotation_groups(R, radix)."""
+        for grp in rotation_groups(self.lay.R, radix):
             a = self.o.rotate_sum(a, grp)
         return a
 
-    def bcast(self, a: C.Ct) -> C.Ct:
+    def bcast(self, a: C.Ct, radix: int = FIXED_RADIX) -> C.Ct:
         """sum_{i < R} Rot(a, -i): copies each block's first slot over its block."""
-        for grp in rotation_groups(self.lay.R):
+        for grp in rotation_groups(self.lay.R, radix):
             a = self.o.rotate_sum(a, [-r for r in grp])
         return a
 
@@ -278,20 +290,20 @@ class Circuit:
         cs = []
         for j in range(k):
             pj = o.mul(self.at(fx.rr[j], ds), S)
-            cj = self.rot_sum(pj)                 # column sums at block starts (Alg. colSum)
+            cj = self.rot_sum(pj, BATCH_RADIX)    # column sums at block starts (Alg. colSum)
             cj = o.mul_mask(cj, self.lay.R)       # keep block starts only
-            cs.append(self.bcast(cj))             # (A X^T S)_{j, c} over block c
+            cs.append(self.bcast(cj, BATCH_RADIX))   # (A X^T S)_{j, c} over block c
         dc = cs[0].depth
         xe = o.mul_sum([(self.at(fx.x[j], dc), cs[j]) for j in range(k)])
         sp = o.sub(self.at(S, xe.depth), xe)
         dsp = sp.depth
-        num = self.rot_sum(o.mul(self.at(fx.u, dsp), sp))
+        num = self.rot_sum(o.mul(self.at(fx.u, dsp), sp), BATCH_RADIX)
         ws = o.mul(self.at(fx.w, dsp), sp)
         sc = o.conjugate(sp)
         wss = o.mul(ws, self.at(sp, ws.depth))
         wsc = o.mul(ws, self.at(sc, ws.depth))
-        de = self.rot_sum(o.set_scale(o.add(wsc, wss), 2.0))
-        do = self.rot_sum(o.set_scale(o.sub(wsc, wss), 2.0))
+        de = self.rot_sum(o.set_scale(o.add(wsc, wss), 2.0), BATCH_RADIX)
+        do = self.rot_sum(o.set_scale(o.sub(wsc, wss), 2.0), BATCH_RADIX)
         return sp, num, de, do
 
     def run(self, inp: EncInput) -> EncOutput:

@@ -329,13 +329,13 @@ class Context:
         _check(lib().ckks_ctx_set_streams(self.h, int(n)))
 
     def kernel_report(self):
-        """{kernel: (launches, total_ms, algorithmic_bytes)} from the HIP-event timing."""
+        """{kernel: (launches, total_ms, algorithmic_bytes, algorithmic_fp64_ops)} from the HIP-event timing."""
         buf = ctypes.create_string_buffer(1 << 16)
         _check(lib().ckks_ctx_kernel_report(self.h, buf, len(buf)))
         out = {}
         for line in buf.value.decode().splitlines():
-            name, cnt, ms, by = line.rsplit(None, 3)   # kernel names may contain spaces
-            out[name] = (int(cnt), float(ms), float(by))
+            name, cnt, ms, by, fl = line.rsplit(None, 4)   # kernel names may contain spaces
+            out[name] = (int(cnt), float(ms), float(by), float(fl))
         return out
 
     # ---- keys
@@ -437,7 +437,7 @@ class Context:
         return self._op(lib().ckks_rotate, a.h, int(r))
 
     def rotate_sum(self, a, rots: Sequence[int]):
-        """a + sum_i rotate(a, rots[i]) with one shared key switch (1 to 8 rotations)."""
+        """a + sum_i rotate(a, rots[i]) with one shared key switch (1 to 16 rotations)."""
         arr = (ctypes.c_int64 * len(rots))(*[int(r) for r in rots])
         return self._op(lib().ckks_rotate_sum, a.h, arr, len(rots))
 

@@ -397,8 +397,8 @@ int ckks_ctx_kernel_report(ckks_ctx *ctx, char *buf, size_t cap) {
         char line[256];
         for (size_t i = 0; i < ctx->timer.names.size(); ++i) {
             const auto &st = ctx->timer.stats[i];
-            std::snprintf(line, sizeof line, "%s %llu %.6f %.0f\n", ctx->timer.names[i].c_str(),
-                          (unsigned long long)st.count, st.ms, st.bytes);
+            std::snprintf(line, sizeof line, "%s %llu %.6f %.0f %.0f\n", ctx->timer.names[i].c_str(),
+                          (unsigned long long)st.count, st.ms, st.bytes, st.flops);
             s += line;
         }
         need(s.size() + 1 <= cap, "report buffer too small");
@@ -609,7 +609,7 @@ int ckks_rotate(ckks_ctx *ctx, const ckks_ct *a, int64_t r, ckks_ct **out) {
 int ckks_rotate_sum(ckks_ctx *ctx, const ckks_ct *a, const int64_t *rots, int n, ckks_ct **out) {
     return guard_ctx(ctx, [&] {
         check_ct(ctx, a);
-        need(out && rots && n >= 1 && n <= kMaxKeys, "need 1 to 8 rotations and an output");
+        need(out && rots && n >= 1 && n <= kMaxKeys, "need 1 to 16 rotations and an output");
         *out = release(rotate_sum(*ctx, *a, std::vector<i64>(rots, rots + n)));
     });
 }

@@ -140,7 +140,7 @@ struct KTimer {
     struct Rec {
         int id;
         hipEvent_t a, b;
-        double bytes;
+        double bytes, flops;
         bool launched;
     };
     std::vector<Rec> recs;
@@ -149,11 +149,11 @@ struct KTimer {
     std::map<std::string, int> ids;
     struct Stat {
         uint64_t count = 0;
-        double ms = 0, bytes = 0;
+        double ms = 0, bytes = 0, flops = 0;   // algorithmic HBM bytes and FP64 operations (0: not declared)
     };
     std::vector<Stat> stats;
     hipEvent_t take();
-    int begin(const char *name, double bytes, hipStream_t st);
+    int begin(const char *name, double bytes, double flops, hipStream_t st);
     void end(int idx, hipStream_t st);
     void collect();   // synchronises, folds recorded events into stats
     void reset();
@@ -211,7 +211,7 @@ inline Gather gather_plain(const u64 *p) { return Gather{p, 1, 1, 0, 0, kPlain, 
 // aut_self * aut[lam][k] +
 // sum_i aut[lam][k_i] with k_i the source word of the NTT-domain automorphism X -> X^g[i], odd rows add
 // aut_self * aut[lam][k] (rotate-and-sum: a + sum_i sigma_i(a c0); a single Galois map: sigma(a c0)).
-constexpr int kMaxKeys = 8;
+constexpr int kMaxKeys = 16;
 struct ModDownEpi {
     Gather acc, add;
     int add_even, rowlen;
@@ -260,6 +260,9 @@ struct KsKeys {
 // [2][ng][L + 1 + alpha][N] in NTT and Montgomery form (times 2^64); digits hold K limbs per ciphertext.
 void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const int *didx, const Gather &own,
                 const KsKeys &keys, int ng, int count, int l, int levels, int alpha, hipStream_t st);
+// z[c][j] = sum_i sigma_i(a[c][0][j]) mod q_j (NTT domain) for the keys' automorphisms (any Galois maps,
+// up to kMaxKeys), a [count][2][l][N] and z [count][l][N]
+void k_aut_sum(const DevTables &t, u64 *z, const u64 *a, int count, int l, const KsKeys &keys, hipStream_t st);
 // samplers of the test-only SplitMix64 streams
 void k_sample_uniform(const DevTables &t, u64 *out, u64 seed, u64 sid, int n_limbs, ModMap m, int mi_of_p,
                       hipStream_t st);

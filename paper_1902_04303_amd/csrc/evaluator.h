@@ -97,7 +97,7 @@ Ct mul_sum(ckks_ctx &c, const std::vector<std::pair<const ckks_ct *, const ckks_
 Ct mul(ckks_ctx &c, const ckks_ct &a, const ckks_ct &b);
 Ct apply_galois(ckks_ctx &c, const ckks_ct &a, u64 g);
 Ct rotate(ckks_ctx &c, const ckks_ct &a, i64 r);
-// a + sum_i Rot(a, rots[i]) with one key switch shared by the rotations (at most 8)
+// a + sum_i Rot(a, rots[i]) with one key switch shared by the rotations (at most 16)
 Ct rotate_sum(ckks_ctx &c, const ckks_ct &a, const std::vector<i64> &rots);
 Ct conjugate(ckks_ctx &c, const ckks_ct &a);
 u64 galois_rotate(const ckks_ctx &c, i64 r);

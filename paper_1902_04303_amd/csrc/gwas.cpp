@@ -35,28 +35,30 @@ Layout make_layout(int n_ring, int n, int k, int m) {
     return L;
 }
 
-std::vector<std::vector<i64>> rotation_groups(int R) {
+std::vector<std::vector<i64>> rotation_groups(int R, int radix) {
     std::vector<std::vector<i64>> out;
     for (i64 s = 1; s < R;) {
-        if (4 * s <= R) {
-            out.push_back({s, 2 * s, 3 * s});
-            s *= 4;
-        } else {
-            out.push_back({s});
-            s *= 2;
-        }
+        const i64 m = std::min<i64>(radix, R / s);   // this group covers the shifts j s, j < m
+        std::vector<i64> grp;
+        for (i64 j = 1; j < m; ++j) grp.push_back(j * s);
+        out.push_back(grp);
+        s *= m;
     }
     return out;
 }
 
 std::vector<u64> required_galois(int n, int R) {
     std::vector<u64> g;
-    for (const auto &grp : rotation_groups(R))
-        for (i64 r : grp) {
-            g.push_back(galois_rotate_n(n, r));
-            g.push_back(galois_rotate_n(n, -r));
-        }
-    g.push_back(2ULL * (u64)n - 1);   // conjugation
+    auto put = [&](u64 e) {
+        if (std::find(g.begin(), g.end(), e) == g.end()) g.push_back(e);
+    };
+    for (int radix : {kFixedRadix, kBatchRadix})
+        for (const auto &grp : rotation_groups(R, radix))
+            for (i64 r : grp) {
+                put(galois_rotate_n(n, r));
+                put(galois_rotate_n(n, -r));
+            }
+    put(2ULL * (u64)n - 1);   // conjugation
     return g;
 }
 
@@ -65,21 +67,22 @@ namespace {
 struct Circ {
     ckks_ctx &c;
     const Layout &lay;
-    explicit Circ(ckks_ctx &cc, const Layout &l) : c(cc), lay(l) {}
+    int radix;   // rotate-and-sum groups: up to radix - 1 rotations per key switch
+    Circ(ckks_ctx &cc, const Layout &l, int rdx) : c(cc), lay(l), radix(rdx) {}
 
     // a at depth d and the canonical scale; factor multiplies the value
     Ct at(const ckks_ct &a, int d, double factor = 1.0) {
         if (d == a.depth && factor == 1.0) return clone(c, a);
         return align(c, a, d, c.p.scales[d], factor);
     }
-    // sum_{i < R} Rot(a, i) (Alg. colSum / Alg. DotProd): per group {s, 2s, 3s} of rotation_groups,
-    // a <- a + Rot(a, s) + Rot(a, 2s) + Rot(a, 3s) with one shared key switch
+    // sum_{i < R} Rot(a, i) (Alg. colSum / Alg. DotProd): per group {s, 2s, .., (m - 1) s} of
+    // rotation_groups, a <- a + sum_j Rot(a, j s) with one shared key switch
     Ct rot_sum(Ct a) {
-        for (const auto &grp : rotation_groups(lay.R)) a = rotate_sum(c, *a, grp);
+        for (const auto &grp : rotation_groups(lay.R, radix)) a = rotate_sum(c, *a, grp);
         return a;
     }
     Ct bcast(Ct a) {     // sum_{i < R} Rot(a, -i): the first slot of each block over the block
-        for (const auto &grp : rotation_groups(lay.R)) {
+        for (const auto &grp : rotation_groups(lay.R, radix)) {
             std::vector<i64> neg;
             for (i64 r : grp) neg.push_back(-r);
             a = rotate_sum(c, *a, neg);
@@ -140,7 +143,7 @@ struct Stacked {
     Ct Xs;
     std::vector<Ct> Acol;
     Stacked(ckks_ctx &ctx, int R, int k_, const std::vector<const ckks_ct *> &x, const std::vector<const ckks_ct *> &Ain)
-        : c(ctx), lay(make_lay(R, k_)), C(ctx, lay), k(k_), J(x[0]->count) {
+        : c(ctx), lay(make_lay(R, k_)), C(ctx, lay, kFixedRadix), k(k_), J(x[0]->count) {
         Xs = stack(c, x);
         Acol.resize(k);
         for (int l = 0; l < k; ++l) {
@@ -260,7 +263,7 @@ Ct batch_front(ckks_ctx &c, int R, int k, const FixedOut &fx, const ckks_ct &S) 
     Layout lay;
     lay.R = R;
     lay.k = k;
-    Circ C(c, lay);
+    Circ C(c, lay, kBatchRadix);
     std::vector<Ct> E(k);
     for (int j = 0; j < k; ++j) {
         Ct pj = mul(c, *fx.r_s[j], S);
@@ -279,7 +282,7 @@ BatchOut batch_back(ckks_ctx &c, int R, int k, const FixedOut &fx, Ct sp) {
     Layout lay;
     lay.R = R;
     lay.k = k;
-    Circ C(c, lay);
+    Circ C(c, lay, kBatchRadix);
     BatchOut o;
     o.sp = std::move(sp);
     o.num = C.rot_sum(mul(c, *fx.u_s, *o.sp));

@@ -61,10 +61,15 @@ struct BatchOut {
 int circuit_levels(int kappa);
 int snp_depth(int kappa);
 Layout make_layout(int n_ring, int n, int k, int m);
-// rotations of the rotate-and-sum over R slots, by shared key switch: {s, 2s, 3s} for s = 1, 4, 16, ...
-// while 4s <= R, then {s} when log2 R is odd
-std::vector<std::vector<i64>> rotation_groups(int R);
-// Galois elements of the rotations of rotation_groups(R) in both directions, and conjugation
+// Rotations of the rotate-and-sum over R = 2^r slots, by shared key switch: {s, 2s, .., (m - 1) s} with
+// m = min(radix, R / s) for s = 1, then s times the previous m.  Radix 4 gives {s, 2s, 3s} for
+// s = 1, 4, 16, .. and a last {s} when r is odd.  The fixed part (few ciphertexts per call, key reads
+// dominate) uses radix 4; the per-SNP-batch part (many ciphertexts per call, ModUp and ModDown dominate)
+// uses radix 16, half as many key switches for R = 256.
+constexpr int kFixedRadix = 4, kBatchRadix = 16;
+std::vector<std::vector<i64>> rotation_groups(int R, int radix);
+// Galois elements of the rotations of rotation_groups(R, 4) and rotation_groups(R, 16) in both
+// directions (each once, in that order), then conjugation
 std::vector<u64> required_galois(int n, int R);
 void run_fixed(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckks_ct *> &x, const ckks_ct &y,
                const std::vector<const ckks_ct *> &A, int ds, FixedOut &fx, EncOutput &rep);

@@ -12,6 +12,8 @@
 // chain index of each limb (see ckks_internal.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ckks_internal.h"
 #include "modarith.h"
 
@@ -30,7 +32,7 @@ hipEvent_t KTimer::take() {
     return e;
 }
 
-int KTimer::begin(const char *name, double bytes, hipStream_t st) {
+int KTimer::begin(const char *name, double bytes, double flops, hipStream_t st) {
     if (!only.empty() && only != name) return -1;
     auto it = ids.find(name);
     int id;
@@ -43,7 +45,7 @@ int KTimer::begin(const char *name, double bytes, hipStream_t st) {
         id = it->second;
     }
     (void)st;
-    recs.push_back(Rec{id, take(), take(), bytes, false});
+    recs.push_back(Rec{id, take(), take(), bytes, flops, false});
     tl_timed_launch = &recs.back();   // the next launch on this thread fills its events
     return (int)recs.size() - 1;
 }
@@ -68,6 +70,7 @@ void KTimer::collect() {
         ++s.count;
         s.ms += ms;
         s.bytes += r.bytes;
+        s.flops += r.flops;
         spare.push_back(r.a);
         spare.push_back(r.b);
     }
@@ -270,9 +273,9 @@ struct KsAcc<CB, true> {
         for (int b = 0; b < CB; ++b) a0[b] = a1[b] = 0.0;
     }
     __device__ void mac(int b, u64 d, u64 k0, u64 k1, const ModInfo &M, const FMod &fm) {
-        const double dd = (double)d;   // a residue of this target
-        a0[b] += fmul_mod(dd, (double)k0, fm);
-        a1[b] += fmul_mod(dd, (double)k1, fm);
+        const double dd = u2d(d);   // a residue of this target (below 2^41)
+        a0[b] += fmul_mod(dd, u2d(k0), fm);
+        a1[b] += fmul_mod(dd, u2d(k1), fm);
     }
     __device__ void settle(const FMod &fm) {   // each term is below 0.6 q: keep the sums below 2^47
 #pragma unroll
@@ -311,7 +314,8 @@ struct KsAcc<CB, false> {
 };
 
 // one target word for CB ciphertexts.  MK > 0: exactly MK keys, their loads for one digit group issued
-// together (unrolled); MK == 0: keys.m keys in a loop.
+// together (unrolled); MK < 0: keys.m keys in chunks of -MK (the last chunk padded with zero words), the
+// loads of one (digit group, chunk) unit issued together; MK == 0: keys.m keys in a loop.
 template <int CB, int MK, bool FP>
 __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, const int *__restrict__ didx,
                                         const u64 *const (&own_row)[CB], const KsKeys &keys, const size_t (&kd)[MK > 0 ? MK : 1],
@@ -320,7 +324,50 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
     const FMod fm{M.qd, M.qinv};
     KsAcc<CB, FP> A;
     A.zero();
-    if constexpr (MK > 0) {
+    if constexpr (MK < 0) {
+        // units u = (digit group gb, key chunk kc), gb-major; the loads of unit u + 1 are issued before the
+        // products of unit u (double buffer).  A padded key contributes 0 x 0.
+        constexpr int KC = -MK;
+        const int m = keys.m, nkc = (m + KC - 1) / KC, nu = gl * nkc;
+        u64 kw0[2][KC], kw1[2][KC], dw[2][KC][CB];
+        auto load = [&](int u, int s) {
+            const int gb = u / nkc, kc = u - gb * nkc;
+            const int e = didx[gb * nt + tt];
+#pragma unroll
+            for (int i = 0; i < KC; ++i) {
+                const int ki = kc * KC + i;
+                const bool on = ki < m;
+                const u64 *key = keys.key[on ? ki : 0];
+                const u64 g = on ? keys.g[ki] : 0;
+                const size_t kdi = g ? automorph_src(k, log_n, g) : k;
+                kw0[s][i] = on ? key[(size_t)gb * key_grp + krow] : 0;
+                kw1[s][i] = on ? key[key_comp + (size_t)gb * key_grp + krow] : 0;
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    const u64 *src = e >= 0 ? digits + ((size_t)(c0 + b) * K + e) * n : own_row[b];
+                    dw[s][i][b] = (on && b < nb) ? src[kdi] : 0;
+                }
+            }
+        };
+        load(0, 0);
+        for (int u = 0; u < nu; u += 2) {
+            if (u + 1 < nu) load(u + 1, 1);
+#pragma unroll
+            for (int i = 0; i < KC; ++i)
+#pragma unroll
+                for (int b = 0; b < CB; ++b)
+                    if (b < nb) A.mac(b, dw[0][i][b], kw0[0][i], kw1[0][i], M, fm);
+            A.settle(fm);
+            if (u + 1 >= nu) break;
+            if (u + 2 < nu) load(u + 2, 0);
+#pragma unroll
+            for (int i = 0; i < KC; ++i)
+#pragma unroll
+                for (int b = 0; b < CB; ++b)
+                    if (b < nb) A.mac(b, dw[1][i][b], kw0[1][i], kw1[1][i], M, fm);
+            A.settle(fm);
+        }
+    } else if constexpr (MK > 0) {
         // the loads of digit group gb + 1 are issued before the products of group gb (double buffer)
         u64 kw0[2][MK], kw1[2][MK], dw[2][MK][CB];
         auto load = [&](int gb, int s) {
@@ -376,9 +423,37 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
         if (b < nb) A.store(b, acc + ((size_t)(c0 + b) * 2 * nt + tt) * n + k, (size_t)nt * n, M, fm);
 }
 
+// Rotation lines of the NTT domain.  The words of an aligned group of 64 share the low log_n - 5 bits of
+// their evaluation exponent e = 2 brev(k) + 1, and X -> X^g maps the group with exponent class E (odd, mod
+// 2^(log_n - 5)) onto the group with class E g.  Every odd class is +-5^t for one sign and one
+// t < T = N / 128, and a rotation by r slots (g = 5^r) moves t to t + r: the key words of output group
+// (sign, t) pair with the digit groups (sign, t + r_i).  When every r_i is a multiple of s, the groups
+// (sign, v + s u), u < T / s, form a line that the key switch never leaves.  KsLines hands each XCD whole
+// lines (or, for s < 4, one of P contiguous segments of a line) walked in order of u, so that the digit
+// groups read through the automorphisms of nearby output groups are the same and stay in the XCD's L2.
+struct KsLines {
+    int s = 0;        // shift unit (0: the position-range mapping)
+    int P = 1;        // segments per line
+    int seglen = 0;   // groups per segment
+    int spx = 0;      // segments per XCD
+};
+
+// group index (word index >> 6) of the class (sign, t): E = +-5^t mod 2^(log_n - 5), G = brev((E - 1) / 2)
+__device__ __forceinline__ unsigned rot_group(int sign, unsigned t, int log_n) {
+    const unsigned mask = (1u << (log_n - 5)) - 1;
+    unsigned e = 1, p = 5;
+    for (unsigned x = t; x; x >>= 1) {
+        if (x & 1) e = (e * p) & mask;
+        p = (p * p) & mask;
+    }
+    if (sign) e = (0u - e) & mask;
+    return __brev((e - 1) >> 1) >> (32 - (log_n - 6));
+}
+
 template <int CB, int MK>
 __global__ void __launch_bounds__(kEwThreads, 3) ks_inner(u64 *acc, const u64 *digits, int K, const int *__restrict__ didx, Gather own, KsKeys keys,
-                         int ng, size_t total, int log_n, int l, int levels, int alpha, int count, const ModInfo *mods) {
+                         int ng, size_t total, int log_n, int l, int levels, int alpha, int count, const ModInfo *mods,
+                         KsLines ln) {
     const size_t n = (size_t)1 << log_n;
     const int nt = l + alpha;                 // targets of this key switch
     const int nt_key = levels + 1 + alpha;    // targets of a key
@@ -395,15 +470,29 @@ __global__ void __launch_bounds__(kEwThreads, 3) ks_inner(u64 *acc, const u64 *d
     const int x = (int)(blockIdx.x & 7);
     const int pos0 = x * p8;
     const int npos = pos0 >= (int)chunks ? 0 : ((int)chunks - pos0 < p8 ? (int)chunks - pos0 : p8);
-    const size_t items_x = (size_t)npos * nt * groups;   // items of this XCD
+    // line mapping: 64-thread workgroups, one group of 64 words each; the slot of a workgroup on its XCD
+    // runs over (ciphertext group, position u along the segment, target, segment), fastest first
+    const size_t items_x = ln.s ? (size_t)ln.spx * ln.seglen * nt * groups : (size_t)npos * nt * groups;
     for (size_t b = blockIdx.x; b < total; b += gridDim.x) {
         const size_t sl = b >> 3;                          // slot of this workgroup on its XCD
         if (sl >= items_x) break;
         const int grp = (int)(sl % groups);
-        const size_t rest = sl / groups;
-        const int pos = pos0 + (int)(rest % npos);
-        const int tt = (int)(rest / npos);
-        const size_t k = ((size_t)pos << 8) + threadIdx.x;
+        size_t rest = sl / groups;
+        int tt;
+        size_t k;
+        if (ln.s) {
+            const int ui = (int)(rest % ln.seglen);
+            rest /= ln.seglen;
+            tt = (int)(rest % nt);
+            const int seg = (int)(rest / nt) * 8 + x;
+            const int line = seg / ln.P, part = seg % ln.P;
+            const unsigned t = (unsigned)(line % ln.s) + (unsigned)ln.s * (unsigned)(part * ln.seglen + ui);
+            k = ((size_t)rot_group(line / ln.s, t, log_n) << 6) + threadIdx.x;
+        } else {
+            const int pos = pos0 + (int)(rest % npos);
+            tt = (int)(rest / npos);
+            k = ((size_t)pos << 8) + threadIdx.x;
+        }
         const int chain = tt < l ? tt : levels + 1 + (tt - l);
         const ModInfo M = mods[chain];
         const size_t krow = (size_t)chain * n + k;   // key word of group b: key[b key_grp + krow]
@@ -427,27 +516,70 @@ __global__ void __launch_bounds__(kEwThreads, 3) ks_inner(u64 *acc, const u64 *d
                                    n, c0, nb, M);
     }
 }
+// The line mapping for a key set of two or more rotations (Galois elements 5^r mod 2N, or none); 0 when a
+// key is not a rotation (conjugation) or the ring is too small for 8 segments.
+static KsLines ks_lines(const KsKeys &keys, int log_n) {
+    KsLines ln;
+    if (keys.m < 2 || log_n < 9) return ln;
+    const int b = log_n - 5, T = 1 << (b - 2);
+    const u64 mask = (1ULL << b) - 1;
+    int s = T;
+    for (int i = 0; i < keys.m; ++i) {
+        if (!keys.g[i]) continue;
+        const u64 gb = keys.g[i] & mask;
+        int r = -1;
+        u64 p = 1;
+        for (int j = 0; j < T; ++j, p = (p * 5) & mask)
+            if (p == gb) {
+                r = j;
+                break;
+            }
+        if (r < 0) return ln;   // -5^r: not a rotation
+        if (r) s = std::min(s, r & -r);
+    }
+    ln.s = s;
+    ln.P = 2 * s >= 8 ? 1 : 8 / (2 * s);
+    ln.seglen = T / s / ln.P;
+    ln.spx = 2 * s * ln.P / 8;
+    if (ln.seglen < 1 || ln.spx < 1) return KsLines{};
+    return ln;
+}
+
 void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const int *didx, const Gather &own,
                 const KsKeys &keys, int ng, int count, int l, int levels, int alpha, hipStream_t st) {
     const int nt = l + alpha, gl = ks_groups(l, alpha);
     // algorithmic bytes: every key word and every digit word read once, the accumulators written once
     const int cb = count >= 4 ? 4 : (count >= 2 ? 2 : 1);   // 2 or 8 (fewer waves, or spills) measured slower
-    const int mk = (keys.m == 1 || keys.m == 3) ? keys.m : 0;
-    static const char *const names[3][3] = {{"ks_inner<1, 0>", "ks_inner<1, 1>", "ks_inner<1, 3>"},
-                                            {"ks_inner<2, 0>", "ks_inner<2, 1>", "ks_inner<2, 3>"},
-                                            {"ks_inner<4, 0>", "ks_inner<4, 1>", "ks_inner<4, 3>"}};
-    TScope ts_(t, names[cb == 4 ? 2 : cb - 1][mk == 3 ? 2 : mk],
-               8.0 * (double)t.n * (keys.m * 2.0 * gl * nt + (double)count * (gl * nt + 2.0 * nt)), st);
+    // exactly 1 or 3 keys unrolled; more than 3 in chunks of 3 (a fully unrolled 15-key form spilled or ran
+    // slower); 2 in the loop
+    const int mk = (keys.m == 1 || keys.m == 3) ? keys.m : (keys.m > 3 ? -3 : 0);
+    const int mi = mk == 0 ? 0 : (mk == 1 ? 1 : (mk == 3 ? 2 : 3));
+    static const char *const names[3][4] = {
+        {"ks_inner<1, 0>", "ks_inner<1, 1>", "ks_inner<1, 3>", "ks_inner<1, -3>"},
+        {"ks_inner<2, 0>", "ks_inner<2, 1>", "ks_inner<2, 3>", "ks_inner<2, -3>"},
+        {"ks_inner<4, 0>", "ks_inner<4, 1>", "ks_inner<4, 3>", "ks_inner<4, -3>"}};
+    // algorithmic FP64 operations: one multiply-accumulate per (ciphertext, target, word, digit group, key), each
+    // two modular products (a product and its FMA error 3, the quotient 2, the remainder 2, their sum 1) and
+    // two additions: 18
+    TScope ts_(t, names[cb == 4 ? 2 : cb - 1][mi],
+               8.0 * (double)t.n * (keys.m * 2.0 * gl * nt + (double)count * (gl * nt + 2.0 * nt)), st,
+               18.0 * (double)count * nt * (double)t.n * gl * keys.m);
     if (t.log_n < 8) throw Error(CKKS_E_INVALID_ARG, "key switching needs N >= 256");
     const size_t chunks = (size_t)1 << (t.log_n - 8);
     const size_t p8 = chunks >= 8 ? chunks / 8 : 1;
-    const size_t total = 8 * p8 * nt * (size_t)((count + cb - 1) / cb);   // workgroup items
+    const size_t ngrp = (size_t)((count + cb - 1) / cb);
+    const KsLines ln = ks_lines(keys, t.log_n);
+    const size_t total = ln.s ? 8 * (size_t)ln.spx * ln.seglen * nt * ngrp   // workgroup items
+                              : 8 * p8 * nt * ngrp;
     if (!count) return;
-    const dim3 grid((unsigned)(total < 65536 * 8 ? total : 65536 * 8)), block(kEwThreads);
+    const dim3 grid((unsigned)(total < 65536 * 8 ? total : 65536 * 8)), block(ln.s ? 64 : kEwThreads);
 #define GCK_KS(CB_, MK_) \
     gck_launch((ks_inner<CB_, MK_>), grid, block, 0, st, acc, digits, K, didx, own, keys, ng, total, t.log_n, \
-                       l, levels, alpha, count, t.mods)
+                       l, levels, alpha, count, t.mods, ln)
     switch (cb * 10 + mk) {
+    case 37: GCK_KS(4, -3); break;
+    case 17: GCK_KS(2, -3); break;
+    case 7: GCK_KS(1, -3); break;
     case 41: GCK_KS(4, 1); break;
     case 43: GCK_KS(4, 3); break;
     case 40: GCK_KS(4, 0); break;
@@ -459,6 +591,63 @@ void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const in
     default: GCK_KS(1, 0); break;
     }
 #undef GCK_KS
+    check_launch();
+}
+
+// z[c][j] = sum_i sigma_i(a[c][0][j]) mod q_j over the keys' automorphisms (NTT domain), a [count][2][l][N].
+// One 64-thread workgroup per (limb, group of 64 words), the groups walked along the rotation lines of the
+// key set (KsLines) so that the permuted reads of neighbouring workgroups share the XCD's L2.  The residues
+// are summed as integers (at most 16 terms below 2^60: below 2^64) and reduced once.
+__global__ void __launch_bounds__(64) aut_sum(u64 *z, const u64 *a, int l, KsKeys keys, int log_n, size_t total,
+                                              int n_limbs, KsLines ln, const ModInfo *mods) {
+    const size_t n = (size_t)1 << log_n;
+    const int x = (int)(blockIdx.x & 7);
+    const int groups = (int)(n >> 6);
+    for (size_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const size_t sl = b >> 3;
+        int lam;
+        unsigned grp;
+        if (ln.s) {
+            const int ui = (int)(sl % ln.seglen);
+            const size_t rest = sl / ln.seglen;
+            lam = (int)(rest % n_limbs);
+            const int seg = (int)(rest / n_limbs) * 8 + x;
+            if (seg >= 8 * ln.spx) break;
+            const int line = seg / ln.P, part = seg % ln.P;
+            const unsigned t = (unsigned)(line % ln.s) + (unsigned)ln.s * (unsigned)(part * ln.seglen + ui);
+            grp = rot_group(line / ln.s, t, log_n);
+        } else {
+            if (b >= (size_t)n_limbs * groups) break;
+            lam = (int)(b / groups);
+            grp = (unsigned)(b % groups);
+        }
+        const int c = lam / l, j = lam % l;
+        const u64 *src = a + ((size_t)c * 2 * l + j) * n;
+        const size_t k = ((size_t)grp << 6) + threadIdx.x;
+        u64 v[kMaxKeys];
+#pragma unroll
+        for (int i = 0; i < kMaxKeys; ++i) v[i] = i < keys.m ? src[automorph_src(k, log_n, keys.g[i])] : 0;
+        u64 sum = 0;
+#pragma unroll
+        for (int i = 0; i < kMaxKeys; ++i) sum += v[i];
+        const ModInfo M = mods[j];
+        if (M.fp) {
+            const FMod fm{M.qd, M.qinv};
+            z[(size_t)lam * n + k] = fcanon(u2d(sum), fm);
+        } else {
+            z[(size_t)lam * n + k] = reduce64(sum, M);
+        }
+    }
+}
+void k_aut_sum(const DevTables &t, u64 *z, const u64 *a, int count, int l, const KsKeys &keys, hipStream_t st) {
+    const int n_limbs = count * l;
+    TScope ts_(t, "aut_sum", 16.0 * (double)n_limbs * t.n, st);
+    if (!n_limbs) return;
+    const KsLines ln = ks_lines(keys, t.log_n);
+    const size_t groups = (size_t)t.n >> 6;
+    const size_t total = ln.s ? 8 * (size_t)ln.spx * ln.seglen * n_limbs : ((size_t)n_limbs * groups + 7) / 8 * 8;
+    const dim3 grid((unsigned)(total < 65536 * 8 ? total : 65536 * 8)), block(64);
+    gck_launch(aut_sum, grid, block, 0, st, z, a, l, keys, t.log_n, total, n_limbs, ln, t.mods);
     check_launch();
 }
 

@@ -53,11 +53,24 @@ __device__ __forceinline__ int chain_of(int lam, ModMap m) {
 // NTT-domain automorphism X -> X^g: word k of the result is word k2 of the input, where the evaluation
 // point of k2 is that of k raised to g, psi^(2 brev(k2) + 1) = (psi^(2 brev(k) + 1))^g.  The 64 words of
 // an aligned group of 64 map into one aligned group of 64 (only the top bits of brev(k) vary).
+// The exponents live modulo 2N: 32-bit arithmetic keeps their low bits exactly for log_n <= 30.
 __device__ __forceinline__ size_t automorph_src(size_t k, int log_n, u64 g) {
-    const u64 mask2n = (2ULL << log_n) - 1;
-    const u64 e = 2 * (u64)(__brev((unsigned)k) >> (32 - log_n)) + 1;
-    const u64 e2 = (e * g) & mask2n;
-    return __brev((unsigned)((e2 - 1) >> 1)) >> (32 - log_n);
+    const unsigned mask2n = (2u << log_n) - 1;
+    const unsigned e = 2 * (__brev((unsigned)k) >> (32 - log_n)) + 1;
+    const unsigned e2 = (e * (unsigned)g) & mask2n;
+    return __brev((e2 - 1) >> 1) >> (32 - log_n);
+}
+
+// exact conversions between integers below 2^52 and doubles through the bias 2^52 (the integer fills the
+// mantissa of 2^52 + x): one integer OR or AND and one FP64 add, where a general 64-bit conversion takes
+// several instructions
+__device__ __forceinline__ double u2d(u64 x) {
+#pragma clang fp contract(off)
+    return __longlong_as_double((long long)(x | 0x4330000000000000ULL)) - 4503599627370496.0;
+}
+__device__ __forceinline__ u64 d2u(double x) {   // x integer-valued in [0, 2^52)
+#pragma clang fp contract(off)
+    return (u64)__double_as_longlong(x + 4503599627370496.0) & 0xFFFFFFFFFFFFFULL;
 }
 
 // ---------------------------------------------------------------- FP64 arithmetic (q < 2^41)
@@ -92,7 +105,7 @@ __device__ __forceinline__ u64 fcanon(double x, FMod m) {
     double r = __builtin_fma(-qt, m.q, x);
     r = r < 0.0 ? r + m.q : r;
     r = r >= m.q ? r - m.q : r;
-    return (u64)r;
+    return d2u(r);
 }
 
 // ---------------------------------------------------------------- SplitMix64 (test-only randomness)
@@ -138,8 +151,11 @@ struct TScope {
     KTimer *t;
     int idx = -1;
     hipStream_t st;
-    TScope(const DevTables &tab, const char *name, double bytes, hipStream_t s) : t(tab.timer), st(s) {
-        if (t && t->on) idx = t->begin(name, bytes, st);
+    // bytes: algorithmic HBM bytes of the launch; flops: its algorithmic FP64 operations when the kernel is
+    // bound by arithmetic rather than memory (0 otherwise)
+    TScope(const DevTables &tab, const char *name, double bytes, hipStream_t s, double flops = 0)
+        : t(tab.timer), st(s) {
+        if (t && t->on) idx = t->begin(name, bytes, flops, st);
     }
     ~TScope() {
         if (idx >= 0) t->end(idx, st);

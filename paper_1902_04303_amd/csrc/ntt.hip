@@ -348,8 +348,9 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
 #pragma unroll
                 for (int e = 0; e < H; ++e) {
                     const u64 y = yb[e];
-                    const double a = split ? fred(fmul_mod((double)(y >> 32), M.c32_d, fm) + (double)(y & 0xFFFFFFFFULL), fm)
-                                           : (double)y;
+                    const double a = split ? fred(fmul_mod((double)(unsigned)(y >> 32), M.c32_d, fm) +
+                                                      (double)(unsigned)(y & 0xFFFFFFFFULL), fm)
+                                           : u2d(y);
                     xh[e] += fmul_mod(a, w, fm);
                 }
             };
@@ -396,7 +397,7 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
             for (int e = 0; e < kPer; ++e) f[e] = __longlong_as_double((long long)v[e]);
         } else if (mode == kPlain) {
 #pragma unroll
-            for (int e = 0; e < kPer; ++e) f[e] = (double)v[e];
+            for (int e = 0; e < kPer; ++e) f[e] = u2d(v[e]);
         } else {
             // any word x < 2^64 taken mod q as (x >> 32) (2^32 mod q) + (x mod 2^32); a centred source
             // residue above half its modulus also subtracts that modulus
@@ -404,7 +405,7 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
 #pragma unroll
             for (int e = 0; e < kPer; ++e) {
                 const u64 x = v[e];
-                double y = fmul_mod((double)(x >> 32), M.c32_d, fm) + (double)(x & 0xFFFFFFFFULL);
+                double y = fmul_mod((double)(unsigned)(x >> 32), M.c32_d, fm) + (double)(unsigned)(x & 0xFFFFFFFFULL);
                 if (mode == kCentred && x > src_half) y -= sq;
                 f[e] = fred(y, fm);
             }
@@ -463,7 +464,7 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
             const bool aut_self = xs && E.aut_self;
             if (M.fp) {
                 // FP64: |acc - t| < q, the product's remainder below 1.1 q, each added residue below q: the
-                // sum stays below 12 q for up to 8 automorphism terms, well inside the exact range (the
+                // sum stays below 20 q for up to 16 automorphism terms, well inside the exact range (the
                 // sums of two residues below 2^42 are exact as well)
                 const FMod fm{M.qd, M.qinv};
                 const double pd = E.pinv_d[chain];
@@ -483,15 +484,32 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
 #pragma unroll
                         for (int i = 0; i < AU; ++i) vp[i][j] = i < n_aut ? xs[automorph_src(w, g.log_n, E.g[i])] : 0;
                     }
+                    double r[EG];
+#pragma unroll
+                    for (int j = 0; j < EG; ++j) {
+                        r[j] = fmul_mod(u2d(va[j]) - u2d(vt[j]), pd, fm);
+                        r[j] += u2d(vd[j]) + u2d(vs[j]);
+#pragma unroll
+                        for (int i = 0; i < AU; ++i) r[j] += u2d(vp[i][j]);
+                    }
+                    // further automorphism terms AU at a time, the loads of a batch issued together
+                    for (int i0 = AU; i0 < n_aut; i0 += AU) {
+#pragma unroll
+                        for (int j = 0; j < EG; ++j) {
+                            const size_t w = base + slot_index<LOGM, 0, Ph<LOGM, 0>::R>(e0 + j, q);
+#pragma unroll
+                            for (int i = 0; i < AU; ++i)
+                                vp[i][j] = i0 + i < n_aut ? xs[automorph_src(w, g.log_n, E.g[i0 + i])] : 0;
+                        }
+#pragma unroll
+                        for (int j = 0; j < EG; ++j)
+#pragma unroll
+                            for (int i = 0; i < AU; ++i) r[j] += u2d(vp[i][j]);
+                    }
 #pragma unroll
                     for (int j = 0; j < EG; ++j) {
                         const size_t w = base + slot_index<LOGM, 0, Ph<LOGM, 0>::R>(e0 + j, q);
-                        double r = fmul_mod((double)va[j] - (double)vt[j], pd, fm);
-                        r += (double)vd[j] + (double)vs[j];
-#pragma unroll
-                        for (int i = 0; i < AU; ++i) r += (double)vp[i][j];
-                        for (int i = AU; i < n_aut; ++i) r += (double)xs[automorph_src(w, g.log_n, E.g[i])];
-                        a[w] = fcanon(r, fm);
+                        a[w] = fcanon(r[j], fm);
                     }
                 }
             } else {

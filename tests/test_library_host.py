@@ -50,15 +50,31 @@ def test_galois_elements_match_oracle(log_n, R):
     assert P.gwas_galois_elements(log_n, R) == G.required_galois(1 << log_n, R)
 
 
-def test_rotation_groups_cover_every_shift_once():
+@pytest.mark.parametrize("radix", [4, 16])
+def test_rotation_groups_cover_every_shift_once(radix):
     """The grouped rotate-and-sum adds Rot(a, i) for each i < R exactly once (both implementations'
-    group lists generate the same Galois elements, checked above)."""
+    group lists generate the same Galois elements, checked above): the sums of one shift per group,
+    taken with multiplicity, are 0..R-1 each once."""
     from oracle import gwas_circuit as G
-    for R in (2, 4, 8, 16, 32, 256, 2048):
-        sums = {0}
-        for grp in G.rotation_groups(R):
-            sums = {a + b for a in sums for b in [0] + grp}
-        assert sorted(sums) == list(range(R)), R
+    for R in (2, 4, 8, 16, 32, 64, 128, 256, 2048, 32768):
+        sums = [0]
+        groups = G.rotation_groups(R, radix)
+        for grp in groups:
+            assert 1 <= len(grp) <= radix - 1
+            sums = [a + b for a in sums for b in [0] + grp]
+        assert sorted(sums) == list(range(R)), (R, radix)
+        # key switches per rotate-and-sum: ceil(log2 R / log2 radix)
+        lr, lk = R.bit_length() - 1, radix.bit_length() - 1
+        assert len(groups) == -(-lr // lk), (R, radix)
+
+
+def test_rotation_groups_radix4_are_the_triples():
+    """Radix 4 groups two doubling steps of Alg. colSum: {s, 2s, 3s} for s = 1, 4, 16, .., then {s}."""
+    from oracle import gwas_circuit as G
+    assert G.rotation_groups(256, 4) == [[1, 2, 3], [4, 8, 12], [16, 32, 48], [64, 128, 192]]
+    assert G.rotation_groups(512, 4) == [[1, 2, 3], [4, 8, 12], [16, 32, 48], [64, 128, 192], [256]]
+    assert G.rotation_groups(256, 16) == [list(range(1, 16)), list(range(16, 256, 16))]
+    assert G.rotation_groups(8, 16) == [list(range(1, 8))]
 
 
 def test_bad_parameters_are_rejected():
