@@ -236,8 +236,8 @@ void k_mul(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs
 // out = a * c[chain]
 void k_mul_const(const DevTables &t, u64 *out, const u64 *a, int n_limbs, ModMap m, const ChainConst &c,
                  hipStream_t st);
-// ct data [count][2][l][N]: poly 0 limbs += c[chain]
-void k_add_const_c0(const DevTables &t, u64 *ct, int count, int l, const ChainConst &c, hipStream_t st);
+// ct data [count][2][l][N]: out = a with c[chain] added to the limbs of poly 0 (out may be a)
+void k_add_const_c0(const DevTables &t, u64 *out, const u64 *a, int count, int l, const ChainConst &c, hipStream_t st);
 // tensor of [count][2][l] ciphertexts into [count][3][l]; a / b read at ciphertext (c % na) / (c % nb)
 void k_tensor(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int count, int l, int na, int nb,
               bool accumulate, hipStream_t st);

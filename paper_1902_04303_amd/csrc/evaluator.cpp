@@ -250,9 +250,9 @@ Ct mul_int(ckks_ctx &c, const ckks_ct &a, i64 k) {
 Ct neg(ckks_ctx &c, const ckks_ct &a) { return mul_int(c, a, -1); }
 
 Ct add_const(ckks_ctx &c, const ckks_ct &a, double v) {
-    Ct r = clone(c, a);
+    Ct r = new_ct(c, a.count, a.depth, a.scale);
     i64 k = round_half_away(v * a.scale);
-    k_add_const_c0(c.tab, r->data.ptr, a.count, a.limbs, chain_const_of(c, k), c.stream);
+    k_add_const_c0(c.tab, r->data.ptr, a.data.ptr, a.count, a.limbs, chain_const_of(c, k), c.stream);
     ++c.n_launch;
     return r;
 }

@@ -70,9 +70,10 @@ struct Circ {
     int radix;   // rotate-and-sum groups: up to radix - 1 rotations per key switch
     Circ(ckks_ctx &cc, const Layout &l, int rdx) : c(cc), lay(l), radix(rdx) {}
 
-    // a at depth d and the canonical scale; factor multiplies the value
+    // a at depth d and the canonical scale; factor multiplies the value.  Already there: a view of a (no
+    // copy; valid while a lives, and only read)
     Ct at(const ckks_ct &a, int d, double factor = 1.0) {
-        if (d == a.depth && factor == 1.0) return clone(c, a);
+        if (d == a.depth && factor == 1.0) return view(a, 0, a.count);
         return align(c, a, d, c.p.scales[d], factor);
     }
     // sum_{i < R} Rot(a, i) (Alg. colSum / Alg. DotProd): per group {s, 2s, .., (m - 1) s} of
@@ -196,9 +197,14 @@ void fixed_front(ckks_ctx &c, int R, int k, const std::vector<const ckks_ct *> &
     fx.r_s.resize(k);
     fx.x_c.resize(k);
     for (int j = 0; j < k; ++j) {
-        fx.r_s[j] = clone(c, *view(*RRs, j * J, J));
-        fx.x_c[j] = clone(c, *view(*Xc, j * J, J));
+        fx.r_s[j] = view(*RRs, j * J, J);
+        fx.x_c[j] = view(*Xc, j * J, J);
     }
+    // RRs and Xc may themselves be views of RR and the stacked x (at() does not copy)
+    fx.hold.push_back(std::move(RRs));
+    fx.hold.push_back(std::move(Xc));
+    fx.hold.push_back(std::move(RR));
+    fx.hold.push_back(std::move(st.Xs));
 }
 
 void fixed_back(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckks_ct *> &x, const ckks_ct &y,
@@ -242,7 +248,7 @@ void fixed_back(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ck
     Ct u = mul(c, *C.at(*w, z_proj->depth), *z_proj);
     // ---- what the per-batch part needs, at the depths it uses them
     for (int j = 0; j < k; ++j) rep.beta.push_back(clone(c, *view(*beta, j * J, J)));
-    fx.u_s = C.at(*u, ds + 3);
+    fx.u_s = C.at(*u, ds + 3);   // may be views of u and w, which rep owns from here on
     fx.w_s = C.at(*w, ds + 3);
     rep.w = std::move(w);
     rep.w_inv = std::move(w_inv);
@@ -356,8 +362,8 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
         std::vector<Ct> sps;
         for (int b0 = 0; b0 < nb; b0 += chunk) {
             const int cnt = std::min(chunk, nb - b0);
-            Ct S = new_ct(c, cnt, ds, in.S->scale);
-            fetch_snp(c, in, b0, cnt, *S, 0, c.stream);
+            // the batches are device-resident here (no spill): the chunk is a view, read only
+            Ct S = view(*in.S, b0, cnt);
             sps.push_back(batch_front(c, lay.R, k, fx, *S));
         }
         stream_wait(c.stream, c.aux_stream);   // u and w

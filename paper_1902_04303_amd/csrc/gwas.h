@@ -53,6 +53,7 @@ struct FixedOut {
     std::vector<Ct> r_s;   // r_j = (X A)_{:, j} at the SNP depth
     std::vector<Ct> x_c;   // x_j at the SNP depth + 2
     Ct u_s, w_s;           // u = w z' and w at the SNP depth + 3
+    std::vector<Ct> hold;  // batches that r_s and x_c may be views of
 };
 struct BatchOut {
     Ct sp, num, de, dodd;

@@ -160,23 +160,22 @@ void k_mul_const(const DevTables &t, u64 *out, const u64 *a, int n_limbs, ModMap
     check_launch();
 }
 
-// a constant polynomial c evaluates to c at every NTT point
-__global__ void ew_add_const_c0(u64 *ct, size_t total, int log_n, int l, const ModInfo *mods, ChainConst c) {
-    // total = count * l * N words of poly 0
+// a constant polynomial c evaluates to c at every NTT point: out = a + (c, 0), every word written once
+__global__ void ew_add_const_c0(u64 *out, const u64 *a, size_t total, int log_n, int l, const ModInfo *mods,
+                                ChainConst c) {
+    // total = count * 2 * l * N words
     const size_t n = (size_t)1 << log_n;
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
-        int lam = (int)(idx >> log_n);        // over count * l
-        int ci = lam / l, i = lam % l;
-        size_t k = idx & (n - 1);
-        size_t off = ((size_t)ci * 2 * l + i) * n + k;
-        ct[off] = add_mod(ct[off], c.v[i], mods[i].q);
+        const int lam = (int)(idx >> log_n);   // over count * 2 * l
+        const int row = lam % (2 * l);
+        out[idx] = row < l ? add_mod(a[idx], c.v[row], mods[row].q) : a[idx];
     }
 }
-void k_add_const_c0(const DevTables &t, u64 *ct, int count, int l, const ChainConst &c, hipStream_t st) {
-    TScope ts_(t, "ew_add_const_c0", 16.0 * (double)((size_t)count * l) * t.n, st);
-    size_t total = ((size_t)count * l) << t.log_n;
+void k_add_const_c0(const DevTables &t, u64 *out, const u64 *a, int count, int l, const ChainConst &c, hipStream_t st) {
+    TScope ts_(t, "ew_add_const_c0", 16.0 * (double)((size_t)count * 2 * l) * t.n, st);
+    size_t total = ((size_t)count * 2 * l) << t.log_n;
     if (!total) return;
-    gck_launch(ew_add_const_c0, ew_grid(total), dim3(kEwThreads), 0, st, ct, total, t.log_n, l, t.mods, c);
+    gck_launch(ew_add_const_c0, ew_grid(total), dim3(kEwThreads), 0, st, out, a, total, t.log_n, l, t.mods, c);
     check_launch();
 }
 
