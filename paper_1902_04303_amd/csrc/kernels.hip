@@ -314,8 +314,10 @@ struct KsAcc<CB, false> {
 
 // one target word for CB ciphertexts.  MK > 0: exactly MK keys, their loads for one digit group issued
 // together (unrolled); MK < 0: keys.m keys in chunks of -MK (the last chunk padded with zero words), the
-// loads of one (digit group, chunk) unit issued together; MK == 0: keys.m keys in a loop.
-template <int CB, int MK, bool FP>
+// loads of one (digit group, chunk) unit issued together; MK == 0: keys.m keys in a loop.  FULL: (MK < 0)
+// keys.m a multiple of the chunk, and absent ciphertexts (b >= nb) repeat the last present one (computed,
+// not stored), so that no load or product is guarded.
+template <int CB, int MK, bool FP, bool FULL>
 __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, const int *__restrict__ didx,
                                         const u64 *const (&own_row)[CB], const KsKeys &keys, const size_t (&kd)[MK > 0 ? MK : 1],
                                         int gl, int nt, int tt, size_t k, size_t krow, size_t key_grp, size_t key_comp,
@@ -335,7 +337,7 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
 #pragma unroll
             for (int i = 0; i < KC; ++i) {
                 const int ki = kc * KC + i;
-                const bool on = ki < m;
+                const bool on = FULL || ki < m;
                 const u64 *key = keys.key[on ? ki : 0];
                 const u64 g = on ? keys.g[ki] : 0;
                 const size_t kdi = g ? automorph_src(k, log_n, g) : k;
@@ -343,8 +345,9 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
                 kw1[s][i] = on ? key[key_comp + (size_t)gb * key_grp + krow] : 0;
 #pragma unroll
                 for (int b = 0; b < CB; ++b) {
-                    const u64 *src = e >= 0 ? digits + ((size_t)(c0 + b) * K + e) * n : own_row[b];
-                    dw[s][i][b] = (on && b < nb) ? src[kdi] : 0;
+                    const int bb = FULL && b >= nb ? nb - 1 : b;
+                    const u64 *src = e >= 0 ? digits + ((size_t)(c0 + bb) * K + e) * n : own_row[bb];
+                    dw[s][i][b] = (on && (FULL || b < nb)) ? src[kdi] : 0;
                 }
             }
         };
@@ -355,7 +358,7 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
             for (int i = 0; i < KC; ++i)
 #pragma unroll
                 for (int b = 0; b < CB; ++b)
-                    if (b < nb) A.mac(b, dw[0][i][b], kw0[0][i], kw1[0][i], M, fm);
+                    if (FULL || b < nb) A.mac(b, dw[0][i][b], kw0[0][i], kw1[0][i], M, fm);
             A.settle(fm);
             if (u + 1 >= nu) break;
             if (u + 2 < nu) load(u + 2, 0);
@@ -363,7 +366,7 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
             for (int i = 0; i < KC; ++i)
 #pragma unroll
                 for (int b = 0; b < CB; ++b)
-                    if (b < nb) A.mac(b, dw[1][i][b], kw0[1][i], kw1[1][i], M, fm);
+                    if (FULL || b < nb) A.mac(b, dw[1][i][b], kw0[1][i], kw1[1][i], M, fm);
             A.settle(fm);
         }
     } else if constexpr (MK > 0) {
@@ -377,8 +380,9 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
                 kw1[s][i] = keys.key[i][key_comp + (size_t)gb * key_grp + krow];
 #pragma unroll
                 for (int b = 0; b < CB; ++b) {
-                    const u64 *src = e >= 0 ? digits + ((size_t)(c0 + b) * K + e) * n : own_row[b];
-                    dw[s][i][b] = b < nb ? src[kd[i]] : 0;
+                    const int bb = FULL && b >= nb ? nb - 1 : b;
+                    const u64 *src = e >= 0 ? digits + ((size_t)(c0 + bb) * K + e) * n : own_row[bb];
+                    dw[s][i][b] = (FULL || b < nb) ? src[kd[i]] : 0;
                 }
             }
         };
@@ -389,7 +393,7 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
             for (int i = 0; i < MK; ++i)
 #pragma unroll
                 for (int b = 0; b < CB; ++b)
-                    if (b < nb) A.mac(b, dw[0][i][b], kw0[0][i], kw1[0][i], M, fm);
+                    if (FULL || b < nb) A.mac(b, dw[0][i][b], kw0[0][i], kw1[0][i], M, fm);
             A.settle(fm);
             if (gb + 1 >= gl) break;
             if (gb + 2 < gl) load(gb + 2, 0);
@@ -397,7 +401,7 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
             for (int i = 0; i < MK; ++i)
 #pragma unroll
                 for (int b = 0; b < CB; ++b)
-                    if (b < nb) A.mac(b, dw[1][i][b], kw0[1][i], kw1[1][i], M, fm);
+                    if (FULL || b < nb) A.mac(b, dw[1][i][b], kw0[1][i], kw1[1][i], M, fm);
             A.settle(fm);
         }
     } else {
@@ -405,14 +409,17 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
             const int e = didx[gb * nt + tt];
             const u64 *src[CB];
 #pragma unroll
-            for (int b = 0; b < CB; ++b) src[b] = e >= 0 ? digits + ((size_t)(c0 + b) * K + e) * n : own_row[b];
+            for (int b = 0; b < CB; ++b) {
+                const int bb = FULL && b >= nb ? nb - 1 : b;
+                src[b] = e >= 0 ? digits + ((size_t)(c0 + bb) * K + e) * n : own_row[bb];
+            }
             for (int i = 0; i < keys.m; ++i) {
                 const size_t kdi = keys.g[i] ? automorph_src(k, log_n, keys.g[i]) : k;
                 const u64 k0 = keys.key[i][(size_t)gb * key_grp + krow];
                 const u64 k1 = keys.key[i][key_comp + (size_t)gb * key_grp + krow];
 #pragma unroll
                 for (int b = 0; b < CB; ++b)
-                    if (b < nb) A.mac(b, src[b][kdi], k0, k1, M, fm);
+                    if (FULL || b < nb) A.mac(b, src[b][kdi], k0, k1, M, fm);
             }
             A.settle(fm);
         }
@@ -449,10 +456,10 @@ __device__ __forceinline__ unsigned rot_group(int sign, unsigned t, int log_n) {
     return __brev((e - 1) >> 1) >> (32 - (log_n - 6));
 }
 
-template <int CB, int MK>
+template <int CB, int MK, bool FULL>
 __global__ void __launch_bounds__(kEwThreads, 3) ks_inner(u64 *acc, const u64 *digits, int K, const int *__restrict__ didx, Gather own, KsKeys keys,
-                         int ng, size_t total, int log_n, int l, int levels, int alpha, int count, const ModInfo *mods,
-                         KsLines ln) {
+                         int ng, size_t total, int log_n, int l, int levels, int alpha, int c_first, int count,
+                         const ModInfo *mods, KsLines ln) {
     const size_t n = (size_t)1 << log_n;
     const int nt = l + alpha;                 // targets of this key switch
     const int nt_key = levels + 1 + alpha;    // targets of a key
@@ -495,8 +502,8 @@ __global__ void __launch_bounds__(kEwThreads, 3) ks_inner(u64 *acc, const u64 *d
         const int chain = tt < l ? tt : levels + 1 + (tt - l);
         const ModInfo M = mods[chain];
         const size_t krow = (size_t)chain * n + k;   // key word of group b: key[b key_grp + krow]
-        const int c0 = grp * CB;
-        const int nb = count - c0 < CB ? count - c0 : CB;
+        const int c0 = c_first + grp * CB;   // ciphertexts [c_first, c_first + count) in this launch
+        const int nb = c_first + count - c0 < CB ? c_first + count - c0 : CB;
         // the input limb tt of each ciphertext (the digit of tt's own group), when tt is a q-target
         const u64 *own_row[CB];
 #pragma unroll
@@ -508,11 +515,11 @@ __global__ void __launch_bounds__(kEwThreads, 3) ks_inner(u64 *acc, const u64 *d
 #pragma unroll
         for (int i = 0; i < (MK > 0 ? MK : 1); ++i) kd[i] = (MK > 0 && keys.g[i]) ? automorph_src(k, log_n, keys.g[i]) : k;
         if (M.fp)
-            ks_word<CB, MK, true>(acc, digits, K, didx, own_row, keys, kd, gl, nt, tt, k, krow, key_grp, key_comp, log_n, n,
-                                  c0, nb, M);
+            ks_word<CB, MK, true, FULL>(acc, digits, K, didx, own_row, keys, kd, gl, nt, tt, k, krow, key_grp, key_comp,
+                                        log_n, n, c0, nb, M);
         else
-            ks_word<CB, MK, false>(acc, digits, K, didx, own_row, keys, kd, gl, nt, tt, k, krow, key_grp, key_comp, log_n,
-                                   n, c0, nb, M);
+            ks_word<CB, MK, false, FULL>(acc, digits, K, didx, own_row, keys, kd, gl, nt, tt, k, krow, key_grp, key_comp,
+                                         log_n, n, c0, nb, M);
     }
 }
 // The line mapping for a key set of two or more rotations (Galois elements 5^r mod 2N, or none); 0 when a
@@ -553,44 +560,56 @@ void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const in
     // slower); 2 in the loop
     const int mk = (keys.m == 1 || keys.m == 3) ? keys.m : (keys.m > 3 ? -3 : 0);
     const int mi = mk == 0 ? 0 : (mk == 1 ? 1 : (mk == 3 ? 2 : 3));
-    static const char *const names[3][4] = {
-        {"ks_inner<1, 0>", "ks_inner<1, 1>", "ks_inner<1, 3>", "ks_inner<1, -3>"},
-        {"ks_inner<2, 0>", "ks_inner<2, 1>", "ks_inner<2, 3>", "ks_inner<2, -3>"},
-        {"ks_inner<4, 0>", "ks_inner<4, 1>", "ks_inner<4, 3>", "ks_inner<4, -3>"}};
-    // algorithmic FP64 operations: one multiply-accumulate per (ciphertext, target, word, digit group, key), each
-    // two modular products (a product and its FMA error 3, the quotient 2, the remainder 2, their sum 1) and
-    // two additions: 18
-    TScope ts_(t, names[cb == 4 ? 2 : cb - 1][mi],
-               8.0 * (double)t.n * (keys.m * 2.0 * gl * nt + (double)count * (gl * nt + 2.0 * nt)), st,
-               18.0 * (double)count * nt * (double)t.n * gl * keys.m);
+    static const char *const names[2][3][4] = {
+        {{"ks_inner<1, 0, false>", "ks_inner<1, 1, false>", "ks_inner<1, 3, false>", "ks_inner<1, -3, false>"},
+         {"ks_inner<2, 0, false>", "ks_inner<2, 1, false>", "ks_inner<2, 3, false>", "ks_inner<2, -3, false>"},
+         {"ks_inner<4, 0, false>", "ks_inner<4, 1, false>", "ks_inner<4, 3, false>", "ks_inner<4, -3, false>"}},
+        {{"ks_inner<1, 0, true>", "ks_inner<1, 1, true>", "ks_inner<1, 3, true>", "ks_inner<1, -3, true>"},
+         {"ks_inner<2, 0, true>", "ks_inner<2, 1, true>", "ks_inner<2, 3, true>", "ks_inner<2, -3, true>"},
+         {"ks_inner<4, 0, true>", "ks_inner<4, 1, true>", "ks_inner<4, 3, true>", "ks_inner<4, -3, true>"}}};
     if (t.log_n < 8) throw Error(CKKS_E_INVALID_ARG, "key switching needs N >= 256");
+    if (!count) return;
     const size_t chunks = (size_t)1 << (t.log_n - 8);
     const size_t p8 = chunks >= 8 ? chunks / 8 : 1;
-    const size_t ngrp = (size_t)((count + cb - 1) / cb);
     const KsLines ln = ks_lines(keys, t.log_n);
-    const size_t total = ln.s ? 8 * (size_t)ln.spx * ln.seglen * nt * ngrp   // workgroup items
-                              : 8 * p8 * nt * ngrp;
-    if (!count) return;
-    const dim3 grid((unsigned)(total < 65536 * 8 ? total : 65536 * 8)), block(ln.s ? 64 : kEwThreads);
-#define GCK_KS(CB_, MK_) \
-    gck_launch((ks_inner<CB_, MK_>), grid, block, 0, st, acc, digits, K, didx, own, keys, ng, total, t.log_n, \
-                       l, levels, alpha, count, t.mods, ln)
-    switch (cb * 10 + mk) {
-    case 37: GCK_KS(4, -3); break;
-    case 17: GCK_KS(2, -3); break;
-    case 7: GCK_KS(1, -3); break;
-    case 41: GCK_KS(4, 1); break;
-    case 43: GCK_KS(4, 3); break;
-    case 40: GCK_KS(4, 0); break;
-    case 21: GCK_KS(2, 1); break;
-    case 23: GCK_KS(2, 3); break;
-    case 20: GCK_KS(2, 0); break;
-    case 11: GCK_KS(1, 1); break;
-    case 13: GCK_KS(1, 3); break;
-    default: GCK_KS(1, 0); break;
-    }
+    // the guard-free form (a ragged last ciphertext group padded) for one key and for key counts that fill
+    // their chunks of 3: 140 to 127 us and 709 to 562 us per launch at the 42-batch chunk; with exactly 3 keys
+    // it spills and was not faster, so that form keeps its guards
+    const bool keys_fill = mk == 1 || (mk < 0 && keys.m % 3 == 0);
+    auto launch = [&](bool full, int c_first, int cnt) {
+        // algorithmic FP64 operations: one multiply-accumulate per (ciphertext, target, word, digit group, key),
+        // each two modular products (a product and its FMA error 3, the quotient 2, the remainder 2, their sum
+        // 1) and two additions: 18
+        TScope ts_(t, names[full ? 1 : 0][cb == 4 ? 2 : cb - 1][mi],
+                   8.0 * (double)t.n * (keys.m * 2.0 * gl * nt * cnt / count + (double)cnt * (gl * nt + 2.0 * nt)), st,
+                   18.0 * (double)cnt * nt * (double)t.n * gl * keys.m);
+        const size_t ngrp = (size_t)((cnt + cb - 1) / cb);
+        const size_t total = ln.s ? 8 * (size_t)ln.spx * ln.seglen * nt * ngrp   // workgroup items
+                                  : 8 * p8 * nt * ngrp;
+        const dim3 grid((unsigned)(total < 65536 * 8 ? total : 65536 * 8)), block(ln.s ? 64 : kEwThreads);
+#define GCK_KS(CB_, MK_)                                                                                              \
+    (full ? gck_launch((ks_inner<CB_, MK_, true>), grid, block, 0, st, acc, digits, K, didx, own, keys, ng, total,     \
+                       t.log_n, l, levels, alpha, c_first, cnt, t.mods, ln)                                            \
+          : gck_launch((ks_inner<CB_, MK_, false>), grid, block, 0, st, acc, digits, K, didx, own, keys, ng, total,    \
+                       t.log_n, l, levels, alpha, c_first, cnt, t.mods, ln))
+        switch (cb * 10 + mk) {
+        case 37: GCK_KS(4, -3); break;
+        case 17: GCK_KS(2, -3); break;
+        case 7: GCK_KS(1, -3); break;
+        case 41: GCK_KS(4, 1); break;
+        case 43: GCK_KS(4, 3); break;
+        case 40: GCK_KS(4, 0); break;
+        case 21: GCK_KS(2, 1); break;
+        case 23: GCK_KS(2, 3); break;
+        case 20: GCK_KS(2, 0); break;
+        case 11: GCK_KS(1, 1); break;
+        case 13: GCK_KS(1, 3); break;
+        default: GCK_KS(1, 0); break;
+        }
+        check_launch();
+    };
+    launch(keys_fill, 0, count);
 #undef GCK_KS
-    check_launch();
 }
 
 // z[c][j] = sum_i sigma_i(a[c][0][j]) mod q_j over the keys' automorphisms (NTT domain), a [count][2][l][N].
