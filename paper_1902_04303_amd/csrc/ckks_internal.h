@@ -208,9 +208,10 @@ inline Gather gather_plain(const u64 *p) { return Gather{p, 1, 1, 0, 0, kPlain, 
 // rows lam / rowlen that are even, the first polynomial of each ciphertext); pinv[chain], pinv_sh[chain]
 // and pinv_d[chain] (device) hold P^-1 modulo each chain modulus, with Shoup companions and as doubles.
 // aut (may be null) is a ciphertext batch laid out like the output, [count][2][rowlen][N]: even rows add
-// aut_self * aut[lam][k] +
+// self * aut[lam][k] +
 // sum_i aut[lam][k_i] with k_i the source word of the NTT-domain automorphism X -> X^g[i], odd rows add
-// aut_self * aut[lam][k] (rotate-and-sum: a + sum_i sigma_i(a c0); a single Galois map: sigma(a c0)).
+// self * aut[lam][k] (rotate-and-sum: a + sum_i sigma_i(a c0); a single Galois map: sigma(a c0)); self is
+// aut_self on odd rows and (aut_self == 1) on even rows.
 constexpr int kMaxKeys = 16;
 struct ModDownEpi {
     Gather acc, add;
@@ -260,8 +261,8 @@ struct KsKeys {
 // [2][ng][L + 1 + alpha][N] in NTT and Montgomery form (times 2^64); digits hold K limbs per ciphertext.
 void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const int *didx, const Gather &own,
                 const KsKeys &keys, int ng, int count, int l, int levels, int alpha, hipStream_t st);
-// z[c][j] = sum_i sigma_i(a[c][0][j]) mod q_j (NTT domain) for the keys' automorphisms (any Galois maps,
-// up to kMaxKeys), a [count][2][l][N] and z [count][l][N]
+// z[c][j] = a[c][0][j] + sum_i sigma_i(a[c][0][j]) mod q_j (NTT domain) for the keys' automorphisms (any
+// Galois maps, up to kMaxKeys), a [count][2][l][N] and z [count][l][N]
 void k_aut_sum(const DevTables &t, u64 *z, const u64 *a, int count, int l, const KsKeys &keys, hipStream_t st);
 // samplers of the test-only SplitMix64 streams
 void k_sample_uniform(const DevTables &t, u64 *out, u64 seed, u64 sid, int n_limbs, ModMap m, int mi_of_p,

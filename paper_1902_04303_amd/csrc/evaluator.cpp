@@ -357,7 +357,7 @@ static const u64 *key_of(const ckks_ctx &c, u64 id) {
 // plus the gathered `add` term (on every row, or on the first polynomial of each ciphertext when
 // add_even).  Output [count][2][l][N] in NTT form.
 static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, const KsKeys &keys, const Gather &add,
-                      bool add_even, const u64 *aut = nullptr, bool aut_self = false, bool aut_gather = true) {
+                      bool add_even, const u64 *aut = nullptr, int aut_self = 0, bool aut_gather = true) {
     const size_t N = (size_t)c.p.n;
     const ckks_ctx::KsLevel &kl = c.ks_levels.at(l);
     const int a = c.p.alpha, nt = l + a, P = c.p.p_index();
@@ -376,7 +376,7 @@ static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, const KsKe
                     c.down_scale, a);
     DBuf out(c.pool.get(), (size_t)rows * l * N);
     ModDownEpi epi{Gather{acc.ptr, l, nt, 0, 1, kPlain, 0}, add, add_even ? 1 : 0, l, c.p_inv_dev, c.p_inv_sh_dev,
-                   c.p_inv_d_dev, aut, aut_self ? 1 : 0, aut && aut_gather ? keys.m : 0, {}};
+                   c.p_inv_d_dev, aut, aut_self, aut && aut_gather ? keys.m : 0, {}};
     for (int i = 0; i < keys.m; ++i) epi.g[i] = keys.g[i];
     k_ntt_forward_g(c.tab, out.ptr, Gather{ap.ptr, 1, 1, 0, 0, kConv, 0, c.down_conv, l, a}, rows * l, map_q(l),
                     c.stream, &epi);
@@ -482,8 +482,9 @@ Ct rotate_sum(ckks_ctx &c, const ckks_ct &a, const std::vector<i64> &rots) {
     } else {
         DBuf z(c.pool.get(), (size_t)a.count * l * c.p.n);
         k_aut_sum(c.tab, z.ptr, a.data.ptr, a.count, l, keys, c.stream);
+        // z = c0 + sum_i sigma_i(c0) on the even rows; the odd rows add c1 itself
         ks = keyswitch(c, Gather{a.data.ptr, l, 2 * l, l, 1, kPlain, 0}, a.count, l, keys,
-                       Gather{z.ptr, 2 * l, l, 0, 1, kPlain, 0}, true, a.data.ptr, true, false);
+                       Gather{z.ptr, 2 * l, l, 0, 1, kPlain, 0}, true, a.data.ptr, 2, false);
     }
     Ct r(new ckks_ct());
     r->ctx = &c;

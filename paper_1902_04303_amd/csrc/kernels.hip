@@ -612,48 +612,57 @@ void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const in
 #undef GCK_KS
 }
 
-// z[c][j] = sum_i sigma_i(a[c][0][j]) mod q_j over the keys' automorphisms (NTT domain), a [count][2][l][N].
-// One 64-thread workgroup per (limb, group of 64 words), the groups walked along the rotation lines of the
-// key set (KsLines) so that the permuted reads of neighbouring workgroups share the XCD's L2.  The residues
-// are summed as integers (at most 16 terms below 2^60: below 2^64) and reduced once.
-__global__ void __launch_bounds__(64) aut_sum(u64 *z, const u64 *a, int l, KsKeys keys, int log_n, size_t total,
-                                              int n_limbs, KsLines ln, const ModInfo *mods) {
+// z[c][j] = a[c][0][j] + sum_i sigma_i(a[c][0][j]) mod q_j over the keys' automorphisms (NTT domain), a
+// [count][2][l][N].  A 256-thread workgroup takes 4 groups of 64 words of one limb, consecutive along a
+// rotation line of the key set (KsLines), so that the permuted reads of neighbouring workgroups share the
+// XCD's L2 (the word itself is among them).  Residues below 2^41 are summed as integers (at most 17 terms,
+// below 2^46) and reduced once; the 60-bit q_0 adds modulo q_0 term by term.
+__global__ void __launch_bounds__(256) aut_sum(u64 *z, const u64 *a, int l, KsKeys keys, int log_n, size_t total,
+                                               int n_limbs, KsLines ln, const ModInfo *mods) {
     const size_t n = (size_t)1 << log_n;
     const int x = (int)(blockIdx.x & 7);
-    const int groups = (int)(n >> 6);
+    const int groups = (int)(n >> 6), wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int steps = ln.s ? (ln.seglen + 3) / 4 : (groups + 3) / 4;   // workgroups along a segment / limb
     for (size_t b = blockIdx.x; b < total; b += gridDim.x) {
         const size_t sl = b >> 3;
-        int lam;
+        int lam, ui;
         unsigned grp;
         if (ln.s) {
-            const int ui = (int)(sl % ln.seglen);
-            const size_t rest = sl / ln.seglen;
+            ui = (int)(sl % steps) * 4 + wave;
+            const size_t rest = sl / steps;
             lam = (int)(rest % n_limbs);
             const int seg = (int)(rest / n_limbs) * 8 + x;
             if (seg >= 8 * ln.spx) break;
+            if (ui >= ln.seglen) continue;
             const int line = seg / ln.P, part = seg % ln.P;
             const unsigned t = (unsigned)(line % ln.s) + (unsigned)ln.s * (unsigned)(part * ln.seglen + ui);
             grp = rot_group(line / ln.s, t, log_n);
         } else {
-            if (b >= (size_t)n_limbs * groups) break;
-            lam = (int)(b / groups);
-            grp = (unsigned)(b % groups);
+            const size_t item = b;   // (limb, step) in order
+            if (item >= (size_t)n_limbs * steps) break;
+            lam = (int)(item / steps);
+            ui = (int)(item % steps) * 4 + wave;
+            if (ui >= groups) continue;
+            grp = (unsigned)ui;
         }
         const int c = lam / l, j = lam % l;
         const u64 *src = a + ((size_t)c * 2 * l + j) * n;
-        const size_t k = ((size_t)grp << 6) + threadIdx.x;
+        const size_t k = ((size_t)grp << 6) + lane;
         u64 v[kMaxKeys];
 #pragma unroll
         for (int i = 0; i < kMaxKeys; ++i) v[i] = i < keys.m ? src[automorph_src(k, log_n, keys.g[i])] : 0;
-        u64 sum = 0;
-#pragma unroll
-        for (int i = 0; i < kMaxKeys; ++i) sum += v[i];
+        const u64 self = src[k];
         const ModInfo M = mods[j];
         if (M.fp) {
-            const FMod fm{M.qd, M.qinv};
-            z[(size_t)lam * n + k] = fcanon(u2d(sum), fm);
+            u64 sum = self;
+#pragma unroll
+            for (int i = 0; i < kMaxKeys; ++i) sum += v[i];
+            z[(size_t)lam * n + k] = fcanon(u2d(sum), FMod{M.qd, M.qinv});
         } else {
-            z[(size_t)lam * n + k] = reduce64(sum, M);
+            u64 r = self;
+#pragma unroll
+            for (int i = 0; i < kMaxKeys; ++i) r = add_mod(r, v[i], M.q);
+            z[(size_t)lam * n + k] = r;
         }
     }
 }
@@ -663,8 +672,9 @@ void k_aut_sum(const DevTables &t, u64 *z, const u64 *a, int count, int l, const
     if (!n_limbs) return;
     const KsLines ln = ks_lines(keys, t.log_n);
     const size_t groups = (size_t)t.n >> 6;
-    const size_t total = ln.s ? 8 * (size_t)ln.spx * ln.seglen * n_limbs : ((size_t)n_limbs * groups + 7) / 8 * 8;
-    const dim3 grid((unsigned)(total < 65536 * 8 ? total : 65536 * 8)), block(64);
+    const size_t total = ln.s ? 8 * (size_t)ln.spx * ((ln.seglen + 3) / 4) * n_limbs
+                              : ((size_t)n_limbs * ((groups + 3) / 4) + 7) / 8 * 8;
+    const dim3 grid((unsigned)(total < 65536 * 8 ? total : 65536 * 8)), block(256);
     gck_launch(aut_sum, grid, block, 0, st, z, a, l, keys, t.log_n, total, n_limbs, ln, t.mods);
     check_launch();
 }

@@ -461,7 +461,9 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
             const u64 *xd = with_add ? E.add.ptr + gathered(E.add, limb) * n : nullptr;
             const u64 *xs = E.aut ? E.aut + (size_t)limb * n : nullptr;
             const int n_aut = (xs && even) ? E.n_g : 0;
-            const bool aut_self = xs && E.aut_self;
+            // aut_self 1: the ciphertext itself on every row; 2: on odd rows only (the even rows' term comes
+            // summed in add)
+            const bool aut_self = xs && (E.aut_self == 1 || (E.aut_self == 2 && !even));
             if (M.fp) {
                 // FP64: |acc - t| < q, the product's remainder below 1.1 q, each added residue below q: the
                 // sum stays below 20 q for up to 16 automorphism terms, well inside the exact range (the
@@ -626,7 +628,7 @@ static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, 
             const double epi_bytes =
                 epi ? 8.0 * t.n * n_limbs *
                           (1.0 + (epi->add.ptr ? (epi->add_even ? 0.5 : 1.0) : 0.0) +
-                           (epi->aut ? (epi->aut_self ? 1.0 : 0.5) : 0.0))
+                           (epi->aut ? (epi->aut_self == 1 ? 1.0 : 0.5) : 0.0))
                     : 0.0;
             TScope ts_(t, name(false, true, g.log_n2, epi ? kGmEpi : kGmPlain), bytes + epi_bytes, st);
             if (epi)
