@@ -297,20 +297,35 @@ Ct mul_const(ckks_ctx &c, const ckks_ct &a, double v) {
     return r;
 }
 
-Ct mul_mask(ckks_ctx &c, const ckks_ct &a, int R) {
-    const u64 q = c.p.dropped_at(a.depth);
-    const int n = c.p.n, l = a.limbs;
+// the mask at a's scale in NTT form over l limbs: encoded once per (R, l, scale) and kept in the context;
+// a new entry is completed (stream synchronised) before it is used, so any stream may read it later
+static const u64 *mask_plain(ckks_ctx &c, int R, int l, double scale) {
+    uint64_t bits;
+    std::memcpy(&bits, &scale, sizeof bits);
+    const auto key = std::make_tuple(R, l, bits);
+    auto it = c.mask_cache.find(key);
+    if (it != c.mask_cache.end()) return it->second.ptr;
+    const int n = c.p.n;
     std::vector<i64> h(n);
-    mask_poly(n, R, a.scale, h.data());
+    mask_poly(n, R, scale, h.data());
     DBuf small(c.pool.get(), (size_t)n);
     GCK_HIP(hipMemcpyAsync(small.ptr, h.data(), (size_t)n * 8, hipMemcpyHostToDevice, c.stream));
-    sync(c);   // the host vector goes out of scope
     DBuf pt(c.pool.get(), (size_t)l * n);
     k_signed_to_limbs(c.tab, pt.ptr, reinterpret_cast<const i64 *>(small.ptr), l, map_q(l), c.stream);
     ntt_fwd(c, pt.ptr, l, map_q(l));
+    sync(c);   // the host vector goes out of scope; the entry is complete for every stream
+    const u64 *p = pt.ptr;
+    c.mask_cache.emplace(key, std::move(pt));
+    return p;
+}
+
+Ct mul_mask(ckks_ctx &c, const ckks_ct &a, int R) {
+    const u64 q = c.p.dropped_at(a.depth);
+    const int l = a.limbs;
+    const u64 *pt = mask_plain(c, R, l, a.scale);
     Ct t = new_ct(c, a.count, a.depth, a.scale);
-    k_mul(c.tab, t->data.ptr, a.data.ptr, pt.ptr, a.count * 2 * l, map_q(l), a.count * 2 * l, l, c.stream);
-    c.n_launch += 2;
+    k_mul(c.tab, t->data.ptr, a.data.ptr, pt, a.count * 2 * l, map_q(l), a.count * 2 * l, l, c.stream);
+    c.n_launch += 1;
     Ct r = rescale(c, *t);
     r->scale = (a.scale * a.scale) / (double)q;
     return r;
@@ -713,6 +728,7 @@ ckks_ctx::~ckks_ctx() {
     if (stream) hipStreamSynchronize(stream);
     else hipDeviceSynchronize();
     if (aux_stream) hipStreamSynchronize(aux_stream);
+    mask_cache.clear();   // entries may come from either pool
     aux_pool.reset();
     ksk.clear();   // every pool-backed member goes back to the pool before the pool is destroyed
     sk_ntt.release();

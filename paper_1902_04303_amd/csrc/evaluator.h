@@ -1,7 +1,9 @@
 // Context, ciphertext batches and the evaluation operations (host driver over the HIP kernels).
 #pragma once
 
+#include <map>
 #include <mutex>
+#include <tuple>
 
 #include "ckks_internal.h"
 
@@ -53,6 +55,8 @@ struct ckks_ctx {
     hipStream_t aux_stream = nullptr;
     std::unique_ptr<gck::Pool> aux_pool;
     int n_streams = 2;   // 1: the circuit runs in order on `stream` only
+    // block-start masks in NTT form by (R, limbs, scale bits), made once and then only read
+    std::map<std::tuple<int, int, uint64_t>, gck::DBuf> mask_cache;
     ~ckks_ctx();
 };
 

@@ -190,10 +190,12 @@ def wide(torch_dev):
 
 
 @pytest.mark.parametrize("rots", [list(range(1, 16)), [-r for r in range(1, 16)], list(range(1, 8)), [1, 2, 3, 4],
-                                  [2, -5], list(range(1, 16)) + [16], [16, 32, 48, -7, 9]])
+                                  [2, -5], list(range(1, 16)) + [16], [16, 32, 48, -7, 9], [2, 4, -6], [4, 8, 12],
+                                  [16, 32, 48]])
 def test_wide_rotate_sum_matches_oracle(wide, rots):
     """One key switch shared by 2 to 16 rotations (the inner product's key chunks of 3, the last one
-    padded, and the loop over 2 keys; up to 16 automorphism terms in the ModDown epilogue) equals the
+    padded, and the loop over 2 keys; the automorphism sum of more than 3 rotations; rotation lines with shift
+    units 1, 2, 4 and, at N = 2^10 where 16 slots is a multiple of N / 128, lines of one group) equals the
     oracle's, at every depth."""
     ctx, o, p = wide
     rng = np.random.default_rng(len(rots))
