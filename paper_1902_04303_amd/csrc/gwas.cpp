@@ -351,14 +351,15 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
     const int nb = in.S->count;
     if (!in.S_host && c.pool->budget == 0 && c.n_streams == 2) {
         // The logistic regression (u, w) runs on the auxiliary stream while the main stream computes what
-        // needs only r_j and x_j: S' of every SNP batch.  The numerator and denominators then wait for it.
-        fixed_front(c, lay.R, k, x, A, ds, fx);
+        // needs only r_j and x_j (their fixed-part products, then S' of every SNP batch).  The numerator and
+        // denominators then wait for it.
         ensure_aux(c);
         stream_wait(c.aux_stream, c.stream);   // inputs and this call's earlier work before the fixed part
         {
             OnStream on_aux(c);
             fixed_back(c, lay.R, k, in.kappa, x, *in.y, A, ds, fx, out);
         }
+        fixed_front(c, lay.R, k, x, A, ds, fx);
         std::vector<Ct> sps;
         for (int b0 = 0; b0 < nb; b0 += chunk) {
             const int cnt = std::min(chunk, nb - b0);
