@@ -276,7 +276,7 @@ struct KsAcc<CB, true> {
         a0[b] += fmul_mod(dd, u2d(k0), fm);
         a1[b] += fmul_mod(dd, u2d(k1), fm);
     }
-    __device__ void settle(const FMod &fm) {   // each term is below 0.6 q: keep the sums below 2^47
+    __device__ void settle(const FMod &fm) {   // each term is below 0.6 q: reduce the sums to below 0.6 q
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
             a0[b] = fred(a0[b], fm);
@@ -325,6 +325,10 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
     const FMod fm{M.qd, M.qinv};
     KsAcc<CB, FP> A;
     A.zero();
+    // FP64 sums are reduced every kSettleUnits units (at most 3 terms each, every term below 0.6 q): they stay
+    // below 15 q < 2^45, exact, and the final multiply by R^-1 takes them (below 2^47)
+    constexpr int kSettleUnits = 8;
+    int pend = 0;
     if constexpr (MK < 0) {
         // units u = (digit group gb, key chunk kc), gb-major; the loads of unit u + 1 are issued before the
         // products of unit u (double buffer).  A padded key contributes 0 x 0.
@@ -359,7 +363,10 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
 #pragma unroll
                 for (int b = 0; b < CB; ++b)
                     if (FULL || b < nb) A.mac(b, dw[0][i][b], kw0[0][i], kw1[0][i], M, fm);
-            A.settle(fm);
+            if (++pend == kSettleUnits) {
+                A.settle(fm);
+                pend = 0;
+            }
             if (u + 1 >= nu) break;
             if (u + 2 < nu) load(u + 2, 0);
 #pragma unroll
@@ -367,7 +374,10 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
 #pragma unroll
                 for (int b = 0; b < CB; ++b)
                     if (FULL || b < nb) A.mac(b, dw[1][i][b], kw0[1][i], kw1[1][i], M, fm);
-            A.settle(fm);
+            if (++pend == kSettleUnits) {
+                A.settle(fm);
+                pend = 0;
+            }
         }
     } else if constexpr (MK > 0) {
         // the loads of digit group gb + 1 are issued before the products of group gb (double buffer)
@@ -394,7 +404,10 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
 #pragma unroll
                 for (int b = 0; b < CB; ++b)
                     if (FULL || b < nb) A.mac(b, dw[0][i][b], kw0[0][i], kw1[0][i], M, fm);
-            A.settle(fm);
+            if (++pend == kSettleUnits) {
+                A.settle(fm);
+                pend = 0;
+            }
             if (gb + 1 >= gl) break;
             if (gb + 2 < gl) load(gb + 2, 0);
 #pragma unroll
@@ -402,7 +415,10 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
 #pragma unroll
                 for (int b = 0; b < CB; ++b)
                     if (FULL || b < nb) A.mac(b, dw[1][i][b], kw0[1][i], kw1[1][i], M, fm);
-            A.settle(fm);
+            if (++pend == kSettleUnits) {
+                A.settle(fm);
+                pend = 0;
+            }
         }
     } else {
         for (int gb = 0; gb < gl; ++gb) {
