@@ -36,7 +36,8 @@ sys.path.insert(0, ROOT)
 N_SAMPLES, K_COV, M_SNPS, KAPPA, LOG_N, LOG_SCALE = 245, 4, 10643, 3, 16, 40
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X, FP64 on the vector ALUs (an FMA counts 2)
-CPU_SAMPLE_BATCHES = 3           # SNP batches the CPU oracle runs for cpu_baseline (about 15 s on 8 threads)
+CPU_SAMPLE_S = 12.0              # cpu_baseline: SNP batches run until this much oracle time has passed,
+CPU_SAMPLE_MAX_BATCHES = 8       # or this many batches
 WORKLOAD = "encrypted semi-parallel GWAS n=245 k=4 m=10643, RNS-CKKS N=2^16 L=26 scale=2^40, kappa=3"
 
 
@@ -273,21 +274,24 @@ def cpu_baseline_leg(alpha: int):
     fx = G.FixedPart(x=[enc(d.X[:, j], ds + 2, j) for j in range(K_COV)],
                      rr=[enc(XA[:, j], ds, 10 + j) for j in range(K_COV)],
                      w=enc(ref.w, ds + 3, 20), u=enc(ref.w * ref.z_proj, ds + 3, 21))
-    Ss = [o.encrypt(C.encode(G.snp_batch_slots(d.S, lay, b), p.N, p.scales[ds]), ds, p.scales[ds], 30 + b)
-          for b in range(CPU_SAMPLE_BATCHES)]
+    # SNP batches in order until the timed oracle work reaches CPU_SAMPLE_S seconds (at most
+    # CPU_SAMPLE_MAX_BATCHES); each batch's encryption is outside the timed part
     circ = G.Circuit(o, lay)
     ks0 = o.n_keyswitch
-    t0 = time.perf_counter()
-    for S in Ss:
+    t = 0.0
+    nb = 0
+    while nb < CPU_SAMPLE_MAX_BATCHES and (nb == 0 or t < CPU_SAMPLE_S):
+        S = o.encrypt(C.encode(G.snp_batch_slots(d.S, lay, nb), p.N, p.scales[ds]), ds, p.scales[ds], 30 + nb)
+        t0 = time.perf_counter()
         circ.run_batch(S, fx)
-    t = time.perf_counter() - t0
+        t += time.perf_counter() - t0
+        nb += 1
     cores = int(C.lib().ref_num_threads())
-    nb = len(Ss)
     log("[bench] cpu oracle: %d SNP batches (%d SNPs) in %.1fs on %d threads" % (nb, nb * lay.tau, t, cores))
     return {"value": round(nb * lay.tau / t, 3), "unit": "SNPs/s", "cores": cores, "kind": "oracle",
             "sample": "per-batch part of the first %d 256-SNP batches of the same workload (S' = M S, numerator, "
-                      "both denominators; %d key switches at <= 6 limbs), %.1f s; the fixed logistic-regression "
-                      "part is excluded" % (nb, o.n_keyswitch - ks0, t)}
+                      "both denominators; %d key switches at <= 6 limbs), %.1f s of oracle time; the fixed "
+                      "logistic-regression part is excluded" % (nb, o.n_keyswitch - ks0, t)}
 
 
 def copy_calibration(nbytes: int) -> int:
