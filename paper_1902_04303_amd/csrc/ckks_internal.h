@@ -195,7 +195,8 @@ struct Gather {
     int mode, src_chain;
     const ConvEntry *conv;   // kConv only
     int conv_period, src_stride;
-};
+    u64 cmul, cmul_sh;       // kCentred: when cmul != 0, each source residue is first multiplied by cmul
+};                           // modulo the source modulus (Shoup companion cmul_sh)
 enum { kPlain = 0, kReduce = 1, kCentred = 2, kConv = 3 };
 // per output limb scale of an inverse NTT (replaces N^-1): entry lam % period
 struct LimbScale {
@@ -221,6 +222,8 @@ struct ModDownEpi {
     const u64 *aut;
     int aut_self, n_g;
     u64 g[kMaxKeys];
+    int acc_mul;           // 1: acc is first multiplied by km[chain] (an integer constant modulo each modulus)
+    u64 km[kMaxMods];
 };
 void k_ntt_forward_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st,
                      const ModDownEpi *epi = nullptr);

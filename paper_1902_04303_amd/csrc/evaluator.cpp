@@ -278,6 +278,32 @@ Ct rescale(ckks_ctx &c, const ckks_ct &a) {
     return r;
 }
 
+// rescale(k a) of the first lt limbs of a (lt <= a.limbs): the last of them is multiplied by k while the
+// forward NTT gathers it (before centring), the others in the epilogue; the same residues as mod_drop,
+// mul_int and rescale in turn, without their intermediate batches
+static Ct rescale_mul(ckks_ctx &c, const ckks_ct &a, int lt, i64 k) {
+    const int la = a.limbs, rows = a.count * 2;
+    if (lt < 2 || lt > la) throw Error(CKKS_E_LEVEL, "no limb left to rescale");
+    const size_t N = (size_t)c.p.n;
+    DBuf last(c.pool.get(), (size_t)rows * N);
+    k_ntt_inverse_g(c.tab, last.ptr, Gather{a.data.ptr, 1, la, lt - 1, 0, kPlain, 0}, rows, ModMap{1, 0, lt - 1},
+                    c.stream);
+    Ct r = new_ct(c, a.count, c.p.levels + 2 - lt, a.scale);   // lt - 1 limbs
+    const ckks_ctx::QInv &qi = c.q_inv.at(lt - 1);
+    const ChainConst cc = chain_const_of(c, k);
+    ModDownEpi epi{Gather{a.data.ptr, lt - 1, la, 0, 1, kPlain, 0}, Gather{}, 0, lt - 1, qi.v, qi.sh, qi.d, nullptr,
+                   0, 0, {}};
+    epi.acc_mul = 1;
+    for (int i = 0; i < lt - 1; ++i) epi.km[i] = cc.v[i];
+    Gather gl{last.ptr, lt - 1, 1, 0, 0, kCentred, lt - 1};
+    gl.cmul = cc.v[lt - 1];
+    gl.cmul_sh = cc.sh[lt - 1];
+    k_ntt_forward_g(c.tab, r->data.ptr, gl, rows * (lt - 1), map_q(lt - 1), c.stream, &epi);
+    c.n_limb_ntt += (uint64_t)rows * lt;
+    c.n_launch += 4;
+    return r;
+}
+
 Ct mod_drop(ckks_ctx &c, const ckks_ct &a, int depth) {
     if (depth == a.depth) return clone(c, a);
     if (depth < a.depth) throw Error(CKKS_E_LEVEL, "mod-drop to a shallower depth");
@@ -291,8 +317,7 @@ Ct mod_drop(ckks_ctx &c, const ckks_ct &a, int depth) {
 
 Ct mul_const(ckks_ctx &c, const ckks_ct &a, double v) {
     const u64 q = c.p.dropped_at(a.depth);
-    Ct t = mul_int(c, a, round_half_away(v * a.scale));
-    Ct r = rescale(c, *t);
+    Ct r = rescale_mul(c, a, a.limbs, round_half_away(v * a.scale));
     r->scale = (a.scale * a.scale) / (double)q;
     return r;
 }
@@ -334,11 +359,10 @@ Ct mul_mask(ckks_ctx &c, const ckks_ct &a, int R) {
 Ct align(ckks_ctx &c, const ckks_ct &a, int depth, double scale, double factor) {
     if (depth == a.depth && scale == a.scale && factor == 1.0) return clone(c, a);
     if (depth <= a.depth) throw Error(CKKS_E_LEVEL, "align needs a deeper target depth");
-    Ct t = mod_drop(c, a, depth - 1);
     const u64 q = c.p.dropped_at(depth - 1);
     i64 k = round_half_away(((scale * factor) * (double)q) / a.scale);
-    Ct u = mul_int(c, *t, k);
-    Ct r = rescale(c, *u);
+    // mod_drop to depth - 1, times k, rescale: one chain over the first limbs of a
+    Ct r = rescale_mul(c, a, c.p.limbs_at(depth - 1), k);
     r->scale = scale;
     return r;
 }

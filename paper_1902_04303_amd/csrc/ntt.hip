@@ -386,6 +386,10 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
             const int idx = slot_index<LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(e, q);
             v[e] = ain[base + (size_t)idx * stride];
         }
+        if (mode == kCentred && in.cmul) {   // a rescale of k a: the source residue times k, then centred
+#pragma unroll
+            for (int e = 0; e < kPer; ++e) v[e] = mul_shoup(v[e], in.cmul, in.cmul_sh, src_q);
+        }
     }
     if (M.fp) {
         // FP64 butterflies; the first pass reads residues, the second the first pass's doubles
@@ -487,9 +491,11 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
                         for (int i = 0; i < AU; ++i) vp[i][j] = i < n_aut ? xs[automorph_src(w, g.log_n, E.g[i])] : 0;
                     }
                     double r[EG];
+                    const double kmul = E.acc_mul ? u2d(E.km[chain]) : 0.0;
 #pragma unroll
                     for (int j = 0; j < EG; ++j) {
-                        r[j] = fmul_mod(u2d(va[j]) - u2d(vt[j]), pd, fm);
+                        const double av = E.acc_mul ? fmul_mod(u2d(va[j]), kmul, fm) : u2d(va[j]);
+                        r[j] = fmul_mod(av - u2d(vt[j]), pd, fm);
                         r[j] += u2d(vd[j]) + u2d(vs[j]);
 #pragma unroll
                         for (int i = 0; i < AU; ++i) r[j] += u2d(vp[i][j]);
@@ -520,7 +526,8 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
                 for (int e = 0; e < kPer; ++e) {
                     const int idx = slot_index<LOGM, 0, Ph<LOGM, 0>::R>(e, q);
                     const u64 t = sh[lds_addr<ROWS>(gi, idx, LOGM, log_g)];
-                    u64 r = mul_shoup(sub_mod(xa[base + idx], t, qm), pv, ps, qm);
+                    const u64 av = E.acc_mul ? mul_mod(xa[base + idx], E.km[chain], M) : xa[base + idx];
+                    u64 r = mul_shoup(sub_mod(av, t, qm), pv, ps, qm);
                     if (with_add) r = add_mod(r, xd[base + idx], qm);
                     if (aut_self) r = add_mod(r, xs[base + idx], qm);
                     for (int i = 0; i < n_aut; ++i) r = add_mod(r, xs[automorph_src(base + idx, g.log_n, E.g[i])], qm);
