@@ -136,23 +136,34 @@ namespace {
 // into one batch (x_j of job i at position j J + i), and so is each column of A: the k independent
 // products, rotate-and-sums and product sums over j then run as one batched call each.  Every ciphertext
 // goes through the same operations as in a per-j loop.
+struct StackIn {
+    Ct Xs;
+    std::vector<Ct> Acol;
+};
+StackIn stack_inputs(ckks_ctx &c, int k, const std::vector<const ckks_ct *> &x, const std::vector<const ckks_ct *> &Ain) {
+    StackIn s;
+    s.Xs = stack(c, x);
+    s.Acol.resize(k);
+    for (int l = 0; l < k; ++l) {
+        std::vector<const ckks_ct *> col;
+        for (int j = 0; j < k; ++j) col.push_back(Ain[a_index(k, std::min(j, l), std::max(j, l))]);
+        s.Acol[l] = stack(c, col);
+    }
+    return s;
+}
 struct Stacked {
     ckks_ctx &c;
     Layout lay;
     Circ C;
     int k, J;
-    Ct Xs;
-    std::vector<Ct> Acol;
-    Stacked(ckks_ctx &ctx, int R, int k_, const std::vector<const ckks_ct *> &x, const std::vector<const ckks_ct *> &Ain)
-        : c(ctx), lay(make_lay(R, k_)), C(ctx, lay, kFixedRadix), k(k_), J(x[0]->count) {
-        Xs = stack(c, x);
-        Acol.resize(k);
-        for (int l = 0; l < k; ++l) {
-            std::vector<const ckks_ct *> col;
-            for (int j = 0; j < k; ++j) col.push_back(Ain[a_index(k, std::min(j, l), std::max(j, l))]);
-            Acol[l] = stack(c, col);
-        }
-    }
+    StackIn own;
+    const StackIn &in;   // pre: stacked once by the caller and shared (read only); else own
+    const ckks_ct &Xs;
+    const std::vector<Ct> &Acol;
+    Stacked(ckks_ctx &ctx, int R, int k_, const std::vector<const ckks_ct *> &x, const std::vector<const ckks_ct *> &Ain,
+            const StackIn *pre)
+        : c(ctx), lay(make_lay(R, k_)), C(ctx, lay, kFixedRadix), k(k_), J(x[0]->count),
+          own(pre ? StackIn{} : stack_inputs(ctx, k_, x, Ain)), in(pre ? *pre : own), Xs(*in.Xs), Acol(in.Acol) {}
     static Layout make_lay(int R, int k) {
         Layout l;
         l.R = R;
@@ -176,7 +187,7 @@ struct Stacked {
     }
     // sum_j x_j t_j for stacked t, x at the depth of t (times factor)
     Ct x_dot(const ckks_ct &t, double factor) {
-        Ct Xd = C.at(*Xs, t.depth, factor);
+        Ct Xd = C.at(Xs, t.depth, factor);
         std::vector<Ct> a = parts(*Xd), b = parts(t);
         std::vector<std::pair<const ckks_ct *, const ckks_ct *>> q;
         for (int j = 0; j < k; ++j) q.push_back({a[j].get(), b[j].get()});
@@ -186,33 +197,35 @@ struct Stacked {
 }  // namespace
 
 void fixed_front(ckks_ctx &c, int R, int k, const std::vector<const ckks_ct *> &x, const std::vector<const ckks_ct *> &Ain,
-                 int ds, FixedOut &fx) {
-    Stacked st(c, R, k, x, Ain);
+                 int ds, FixedOut &fx, const StackIn *pre = nullptr) {
+    Stacked st(c, R, k, x, Ain, pre);
     const int J = st.J;
     // ---- r_j = (X A)_{:, j}, and x_j at the depth the per-batch part uses it
     std::vector<Ct> x1(k);
     for (int l = 0; l < k; ++l) x1[l] = st.C.at(*x[l], 1);
     Ct RR = st.a_times(x1);
-    Ct RRs = st.C.at(*RR, ds), Xc = st.C.at(*st.Xs, ds + 2);
+    Ct RRs = st.C.at(*RR, ds);
+    // x_j at ds + 2 owned here (the stacked x may be the caller's, shared with the other part)
+    Ct Xc = st.Xs.depth == ds + 2 ? clone(c, st.Xs) : st.C.at(st.Xs, ds + 2);
     fx.r_s.resize(k);
     fx.x_c.resize(k);
     for (int j = 0; j < k; ++j) {
         fx.r_s[j] = view(*RRs, j * J, J);
         fx.x_c[j] = view(*Xc, j * J, J);
     }
-    // RRs and Xc may themselves be views of RR and the stacked x (at() does not copy)
+    // RRs may be a view of RR (at() does not copy)
     fx.hold.push_back(std::move(RRs));
     fx.hold.push_back(std::move(Xc));
     fx.hold.push_back(std::move(RR));
-    fx.hold.push_back(std::move(st.Xs));
 }
 
 void fixed_back(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckks_ct *> &x, const ckks_ct &y,
-                const std::vector<const ckks_ct *> &Ain, int ds, FixedOut &fx, EncOutput &rep) {
-    Stacked st(c, R, k, x, Ain);
+                const std::vector<const ckks_ct *> &Ain, int ds, FixedOut &fx, EncOutput &rep,
+                const StackIn *pre = nullptr) {
+    Stacked st(c, R, k, x, Ain, pre);
     Circ &C = st.C;
     const int J = st.J;
-    const ckks_ct &Xs = *st.Xs;
+    const ckks_ct &Xs = st.Xs;
     // ---- Alg. Homomorphic LogReg, first pass: beta = 0, so p = sigma7(0) = 1/2 is public
     Ct r = add_const(c, y, -0.5);
     Ct G = C.rot_sum(mul(c, Xs, *r));                    // g_j = X^T (y - p), stacked over j
@@ -354,12 +367,13 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
         // needs only r_j and x_j (their fixed-part products, then S' of every SNP batch).  The numerator and
         // denominators then wait for it.
         ensure_aux(c);
-        stream_wait(c.aux_stream, c.stream);   // inputs and this call's earlier work before the fixed part
+        const StackIn sin = stack_inputs(c, k, x, A);   // shared by both parts, read only
+        stream_wait(c.aux_stream, c.stream);   // inputs, their stacking and this call's earlier work
         {
             OnStream on_aux(c);
-            fixed_back(c, lay.R, k, in.kappa, x, *in.y, A, ds, fx, out);
+            fixed_back(c, lay.R, k, in.kappa, x, *in.y, A, ds, fx, out, &sin);
         }
-        fixed_front(c, lay.R, k, x, A, ds, fx);
+        fixed_front(c, lay.R, k, x, A, ds, fx, &sin);
         std::vector<Ct> sps;
         for (int b0 = 0; b0 < nb; b0 += chunk) {
             const int cnt = std::min(chunk, nb - b0);
