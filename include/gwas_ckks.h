@@ -210,7 +210,7 @@ int gwas_layout(const ckks_ctx *ctx, int n, int k, int m, int kappa, int *R, int
 
 /* Host only: the Galois elements whose keys the circuit needs for block size R at ring degree 2^log_n
  * (the rotations of the grouped rotate-and-sum in both directions, each once: the fixed part groups
- * them by up to 3 per key switch, {s, 2s, 3s}, the per-SNP-batch part by up to 15, {s, 2s, .., 15s};
+ * them by up to 7 per key switch, {s, 2s, .., 7s}, the per-SNP-batch part by up to 15, {s, 2s, .., 15s};
  * then conjugation).  Writes at most cap elements to out and the number needed to *count. */
 int gwas_galois_elements(int log_n, int R, uint64_t *out, int cap, int *count);
 

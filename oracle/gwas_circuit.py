@@ -186,7 +186,7 @@ def encrypt_inputs(o: C.Oracle, pts: Plaintexts, n: int, k: int, m: int, kappa: 
 
 # Rotations per shared key switch: up to FIXED_RADIX - 1 in the fixed part (one to a few ciphertexts per
 # call) and up to BATCH_RADIX - 1 in the per-SNP-batch part.
-FIXED_RADIX = 4
+FIXED_RADIX = 8
 BATCH_RADIX = 16
 
 

@@ -64,12 +64,13 @@ int snp_depth(int kappa);
 Layout make_layout(int n_ring, int n, int k, int m);
 // Rotations of the rotate-and-sum over R = 2^r slots, by shared key switch: {s, 2s, .., (m - 1) s} with
 // m = min(radix, R / s) for s = 1, then s times the previous m.  Radix 4 gives {s, 2s, 3s} for
-// s = 1, 4, 16, .. and a last {s} when r is odd.  The fixed part (few ciphertexts per call, key reads
-// dominate) uses radix 4; the per-SNP-batch part (many ciphertexts per call, ModUp and ModDown dominate)
-// uses radix 16, half as many key switches for R = 256.
-constexpr int kFixedRadix = 4, kBatchRadix = 16;
+// s = 1, 4, 16, .. and a last {s} when r is odd.  The fixed part (few ciphertexts per call at high
+// levels, so key reads weigh more) uses radix 8, 3 key switches for R = 256 (measured: radix 4, 8 and 16
+// took 65.4, 64.4 and 64.8 ms per paper-size job); the per-SNP-batch part (many ciphertexts per call,
+// ModUp and ModDown weigh most) uses radix 16, 2 key switches for R = 256.
+constexpr int kFixedRadix = 8, kBatchRadix = 16;
 std::vector<std::vector<i64>> rotation_groups(int R, int radix);
-// Galois elements of the rotations of rotation_groups(R, 4) and rotation_groups(R, 16) in both
+// Galois elements of the rotations of rotation_groups(R, 8) and rotation_groups(R, 16) in both
 // directions (each once, in that order), then conjugation
 std::vector<u64> required_galois(int n, int R);
 void run_fixed(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckks_ct *> &x, const ckks_ct &y,
