@@ -312,6 +312,14 @@ struct KsAcc<CB, false> {
     }
 };
 
+// word at a 32-bit byte offset from a wave-uniform base: the empty asm statement keeps the optimizer from
+// widening the offset to 64 bits, so the load takes the base from scalar registers and the offset from one
+// vector register (no 64-bit address arithmetic per lane)
+__device__ __forceinline__ u64 ld_off(const u64 *base, unsigned byte_off) {
+    asm("" : "+v"(byte_off));
+    return *reinterpret_cast<const u64 *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
 // one target word for CB ciphertexts.  MK > 0: exactly MK keys, their loads for one digit group issued
 // together (unrolled); MK < 0: keys.m keys in chunks of -MK (the last chunk padded with zero words), the
 // loads of one (digit group, chunk) unit issued together; MK == 0: keys.m keys in a loop.  FULL: (MK < 0)
@@ -342,16 +350,17 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
             for (int i = 0; i < KC; ++i) {
                 const int ki = kc * KC + i;
                 const bool on = FULL || ki < m;
-                const u64 *key = keys.key[on ? ki : 0];
+                const u64 *key = keys.key[on ? ki : 0] + (size_t)gb * key_grp + (krow - k);   // wave-uniform
                 const u64 g = on ? keys.g[ki] : 0;
-                const size_t kdi = g ? automorph_src(k, log_n, g) : k;
-                kw0[s][i] = on ? key[(size_t)gb * key_grp + krow] : 0;
-                kw1[s][i] = on ? key[key_comp + (size_t)gb * key_grp + krow] : 0;
+                const unsigned kdb = (unsigned)(g ? automorph_src(k, log_n, g) : k) << 3;
+                const unsigned kb = (unsigned)k << 3;
+                kw0[s][i] = on ? ld_off(key, kb) : 0;
+                kw1[s][i] = on ? ld_off(key + key_comp, kb) : 0;
 #pragma unroll
                 for (int b = 0; b < CB; ++b) {
                     const int bb = FULL && b >= nb ? nb - 1 : b;
                     const u64 *src = e >= 0 ? digits + ((size_t)(c0 + bb) * K + e) * n : own_row[bb];
-                    dw[s][i][b] = (on && (FULL || b < nb)) ? src[kdi] : 0;
+                    dw[s][i][b] = (on && (FULL || b < nb)) ? ld_off(src, kdb) : 0;
                 }
             }
         };
