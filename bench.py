@@ -171,9 +171,9 @@ def forms_leg(args):
                "ratio": round(t_plain / t_batched, 3), "m_scale": args.forms_m_scale}
     del ins
 
-    def serve(max_jobs):
+    def serve(max_jobs, burst=False):
         ins = pack_all()
-        arrivals = poisson_arrivals(len(ins), args.forms_rate, 302)
+        arrivals = [0.0] * len(ins) if burst else poisson_arrivals(len(ins), args.forms_rate, 302)
         srv = ctx.gwas_server(hbm_budget=0, max_jobs=max_jobs, chunk=64)
         t0 = time.perf_counter()
         ids = []
@@ -191,9 +191,15 @@ def forms_leg(args):
     fifo = serve(1)
     log("[bench] serving: continuous p50 %.0f ms p99 %.0f ms; FIFO p50 %.0f ms p99 %.0f ms" %
         (cb["p50_ms"], cb["p99_ms"], fifo["p50_ms"], fifo["p99_ms"]))
+    # the same jobs all at once: requests that wait while others run, where continuous batching matters
+    cb_b = serve(64, burst=True)
+    fifo_b = serve(1, burst=True)
+    log("[bench] serving, all jobs at once: continuous %.1f jobs/s p99 %.0f ms; FIFO %.1f jobs/s p99 %.0f ms" %
+        (cb_b["jobs_per_s"], cb_b["p99_ms"], fifo_b["jobs_per_s"], fifo_b["p99_ms"]))
+    rnd = lambda st: {k: (round(v, 2) if isinstance(v, float) else v) for k, v in st.items()}  # noqa: E731
     serving = {"jobs": len(jobs), "arrival_rate_per_s": args.forms_rate,
-               "continuous": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in cb.items()},
-               "fifo_one_at_a_time": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in fifo.items()}}
+               "continuous": rnd(cb), "fifo_one_at_a_time": rnd(fifo),
+               "burst": {"continuous": rnd(cb_b), "fifo_one_at_a_time": rnd(fifo_b)}}
     ctx.close()
     return batched, serving
 
