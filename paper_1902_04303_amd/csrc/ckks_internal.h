@@ -267,6 +267,10 @@ void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const in
 // z[c][j] = a[c][0][j] + sum_i sigma_i(a[c][0][j]) mod q_j (NTT domain) for the keys' automorphisms (any
 // Galois maps, up to kMaxKeys), a [count][2][l][N] and z [count][l][N]
 void k_aut_sum(const DevTables &t, u64 *z, const u64 *a, int count, int l, const KsKeys &keys, hipStream_t st);
+// the same for the rotations r1, 2 r1, .., (m - 1) r1 (m a power of 2 up to 16, |r1| a power of 2; g1 the
+// Galois element of r1) by log2 m doubling steps in LDS; false (nothing launched) for other rotation sets
+bool aut_sum_doubling(const DevTables &t, u64 *z, const u64 *a, int count, int l, i64 r1, int m, u64 g1,
+                      hipStream_t st);
 // samplers of the test-only SplitMix64 streams
 void k_sample_uniform(const DevTables &t, u64 *out, u64 seed, u64 sid, int n_limbs, ModMap m, int mi_of_p,
                       hipStream_t st);

@@ -520,7 +520,12 @@ Ct rotate_sum(ckks_ctx &c, const ckks_ct &a, const std::vector<i64> &rots) {
                        true);
     } else {
         DBuf z(c.pool.get(), (size_t)a.count * l * c.p.n);
-        k_aut_sum(c.tab, z.ptr, a.data.ptr, a.count, l, keys, c.stream);
+        // rotations r1, 2 r1, .., (m - 1) r1 (a grouped rotate-and-sum step): the doubling form
+        bool arith = true;
+        for (size_t i = 0; i < rots.size(); ++i) arith = arith && rots[i] == (i64)(i + 1) * rots[0];
+        if (!(arith && aut_sum_doubling(c.tab, z.ptr, a.data.ptr, a.count, l, rots[0], (int)rots.size() + 1, gs[0],
+                                        c.stream)))
+            k_aut_sum(c.tab, z.ptr, a.data.ptr, a.count, l, keys, c.stream);
         // z = c0 + sum_i sigma_i(c0) on the even rows; the odd rows add c1 itself
         ks = keyswitch(c, Gather{a.data.ptr, l, 2 * l, l, 1, kPlain, 0}, a.count, l, keys,
                        Gather{z.ptr, 2 * l, l, 0, 1, kPlain, 0}, true, a.data.ptr, 2, false);

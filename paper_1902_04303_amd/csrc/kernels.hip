@@ -469,6 +469,19 @@ struct KsLines {
     int spx = 0;      // segments per XCD
 };
 
+// Doubling form of a rotate-and-sum group's automorphism sum (aut_sum_dbl)
+struct AutDbl {
+    int log_m;   // m = 2^log_m terms: the word itself and m - 1 rotations
+    int step;    // group-exponent shift of one rotation (s mod T, a power of 2; 0: within each group)
+    int dir;     // +1 or -1: the sign of the rotations
+    int U;       // groups per line
+    int W;       // output groups per workgroup (W divides U)
+    int nb;      // groups in LDS: W + m - 1, or U when the window is the whole line
+    int cyc;     // 1: the window is the whole line (indices modulo U)
+    int lines;   // 2 signs x step lines, or 2 T single-group lines when step == 0
+    u64 gp[4];   // Galois elements of sigma^(2^j), j < log_m
+};
+
 // group index (word index >> 6) of the class (sign, t): E = +-5^t mod 2^(log_n - 5), G = brev((E - 1) / 2)
 __device__ __forceinline__ unsigned rot_group(int sign, unsigned t, int log_n) {
     const unsigned mask = (1u << (log_n - 5)) - 1;
@@ -702,6 +715,103 @@ void k_aut_sum(const DevTables &t, u64 *z, const u64 *a, int count, int l, const
     const dim3 grid((unsigned)(total < 65536 * 8 ? total : 65536 * 8)), block(256);
     gck_launch(aut_sum, grid, block, 0, st, z, a, l, keys, t.log_n, total, n_limbs, ln, t.mods);
     check_launch();
+}
+
+// The same sum for the rotations of one rotate-and-sum group, d s, 2 d s, .., (m - 1) d s with m a power of
+// 2: z = (1 + sigma)(1 + sigma^2)..(1 + sigma^(m/2)) c0 with sigma the rotation by d s, so log2 m doubling
+// steps A <- A + sigma^p(A), each reading its partner word once, in place of m - 1 gathers per word.  A
+// 256-thread workgroup loads a window of W groups of one rotation line (t = v + d s u, u along the line) and
+// the m - 1 groups after it, or the whole line when it is short (indices then cyclic), into LDS, and runs
+// the steps there; the partner of a word is its automorphism source under sigma^p, a word of the group p
+// places further along the line.
+__global__ void __launch_bounds__(256) aut_sum_dbl(u64 *z, const u64 *a, int l, int log_n, AutDbl ad, int n_limbs,
+                                                   const ModInfo *mods) {
+    extern __shared__ u64 buf[];                    // nb groups of 64 words
+    int *gid = reinterpret_cast<int *>(buf + (size_t)ad.nb * 64);   // group index of each window slot
+    const size_t n = (size_t)1 << log_n;
+    const unsigned T = 1u << (log_n - 7);
+    const int segs = ad.U / ad.W;
+    const int item = blockIdx.x;
+    const int seg = item % segs, line = (item / segs) % ad.lines, lam = item / (segs * ad.lines);
+    if (lam >= n_limbs) return;
+    const int per_sign = ad.lines / 2;
+    const int sign = line / per_sign, v = line % per_sign;
+    const int u0 = seg * ad.W;
+    const int c = lam / l, j = lam % l;
+    const u64 *src = a + ((size_t)c * 2 * l + j) * n;
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    for (int gx = wave; gx < ad.nb; gx += 4) {
+        const int u = (u0 + gx) % ad.U;
+        const unsigned t = ad.step ? (unsigned)(v + ad.dir * ad.step * u) & (T - 1) : (unsigned)v;
+        const unsigned g = rot_group(sign, t, log_n);
+        if (lane == 0) gid[gx] = (int)g;
+        buf[(size_t)gx * 64 + lane] = src[((size_t)g << 6) + lane];
+    }
+    __syncthreads();
+    constexpr int kMaxPer = 20;   // words per thread per step: nb 64 / 256 with nb <= 79
+    for (int st = 0; st < ad.log_m; ++st) {
+        const int p = 1 << st;
+        const int valid = ad.cyc ? ad.nb : ad.nb - (2 * p - 1);
+        u64 r[kMaxPer];
+#pragma unroll
+        for (int e = 0; e < kMaxPer; ++e) {
+            const int x = (int)threadIdx.x + e * 256;
+            r[e] = 0;
+            if (x < valid * 64) {
+                const int gx = x >> 6, w = x & 63;
+                const size_t k = ((size_t)gid[gx] << 6) + w;
+                const int gp = ad.cyc ? (gx + p) % ad.nb : gx + p;
+                const int wp = (int)(automorph_src(k, log_n, ad.gp[st]) & 63);
+                r[e] = buf[x] + buf[(size_t)gp * 64 + wp];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < kMaxPer; ++e) {
+            const int x = (int)threadIdx.x + e * 256;
+            if (x < valid * 64) buf[x] = r[e];
+        }
+        __syncthreads();
+    }
+    const ModInfo M = mods[j];
+    for (int gx = wave; gx < ad.W; gx += 4) {
+        const u64 sum = buf[(size_t)gx * 64 + lane];   // at most 16 terms below q: below 2^64 (2^45 for q < 2^41)
+        const size_t k = ((size_t)gid[gx] << 6) + lane;
+        z[(size_t)lam * n + k] = M.fp ? fcanon(u2d(sum), FMod{M.qd, M.qinv}) : reduce64(sum, M);
+    }
+}
+
+bool aut_sum_doubling(const DevTables &t, u64 *z, const u64 *a, int count, int l, i64 r1, int m, u64 g1,
+                      hipStream_t st) {
+    // r1: the first rotation (d s), m: terms (m - 1 rotations r1, 2 r1, ..); g1 its Galois element
+    if (t.log_n < 9 || m < 2 || m > 16 || (m & (m - 1)) || r1 == 0) return false;
+    const i64 s_abs = r1 < 0 ? -r1 : r1;
+    if (s_abs & (s_abs - 1)) return false;   // a power of 2, so that the shifts walk one line
+    const int T = 1 << (t.log_n - 7);
+    AutDbl ad{};
+    ad.log_m = __builtin_ctz((unsigned)m);
+    ad.dir = r1 < 0 ? -1 : 1;
+    ad.step = s_abs < T ? (int)s_abs : 0;
+    ad.U = ad.step ? T / ad.step : 1;
+    ad.W = ad.U < 64 ? ad.U : 64;
+    ad.cyc = ad.W == ad.U ? 1 : 0;
+    ad.nb = ad.cyc ? ad.U : ad.W + m - 1;
+    ad.lines = ad.step ? 2 * ad.step : 2 * T;
+    const u64 mask = (2ULL << t.log_n) - 1;
+    u64 g = g1 & mask;
+    for (int j = 0; j < ad.log_m; ++j) {
+        ad.gp[j] = g;
+        g = (g * g) & mask;
+    }
+    if (ad.nb * 64 > 20 * 256) return false;
+    const int n_limbs = count * l;
+    TScope ts_(t, "aut_sum_dbl", 16.0 * (double)n_limbs * t.n, st);
+    if (!n_limbs) return true;
+    const size_t items = (size_t)n_limbs * ad.lines * (ad.U / ad.W);
+    const size_t lds = (size_t)ad.nb * 64 * sizeof(u64) + (size_t)ad.nb * sizeof(int);
+    gck_launch(aut_sum_dbl, dim3((unsigned)items), dim3(256), (unsigned)lds, st, z, a, l, t.log_n, ad, n_limbs, t.mods);
+    check_launch();
+    return true;
 }
 
 // ---------------------------------------------------------------- samplers and conversions
