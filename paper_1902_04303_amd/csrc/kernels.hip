@@ -312,12 +312,20 @@ struct KsAcc<CB, false> {
     }
 };
 
+// Loads through the global address space.  A pointer chosen at run time between a kernel argument and a
+// pointer read from an argument struct is generic to the compiler, and a generic load is a FLAT access,
+// which counts on the LDS counter as well: the wait before the first product of a unit then has to drain
+// every load in flight, including the next unit's prefetch.  All buffers here are device memory.
+typedef __attribute__((address_space(1))) const u64 gu64;
+typedef __attribute__((address_space(1))) const char gchar;
+__device__ __forceinline__ u64 ld_g(const u64 *p) { return *(gu64 *)p; }
+
 // word at a 32-bit byte offset from a wave-uniform base: the empty asm statement keeps the optimizer from
 // widening the offset to 64 bits, so the load takes the base from scalar registers and the offset from one
 // vector register (no 64-bit address arithmetic per lane)
 __device__ __forceinline__ u64 ld_off(const u64 *base, unsigned byte_off) {
     asm("" : "+v"(byte_off));
-    return *reinterpret_cast<const u64 *>(reinterpret_cast<const char *>(base) + byte_off);
+    return *(gu64 *)((gchar *)base + byte_off);
 }
 
 // one target word for CB ciphertexts.  MK > 0: exactly MK keys, their loads for one digit group issued
@@ -364,9 +372,18 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
                 }
             }
         };
+        // FULL: the prefetch is unconditional (past the end it re-reads the last unit), so that the wait
+        // before a unit's products counts only the loads issued before the other buffer's, and an empty asm
+        // statement that clobbers memory keeps the compiler from sinking it down to its own products (the
+        // guarded form measures faster with the fence and the clamp left out)
         load(0, 0);
         for (int u = 0; u < nu; u += 2) {
-            if (u + 1 < nu) load(u + 1, 1);
+            if constexpr (FULL) {
+                load(min(u + 1, nu - 1), 1);
+                asm volatile("" ::: "memory");
+            } else if (u + 1 < nu) {
+                load(u + 1, 1);
+            }
 #pragma unroll
             for (int i = 0; i < KC; ++i)
 #pragma unroll
@@ -377,7 +394,12 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
                 pend = 0;
             }
             if (u + 1 >= nu) break;
-            if (u + 2 < nu) load(u + 2, 0);
+            if constexpr (FULL) {
+                load(min(u + 2, nu - 1), 0);
+                asm volatile("" ::: "memory");
+            } else if (u + 2 < nu) {
+                load(u + 2, 0);
+            }
 #pragma unroll
             for (int i = 0; i < KC; ++i)
 #pragma unroll
@@ -401,7 +423,7 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
                 for (int b = 0; b < CB; ++b) {
                     const int bb = FULL && b >= nb ? nb - 1 : b;
                     const u64 *src = e >= 0 ? digits + ((size_t)(c0 + bb) * K + e) * n : own_row[bb];
-                    dw[s][i][b] = (FULL || b < nb) ? src[kd[i]] : 0;
+                    dw[s][i][b] = (FULL || b < nb) ? ld_g(src + kd[i]) : 0;
                 }
             }
         };
@@ -444,7 +466,7 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
                 const u64 k1 = keys.key[i][key_comp + (size_t)gb * key_grp + krow];
 #pragma unroll
                 for (int b = 0; b < CB; ++b)
-                    if (FULL || b < nb) A.mac(b, src[b][kdi], k0, k1, M, fm);
+                    if (FULL || b < nb) A.mac(b, ld_g(src[b] + kdi), k0, k1, M, fm);
             }
             A.settle(fm);
         }
