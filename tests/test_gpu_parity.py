@@ -205,6 +205,60 @@ def test_wide_rotate_sum_matches_oracle(wide, rots):
         assert np.array_equal(ctx.export(ctx.rotate_sum(ga, rots)), o.rotate_sum(oa, rots).data)
 
 
+@pytest.fixture(scope="module")
+def full_ring(torch_dev):
+    """The workload's ring and chain (N = 2^16, L = 26, 40-bit scale primes, digit groups of 3) with the
+    keys of the per-batch rotate-and-sums (rotations 1..15 and 16..240 step 16) and conjugation.  The
+    library holds full keys; one oracle holds the same keys restricted to ciphertexts of at most 6 limbs
+    (the per-batch levels), a second one full-height keys for relinearisation, rotation by 1 and 16."""
+    say("[gpu] full ring N=2^16 L=26: library keys")
+    rots = list(range(1, 16)) + [16 * i for i in range(1, 16)]
+    ctx = P.Context(16, 26, 40)
+    p = C.make_params(16, 26, 40)
+    assert ctx.moduli() == [int(q) for q in p.q] + [int(q) for q in p.P]
+    g = [C.galois_rotate(p.N, r) for r in rots] + [C.galois_conj(p.N)]
+    ctx.keygen(7, g)
+    say("[gpu] full ring: oracle keys (6 limbs, then full height)")
+    low = C.Oracle(p)
+    low.keygen(7, g, max_limbs=p.limbs_at_depth(21))
+    top = C.Oracle(p)
+    top.keygen(7, [C.galois_rotate(p.N, 1), C.galois_rotate(p.N, 16)])
+    return ctx, low, top, p
+
+
+@pytest.mark.parametrize("depth", [21, 24])
+def test_full_ring_batch_level_ops_match_oracle(full_ring, depth):
+    """At the workload's own ring and levels, the key switches of the per-batch part (relinearisation, the
+    15-rotation rotate-and-sums on the lines of shift 1 and 16, a single rotation, conjugation) equal the
+    oracle's bit for bit."""
+    ctx, o, _, p = full_ring
+    rng = np.random.default_rng(100 + depth)
+    ga, oa = _both(ctx, o, p, rand_ct(p, depth, rng), depth)
+    gb, ob = _both(ctx, o, p, rand_ct(p, depth, rng), depth)
+    say("[gpu] full ring mul at depth", depth)
+    assert np.array_equal(ctx.export(ctx.mul(ga, gb)), o.mul(oa, ob).data)
+    for rots in (list(range(1, 16)), [16 * i for i in range(1, 16)], [1, 2, 3], [16]):
+        say("[gpu] full ring rotate_sum of", len(rots), "rotations from", rots[0], "at depth", depth)
+        assert np.array_equal(ctx.export(ctx.rotate_sum(ga, rots)), o.rotate_sum(oa, rots).data)
+    say("[gpu] full ring rotate and conjugate at depth", depth)
+    assert np.array_equal(ctx.export(ctx.rotate(ga, 7)), o.rotate(oa, 7).data)
+    assert np.array_equal(ctx.export(ctx.conjugate(ga)), o.conjugate(oa).data)
+
+
+def test_full_ring_top_level_ops_match_oracle(full_ring):
+    """At 27 limbs (all nine digit groups, the fixed part's first key switches) relinearisation and
+    rotations equal the oracle's bit for bit."""
+    ctx, _, o, p = full_ring
+    rng = np.random.default_rng(99)
+    ga, oa = _both(ctx, o, p, rand_ct(p, 0, rng), 0)
+    gb, ob = _both(ctx, o, p, rand_ct(p, 0, rng), 0)
+    say("[gpu] full ring mul at depth 0")
+    assert np.array_equal(ctx.export(ctx.mul(ga, gb)), o.mul(oa, ob).data)
+    say("[gpu] full ring rotate 1, rotate_sum [1, 16] at depth 0")
+    assert np.array_equal(ctx.export(ctx.rotate(ga, 1)), o.rotate(oa, 1).data)
+    assert np.array_equal(ctx.export(ctx.rotate_sum(ga, [1, 16])), o.rotate_sum(oa, [1, 16]).data)
+
+
 def test_kernel_timing_report(small):
     """Per-kernel timing: every launched kernel appears with its launches and a positive time, a timing
     restricted to one kernel records that kernel only, and timing leaves the results unchanged."""
