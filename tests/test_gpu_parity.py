@@ -361,8 +361,11 @@ def test_circuit_bit_exact_against_oracle(torch_dev, n, k, m, log_n, b, chunk):
     assert np.allclose(res["b"][ok], bb[ok], rtol=1e-7, atol=1e-12)
 
 
-@pytest.mark.parametrize("n,k,m,log_n,b,tol", [(245, 4, 32, 13, 30, 1e-3), (245, 4, 600, 16, 40, 1e-3)])
+@pytest.mark.parametrize("n,k,m,log_n,b,tol", [(245, 4, 32, 13, 30, 1e-3), (245, 4, 600, 16, 40, 1e-3),
+                                               (245, 4, 10643, 16, 40, 1e-3)])
 def test_end_to_end_accuracy_against_fp64(torch_dev, n, k, m, log_n, b, tol):
+    """Decrypted b' within tol of the FP64 modified GWAS (relative to max(|b'|, se)) and se within 1e-3,
+    up to the benchmark's full workload (42 SNP batches of 256, the batched launches it times)."""
     kappa = 3
     say("[gpu] end-to-end n=%d m=%d logN=%d" % (n, m, log_n))
     L = G.circuit_depth(kappa)
