@@ -351,8 +351,19 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
         constexpr int KC = -MK;
         const int m = keys.m, nkc = (m + KC - 1) / KC, nu = gl * nkc;
         u64 kw0[2][KC], kw1[2][KC], dw[2][KC][CB];
-        auto load = [&](int u, int s) {
-            const int gb = u / nkc, kc = u - gb * nkc;
+        // digit rows of the thread's ciphertexts (digit index e adds e N), and the unit the next load takes,
+        // advanced by one per load (no division per unit); past the last unit a load repeats it
+        const u64 *dbase[CB];
+#pragma unroll
+        for (int b = 0; b < CB; ++b) dbase[b] = digits + (size_t)(c0 + (FULL && b >= nb ? nb - 1 : b)) * K * n;
+        int cur_gb = 0, cur_kc = 0;
+        auto load = [&](int s) {
+            const bool past = cur_gb >= gl;
+            const int gb = past ? gl - 1 : cur_gb, kc = past ? nkc - 1 : cur_kc;
+            if (++cur_kc == nkc) {
+                cur_kc = 0;
+                ++cur_gb;
+            }
             const int e = didx[gb * nt + tt];
 #pragma unroll
             for (int i = 0; i < KC; ++i) {
@@ -367,7 +378,7 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
 #pragma unroll
                 for (int b = 0; b < CB; ++b) {
                     const int bb = FULL && b >= nb ? nb - 1 : b;
-                    const u64 *src = e >= 0 ? digits + ((size_t)(c0 + bb) * K + e) * n : own_row[bb];
+                    const u64 *src = e >= 0 ? dbase[b] + ((size_t)e << log_n) : own_row[bb];
                     dw[s][i][b] = (on && (FULL || b < nb)) ? ld_off(src, kdb) : 0;
                 }
             }
@@ -376,13 +387,13 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
         // before a unit's products counts only the loads issued before the other buffer's, and an empty asm
         // statement that clobbers memory keeps the compiler from sinking it down to its own products (the
         // guarded form measures faster with the fence and the clamp left out)
-        load(0, 0);
+        load(0);
         for (int u = 0; u < nu; u += 2) {
             if constexpr (FULL) {
-                load(min(u + 1, nu - 1), 1);
+                load(1);
                 asm volatile("" ::: "memory");
             } else if (u + 1 < nu) {
-                load(u + 1, 1);
+                load(1);
             }
 #pragma unroll
             for (int i = 0; i < KC; ++i)
@@ -395,10 +406,10 @@ __device__ __forceinline__ void ks_word(u64 *acc, const u64 *digits, int K, cons
             }
             if (u + 1 >= nu) break;
             if constexpr (FULL) {
-                load(min(u + 2, nu - 1), 0);
+                load(0);
                 asm volatile("" ::: "memory");
             } else if (u + 2 < nu) {
-                load(u + 2, 0);
+                load(0);
             }
 #pragma unroll
             for (int i = 0; i < KC; ++i)
