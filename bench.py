@@ -38,7 +38,9 @@ HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X, FP64 on the vector ALUs (an FMA counts 2)
 CPU_SAMPLE_S = 12.0              # cpu_baseline: SNP batches run until this much oracle time has passed,
 CPU_SAMPLE_MAX_BATCHES = 8       # or this many batches
-WORKLOAD = "encrypted semi-parallel GWAS n=245 k=4 m=10643, RNS-CKKS N=2^16 L=26 scale=2^40, kappa=3"
+WORKLOAD = ("encrypted semi-parallel GWAS n=245 k=4 m=10643, RNS-CKKS N=2^16, q_0 of 60 bits + L=26 primes of "
+            "40 bits, scale=2^40, kappa=3; key switching with 3 special primes of 41 bits and digit groups of 3 "
+            "(hybrid) in place of one 60-bit special prime")
 
 
 def log(*a):
@@ -115,16 +117,26 @@ def gpu_leg(args):
     region_marker(4)
     ctx.kernel_timing(False)
     kt = ctx.kernel_report()
-    ctx.kernel_timing_only(None)
-    ctx.set_streams(2)
     ms_one = (t3 - t2) * 1e3 / args.steps
     log("[bench] one stream: %.1f ms/step (dominant kernel %s timed)" % (ms_one, dominant))
+    # key-switch region (markers 5, 6): every key switch of the steps timed as a whole on one stream
+    ctx.kernel_timing_only("keyswitch")
+    ctx.kernel_timing(True)
+    region_marker(5)
+    for _ in range(args.steps):
+        ctx.gwas_semiparallel(gin)
+    torch.cuda.synchronize()
+    region_marker(6)
+    ctx.kernel_timing(False)
+    ks = ctx.kernel_report().get("keyswitch")
+    ctx.kernel_timing_only(None)
+    ctx.set_streams(2)
     # end-to-end with the host boundary (outside the timed region): finalize = D2H + decrypt + divide
     t4 = time.perf_counter()
     res = ctx.gwas_finalize(out)
     t5 = time.perf_counter()
     per_step = {k: (c1[k] - c0[k]) // args.steps for k in c0}
-    return dict(ms=ms, ms_one_stream=ms_one, kernels=kt, warm_kernels=warm, counters=per_step,
+    return dict(ms=ms, ms_one_stream=ms_one, kernels=kt, warm_kernels=warm, counters=per_step, keyswitch=ks,
                 finalize_ms=(t5 - t4) * 1e3,
                 b_finite=int(np.isfinite(res["b"]).sum()), pool=ctx.pool_stats(), alpha=ctx.alpha)
 
@@ -204,7 +216,8 @@ def forms_leg(args):
     return batched, serving
 
 
-DEVICE_SOURCES = ["paper_1902_04303_amd/csrc/" + f for f in ("ntt.hip", "kernels.hip", "modarith.h", "ckks_internal.h")]
+DEVICE_SOURCES = ["paper_1902_04303_amd/csrc/" + f
+                  for f in ("ntt.hip", "kernels.hip", "modarith.h", "fmod64.h", "ckks_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
@@ -217,10 +230,7 @@ def device_source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter runs (FETCH_SIZE and WRITE_SIZE, each
-    scaled by the same counter's reading for a device copy of known size), or None when there is no
-    record for this kernel or the device sources changed since the counters were taken."""
+def _counter_record():
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -228,18 +238,45 @@ def measured_traffic(kernel: str):
         return None
     if rec.get("source_sha256") != device_source_digest():
         return None
-    k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else int(k["hbm_bytes_per_launch"])
+    return rec
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter runs (FETCH_SIZE and WRITE_SIZE, each
+    scaled by the same counter's reading for a device copy of known size), or None when there is no
+    record for this kernel or the device sources changed since the counters were taken.  The figure is
+    replayed from that file, not measured in this run."""
+    rec = _counter_record()
+    k = (rec or {}).get("kernels", {}).get(kernel)
+    if k is None:
+        return None
+    return {"hbm_bytes_per_launch": int(k["hbm_bytes_per_launch"]),
+            "source": "replayed from profiles/hbm_traffic.json (rocprofv3 FETCH_SIZE, WRITE_SIZE)"}
+
+
+def measured_valu(kernel: str):
+    """VALU issue of `kernel` from the committed SQ counter run (SQ_INSTS_VALU over its busy CU cycles:
+    wave64 VALU instructions per CU per cycle, the limit being 1), or None (no record, or the device
+    sources changed since)."""
+    rec = _counter_record()
+    k = (rec or {}).get("valu", {}).get(kernel)
+    if k is None:
+        return None
+    return {"valu_insts_per_cu_cycle": k["valu_insts_per_cu_cycle"], "frac": k["valu_insts_per_cu_cycle"],
+            "source": "replayed from profiles/hbm_traffic.json (rocprofv3 SQ_INSTS_VALU, SQ_BUSY_CU_CYCLES)"}
 
 
 def roofline(kernels, warm, steps):
     """The dominant kernel (largest share of kernel time in the one-stream step where every kernel is timed),
     measured with HIP events at the start and end of its own launches over the roofline region's steps.
     A kernel that declares algorithmic FP64 operations (the key-switch inner product, bound by its modular
-    products) is placed against the FP64 vector peak, the others against HBM bandwidth."""
-    name, (cnt, tot_ms, by, fl) = max(kernels.items(), key=lambda kv: kv[1][1])
+    products) is placed against the FP64 vector peak, the others against HBM bandwidth.  Algorithmic bytes
+    count an NTT as 16 N per limb transform (8 N per pass: the first pass's reads, the second pass's
+    writes) plus a fused epilogue's operands; pass_bytes add the two-pass NTT's intermediate round trip."""
+    name, (cnt, tot_ms, by, fl, pb) = max(kernels.items(), key=lambda kv: kv[1][1])
     avg_ms = tot_ms / cnt
     gbs = (by / cnt) / (avg_ms * 1e-3) / 1e9
+    pass_gbs = (pb / cnt) / (avg_ms * 1e-3) / 1e9
     out = {"kernel": name}
     if fl > 0:
         tf = (fl / cnt) / (avg_ms * 1e-3) / 1e12
@@ -248,16 +285,87 @@ def roofline(kernels, warm, steps):
     else:
         out.update({"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbs / HBM_PEAK_GBS, 4)})
-    out.update({"traffic": measured_traffic(name), "launches_per_step": cnt // steps,
+    tr = measured_traffic(name)
+    out.update({"traffic": tr["hbm_bytes_per_launch"] if tr else None,
+                "traffic_source": tr["source"] if tr else None,
+                "launches_per_step": cnt // steps,
                 "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": int(by / cnt),
-                "algorithmic_hbm_gbs": round(gbs, 1), "algorithmic_fp64_ops_per_launch": int(fl / cnt),
+                "algorithmic_hbm_gbs": round(gbs, 1), "pass_bytes_per_launch": int(pb / cnt),
+                "pass_hbm_gbs": round(pass_gbs, 1), "pass_frac": round(pass_gbs / HBM_PEAK_GBS, 4),
+                "algorithmic_fp64_ops_per_launch": int(fl / cnt),
                 "share_of_kernel_time": round(warm[name][1] / sum(v[1] for v in warm.values()), 3)})
+    v = measured_valu(name)
+    if v:
+        out["valu"] = v
+    return out
+
+
+def keyswitch_roofline(ks, steps):
+    """Whole key switches (ModUp, inner product, ModDown: every kernel between the events around a key
+    switch) against HBM: algorithmic bytes 8 N [count l + keys 2 G (l + alpha) + count 4 l] per call."""
+    if not ks:
+        return None
+    cnt, ms, by, _, _ = ks
+    gbs = by / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "calls_per_step": cnt // steps,
+            "ms_per_step": round(ms / steps, 3), "algorithmic_bytes_per_step": int(by / steps)}
+
+
+def ntt_aggregate(warm, limb_ntts):
+    """Every NTT pass of one step (one stream, every kernel timed) against the transforms' own bytes:
+    limb transforms x 16 N over the summed pass time."""
+    ms = sum(v[1] for k, v in warm.items() if k.startswith("ntt_pass<"))
+    by = limb_ntts * 16.0 * (1 << LOG_N)
+    gbs = by / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "limb_transforms_per_step": int(limb_ntts),
+            "ms_per_step": round(ms, 3)}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_op_times(C, G, p, o, rng):
+    """Per-operation times of the oracle at the workload's ring (N = 2^16): one limb NTT, a key switch
+    (relinearisation key) at 6, 15 and 27 limbs, a tensor product and a rescale at 27 limbs (ms)."""
+    def rand_ct(depth):
+        l = p.limbs_at_depth(depth)
+        return C.Ct(np.stack([np.stack([rng.integers(0, q, size=p.N, dtype=np.uint64) for q in p.q[:l]])
+                              for _ in range(2)]), depth, p.scales[depth])
+
+    def timed(f, reps=1):
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            f()
+        return round((time.perf_counter() - t0) * 1e3 / reps, 3)
+
+    out = {}
+    a = rand_ct(0)
+    limb = np.ascontiguousarray(a.data[0, 1])
+    ev = np.empty_like(limb)
+    out["limb_ntt_ms"] = timed(lambda: C.lib().ref_to_eval(o._ctx, 1, C._p(limb), C._p(ev)), 5)
+    for l in (6, 15, 27):
+        d = np.ascontiguousarray(rand_ct(p.L + 1 - l).data[1])
+        out["keyswitch_l%d_ms" % l] = timed(lambda: o.keyswitch(d, 0))
+    b = rand_ct(0)
+    out["tensor_l27_ms"] = timed(lambda: o.tensor([(a, b)]))
+    out["rescale_l27_ms"] = timed(lambda: o.rescale(a))
     return out
 
 
 def cpu_baseline_leg(alpha: int):
-    """The CPU oracle on a bounded sample of the same workload: the per-batch part of one SNP batch
-    (256 SNPs; the fixed logistic-regression part is excluded, which favours the CPU)."""
+    """The CPU oracle on a bounded sample of the same workload: the per-batch part of whole 256-SNP batches
+    (the fixed logistic-regression part is excluded, which favours the CPU), on every host thread; plus
+    per-operation times on one thread and on every thread, and the FP64 plaintext GWAS."""
     from oracle import ckks as C
     from oracle import gwas_circuit as G
     from oracle import gwas_fp64 as F
@@ -270,9 +378,12 @@ def cpu_baseline_leg(alpha: int):
     ds = G.snp_depth(KAPPA)
     o = C.Oracle(p)
     t0 = time.time()
-    o.keygen(7, G.required_galois(p.N, lay.R), max_limbs=p.limbs_at_depth(ds))
-    log("[bench] cpu oracle keygen (low-level key block) %.1fs" % (time.time() - t0))
+    # the per-batch keys at the batch levels; relinearisation at full height for the per-operation times
+    o.keygen(7, G.required_galois(p.N, lay.R), max_limbs=p.limbs_at_depth(ds), key_limbs={0: p.L + 1})
+    log("[bench] cpu oracle keygen %.1fs" % (time.time() - t0))
+    t0 = time.perf_counter()
     ref = F.modified_gwas(d.X, d.y, d.S, KAPPA)
+    fp64_ms = (time.perf_counter() - t0) * 1e3
     A = F.xtx_inverse(d.X)
     enc = lambda v, depth, i: o.encrypt(C.encode(G.periodic_slots(v, lay), p.N, p.scales[depth]), depth,  # noqa
                                         p.scales[depth], 1000 + i)
@@ -294,10 +405,30 @@ def cpu_baseline_leg(alpha: int):
         nb += 1
     cores = int(C.lib().ref_num_threads())
     log("[bench] cpu oracle: %d SNP batches (%d SNPs) in %.1fs on %d threads" % (nb, nb * lay.tau, t, cores))
+    rng = np.random.default_rng(5)
+    ops_all = oracle_op_times(C, G, p, o, rng)
+    C.lib().ref_set_threads(1)
+    try:
+        ops_one = oracle_op_times(C, G, p, o, rng)
+    finally:
+        C.lib().ref_set_threads(0)
+    log("[bench] cpu oracle per-op ms, %d threads: %s; 1 thread: %s" % (cores, ops_all, ops_one))
+    whole = None
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", "circuit_digests.json")) as fh:
+            rec = json.load(fh)["gwas_n245_k4_m10643"]
+        whole = {"seconds": rec["oracle_circuit_seconds"], "threads": rec["oracle_threads"],
+                 "source": "whole circuit (fixed part and 42 SNP batches) timed offline by "
+                           "tests/golden/make_circuit_digests.py on another host"}
+    except (OSError, KeyError, ValueError):
+        pass
     return {"value": round(nb * lay.tau / t, 3), "unit": "SNPs/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": "per-batch part of the first %d 256-SNP batches of the same workload (S' = M S, numerator, "
-                      "both denominators; %d key switches at <= 6 limbs), %.1f s of oracle time; the fixed "
-                      "logistic-regression part is excluded" % (nb, o.n_keyswitch - ks0, t)}
+                      "both denominators; %d key switches at <= 6 limbs), %.1f s of oracle time on %d threads; "
+                      "the fixed logistic-regression part is excluded" % (nb, o.n_keyswitch - ks0, t, cores),
+            "per_op_ms_all_threads": ops_all, "per_op_ms_one_thread": ops_one,
+            "fp64_plaintext_gwas_ms": round(fp64_ms, 2), "whole_job_oracle": whole}
 
 
 def copy_calibration(nbytes: int) -> int:
@@ -323,6 +454,8 @@ def run(args) -> int:
     batched = serving = None
     if args.forms_jobs > 0:
         batched, serving = forms_leg(args)
+    ks = keyswitch_roofline(g["keyswitch"], args.steps)
+    ntt = ntt_aggregate(g["warm_kernels"], g["counters"]["limb_ntts"])
     line = {
         "metric": "encrypted SNPs/s at 245x4x10643",
         "value": round(value, 1),
@@ -341,6 +474,8 @@ def run(args) -> int:
                    "snp_batches": 42,
                    "parallelism": "1 GPU"},
         "roofline": rl,
+        "keyswitch": ks,
+        "ntt_all_passes": ntt,
         "cpu_baseline": cpu,
         "batched": batched,
         "serving": serving,

@@ -127,8 +127,22 @@ uint64_t ckks_galois_conj(const ckks_ctx *ctx);
  * G = 1 + floor((L+1)/alpha) groups, targets q_0..q_L then p_1..p_alpha.
  * Secret: [N] int64; public key: [2][L+1][N]. */
 int ckks_export_switching_key(ckks_ctx *ctx, uint64_t key_id, uint64_t *buf, size_t cap_words);
+/* CKKS_E_KEY_MISSING in a context that holds no secret (one that only imported keys). */
 int ckks_export_secret(ckks_ctx *ctx, int64_t *buf, size_t cap);
 int ckks_export_public_key(ckks_ctx *ctx, uint64_t *buf, size_t cap_words);
+
+/* Client and server (paper: Introduction and Methods: the data owner encrypts and decrypts, the server
+ * computes on ciphertexts only).  An evaluating context is created with ckks_ctx_create and never runs
+ * ckks_keygen: it imports the public key and the switching keys the client exported (canonical
+ * coefficient form, the layouts of the exports above: words = 2 (L+1) N for the public key and
+ * 2 G (L+1+alpha) N for a switching key; every residue below its modulus, else CKKS_E_INVALID_ARG).  It
+ * holds no secret: ckks_decrypt, ckks_decrypt_poly, gwas_finalize and ckks_export_secret return
+ * CKKS_E_KEY_MISSING there, and encryption needs an imported public key.  Importing a key id that is
+ * present replaces it.  The buffers stay the caller's. */
+int ckks_import_public_key(ckks_ctx *ctx, const uint64_t *buf, size_t words);
+int ckks_import_switching_key(ckks_ctx *ctx, uint64_t key_id, const uint64_t *buf, size_t words);
+/* 1 when the context holds the secret (it ran ckks_keygen), else 0 (also for NULL). */
+int ckks_ctx_has_secret(const ckks_ctx *ctx);
 
 /* ---------------------------------------------------------------- encode / encrypt / decrypt */
 
@@ -226,6 +240,10 @@ int gwas_pack_encrypt(ckks_ctx *ctx, const double *X, const double *y, const uin
 int gwas_input_from_cts(ckks_ctx *ctx, int n, int k, int m, int kappa, ckks_ct *const *x, const ckks_ct *y,
                         ckks_ct *const *A, ckks_ct *const *S, int n_s, gwas_enc_input **out);
 void gwas_input_free(gwas_enc_input *in);
+/* Input ciphertexts, e.g. for export to a server: which = 0 x_j (index j), 1 y, 2 A (index in row-major
+ * upper-triangle order), 3 the SNP batches (one batch handle, index 0; CKKS_E_INVALID_ARG once spilled).
+ * The handle stays owned by the input. */
+int gwas_input_ct(const gwas_enc_input *in, int which, int index, const ckks_ct **ct);
 
 /* Server side (the hot path): the encrypted circuit.  Fails with CKKS_E_LEVEL or
  * CKKS_E_KEY_MISSING before any launch when the chain or keys do not fit.  The SNP
@@ -236,6 +254,10 @@ int gwas_semiparallel_chunked(ckks_ctx *ctx, const gwas_enc_input *in, int chunk
  * index = chunk number, each a batch of up to `chunk` ciphertexts in SNP-batch order;
  * 4 beta_j (index j), 5 w, 6 w^-1, 7 z', 8 u = w z'.  The handle stays owned by out. */
 int gwas_output_ct(const gwas_enc_output *out, int which, int index, const ckks_ct **ct);
+/* Client side: an output assembled from the server's num, den_even and den_odd ciphertexts (one per SNP
+ * batch, n_batches of each, e.g. imported with ckks_ct_import), for gwas_finalize; the handles are copied. */
+int gwas_output_from_cts(ckks_ctx *ctx, int n, int k, int m, ckks_ct *const *num, ckks_ct *const *den_even,
+                         ckks_ct *const *den_odd, int n_batches, gwas_enc_output **out);
 int gwas_output_batches(const gwas_enc_output *out, int *n_batches);
 void gwas_output_free(gwas_enc_output *out);
 
@@ -248,14 +270,22 @@ int gwas_finalize(ckks_ctx *ctx, const gwas_enc_output *out, int m, double *b, d
  * every launch of the instrumented kernels (hipExtLaunchKernelGGL), on the stream
  * each kernel is launched on.  enable = 1 clears the counters and starts
  * recording; 0 stops.  The report is text, one line per kernel:
- * "name launches total_ms algorithmic_bytes algorithmic_fp64_ops" (the name, a kernel symbol such as
- * "ntt_pass<false, true, 8, 0>", may contain spaces; the last four fields are numbers; the FP64 operation
- * count is 0 for kernels bound by memory rather than arithmetic).
+ * "name launches total_ms algorithmic_bytes algorithmic_fp64_ops pass_bytes" (the name, a kernel symbol
+ * such as "ntt_pass<false, true, 8, 0>", may contain spaces; the last five fields are numbers).
+ * algorithmic_bytes count each distinct word a launch must read and each word it must write once; an NTT
+ * is 16 N bytes per limb transform, its first pass credited with the reads and its second with the writes
+ * (plus operands of a fused epilogue).  pass_bytes count what a pass moves when it reads and writes every
+ * word once itself (the two-pass NTT's intermediate round trip included).  The FP64 operation count is 0
+ * for kernels bound by memory rather than arithmetic.
  * While two streams run at once a kernel's interval includes waiting for workgroup
  * slots held by the other stream's kernels (see ckks_ctx_set_streams). */
 int ckks_ctx_kernel_timing(ckks_ctx *ctx, int enable);
 /* Restrict recording to launches of one kernel name (as it appears in the report), so that timing a
- * single kernel adds two event records per launch of that kernel only; NULL or "" records all. */
+ * single kernel adds two event records per launch of that kernel only; NULL or "" records all kernels.
+ * The name "keyswitch" records whole key switches instead (events on the stream before the first and
+ * after the last kernel of each key switch; algorithmic bytes 8 N [count l (input) + keys 2 G (l + alpha)
+ * (key words of the G digit groups below l, read once per call) + count 4 l (two outputs read and
+ * written)]); it is meaningful with one compute stream (ckks_ctx_set_streams(ctx, 1)). */
 int ckks_ctx_kernel_timing_only(ckks_ctx *ctx, const char *name);
 int ckks_ctx_kernel_report(ckks_ctx *ctx, char *buf, size_t cap);
 /* Number of compute streams the GWAS circuit may use: 2 (the default) runs the
@@ -289,11 +319,15 @@ int gwas_input_spill(ckks_ctx *ctx, gwas_enc_input *in);
  * from other threads are serialised with the worker. */
 int gwas_server_create(ckks_ctx *ctx, size_t hbm_budget_bytes, int max_jobs_in_flight, int chunk,
                        gwas_server **out);
-/* Ownership of `in` passes to the server. */
+/* Ownership of `in` passes to the server when the call succeeds; when it fails the input is unchanged and
+ * still the caller's. */
 int gwas_server_submit(gwas_server *s, gwas_enc_input *in, uint64_t *job_id);
 /* CKKS_OK with *out set (ownership passes to the caller) when the job is done; CKKS_E_NOT_READY when
  * it is not (wait = 0) ; wait = 1 blocks until it is done; CKKS_E_CANCELLED for a cancelled job. */
 int gwas_server_poll(gwas_server *s, uint64_t job_id, int wait, gwas_enc_output **out);
+/* Cancel a queued, admitted or running job (a finished job is left as it is).  Its device memory and its
+ * share of the budget are released by the worker as soon as no launch in flight reads them; polling it
+ * then returns CKKS_E_CANCELLED. */
 int gwas_server_cancel(gwas_server *s, uint64_t job_id);
 /* Latency percentiles (completion - submission) over completed jobs, completed jobs per second
  * (first submission to last completion), and the largest number of jobs in flight together. */

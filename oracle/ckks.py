@@ -104,6 +104,7 @@ def lib():
                                   ctypes.c_uint64, ctypes.c_int, _u64p]
         L.ref_key_to_eval.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64p, _u64p]
         L.ref_num_threads.restype = ctypes.c_int
+        L.ref_set_threads.argtypes = [ctypes.c_int]
         L.ref_gen_pk.argtypes = [ctypes.c_void_p, ctypes.c_int, _i64p, ctypes.c_uint64, ctypes.c_uint64,
                                  ctypes.c_uint64, _u64p]
         L.ref_encrypt.argtypes = [ctypes.c_void_p, ctypes.c_int, _u64p, ctypes.c_int, _i64p, ctypes.c_uint64,
@@ -465,11 +466,15 @@ class Oracle:
             pass
 
     # ---------------- key generation ----------------
-    def keygen(self, seed: int, galois: Sequence[int], relin: bool = True, max_limbs: Optional[int] = None) -> None:
+    def keygen(self, seed: int, galois: Sequence[int], relin: bool = True, max_limbs: Optional[int] = None,
+               key_limbs: Optional[Dict[int, int]] = None) -> None:
         """Keys of the scheme.  max_limbs restricts the switching keys to the digits and targets a
-        ciphertext of at most that many limbs uses (the entries are the same as in the full key)."""
+        ciphertext of at most that many limbs uses (the entries are the same as in the full key);
+        key_limbs overrides that limit per key id (0: relinearisation, else the Galois element)."""
         p = self.p
         self._max_l = p.L + 1 if max_limbs is None else int(max_limbs)
+        self._key_l: Dict[int, int] = {}
+        self._key_limbs = dict(key_limbs or {})
         N, L = p.N, p.L
         s = np.zeros(N, dtype=np.int64)
         lib().ref_sample_hwt(seed, SID_SECRET, N, secret_weight(N), _p(s))
@@ -500,13 +505,16 @@ class Oracle:
     def _add_key(self, K: int, sp: np.ndarray) -> None:
         p = self.p
         N, L = p.N, p.L
+        ml = min(p.L + 1, int(self._key_limbs.get(K, self._max_l)))
+        # np.zeros maps untouched pages lazily, so a key restricted to a few limbs holds only those entries
         key = np.zeros((2, self.ng, L + 1 + self.alpha, N), dtype=np.uint64)
         lib().ref_gen_ksk(self._ctx, L, self.alpha, _p(self.sk), _p(np.ascontiguousarray(sp)), self._seed,
-                          ksk_sid_base(K), self._max_l, _p(key))
-        kev = np.zeros_like(key)
-        lib().ref_key_to_eval(self._ctx, L, self.alpha, self._max_l, _p(key), _p(kev))
+                          ksk_sid_base(K), ml, _p(key))
+        kev = np.zeros(key.shape, dtype=np.uint64)
+        lib().ref_key_to_eval(self._ctx, L, self.alpha, ml, _p(key), _p(kev))
         self.keys[K] = key
         self._kev[K] = kev
+        self._key_l[K] = ml
 
     # ---------------- encryption ----------------
     def encrypt(self, m: np.ndarray, depth: int, scale: float, seed: int) -> Ct:
@@ -635,8 +643,9 @@ class Oracle:
         is taken modulo the target moduli first and then permuted by its automorphism (g = 0: none),
         and all products are summed before the single division by P."""
         l = d.shape[0]
-        if l > self._max_l:
-            raise ValueError("keys were generated for at most %d limbs" % self._max_l)
+        for _, K in pairs:
+            if l > self._key_l[K]:
+                raise ValueError("key %d was generated for at most %d limbs" % (K, self._key_l[K]))
         p = self.p
         out = np.zeros((2, l, p.N), dtype=np.uint64)
         gal = np.array([g for g, _ in pairs], dtype=np.uint64)

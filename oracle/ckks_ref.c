@@ -651,6 +651,9 @@ int ref_num_threads(void) {
     return n;
 }
 
+/* set the number of OpenMP threads of later calls (n <= 0: one per processor) */
+void ref_set_threads(int n) { omp_set_num_threads(n > 0 ? n : omp_get_num_procs()); }
+
 /* s^2 mod each q_t, t < nl (the relinearisation key's target secret) */
 void ref_secret_square(const ref_ctx *c, int nl, const i64 *s, u64 *out) {
     int n = c->n;

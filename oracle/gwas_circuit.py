@@ -9,10 +9,12 @@ Alg. "inverseSlots") step by step on oracle ciphertexts.  Layouts:
   Matrices") already duplicated into every block (Alg. Duplicate done by the
   client).  On such data the rotate-and-sum of Alg. DotProd leaves the full dot
   product in every slot.  The rotate-and-sum adds Rot(a, i) for every i < R; it
-  is taken as groups a <- a + Rot(a, s) + Rot(a, 2s) + Rot(a, 3s), s = 1, 4, 16, ...
-  (one shared key switch per group, Oracle.rotate_sum), which sums the same
-  rotations as the log2(R) doubling steps of Alg. colSum with half the key-switch
-  decompositions.
+  is taken as groups a <- a + sum_{0 < j < m} Rot(a, j s) with one shared key
+  switch per group (Oracle.rotate_sum), m = min(radix, R / s) and the next group
+  starting at shift m s (rotation_groups): radix 8 in the fixed part ({1..7},
+  {8, 16, .., 56}, {64, 128, 192} for R = 256) and radix 16 per SNP batch
+  ({1..15}, {16, 32, .., 240}).  This sums the same rotations as the log2(R)
+  doubling steps of Alg. colSum with fewer key switches.
 * Entries of A = (X^T X)^-1 are replicated scalars (the same value in every slot).
 * A SNP batch is a CCP matrix (Methods, "Column-Compact-Packed Matrices") with
   two SNPs per complex slot (Methods, "Complex Space of CKKS ciphertext"):

@@ -83,15 +83,16 @@ class GwasResult:
     se: np.ndarray        # sqrt(err')
 
 
-def homomorphic_logreg_plain(X: np.ndarray, y: np.ndarray, A: np.ndarray, kappa: int):
+def homomorphic_logreg_plain(X: np.ndarray, y: np.ndarray, A: np.ndarray, kappa: int, sig=None):
     """Alg. Homomorphic LogReg in FP64: kappa fixed-Hessian Newton steps from beta = 0.
 
-    Returns (beta^(kappa), p^(kappa-1)).
+    sig is the sigmoid (default: the degree-7 approximation sigma7).  Returns (beta^(kappa), p^(kappa-1)).
     """
+    sig = sigma7 if sig is None else sig
     beta = np.zeros(X.shape[1])
     p = None
     for _ in range(kappa):
-        p = sigma7(X @ beta)
+        p = sig(X @ beta)
         g = X.T @ (y - p)
         beta = beta + 4.0 * (A @ g)
     return beta, p

@@ -84,6 +84,9 @@ _SIGS = [
     ("ckks_export_switching_key", ctypes.c_int, [_vp, ctypes.c_uint64, _u64p, ctypes.c_size_t]),
     ("ckks_export_secret", ctypes.c_int, [_vp, _i64p, ctypes.c_size_t]),
     ("ckks_export_public_key", ctypes.c_int, [_vp, _u64p, ctypes.c_size_t]),
+    ("ckks_import_public_key", ctypes.c_int, [_vp, _u64p, ctypes.c_size_t]),
+    ("ckks_import_switching_key", ctypes.c_int, [_vp, ctypes.c_uint64, _u64p, ctypes.c_size_t]),
+    ("ckks_ctx_has_secret", ctypes.c_int, [_vp]),
     ("ckks_encode", ctypes.c_int, [_vp, _dp, _dp, ctypes.c_size_t, ctypes.c_double, _i64p]),
     ("ckks_decode", ctypes.c_int, [_vp, _dp, _dp, _dp]),
     ("ckks_encrypt", ctypes.c_int, [_vp, _i64p, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(_vp)]),
@@ -118,6 +121,10 @@ _SIGS = [
                                            ctypes.POINTER(_vp), _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                            ctypes.c_int, ctypes.POINTER(_vp)]),
     ("gwas_input_free", None, [_vp]),
+    ("gwas_input_ct", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]),
+    ("gwas_output_from_cts", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp),
+                                            ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int,
+                                            ctypes.POINTER(_vp)]),
     ("gwas_semiparallel", ctypes.c_int, [_vp, _vp, ctypes.POINTER(_vp)]),
     ("gwas_semiparallel_chunked", ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(_vp)]),
     ("gwas_output_ct", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]),
@@ -329,13 +336,14 @@ class Context:
         _check(lib().ckks_ctx_set_streams(self.h, int(n)))
 
     def kernel_report(self):
-        """{kernel: (launches, total_ms, algorithmic_bytes, algorithmic_fp64_ops)} from the HIP-event timing."""
+        """{kernel: (launches, total_ms, algorithmic_bytes, algorithmic_fp64_ops, pass_bytes)} from the
+        HIP-event timing ("keyswitch": whole key switches, when selected with kernel_timing_only)."""
         buf = ctypes.create_string_buffer(1 << 16)
         _check(lib().ckks_ctx_kernel_report(self.h, buf, len(buf)))
         out = {}
         for line in buf.value.decode().splitlines():
-            name, cnt, ms, by, fl = line.rsplit(None, 4)   # kernel names may contain spaces
-            out[name] = (int(cnt), float(ms), float(by), float(fl))
+            name, cnt, ms, by, fl, pb = line.rsplit(None, 5)   # kernel names may contain spaces
+            out[name] = (int(cnt), float(ms), float(by), float(fl), float(pb))
         return out
 
     # ---- keys
@@ -364,6 +372,17 @@ class Context:
         a = np.zeros((2, self.levels + 1, self.N), dtype=np.uint64)
         _check(lib().ckks_export_public_key(self.h, _u64(a), a.size))
         return a
+
+    def import_public_key(self, a: np.ndarray):
+        a = np.ascontiguousarray(a, dtype=np.uint64)
+        _check(lib().ckks_import_public_key(self.h, _u64(a), a.size))
+
+    def import_switching_key(self, key_id: int, a: np.ndarray):
+        a = np.ascontiguousarray(a, dtype=np.uint64)
+        _check(lib().ckks_import_switching_key(self.h, key_id, _u64(a), a.size))
+
+    def has_secret(self) -> bool:
+        return bool(lib().ckks_ctx_has_secret(self.h))
 
     # ---- encode / encrypt / decrypt
     def encode(self, z: np.ndarray, scale: float) -> np.ndarray:
@@ -477,6 +496,14 @@ class Context:
         _check(lib().gwas_input_from_cts(self.h, n, k, m, kappa, xa, y.h, aa, sa, len(S), ctypes.byref(out)))
         return GwasInput(self, out.value, n, k, m, kappa)
 
+    def gwas_output_from_cts(self, n, k, m, num: Sequence[Ciphertext], den_even: Sequence[Ciphertext],
+                             den_odd: Sequence[Ciphertext]) -> "GwasOutput":
+        arr = lambda v: (_vp * len(v))(*[c.h for c in v])  # noqa: E731
+        out = _vp()
+        _check(lib().gwas_output_from_cts(self.h, n, k, m, arr(num), arr(den_even), arr(den_odd), len(num),
+                                          ctypes.byref(out)))
+        return GwasOutput(self, out.value, m)
+
     def gwas_semiparallel(self, inp: "GwasInput", chunk: Optional[int] = None) -> "GwasOutput":
         out = _vp()
         if chunk is None:
@@ -511,6 +538,15 @@ class GwasInput:
             lib().gwas_input_free(self.h)
             self.h = None
 
+    X, Y, A, S = range(4)
+
+    def ct(self, which: int, index: int = 0) -> Ciphertext:
+        out = _vp()
+        _check(lib().gwas_input_ct(self.h, which, index, ctypes.byref(out)))
+        ct = Ciphertext(self.ctx, out.value, owned=False)
+        ct._parent = self   # the handle belongs to this input
+        return ct
+
     def footprint(self) -> int:
         v = ctypes.c_size_t()
         _check(lib().gwas_input_footprint(self.h, ctypes.byref(v)))
@@ -532,7 +568,7 @@ class GwasServer:
     def submit(self, inp: GwasInput) -> int:
         jid = ctypes.c_uint64()
         _check(lib().gwas_server_submit(self.h, inp.h, ctypes.byref(jid)))
-        inp.h = None          # owned by the server now
+        inp.h = None          # owned by the server now (a failed submit leaves it with the caller)
         return jid.value
 
     def poll(self, job_id: int, m: int, wait: bool = False) -> Optional["GwasOutput"]:
@@ -580,4 +616,6 @@ class GwasOutput:
     def ct(self, which: int, index: int = 0) -> Ciphertext:
         out = _vp()
         _check(lib().gwas_output_ct(self.h, which, index, ctypes.byref(out)))
-        return Ciphertext(self.ctx, out.value, owned=False)
+        ct = Ciphertext(self.ctx, out.value, owned=False)
+        ct._parent = self   # the handle belongs to this output: keep it alive while the ciphertext is used
+        return ct

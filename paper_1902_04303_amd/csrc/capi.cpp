@@ -397,8 +397,8 @@ int ckks_ctx_kernel_report(ckks_ctx *ctx, char *buf, size_t cap) {
         char line[256];
         for (size_t i = 0; i < ctx->timer.names.size(); ++i) {
             const auto &st = ctx->timer.stats[i];
-            std::snprintf(line, sizeof line, "%s %llu %.6f %.0f %.0f\n", ctx->timer.names[i].c_str(),
-                          (unsigned long long)st.count, st.ms, st.bytes, st.flops);
+            std::snprintf(line, sizeof line, "%s %llu %.6f %.0f %.0f %.0f\n", ctx->timer.names[i].c_str(),
+                          (unsigned long long)st.count, st.ms, st.bytes, st.flops, st.pass_bytes);
             s += line;
         }
         need(s.size() + 1 <= cap, "report buffer too small");
@@ -437,7 +437,7 @@ int ckks_export_switching_key(ckks_ctx *ctx, uint64_t key_id, uint64_t *buf, siz
 int ckks_export_secret(ckks_ctx *ctx, int64_t *buf, size_t cap) {
     return guard_ctx(ctx, [&] {
         need(ctx && buf && cap >= (size_t)ctx->p.n, "bad buffer");
-        if (!ctx->have_keys) throw Error(CKKS_E_KEY_MISSING, "keygen has not been run");
+        if (!ctx->have_secret) throw Error(CKKS_E_KEY_MISSING, "no secret key in this context");
         std::memcpy(buf, ctx->sk.data(), (size_t)ctx->p.n * 8);
     });
 }
@@ -445,7 +445,7 @@ int ckks_export_secret(ckks_ctx *ctx, int64_t *buf, size_t cap) {
 int ckks_export_public_key(ckks_ctx *ctx, uint64_t *buf, size_t cap_words) {
     return guard_ctx(ctx, [&] {
         need(ctx && buf, "null argument");
-        if (!ctx->have_keys) throw Error(CKKS_E_KEY_MISSING, "keygen has not been run");
+        if (!ctx->have_pk) throw Error(CKKS_E_KEY_MISSING, "no public key in this context");
         const int l = ctx->p.levels + 1;
         const size_t N = (size_t)ctx->p.n, words = (size_t)2 * l * N;
         need(cap_words >= words, "buffer too small");
@@ -456,6 +456,25 @@ int ckks_export_public_key(ckks_ctx *ctx, uint64_t *buf, size_t cap_words) {
         sync(*ctx);
     });
 }
+
+int ckks_import_public_key(ckks_ctx *ctx, const uint64_t *buf, size_t words) {
+    return guard_ctx(ctx, [&] {
+        need(ctx && buf, "null argument");
+        need(words == (size_t)2 * (ctx->p.levels + 1) * ctx->p.n, "public key size does not match the parameters");
+        import_public_key(*ctx, buf);
+    });
+}
+
+int ckks_import_switching_key(ckks_ctx *ctx, uint64_t key_id, const uint64_t *buf, size_t words) {
+    return guard_ctx(ctx, [&] {
+        need(ctx && buf, "null argument");
+        need(words == (size_t)2 * ctx->ng * ctx->p.n_mods() * ctx->p.n,
+             "switching key size does not match the parameters");
+        import_switching_key(*ctx, key_id, buf);
+    });
+}
+
+int ckks_ctx_has_secret(const ckks_ctx *ctx) { return ctx && ctx->have_secret ? 1 : 0; }
 
 int ckks_encode(ckks_ctx *ctx, const double *re, const double *im, size_t n, double scale, int64_t *coeffs_out) {
     return guard_ctx(ctx, [&] {
@@ -705,6 +724,54 @@ int gwas_input_from_cts(ckks_ctx *ctx, int n, int k, int m, int kappa, ckks_ct *
 }
 
 void gwas_input_free(gwas_enc_input *in) { delete in; }
+
+int gwas_input_ct(const gwas_enc_input *in, int which, int index, const ckks_ct **ct) {
+    return guard([&] {
+        need(in && ct, "null argument");
+        const EncInput &e = *in->in;
+        switch (which) {
+        case 0:
+            need(index >= 0 && index < (int)e.x.size(), "x index out of range");
+            *ct = e.x[index].get();
+            return;
+        case 1: *ct = e.y.get(); return;
+        case 2:
+            need(index >= 0 && index < (int)e.A.size(), "A index out of range");
+            *ct = e.A[index].get();
+            return;
+        case 3:
+            need(!e.S_host && e.S->data.ptr, "the SNP batches are spilled to the host");
+            *ct = e.S.get();
+            return;
+        default: need(false, "unknown input");
+        }
+    });
+}
+
+int gwas_output_from_cts(ckks_ctx *ctx, int n, int k, int m, ckks_ct *const *num, ckks_ct *const *den_even,
+                         ckks_ct *const *den_odd, int n_b, gwas_enc_output **out) {
+    return guard_ctx(ctx, [&] {
+        need(ctx && num && den_even && den_odd && out, "null argument");
+        auto o = std::make_unique<gwas_enc_output>();
+        o->ctx = ctx;
+        o->lay = make_layout(ctx->p.n, n, k, m);
+        need(n_b == o->lay.n_batches, "wrong number of SNP batches");
+        auto gather_all = [&](ckks_ct *const *v) {
+            std::vector<const ckks_ct *> parts;
+            for (int b = 0; b < n_b; ++b) {
+                check_ct(ctx, v[b]);
+                need(v[b]->count == 1, "one ciphertext per SNP batch");
+                parts.push_back(v[b]);
+            }
+            return stack(*ctx, parts);
+        };
+        o->out.num.push_back(gather_all(num));
+        o->out.den_even.push_back(gather_all(den_even));
+        o->out.den_odd.push_back(gather_all(den_odd));
+        o->out.chunk = n_b;
+        *out = o.release();
+    });
+}
 
 int gwas_input_spill(ckks_ctx *ctx, gwas_enc_input *in) {
     return guard_ctx(ctx, [&] {

@@ -133,14 +133,16 @@ inline ModMap map_q(int l) { return ModMap{l, l, 0}; }
 
 // Optional per-kernel timing (off by default).  Each timed launch carries a start and a stop event that
 // the runtime sets when the kernel itself starts and ends (hipExtLaunchKernelGGL), so the time excludes
-// waiting for workgroup slots behind kernels of another stream.
+// waiting for workgroup slots behind kernels of another stream.  A region (e.g. "keyswitch": every kernel
+// of one key switch) is timed by events recorded on its stream before its first and after its last
+// launch; regions are recorded only when `only` names them.
 struct KTimer {
     bool on = false;
-    std::string only;   // when not empty, only launches of this name are recorded
+    std::string only;   // when not empty, only launches (or regions) of this name are recorded
     struct Rec {
         int id;
         hipEvent_t a, b;
-        double bytes, flops;
+        double bytes, flops, pass_bytes;
         bool launched;
     };
     std::vector<Rec> recs;
@@ -149,15 +151,36 @@ struct KTimer {
     std::map<std::string, int> ids;
     struct Stat {
         uint64_t count = 0;
-        double ms = 0, bytes = 0, flops = 0;   // algorithmic HBM bytes and FP64 operations (0: not declared)
+        // algorithmic HBM bytes (each word of a transform read and written once over its two passes) and
+        // FP64 operations (0: not declared), and the bytes a pass moves when it reads and writes each word
+        // once itself
+        double ms = 0, bytes = 0, flops = 0, pass_bytes = 0;
     };
     std::vector<Stat> stats;
     hipEvent_t take();
-    int begin(const char *name, double bytes, double flops, hipStream_t st);
+    int id_of(const char *name);
+    int begin(const char *name, double bytes, double flops, hipStream_t st, double pass_bytes = -1);
     void end(int idx, hipStream_t st);
+    int region_begin(const char *name, double bytes, hipStream_t st);
+    void region_end(int idx, hipStream_t st);
     void collect();   // synchronises, folds recorded events into stats
     void reset();
     ~KTimer();
+};
+
+// RAII timing of a region of launches on one stream (recorded when the timer is on and `only` names it)
+struct KRegion {
+    KTimer *t;
+    int idx = -1;
+    hipStream_t st;
+    KRegion(KTimer *timer, const char *name, double bytes, hipStream_t s) : t(timer), st(s) {
+        if (t && t->on) idx = t->region_begin(name, bytes, st);
+    }
+    ~KRegion() {
+        if (idx >= 0) t->region_end(idx, st);
+    }
+    KRegion(const KRegion &) = delete;
+    KRegion &operator=(const KRegion &) = delete;
 };
 
 struct DevTables {

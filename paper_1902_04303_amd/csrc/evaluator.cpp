@@ -400,6 +400,13 @@ static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, const KsKe
     const size_t N = (size_t)c.p.n;
     const ckks_ctx::KsLevel &kl = c.ks_levels.at(l);
     const int a = c.p.alpha, nt = l + a, P = c.p.p_index();
+    // algorithmic bytes of the key switch: the input polynomial (l limbs per ciphertext), each key's digit
+    // groups below l at every target (read once per call, shared by the ciphertexts) and the two output
+    // polynomials read and written once (2 x 2 l limbs per ciphertext)
+    const int groups = 1 + l / a;
+    const double ks_bytes = 8.0 * (double)N *
+                            ((double)count * l + (double)keys.m * 2.0 * groups * nt + (double)count * 4.0 * l);
+    KRegion region_(c.tab.timer, "keyswitch", ks_bytes, c.stream);
     DBuf dc(c.pool.get(), (size_t)count * l * N);
     k_ntt_inverse_g(c.tab, dc.ptr, d, count * l, map_q(l), c.stream, kl.up_scale, l);
     DBuf dig(c.pool.get(), (size_t)count * kl.K * N);
@@ -651,12 +658,55 @@ void keygen(ckks_ctx &c, u64 seed, const std::vector<u64> &galois) {
         k_automorph(c.tab, sp.ptr, c.sk_ntt.ptr, L + 1, g, c.stream);
         make_switching_key(c, seed, g, sp.ptr);
     }
-    c.have_keys = true;
+    c.have_secret = true;
+    c.have_pk = true;
     sync(c);
 }
 
+// every residue of limb i of buf (limbs of N words) below the modulus of chain index chain(i)
+template <typename F>
+static void check_residues(const ckks_ctx &c, const u64 *buf, size_t limbs, F chain) {
+    const size_t N = (size_t)c.p.n;
+    for (size_t i = 0; i < limbs; ++i) {
+        const u64 q = c.h_mods[chain(i)].q;
+        const u64 *row = buf + i * N;
+        for (size_t k = 0; k < N; ++k)
+            if (row[k] >= q) throw Error(CKKS_E_INVALID_ARG, "imported key residue out of range");
+    }
+}
+
+void import_public_key(ckks_ctx &c, const u64 *buf) {
+    const int l = c.p.levels + 1;
+    const size_t N = (size_t)c.p.n;
+    check_residues(c, buf, (size_t)2 * l, [&](size_t i) { return (int)(i % l); });
+    DBuf pk(c.pool.get(), (size_t)2 * l * N);
+    GCK_HIP(hipMemcpyAsync(pk.ptr, buf, (size_t)2 * l * N * 8, hipMemcpyHostToDevice, c.stream));
+    ntt_fwd(c, pk.ptr, 2 * l, map_q(l));
+    sync(c);   // the caller's buffer may be reused after return
+    c.pk = std::move(pk);
+    c.have_pk = true;
+}
+
+void import_switching_key(ckks_ctx &c, u64 key_id, const u64 *buf) {
+    const int L = c.p.levels, nt = c.p.n_mods(), ng = c.ng, P = c.p.p_index();
+    const size_t N = (size_t)c.p.n;
+    if (key_id != 0 && ((key_id & 1) == 0 || key_id >= 2 * N))
+        throw Error(CKKS_E_INVALID_ARG, "key id must be 0 (relinearisation) or an odd Galois element < 2N");
+    const ModMap mt{nt, L + 1, P};
+    check_residues(c, buf, (size_t)2 * ng * nt, [&](size_t i) {
+        const int t = (int)(i % nt);
+        return t <= L ? t : P + (t - (L + 1));
+    });
+    DBuf key(c.pool.get(), (size_t)2 * ng * nt * N);
+    GCK_HIP(hipMemcpyAsync(key.ptr, buf, key.words * 8, hipMemcpyHostToDevice, c.stream));
+    ntt_fwd(c, key.ptr, 2 * ng * nt, mt);
+    k_to_mont(c.tab, key.ptr, 2 * ng * nt, mt, c.stream);
+    sync(c);
+    c.ksk[key_id] = std::move(key);
+}
+
 Ct encrypt(ckks_ctx &c, const i64 *m, int depth, double scale, u64 seed) {
-    if (!c.have_keys) throw Error(CKKS_E_KEY_MISSING, "keygen has not been run");
+    if (!c.have_pk) throw Error(CKKS_E_KEY_MISSING, "no public key in this context (keygen or import one)");
     if (seed == 0) seed = os_seed();
     const int n = c.p.n;
     const size_t N = (size_t)n;
@@ -690,7 +740,7 @@ Ct encrypt(ckks_ctx &c, const i64 *m, int depth, double scale, u64 seed) {
 }
 
 std::vector<long double> decrypt_poly(ckks_ctx &c, const ckks_ct &a, int index) {
-    if (!c.have_keys) throw Error(CKKS_E_KEY_MISSING, "keygen has not been run");
+    if (!c.have_secret) throw Error(CKKS_E_KEY_MISSING, "no secret key in this context (an evaluating context)");
     const int n = c.p.n;
     const size_t N = (size_t)n;
     const int l = a.limbs, lu = std::min(l, 2);

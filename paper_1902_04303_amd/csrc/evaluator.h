@@ -38,8 +38,10 @@ struct ckks_ctx {
     };
     std::vector<QInv> q_inv;
     int ng = 0;                              // digit groups of a key (at L + 1 limbs)
-    // keys
-    bool have_keys = false;
+    // keys: a context made by keygen holds the secret (the client's side); an evaluating context may hold
+    // only imported switching keys (and a public key), never the secret
+    bool have_secret = false;      // sk and sk_ntt are set (keygen)
+    bool have_pk = false;          // pk is set (keygen or import)
     std::vector<int64_t> sk;       // secret, signed coefficients
     gck::DBuf sk_ntt;              // [L+1+alpha][N]: s mod q_0..q_L, p_1..p_alpha in NTT form
     gck::DBuf pk;                  // [2][L+1][N] NTT form
@@ -111,6 +113,9 @@ bool has_key(const ckks_ctx &c, u64 id);
 
 // ---- keys / encryption
 void keygen(ckks_ctx &c, u64 seed, const std::vector<u64> &galois);
+// canonical coefficient-form keys (as exported) into the context's device form
+void import_public_key(ckks_ctx &c, const u64 *buf);
+void import_switching_key(ckks_ctx &c, u64 key_id, const u64 *buf);
 Ct encrypt(ckks_ctx &c, const i64 *m, int depth, double scale, u64 seed);
 // c0 + c1 s in coefficient form, centred over q_0 (q_0 q_1 when limbs >= 2), as long doubles
 std::vector<long double> decrypt_poly(ckks_ctx &c, const ckks_ct &a, int index);

@@ -32,20 +32,21 @@ hipEvent_t KTimer::take() {
     return e;
 }
 
-int KTimer::begin(const char *name, double bytes, double flops, hipStream_t st) {
-    if (!only.empty() && only != name) return -1;
+int KTimer::id_of(const char *name) {
     auto it = ids.find(name);
-    int id;
-    if (it == ids.end()) {
-        id = (int)names.size();
-        ids[name] = id;
-        names.push_back(name);
-        stats.emplace_back();
-    } else {
-        id = it->second;
-    }
+    if (it != ids.end()) return it->second;
+    const int id = (int)names.size();
+    ids[name] = id;
+    names.push_back(name);
+    stats.emplace_back();
+    return id;
+}
+
+int KTimer::begin(const char *name, double bytes, double flops, hipStream_t st, double pass_bytes) {
+    if (!only.empty() && only != name) return -1;
+    const int id = id_of(name);
     (void)st;
-    recs.push_back(Rec{id, take(), take(), bytes, flops, false});
+    recs.push_back(Rec{id, take(), take(), bytes, flops, pass_bytes < 0 ? bytes : pass_bytes, false});
     tl_timed_launch = &recs.back();   // the next launch on this thread fills its events
     return (int)recs.size() - 1;
 }
@@ -59,6 +60,16 @@ void KTimer::end(int idx, hipStream_t) {
     }
 }
 
+int KTimer::region_begin(const char *name, double bytes, hipStream_t st) {
+    if (only != name) return -1;
+    const int id = id_of(name);
+    recs.push_back(Rec{id, take(), take(), bytes, 0.0, bytes, true});
+    GCK_HIP(hipEventRecord(recs.back().a, st));
+    return (int)recs.size() - 1;
+}
+
+void KTimer::region_end(int idx, hipStream_t st) { GCK_HIP(hipEventRecord(recs[idx].b, st)); }
+
 thread_local KTimer::Rec *tl_timed_launch = nullptr;
 
 void KTimer::collect() {
@@ -71,6 +82,7 @@ void KTimer::collect() {
         s.ms += ms;
         s.bytes += r.bytes;
         s.flops += r.flops;
+        s.pass_bytes += r.pass_bytes;
         spare.push_back(r.a);
         spare.push_back(r.b);
     }
@@ -648,12 +660,13 @@ void k_ks_inner(const DevTables &t, u64 *acc, const u64 *digits, int K, const in
     // it spills and was not faster, so that form keeps its guards
     const bool keys_fill = mk == 1 || (mk < 0 && keys.m % 3 == 0);
     auto launch = [&](bool full, int c_first, int cnt) {
-        // algorithmic FP64 operations: one multiply-accumulate per (ciphertext, target, word, digit group, key),
-        // each two modular products (a product and its FMA error 3, the quotient 2, the remainder 2, their sum
-        // 1) and two additions: 18
+        // algorithmic FP64 operations: one multiply-accumulate per (ciphertext, FP64 target, word, digit group,
+        // key), each two modular products (a product and its FMA error 3, the quotient 2, the remainder 2,
+        // their sum 1) and two additions: 18.  The target q_0 (60 bits) accumulates in 128-bit integers and
+        // does no FP64 work: nt - 1 targets count.
         TScope ts_(t, names[full ? 1 : 0][cb == 4 ? 2 : cb - 1][mi],
                    8.0 * (double)t.n * (keys.m * 2.0 * gl * nt * cnt / count + (double)cnt * (gl * nt + 2.0 * nt)), st,
-                   18.0 * (double)cnt * nt * (double)t.n * gl * keys.m);
+                   18.0 * (double)cnt * (nt - 1) * (double)t.n * gl * keys.m);
         const size_t ngrp = (size_t)((cnt + cb - 1) / cb);
         const size_t total = ln.s ? 8 * (size_t)ln.spx * ln.seglen * nt * ngrp   // workgroup items
                                   : 8 * p8 * nt * ngrp;

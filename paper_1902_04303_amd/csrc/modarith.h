@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include "ckks_internal.h"
+// u2d / d2u and the FP64 arithmetic for moduli below 2^41 (host and device: a host build of the same
+// source is checked against 128-bit integers on the CPU)
+#include "fmod64.h"
 
 namespace gck {
 
@@ -61,53 +64,6 @@ __device__ __forceinline__ size_t automorph_src(size_t k, int log_n, u64 g) {
     return __brev((e2 - 1) >> 1) >> (32 - log_n);
 }
 
-// exact conversions between integers below 2^52 and doubles through the bias 2^52 (the integer fills the
-// mantissa of 2^52 + x): one integer OR or AND and one FP64 add, where a general 64-bit conversion takes
-// several instructions
-__device__ __forceinline__ double u2d(u64 x) {
-#pragma clang fp contract(off)
-    return __longlong_as_double((long long)(x | 0x4330000000000000ULL)) - 4503599627370496.0;
-}
-__device__ __forceinline__ u64 d2u(double x) {   // x integer-valued in [0, 2^52)
-#pragma clang fp contract(off)
-    return (u64)__double_as_longlong(x + 4503599627370496.0) & 0xFFFFFFFFFFFFFULL;
-}
-
-// ---------------------------------------------------------------- FP64 arithmetic (q < 2^41)
-// Residues of moduli below 2^41 as integer-valued doubles: a product a w is split exactly into its
-// rounded value and the FMA error, the quotient by q is rounded from a multiply by RN(1/q), and the
-// remainder is then exact.
-struct FMod {
-    double q, qinv;
-};
-
-// a w mod q as a signed representative in (-1.1q, 1.1q), exact; a, w integers, |a| < 2^47, 0 <= w < q
-__device__ __forceinline__ double fmul_mod(double a, double w, FMod m) {
-#pragma clang fp contract(off)
-    const double h = a * w;
-    const double l = __builtin_fma(a, w, -h);         // a w = h + l exactly
-    const double qt = __builtin_rint(h * m.qinv);
-    const double r = __builtin_fma(-qt, m.q, h);      // integer of magnitude < q: exact
-    return r + l;
-}
-
-// signed reduction of an integer |x| < 2^52 to (-0.6q, 0.6q)
-__device__ __forceinline__ double fred(double x, FMod m) {
-#pragma clang fp contract(off)
-    const double qt = __builtin_rint(x * m.qinv);
-    return __builtin_fma(-qt, m.q, x);
-}
-
-// canonical residue in [0, q) of an integer |x| < 2^52, as a 64-bit word
-__device__ __forceinline__ u64 fcanon(double x, FMod m) {
-#pragma clang fp contract(off)
-    const double qt = __builtin_floor(x * m.qinv);
-    double r = __builtin_fma(-qt, m.q, x);
-    r = r < 0.0 ? r + m.q : r;
-    r = r >= m.q ? r - m.q : r;
-    return d2u(r);
-}
-
 // ---------------------------------------------------------------- SplitMix64 (test-only randomness)
 
 __device__ __forceinline__ u64 sm_mix(u64 z) {
@@ -153,9 +109,11 @@ struct TScope {
     hipStream_t st;
     // bytes: algorithmic HBM bytes of the launch; flops: its algorithmic FP64 operations when the kernel is
     // bound by arithmetic rather than memory (0 otherwise)
-    TScope(const DevTables &tab, const char *name, double bytes, hipStream_t s, double flops = 0)
+    // pass_bytes: the bytes of the launch when each word it touches is read and written once (default: bytes)
+    TScope(const DevTables &tab, const char *name, double bytes, hipStream_t s, double flops = 0,
+           double pass_bytes = -1)
         : t(tab.timer), st(s) {
-        if (t && t->on) idx = t->begin(name, bytes, flops, st);
+        if (t && t->on) idx = t->begin(name, bytes, flops, st, pass_bytes);
     }
     ~TScope() {
         if (idx >= 0) t->end(idx, st);

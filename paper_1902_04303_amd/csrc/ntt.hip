@@ -611,20 +611,26 @@ static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, 
     const dim3 block_c((unsigned)((1 << g.log_tile_cols) / kPer));
     const dim3 grid_r((unsigned)((size_t)n_limbs << (t.log_n - g.log_tile_rows)));
     const dim3 block_r((unsigned)((1 << g.log_tile_rows) / kPer));
-    // algorithmic bytes of a pass: each word written once and each distinct input word read once (a
-    // gather whose output limbs share a source limb, inner == 0, reads n_limbs / div source limbs)
+    // Algorithmic bytes of a transform: each distinct input word read once and each output word written
+    // once, 16 N per limb (a gather whose output limbs share a source limb, inner == 0, reads n_limbs / div
+    // source limbs; a basis conversion reads its source limbs once).  The first pass is credited with the
+    // reads and the second with the writes; the words the first pass writes and the second reads again
+    // are the price of the two-pass design and count only in the pass bytes (each pass reading and
+    // writing every word once).
     const double bytes = 16.0 * (double)n_limbs * t.n;
     const bool conv = in.ptr && in.mode == kConv;
     const bool shared_src = conv || (in.ptr && in.div > 1 && in.inner == 0);
     const double src_limbs = conv ? (double)(n_limbs / in.conv_period) * in.src_stride : (double)n_limbs / in.div;
     const double bytes1 = shared_src ? 8.0 * t.n * ((double)n_limbs + src_limbs) : bytes;
+    const double alg_read = 8.0 * t.n * (shared_src ? src_limbs : (double)n_limbs);
+    const double alg_write = 8.0 * t.n * (double)n_limbs;
     const Gather none{nullptr, 1, 1, 0, 0, kPlain, 0};
     auto name = [&](bool i, bool rows, int log_m, int gm = kGmPlain) { return pass_name(i, rows, log_m, gm); };
     Geom g1 = g;   // first pass: group the readers of a shared source limb on one XCD
     g1.xcd_group = (shared_src && (inv ? grid_r.x : grid_c.x) % 8 == 0) ? 1 : 0;
     if (!inv) {
         {
-            TScope ts_(t, name(false, false, g.log_n1, conv ? kGmConv : kGmPlain), bytes1, st);
+            TScope ts_(t, name(false, false, g.log_n1, conv ? kGmConv : kGmPlain), alg_read, st, 0, bytes1);
             if (conv)
                 launch_pass<false, false, kGmConv>(g.log_n1, grid_c, block_c, st, buf, in, m, t.mods, t.psi, t.psi_sh, t.psi_f, g1);
             else
@@ -637,7 +643,8 @@ static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, 
                           (1.0 + (epi->add.ptr ? (epi->add_even ? 0.5 : 1.0) : 0.0) +
                            (epi->aut ? (epi->aut_self == 1 ? 1.0 : 0.5) : 0.0))
                     : 0.0;
-            TScope ts_(t, name(false, true, g.log_n2, epi ? kGmEpi : kGmPlain), bytes + epi_bytes, st);
+            TScope ts_(t, name(false, true, g.log_n2, epi ? kGmEpi : kGmPlain), alg_write + epi_bytes, st, 0,
+                       bytes + epi_bytes);
             if (epi)
                 launch_pass<false, true, kGmEpi>(g.log_n2, grid_r, block_r, st, buf, none, m, t.mods, t.psi, t.psi_sh, t.psi_f, g_rows);
             else
@@ -645,11 +652,11 @@ static void launch(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, 
         }
     } else {
         {
-            TScope ts_(t, name(true, true, g.log_n2), bytes1, st);
+            TScope ts_(t, name(true, true, g.log_n2), alg_read, st, 0, bytes1);
             launch_pass<true, true>(g.log_n2, grid_r, block_r, st, buf, in, m, t.mods, t.ipsi, t.ipsi_sh, t.ipsi_f, g1);
         }
         {
-            TScope ts_(t, name(true, false, g.log_n1), bytes, st);
+            TScope ts_(t, name(true, false, g.log_n1), alg_write, st, 0, bytes);
             launch_pass<true, false>(g.log_n1, grid_c, block_c, st, buf, none, m, t.mods, t.ipsi, t.ipsi_sh, t.ipsi_f, g);
         }
     }

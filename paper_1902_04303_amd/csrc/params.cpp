@@ -2,7 +2,8 @@
 //
 // The paper describes CKKS with power-of-two moduli (Methods, "Homomorphic
 // Encryption"); this is its residue-number-system form.  Chain rule:
-//   q_0 = largest prime < 2^60 with q = 1 mod 2N;  P = largest prime < 2^62, P = 1 mod 2N;
+//   q_0 = largest prime < 2^60 with q = 1 mod 2N;  P = p_1 ... p_alpha, the alpha largest primes < 2^41
+//   with p = 1 mod 2N that are not in the chain (alpha: the digit-group size of the hybrid key switch);
 //   pool = the 4L primes = 1 mod 2N nearest to 2^b (lower candidate first on equal distance);
 //   for depth d = 0..L-1: q_{L-d} = unused pool prime nearest to Delta_d^2 / 2^b (smaller on ties),
 //   Delta_0 = 2^b, Delta_{d+1} = (Delta_d * Delta_d) / q_{L-d} in FP64.

@@ -49,6 +49,7 @@ struct gwas_server {
         size_t footprint = 0;
         int remaining = 0;
         int state = 0;   // 0 queued, 1 admitted (fixed part pending), 2 active, 3 done, 4 cancelled
+        bool counted = false;   // footprint included in in_flight_bytes (from admission until released)
         Clock::time_point t_submit, t_done;
     };
 
@@ -61,6 +62,7 @@ struct gwas_server {
     uint64_t next_id = 1;
     size_t in_flight_bytes = 0;
     bool stop = false;
+    bool sweep = false;   // an admitted or active job was cancelled: the worker releases its resources
     std::thread worker;
     std::string error;
     // statistics
@@ -70,12 +72,23 @@ struct gwas_server {
     int peak_in_flight = 0;
     uint64_t iterations = 0;
 
+    // Free what a finished or cancelled job holds on the device (its input and the fixed-part values) and
+    // return its footprint to the budget, once.  Called by the worker with m and the context lock held.
+    void release(Job *j) {
+        j->fx = FixedOut{};
+        j->in.reset();
+        if (j->counted) {
+            in_flight_bytes -= j->footprint;
+            j->counted = false;
+        }
+    }
+
     void run() {
         for (;;) {
             std::vector<Job *> admitted;
             {
                 std::unique_lock<std::mutex> lk(m);
-                cv.wait(lk, [&] { return stop || !queue.empty() || !work.empty(); });
+                cv.wait(lk, [&] { return stop || sweep || !queue.empty() || !work.empty(); });
                 if (stop) return;
                 while (!queue.empty() && (int)active.size() + (int)admitted.size() < max_jobs) {
                     Job *j = queue.front();
@@ -84,6 +97,7 @@ struct gwas_server {
                     if (!fits && !(active.empty() && admitted.empty())) break;   // wait for memory
                     queue.pop_front();
                     in_flight_bytes += j->footprint;
+                    j->counted = true;
                     j->state = 1;
                     admitted.push_back(j);
                 }
@@ -103,6 +117,10 @@ struct gwas_server {
                         std::lock_guard<std::mutex> lk(m);
                         for (size_t q = 0; q < kv.second.size(); ++q) {
                             Job *j = kv.second[q];
+                            if (j->state == 4) {   // cancelled while its fixed part ran: nothing is queued
+                                release(j);
+                                continue;
+                            }
                             j->fx = std::move(fxs[q]);
                             j->out = std::make_unique<gwas_enc_output>();
                             j->out->ctx = ctx;
@@ -147,12 +165,21 @@ struct gwas_server {
                         j->t_done = now;
                         last_done = now;
                         latencies_ms.push_back(std::chrono::duration<double, std::milli>(now - j->t_submit).count());
-                        in_flight_bytes -= j->footprint;
-                        j->fx = FixedOut{};
-                        j->in.reset();
+                        release(j);
                         active.erase(std::find(active.begin(), active.end(), j));
                     }
                 }
+                // cancelled active jobs: no chunk references them any more (the chunk above has finished)
+                for (auto it = active.begin(); it != active.end();) {
+                    if ((*it)->state == 4) {
+                        release(*it);
+                        (*it)->out.reset();
+                        it = active.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+                sweep = false;
                 done_cv.notify_all();
             } catch (const std::exception &e) {
                 std::lock_guard<std::mutex> lk(m);
@@ -224,17 +251,23 @@ int gwas_server_submit(gwas_server *s, gwas_enc_input *in, uint64_t *job_id) {
     return sguard([&] {
         if (!s || !in || !job_id) throw Error(CKKS_E_INVALID_ARG, "null argument");
         if (in->ctx != s->ctx) throw Error(CKKS_E_PARAM_MISMATCH, "input belongs to another context");
-        auto j = std::make_unique<gwas_server::Job>();
-        j->in.reset(in);
-        j->footprint = input_footprint(*s->ctx, *in->in);
-        if (j->footprint > s->budget) {   // larger than the whole budget: keep its SNP batches on the host
-            std::lock_guard<std::recursive_mutex> ck(s->ctx->mu);
-            spill_snp(*s->ctx, *in->in);
-            j->footprint = input_footprint(*s->ctx, *in->in);
+        {
+            std::lock_guard<std::mutex> lk(s->m);
+            if (!s->error.empty()) throw Error(CKKS_E_HIP, "server stopped: " + s->error);
         }
+        size_t fp = input_footprint(*s->ctx, *in->in);
+        if (fp > s->budget) {   // larger than the whole budget: keep its SNP batches on the host
+            std::lock_guard<std::recursive_mutex> ck(s->ctx->mu);
+            spill_snp(*s->ctx, *in->in);   // on failure the input is unchanged and still the caller's
+            fp = input_footprint(*s->ctx, *in->in);
+        }
+        auto j = std::make_unique<gwas_server::Job>();
+        j->footprint = fp;
         j->t_submit = Clock::now();
         std::lock_guard<std::mutex> lk(s->m);
         if (!s->error.empty()) throw Error(CKKS_E_HIP, "server stopped: " + s->error);
+        // nothing below throws: ownership of the input passes to the server only on success
+        j->in.reset(in);
         j->id = s->next_id++;
         *job_id = j->id;
         if (!s->any) {
@@ -272,13 +305,12 @@ int gwas_server_cancel(gwas_server *s, uint64_t job_id) {
         auto it = s->jobs.find(job_id);
         if (it == s->jobs.end()) throw Error(CKKS_E_INVALID_ARG, "unknown job");
         gwas_server::Job *j = it->second.get();
-        if (j->state == 3) return (int)CKKS_OK;
-        if (j->state == 1 || j->state == 2) {
-            s->in_flight_bytes -= j->footprint;
-            auto a = std::find(s->active.begin(), s->active.end(), j);
-            if (a != s->active.end()) s->active.erase(a);
-        }
+        if (j->state == 3 || j->state == 4) return (int)CKKS_OK;
+        // A queued job holds no budget and is skipped at admission.  An admitted or active job may be in
+        // the worker's hands right now: the worker releases its memory and budget once no launch reads it.
+        if (j->state == 1 || j->state == 2) s->sweep = true;
         j->state = 4;
+        s->cv.notify_all();
         s->done_cv.notify_all();
         return (int)CKKS_OK;
     });

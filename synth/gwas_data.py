@@ -8,7 +8,8 @@ a seeded generator with these distributions:
 * b: iid N(0, 0.5) (variance 0.5), the covariate effects of the phenotype model.
 * y_i ~ Bernoulli(sigmoid(x_i . b)), the binary response.
 * MAF_j ~ U[0.05, 0.5] and S_ij ~ Binomial(2, MAF_j), independent of y (null SNPs),
-  optionally with a planted logit effect on a fraction of the SNPs.
+  optionally with a planted logit effect on a fraction of the SNPs (acting on the centred genotype
+  S_ij - 2 MAF_j).
 
 The draws are made in this fixed order from ``numpy.random.default_rng(seed)``
 (PCG64): X, b, MAF, S, then y.
@@ -73,7 +74,9 @@ def make_gwas_data(n: int, k: int, m: int, seed: int, planted_frac: float = 0.0,
         n_pl = max(1, int(round(planted_frac * m)))
         idx = rng.choice(m, size=n_pl, replace=False)
         planted[idx] = planted_effect
-    logit = X @ b + S.astype(np.float64) @ planted
+    # planted effects act on centred genotypes (S - 2 MAF), so that many planted SNPs shift the spread of
+    # the logit rather than its mean (the phenotype stays a mix of both classes)
+    logit = X @ b + (S.astype(np.float64) - 2.0 * maf[None, :]) @ planted
     p = 1.0 / (1.0 + np.exp(-logit))
     y = (rng.uniform(size=n) < p).astype(np.float64)
     return GwasData(X=X, y=y, S=S, b=b, maf=maf, planted=planted, seed=seed)

@@ -74,13 +74,28 @@ def test_projection_invariants(data):
 
 
 def test_fixed_hessian_newton_converges_to_mle(data):
+    """homomorphic_logreg_plain with the exact sigmoid and many passes reaches the IRLS maximum-likelihood
+    fit (pins the ascent sign of the update, reading of eq. updateBeta with the lower-bound Hessian)."""
     X, y = data.X, data.y
     A = F.xtx_inverse(X)
-    beta = np.zeros(X.shape[1])
-    for _ in range(300):
-        p = F.sigmoid(X @ beta)
-        beta = beta + 4 * A @ (X.T @ (y - p))
+    beta, _ = F.homomorphic_logreg_plain(X, y, A, 300, sig=F.sigmoid)
     assert np.allclose(beta, F.irls_logreg(X, y), atol=1e-8)
+
+
+def test_homomorphic_logreg_iterates(data):
+    """Closed forms of the first passes: p^(0) = sigma7(0) = 1/2 everywhere and beta^(1) = 4 A X^T (y - 1/2);
+    the p returned with beta^(kappa) is the one of the last pass, p^(kappa-1) = sigma7(X beta^(kappa-1))."""
+    X, y = data.X, data.y
+    A = F.xtx_inverse(X)
+    b1, p0 = F.homomorphic_logreg_plain(X, y, A, 1)
+    assert np.all(p0 == 0.5)
+    assert np.allclose(b1, 4 * A @ (X.T @ (y - 0.5)), rtol=1e-13, atol=1e-15)
+    b2, p1 = F.homomorphic_logreg_plain(X, y, A, 2)
+    assert np.allclose(p1, F.sigma7(X @ b1), rtol=1e-14)
+    assert np.allclose(b2, b1 + 4 * A @ (X.T @ (y - p1)), rtol=1e-12, atol=1e-15)
+    b3, p2 = F.homomorphic_logreg_plain(X, y, A, 3)
+    assert np.allclose(p2, F.sigma7(X @ b2), rtol=1e-14)
+    assert not np.allclose(p2, F.sigma7(X @ b3), rtol=1e-6)   # not the p of beta^(kappa)
 
 
 def test_sikorska_close_to_brute_force():
