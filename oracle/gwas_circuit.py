@@ -30,6 +30,15 @@ Newton pass adds 7 levels (eta, 4 for sigma7, g, beta); w at D_p + 1,
 w^-1 at D_p + 5, z at D_p + 6, z' at D_p + 9, u = w z' at D_p + 10; SNP batches
 are encrypted at D_S = D_p + 7, S' at D_S + 3, num at D_S + 4 and the two
 denominators at D_S + 5 = 7 kappa + 5 = L.
+
+kappa = 1 (Discussion: the SEAL run reduces kappa to 1): the only Newton pass
+starts from beta = 0, so the p it leaves for the weights is sigma7(0) = 1/2 and
+w = 1/4 and w^-1 = inverseSlots(1/4) = 4 - 2^-14 are public constants.  beta^(1)
+at 2, z = X beta + w^-1 (y - 1/2) at 3 (the constant folded into the alignment
+of y - 1/2), z' at 6, u = z' / 4 at 7 (the 1/4 folded into an alignment); SNP
+batches at D_S = 4, S' at 7, and num and both denominators at 8 = L (the
+denominators square S' directly and take w = 1/4 into their tracked scale).
+No w or w^-1 ciphertext exists.
 """
 from __future__ import annotations
 
@@ -39,18 +48,25 @@ from typing import Dict, List, Optional
 import numpy as np
 
 from . import ckks as C
-from .gwas_fp64 import SIGMA7_C1, SIGMA7_C3, SIGMA7_C5, SIGMA7_C7, xtx_inverse
+from .gwas_fp64 import SIGMA7_C1, SIGMA7_C3, SIGMA7_C5, SIGMA7_C7, inverse_slots, xtx_inverse
+
+# kappa = 1: the weights of the only Newton pass are public, w = sigma7(0) (1 - sigma7(0)) = 1/4
+W_KAPPA1 = 0.25
+W_INV_KAPPA1 = float(inverse_slots(np.array(W_KAPPA1)))   # Alg. inverseSlots at w = 1/4: 4 - 2^-14
 
 
 def circuit_depth(kappa: int) -> int:
     """Number of rescales (L) the circuit consumes for kappa Newton passes."""
-    if kappa < 2:
-        raise ValueError("the encrypted circuit needs kappa >= 2 (kappa = 1 leaves p = 1/2 public)")
-    return 7 * kappa + 5
+    if kappa < 1:
+        raise ValueError("kappa >= 1 Newton passes")
+    return 8 if kappa == 1 else 7 * kappa + 5
 
 
 def snp_depth(kappa: int) -> int:
-    return 7 * (kappa - 1) + 7
+    """Depth at which the SNP batches are encrypted."""
+    if kappa < 1:
+        raise ValueError("kappa >= 1 Newton passes")
+    return 4 if kappa == 1 else 7 * (kappa - 1) + 7
 
 
 @dataclass
@@ -227,18 +243,19 @@ def required_galois(N: int, R: int) -> List[int]:
 
 @dataclass
 class FixedPart:
-    """What the per-batch part needs from the fixed part: x_j, r_j = (X A)_{:, j}, w and u = w z'."""
+    """What the per-batch part needs from the fixed part: x_j, r_j = (X A)_{:, j}, w and u = w z'
+    (w is None when it is the public 1/4 of kappa = 1)."""
     x: List[C.Ct]
     rr: List[C.Ct]
-    w: C.Ct
+    w: Optional[C.Ct]
     u: C.Ct
 
 
 @dataclass
 class EncOutput:
     beta: List[C.Ct]
-    w: C.Ct
-    w_inv: C.Ct
+    w: Optional[C.Ct]        # None for kappa = 1 (public)
+    w_inv: Optional[C.Ct]    # None for kappa = 1 (public)
     z_proj: C.Ct
     u: C.Ct
     S_proj: List[C.Ct]
@@ -300,6 +317,14 @@ class Circuit:
         sp = o.sub(self.at(S, xe.depth), xe)
         dsp = sp.depth
         num = self.rot_sum(o.mul(self.at(fx.u, dsp), sp), BATCH_RADIX)
+        if fx.w is None:
+            # public w = 1/4: den_even / den_odd = (S' conj(S') +- S' S') / 8, the 1/8 in the tracked scale
+            sc = o.conjugate(sp)
+            ss = o.mul(sp, sp)
+            ssc = o.mul(sp, sc)
+            de = self.rot_sum(o.set_scale(o.add(ssc, ss), 2.0 / W_KAPPA1), BATCH_RADIX)
+            do = self.rot_sum(o.set_scale(o.sub(ssc, ss), 2.0 / W_KAPPA1), BATCH_RADIX)
+            return sp, num, de, do
         ws = o.mul(self.at(fx.w, dsp), sp)
         sc = o.conjugate(sp)
         wss = o.mul(ws, self.at(sp, ws.depth))
@@ -307,6 +332,47 @@ class Circuit:
         de = self.rot_sum(o.set_scale(o.add(wsc, wss), 2.0), BATCH_RADIX)
         do = self.rot_sum(o.set_scale(o.sub(wsc, wss), 2.0), BATCH_RADIX)
         return sp, num, de, do
+
+    def _project_z(self, inp: EncInput, z: C.Ct) -> C.Ct:
+        """z' = M z = z - X (A (X^T z))."""
+        o = self.o
+        k = self.lay.k
+        x = inp.x
+        h = [self.rot_sum(o.mul(self.at(x[j], z.depth), z)) for j in range(k)]
+        dh = h[0].depth
+        v = [o.mul_sum([(self.at(inp.a(j, l), dh), h[l]) for l in range(k)]) for j in range(k)]
+        dv = v[0].depth
+        xv = o.mul_sum([(self.at(x[j], dv), v[j]) for j in range(k)])
+        return o.sub(self.at(z, xv.depth), xv)
+
+    def _xa(self, inp: EncInput) -> List[C.Ct]:
+        """r_j = (X A)_{:, j} = sum_l A_jl x_l for the projection of the SNP batches."""
+        k = self.lay.k
+        return [self.o.mul_sum([(self.at(inp.a(j, l), 1), self.at(inp.x[l], 1)) for l in range(k)])
+                for j in range(k)]
+
+    def _batches(self, inp: EncInput, fixed: FixedPart, beta, w, w_inv, z_proj, u) -> EncOutput:
+        S_proj, nums, dens_e, dens_o = [], [], [], []
+        for S in inp.S:
+            sp, num, de, do = self.run_batch(S, fixed)
+            S_proj.append(sp)
+            nums.append(num)
+            dens_e.append(de)
+            dens_o.append(do)
+        return EncOutput(beta=beta, w=w, w_inv=w_inv, z_proj=z_proj, u=u, S_proj=S_proj,
+                         num=nums, den_even=dens_e, den_odd=dens_o)
+
+    def _run_kappa1(self, inp: EncInput, r: C.Ct, beta: List[C.Ct]) -> EncOutput:
+        """kappa = 1: p = 1/2, w = 1/4 and w^-1 public; z = X beta^(1) + w^-1 (y - 1/2), z' = M z, u = z'/4."""
+        o = self.o
+        k = self.lay.k
+        db = beta[0].depth
+        xb = o.mul_sum([(self.at(inp.x[j], db), beta[j]) for j in range(k)])
+        z = o.add(xb, self.at(r, xb.depth, W_INV_KAPPA1))
+        z_proj = self._project_z(inp, z)
+        u = self.at(z_proj, snp_depth(1) + 3, W_KAPPA1)
+        fixed = FixedPart(x=inp.x, rr=self._xa(inp), w=None, u=u)
+        return self._batches(inp, fixed, beta, None, None, z_proj, u)
 
     def run(self, inp: EncInput) -> EncOutput:
         o = self.o
@@ -317,6 +383,8 @@ class Circuit:
         r = o.add_const(y, -0.5)
         g = [self.rot_sum(o.mul(x[j], r)) for j in range(k)]
         beta = [o.mul_int(o.mul_sum([(self.at(inp.a(j, l), 1), g[l]) for l in range(k)]), 4) for j in range(k)]
+        if inp.kappa == 1:
+            return self._run_kappa1(inp, r, beta)
         p = None
         for _t in range(1, inp.kappa):
             d = beta[0].depth
@@ -343,26 +411,11 @@ class Circuit:
         xb = o.mul_sum([(self.at(x[j], db), beta[j]) for j in range(k)])
         t = o.mul(self.at(r, w_inv.depth), w_inv)
         z = o.add(self.at(xb, t.depth), t)
-        # ---- z' = M z = z - X (A (X^T z))
-        h = [self.rot_sum(o.mul(self.at(x[j], z.depth), z)) for j in range(k)]
-        dh = h[0].depth
-        v = [o.mul_sum([(self.at(inp.a(j, l), dh), h[l]) for l in range(k)]) for j in range(k)]
-        dv = v[0].depth
-        xv = o.mul_sum([(self.at(x[j], dv), v[j]) for j in range(k)])
-        z_proj = o.sub(self.at(z, xv.depth), xv)
+        # ---- z' = M z = z - X (A (X^T z)), u = w z'
+        z_proj = self._project_z(inp, z)
         u = o.mul(self.at(w, z_proj.depth), z_proj)
-        # ---- r_j = (X A)_{:, j} for the projection of the SNP batches
-        rr = [o.mul_sum([(self.at(inp.a(j, l), 1), self.at(x[l], 1)) for l in range(k)]) for j in range(k)]
-        fixed = FixedPart(x=x, rr=rr, w=w, u=u)
-        S_proj, nums, dens_e, dens_o = [], [], [], []
-        for S in inp.S:
-            sp, num, de, do = self.run_batch(S, fixed)
-            S_proj.append(sp)
-            nums.append(num)
-            dens_e.append(de)
-            dens_o.append(do)
-        return EncOutput(beta=beta, w=w, w_inv=w_inv, z_proj=z_proj, u=u, S_proj=S_proj,
-                         num=nums, den_even=dens_e, den_odd=dens_o)
+        fixed = FixedPart(x=x, rr=self._xa(inp), w=w, u=u)
+        return self._batches(inp, fixed, beta, w, w_inv, z_proj, u)
 
 
 def finalize(o: C.Oracle, lay: Layout, out: EncOutput):

@@ -150,3 +150,68 @@ def test_encrypted_circuit_on_oracle_config1_accuracy():
     num, den, b, err, se = G.finalize(o, lay, out)
     ref = F.modified_gwas(d.X, d.y, d.S, kappa)
     assert np.max(np.abs(b - ref.b) / np.maximum(np.abs(ref.b), ref.se)) < 1e-3
+
+
+def test_accuracy_methods_against_paper_tables():
+    """The paper's two accuracy methods: the count of entries differing by more than e with the accuracy
+    percentage 100 (1 - count / m) (both printed in the HEAAN and SEAL accuracy tables, m = 10643), and the
+    least-squares line of b' (y) against b (x)."""
+    g = _golden()["accuracy_tables"]
+    m = g["m"]
+    rng = np.random.default_rng(12)
+    b_ref = rng.standard_normal(m)
+    for lib in ("heaan", "seal"):
+        rows = g[lib]["rows"]
+        # differences placed so that exactly the printed number of entries exceeds each e
+        diff = np.zeros(m)
+        order = rng.permutation(m)
+        n01, n001, n0005 = (r[1] for r in rows)
+        diff[order[:n0005]] = 0.0075                 # above 0.005 only
+        diff[order[:n001]] = 0.05                    # above 0.01 too
+        diff[order[:n01]] = 0.5                      # above 0.1 too
+        got = F.accuracy_counts(b_ref, b_ref + diff * np.sign(rng.standard_normal(m)))
+        for e, count, pct in rows:
+            assert got[e][0] == count
+            assert round(got[e][1], 2) == pct, (lib, e, got[e])
+        slope, icpt = g[lib]["fit_line"]
+        s, c = F.fit_line(b_ref, slope * b_ref + icpt)
+        assert abs(s - slope) < 1e-12 and abs(c - icpt) < 1e-12
+        s2, _ = F.fit_line(slope * b_ref + icpt, b_ref)   # swapped axes give the inverse slope
+        assert abs(s2 - 1 / slope) < 1e-12
+
+
+def test_kappa1_weights_are_public_constants(data):
+    """kappa = 1 (Discussion: the SEAL run): the only Newton pass starts at beta = 0, so p = sigma7(0) = 1/2,
+    w = 1/4 and w^-1 = inverseSlots(1/4) = 4 - 2^-14 = (1 - (1 - 3/4)^8) / (1/4) exactly."""
+    r = F.modified_gwas(data.X, data.y, data.S, 1)
+    assert np.all(r.p == 0.5) and np.all(r.w == 0.25)
+    assert np.all(r.w_inv == 4 - 2.0 ** -14) and G.W_INV_KAPPA1 == 4 - 2.0 ** -14
+    assert G.W_KAPPA1 == 0.25
+    A = F.xtx_inverse(data.X)
+    assert np.allclose(r.beta, 4 * A @ (data.X.T @ (data.y - 0.5)), rtol=1e-13, atol=1e-15)
+    assert G.circuit_depth(1) == 8 and G.snp_depth(1) == 4
+    assert [G.circuit_depth(k) for k in (2, 3)] == [19, 26]
+
+
+@pytest.mark.parametrize("kappa", [1, 2])
+def test_encrypted_circuit_on_oracle_other_kappa_matches_fp64(kappa):
+    """The encrypted circuit on the oracle for kappa = 1 (public weights) and 2 against the FP64 GWAS of
+    the same kappa (N = 2^10, 40-bit scale, a ragged last SNP batch)."""
+    n, k, m = 30, 4, 70
+    p = C.make_params(10, G.circuit_depth(kappa), 40)
+    d = make_gwas_data(n, k, m, seed=78)
+    lay = G.make_layout(p.N, n, k, m)
+    o = C.Oracle(p)
+    o.keygen(7, G.required_galois(p.N, lay.R))
+    inp = G.encrypt_inputs(o, G.encode_inputs(p, d.X, d.y, d.S, kappa), n, k, m, kappa, 11)
+    out = G.Circuit(o, lay).run(inp)
+    assert out.den_even[0].depth == p.L and out.den_odd[0].depth == p.L
+    assert (out.w is None) == (kappa == 1) and (out.w_inv is None) == (kappa == 1)
+    num, den, b, err, se = G.finalize(o, lay, out)
+    ref = F.modified_gwas(d.X, d.y, d.S, kappa)
+    assert np.max(np.abs(b - ref.b) / np.maximum(np.abs(ref.b), ref.se)) < 1e-4
+    assert np.allclose(den, ref.den, rtol=1e-6)
+    beta = np.array([o.decrypt(c)[0].real for c in out.beta])
+    assert np.allclose(beta, ref.beta, atol=1e-5)
+    zp = o.decrypt(out.z_proj).real
+    assert np.allclose(zp[:n], ref.z_proj, atol=1e-5)
