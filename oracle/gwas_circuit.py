@@ -48,7 +48,8 @@ from typing import Dict, List, Optional
 import numpy as np
 
 from . import ckks as C
-from .gwas_fp64 import SIGMA7_C1, SIGMA7_C3, SIGMA7_C5, SIGMA7_C7, inverse_slots, xtx_inverse
+from .gwas_fp64 import (DIV_GUESS, DIV_ITERS, SIGMA7_C1, SIGMA7_C3, SIGMA7_C5, SIGMA7_C7, inverse_slots,
+                        snp_normalisers, xtx_inverse)
 
 # kappa = 1: the weights of the only Newton pass are public, w = sigma7(0) (1 - sigma7(0)) = 1/4
 W_KAPPA1 = 0.25
@@ -416,6 +417,107 @@ class Circuit:
         u = o.mul(self.at(w, z_proj.depth), z_proj)
         fixed = FixedPart(x=x, rr=self._xa(inp), w=w, u=u)
         return self._batches(inp, fixed, beta, w, w_inv, z_proj, u)
+
+
+# ---- homomorphic division (an extension beyond the paper, which divides on the client): b' and err' as
+#      ciphertexts through a Newton reciprocal of den normalised by the public bound d_j of each SNP
+DIV_LEVELS = 3 + 2 * (DIV_ITERS - 1)    # x = den v, the Newton steps after the first, err' = g v, b' = num err'
+DIV_SEED_BASE = 1 << 20                 # encryption seeds of the normalisers: input_seed(enc_seed, base + i)
+assert DIV_GUESS == 1.0                 # the first Newton step is then 2 - x, with no product
+
+
+def den_scale_factor(kappa: int) -> float:
+    """The factor by which a denominator's tracked scale exceeds the canonical scale of its depth."""
+    return 2.0 / W_KAPPA1 if kappa == 1 else 2.0
+
+
+def normaliser_scale(params: C.Params, kappa: int) -> float:
+    """Scale of the normalisers: Delta_L / (2 f), so that Re(den) v = ((den + conj(den)) / 2) v is canonical
+    (f = den_scale_factor; the real part doubles the tracked scale once more)."""
+    return params.scales[circuit_depth(kappa)] / (2.0 * den_scale_factor(kappa))
+
+
+def normaliser_slots(S: np.ndarray, lay: Layout, b: int, parity: int) -> np.ndarray:
+    """1 / d_j at the block start of SNP j = b tau + 2c + parity (c = 0 .. B-1), 0 elsewhere and for SNPs
+    beyond m or with d_j = 0."""
+    d = snp_normalisers(S)
+    z = np.zeros(lay.N // 2, dtype=np.complex128)
+    for c in range(lay.blocks):
+        j = b * lay.tau + 2 * c + parity
+        if j < lay.m and d[j] > 0:
+            z[c * lay.R] = 1.0 / d[j]
+    return z
+
+
+def encode_normalisers(params: C.Params, S: np.ndarray, lay: Layout, kappa: int) -> Plaintexts:
+    """Client side: the normalisers of every SNP batch, even SNPs of all batches then odd SNPs, at the
+    denominators' depth and at normaliser_scale."""
+    d = circuit_depth(kappa)
+    sc = normaliser_scale(params, kappa)
+    polys = [C.encode(normaliser_slots(S, lay, b, par), params.N, sc)
+             for par in (0, 1) for b in range(lay.n_batches)]
+    return Plaintexts(polys=polys, depths=[d] * len(polys))
+
+
+def encrypt_normalisers(o: C.Oracle, pts: Plaintexts, kappa: int, enc_seed: int) -> List[C.Ct]:
+    sc = normaliser_scale(o.p, kappa)
+    return [o.encrypt(pt, dd, sc, input_seed(enc_seed, DIV_SEED_BASE + i))
+            for i, (pt, dd) in enumerate(zip(pts.polys, pts.depths))]
+
+
+@dataclass
+class DivOutput:
+    b_even: List[C.Ct]     # per batch: real part at block start c = b' of SNP b tau + 2c
+    b_odd: List[C.Ct]      # per batch: imaginary part at block start c = b' of SNP b tau + 2c + 1
+    inv_even: List[C.Ct]   # per batch: err' = 1 / den of the even SNPs (real part at block starts)
+    inv_odd: List[C.Ct]
+
+
+def divide(o: C.Oracle, num: C.Ct, den: C.Ct, v: C.Ct):
+    """Encrypted b' and err' of one batch and parity.  The denominator's slots are complex (its imaginary
+    parts are cross terms of the packing), so its real part (den + conj(den)) / 2 is taken first; then
+    x = Re(den) v (canonical), g_1 = 2 - x (guess 1), g <- g (2 - x g) (Alg. inverseSlots' pattern),
+    err' = g v (real) and b' = num err' (real part: the even SNP's b', imaginary part: the odd one's)."""
+    sc = o.p.scales
+    at = lambda a, d: a if d == a.depth else o.align(a, d, sc[d])  # noqa: E731
+    x = o.mul(o.set_scale(o.add(den, o.conjugate(den)), 2.0), v)
+    g = o.add_const(o.neg(x), 2.0)     # g_1 = g_0 (2 - x g_0) with g_0 = DIV_GUESS = 1
+    for _ in range(DIV_ITERS - 1):
+        h = o.mul(at(x, g.depth), g)
+        e = o.add_const(o.neg(h), 2.0)
+        g = o.mul(at(g, e.depth), e)
+    inv = o.mul(g, at(v, g.depth))
+    b = o.mul(at(num, inv.depth), inv)
+    return b, inv
+
+
+def divide_all(o: C.Oracle, out: EncOutput, v: List[C.Ct]) -> DivOutput:
+    """divide() for the even and the odd SNPs of every batch (v: even normalisers, then odd)."""
+    nb = len(out.num)
+    be, bo, ie, io = [], [], [], []
+    for b in range(nb):
+        x, y = divide(o, out.num[b], out.den_even[b], v[b])
+        be.append(x)
+        ie.append(y)
+        x, y = divide(o, out.num[b], out.den_odd[b], v[nb + b])
+        bo.append(x)
+        io.append(y)
+    return DivOutput(b_even=be, b_odd=bo, inv_even=ie, inv_odd=io)
+
+
+def finalize_divided(o: C.Oracle, lay: Layout, dv: DivOutput):
+    """Client side for the divided outputs: b' and err' decrypted directly (no division), se = sqrt(err')."""
+    b = np.zeros(lay.n_batches * lay.tau)
+    err = np.zeros(lay.n_batches * lay.tau)
+    starts = np.arange(lay.blocks) * lay.R
+    for bi in range(lay.n_batches):
+        base = bi * lay.tau
+        b[base:base + lay.tau:2] = o.decrypt(dv.b_even[bi])[starts].real
+        b[base + 1:base + lay.tau:2] = o.decrypt(dv.b_odd[bi])[starts].imag
+        err[base:base + lay.tau:2] = o.decrypt(dv.inv_even[bi])[starts].real
+        err[base + 1:base + lay.tau:2] = o.decrypt(dv.inv_odd[bi])[starts].real
+    b, err = b[:lay.m], err[:lay.m]
+    return b, err, np.sqrt(np.maximum(err, 0.0))
 
 
 def finalize(o: C.Oracle, lay: Layout, out: EncOutput):

@@ -208,3 +208,37 @@ def fit_line(b_ref: np.ndarray, b_test: np.ndarray):
     """The paper's second accuracy method: least-squares line b_test ~ slope * b_ref + intercept."""
     slope, intercept = np.polyfit(b_ref, b_test, 1)
     return float(slope), float(intercept)
+
+
+# ---- homomorphic division of num by den (an extension: the paper decrypts num and den separately and
+#      divides on the client, Methods, walk-through of Alg. Semi Parallel GWAS)
+DIV_GUESS = 1.0   # initial guess of the Newton reciprocal of x = den / d (x in (0, 1])
+DIV_ITERS = 5     # Newton steps; the first, g = 2 - x, needs no product
+
+
+def snp_normalisers(S: np.ndarray) -> np.ndarray:
+    """d_j = 1/4 ||S_j - mean(S_j)||^2: an upper bound of den_j = sum_i w_i S'_ij^2 known to the holder of S.
+
+    w_i = p_i (1 - p_i) <= 1/4 for every real p_i, and S'_j = M S_j is the shortest residual of S_j after
+    projecting out the columns of X, which include the intercept, so ||S'_j|| <= ||S_j - mean(S_j)||.
+    A monomorphic SNP has d_j = 0 (no estimate)."""
+    Sf = np.asarray(S, dtype=np.float64)
+    return 0.25 * ((Sf - Sf.mean(axis=0)) ** 2).sum(axis=0)
+
+
+def reciprocal_newton(x: np.ndarray, iters: int = DIV_ITERS, guess: float = DIV_GUESS) -> np.ndarray:
+    """g <- g (2 - x g) from g = guess (the pattern of Alg. inverseSlots); 1 - x g_t = (1 - guess x)^(2^t)."""
+    g = np.full_like(np.asarray(x, dtype=np.float64), guess)
+    for _ in range(iters):
+        g = g * (2.0 - x * g)
+    return g
+
+
+def divide_plain(num: np.ndarray, den: np.ndarray, d: np.ndarray, iters: int = DIV_ITERS,
+                 guess: float = DIV_GUESS):
+    """FP64 counterpart of the encrypted division: x = den / d, g = Newton reciprocal of x,
+    err' = g / d (about 1 / den) and b' = num err'.  SNPs with d = 0 give 0."""
+    v = np.where(d > 0, 1.0 / np.where(d > 0, d, 1.0), 0.0)
+    x = den * v
+    inv = reciprocal_newton(x, iters, guess) * v
+    return num * inv, inv

@@ -215,3 +215,58 @@ def test_encrypted_circuit_on_oracle_other_kappa_matches_fp64(kappa):
     assert np.allclose(beta, ref.beta, atol=1e-5)
     zp = o.decrypt(out.z_proj).real
     assert np.allclose(zp[:n], ref.z_proj, atol=1e-5)
+
+
+def test_reciprocal_newton_closed_form():
+    """Newton's reciprocal from g_0 = 1 (the division extension): 1 - x g_t = (1 - x)^(2^t) exactly in real
+    arithmetic, so t = 5 steps leave a relative error (1 - x)^32 (below 1e-3 for x >= 0.2)."""
+    x = np.linspace(0.05, 1.0, 400)
+    g = F.reciprocal_newton(x, F.DIV_ITERS, F.DIV_GUESS)
+    assert np.allclose(1 - x * g, (1 - x) ** (2 ** F.DIV_ITERS), rtol=1e-9, atol=1e-15)
+    assert np.max(np.abs(g * x - 1)[x >= 0.2]) < 1e-3
+    assert G.DIV_LEVELS == 3 + 2 * (F.DIV_ITERS - 1)
+
+
+@pytest.mark.parametrize("kappa", [1, 2, 3])
+def test_snp_normalisers_bound_the_denominators(data, kappa):
+    """d_j = ||S_j - mean(S_j)||^2 / 4 bounds den_j = sum_i w_i S'_ij^2 from above (w <= 1/4; S' = M S is
+    the shortest residual after projecting out X, whose first column is the intercept), so x = den / d lies
+    in (0, 1]; a monomorphic SNP has d = 0."""
+    r = F.modified_gwas(data.X, data.y, data.S, kappa)
+    d = F.snp_normalisers(data.S)
+    ok = d > 0
+    assert np.all(r.den[ok] <= d[ok] * (1 + 1e-12))
+    assert np.all(r.den[ok] > 0.2 * d[ok])
+    Sc = data.S.astype(float) - data.S.astype(float).mean(axis=0)
+    assert np.all((r.S_proj ** 2).sum(axis=0) <= (Sc ** 2).sum(axis=0) * (1 + 1e-12))
+    S0 = data.S.copy()
+    S0[:, 0] = 1
+    assert F.snp_normalisers(S0)[0] == 0
+    b, inv = F.divide_plain(r.num, r.den, d)
+    assert np.max(np.abs(b - r.b)[ok] / np.maximum(np.abs(r.b), r.se)[ok]) < 1e-4
+    assert np.allclose(inv[ok], r.err[ok], rtol=1e-4)
+
+
+@pytest.mark.parametrize("kappa", [1, 2])
+def test_encrypted_division_on_oracle(kappa):
+    """b' and err' as ciphertexts (Newton reciprocal of the normalised denominators) on a chain longer by
+    DIV_LEVELS: decrypted directly, they match the FP64 division of the same steps and the FP64 GWAS."""
+    n, k, m = 30, 4, 70
+    p = C.make_params(10, G.circuit_depth(kappa) + G.DIV_LEVELS, 40)
+    d = make_gwas_data(n, k, m, seed=77)
+    lay = G.make_layout(p.N, n, k, m)
+    o = C.Oracle(p)
+    o.keygen(7, G.required_galois(p.N, lay.R))
+    inp = G.encrypt_inputs(o, G.encode_inputs(p, d.X, d.y, d.S, kappa), n, k, m, kappa, 11)
+    out = G.Circuit(o, lay).run(inp)
+    v = G.encrypt_normalisers(o, G.encode_normalisers(p, d.S, lay, kappa), kappa, 11)
+    assert len(v) == 2 * lay.n_batches and v[0].scale == G.normaliser_scale(p, kappa)
+    dv = G.divide_all(o, out, v)
+    assert dv.b_even[0].depth == p.L and dv.inv_odd[-1].depth == p.L - 1
+    b, err, se = G.finalize_divided(o, lay, dv)
+    ref = F.modified_gwas(d.X, d.y, d.S, kappa)
+    ok = ref.den > 1e-9 * np.max(ref.den)
+    bd, invd = F.divide_plain(ref.num, ref.den, F.snp_normalisers(d.S))
+    assert np.max(np.abs(b - bd)[ok] / np.maximum(np.abs(bd), np.sqrt(invd))[ok]) < 1e-6
+    assert np.allclose(err[ok], invd[ok], rtol=1e-6)
+    assert np.max(np.abs(b - ref.b)[ok] / np.maximum(np.abs(ref.b), ref.se)[ok]) < 1e-4
