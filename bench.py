@@ -216,6 +216,65 @@ def forms_leg(args):
     return batched, serving
 
 
+def kappa_sweep_leg(args):
+    """kappa = 1, 2, 3 Newton passes on the same workload (Discussion: the SEAL run reduces kappa to 1 to fit
+    its memory; depth table of the circuit): levels and limbs, ms per step, and the accuracy of the decrypted
+    b' against the exact semi-parallel GWAS (Sikorska et al., IRLS with the exact sigmoid) by the paper's two
+    methods (entries differing by more than e = 0.1, 0.01, 0.005, and the least-squares line of b' against
+    b), plus the largest error against the FP64 modified GWAS of the same kappa.  kappa = 1 also runs with
+    the homomorphic division (b' and err' as ciphertexts) on a chain longer by its levels."""
+    import torch
+
+    import paper_1902_04303_amd as P
+    from oracle import gwas_circuit as G
+    from oracle import gwas_fp64 as F
+    from synth import config_seed, make_gwas_data
+
+    d = make_gwas_data(N_SAMPLES, K_COV, M_SNPS, seed=config_seed(2))
+    b_exact, _ = F.sikorska_gwas(d.X, d.y, d.S)
+    rows = []
+    for kappa, divide in ((1, False), (2, False), (3, False), (1, True)):
+        L = G.circuit_depth(kappa) + (P.gwas_div_levels() if divide else 0)
+        ctx = P.Context(LOG_N, L, LOG_SCALE, alpha=args.ks_alpha)
+        lay = ctx.gwas_layout(N_SAMPLES, K_COV, M_SNPS, kappa)
+        ctx.keygen(7, galois_set(lay["R"]))
+        gin = ctx.gwas_pack_encrypt(d.X, d.y, d.S, kappa, 11)
+        v = ctx.gwas_pack_normalisers(d.S, kappa, 11) if divide else None
+        steps = max(1, min(args.steps, 3))
+        out = ctx.gwas_semiparallel(gin)
+        if divide:
+            ctx.gwas_divide(out, v)
+        torch.cuda.synchronize()
+        c0 = ctx.counters()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = ctx.gwas_semiparallel(gin)
+            if divide:
+                ctx.gwas_divide(out, v)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        c1 = ctx.counters()
+        res = ctx.gwas_finalize_divided(out) if divide else ctx.gwas_finalize(out)
+        ref = F.modified_gwas(d.X, d.y, d.S, kappa)
+        ok = ref.den > 1e-9 * np.max(ref.den)
+        g26 = float(np.max(np.abs(res["b"] - ref.b)[ok] / np.maximum(np.abs(ref.b), ref.se)[ok]))
+        counts = F.accuracy_counts(b_exact[ok], res["b"][ok])
+        slope, icpt = F.fit_line(b_exact[ok], res["b"][ok])
+        row = {"kappa": kappa, "division": divide, "levels": L, "limbs_top": L + 1,
+               "limbs_snp_batches": L + 1 - G.snp_depth(kappa), "ms_per_step": round(ms, 2),
+               "snps_per_s": round(M_SNPS / (ms * 1e-3), 1),
+               "keyswitches_per_step": (c1["keyswitches"] - c0["keyswitches"]) // steps,
+               "max_error_vs_fp64_same_kappa": g26,
+               "vs_exact_semi_parallel": {"different_entries": {str(e): c for e, (c, _) in counts.items()},
+                                          "accuracy_pct": {str(e): round(pct, 2) for e, (_, pct) in counts.items()},
+                                          "fit_line": [round(slope, 5), round(icpt, 6)], "snps": int(ok.sum())}}
+        log("[bench] kappa %d%s: L = %d, %.1f ms/step, within 0.01 of exact: %.2f %%, fit %.4f x + %.5f" %
+            (kappa, " with division" if divide else "", L, ms, counts[0.01][1], slope, icpt))
+        rows.append(row)
+        ctx.close()
+    return rows
+
+
 DEVICE_SOURCES = ["paper_1902_04303_amd/csrc/" + f
                   for f in ("ntt.hip", "kernels.hip", "modarith.h", "fmod64.h", "ckks_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
@@ -454,6 +513,7 @@ def run(args) -> int:
     batched = serving = None
     if args.forms_jobs > 0:
         batched, serving = forms_leg(args)
+    sweep = kappa_sweep_leg(args) if args.kappa_sweep else None
     ks = keyswitch_roofline(g["keyswitch"], args.steps)
     ntt = ntt_aggregate(g["warm_kernels"], g["counters"]["limb_ntts"])
     line = {
@@ -479,6 +539,7 @@ def run(args) -> int:
         "cpu_baseline": cpu,
         "batched": batched,
         "serving": serving,
+        "kappa_sweep": sweep,
         "per_step": g["counters"],
         "ms_per_step_one_stream": round(g["ms_one_stream"], 3),
         "finalize_ms": round(g["finalize_ms"], 1),
@@ -497,6 +558,8 @@ def main():
     ap.add_argument("--forms-jobs", type=int, default=12, help="jobs in the batched / serving legs (0: skip)")
     ap.add_argument("--forms-m-scale", type=float, default=0.1, help="scale of the job SNP counts")
     ap.add_argument("--forms-rate", type=float, default=4.0, help="Poisson arrival rate (jobs/s)")
+    ap.add_argument("--no-kappa-sweep", dest="kappa_sweep", action="store_false",
+                    help="skip the kappa = 1, 2, 3 sweep (and the division run)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy of BYTES (byte-counter calibration)")
     args = ap.parse_args()

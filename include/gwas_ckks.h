@@ -218,7 +218,9 @@ int ckks_ntt_device(ckks_ctx *ctx, uint64_t *dev_limbs, int count, const int *mo
 
 /* Layout: R = PO2(n) rows per block, B = N / (2R) blocks, tau = N / R SNPs per
  * SNP-batch ciphertext (two per complex slot), ceil(m / tau) batches.
- * Circuit depth: L must equal 7 kappa + 5 (kappa >= 2 Newton passes). */
+ * Circuit depth: L must be at least 7 kappa + 5 for kappa >= 2 Newton passes, and 8 for kappa = 1 (then
+ * p = sigma7(0) = 1/2, w = 1/4 and w^-1 = inverseSlots(1/4) are public constants, as in the paper's
+ * Discussion of the reduced kappa; there is no w or w^-1 ciphertext). */
 int gwas_layout(const ckks_ctx *ctx, int n, int k, int m, int kappa, int *R, int *tau, int *n_batches,
                 int *levels_needed);
 
@@ -230,7 +232,7 @@ int gwas_galois_elements(int log_n, int R, uint64_t *out, int cap, int *count);
 
 /* Client side: compute A = (X^T X)^-1 in FP64, encode and encrypt x_j (R-periodic,
  * depth 0), y (depth 0), A_jl for j <= l (replicated, depth 0, scale R Delta_0)
- * and the SNP batches (depth 7 kappa, complex-packed).  X is n x k row-major
+ * and the SNP batches (depth 7 kappa, or 4 for kappa = 1; complex-packed).  X is n x k row-major
  * with X[:,0] = 1; y in {0, 1}; S is n x m row-major uint8 in {0, 1, 2}.
  * Input ciphertext i is encrypted with seed output_i(SplitMix64(enc_seed)). */
 int gwas_pack_encrypt(ckks_ctx *ctx, const double *X, const double *y, const uint8_t *S, int n, int k, int m,
@@ -252,8 +254,36 @@ int gwas_semiparallel(ckks_ctx *ctx, const gwas_enc_input *in, gwas_enc_output *
 int gwas_semiparallel_chunked(ckks_ctx *ctx, const gwas_enc_input *in, int chunk, gwas_enc_output **out);
 /* Output ciphertexts: which = 0 num, 1 den_even, 2 den_odd, 3 S' (projected batches):
  * index = chunk number, each a batch of up to `chunk` ciphertexts in SNP-batch order;
- * 4 beta_j (index j), 5 w, 6 w^-1, 7 z', 8 u = w z'.  The handle stays owned by out. */
+ * 4 beta_j (index j), 5 w, 6 w^-1 (CKKS_E_INVALID_ARG for kappa = 1, where both are public), 7 z',
+ * 8 u = w z'.  The handle stays owned by out. */
 int gwas_output_ct(const gwas_enc_output *out, int which, int index, const ckks_ct **ct);
+
+/* ---- homomorphic division: b' and err' as ciphertexts (an extension; the paper decrypts num and den
+ * separately and divides on the client, Methods, walk-through of Alg. Semi Parallel GWAS).  The chain must
+ * hold gwas_div_levels() levels after the denominators' depth L_c (7 kappa + 5, or 8 for kappa = 1):
+ * create the context with levels >= L_c + gwas_div_levels(); the circuit itself runs unchanged on the
+ * longer chain. */
+/* Levels the division takes after the denominators: 3 + 2 (5 - 1) = 11 (5 Newton steps from guess 1). */
+int gwas_div_levels(void);
+/* Client side: the normalisers, 1 / d_j at the block start of SNP j with d_j = ||S_j - mean(S_j)||^2 / 4
+ * (an upper bound of den_j since w <= 1/4 and S' = M S is the shortest residual of S_j after projecting
+ * out X, whose first column is the intercept; 0 for a constant SNP), one ciphertext per SNP batch and
+ * parity: a batch of 2 n_batches ciphertexts, the even SNPs of every batch, then the odd, at depth L_c and
+ * scale Delta_{L_c} / (2 f), f = 2 (or 8 for kappa = 1) the factor of the denominators' tracked scale.
+ * Ciphertext i is encrypted with seed output_{2^20 + i}(SplitMix64(enc_seed)).  S as in gwas_pack_encrypt. */
+int gwas_pack_normalisers(ckks_ctx *ctx, const uint8_t *S, int n, int m, int kappa, uint64_t enc_seed,
+                          ckks_ct **out);
+/* Server side: x = Re(den) v (the real part (den + conj(den)) / 2, since the packed denominators carry
+ * cross terms in their imaginary parts), g_1 = 2 - x, then g <- g (2 - x g) four times (the pattern of
+ * Alg. inverseSlots), err' = g v and b' = num err', per chunk of SNP batches, stored in `out` (which = 9
+ * b', 10 err' of gwas_output_ct, index = chunk: 2 cnt ciphertexts, the even SNPs' then the odd SNPs'; b'
+ * of an even SNP is the real part, of an odd SNP the imaginary part).  Needs the conjugation key.  The
+ * relative error of the reciprocal is (1 - x)^32 with x = den_j / d_j in (0, 1]. */
+int gwas_divide(ckks_ctx *ctx, gwas_enc_output *out, const ckks_ct *v);
+/* Client side: decrypt the divided outputs: b', err' and se = sqrt(err') per SNP (no division). */
+int gwas_finalize_divided(ckks_ctx *ctx, const gwas_enc_output *out, int m, double *b, double *err, double *se);
+/* One batch holding the ciphertexts of parts[0..n) in order (equal depth and scale); handles are copied. */
+int ckks_ct_stack(ckks_ctx *ctx, const ckks_ct *const *parts, int n, ckks_ct **out);
 /* Client side: an output assembled from the server's num, den_even and den_odd ciphertexts (one per SNP
  * batch, n_batches of each, e.g. imported with ckks_ct_import), for gwas_finalize; the handles are copied. */
 int gwas_output_from_cts(ckks_ctx *ctx, int n, int k, int m, ckks_ct *const *num, ckks_ct *const *den_even,
@@ -337,6 +367,10 @@ void gwas_server_destroy(gwas_server *s);
 
 /* Number of key switches and NTT limb transforms issued by the context so far. */
 int ckks_ctx_counters(const ckks_ctx *ctx, uint64_t *keyswitches, uint64_t *limb_ntts, uint64_t *launches);
+/* Key switches counted per ciphertext since creation: a key switch over a batch of count ciphertexts adds
+ * count (ckks_ctx_counters counts it once).  Equals the number of single-ciphertext key switches a
+ * ciphertext-at-a-time evaluator makes for the same work. */
+int ckks_ctx_keyswitch_ciphertexts(const ckks_ctx *ctx, uint64_t *n);
 
 #ifdef __cplusplus
 }

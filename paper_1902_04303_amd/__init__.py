@@ -14,6 +14,7 @@ from ._binding import (  # noqa: F401
     LIB_PATH,
     chain,
     exported_symbols,
+    gwas_div_levels,
     gwas_galois_elements,
     ks_alpha,
     lib,

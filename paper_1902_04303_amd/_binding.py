@@ -78,6 +78,7 @@ _SIGS = [
     ("ckks_ctx_kernel_timing_only", ctypes.c_int, [_vp, ctypes.c_char_p]),
     ("ckks_ctx_set_streams", ctypes.c_int, [_vp, ctypes.c_int]),
     ("ckks_ctx_counters", ctypes.c_int, [_vp, _u64p, _u64p, _u64p]),
+    ("ckks_ctx_keyswitch_ciphertexts", ctypes.c_int, [_vp, _u64p]),
     ("ckks_keygen", ctypes.c_int, [_vp, ctypes.c_uint64, _u64p, ctypes.c_int]),
     ("ckks_galois_rotate", ctypes.c_uint64, [_vp, ctypes.c_int64]),
     ("ckks_galois_conj", ctypes.c_uint64, [_vp]),
@@ -131,6 +132,12 @@ _SIGS = [
     ("gwas_output_batches", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
     ("gwas_output_free", None, [_vp]),
     ("gwas_finalize", ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]),
+    ("gwas_div_levels", ctypes.c_int, []),
+    ("gwas_pack_normalisers", ctypes.c_int, [_vp, _u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                             ctypes.POINTER(_vp)]),
+    ("gwas_divide", ctypes.c_int, [_vp, _vp, _vp]),
+    ("gwas_finalize_divided", ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _dp, _dp]),
+    ("ckks_ct_stack", ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp)]),
     ("gwas_semiparallel_multi", ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int,
                                                ctypes.POINTER(_vp)]),
     ("gwas_input_footprint", ctypes.c_int, [_vp, _szp]),
@@ -182,6 +189,11 @@ def _i64(a: np.ndarray):
 def _f64(a: np.ndarray):
     assert a.dtype == np.float64 and a.flags.c_contiguous
     return a.ctypes.data_as(_dp)
+
+
+def gwas_div_levels() -> int:
+    """Levels the homomorphic division takes after the denominators."""
+    return int(lib().gwas_div_levels())
 
 
 def ks_alpha(log_n: int, levels: int, log2_scale: int, alpha: int = 0) -> int:
@@ -322,7 +334,10 @@ class Context:
     def counters(self):
         v = [ctypes.c_uint64() for _ in range(3)]
         _check(lib().ckks_ctx_counters(self.h, *[ctypes.byref(x) for x in v]))
-        return dict(zip(("keyswitches", "limb_ntts", "launches"), [x.value for x in v]))
+        n = ctypes.c_uint64()
+        _check(lib().ckks_ctx_keyswitch_ciphertexts(self.h, ctypes.byref(n)))
+        return dict(zip(("keyswitches", "limb_ntts", "launches", "keyswitch_ciphertexts"),
+                        [x.value for x in v] + [n.value]))
 
     def kernel_timing(self, enable: bool):
         _check(lib().ckks_ctx_kernel_timing(self.h, 1 if enable else 0))
@@ -521,6 +536,33 @@ class Context:
     def gwas_server(self, hbm_budget: int = 0, max_jobs: int = 64, chunk: int = 64) -> "GwasServer":
         return GwasServer(self, hbm_budget, max_jobs, chunk)
 
+    def stack(self, parts: Sequence[Ciphertext]) -> Ciphertext:
+        """One batch holding the ciphertexts of every part, in order (copied)."""
+        arr = (_vp * len(parts))(*[p.h for p in parts])
+        out = _vp()
+        _check(lib().ckks_ct_stack(self.h, arr, len(parts), ctypes.byref(out)))
+        return Ciphertext(self, out.value)
+
+    def gwas_pack_normalisers(self, S: np.ndarray, kappa: int, enc_seed: int) -> Ciphertext:
+        """Client side: the division's normalisers 1 / d_j (2 per SNP batch: even SNPs, then odd)."""
+        S = np.ascontiguousarray(S, dtype=np.uint8)
+        n, m = S.shape
+        out = _vp()
+        _check(lib().gwas_pack_normalisers(self.h, S.ctypes.data_as(_u8p), n, m, kappa, enc_seed,
+                                           ctypes.byref(out)))
+        return Ciphertext(self, out.value)
+
+    def gwas_divide(self, out: "GwasOutput", v: Ciphertext) -> "GwasOutput":
+        """Encrypted b' and err' (Newton reciprocal of the normalised denominators), stored in out."""
+        _check(lib().gwas_divide(self.h, out.h, v.h))
+        return out
+
+    def gwas_finalize_divided(self, out: "GwasOutput"):
+        m = out.m
+        b, err, se = (np.zeros(m) for _ in range(3))
+        _check(lib().gwas_finalize_divided(self.h, out.h, m, _f64(b), _f64(err), _f64(se)))
+        return dict(b=b, err=err, se=se)
+
     def gwas_finalize(self, out: "GwasOutput"):
         m = out.m
         b, err, se, num, den = (np.zeros(m) for _ in range(5))
@@ -603,7 +645,7 @@ class GwasServer:
 
 
 class GwasOutput:
-    NUM, DEN_EVEN, DEN_ODD, S_PROJ, BETA, W, W_INV, Z_PROJ, U = range(9)
+    NUM, DEN_EVEN, DEN_ODD, S_PROJ, BETA, W, W_INV, Z_PROJ, U, DIV_B, DIV_ERR = range(11)
 
     def __init__(self, ctx: Context, handle: int, m: int):
         self.ctx, self.h, self.m = ctx, _vp(handle), m

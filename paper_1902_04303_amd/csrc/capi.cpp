@@ -365,6 +365,13 @@ int ckks_ctx_counters(const ckks_ctx *ctx, uint64_t *keyswitches, uint64_t *limb
     });
 }
 
+int ckks_ctx_keyswitch_ciphertexts(const ckks_ctx *ctx, uint64_t *n) {
+    return guard_ctx(ctx, [&] {
+        need(n, "null argument");
+        *n = ctx->n_keyswitch_ct;
+    });
+}
+
 int ckks_ctx_kernel_timing(ckks_ctx *ctx, int enable) {
     return guard_ctx(ctx, [&] {
         need(ctx, "null context");
@@ -683,8 +690,8 @@ int gwas_pack_encrypt(ckks_ctx *ctx, const double *X, const double *y, const uin
                       int kappa, uint64_t enc_seed, gwas_enc_input **out) {
     return guard_ctx(ctx, [&] {
         need(ctx && X && y && S && out, "null argument");
-        need(kappa >= 2, "kappa must be >= 2");
-        if (ctx->p.levels != circuit_levels(kappa)) throw Error(CKKS_E_LEVEL, "chain length does not match kappa");
+        need(kappa >= 1, "kappa must be >= 1");
+        if (ctx->p.levels < circuit_levels(kappa)) throw Error(CKKS_E_LEVEL, "chain too short for kappa");
         auto in = pack_encrypt(*ctx, X, y, S, n, k, m, kappa, enc_seed);
         *out = new gwas_enc_input{ctx, std::move(in)};
     });
@@ -694,7 +701,7 @@ int gwas_input_from_cts(ckks_ctx *ctx, int n, int k, int m, int kappa, ckks_ct *
                         ckks_ct *const *A, ckks_ct *const *S, int n_s, gwas_enc_input **out) {
     return guard_ctx(ctx, [&] {
         need(ctx && x && y && A && S && out, "null argument");
-        need(kappa >= 2, "kappa must be >= 2");
+        need(kappa >= 1, "kappa must be >= 1");
         auto in = std::make_unique<EncInput>();
         in->lay = make_layout(ctx->p.n, n, k, m);
         in->kappa = kappa;
@@ -842,10 +849,15 @@ int gwas_output_ct(const gwas_enc_output *out, int which, int index, const ckks_
             need(index >= 0 && index < (int)o.beta.size(), "beta index out of range");
             *ct = o.beta[index].get();
             return;
-        case 5: *ct = o.w.get(); return;
-        case 6: *ct = o.w_inv.get(); return;
+        case 5:
+        case 6:
+            *ct = which == 5 ? o.w.get() : o.w_inv.get();
+            if (!*ct) throw Error(CKKS_E_INVALID_ARG, "w and w^-1 are public constants for kappa = 1 (no ciphertext)");
+            return;
         case 7: *ct = o.z_proj.get(); return;
         case 8: *ct = o.u.get(); return;
+        case 9: vec = &o.div_b; break;
+        case 10: vec = &o.div_inv; break;
         default: need(false, "unknown output");
         }
         need(index >= 0 && index < (int)vec->size(), "chunk index out of range");
@@ -854,6 +866,75 @@ int gwas_output_ct(const gwas_enc_output *out, int which, int index, const ckks_
 }
 
 void gwas_output_free(gwas_enc_output *out) { delete out; }
+
+int gwas_div_levels(void) { return div_levels(); }
+
+int gwas_pack_normalisers(ckks_ctx *ctx, const uint8_t *S, int n, int m, int kappa, uint64_t enc_seed,
+                          ckks_ct **out) {
+    return guard_ctx(ctx, [&] {
+        need(ctx && S && out, "null argument");
+        need(kappa >= 1 && n >= 2 && m >= 1, "bad sizes");
+        *out = release(pack_normalisers(*ctx, S, n, m, kappa, enc_seed));
+    });
+}
+
+int gwas_divide(ckks_ctx *ctx, gwas_enc_output *out, const ckks_ct *v) {
+    return guard_ctx(ctx, [&] {
+        need(out && v, "null argument");
+        need(out->ctx == ctx, "output belongs to another context");
+        check_ct(ctx, v);
+        run_divide(*ctx, out->out, *v);
+    });
+}
+
+int gwas_finalize_divided(ckks_ctx *ctx, const gwas_enc_output *out, int m, double *b, double *err, double *se) {
+    return guard_ctx(ctx, [&] {
+        need(ctx && out, "null argument");
+        const Layout &lay = out->lay;
+        need(m == lay.m, "m does not match the layout");
+        need(!out->out.div_b.empty(), "no divided outputs (gwas_divide not run)");
+        const int N = ctx->p.n, slots = N / 2;
+        std::vector<double> vb((size_t)lay.n_batches * lay.tau, 0.0), ve(vb.size(), 0.0);
+        std::vector<double> re(slots), im(slots), coeffs(N);
+        auto dec = [&](const ckks_ct &ct, int idx) {
+            auto v = decrypt_poly(*ctx, ct, idx);
+            for (int t = 0; t < N; ++t) coeffs[t] = (double)(v[t] / (long double)ct.scale);
+            decode_poly(N, coeffs.data(), re.data(), im.data());
+        };
+        int batch = 0;
+        for (size_t ch = 0; ch < out->out.div_b.size(); ++ch) {
+            const ckks_ct &cb = *out->out.div_b[ch], &ci = *out->out.div_inv[ch];
+            const int cnt = cb.count / 2;
+            for (int i = 0; i < cnt; ++i, ++batch) {
+                const size_t base = (size_t)batch * lay.tau;
+                for (int par = 0; par < 2; ++par) {
+                    dec(cb, par * cnt + i);
+                    for (int q = 0; q < lay.blocks; ++q)
+                        vb[base + 2 * q + par] = par == 0 ? re[(size_t)q * lay.R] : im[(size_t)q * lay.R];
+                    dec(ci, par * cnt + i);
+                    for (int q = 0; q < lay.blocks; ++q) ve[base + 2 * q + par] = re[(size_t)q * lay.R];
+                }
+            }
+        }
+        for (int j = 0; j < m; ++j) {
+            if (b) b[j] = vb[j];
+            if (err) err[j] = ve[j];
+            if (se) se[j] = std::sqrt(std::max(ve[j], 0.0));
+        }
+    });
+}
+
+int ckks_ct_stack(ckks_ctx *ctx, const ckks_ct *const *parts, int n, ckks_ct **out) {
+    return guard_ctx(ctx, [&] {
+        need(parts && out && n >= 1, "bad arguments");
+        std::vector<const ckks_ct *> v;
+        for (int i = 0; i < n; ++i) {
+            check_ct(ctx, parts[i]);
+            v.push_back(parts[i]);
+        }
+        *out = release(stack(*ctx, v));
+    });
+}
 
 int gwas_finalize(ckks_ctx *ctx, const gwas_enc_output *out, int m, double *b, double *err, double *se, double *num,
                   double *den) {

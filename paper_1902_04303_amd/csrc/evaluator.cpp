@@ -429,6 +429,7 @@ static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, const KsKe
     c.n_limb_ntt += (uint64_t)count * (l + kl.K) + (uint64_t)rows * (a + l);
     c.n_launch += 9;
     ++c.n_keyswitch;
+    c.n_keyswitch_ct += (uint64_t)count;
     return out;
 }
 

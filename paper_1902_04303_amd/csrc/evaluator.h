@@ -48,6 +48,7 @@ struct ckks_ctx {
     std::map<uint64_t, gck::DBuf> ksk;   // key id (0 = relinearisation, else Galois element) -> [2][ng][L+1+alpha][N]
     // counters and optional per-kernel timing
     uint64_t n_keyswitch = 0, n_limb_ntt = 0, n_launch = 0;
+    uint64_t n_keyswitch_ct = 0;   // key switches counted per ciphertext (a call over count ciphertexts adds count)
     gck::KTimer timer;
     // serialises use of the context between host threads (client calls and a server's worker)
     std::recursive_mutex mu;

@@ -16,8 +16,25 @@
 
 namespace gck {
 
-int circuit_levels(int kappa) { return 7 * kappa + 5; }
-int snp_depth(int kappa) { return 7 * kappa; }
+// kappa >= 2: 7 levels per Newton pass after the first, SNP batches at 7 kappa, denominators at 7 kappa + 5.
+// kappa = 1: the weights are public (p = sigma7(0) = 1/2), SNP batches at 4, outputs at 8.
+int circuit_levels(int kappa) {
+    if (kappa < 1) throw Error(CKKS_E_INVALID_ARG, "kappa must be >= 1");
+    return kappa == 1 ? 8 : 7 * kappa + 5;
+}
+int snp_depth(int kappa) {
+    if (kappa < 1) throw Error(CKKS_E_INVALID_ARG, "kappa must be >= 1");
+    return kappa == 1 ? 4 : 7 * kappa;
+}
+
+// Alg. inverseSlots (guess 3, three Newton steps g <- g (2 - w g)) at the public w of kappa = 1; every
+// step is exact in FP64 here: 3.75, 3.984375, 4 - 2^-14
+static double inverse_slots_public(double w) {
+    double g = 3.0;
+    for (int i = 0; i < 3; ++i) g = g * (2.0 - w * g);
+    return g;
+}
+constexpr double kWKappa1 = 0.25;
 
 Layout make_layout(int n_ring, int n, int k, int m) {
     if (n < 2 || k < 1 || m < 1) throw Error(CKKS_E_INVALID_ARG, "need n >= 2, k >= 1, m >= 1");
@@ -230,6 +247,23 @@ void fixed_back(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ck
     Ct r = add_const(c, y, -0.5);
     Ct G = C.rot_sum(mul(c, Xs, *r));                    // g_j = X^T (y - p), stacked over j
     Ct beta = mul_int(c, *st.a_times(st.parts(*G)), 4);  // beta_j = 4 (A g)_j, stacked over j
+    if (kappa == 1) {
+        // p = 1/2, w = 1/4 and w^-1 = inverseSlots(1/4) are public: z = X beta + w^-1 (y - 1/2) with the
+        // constant folded into the alignment of y - 1/2; u = z' / 4 by an alignment to the SNP part's depth
+        Ct xbeta = st.x_dot(*beta, 1.0);
+        Ct z = add(c, *xbeta, *C.at(*r, xbeta->depth, inverse_slots_public(kWKappa1)));
+        Ct H = C.rot_sum(mul(c, *C.at(Xs, z->depth), *z));
+        Ct V = st.a_times(st.parts(*H));
+        Ct xvs = st.x_dot(*V, 1.0);
+        Ct z_proj = sub(c, *C.at(*z, xvs->depth), *xvs);
+        Ct u = C.at(*z_proj, ds + 3, kWKappa1);
+        for (int j = 0; j < k; ++j) rep.beta.push_back(clone(c, *view(*beta, j * J, J)));
+        fx.u_s = C.at(*u, ds + 3);   // a view of u, which rep owns from here on
+        fx.w_s.reset();
+        rep.z_proj = std::move(z_proj);
+        rep.u = std::move(u);
+        return;
+    }
     Ct pk;
     for (int t = 1; t < kappa; ++t) {
         Ct u = st.x_dot(*beta, 0.125);                   // the 1/8 of sigma7's argument
@@ -305,6 +339,15 @@ BatchOut batch_back(ckks_ctx &c, int R, int k, const FixedOut &fx, Ct sp) {
     BatchOut o;
     o.sp = std::move(sp);
     o.num = C.rot_sum(mul(c, *fx.u_s, *o.sp));
+    if (!fx.w_s) {
+        // kappa = 1, public w = 1/4: (S' conj(S') +- S' S') / 8, the 1/8 in the tracked scale
+        Ct sc = conjugate(c, *o.sp);
+        Ct ss = mul(c, *o.sp, *o.sp);
+        Ct ssc = mul(c, *o.sp, *sc);
+        o.de = C.rot_sum(set_scale(c, add(c, *ssc, *ss), 2.0 / kWKappa1));
+        o.dodd = C.rot_sum(set_scale(c, sub(c, *ssc, *ss), 2.0 / kWKappa1));
+        return o;
+    }
     Ct ws = mul(c, *fx.w_s, *o.sp);
     Ct sc = conjugate(c, *o.sp);
     Ct wss = mul(c, *ws, *C.at(*o.sp, ws->depth));
@@ -352,7 +395,7 @@ static hipStream_t copy_stream(ckks_ctx &c) {
 void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
     const Layout &lay = in.lay;
     const int k = lay.k;
-    if (c.p.levels != circuit_levels(in.kappa))
+    if (c.p.levels < circuit_levels(in.kappa))
         throw Error(CKKS_E_LEVEL, "the chain has " + std::to_string(c.p.levels) + " levels, the circuit needs " +
                                       std::to_string(circuit_levels(in.kappa)));
     check_keys(c, lay.R);
@@ -442,6 +485,52 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
     }
 }
 
+// ---------------------------------------------------------------- homomorphic division
+
+// b' = num / den and err' = 1 / den as ciphertexts (an extension: the paper decrypts num and den and
+// divides on the client).  Per chunk, the even and the odd denominators are stacked into one batch; the
+// real part of each (its imaginary parts are cross terms of the complex packing) times the client's
+// normaliser 1 / d_j gives x in (0, 1], whose reciprocal is taken by Newton steps from guess 1 (the
+// pattern of Alg. inverseSlots: g_1 = 2 - x, then g <- g (2 - x g)); err' = g / d_j and b' = num err'
+// (num read cyclically: its real part pairs with the even half, its imaginary part with the odd half).
+int div_levels() { return 3 + 2 * (kDivIters - 1); }
+
+void run_divide(ckks_ctx &c, EncOutput &out, const ckks_ct &v) {
+    const int nb = v.count / 2;
+    if (v.count != 2 * nb || nb < 1) throw Error(CKKS_E_INVALID_ARG, "normalisers: 2 per SNP batch");
+    if (out.num.empty()) throw Error(CKKS_E_INVALID_ARG, "output has no SNP batches");
+    int total = 0;
+    for (auto &ct : out.num) total += ct->count;
+    if (total != nb) throw Error(CKKS_E_INVALID_ARG, "normalisers do not match the number of SNP batches");
+    const int dd = out.den_even[0]->depth;
+    if (v.depth != dd) throw Error(CKKS_E_LEVEL, "normalisers must be at the denominators' depth");
+    if (c.p.levels < dd + div_levels())
+        throw Error(CKKS_E_LEVEL, "the division needs " + std::to_string(div_levels()) + " levels after depth " +
+                                      std::to_string(dd));
+    Layout lay;
+    Circ C(c, lay, kBatchRadix);
+    out.div_b.clear();
+    out.div_inv.clear();
+    int b0 = 0;
+    for (size_t ch = 0; ch < out.num.size(); ++ch) {
+        const int cnt = out.num[ch]->count;
+        Ct D = stack(c, {out.den_even[ch].get(), out.den_odd[ch].get()});
+        Ct Ve = view(v, b0, cnt), Vo = view(v, nb + b0, cnt);
+        Ct V = stack(c, {Ve.get(), Vo.get()});
+        Ct x = mul(c, *set_scale(c, add(c, *D, *conjugate(c, *D)), 2.0), *V);
+        Ct g = add_const(c, *neg(c, *x), 2.0);
+        for (int it = 1; it < kDivIters; ++it) {
+            Ct h = mul(c, *C.at(*x, g->depth), *g);
+            Ct e = add_const(c, *neg(c, *h), 2.0);
+            g = mul(c, *C.at(*g, e->depth), *e);
+        }
+        Ct inv = mul(c, *g, *C.at(*V, g->depth));
+        out.div_b.push_back(mul(c, *C.at(*out.num[ch], inv->depth), *inv));
+        out.div_inv.push_back(std::move(inv));
+        b0 += cnt;
+    }
+}
+
 // ---------------------------------------------------------------- several jobs
 
 std::tuple<int, int, int> bucket_of(const EncInput &in) { return std::make_tuple(in.lay.R, in.lay.k, in.kappa); }
@@ -452,7 +541,7 @@ void fixed_for_jobs(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std:
                     std::vector<EncOutput> &reps) {
     const EncInput &j0 = *jobs[0];
     const int R = j0.lay.R, k = j0.lay.k, kappa = j0.kappa, J = (int)jobs.size();
-    if (c.p.levels != circuit_levels(kappa)) throw Error(CKKS_E_LEVEL, "chain length does not match kappa");
+    if (c.p.levels < circuit_levels(kappa)) throw Error(CKKS_E_LEVEL, "chain too short for kappa");
     check_keys(c, R);
     std::vector<Ct> xs(k), As(k * (k + 1) / 2);
     for (int j = 0; j < k; ++j) {
@@ -483,11 +572,11 @@ void fixed_for_jobs(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std:
         for (int j = 0; j < k; ++j) f.r_s.push_back(gather(c, {{fx.r_s[j].get(), q}}));
         for (int j = 0; j < k; ++j) f.x_c.push_back(gather(c, {{fx.x_c[j].get(), q}}));
         f.u_s = gather(c, {{fx.u_s.get(), q}});
-        f.w_s = gather(c, {{fx.w_s.get(), q}});
+        if (fx.w_s) f.w_s = gather(c, {{fx.w_s.get(), q}});
         EncOutput &o = reps[q];
         for (int j = 0; j < k; ++j) o.beta.push_back(gather(c, {{rep.beta[j].get(), q}}));
-        o.w = gather(c, {{rep.w.get(), q}});
-        o.w_inv = gather(c, {{rep.w_inv.get(), q}});
+        if (rep.w) o.w = gather(c, {{rep.w.get(), q}});
+        if (rep.w_inv) o.w_inv = gather(c, {{rep.w_inv.get(), q}});
         o.z_proj = gather(c, {{rep.z_proj.get(), q}});
         o.u = gather(c, {{rep.u.get(), q}});
     }
@@ -514,7 +603,7 @@ void chunk_for_jobs(ckks_ctx &c, const std::vector<WorkItem> &items) {
     for (int j = 0; j < k; ++j) fc.r_s.push_back(per_item([&](const FixedOut &f) { return f.r_s[j].get(); }));
     for (int j = 0; j < k; ++j) fc.x_c.push_back(per_item([&](const FixedOut &f) { return f.x_c[j].get(); }));
     fc.u_s = per_item([](const FixedOut &f) { return f.u_s.get(); });
-    fc.w_s = per_item([](const FixedOut &f) { return f.w_s.get(); });
+    if (items[0].fx->w_s) fc.w_s = per_item([](const FixedOut &f) { return f.w_s.get(); });
     BatchOut bo = run_batch(c, R, k, fc, *S);
     for (size_t i = 0; i < items.size(); ++i) {
         EncOutput &o = *items[i].out;
@@ -661,6 +750,53 @@ std::unique_ptr<EncInput> pack_encrypt(ckks_ctx &c, const double *X, const doubl
     }
     sync(c);
     return in;
+}
+
+// Client side: the normalisers of the division, 1 / d_j with d_j = ||S_j - mean(S_j)||^2 / 4 (an upper
+// bound of den_j: w <= 1/4 and S' = M S is the shortest residual of S_j after projecting out X, whose
+// first column is the intercept) at the block start of SNP j, 0 elsewhere and for SNPs with d_j = 0.
+// One ciphertext per SNP batch and parity (even SNPs of all batches, then odd), at the denominators'
+// depth and at scale Delta / (2 f), f the factor of the denominators' tracked scale (2, or 8 for
+// kappa = 1), so that Re(den) v lands on the canonical scale.
+Ct pack_normalisers(ckks_ctx &c, const uint8_t *S, int n, int m, int kappa, u64 enc_seed) {
+    const Layout lay = make_layout(c.p.n, n, 1, m);
+    const int dd = circuit_levels(kappa);
+    if (c.p.levels < dd) throw Error(CKKS_E_LEVEL, "chain shorter than the circuit");
+    const double f = kappa == 1 ? 2.0 / kWKappa1 : 2.0;
+    const double sc = c.p.scales[dd] / (2.0 * f);
+    std::vector<double> inv_d(m, 0.0);
+    for (int j = 0; j < m; ++j) {
+        double mean = 0;
+        for (int r = 0; r < n; ++r) mean += (double)S[(size_t)r * m + j];
+        mean /= n;
+        double ss = 0;
+        for (int r = 0; r < n; ++r) {
+            const double t = (double)S[(size_t)r * m + j] - mean;
+            ss += t * t;
+        }
+        const double d = 0.25 * ss;
+        inv_d[j] = d > 0 ? 1.0 / d : 0.0;
+    }
+    const int N = c.p.n, slots = N / 2, nb = lay.n_batches;
+    Ct v = new_ct(c, 2 * nb, dd, sc);
+    const size_t per = (size_t)2 * v->limbs * N;
+    std::vector<double> re(slots);
+    std::vector<i64> poly(N);
+    for (int par = 0; par < 2; ++par)
+        for (int b = 0; b < nb; ++b) {
+            std::fill(re.begin(), re.end(), 0.0);
+            for (int cb = 0; cb < lay.blocks; ++cb) {
+                const int j = b * lay.tau + 2 * cb + par;
+                if (j < m) re[(size_t)cb * lay.R] = inv_d[j];
+            }
+            encode_poly(N, re.data(), nullptr, slots, sc, poly.data());
+            const int i = par * nb + b;
+            Ct one = encrypt(c, poly.data(), dd, sc, input_seed(enc_seed, (1ULL << 20) + (u64)i));
+            GCK_HIP(hipMemcpyAsync(v->data.ptr + (size_t)i * per, one->data.ptr, per * 8, hipMemcpyDeviceToDevice,
+                                   c.stream));
+        }
+    sync(c);
+    return v;
 }
 
 }  // namespace gck

@@ -30,7 +30,7 @@ struct EncInput {
     std::vector<Ct> x;   // k ciphertexts, depth 0
     Ct y;                // depth 0
     std::vector<Ct> A;   // k(k+1)/2, depth 0, scale R Delta_0
-    Ct S;                // batched: n_batches ciphertexts at depth 7 kappa (data empty when spilled)
+    Ct S;                // batched: n_batches ciphertexts at snp_depth(kappa) (data empty when spilled)
     u64 *S_host = nullptr;   // the SNP batches in pinned host memory after a spill
     ~EncInput() {
         if (S_host) (void)hipHostFree(S_host);
@@ -43,8 +43,11 @@ void spill_snp(ckks_ctx &c, EncInput &in);
 
 struct EncOutput {
     std::vector<Ct> beta;
-    Ct w, w_inv, z_proj, u;
+    Ct w, w_inv, z_proj, u;   // w and w_inv empty for kappa = 1 (public constants)
     std::vector<Ct> S_proj, num, den_even, den_odd;   // one batched ciphertext per chunk
+    // after run_divide, per chunk of cnt SNP batches: 2 cnt ciphertexts, the even SNPs' then the odd SNPs'
+    // (b': real part of the even half, imaginary part of the odd half; err': real part)
+    std::vector<Ct> div_b, div_inv;
     int chunk = 0;
 };
 
@@ -52,7 +55,7 @@ struct EncOutput {
 struct FixedOut {
     std::vector<Ct> r_s;   // r_j = (X A)_{:, j} at the SNP depth
     std::vector<Ct> x_c;   // x_j at the SNP depth + 2
-    Ct u_s, w_s;           // u = w z' and w at the SNP depth + 3
+    Ct u_s, w_s;           // u = w z' and w at the SNP depth + 3 (w_s empty when w is public: kappa = 1)
     std::vector<Ct> hold;  // batches that r_s and x_c may be views of
 };
 struct BatchOut {
@@ -93,6 +96,12 @@ std::unique_ptr<EncInput> pack_encrypt(ckks_ctx &c, const double *X, const doubl
                                        int m, int kappa, u64 enc_seed);
 
 size_t input_footprint(const ckks_ctx &c, const EncInput &in);
+
+// homomorphic division (b' and err' as ciphertexts), kDivIters Newton steps from guess 1
+constexpr int kDivIters = 5;
+int div_levels();
+void run_divide(ckks_ctx &c, EncOutput &out, const ckks_ct &v);
+Ct pack_normalisers(ckks_ctx &c, const uint8_t *S, int n, int m, int kappa, u64 enc_seed);
 
 }  // namespace gck
 

@@ -334,15 +334,19 @@ def _oracle_circuit(n, k, m, kappa, log_n, b, data_seed):
     o.keygen(7, G.required_galois(p.N, lay.R))
     pts = G.encode_inputs(p, d.X, d.y, d.S, kappa)
     inp = G.encrypt_inputs(o, pts, n, k, m, kappa, 11)
+    ks0 = o.n_keyswitch
     out = G.Circuit(o, lay).run(inp)
+    o.n_keyswitch_circuit = o.n_keyswitch - ks0
     return p, d, lay, o, inp, out
 
 
-@pytest.mark.parametrize("n,k,m,log_n,b,chunk", [(30, 4, 70, 10, 30, 2), (30, 4, 150, 10, 30, None),
-                                                   (245, 4, 32, 13, 30, None)])
-def test_circuit_bit_exact_against_oracle(torch_dev, n, k, m, log_n, b, chunk):
-    kappa = 3
-    say("[gpu] circuit n=%d k=%d m=%d logN=%d" % (n, k, m, log_n))
+@pytest.mark.parametrize("n,k,m,log_n,b,chunk,kappa", [(30, 4, 70, 10, 30, 2, 3), (30, 4, 150, 10, 30, None, 3),
+                                                         (245, 4, 32, 13, 30, None, 3), (30, 4, 70, 10, 30, 2, 2),
+                                                         (30, 4, 150, 10, 30, None, 1), (245, 4, 32, 13, 30, 1, 1)])
+def test_circuit_bit_exact_against_oracle(torch_dev, n, k, m, log_n, b, chunk, kappa):
+    """Every output ciphertext of the circuit bit for bit against the oracle, for kappa = 3, 2 and 1 (the
+    reduced kappa of the paper's Discussion, with public weights)."""
+    say("[gpu] circuit n=%d k=%d m=%d logN=%d kappa=%d" % (n, k, m, log_n, kappa))
     p, d, lay, o, inp, ref = _oracle_circuit(n, k, m, kappa, log_n, b, config_seed(1))
     ctx = P.Context(log_n, p.L, b)
     ctx.keygen(7, G.required_galois(p.N, lay.R))
@@ -351,11 +355,18 @@ def test_circuit_bit_exact_against_oracle(torch_dev, n, k, m, log_n, b, chunk):
     A = [imp(inp.A[pr]) for pr in G.a_pairs(k)]
     S = [imp(c) for c in inp.S]
     gin = ctx.gwas_input_from_cts(n, k, m, kappa, x, imp(inp.y), A, S)
+    ks0 = ctx.counters()["keyswitch_ciphertexts"]
     out = ctx.gwas_semiparallel(gin, chunk)
+    # the same work as the oracle's ciphertext-at-a-time circuit: one key switch per ciphertext and step
+    assert ctx.counters()["keyswitch_ciphertexts"] - ks0 == o.n_keyswitch_circuit
     for j in range(k):
         assert np.array_equal(ctx.export(out.ct(P.GwasOutput.BETA, j)), ref.beta[j].data)
     for which, r in [(P.GwasOutput.W, ref.w), (P.GwasOutput.W_INV, ref.w_inv), (P.GwasOutput.Z_PROJ, ref.z_proj),
                      (P.GwasOutput.U, ref.u)]:
+        if r is None:   # kappa = 1: w and w^-1 are public constants
+            with pytest.raises(P.CkksError):
+                out.ct(which)
+            continue
         assert np.array_equal(ctx.export(out.ct(which)), r.data), which
     ch = chunk or lay.n_batches
     for bi in range(lay.n_batches):
@@ -374,13 +385,13 @@ def test_circuit_bit_exact_against_oracle(torch_dev, n, k, m, log_n, b, chunk):
     assert np.allclose(res["b"][ok], bb[ok], rtol=1e-7, atol=1e-12)
 
 
-@pytest.mark.parametrize("n,k,m,log_n,b,tol", [(245, 4, 32, 13, 30, 1e-3), (245, 4, 600, 16, 40, 1e-3),
-                                               (245, 4, 10643, 16, 40, 1e-3)])
-def test_end_to_end_accuracy_against_fp64(torch_dev, n, k, m, log_n, b, tol):
+@pytest.mark.parametrize("n,k,m,log_n,b,tol,kappa", [(245, 4, 32, 13, 30, 1e-3, 3), (245, 4, 600, 16, 40, 1e-3, 3),
+                                                       (245, 4, 10643, 16, 40, 1e-3, 3),
+                                                       (245, 4, 10643, 16, 40, 1e-3, 1)])
+def test_end_to_end_accuracy_against_fp64(torch_dev, n, k, m, log_n, b, tol, kappa):
     """Decrypted b' within tol of the FP64 modified GWAS (relative to max(|b'|, se)) and se within 1e-3,
     up to the benchmark's full workload (42 SNP batches of 256, the batched launches it times)."""
-    kappa = 3
-    say("[gpu] end-to-end n=%d m=%d logN=%d" % (n, m, log_n))
+    say("[gpu] end-to-end n=%d m=%d logN=%d kappa=%d" % (n, m, log_n, kappa))
     L = G.circuit_depth(kappa)
     ctx = P.Context(log_n, L, b)
     lay = ctx.gwas_layout(n, k, m, kappa)
