@@ -394,6 +394,23 @@ def mask_block_start_poly(N: int, R: int, scale: float) -> np.ndarray:
     return out
 
 
+def automorph_poly(a: np.ndarray, g: int) -> np.ndarray:
+    """X -> X^g on a signed integer polynomial: coefficient t moves to t g mod 2N, negated past N."""
+    N = len(a)
+    out = np.zeros(N, dtype=np.int64)
+    idx = (np.arange(N, dtype=np.int64) * g) % (2 * N)
+    pos = idx < N
+    out[idx[pos]] = a[pos]
+    out[idx[~pos] - N] = -a[~pos]
+    return out
+
+
+def slot_class_indicator_poly(N: int, R: int, i: int, scale: float) -> np.ndarray:
+    """Exact integer encoding of 1 at the slots j = i mod R: the block-start mask rotated right by i, i.e.
+    the automorphism X -> X^(5^-i) of mask_block_start_poly (a signed permutation of its coefficients)."""
+    return automorph_poly(mask_block_start_poly(N, R, scale), galois_rotate(N, -i))
+
+
 # --------------------------------------------------------------------------
 # keys and ciphertexts
 # --------------------------------------------------------------------------
@@ -601,6 +618,14 @@ class Oracle:
         r = self.rescale(t)
         r.scale = (a.scale * a.scale) / float(q)
         return r
+
+    def add_plain(self, a: Ct, pt: np.ndarray) -> Ct:
+        """Add a signed integer plaintext polynomial (already at a's scale) to c0."""
+        out = a.data.copy()
+        for i in range(a.limbs):
+            q = int(self.p.q[i])
+            out[0, i] = (out[0, i] + np.mod(pt, q).astype(np.uint64)) % np.uint64(q)
+        return Ct(out, a.depth, a.scale)
 
     def mul_mask(self, a: Ct, R: int) -> Ct:
         """Multiply by the block-start mask (1 at slots = 0 mod R) encoded at the ciphertext's

@@ -263,13 +263,17 @@ class EncOutput:
     num: List[C.Ct]
     den_even: List[C.Ct]
     den_odd: List[C.Ct]
+    m_cols: Optional[List[C.Ct]] = None   # M-materialised layout: Dup(M_i), i < n
 
 
 class Circuit:
-    def __init__(self, o: C.Oracle, lay: Layout):
+    def __init__(self, o: C.Oracle, lay: Layout, m_in: Optional["MInput"] = None):
+        """m_in: the client's inputs of the M-materialised layout (then S' = M S by CP-REP-MatMult and the
+        CCP SNP batches of the input are not used)."""
         self.o = o
         self.lay = lay
         self.sc = o.p.scales
+        self.m_in = m_in
 
     # canonical-scale helpers
     def at(self, a: C.Ct, d: int, factor: float = 1.0) -> C.Ct:
@@ -316,6 +320,11 @@ class Circuit:
         dc = cs[0].depth
         xe = o.mul_sum([(self.at(fx.x[j], dc), cs[j]) for j in range(k)])
         sp = o.sub(self.at(S, xe.depth), xe)
+        return (sp,) + self.num_den(sp, fx)
+
+    def num_den(self, sp: C.Ct, fx: "FixedPart"):
+        """numerator and both denominators of a projected batch S' (Alg. Semi Parallel GWAS)."""
+        o = self.o
         dsp = sp.depth
         num = self.rot_sum(o.mul(self.at(fx.u, dsp), sp), BATCH_RADIX)
         if fx.w is None:
@@ -325,14 +334,33 @@ class Circuit:
             ssc = o.mul(sp, sc)
             de = self.rot_sum(o.set_scale(o.add(ssc, ss), 2.0 / W_KAPPA1), BATCH_RADIX)
             do = self.rot_sum(o.set_scale(o.sub(ssc, ss), 2.0 / W_KAPPA1), BATCH_RADIX)
-            return sp, num, de, do
+            return num, de, do
         ws = o.mul(self.at(fx.w, dsp), sp)
         sc = o.conjugate(sp)
         wss = o.mul(ws, self.at(sp, ws.depth))
         wsc = o.mul(ws, self.at(sc, ws.depth))
         de = self.rot_sum(o.set_scale(o.add(wsc, wss), 2.0), BATCH_RADIX)
         do = self.rot_sum(o.set_scale(o.sub(wsc, wss), 2.0), BATCH_RADIX)
-        return sp, num, de, do
+        return num, de, do
+
+    # ---- the M-materialised layout (paper: Alg. CP-REP-MatMult; the walk-through of Alg. Semi Parallel
+    #      GWAS: M as a CP matrix, S' = M S_i by CP-REP-MatMult with S_i in REP form)
+    def m_columns(self, inp: EncInput, rr: List[C.Ct], m_in: "MInput") -> List[C.Ct]:
+        """Dup(M_i) = Dup(e_i) - sum_j r_j X_ij for every sample i: column i of M = I - X A X^T duplicated
+        over the ciphertext (CP), by CP-REP-MatMult of X A (columns r_j) with X^T in REP form (entry X_ij
+        replicated over every slot); the identity column is the exact indicator of the slots = i mod R."""
+        o = self.o
+        k = self.lay.k
+        out = []
+        for i in range(self.lay.n):
+            g = o.mul_sum([(rr[j], m_in.Xrep[i][j]) for j in range(k)])
+            e = C.slot_class_indicator_poly(self.lay.N, self.lay.R, i, g.scale)
+            out.append(o.add_plain(o.neg(g), e))
+        return out
+
+    def project_m(self, cols: List[C.Ct], S_rep: List[C.Ct]) -> C.Ct:
+        """S' = M S_b = sum_i Dup(M_i) (.) S_rep(i) (Alg. CP-REP-MatMult): n products in one lazy sum."""
+        return self.o.mul_sum([(self.at(cols[i], S_rep[i].depth), S_rep[i]) for i in range(self.lay.n)])
 
     def _project_z(self, inp: EncInput, z: C.Ct) -> C.Ct:
         """z' = M z = z - X (A (X^T z))."""
@@ -354,14 +382,27 @@ class Circuit:
 
     def _batches(self, inp: EncInput, fixed: FixedPart, beta, w, w_inv, z_proj, u) -> EncOutput:
         S_proj, nums, dens_e, dens_o = [], [], [], []
-        for S in inp.S:
-            sp, num, de, do = self.run_batch(S, fixed)
-            S_proj.append(sp)
-            nums.append(num)
-            dens_e.append(de)
-            dens_o.append(do)
+        cols = None
+        if self.m_in is not None:
+            cols = self.m_columns(inp, fixed.rr, self.m_in)
+            ds = snp_depth(inp.kappa) + 2
+            cols_al = [self.at(c, ds) for c in cols]
+            for Sr in self.m_in.S_rep:
+                sp = self.project_m(cols_al, Sr)
+                num, de, do = self.num_den(sp, fixed)
+                S_proj.append(sp)
+                nums.append(num)
+                dens_e.append(de)
+                dens_o.append(do)
+        else:
+            for S in inp.S:
+                sp, num, de, do = self.run_batch(S, fixed)
+                S_proj.append(sp)
+                nums.append(num)
+                dens_e.append(de)
+                dens_o.append(do)
         return EncOutput(beta=beta, w=w, w_inv=w_inv, z_proj=z_proj, u=u, S_proj=S_proj,
-                         num=nums, den_even=dens_e, den_odd=dens_o)
+                         num=nums, den_even=dens_e, den_odd=dens_o, m_cols=cols)
 
     def _run_kappa1(self, inp: EncInput, r: C.Ct, beta: List[C.Ct]) -> EncOutput:
         """kappa = 1: p = 1/2, w = 1/4 and w^-1 public; z = X beta^(1) + w^-1 (y - 1/2), z' = M z, u = z'/4."""
@@ -417,6 +458,63 @@ class Circuit:
         u = o.mul(self.at(w, z_proj.depth), z_proj)
         fixed = FixedPart(x=x, rr=self._xa(inp), w=w, u=u)
         return self._batches(inp, fixed, beta, w, w_inv, z_proj, u)
+
+
+# ---- the M-materialised layout's client inputs: X^T in REP form (X_ij in every slot, depth 2, the depth of
+#      r_j) and every SNP batch in REP form (row i of the batch, each entry over its block of R slots, two
+#      SNPs per complex slot, depth snp_depth + 2, so that S' lands at the depth of the CCP layout's S')
+M_SEED_BASE = 2 << 20    # encryption seeds: input_seed(enc_seed, base + i)
+
+
+@dataclass
+class MInput:
+    Xrep: List[List[C.Ct]]    # [i][j], i < n, j < k
+    S_rep: List[List[C.Ct]]   # [b][i]: batch b, row i
+
+
+def m_depths(kappa: int):
+    return 2, snp_depth(kappa) + 2
+
+
+def snp_rep_slots(S: np.ndarray, lay: Layout, b: int, i: int) -> np.ndarray:
+    """Row i of SNP batch b in REP form: slot c R + r (every r < R) holds S[i, b tau + 2c] + i S[i, b tau + 2c + 1]."""
+    z = np.zeros(lay.N // 2, dtype=np.complex128)
+    for c in range(lay.blocks):
+        j0 = b * lay.tau + 2 * c
+        v = 0j
+        if j0 < lay.m:
+            v += float(S[i, j0])
+        if j0 + 1 < lay.m:
+            v += 1j * float(S[i, j0 + 1])
+        z[c * lay.R:(c + 1) * lay.R] = v
+    return z
+
+
+def encode_inputs_m(params: C.Params, X: np.ndarray, S: np.ndarray, kappa: int) -> Plaintexts:
+    """Client-side encoding of the M layout's inputs: X_ij replicated (exact constant polynomials, i-major),
+    then the REP rows of every SNP batch (batch-major)."""
+    n, k = X.shape
+    lay = make_layout(params.N, n, k, S.shape[1])
+    dx, dsr = m_depths(kappa)
+    polys, depths = [], []
+    for i in range(n):
+        for j in range(k):
+            polys.append(constant_poly(X[i, j], params.N, params.scales[dx]))
+            depths.append(dx)
+    for b in range(lay.n_batches):
+        for i in range(n):
+            polys.append(C.encode(snp_rep_slots(S, lay, b, i), params.N, params.scales[dsr]))
+            depths.append(dsr)
+    return Plaintexts(polys=polys, depths=depths)
+
+
+def encrypt_inputs_m(o: C.Oracle, pts: Plaintexts, n: int, k: int, enc_seed: int) -> MInput:
+    cts = [o.encrypt(pt, d, o.p.scales[d], input_seed(enc_seed, M_SEED_BASE + i))
+           for i, (pt, d) in enumerate(zip(pts.polys, pts.depths))]
+    Xrep = [cts[i * k:(i + 1) * k] for i in range(n)]
+    rest = cts[n * k:]
+    S_rep = [rest[b * n:(b + 1) * n] for b in range(len(rest) // n)]
+    return MInput(Xrep=Xrep, S_rep=S_rep)
 
 
 # ---- homomorphic division (an extension beyond the paper, which divides on the client): b' and err' as

@@ -270,3 +270,47 @@ def test_encrypted_division_on_oracle(kappa):
     assert np.max(np.abs(b - bd)[ok] / np.maximum(np.abs(bd), np.sqrt(invd))[ok]) < 1e-6
     assert np.allclose(err[ok], invd[ok], rtol=1e-6)
     assert np.max(np.abs(b - ref.b)[ok] / np.maximum(np.abs(ref.b), ref.se)[ok]) < 1e-4
+
+
+def test_slot_class_indicator_is_the_rotated_mask():
+    """Dup(e_i) of the M layout: the exact encoding of 1 at slots = i mod R is the block-start mask moved
+    by the automorphism of a right rotation by i; it decodes to the indicator and is the mask for i = 0."""
+    N, R, sc = 1024, 32, 2.0 ** 40
+    assert np.array_equal(C.slot_class_indicator_poly(N, R, 0, sc), C.mask_block_start_poly(N, R, sc))
+    for i in (1, 7, 31):
+        m = C.slot_class_indicator_poly(N, R, i, sc)
+        assert np.count_nonzero(m) == np.count_nonzero(C.mask_block_start_poly(N, R, sc))
+        z = C.decode_poly(m.astype(np.float64) / sc, N)
+        assert np.max(np.abs(z - (np.arange(N // 2) % R == i))) < 1e-9
+
+
+@pytest.mark.parametrize("kappa", [1, 3])
+def test_m_materialised_layout_on_oracle(kappa):
+    """The M-materialised layout (Alg. CP-REP-MatMult): the n duplicated columns of M = I - X A X^T decrypt
+    to FP64 M, S' = sum_i Dup(M_i) S_rep(i) decrypts to the S' of the factorised layout, and b' matches the
+    FP64 GWAS (N = 2^10, n = 30, a ragged last batch)."""
+    n, k, m = 30, 4, 70
+    p = C.make_params(10, G.circuit_depth(kappa), 40)
+    d = make_gwas_data(n, k, m, seed=77)
+    lay = G.make_layout(p.N, n, k, m)
+    o = C.Oracle(p)
+    o.keygen(7, G.required_galois(p.N, lay.R))
+    inp = G.encrypt_inputs(o, G.encode_inputs(p, d.X, d.y, d.S, kappa), n, k, m, kappa, 11)
+    mi = G.encrypt_inputs_m(o, G.encode_inputs_m(p, d.X, d.S, kappa), n, k, 11)
+    assert len(mi.Xrep) == n and len(mi.S_rep) == lay.n_batches and len(mi.S_rep[0]) == n
+    out_m = G.Circuit(o, lay, mi).run(inp)
+    out = G.Circuit(o, lay).run(inp)
+    A = F.xtx_inverse(d.X)
+    M = np.eye(n) - d.X @ A @ d.X.T
+    cols = np.array([o.decrypt(c).real for c in out_m.m_cols])    # [i][slot]
+    for blk in (0, lay.blocks - 1):
+        got = cols[:, blk * lay.R:blk * lay.R + lay.R]
+        assert np.max(np.abs(got[:, :n].T - M)) < 1e-7          # column i of M over every block
+        assert np.max(np.abs(got[:, n:])) < 1e-7                 # padding rows
+    for b in range(lay.n_batches):
+        assert out_m.S_proj[b].depth == out.S_proj[b].depth
+        assert np.max(np.abs(o.decrypt(out_m.S_proj[b]) - o.decrypt(out.S_proj[b]))) < 1e-6
+    num, den, bb, err, se = G.finalize(o, lay, out_m)
+    ref = F.modified_gwas(d.X, d.y, d.S, kappa)
+    ok = ref.den > 1e-9 * np.max(ref.den)
+    assert np.max(np.abs(bb - ref.b)[ok] / np.maximum(np.abs(ref.b), ref.se)[ok]) < 1e-4
