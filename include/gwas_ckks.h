@@ -190,6 +190,22 @@ int ckks_add_const(ckks_ctx *ctx, const ckks_ct *a, double c, ckks_ct **out);
 /* Mult (paper: Mult then Rescale): tensor, relinearise with the s^2 key, rescale
  * by the last prime; result scale (s_a * s_b) / q. */
 int ckks_mul(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out);
+/* ckks_mul without any device allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The product (the same kernels and the same bits as ckks_mul) is
+ * written into `out`, a ciphertext batch of this context made earlier by the caller
+ * (e.g. by ckks_ct_import) holding max(count_a, count_b) ciphertexts at depth
+ * depth_a + 1; its data are overwritten and it takes the product's scale.  out may
+ * not overlap a or b.  Every intermediate buffer comes from one static device
+ * array of CKKS_NOALLOC_SCRATCH_BYTES per GPU, held from library load until the
+ * process ends: a product whose buffers need more (about 2N (3l + K + ...) words
+ * at l limbs) returns CKKS_E_INVALID_ARG before any work is enqueued.  Calls that
+ * overlap on one GPU (other host threads, other contexts or streams) share that
+ * array and race: the caller serialises them.  Nothing of the array needs to start
+ * at zero.  Errors as ckks_mul, plus CKKS_E_PARAM_MISMATCH when out has another
+ * count or depth. */
+#define CKKS_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int ckks_mul_noalloc(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct *out);
 /* Multiply by the real c encoded at a's scale s (integer round_half_away(c s)), then
  * rescale by q; result scale (s * s) / q. */
 int ckks_mul_const(ckks_ctx *ctx, const ckks_ct *a, double c, ckks_ct **out);

@@ -101,6 +101,7 @@ _SIGS = [
     ("ckks_add", ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_vp)]),
     ("ckks_sub", ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_vp)]),
     ("ckks_mul", ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    ("ckks_mul_noalloc", ctypes.c_int, [_vp, _vp, _vp, _vp]),
     ("ckks_mul_int", ctypes.c_int, [_vp, _vp, ctypes.c_int64, ctypes.POINTER(_vp)]),
     ("ckks_add_const", ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.POINTER(_vp)]),
     ("ckks_mul_const", ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.POINTER(_vp)]),
@@ -451,6 +452,11 @@ class Context:
 
     def mul(self, a, b):
         return self._op(lib().ckks_mul, a.h, b.h)
+
+    def mul_noalloc(self, a, b, out: Ciphertext) -> Ciphertext:
+        """a * b (as mul) written into the existing ciphertext `out` without any device allocation."""
+        _check(lib().ckks_mul_noalloc(self.h, a.h, b.h, out.h))
+        return out
 
     def mul_int(self, a, k: int):
         return self._op(lib().ckks_mul_int, a.h, int(k))

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libgwasckks.so")
-SOURCES = ["kernels.hip", "ntt.hip", "params.cpp", "encode.cpp", "evaluator.cpp", "gwas.cpp", "capi.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "ntt.hip", "params.cpp", "encode.cpp", "evaluator.cpp", "gwas.cpp", "capi.cpp", "server.cpp", "noalloc.hip"]
 ARCH = "gfx950"
 
 

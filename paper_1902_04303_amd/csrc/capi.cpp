@@ -315,6 +315,7 @@ int ckks_ctx_create(const ckks_params *params, const ckks_allocator *allocator, 
         c->pool->stream = c->stream;
         build_tables(*c);
         build_ks_tables(*c);
+        noalloc_init();
         c->tab.timer = &c->timer;
         *out = c.release();
     });
@@ -589,6 +590,15 @@ int ckks_mul(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out) {
         check_ct(ctx, b);
         need(out, "null output");
         *out = release(mul(*ctx, *a, *b));
+    });
+}
+
+int ckks_mul_noalloc(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct *out) {
+    return guard_ctx(ctx, [&] {
+        check_ct(ctx, a);
+        check_ct(ctx, b);
+        check_ct(ctx, out);
+        mul_noalloc(*ctx, *a, *b, *out);
     });
 }
 

@@ -81,6 +81,10 @@ i64 round_half_away(double x);
 class Pool {
 public:
     Pool(const ckks_allocator *alloc, size_t budget);
+    // An arena over one fixed device region [base, base + bytes): get() takes the next 256-byte aligned
+    // block (CKKS_E_NOMEM past the end), put() gives back only the most recent block; the allocator is
+    // never called and nothing is freed when the pool is destroyed.
+    static std::unique_ptr<Pool> arena(void *base, size_t bytes);
     ~Pool();
     void *get(size_t bytes);
     void put(void *p, size_t bytes);
@@ -92,6 +96,8 @@ public:
 private:
     ckks_allocator alloc_{};
     bool have_alloc_ = false;
+    char *arena_base_ = nullptr;   // arena mode when set
+    size_t arena_bytes_ = 0, arena_top_ = 0;
     std::multimap<size_t, void *> free_;
     void *raw_alloc(size_t bytes);
     void raw_free(void *p, size_t bytes);

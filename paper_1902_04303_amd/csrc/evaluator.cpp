@@ -26,6 +26,7 @@ Pool::Pool(const ckks_allocator *alloc, size_t b) : budget(b) {
 }
 
 Pool::~Pool() {
+    if (arena_base_) return;
     if (stream) hipStreamSynchronize(stream);
     else hipDeviceSynchronize();
     for (auto &kv : free_) raw_free(kv.second, kv.first);
@@ -55,8 +56,25 @@ void Pool::raw_free(void *p, size_t bytes) {
 
 static size_t round_bytes(size_t b) { return (b + 255) & ~size_t(255); }
 
+std::unique_ptr<Pool> Pool::arena(void *base, size_t bytes) {
+    auto p = std::make_unique<Pool>(nullptr, 0);
+    p->arena_base_ = static_cast<char *>(base);
+    p->arena_bytes_ = bytes;
+    return p;
+}
+
 void *Pool::get(size_t bytes) {
     bytes = round_bytes(bytes ? bytes : 8);
+    if (arena_base_) {
+        if (bytes > arena_bytes_ - arena_top_)
+            throw Error(CKKS_E_NOMEM, "scratch region exhausted (" + std::to_string(arena_top_ + bytes) + " > " +
+                                          std::to_string(arena_bytes_) + " bytes)");
+        void *p = arena_base_ + arena_top_;
+        arena_top_ += bytes;
+        in_use += bytes;
+        peak = std::max(peak, in_use);
+        return p;
+    }
     auto it = free_.find(bytes);
     if (it != free_.end()) {
         void *p = it->second;
@@ -86,6 +104,13 @@ void *Pool::get(size_t bytes) {
 
 void Pool::put(void *p, size_t bytes) {
     bytes = round_bytes(bytes ? bytes : 8);
+    if (arena_base_) {
+        if (static_cast<char *>(p) + bytes == arena_base_ + arena_top_) {
+            arena_top_ -= bytes;
+            in_use -= bytes;
+        }
+        return;
+    }
     free_.emplace(bytes, p);
     in_use -= bytes;
     cached += bytes;
@@ -99,7 +124,7 @@ std::unique_ptr<Pool> Pool::sibling() const {
 }
 
 void Pool::trim() {
-    if (free_.empty()) return;
+    if (arena_base_ || free_.empty()) return;
     if (stream) hipStreamSynchronize(stream);
     else hipDeviceSynchronize();
     for (auto &kv : free_) raw_free(kv.second, kv.first);

@@ -128,6 +128,12 @@ void encode_poly(int n, const double *re, const double *im, size_t n_slots, doub
 void decode_poly(int n, const double *coeffs, double *re, double *im);
 void mask_poly(int n, int R, double scale, i64 *out);
 
+// ---- the product without device allocation (noalloc.hip)
+void noalloc_init();                     // takes the current device's scratch address (once per device)
+size_t noalloc_max_bytes();
+size_t mul_noalloc_bytes(const ckks_ctx &c, int count, int l);
+void mul_noalloc(ckks_ctx &c, const ckks_ct &a, const ckks_ct &b, ckks_ct &out);
+
 void sync(ckks_ctx &c);
 // While alive, the context's operations run on its auxiliary stream and allocate from its auxiliary pool
 // (both made on first use).  The caller orders the two streams with events (fork_to_aux, join_from_aux).
