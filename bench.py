@@ -216,6 +216,146 @@ def forms_leg(args):
     return batched, serving
 
 
+def m_layout_leg(args):
+    """The M-materialised layout at the same workload (Alg. CP-REP-MatMult: M as n duplicated columns, each
+    SNP batch in REP form, S' = sum_i Dup(M_i) S_rep(i) by one lazy tensor sum per batch instead of the
+    factorised projection's rotations): ms per step with the REP inputs resident, their client encoding
+    and encryption time and their HBM size, and b' against the FP64 GWAS."""
+    import torch
+
+    import paper_1902_04303_amd as P
+    from oracle import gwas_fp64 as F
+    from synth import config_seed, make_gwas_data
+
+    L = 7 * KAPPA + 5
+    ctx = P.Context(LOG_N, L, LOG_SCALE, alpha=args.ks_alpha)
+    lay = ctx.gwas_layout(N_SAMPLES, K_COV, M_SNPS, KAPPA)
+    ctx.keygen(7, galois_set(lay["R"]))
+    d = make_gwas_data(N_SAMPLES, K_COV, M_SNPS, seed=config_seed(2))
+    gin = ctx.gwas_pack_encrypt(d.X, d.y, d.S, KAPPA, 11)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ctx.gwas_pack_encrypt_m(gin, d.X, d.S, 11)
+    torch.cuda.synchronize()
+    enc_s = time.time() - t0
+    rep_bytes = gin.footprint()
+    out = ctx.gwas_semiparallel(gin)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = ctx.gwas_semiparallel(gin)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    res = ctx.gwas_finalize(out)
+    ref = F.modified_gwas(d.X, d.y, d.S, KAPPA)
+    ok = ref.den > 1e-9 * np.max(ref.den)
+    err = float(np.max(np.abs(res["b"] - ref.b)[ok] / np.maximum(np.abs(ref.b), ref.se)[ok]))
+    log("[bench] M-materialised layout: %.1f ms/step (%.0f SNPs/s), REP inputs encrypted in %.1f s, input "
+        "footprint %.1f GB, max error %.2g" % (ms, M_SNPS / (ms * 1e-3), enc_s, rep_bytes / 1e9, err))
+    ctx.close()
+    return {"ms_per_step": round(ms, 2), "snps_per_s": round(M_SNPS / (ms * 1e-3), 1),
+            "client_rep_encrypt_s": round(enc_s, 2), "input_footprint_bytes": int(rep_bytes),
+            "rep_ciphertexts": N_SAMPLES * lay["n_batches"] + N_SAMPLES * K_COV,
+            "max_error_vs_fp64": err}
+
+
+def config3_leg(args):
+    """The batched configuration at full size: 64 seeded jobs, n ~ U{100..2000}, k = 4,
+    m ~ logU[1e3, 5e4] (R from 128 to 2048), one key set; all inputs resident.  Plain = one job at a time
+    (gwas_semiparallel, each job's outputs freed after it); batched = gwas_semiparallel_multi over all
+    jobs (jobs of one (R, k, kappa) share every launch).  S' is not kept (gwas_keep_projected 0) so that the
+    64 jobs' outputs fit beside their inputs.  A sample of jobs is checked bit for bit between the two."""
+    import torch
+
+    import paper_1902_04303_amd as P
+    from synth import job_mix, make_gwas_data
+
+    L = 7 * KAPPA + 5
+    ctx = P.Context(LOG_N, L, LOG_SCALE, alpha=args.ks_alpha)
+    ctx.keygen(7, galois_set(2048))
+    ctx.keep_projected(False)
+    jobs = job_mix(args.config3_jobs, 301, 1.0)
+    t0 = time.time()
+    ins = []
+    for n, k, m, seed in jobs:
+        d = make_gwas_data(n, k, m, seed=seed)
+        ins.append(ctx.gwas_pack_encrypt(d.X, d.y, d.S, KAPPA, 11))
+    torch.cuda.synchronize()
+    enc_s = time.time() - t0
+    snps = sum(m for _, _, m, _ in jobs)
+    batches = sum(ctx.gwas_layout(n, k, m, KAPPA)["n_batches"] for n, k, m, _ in jobs)
+    log("[bench] config 3: %d jobs, %d SNPs, %d SNP batches encrypted in %.1f s" % (len(jobs), snps, batches, enc_s))
+    sample = [0, len(jobs) // 2, len(jobs) - 1]
+    keep = {}
+    t0 = time.perf_counter()
+    for i, gin in enumerate(ins):
+        o = ctx.gwas_semiparallel(gin)
+        if i in sample:
+            keep[i] = ctx.export(o.ct(P.GwasOutput.NUM, 0), 0)
+        del o
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    log("[bench] config 3 plain: %.1f s (%.2f jobs/s)" % (plain_s, len(jobs) / plain_s))
+    t0 = time.perf_counter()
+    outs = ctx.gwas_semiparallel_multi(ins, 64)
+    torch.cuda.synchronize()
+    batched_s = time.perf_counter() - t0
+    same = all(np.array_equal(ctx.export(outs[i].ct(P.GwasOutput.NUM, 0), 0), keep[i]) for i in sample)
+    log("[bench] config 3 batched: %.1f s (%.2f jobs/s), ratio %.3f, sample bit-identical: %s" %
+        (batched_s, len(jobs) / batched_s, plain_s / batched_s, same))
+    st = ctx.pool_stats()
+    del outs
+    ctx.close()
+    return {"jobs": len(jobs), "snps": snps, "snp_batches": batches, "m_scale": 1.0,
+            "client_encrypt_s": round(enc_s, 1), "plain_s": round(plain_s, 2), "batched_s": round(batched_s, 2),
+            "plain_jobs_per_s": round(len(jobs) / plain_s, 3), "batched_jobs_per_s": round(len(jobs) / batched_s, 3),
+            "batched_snps_per_s": round(snps / batched_s, 1), "ratio": round(plain_s / batched_s, 3),
+            "target_ratio": 3.0, "sample_bit_identical": bool(same), "pool_peak_bytes": int(st["peak"])}
+
+
+def config4_leg(args):
+    """The large single job: n = 2000, k = 6, m = 100000 (R = 2048, 32 SNPs per ciphertext, 3125 SNP
+    batches), kappa = 3, resident; then the same job in a context whose pool budget is below its working
+    set, its SNP batches spilled to pinned host memory and prefetched chunk by chunk on a copy stream."""
+    import torch
+
+    import paper_1902_04303_amd as P
+    from synth import config_seed, make_gwas_data
+
+    n, k, m = 2000, 6, 100000
+    L = 7 * KAPPA + 5
+    d = make_gwas_data(n, k, m, seed=config_seed(4))
+    out = {}
+    for leg, budget in (("resident", 0), ("spilled", args.config4_budget_gb * (1 << 30))):
+        ctx = P.Context(LOG_N, L, LOG_SCALE, alpha=args.ks_alpha, pool_budget=budget)
+        ctx.keep_projected(False)
+        lay = ctx.gwas_layout(n, k, m, KAPPA)
+        ctx.keygen(7, galois_set(lay["R"]))
+        gin = ctx.gwas_pack_encrypt(d.X, d.y, d.S, KAPPA, 11)
+        fp = gin.footprint()
+        if budget:
+            gin.spill()
+        torch.cuda.synchronize()
+        o = ctx.gwas_semiparallel(gin)
+        torch.cuda.synchronize()
+        del o
+        steps = max(1, min(args.steps, 2))
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            o = ctx.gwas_semiparallel(gin)
+            del o
+        torch.cuda.synchronize()
+        s = (time.perf_counter() - t0) / steps
+        st = ctx.pool_stats()
+        out[leg] = {"seconds_per_job": round(s, 3), "snps_per_s": round(m / s, 1), "snp_batches": lay["n_batches"],
+                    "input_footprint_bytes": int(fp), "pool_budget_bytes": int(budget),
+                    "pool_peak_bytes": int(st["peak"])}
+        log("[bench] config 4 %s: %.2f s per job (%.0f SNPs/s), pool peak %.1f GB" %
+            (leg, s, m / s, st["peak"] / 1e9))
+        ctx.close()
+    return out
+
+
 def kappa_sweep_leg(args):
     """kappa = 1, 2, 3 Newton passes on the same workload (Discussion: the SEAL run reduces kappa to 1 to fit
     its memory; depth table of the circuit): levels and limbs, ms per step, and the accuracy of the decrypted
@@ -514,6 +654,9 @@ def run(args) -> int:
     if args.forms_jobs > 0:
         batched, serving = forms_leg(args)
     sweep = kappa_sweep_leg(args) if args.kappa_sweep else None
+    mlay = m_layout_leg(args) if args.m_layout else None
+    c3 = config3_leg(args) if args.config3_jobs > 0 else None
+    c4 = config4_leg(args) if args.config4 else None
     ks = keyswitch_roofline(g["keyswitch"], args.steps)
     ntt = ntt_aggregate(g["warm_kernels"], g["counters"]["limb_ntts"])
     line = {
@@ -540,6 +683,9 @@ def run(args) -> int:
         "batched": batched,
         "serving": serving,
         "kappa_sweep": sweep,
+        "m_layout": mlay,
+        "config3_batched_full": c3,
+        "config4_large_job": c4,
         "per_step": g["counters"],
         "ms_per_step_one_stream": round(g["ms_one_stream"], 3),
         "finalize_ms": round(g["finalize_ms"], 1),
@@ -558,6 +704,12 @@ def main():
     ap.add_argument("--forms-jobs", type=int, default=12, help="jobs in the batched / serving legs (0: skip)")
     ap.add_argument("--forms-m-scale", type=float, default=0.1, help="scale of the job SNP counts")
     ap.add_argument("--forms-rate", type=float, default=4.0, help="Poisson arrival rate (jobs/s)")
+    ap.add_argument("--no-m-layout", dest="m_layout", action="store_false",
+                    help="skip the M-materialised layout at the same workload")
+    ap.add_argument("--config3-jobs", type=int, default=0,
+                    help="run the batched configuration at full size with this many jobs (64: the configuration)")
+    ap.add_argument("--config4", action="store_true", help="run the large single job (n=2000, k=6, m=100000)")
+    ap.add_argument("--config4-budget-gb", type=int, default=48, help="pool budget of the spilled config-4 leg")
     ap.add_argument("--no-kappa-sweep", dest="kappa_sweep", action="store_false",
                     help="skip the kappa = 1, 2, 3 sweep (and the division run)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",

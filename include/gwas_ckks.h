@@ -271,14 +271,67 @@ int gwas_semiparallel_chunked(ckks_ctx *ctx, const gwas_enc_input *in, int chunk
 /* Output ciphertexts: which = 0 num, 1 den_even, 2 den_odd, 3 S' (projected batches):
  * index = chunk number, each a batch of up to `chunk` ciphertexts in SNP-batch order;
  * 4 beta_j (index j), 5 w, 6 w^-1 (CKKS_E_INVALID_ARG for kappa = 1, where both are public), 7 z',
- * 8 u = w z'.  The handle stays owned by out. */
+ * 8 u = w z', 9 b' and 10 err' after gwas_divide, 11 the n columns Dup(M_i) of the M-materialised layout
+ * (depth 3).  The handle stays owned by out. */
 int gwas_output_ct(const gwas_enc_output *out, int which, int index, const ckks_ct **ct);
+
+/* ---- Autotuner.  gwas_tune times every candidate schedule of the circuit on `in` itself (SNP-batch chunks
+ * of all batches up to 64, 32, 16 and 8, each with the logistic-regression part on a second stream and
+ * on one stream; HIP events around whole calls, best of `reps` after one untimed call) and records the
+ * fastest for in's shape (R, k, kappa, number of SNP batches) in the context.  Every candidate computes the
+ * same operations on the same ciphertexts: outputs are bit-identical whichever is chosen.  Returns the
+ * chosen chunk and stream count, its time, the default schedule's time (all batches, two streams) and the
+ * number of candidates.  With ckks_ctx_use_tuned(ctx, 1), gwas_semiparallel runs a recorded schedule for
+ * inputs of a tuned shape. */
+int gwas_tune(ckks_ctx *ctx, const gwas_enc_input *in, int reps, int *chunk, int *streams, double *ms,
+              double *ms_default, int *candidates);
+int ckks_ctx_use_tuned(ckks_ctx *ctx, int enable);
+/* Whether the circuit's outputs keep S' of every SNP batch (default 1).  With 0 the projected batches are
+ * dropped once their numerator and denominators are formed (gwas_output_ct(.., 3, ..) then fails), which
+ * saves their HBM (3 limbs per batch at kappa = 3) in large batched runs; nothing else changes. */
+int gwas_keep_projected(ckks_ctx *ctx, int keep);
+
+/* ---- HIP graph of the circuit (the batched form's replay path).  gwas_graph_create runs the circuit once
+ * on a private copy of `in` (which also creates the second stream and fills the pools), then captures a
+ * second call on the context's stream (which must not be the null stream) as a HIP graph and instantiates
+ * it.  Every device buffer the call takes stays reserved for the graph until gwas_graph_destroy, so a
+ * replay rewrites the same output while other work of the context goes on.  gwas_graph_set_input copies a
+ * job of the same shape (n, k, m, kappa; device-resident) into the graph's input, on the context's stream;
+ * gwas_graph_launch replays the graph on that stream (asynchronous: the output is complete once the stream
+ * reaches that point); gwas_graph_output returns the output (owned by the graph, rewritten by every
+ * replay, usable with gwas_output_ct and gwas_finalize).  chunk <= 0: as gwas_semiparallel.  Not with a
+ * pool budget, kernel timing or a spilled input (CKKS_E_INVALID_ARG). */
+typedef struct gwas_graph gwas_graph;
+int gwas_graph_create(ckks_ctx *ctx, const gwas_enc_input *in, int chunk, gwas_graph **out);
+int gwas_graph_set_input(gwas_graph *g, const gwas_enc_input *in);
+int gwas_graph_launch(gwas_graph *g);
+int gwas_graph_output(const gwas_graph *g, const gwas_enc_output **out);
+void gwas_graph_destroy(gwas_graph *g);
 
 /* ---- homomorphic division: b' and err' as ciphertexts (an extension; the paper decrypts num and den
  * separately and divides on the client, Methods, walk-through of Alg. Semi Parallel GWAS).  The chain must
  * hold gwas_div_levels() levels after the denominators' depth L_c (7 kappa + 5, or 8 for kappa = 1):
  * create the context with levels >= L_c + gwas_div_levels(); the circuit itself runs unchanged on the
  * longer chain. */
+/* ---- M-materialised layout (paper: Alg. CP-REP-MatMult and the walk-through of Alg. Semi Parallel GWAS:
+ * M = I - X (X^T X)^-1 X^T as a CP matrix, S' = M S_i by CP-REP-MatMult with S_i in REP form).  An input
+ * with these REP parts attached runs the per-SNP-batch projection as
+ *   S'_b = sum_{i < n} Dup(M_i) (.) S_rep(b, i)      (one lazy tensor sum, one relinearisation)
+ * where Dup(M_i) = Dup(e_i) - sum_j r_j X_ij is column i of M duplicated over the ciphertext (r_j the
+ * columns of X A, X_ij from the REP X^T, Dup(e_i) the exact indicator of the slots = i mod R), instead of
+ * the rotation-based factorised projection; everything after S' is unchanged, and S' lands at the same
+ * depth and scale.  One job at a time (gwas_semiparallel); n REP rows per SNP batch. */
+/* Attach REP inputs made elsewhere: xrep[n k] sample-major (X_ij replicated over every slot, depth 2,
+ * scale Delta_2), srep[n_batches n] batch-major (row i of batch b, each complex-packed entry
+ * S[i, b tau + 2c] + i S[i, b tau + 2c + 1] over its block of R slots, depth snp_depth + 2 = 7 kappa + 2,
+ * or 6 for kappa = 1, scale Delta of that depth).  Handles are copied. */
+int gwas_input_attach_m(ckks_ctx *ctx, gwas_enc_input *in, const ckks_ct *const *xrep, int n_xrep,
+                        const ckks_ct *const *srep, int n_srep);
+/* Client side: encode and encrypt those REP inputs from X (n x k row-major) and S (n x m row-major uint8)
+ * and attach them; REP ciphertext i (X first, then S) is encrypted with seed
+ * output_{2^21 + i}(SplitMix64(enc_seed)). */
+int gwas_pack_encrypt_m(ckks_ctx *ctx, gwas_enc_input *in, const double *X, const uint8_t *S, uint64_t enc_seed);
+
 /* Levels the division takes after the denominators: 3 + 2 (5 - 1) = 11 (5 Newton steps from guess 1). */
 int gwas_div_levels(void);
 /* Client side: the normalisers, 1 / d_j at the block start of SNP j with d_j = ||S_j - mean(S_j)||^2 / 4

@@ -134,6 +134,18 @@ _SIGS = [
     ("gwas_output_free", None, [_vp]),
     ("gwas_finalize", ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]),
     ("gwas_div_levels", ctypes.c_int, []),
+    ("gwas_tune", ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                 _dp, _dp, ctypes.POINTER(ctypes.c_int)]),
+    ("ckks_ctx_use_tuned", ctypes.c_int, [_vp, ctypes.c_int]),
+    ("gwas_keep_projected", ctypes.c_int, [_vp, ctypes.c_int]),
+    ("gwas_graph_create", ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(_vp)]),
+    ("gwas_graph_set_input", ctypes.c_int, [_vp, _vp]),
+    ("gwas_graph_launch", ctypes.c_int, [_vp]),
+    ("gwas_graph_output", ctypes.c_int, [_vp, ctypes.POINTER(_vp)]),
+    ("gwas_graph_destroy", None, [_vp]),
+    ("gwas_input_attach_m", ctypes.c_int, [_vp, _vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp),
+                                           ctypes.c_int]),
+    ("gwas_pack_encrypt_m", ctypes.c_int, [_vp, _vp, _dp, _u8p, ctypes.c_uint64]),
     ("gwas_pack_normalisers", ctypes.c_int, [_vp, _u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                                              ctypes.POINTER(_vp)]),
     ("gwas_divide", ctypes.c_int, [_vp, _vp, _vp]),
@@ -542,12 +554,45 @@ class Context:
     def gwas_server(self, hbm_budget: int = 0, max_jobs: int = 64, chunk: int = 64) -> "GwasServer":
         return GwasServer(self, hbm_budget, max_jobs, chunk)
 
+    def gwas_tune(self, inp: "GwasInput", reps: int = 2):
+        """Time the bit-identical schedules (chunk, streams) on inp and record the fastest for its shape."""
+        ch, st, cand = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        ms, ms0 = ctypes.c_double(), ctypes.c_double()
+        _check(lib().gwas_tune(self.h, inp.h, reps, ctypes.byref(ch), ctypes.byref(st), ctypes.byref(ms),
+                               ctypes.byref(ms0), ctypes.byref(cand)))
+        return dict(chunk=ch.value, streams=st.value, ms=ms.value, ms_default=ms0.value, candidates=cand.value)
+
+    def keep_projected(self, keep: bool):
+        """Whether outputs keep S' of every SNP batch (default True)."""
+        _check(lib().gwas_keep_projected(self.h, 1 if keep else 0))
+
+    def use_tuned(self, enable: bool = True):
+        _check(lib().ckks_ctx_use_tuned(self.h, 1 if enable else 0))
+
+    def gwas_graph(self, inp: "GwasInput", chunk: int = 0) -> "GwasGraph":
+        """gwas_semiparallel of inp's shape captured as a HIP graph (replayed by GwasGraph.launch)."""
+        return GwasGraph(self, inp, chunk)
+
     def stack(self, parts: Sequence[Ciphertext]) -> Ciphertext:
         """One batch holding the ciphertexts of every part, in order (copied)."""
         arr = (_vp * len(parts))(*[p.h for p in parts])
         out = _vp()
         _check(lib().ckks_ct_stack(self.h, arr, len(parts), ctypes.byref(out)))
         return Ciphertext(self, out.value)
+
+    def gwas_input_attach_m(self, inp: "GwasInput", xrep: Sequence[Ciphertext], srep: Sequence[Ciphertext]):
+        """M-materialised layout: attach the REP X^T (n k, sample-major) and REP SNP rows (n per batch)."""
+        xa = (_vp * len(xrep))(*[c.h for c in xrep])
+        sa = (_vp * len(srep))(*[c.h for c in srep])
+        _check(lib().gwas_input_attach_m(self.h, inp.h, xa, len(xrep), sa, len(srep)))
+        return inp
+
+    def gwas_pack_encrypt_m(self, inp: "GwasInput", X: np.ndarray, S: np.ndarray, enc_seed: int):
+        """Client side: encrypt and attach the REP inputs of the M-materialised layout."""
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        S = np.ascontiguousarray(S, dtype=np.uint8)
+        _check(lib().gwas_pack_encrypt_m(self.h, inp.h, _f64(X), S.ctypes.data_as(_u8p), enc_seed))
+        return inp
 
     def gwas_pack_normalisers(self, S: np.ndarray, kappa: int, enc_seed: int) -> Ciphertext:
         """Client side: the division's normalisers 1 / d_j (2 per SNP batch: even SNPs, then odd)."""
@@ -574,6 +619,34 @@ class Context:
         b, err, se, num, den = (np.zeros(m) for _ in range(5))
         _check(lib().gwas_finalize(self.h, out.h, m, _f64(b), _f64(err), _f64(se), _f64(num), _f64(den)))
         return dict(b=b, err=err, se=se, num=num, den=den)
+
+
+class GwasGraph:
+    def __init__(self, ctx: Context, inp: "GwasInput", chunk: int):
+        self.ctx, self.m = ctx, inp.m
+        h = _vp()
+        _check(lib().gwas_graph_create(ctx.h, inp.h, chunk, ctypes.byref(h)))
+        self.h = h
+        o = _vp()
+        _check(lib().gwas_graph_output(self.h, ctypes.byref(o)))
+        self.out = GwasOutput(ctx, o.value, inp.m, owned=False)
+        self.out._parent = self
+
+    def set_input(self, inp: "GwasInput"):
+        _check(lib().gwas_graph_set_input(self.h, inp.h))
+
+    def launch(self) -> "GwasOutput":
+        """Replay the graph on the context's stream; returns the (graph-owned) output."""
+        _check(lib().gwas_graph_launch(self.h))
+        return self.out
+
+    def close(self):
+        if self.h and self.ctx is not None and self.ctx.h:
+            lib().gwas_graph_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 class GwasInput:
@@ -651,15 +724,15 @@ class GwasServer:
 
 
 class GwasOutput:
-    NUM, DEN_EVEN, DEN_ODD, S_PROJ, BETA, W, W_INV, Z_PROJ, U, DIV_B, DIV_ERR = range(11)
+    NUM, DEN_EVEN, DEN_ODD, S_PROJ, BETA, W, W_INV, Z_PROJ, U, DIV_B, DIV_ERR, M_COLS = range(12)
 
-    def __init__(self, ctx: Context, handle: int, m: int):
-        self.ctx, self.h, self.m = ctx, _vp(handle), m
+    def __init__(self, ctx: Context, handle: int, m: int, owned: bool = True):
+        self.ctx, self.h, self.m, self.owned = ctx, _vp(handle), m, owned
 
     def __del__(self):
-        if self.h and self.ctx is not None and self.ctx.h:
+        if self.owned and self.h and self.ctx is not None and self.ctx.h:
             lib().gwas_output_free(self.h)
-            self.h = None
+        self.h = None
 
     def ct(self, which: int, index: int = 0) -> Ciphertext:
         out = _vp()

@@ -835,7 +835,39 @@ int gwas_semiparallel_multi(ckks_ctx *ctx, const gwas_enc_input *const *in, int 
 
 int gwas_semiparallel(ckks_ctx *ctx, const gwas_enc_input *in, gwas_enc_output **out) {
     const int chunk = in && in->in ? std::max(1, in->in->S->count) : 1;
+    if (ctx && in && in->in && ctx->use_tuned) {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        auto it = ctx->tuned.find(schedule_key(*in->in));
+        if (it != ctx->tuned.end()) {
+            const int saved = ctx->n_streams;
+            ctx->n_streams = it->second.streams;
+            const int rc = gwas_semiparallel_chunked(ctx, in, it->second.chunk, out);
+            ctx->n_streams = saved;
+            return rc;
+        }
+    }
     return gwas_semiparallel_chunked(ctx, in, chunk > 64 ? 64 : chunk, out);
+}
+
+int gwas_tune(ckks_ctx *ctx, const gwas_enc_input *in, int reps, int *chunk, int *streams, double *ms,
+              double *ms_default, int *candidates) {
+    return guard_ctx(ctx, [&] {
+        need(in && in->ctx == ctx, "bad arguments");
+        const TuneResult r = tune_circuit(*ctx, *in->in, reps);
+        if (chunk) *chunk = r.best.chunk;
+        if (streams) *streams = r.best.streams;
+        if (ms) *ms = r.best.ms;
+        if (ms_default) *ms_default = r.ms_default;
+        if (candidates) *candidates = r.candidates;
+    });
+}
+
+int gwas_keep_projected(ckks_ctx *ctx, int keep) {
+    return guard_ctx(ctx, [&] { ctx->keep_s_proj = keep != 0; });
+}
+
+int ckks_ctx_use_tuned(ckks_ctx *ctx, int enable) {
+    return guard_ctx(ctx, [&] { ctx->use_tuned = enable != 0; });
 }
 
 int gwas_output_batches(const gwas_enc_output *out, int *n_batches) {
@@ -868,6 +900,10 @@ int gwas_output_ct(const gwas_enc_output *out, int which, int index, const ckks_
         case 8: *ct = o.u.get(); return;
         case 9: vec = &o.div_b; break;
         case 10: vec = &o.div_inv; break;
+        case 11:
+            *ct = o.m_cols.get();
+            if (!*ct) throw Error(CKKS_E_INVALID_ARG, "no M columns (the input has no M-materialised layout)");
+            return;
         default: need(false, "unknown output");
         }
         need(index >= 0 && index < (int)vec->size(), "chunk index out of range");
@@ -877,7 +913,69 @@ int gwas_output_ct(const gwas_enc_output *out, int which, int index, const ckks_
 
 void gwas_output_free(gwas_enc_output *out) { delete out; }
 
+int gwas_graph_create(ckks_ctx *ctx, const gwas_enc_input *in, int chunk, gwas_graph **out) {
+    return guard_ctx(ctx, [&] {
+        need(in && out && in->ctx == ctx, "bad arguments");
+        *out = nullptr;
+        const int nb = in->in->S->count;
+        if (chunk <= 0) chunk = std::min(64, std::max(1, nb));
+        *out = capture_circuit(*ctx, *in->in, chunk).release();
+    });
+}
+
+int gwas_graph_set_input(gwas_graph *g, const gwas_enc_input *in) {
+    if (!g) return CKKS_E_INVALID_ARG;
+    return guard_ctx(g->ctx, [&] {
+        need(in && in->ctx == g->ctx, "bad arguments");
+        graph_set_input(*g, *in->in);
+    });
+}
+
+int gwas_graph_launch(gwas_graph *g) {
+    if (!g) return CKKS_E_INVALID_ARG;
+    return guard_ctx(g->ctx, [&] { graph_launch(*g); });
+}
+
+int gwas_graph_output(const gwas_graph *g, const gwas_enc_output **out) {
+    return guard([&] {
+        need(g && out, "null argument");
+        *out = g->out.get();
+    });
+}
+
+void gwas_graph_destroy(gwas_graph *g) {
+    if (!g) return;
+    std::lock_guard<std::recursive_mutex> lk(g->ctx->mu);
+    delete g;
+}
+
 int gwas_div_levels(void) { return div_levels(); }
+
+int gwas_input_attach_m(ckks_ctx *ctx, gwas_enc_input *in, const ckks_ct *const *xrep, int n_xrep,
+                        const ckks_ct *const *srep, int n_srep) {
+    return guard_ctx(ctx, [&] {
+        need(in && xrep && srep && in->ctx == ctx, "bad arguments");
+        need(n_xrep == in->in->lay.n * in->in->lay.k && n_srep == in->in->lay.n * in->in->lay.n_batches,
+             "need n k REP entries of X^T and n REP rows per SNP batch");
+        std::vector<const ckks_ct *> xs, ss;
+        for (int i = 0; i < n_xrep; ++i) {
+            check_ct(ctx, xrep[i]);
+            xs.push_back(xrep[i]);
+        }
+        for (int i = 0; i < n_srep; ++i) {
+            check_ct(ctx, srep[i]);
+            ss.push_back(srep[i]);
+        }
+        attach_m(*ctx, *in->in, stack(*ctx, xs), stack(*ctx, ss));
+    });
+}
+
+int gwas_pack_encrypt_m(ckks_ctx *ctx, gwas_enc_input *in, const double *X, const uint8_t *S, uint64_t enc_seed) {
+    return guard_ctx(ctx, [&] {
+        need(in && X && S && in->ctx == ctx, "bad arguments");
+        pack_encrypt_m(*ctx, *in->in, X, S, enc_seed);
+    });
+}
 
 int gwas_pack_normalisers(ckks_ctx *ctx, const uint8_t *S, int n, int m, int kappa, uint64_t enc_seed,
                           ckks_ct **out) {

@@ -89,6 +89,12 @@ public:
     void *get(size_t bytes);
     void put(void *p, size_t bytes);
     void trim();
+    // Graph capture: blocks handed out between capture_begin and capture_end are recorded; capture_end
+    // takes those that are free again out of the free lists and returns them (they stay reserved for the
+    // captured graph, whose replays write them) until give_back.
+    void capture_begin();
+    std::vector<std::pair<void *, size_t>> capture_end();
+    void give_back(const std::vector<std::pair<void *, size_t>> &blocks);
     std::unique_ptr<Pool> sibling() const;   // an empty pool with the same allocator (no budget)
     size_t in_use = 0, cached = 0, peak = 0, n_alloc = 0, budget = 0;
     hipStream_t stream = nullptr;
@@ -96,6 +102,8 @@ public:
 private:
     ckks_allocator alloc_{};
     bool have_alloc_ = false;
+    bool capturing_ = false;
+    std::map<void *, size_t> captured_;
     char *arena_base_ = nullptr;   // arena mode when set
     size_t arena_bytes_ = 0, arena_top_ = 0;
     std::multimap<size_t, void *> free_;
@@ -264,6 +272,10 @@ void k_add(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs
            hipStream_t st);
 void k_sub(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
            hipStream_t st);
+void k_tensor_rep_sum(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int cnt, int n_rows, int l,
+                      hipStream_t st);
+void k_add_rotated_plain(const DevTables &t, u64 *out, const u64 *a, const u64 *pt, int count, int l, int R,
+                         hipStream_t st);
 void k_mul(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
            hipStream_t st);
 // out = a * c[chain]

@@ -6,12 +6,29 @@
 // a length-N complex DFT; decode is the forward transform v_{2k+1} = sum_i (m_i zeta^i) omega^(i k).
 #include <cmath>
 #include <complex>
+#include <map>
+#include <mutex>
 
 #include "ckks_internal.h"
 
 namespace gck {
 
 using cd = std::complex<double>;
+
+// twiddles of one stage of the transform, w_j = exp(i ang j) with ang = sign 2 pi / len, made once per
+// (len, sign) and shared by every thread afterwards (the values are those the butterflies computed inline)
+static const std::vector<cd> &stage_twiddles(size_t len, int sign) {
+    static std::mutex mu;
+    static std::map<std::pair<size_t, int>, std::vector<cd>> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto &w = cache[{len, sign}];
+    if (w.empty()) {
+        const double ang = sign * 2.0 * M_PI / (double)len;
+        w.resize(len / 2);
+        for (size_t j = 0; j < len / 2; ++j) w[j] = cd(std::cos(ang * (double)j), std::sin(ang * (double)j));
+    }
+    return w;
+}
 
 // in-place radix-2 DFT: X_k = sum_i x_i exp(sign * 2 pi i ik / n)
 static void fft(std::vector<cd> &a, int sign) {
@@ -23,11 +40,10 @@ static void fft(std::vector<cd> &a, int sign) {
         if (i < j) std::swap(a[i], a[j]);
     }
     for (size_t len = 2; len <= n; len <<= 1) {
-        const double ang = sign * 2.0 * M_PI / (double)len;
+        const std::vector<cd> &w = stage_twiddles(len, sign);
         for (size_t s = 0; s < n; s += len) {
             for (size_t j = 0; j < len / 2; ++j) {
-                cd w(std::cos(ang * (double)j), std::sin(ang * (double)j));
-                cd u = a[s + j], v = a[s + j + len / 2] * w;
+                cd u = a[s + j], v = a[s + j + len / 2] * w[j];
                 a[s + j] = u + v;
                 a[s + j + len / 2] = u - v;
             }

@@ -82,6 +82,7 @@ void *Pool::get(size_t bytes) {
         cached -= bytes;
         in_use += bytes;
         peak = std::max(peak, in_use);
+        if (capturing_) captured_[p] = bytes;
         return p;
     }
     if (budget && in_use + cached + bytes > budget) {
@@ -99,7 +100,38 @@ void *Pool::get(size_t bytes) {
     }
     in_use += bytes;
     peak = std::max(peak, in_use);
+    if (capturing_) captured_[p] = bytes;
     return p;
+}
+
+void Pool::capture_begin() {
+    capturing_ = true;
+    captured_.clear();
+}
+
+std::vector<std::pair<void *, size_t>> Pool::capture_end() {
+    capturing_ = false;
+    std::vector<std::pair<void *, size_t>> out;
+    for (auto it = free_.begin(); it != free_.end();) {
+        if (captured_.count(it->second)) {
+            out.push_back({it->second, it->first});
+            cached -= it->first;
+            in_use += it->first;
+            it = free_.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    captured_.clear();
+    return out;
+}
+
+void Pool::give_back(const std::vector<std::pair<void *, size_t>> &blocks) {
+    for (auto &b : blocks) {
+        free_.emplace(b.second, b.first);
+        in_use -= b.second;
+        cached += b.second;
+    }
 }
 
 void Pool::put(void *p, size_t bytes) {
@@ -492,20 +524,49 @@ Ct mul_sum(ckks_ctx &c, const std::vector<std::pair<const ckks_ct *, const ckks_
                  pairs[i].second->count, i > 0, c.stream);
         ++c.n_launch;
     }
-    // relinearise: (d0, d1) + KS(d2, s^2 key)
+    return relin_rescale(c, std::move(d), count, a0.depth, l, a0.scale, b0.scale);
+}
+
+// relinearise the tensors d ([count][3][l][N]): (d0, d1) + KS(d2, s^2 key), then rescale; result scale
+// (sa * sb) / q
+Ct relin_rescale(ckks_ctx &c, DBuf d, int count, int depth, int l, double sa, double sb) {
     DBuf ks = keyswitch(c, Gather{d.ptr, l, 3 * l, 2 * l, 1, kPlain, 0}, count, l, ks_keys(c, {0}, false),
                         Gather{d.ptr, 2 * l, 3 * l, 0, 1, kPlain, 0}, false);
     d.release();
     ckks_ct tmp;
     tmp.ctx = &c;
     tmp.count = count;
-    tmp.depth = a0.depth;
+    tmp.depth = depth;
     tmp.limbs = l;
-    tmp.scale = a0.scale;
+    tmp.scale = sa;
     tmp.data = std::move(ks);
-    const u64 q = c.p.dropped_at(a0.depth);
+    const u64 q = c.p.dropped_at(depth);
     Ct r = rescale(c, tmp);
-    r->scale = (a0.scale * b0.scale) / (double)q;
+    r->scale = (sa * sb) / (double)q;
+    return r;
+}
+
+// sum_i cols_i (x) rep_{b, i} for every batch b (CP-REP-MatMult of the M-materialised layout): one
+// tensor-sum launch, one relinearisation and one rescale for the chunk
+Ct mul_sum_rep(ckks_ctx &c, const ckks_ct &cols, const ckks_ct &rep) {
+    const int n_rows = cols.count, cnt = rep.count / cols.count;
+    if (cnt * n_rows != rep.count || cnt < 1) throw Error(CKKS_E_PARAM_MISMATCH, "REP rows do not fill whole batches");
+    if (cols.depth != rep.depth) throw Error(CKKS_E_PARAM_MISMATCH, "product operands at different depths");
+    const int l = cols.limbs;
+    DBuf d(c.pool.get(), (size_t)cnt * 3 * l * c.p.n);
+    k_tensor_rep_sum(c.tab, d.ptr, cols.data.ptr, rep.data.ptr, cnt, n_rows, l, c.stream);
+    ++c.n_launch;
+    return relin_rescale(c, std::move(d), cnt, cols.depth, l, cols.scale, rep.scale);
+}
+
+// c0 of ciphertext i plus the exact indicator of the slots = i mod R at a's scale (the block-start mask
+// moved by the automorphism of a right rotation by i)
+Ct add_slot_indicators(ckks_ctx &c, const ckks_ct &a, int R) {
+    const int l = a.limbs;
+    const u64 *pt = mask_plain(c, R, l, a.scale);
+    Ct r = new_ct(c, a.count, a.depth, a.scale);
+    k_add_rotated_plain(c.tab, r->data.ptr, a.data.ptr, pt, a.count, l, R, c.stream);
+    ++c.n_launch;
     return r;
 }
 

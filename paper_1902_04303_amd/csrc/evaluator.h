@@ -58,6 +58,15 @@ struct ckks_ctx {
     hipStream_t aux_stream = nullptr;
     std::unique_ptr<gck::Pool> aux_pool;
     int n_streams = 2;   // 1: the circuit runs in order on `stream` only
+    bool capturing = false;   // a HIP graph capture of the circuit is in progress on `stream`
+    // schedules chosen by the tuner per input shape (R, k, kappa, SNP batches): chunk and stream count
+    struct Schedule {
+        int chunk = 0, streams = 2;
+        double ms = 0;
+    };
+    std::map<std::tuple<int, int, int, int>, Schedule> tuned;
+    bool use_tuned = false;
+    bool keep_s_proj = true;   // the circuit's outputs include S' of every SNP batch
     // block-start masks in NTT form by (R, limbs, scale bits), made once and then only read
     std::map<std::tuple<int, int, uint64_t>, gck::DBuf> mask_cache;
     ~ckks_ctx();
@@ -102,6 +111,12 @@ Ct set_scale(ckks_ctx &c, Ct a, double factor);
 // sum_i a_i * b_i: one tensor per pair accumulated, one relinearisation, one rescale
 Ct mul_sum(ckks_ctx &c, const std::vector<std::pair<const ckks_ct *, const ckks_ct *>> &pairs);
 Ct mul(ckks_ctx &c, const ckks_ct &a, const ckks_ct &b);
+// relinearise and rescale a batch of tensors d ([count][3][l][N] at `depth`, operand scales sa, sb)
+Ct relin_rescale(ckks_ctx &c, DBuf d, int count, int depth, int l, double sa, double sb);
+// M-materialised layout: sum_i cols_i (x) rep_{b, i} for every batch b (rep: [cnt][n] ciphertexts)
+Ct mul_sum_rep(ckks_ctx &c, const ckks_ct &cols, const ckks_ct &rep);
+// c0 of ciphertext i plus the exact indicator of the slots = i mod R (at a's scale)
+Ct add_slot_indicators(ckks_ctx &c, const ckks_ct &a, int R);
 Ct apply_galois(ckks_ctx &c, const ckks_ct &a, u64 g);
 Ct rotate(ckks_ctx &c, const ckks_ct &a, i64 r);
 // a + sum_i Rot(a, rots[i]) with one key switch shared by the rotations (at most 16)

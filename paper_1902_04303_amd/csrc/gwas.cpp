@@ -11,6 +11,8 @@
 // with r_j = sum_l A_jl x_l, all SNP batches of a chunk in one batched ciphertext.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <thread>
 
 #include "gwas.h"
 
@@ -214,13 +216,31 @@ struct Stacked {
 }  // namespace
 
 void fixed_front(ckks_ctx &c, int R, int k, const std::vector<const ckks_ct *> &x, const std::vector<const ckks_ct *> &Ain,
-                 int ds, FixedOut &fx, const StackIn *pre = nullptr) {
+                 int ds, FixedOut &fx, const StackIn *pre = nullptr, const ckks_ct *xrep = nullptr,
+                 EncOutput *rep = nullptr) {
     Stacked st(c, R, k, x, Ain, pre);
     const int J = st.J;
     // ---- r_j = (X A)_{:, j}, and x_j at the depth the per-batch part uses it
     std::vector<Ct> x1(k);
     for (int l = 0; l < k; ++l) x1[l] = st.C.at(*x[l], 1);
     Ct RR = st.a_times(x1);
+    if (xrep) {
+        // M-materialised layout (Alg. CP-REP-MatMult of X A with the REP X^T, one column of M at a time):
+        // Dup(M_i) = Dup(e_i) - sum_j r_j X_ij for every sample i, as one batch of n
+        if (J != 1) throw Error(CKKS_E_INVALID_ARG, "the M-materialised layout runs one job at a time");
+        const int n = xrep->count / k;
+        std::vector<Ct> rj(k), xj(k);
+        std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pr;
+        for (int j = 0; j < k; ++j) {
+            rj[j] = view(*RR, j, 1);
+            xj[j] = view(*xrep, j * n, n);
+            pr.push_back({rj[j].get(), xj[j].get()});
+        }
+        Ct G = mul_sum(c, pr);
+        Ct D = add_slot_indicators(c, *neg(c, *G), R);
+        fx.m_cols = st.C.at(*D, ds + 2);
+        if (rep) rep->m_cols = std::move(D);
+    }
     Ct RRs = st.C.at(*RR, ds);
     // x_j at ds + 2 owned here (the stacked x may be the caller's, shared with the other part)
     Ct Xc = st.Xs.depth == ds + 2 ? clone(c, st.Xs) : st.C.at(st.Xs, ds + 2);
@@ -330,6 +350,12 @@ Ct batch_front(ckks_ctx &c, int R, int k, const FixedOut &fx, const ckks_ct &S) 
     return sub(c, *C.at(S, xe->depth), *xe);
 }
 
+// S' = M S of a chunk in the M-materialised layout: sum_i Dup(M_i) (.) S_rep(i) per batch
+// (Alg. CP-REP-MatMult), one lazy tensor sum, one relinearisation and one rescale
+Ct batch_front_m(ckks_ctx &c, const FixedOut &fx, const ckks_ct &S_rep_chunk) {
+    return mul_sum_rep(c, *fx.m_cols, S_rep_chunk);
+}
+
 // numerator and denominators from S' (needs u and w of the fixed part)
 BatchOut batch_back(ckks_ctx &c, int R, int k, const FixedOut &fx, Ct sp) {
     Layout lay;
@@ -416,25 +442,46 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
             OnStream on_aux(c);
             fixed_back(c, lay.R, k, in.kappa, x, *in.y, A, ds, fx, out, &sin);
         }
-        fixed_front(c, lay.R, k, x, A, ds, fx, &sin);
+        fixed_front(c, lay.R, k, x, A, ds, fx, &sin, in.Xrep.get(), &out);
         std::vector<Ct> sps;
         for (int b0 = 0; b0 < nb; b0 += chunk) {
             const int cnt = std::min(chunk, nb - b0);
             // the batches are device-resident here (no spill): the chunk is a view, read only
+            if (in.S_rep) {
+                Ct Sr = view(*in.S_rep, b0 * lay.n, cnt * lay.n);
+                sps.push_back(batch_front_m(c, fx, *Sr));
+                continue;
+            }
             Ct S = view(*in.S, b0, cnt);
             sps.push_back(batch_front(c, lay.R, k, fx, *S));
         }
         stream_wait(c.stream, c.aux_stream);   // u and w
         for (Ct &sp : sps) {
             BatchOut o = batch_back(c, lay.R, k, fx, std::move(sp));
-            out.S_proj.push_back(std::move(o.sp));
+            if (c.keep_s_proj) out.S_proj.push_back(std::move(o.sp));
             out.num.push_back(std::move(o.num));
             out.den_even.push_back(std::move(o.de));
             out.den_odd.push_back(std::move(o.dodd));
         }
         // buffers of the auxiliary pool were read on the main stream: later reuse on the auxiliary stream
-        // comes after this work
-        stream_wait(c.aux_stream, c.stream);
+        // comes after this work (under graph capture every block of the call stays reserved for the graph,
+        // and the next call's own first wait orders the streams)
+        if (!c.capturing) stream_wait(c.aux_stream, c.stream);
+        return;
+    }
+    if (in.S_rep) {
+        // M-materialised layout on one stream (or under a pool budget): device-resident REP rows only
+        fixed_front(c, lay.R, k, x, A, ds, fx, nullptr, in.Xrep.get(), &out);
+        fixed_back(c, lay.R, k, in.kappa, x, *in.y, A, ds, fx, out);
+        for (int b0 = 0; b0 < nb; b0 += chunk) {
+            const int cnt = std::min(chunk, nb - b0);
+            Ct Sr = view(*in.S_rep, b0 * lay.n, cnt * lay.n);
+            BatchOut o = batch_back(c, lay.R, k, fx, batch_front_m(c, fx, *Sr));
+            if (c.keep_s_proj) out.S_proj.push_back(std::move(o.sp));
+            out.num.push_back(std::move(o.num));
+            out.den_even.push_back(std::move(o.de));
+            out.den_odd.push_back(std::move(o.dodd));
+        }
         return;
     }
     run_fixed(c, lay.R, k, in.kappa, x, *in.y, A, ds, fx, out);
@@ -444,7 +491,7 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
             Ct S = new_ct(c, cnt, ds, in.S->scale);
             fetch_snp(c, in, b0, cnt, *S, 0, c.stream);
             BatchOut o = run_batch(c, lay.R, k, fx, *S);
-            out.S_proj.push_back(std::move(o.sp));
+            if (c.keep_s_proj) out.S_proj.push_back(std::move(o.sp));
             out.num.push_back(std::move(o.num));
             out.den_even.push_back(std::move(o.de));
             out.den_odd.push_back(std::move(o.dodd));
@@ -476,7 +523,7 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
         GCK_HIP(hipStreamWaitEvent(c.stream, ev_cur, 0));
         BatchOut o = run_batch(c, lay.R, k, fx, *cur);
         (void)hipEventDestroy(ev_cur);
-        out.S_proj.push_back(std::move(o.sp));
+        if (c.keep_s_proj) out.S_proj.push_back(std::move(o.sp));
         out.num.push_back(std::move(o.num));
         out.den_even.push_back(std::move(o.de));
         out.den_odd.push_back(std::move(o.dodd));
@@ -609,14 +656,14 @@ void chunk_for_jobs(ckks_ctx &c, const std::vector<WorkItem> &items) {
         EncOutput &o = *items[i].out;
         const int nbq = items[i].in->S->count;
         if (o.num.empty()) {
-            o.S_proj.push_back(new_ct(c, nbq, bo.sp->depth, bo.sp->scale));
+            if (c.keep_s_proj) o.S_proj.push_back(new_ct(c, nbq, bo.sp->depth, bo.sp->scale));
             o.num.push_back(new_ct(c, nbq, bo.num->depth, bo.num->scale));
             o.den_even.push_back(new_ct(c, nbq, bo.de->depth, bo.de->scale));
             o.den_odd.push_back(new_ct(c, nbq, bo.dodd->depth, bo.dodd->scale));
             o.chunk = nbq;
         }
         const int b = items[i].batch;
-        copy_ct(c, *o.S_proj[0], b, *bo.sp, (int)i);
+        if (c.keep_s_proj) copy_ct(c, *o.S_proj[0], b, *bo.sp, (int)i);
         copy_ct(c, *o.num[0], b, *bo.num, (int)i);
         copy_ct(c, *o.den_even[0], b, *bo.de, (int)i);
         copy_ct(c, *o.den_odd[0], b, *bo.dodd, (int)i);
@@ -689,6 +736,30 @@ static std::vector<double> xtx_inverse(const double *X, int n, int k) {
     return A;
 }
 
+// f(0) .. f(n - 1) on up to 16 host threads (host-side encoding work of the client)
+template <typename F>
+static void parallel_for(int n, F f) {
+    const int T = std::max(1, std::min({n, 16, (int)std::thread::hardware_concurrency()}));
+    if (T <= 1) {
+        for (int i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    std::exception_ptr err;
+    std::mutex mu;
+    for (int t = 0; t < T; ++t)
+        th.emplace_back([&, t] {
+            try {
+                for (int i = t; i < n; i += T) f(i);
+            } catch (...) {
+                std::lock_guard<std::mutex> lk(mu);
+                if (!err) err = std::current_exception();
+            }
+        });
+    for (auto &x : th) x.join();
+    if (err) std::rethrow_exception(err);
+}
+
 static u64 input_seed(u64 enc_seed, u64 i) {
     auto mix = [](u64 z) {
         z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
@@ -733,20 +804,28 @@ std::unique_ptr<EncInput> pack_encrypt(ckks_ctx &c, const double *X, const doubl
     const int ds = snp_depth(kappa);
     in->S = new_ct(c, lay.n_batches, ds, c.p.scales[ds]);
     const size_t per = (size_t)2 * in->S->limbs * N;
-    for (int b = 0; b < lay.n_batches; ++b) {
-        std::fill(re.begin(), re.end(), 0.0);
-        std::fill(im.begin(), im.end(), 0.0);
-        for (int cb = 0; cb < lay.blocks; ++cb) {
-            int j0 = b * lay.tau + 2 * cb;
-            for (int r = 0; r < n; ++r) {
-                if (j0 < m) re[(size_t)cb * lay.R + r] = (double)S[(size_t)r * m + j0];
-                if (j0 + 1 < m) im[(size_t)cb * lay.R + r] = (double)S[(size_t)r * m + j0 + 1];
+    // the host encodings of up to 64 batches at a time in parallel, then their encryptions in order
+    const int group = 64;
+    std::vector<std::vector<i64>> polys(group, std::vector<i64>(N));
+    for (int b0 = 0; b0 < lay.n_batches; b0 += group) {
+        const int cnt = std::min(group, lay.n_batches - b0);
+        parallel_for(cnt, [&](int t) {
+            const int b = b0 + t;
+            std::vector<double> vr(slots, 0.0), vi(slots, 0.0);
+            for (int cb = 0; cb < lay.blocks; ++cb) {
+                const int j0 = b * lay.tau + 2 * cb;
+                for (int r = 0; r < n; ++r) {
+                    if (j0 < m) vr[(size_t)cb * lay.R + r] = (double)S[(size_t)r * m + j0];
+                    if (j0 + 1 < m) vi[(size_t)cb * lay.R + r] = (double)S[(size_t)r * m + j0 + 1];
+                }
             }
+            encode_poly(N, vr.data(), vi.data(), slots, c.p.scales[ds], polys[t].data());
+        });
+        for (int t = 0; t < cnt; ++t) {
+            Ct one = encrypt(c, polys[t].data(), ds, c.p.scales[ds], input_seed(enc_seed, idx++));
+            GCK_HIP(hipMemcpyAsync(in->S->data.ptr + (size_t)(b0 + t) * per, one->data.ptr, per * 8,
+                                   hipMemcpyDeviceToDevice, c.stream));
         }
-        encode_poly(N, re.data(), im.data(), slots, c.p.scales[ds], poly.data());
-        Ct one = encrypt(c, poly.data(), ds, c.p.scales[ds], input_seed(enc_seed, idx++));
-        GCK_HIP(hipMemcpyAsync(in->S->data.ptr + (size_t)b * per, one->data.ptr, per * 8, hipMemcpyDeviceToDevice,
-                               c.stream));
     }
     sync(c);
     return in;
@@ -799,4 +878,238 @@ Ct pack_normalisers(ckks_ctx &c, const uint8_t *S, int n, int m, int kappa, u64 
     return v;
 }
 
+// ---------------------------------------------------------------- HIP graph of one input shape
+
+static void same_shape(const EncInput &a, const EncInput &b) {
+    const Layout &x = a.lay, &y = b.lay;
+    if (x.n != y.n || x.k != y.k || x.m != y.m || x.R != y.R || a.kappa != b.kappa || !a.S || !b.S ||
+        a.S->count != b.S->count || a.S->depth != b.S->depth || a.S->scale != b.S->scale || !!a.S_rep != !!b.S_rep)
+        throw Error(CKKS_E_PARAM_MISMATCH, "input of another shape than the captured one");
+}
+
+static void copy_into(ckks_ctx &c, ckks_ct &dst, const ckks_ct &src) {
+    if (dst.count != src.count || dst.depth != src.depth || dst.scale != src.scale)
+        throw Error(CKKS_E_PARAM_MISMATCH, "input ciphertext of another shape, depth or scale");
+    GCK_HIP(hipMemcpyAsync(dst.data.ptr, src.data.ptr, src.data.words * 8, hipMemcpyDeviceToDevice, c.stream));
+}
+
+std::unique_ptr<gwas_graph> capture_circuit(ckks_ctx &c, const EncInput &in, int chunk) {
+    if (in.S_host) throw Error(CKKS_E_INVALID_ARG, "a spilled input cannot be captured");
+    if (c.pool->budget) throw Error(CKKS_E_INVALID_ARG, "graph capture needs a context without a pool budget");
+    if (c.timer.on) throw Error(CKKS_E_INVALID_ARG, "kernel timing is on");
+    if (!c.stream) throw Error(CKKS_E_INVALID_ARG, "graph capture needs a context on its own stream");
+    auto g = std::make_unique<gwas_graph>();
+    g->ctx = &c;
+    g->chunk = chunk;
+    g->slot = std::make_unique<EncInput>();
+    EncInput &sl = *g->slot;
+    sl.lay = in.lay;
+    sl.kappa = in.kappa;
+    for (auto &x : in.x) sl.x.push_back(clone(c, *x));
+    sl.y = clone(c, *in.y);
+    for (auto &a : in.A) sl.A.push_back(clone(c, *a));
+    sl.S = clone(c, *in.S);
+    if (in.Xrep) sl.Xrep = clone(c, *in.Xrep);
+    if (in.S_rep) sl.S_rep = clone(c, *in.S_rep);
+    {
+        // one call outside the capture: creates the second stream and its pool, fills the mask cache and
+        // leaves every block size the call takes in the pools' free lists
+        EncOutput warm;
+        run_circuit(c, sl, warm, chunk);
+    }
+    sync(c);
+    if (c.aux_stream) GCK_HIP(hipStreamSynchronize(c.aux_stream));
+    g->out = std::make_unique<gwas_enc_output>();
+    g->out->ctx = &c;
+    g->out->lay = sl.lay;
+    g->out->out.chunk = chunk;
+    c.pool->capture_begin();
+    if (c.aux_pool) c.aux_pool->capture_begin();
+    c.capturing = true;
+    GCK_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed));
+    try {
+        run_circuit(c, sl, g->out->out, chunk);
+    } catch (...) {
+        hipGraph_t dead = nullptr;
+        (void)hipStreamEndCapture(c.stream, &dead);
+        if (dead) (void)hipGraphDestroy(dead);
+        c.capturing = false;
+        g->main_blocks = c.pool->capture_end();
+        if (c.aux_pool) g->aux_blocks = c.aux_pool->capture_end();
+        throw;
+    }
+    c.capturing = false;
+    hipError_t e = hipStreamEndCapture(c.stream, &g->graph);
+    g->main_blocks = c.pool->capture_end();
+    if (c.aux_pool) g->aux_blocks = c.aux_pool->capture_end();
+    GCK_HIP(e);
+    GCK_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    return g;
+}
+
+void graph_set_input(gwas_graph &g, const EncInput &in) {
+    ckks_ctx &c = *g.ctx;
+    EncInput &sl = *g.slot;
+    same_shape(sl, in);
+    if (in.S_host) throw Error(CKKS_E_INVALID_ARG, "a spilled input cannot be replayed");
+    for (size_t j = 0; j < sl.x.size(); ++j) copy_into(c, *sl.x[j], *in.x[j]);
+    copy_into(c, *sl.y, *in.y);
+    for (size_t a = 0; a < sl.A.size(); ++a) copy_into(c, *sl.A[a], *in.A[a]);
+    copy_into(c, *sl.S, *in.S);
+    if (sl.Xrep) copy_into(c, *sl.Xrep, *in.Xrep);
+    if (sl.S_rep) copy_into(c, *sl.S_rep, *in.S_rep);
+}
+
+void graph_launch(gwas_graph &g) { GCK_HIP(hipGraphLaunch(g.exec, g.ctx->stream)); }
+
+// ---------------------------------------------------------------- autotuner
+
+std::tuple<int, int, int, int> schedule_key(const EncInput &in) {
+    return std::make_tuple(in.lay.R, in.lay.k, in.kappa, in.S->count);
+}
+
+// Times every candidate schedule on the job itself (HIP events on the context's stream around whole calls,
+// after one untimed call per candidate) and keeps the fastest for the job's shape.  Candidates: SNP-batch
+// chunks of all batches (at most 64), 32, 16 and 8, each on two streams and on one; every one computes
+// the same operations on the same ciphertexts, so the outputs are bit-identical (tested).
+TuneResult tune_circuit(ckks_ctx &c, const EncInput &in, int reps) {
+    if (c.timer.on) throw Error(CKKS_E_INVALID_ARG, "kernel timing is on");
+    const int nb = in.S->count;
+    std::vector<int> chunks;
+    for (int ch : {std::min(64, nb), 32, 16, 8})
+        if (ch >= 1 && ch <= nb && std::find(chunks.begin(), chunks.end(), ch) == chunks.end()) chunks.push_back(ch);
+    const int saved_streams = c.n_streams;
+    hipEvent_t e0, e1;
+    GCK_HIP(hipEventCreate(&e0));
+    GCK_HIP(hipEventCreate(&e1));
+    TuneResult res;
+    res.best.ms = 1e300;
+    try {
+        for (int streams : {2, 1})
+            for (int ch : chunks) {
+                c.n_streams = streams;
+                {
+                    EncOutput warm;
+                    run_circuit(c, in, warm, ch);
+                }
+                double best = 1e300;
+                for (int r = 0; r < std::max(1, reps); ++r) {
+                    EncOutput o;
+                    GCK_HIP(hipEventRecord(e0, c.stream));
+                    run_circuit(c, in, o, ch);
+                    GCK_HIP(hipEventRecord(e1, c.stream));
+                    GCK_HIP(hipEventSynchronize(e1));
+                    float ms = 0;
+                    GCK_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    best = std::min(best, (double)ms);
+                }
+                ++res.candidates;
+                if (streams == 2 && ch == chunks[0]) res.ms_default = best;
+                if (best < res.best.ms) res.best = ckks_ctx::Schedule{ch, streams, best};
+            }
+    } catch (...) {
+        c.n_streams = saved_streams;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    c.n_streams = saved_streams;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c.tuned[schedule_key(in)] = res.best;
+    return res;
+}
+
+int m_xrep_depth() { return 2; }
+int m_srep_depth(int kappa) { return snp_depth(kappa) + 2; }
+
+// Attach the REP inputs of the M-materialised layout: xrep as the client encrypts it (sample-major,
+// [i][j]), reordered to column-major [j][i]; srep batch-major [b][i].
+void attach_m(ckks_ctx &c, EncInput &in, Ct xrep_row_major, Ct srep) {
+    const Layout &lay = in.lay;
+    const int n = lay.n, k = lay.k;
+    if (xrep_row_major->count != n * k || xrep_row_major->depth != m_xrep_depth())
+        throw Error(CKKS_E_INVALID_ARG, "X^T in REP form: n k ciphertexts at depth 2");
+    if (srep->count != lay.n_batches * n || srep->depth != m_srep_depth(in.kappa))
+        throw Error(CKKS_E_INVALID_ARG, "REP SNP rows: n per SNP batch at the SNP depth + 2");
+    if (c.p.n < 2 * lay.R) throw Error(CKKS_E_INVALID_ARG, "ring too small");
+    Ct xr = new_ct(c, n * k, xrep_row_major->depth, xrep_row_major->scale);
+    for (int j = 0; j < k; ++j)
+        for (int i = 0; i < n; ++i) copy_ct(c, *xr, j * n + i, *xrep_row_major, i * k + j);
+    in.Xrep = std::move(xr);
+    in.S_rep = std::move(srep);
+}
+
+// Client side of the M-materialised layout: X_ij replicated over every slot (the exact constant encoding,
+// depth 2, scale Delta_2) and row i of every SNP batch with each entry over its block of R slots (two SNPs
+// per complex slot, depth snp_depth + 2); input ciphertext i of this part is encrypted with seed
+// output_{2^21 + i}(SplitMix64(enc_seed)), sample-major for X, batch-major for S.
+void pack_encrypt_m(ckks_ctx &c, EncInput &in, const double *X, const uint8_t *S, u64 enc_seed) {
+    const Layout &lay = in.lay;
+    const int N = c.p.n, slots = N / 2, n = lay.n, k = lay.k, m = lay.m;
+    const int dx = m_xrep_depth(), dsr = m_srep_depth(in.kappa);
+    if (c.p.levels < circuit_levels(in.kappa)) throw Error(CKKS_E_LEVEL, "chain too short for kappa");
+    Ct xr = new_ct(c, n * k, dx, c.p.scales[dx]);
+    Ct sr = new_ct(c, lay.n_batches * n, dsr, c.p.scales[dsr]);
+    std::vector<i64> poly(N);
+    u64 idx = 2ULL << 20;
+    const size_t per_x = (size_t)2 * xr->limbs * N, per_s = (size_t)2 * sr->limbs * N;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < k; ++j) {
+            std::fill(poly.begin(), poly.end(), 0);
+            poly[0] = round_half_away(X[(size_t)i * k + j] * c.p.scales[dx]);
+            Ct one = encrypt(c, poly.data(), dx, c.p.scales[dx], input_seed(enc_seed, idx++));
+            GCK_HIP(hipMemcpyAsync(xr->data.ptr + (size_t)(i * k + j) * per_x, one->data.ptr, per_x * 8,
+                                   hipMemcpyDeviceToDevice, c.stream));
+        }
+    // host encodings of up to 256 REP rows at a time in parallel, then their encryptions in order
+    const int total = lay.n_batches * n, group = 256;
+    std::vector<std::vector<i64>> polys(std::min(group, total), std::vector<i64>(N));
+    for (int q0 = 0; q0 < total; q0 += group) {
+        const int cnt = std::min(group, total - q0);
+        parallel_for(cnt, [&](int t) {
+            const int b = (q0 + t) / n, i = (q0 + t) % n;
+            std::vector<double> vre(slots, 0.0), vim(slots, 0.0);
+            for (int cb = 0; cb < lay.blocks; ++cb) {
+                const int j0 = b * lay.tau + 2 * cb;
+                const double vr = j0 < m ? (double)S[(size_t)i * m + j0] : 0.0;
+                const double vi = j0 + 1 < m ? (double)S[(size_t)i * m + j0 + 1] : 0.0;
+                for (int r = 0; r < lay.R; ++r) {
+                    vre[(size_t)cb * lay.R + r] = vr;
+                    vim[(size_t)cb * lay.R + r] = vi;
+                }
+            }
+            encode_poly(N, vre.data(), vim.data(), slots, c.p.scales[dsr], polys[t].data());
+        });
+        for (int t = 0; t < cnt; ++t) {
+            Ct one = encrypt(c, polys[t].data(), dsr, c.p.scales[dsr], input_seed(enc_seed, idx++));
+            GCK_HIP(hipMemcpyAsync(sr->data.ptr + (size_t)(q0 + t) * per_s, one->data.ptr, per_s * 8,
+                                   hipMemcpyDeviceToDevice, c.stream));
+        }
+    }
+    sync(c);
+    in.Xrep = std::move(xr);
+    Ct xr_col = new_ct(c, n * k, dx, c.p.scales[dx]);
+    for (int j = 0; j < k; ++j)
+        for (int i = 0; i < n; ++i) copy_ct(c, *xr_col, j * n + i, *in.Xrep, i * k + j);
+    in.Xrep = std::move(xr_col);
+    in.S_rep = std::move(sr);
+}
+
 }  // namespace gck
+
+gwas_graph::~gwas_graph() {
+    if (ctx) {
+        (void)hipStreamSynchronize(ctx->stream);
+        if (ctx->aux_stream) (void)hipStreamSynchronize(ctx->aux_stream);
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    out.reset();    // its blocks go back to the pools they came from
+    slot.reset();
+    if (ctx) {
+        // the reserved blocks came from the main pool or the second stream's pool (ensure_aux made it)
+        ctx->pool->give_back(main_blocks);
+        if (ctx->aux_pool) ctx->aux_pool->give_back(aux_blocks);
+    }
+}

@@ -32,6 +32,10 @@ struct EncInput {
     std::vector<Ct> A;   // k(k+1)/2, depth 0, scale R Delta_0
     Ct S;                // batched: n_batches ciphertexts at snp_depth(kappa) (data empty when spilled)
     u64 *S_host = nullptr;   // the SNP batches in pinned host memory after a spill
+    // M-materialised layout (set by attach_m): X^T in REP form, X_ij replicated, stored column-major
+    // ([j][i], n k ciphertexts at depth 2), and the REP rows of every SNP batch ([b][i], n_batches n
+    // ciphertexts at snp_depth + 2).  When present the circuit computes S' = M S by CP-REP-MatMult.
+    Ct Xrep, S_rep;
     ~EncInput() {
         if (S_host) (void)hipHostFree(S_host);
     }
@@ -48,6 +52,7 @@ struct EncOutput {
     // after run_divide, per chunk of cnt SNP batches: 2 cnt ciphertexts, the even SNPs' then the odd SNPs'
     // (b': real part of the even half, imaginary part of the odd half; err': real part)
     std::vector<Ct> div_b, div_inv;
+    Ct m_cols;   // M-materialised layout: Dup(M_i), i < n (depth 3)
     int chunk = 0;
 };
 
@@ -57,6 +62,7 @@ struct FixedOut {
     std::vector<Ct> x_c;   // x_j at the SNP depth + 2
     Ct u_s, w_s;           // u = w z' and w at the SNP depth + 3 (w_s empty when w is public: kappa = 1)
     std::vector<Ct> hold;  // batches that r_s and x_c may be views of
+    Ct m_cols;             // M-materialised layout: Dup(M_i), i < n, at the SNP depth + 2
 };
 struct BatchOut {
     Ct sp, num, de, dodd;
@@ -103,6 +109,13 @@ int div_levels();
 void run_divide(ckks_ctx &c, EncOutput &out, const ckks_ct &v);
 Ct pack_normalisers(ckks_ctx &c, const uint8_t *S, int n, int m, int kappa, u64 enc_seed);
 
+// M-materialised layout: depths of the REP inputs, their client-side packing, and S' of a chunk
+int m_xrep_depth();
+int m_srep_depth(int kappa);
+void attach_m(ckks_ctx &c, EncInput &in, Ct xrep_row_major, Ct srep);
+void pack_encrypt_m(ckks_ctx &c, EncInput &in, const double *X, const uint8_t *S, u64 enc_seed);
+Ct batch_front_m(ckks_ctx &c, const FixedOut &fx, const ckks_ct &S_rep_chunk);
+
 }  // namespace gck
 
 struct gwas_enc_input {
@@ -115,3 +128,30 @@ struct gwas_enc_output {
     gck::EncOutput out;
     gck::Layout lay;
 };
+
+// gwas_semiparallel of one input shape captured as a HIP graph: the captured call's input (a private
+// copy, refilled by set_input), its output (rewritten by every replay) and every pool block the call
+// used, reserved for the graph until it is destroyed.
+struct gwas_graph {
+    ckks_ctx *ctx = nullptr;
+    std::unique_ptr<gck::EncInput> slot;
+    std::unique_ptr<gwas_enc_output> out;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<std::pair<void *, size_t>> main_blocks, aux_blocks;
+    int chunk = 0;
+    ~gwas_graph();
+};
+namespace gck {
+std::unique_ptr<gwas_graph> capture_circuit(ckks_ctx &c, const EncInput &in, int chunk);
+// autotuner over schedules that leave every ciphertext bit-identical (chunk size, one or two streams)
+struct TuneResult {
+    ckks_ctx::Schedule best;
+    double ms_default = 0;
+    int candidates = 0;
+};
+TuneResult tune_circuit(ckks_ctx &c, const EncInput &in, int reps);
+std::tuple<int, int, int, int> schedule_key(const EncInput &in);
+void graph_set_input(gwas_graph &g, const EncInput &in);
+void graph_launch(gwas_graph &g);
+}  // namespace gck

@@ -231,6 +231,98 @@ void k_tensor(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int coun
     check_launch();
 }
 
+// CP-REP product sum of the M-materialised layout: for every batch b of the chunk,
+//   d_b = sum_{i < n} a_i (x) b_{b, i}   (tensor: d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1, mod q)
+// with a = the n duplicated columns of M ([n][2][l][N]) and b the REP rows ([cnt][n][2][l][N]); out is
+// [cnt][3][l][N].  A thread owns one word of one limb for kRepCB batches, so each column word is read once
+// per kRepCB batches; the sums are kept reduced (one modular addition per product).
+constexpr int kRepCB = 4;
+__global__ void ew_tensor_rep_sum(u64 *out, const u64 *a, const u64 *b, int cnt, int n_rows, int l, int log_n,
+                                  const ModInfo *mods) {
+    const size_t nw = (size_t)1 << log_n;
+    const int groups = (cnt + kRepCB - 1) / kRepCB;
+    const size_t total = (size_t)groups * l * nw;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        const size_t k = idx & (nw - 1);
+        const int lam = (int)((idx >> log_n) % l);
+        const int g0 = (int)((idx >> log_n) / l) * kRepCB;
+        const ModInfo &M = mods[lam];
+        u64 d0[kRepCB], d1[kRepCB], d2[kRepCB];
+        for (int c = 0; c < kRepCB; ++c) d0[c] = d1[c] = d2[c] = 0;
+        const size_t per = (size_t)2 * l * nw;
+        for (int i = 0; i < n_rows; ++i) {
+            const u64 *pa = a + (size_t)i * per;
+            const u64 a0 = pa[(size_t)lam * nw + k], a1 = pa[(size_t)(l + lam) * nw + k];
+            for (int c = 0; c < kRepCB; ++c) {
+                if (g0 + c >= cnt) break;
+                const u64 *pb = b + ((size_t)(g0 + c) * n_rows + i) * per;
+                const u64 b0 = pb[(size_t)lam * nw + k], b1 = pb[(size_t)(l + lam) * nw + k];
+                d0[c] = add_mod(d0[c], mul_mod(a0, b0, M), M.q);
+                u64 lo1 = a0 * b1, hi1 = __umul64hi(a0, b1);
+                u64 lo2 = a1 * b0, hi2 = __umul64hi(a1, b0);
+                u64 lo = lo1 + lo2, hi = hi1 + hi2 + (lo < lo1 ? 1 : 0);
+                if (hi >= M.q) hi -= M.q;
+                d1[c] = add_mod(d1[c], mul_shoup(redc(hi, lo, M), M.r_mod, M.r_mod_sh, M.q), M.q);
+                d2[c] = add_mod(d2[c], mul_mod(a1, b1, M), M.q);
+            }
+        }
+        for (int c = 0; c < kRepCB; ++c) {
+            if (g0 + c >= cnt) break;
+            u64 *po = out + (size_t)(g0 + c) * 3 * l * nw;
+            po[(size_t)lam * nw + k] = d0[c];
+            po[(size_t)(l + lam) * nw + k] = d1[c];
+            po[(size_t)(2 * l + lam) * nw + k] = d2[c];
+        }
+    }
+}
+void k_tensor_rep_sum(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int cnt, int n_rows, int l,
+                      hipStream_t st) {
+    // algorithmic bytes: the columns once per kRepCB batches, the REP rows once, the tensor written once
+    const double groups = (double)((cnt + kRepCB - 1) / kRepCB);
+    TScope ts_(t, "ew_tensor_rep_sum",
+               8.0 * (double)t.n * l * (groups * 2.0 * n_rows + (double)cnt * (2.0 * n_rows + 3.0)), st);
+    const size_t total = (size_t)((cnt + kRepCB - 1) / kRepCB) * l << t.log_n;
+    if (!total) return;
+    gck_launch(ew_tensor_rep_sum, ew_grid(total), dim3(kEwThreads), 0, st, out, a, b, cnt, n_rows, l, t.log_n, t.mods);
+    check_launch();
+}
+
+// c0 of ciphertext i of the batch plus the plaintext pt ([l][N], NTT form) moved by the automorphism of a
+// right rotation by i mod R (Galois element 5^-i mod 2N): pt the block-start mask, this adds the exact
+// indicator of the slots = i mod R (the identity column i of M, duplicated).  c1 is copied.
+__global__ void ew_add_rotated_plain(u64 *out, const u64 *a, const u64 *pt, int count, int l, int log_n, int R,
+                                     const ModInfo *mods) {
+    const size_t nw = (size_t)1 << log_n;
+    const size_t total = (size_t)count * 2 * l * nw;
+    const unsigned two_n = 2u << log_n, half = 1u << (log_n - 1);
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        const size_t row = idx >> log_n;          // over count * 2 * l
+        const int ci = (int)(row / (2 * l)), pl = (int)(row % (2 * l));
+        u64 v = a[idx];
+        if (pl < l) {
+            // 5^e mod 2N with e = -(i mod R) mod N/2 (5 has order N/2 modulo 2N)
+            unsigned e = (half - (unsigned)(ci % R)) % half, g = 1, base = 5;
+            while (e) {
+                if (e & 1) g = (unsigned)(((unsigned long long)g * base) % two_n);
+                base = (unsigned)(((unsigned long long)base * base) % two_n);
+                e >>= 1;
+            }
+            const u64 w = pt[(size_t)pl * nw + automorph_src(idx & (nw - 1), log_n, g)];
+            v = add_mod(v, w, mods[pl].q);
+        }
+        out[idx] = v;
+    }
+}
+void k_add_rotated_plain(const DevTables &t, u64 *out, const u64 *a, const u64 *pt, int count, int l, int R,
+                         hipStream_t st) {
+    TScope ts_(t, "ew_add_rotated_plain", 8.0 * (double)t.n * (4.0 * count * l + l), st);
+    const size_t total = (size_t)count * 2 * l << t.log_n;
+    if (!total) return;
+    gck_launch(ew_add_rotated_plain, ew_grid(total), dim3(kEwThreads), 0, st, out, a, pt, count, l, t.log_n, R,
+               t.mods);
+    check_launch();
+}
+
 __global__ void ew_automorph(u64 *out, const u64 *a, size_t total, int log_n, u64 g) {
     const size_t n = (size_t)1 << log_n;
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {

@@ -19,7 +19,7 @@ namespace gck {
 
 size_t input_footprint(const ckks_ctx &c, const EncInput &in) {
     auto bytes = [](const Ct &p) { return p ? p->data.words * 8 : 0; };
-    size_t b = bytes(in.y) + bytes(in.S);
+    size_t b = bytes(in.y) + bytes(in.S) + bytes(in.Xrep) + bytes(in.S_rep);
     for (auto &p : in.x) b += bytes(p);
     for (auto &p : in.A) b += bytes(p);
     // outputs, the fixed-part values kept for the per-batch part, and working space of the fixed part
