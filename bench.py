@@ -216,6 +216,58 @@ def forms_leg(args):
     return batched, serving
 
 
+def config5_leg(args):
+    """The serving configuration: seeded Poisson arrivals (4 jobs/s) of jobs drawn from the batched
+    configuration's size distribution, the continuous-batching server (admission by HBM footprint, keys
+    resident, jobs that arrive while others run share launches) against the one-job-at-a-time FIFO
+    server on the same trace.  Two regimes: (a) 256 jobs with m scaled by 0.25, so that every job can be
+    encrypted before the run (inputs resident) and the server is not saturated; (b) 64 jobs at full m,
+    where one job at a time serves about 2.6 jobs/s, below the arrival rate, so the FIFO queue diverges
+    for as long as arrivals last."""
+    import torch
+
+    import paper_1902_04303_amd as P
+    from synth import job_mix, make_gwas_data, poisson_arrivals
+
+    torch.cuda.empty_cache()
+    L = 7 * KAPPA + 5
+    ctx = P.Context(LOG_N, L, LOG_SCALE, alpha=args.ks_alpha)
+    ctx.keygen(7, galois_set(2048))
+    ctx.keep_projected(False)
+    out = {}
+    for label, count, m_scale in (("m_scale_0.25", args.config5_jobs, 0.25), ("full_m", 64, 1.0)):
+        jobs = job_mix(count, 501, m_scale)
+        arrivals = poisson_arrivals(count, 4.0, 502)
+        data = [make_gwas_data(n, k, m, seed=ds) for n, k, m, ds in jobs]
+        leg = {"jobs": count, "m_scale": m_scale, "arrival_rate_per_s": 4.0,
+               "snps": int(sum(m for _, _, m, _ in jobs)), "arrivals_end_s": round(float(arrivals[-1]), 2)}
+        for name, max_jobs in (("continuous", 64), ("fifo_one_at_a_time", 1)):
+            ins = [ctx.gwas_pack_encrypt(dd.X, dd.y, dd.S, KAPPA, ds) for dd, (_, _, _, ds) in zip(data, jobs)]
+            torch.cuda.synchronize()
+            srv = ctx.gwas_server(hbm_budget=0, max_jobs=max_jobs, chunk=64)
+            t0 = time.perf_counter()
+            ids = []
+            for a, i in zip(arrivals, ins):
+                while time.perf_counter() - t0 < a:
+                    time.sleep(0.0005)
+                ids.append(srv.submit(i))
+            del ins
+            for q, (jid, (_, _, m, _)) in enumerate(zip(ids, jobs)):
+                srv.poll(jid, m, wait=True)
+                if q % 32 == 31:
+                    log("[bench] config 5 %s %s: %d jobs done, %.1f s" % (label, name, q + 1, time.perf_counter() - t0))
+            st = srv.stats()
+            srv.close()
+            ctx.pool_trim()
+            torch.cuda.empty_cache()
+            leg[name] = {k: (round(v, 2) if isinstance(v, float) else v) for k, v in st.items()}
+            log("[bench] config 5 %s %s: %.2f jobs/s, p50 %.0f ms, p99 %.0f ms, peak %d in flight" %
+                (label, name, st["jobs_per_s"], st["p50_ms"], st["p99_ms"], st.get("peak_jobs_in_flight", -1)))
+        out[label] = leg
+    ctx.close()
+    return out
+
+
 def m_layout_leg(args):
     """The M-materialised layout at the same workload (Alg. CP-REP-MatMult: M as n duplicated columns, each
     SNP batch in REP form, S' = sum_i Dup(M_i) S_rep(i) by one lazy tensor sum per batch instead of the
@@ -277,9 +329,11 @@ def config3_leg(args):
     jobs = job_mix(args.config3_jobs, 301, 1.0)
     t0 = time.time()
     ins = []
-    for n, k, m, seed in jobs:
+    for i, (n, k, m, seed) in enumerate(jobs):
         d = make_gwas_data(n, k, m, seed=seed)
         ins.append(ctx.gwas_pack_encrypt(d.X, d.y, d.S, KAPPA, 11))
+        if i % 8 == 7:
+            log("[bench] config 3: %d jobs encrypted" % (i + 1))
     torch.cuda.synchronize()
     enc_s = time.time() - t0
     snps = sum(m for _, _, m, _ in jobs)
@@ -293,9 +347,14 @@ def config3_leg(args):
         if i in sample:
             keep[i] = ctx.export(o.ct(P.GwasOutput.NUM, 0), 0)
         del o
+        if i % 8 == 7:
+            torch.cuda.synchronize()
+            log("[bench] config 3 plain: %d jobs done, %.1f s" % (i + 1, time.perf_counter() - t0))
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
     log("[bench] config 3 plain: %.1f s (%.2f jobs/s)" % (plain_s, len(jobs) / plain_s))
+    ctx.pool_trim()   # the plain path's cached blocks (every job shape its own sizes) back to the allocator
+    torch.cuda.empty_cache()
     t0 = time.perf_counter()
     outs = ctx.gwas_semiparallel_multi(ins, 64)
     torch.cuda.synchronize()
@@ -305,7 +364,9 @@ def config3_leg(args):
         (batched_s, len(jobs) / batched_s, plain_s / batched_s, same))
     st = ctx.pool_stats()
     del outs
+    del ins
     ctx.close()
+    torch.cuda.empty_cache()
     return {"jobs": len(jobs), "snps": snps, "snp_batches": batches, "m_scale": 1.0,
             "client_encrypt_s": round(enc_s, 1), "plain_s": round(plain_s, 2), "batched_s": round(batched_s, 2),
             "plain_jobs_per_s": round(len(jobs) / plain_s, 3), "batched_jobs_per_s": round(len(jobs) / batched_s, 3),
@@ -657,6 +718,7 @@ def run(args) -> int:
     mlay = m_layout_leg(args) if args.m_layout else None
     c3 = config3_leg(args) if args.config3_jobs > 0 else None
     c4 = config4_leg(args) if args.config4 else None
+    c5 = config5_leg(args) if args.config5_jobs > 0 else None
     ks = keyswitch_roofline(g["keyswitch"], args.steps)
     ntt = ntt_aggregate(g["warm_kernels"], g["counters"]["limb_ntts"])
     line = {
@@ -686,6 +748,7 @@ def run(args) -> int:
         "m_layout": mlay,
         "config3_batched_full": c3,
         "config4_large_job": c4,
+        "config5_serving": c5,
         "per_step": g["counters"],
         "ms_per_step_one_stream": round(g["ms_one_stream"], 3),
         "finalize_ms": round(g["finalize_ms"], 1),
@@ -709,6 +772,9 @@ def main():
     ap.add_argument("--config3-jobs", type=int, default=0,
                     help="run the batched configuration at full size with this many jobs (64: the configuration)")
     ap.add_argument("--config4", action="store_true", help="run the large single job (n=2000, k=6, m=100000)")
+    ap.add_argument("--config5-jobs", type=int, default=0,
+                    help="run the serving configuration with this many jobs at m x 0.25 (256: the configuration), "
+                         "then 64 jobs at full m")
     ap.add_argument("--config4-budget-gb", type=int, default=48, help="pool budget of the spilled config-4 leg")
     ap.add_argument("--no-kappa-sweep", dest="kappa_sweep", action="store_false",
                     help="skip the kappa = 1, 2, 3 sweep (and the division run)")

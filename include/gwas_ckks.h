@@ -272,7 +272,7 @@ int gwas_semiparallel_chunked(ckks_ctx *ctx, const gwas_enc_input *in, int chunk
  * index = chunk number, each a batch of up to `chunk` ciphertexts in SNP-batch order;
  * 4 beta_j (index j), 5 w, 6 w^-1 (CKKS_E_INVALID_ARG for kappa = 1, where both are public), 7 z',
  * 8 u = w z', 9 b' and 10 err' after gwas_divide, 11 the n columns Dup(M_i) of the M-materialised layout
- * (depth 3).  The handle stays owned by out. */
+ * (at the SNP depth + 2).  The handle stays owned by out. */
 int gwas_output_ct(const gwas_enc_output *out, int which, int index, const ckks_ct **ct);
 
 /* ---- Autotuner.  gwas_tune times every candidate schedule of the circuit on `in` itself (SNP-batch chunks
@@ -318,11 +318,12 @@ void gwas_graph_destroy(gwas_graph *g);
  * with these REP parts attached runs the per-SNP-batch projection as
  *   S'_b = sum_{i < n} Dup(M_i) (.) S_rep(b, i)      (one lazy tensor sum, one relinearisation)
  * where Dup(M_i) = Dup(e_i) - sum_j r_j X_ij is column i of M duplicated over the ciphertext (r_j the
- * columns of X A, X_ij from the REP X^T, Dup(e_i) the exact indicator of the slots = i mod R), instead of
+ * columns of X A brought to the REP X^T's depth, X_ij from the REP X^T, Dup(e_i) the exact indicator of the
+ * slots = i mod R; the columns come out at the REP rows' depth), instead of
  * the rotation-based factorised projection; everything after S' is unchanged, and S' lands at the same
  * depth and scale.  One job at a time (gwas_semiparallel); n REP rows per SNP batch. */
-/* Attach REP inputs made elsewhere: xrep[n k] sample-major (X_ij replicated over every slot, depth 2,
- * scale Delta_2), srep[n_batches n] batch-major (row i of batch b, each complex-packed entry
+/* Attach REP inputs made elsewhere: xrep[n k] sample-major (X_ij replicated over every slot, at the SNP
+ * depth + 1 = 7 kappa + 1, or 5 for kappa = 1, and that depth's scale), srep[n_batches n] batch-major (row i of batch b, each complex-packed entry
  * S[i, b tau + 2c] + i S[i, b tau + 2c + 1] over its block of R slots, depth snp_depth + 2 = 7 kappa + 2,
  * or 6 for kappa = 1, scale Delta of that depth).  Handles are copied. */
 int gwas_input_attach_m(ckks_ctx *ctx, gwas_enc_input *in, const ckks_ct *const *xrep, int n_xrep,

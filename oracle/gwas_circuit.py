@@ -351,9 +351,11 @@ class Circuit:
         replicated over every slot); the identity column is the exact indicator of the slots = i mod R."""
         o = self.o
         k = self.lay.k
+        dx = m_in.Xrep[0][0].depth
+        rx = [self.at(r, dx) for r in rr]          # r_j brought to the REP X^T's depth once
         out = []
         for i in range(self.lay.n):
-            g = o.mul_sum([(rr[j], m_in.Xrep[i][j]) for j in range(k)])
+            g = o.mul_sum([(rx[j], m_in.Xrep[i][j]) for j in range(k)])
             e = C.slot_class_indicator_poly(self.lay.N, self.lay.R, i, g.scale)
             out.append(o.add_plain(o.neg(g), e))
         return out
@@ -460,9 +462,10 @@ class Circuit:
         return self._batches(inp, fixed, beta, w, w_inv, z_proj, u)
 
 
-# ---- the M-materialised layout's client inputs: X^T in REP form (X_ij in every slot, depth 2, the depth of
-#      r_j) and every SNP batch in REP form (row i of the batch, each entry over its block of R slots, two
-#      SNPs per complex slot, depth snp_depth + 2, so that S' lands at the depth of the CCP layout's S')
+# ---- the M-materialised layout's client inputs: X^T in REP form (X_ij in every slot, depth snp_depth + 1,
+#      so that the columns of M land at the REP rows' depth with few limbs) and every SNP batch in REP form
+#      (row i of the batch, each entry over its block of R slots, two SNPs per complex slot, depth
+#      snp_depth + 2, so that S' lands at the depth of the CCP layout's S')
 M_SEED_BASE = 2 << 20    # encryption seeds: input_seed(enc_seed, base + i)
 
 
@@ -473,7 +476,7 @@ class MInput:
 
 
 def m_depths(kappa: int):
-    return 2, snp_depth(kappa) + 2
+    return snp_depth(kappa) + 1, snp_depth(kappa) + 2
 
 
 def snp_rep_slots(S: np.ndarray, lay: Layout, b: int, i: int) -> np.ndarray:

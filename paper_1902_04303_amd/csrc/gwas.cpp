@@ -229,17 +229,20 @@ void fixed_front(ckks_ctx &c, int R, int k, const std::vector<const ckks_ct *> &
         // Dup(M_i) = Dup(e_i) - sum_j r_j X_ij for every sample i, as one batch of n
         if (J != 1) throw Error(CKKS_E_INVALID_ARG, "the M-materialised layout runs one job at a time");
         const int n = xrep->count / k;
+        Ct RRx = st.C.at(*RR, xrep->depth);   // r_j at the REP X^T's depth (SNP depth + 1), all j at once
         std::vector<Ct> rj(k), xj(k);
         std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pr;
         for (int j = 0; j < k; ++j) {
-            rj[j] = view(*RR, j, 1);
+            rj[j] = view(*RRx, j, 1);
             xj[j] = view(*xrep, j * n, n);
             pr.push_back({rj[j].get(), xj[j].get()});
         }
-        Ct G = mul_sum(c, pr);
+        Ct G = mul_sum(c, pr);   // at the REP rows' depth, SNP depth + 2
         Ct D = add_slot_indicators(c, *neg(c, *G), R);
-        fx.m_cols = st.C.at(*D, ds + 2);
-        if (rep) rep->m_cols = std::move(D);
+        if (D->depth != ds + 2) throw Error(CKKS_E_LEVEL, "REP X^T at the wrong depth");
+        fx.m_cols = view(*D, 0, D->count);
+        fx.hold.push_back(std::move(D));
+        if (rep) rep->m_cols = clone(c, *fx.m_cols);
     }
     Ct RRs = st.C.at(*RR, ds);
     // x_j at ds + 2 owned here (the stacked x may be the caller's, shared with the other part)
@@ -682,13 +685,44 @@ void run_multi(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std::vect
         const std::vector<int> &ids = kv.second;
         std::vector<const EncInput *> bj;
         for (int id : ids) bj.push_back(jobs[id]);
+        // fixed parts in groups of at most kMaxFixedJobs jobs: each group's launches still cover
+        // k kMaxFixedJobs ciphertexts, and the transient key-switch buffers of the 27-limb fixed part
+        // (about 0.5 GB per job) stay bounded however many jobs share the shape
         std::vector<FixedOut> fxs;
-        std::vector<EncOutput> reps;
-        fixed_for_jobs(c, bj, fxs, reps);
-        for (size_t q = 0; q < ids.size(); ++q) outs[ids[q]] = std::move(reps[q]);
+        for (size_t g0 = 0; g0 < bj.size(); g0 += kMaxFixedJobs) {
+            const size_t g1 = std::min(bj.size(), g0 + kMaxFixedJobs);
+            std::vector<const EncInput *> grp(bj.begin() + g0, bj.begin() + g1);
+            std::vector<FixedOut> f;
+            std::vector<EncOutput> reps;
+            fixed_for_jobs(c, grp, f, reps);
+            for (size_t q = 0; q < grp.size(); ++q) {
+                outs[ids[g0 + q]] = std::move(reps[q]);
+                fxs.push_back(std::move(f[q]));
+            }
+        }
+        // a job with at least half a chunk of SNP batches runs them in chunks of its own (its fixed-part
+        // values read cyclically by every batch, outputs written in place: no per-batch gathers or copies);
+        // the batches of smaller jobs share chunks across jobs
         std::vector<WorkItem> work;
-        for (size_t q = 0; q < ids.size(); ++q)
-            for (int b = 0; b < bj[q]->S->count; ++b) work.push_back(WorkItem{bj[q], &fxs[q], &outs[ids[q]], b});
+        for (size_t q = 0; q < ids.size(); ++q) {
+            const EncInput &in = *bj[q];
+            const int nbq = in.S->count;
+            if (2 * nbq >= chunk && !in.S_host) {
+                EncOutput &o = outs[ids[q]];
+                o.chunk = chunk;
+                for (int b0 = 0; b0 < nbq; b0 += chunk) {
+                    const int cnt = std::min(chunk, nbq - b0);
+                    Ct S = view(*in.S, b0, cnt);
+                    BatchOut bo = run_batch(c, in.lay.R, in.lay.k, fxs[q], *S);
+                    if (c.keep_s_proj) o.S_proj.push_back(std::move(bo.sp));
+                    o.num.push_back(std::move(bo.num));
+                    o.den_even.push_back(std::move(bo.de));
+                    o.den_odd.push_back(std::move(bo.dodd));
+                }
+                continue;
+            }
+            for (int b = 0; b < nbq; ++b) work.push_back(WorkItem{bj[q], &fxs[q], &outs[ids[q]], b});
+        }
         for (size_t w0 = 0; w0 < work.size(); w0 += chunk) {
             const size_t cnt = std::min((size_t)chunk, work.size() - w0);
             chunk_for_jobs(c, std::vector<WorkItem>(work.begin() + w0, work.begin() + w0 + cnt));
@@ -1020,7 +1054,7 @@ TuneResult tune_circuit(ckks_ctx &c, const EncInput &in, int reps) {
     return res;
 }
 
-int m_xrep_depth() { return 2; }
+int m_xrep_depth(int kappa) { return snp_depth(kappa) + 1; }
 int m_srep_depth(int kappa) { return snp_depth(kappa) + 2; }
 
 // Attach the REP inputs of the M-materialised layout: xrep as the client encrypts it (sample-major,
@@ -1028,8 +1062,8 @@ int m_srep_depth(int kappa) { return snp_depth(kappa) + 2; }
 void attach_m(ckks_ctx &c, EncInput &in, Ct xrep_row_major, Ct srep) {
     const Layout &lay = in.lay;
     const int n = lay.n, k = lay.k;
-    if (xrep_row_major->count != n * k || xrep_row_major->depth != m_xrep_depth())
-        throw Error(CKKS_E_INVALID_ARG, "X^T in REP form: n k ciphertexts at depth 2");
+    if (xrep_row_major->count != n * k || xrep_row_major->depth != m_xrep_depth(in.kappa))
+        throw Error(CKKS_E_INVALID_ARG, "X^T in REP form: n k ciphertexts at the SNP depth + 1");
     if (srep->count != lay.n_batches * n || srep->depth != m_srep_depth(in.kappa))
         throw Error(CKKS_E_INVALID_ARG, "REP SNP rows: n per SNP batch at the SNP depth + 2");
     if (c.p.n < 2 * lay.R) throw Error(CKKS_E_INVALID_ARG, "ring too small");
@@ -1041,13 +1075,13 @@ void attach_m(ckks_ctx &c, EncInput &in, Ct xrep_row_major, Ct srep) {
 }
 
 // Client side of the M-materialised layout: X_ij replicated over every slot (the exact constant encoding,
-// depth 2, scale Delta_2) and row i of every SNP batch with each entry over its block of R slots (two SNPs
+// at the SNP depth + 1 and its canonical scale) and row i of every SNP batch with each entry over its block of R slots (two SNPs
 // per complex slot, depth snp_depth + 2); input ciphertext i of this part is encrypted with seed
 // output_{2^21 + i}(SplitMix64(enc_seed)), sample-major for X, batch-major for S.
 void pack_encrypt_m(ckks_ctx &c, EncInput &in, const double *X, const uint8_t *S, u64 enc_seed) {
     const Layout &lay = in.lay;
     const int N = c.p.n, slots = N / 2, n = lay.n, k = lay.k, m = lay.m;
-    const int dx = m_xrep_depth(), dsr = m_srep_depth(in.kappa);
+    const int dx = m_xrep_depth(in.kappa), dsr = m_srep_depth(in.kappa);
     if (c.p.levels < circuit_levels(in.kappa)) throw Error(CKKS_E_LEVEL, "chain too short for kappa");
     Ct xr = new_ct(c, n * k, dx, c.p.scales[dx]);
     Ct sr = new_ct(c, lay.n_batches * n, dsr, c.p.scales[dsr]);

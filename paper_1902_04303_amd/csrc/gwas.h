@@ -33,7 +33,7 @@ struct EncInput {
     Ct S;                // batched: n_batches ciphertexts at snp_depth(kappa) (data empty when spilled)
     u64 *S_host = nullptr;   // the SNP batches in pinned host memory after a spill
     // M-materialised layout (set by attach_m): X^T in REP form, X_ij replicated, stored column-major
-    // ([j][i], n k ciphertexts at depth 2), and the REP rows of every SNP batch ([b][i], n_batches n
+    // ([j][i], n k ciphertexts at snp_depth + 1), and the REP rows of every SNP batch ([b][i], n_batches n
     // ciphertexts at snp_depth + 2).  When present the circuit computes S' = M S by CP-REP-MatMult.
     Ct Xrep, S_rep;
     ~EncInput() {
@@ -52,7 +52,7 @@ struct EncOutput {
     // after run_divide, per chunk of cnt SNP batches: 2 cnt ciphertexts, the even SNPs' then the odd SNPs'
     // (b': real part of the even half, imaginary part of the odd half; err': real part)
     std::vector<Ct> div_b, div_inv;
-    Ct m_cols;   // M-materialised layout: Dup(M_i), i < n (depth 3)
+    Ct m_cols;   // M-materialised layout: Dup(M_i), i < n (at the SNP depth + 2)
     int chunk = 0;
 };
 
@@ -87,6 +87,7 @@ void run_fixed(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckk
 BatchOut run_batch(ckks_ctx &c, int R, int k, const FixedOut &fx, const ckks_ct &S);
 void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk);
 void run_multi(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std::vector<EncOutput> &outs, int chunk);
+constexpr size_t kMaxFixedJobs = 8;   // jobs whose fixed parts run as one batch in run_multi
 // building blocks shared with the server
 struct WorkItem {
     const EncInput *in;
@@ -110,7 +111,7 @@ void run_divide(ckks_ctx &c, EncOutput &out, const ckks_ct &v);
 Ct pack_normalisers(ckks_ctx &c, const uint8_t *S, int n, int m, int kappa, u64 enc_seed);
 
 // M-materialised layout: depths of the REP inputs, their client-side packing, and S' of a chunk
-int m_xrep_depth();
+int m_xrep_depth(int kappa);
 int m_srep_depth(int kappa);
 void attach_m(ckks_ctx &c, EncInput &in, Ct xrep_row_major, Ct srep);
 void pack_encrypt_m(ckks_ctx &c, EncInput &in, const double *X, const uint8_t *S, u64 enc_seed);
