@@ -277,6 +277,19 @@ Ct wrap(Ct r) { return r; }
 
 ckks_ct *release(Ct r) { return r.release(); }
 
+// Freeing returns device buffers to the context's pool, which a server's worker thread may be using: hold
+// the context's lock (the pools' free lists are not thread-safe on their own).
+template <typename T>
+void free_locked(ckks_ctx *c, T *p) {
+    if (!p) return;
+    if (!c) {
+        delete p;
+        return;
+    }
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    delete p;
+}
+
 void check_ct(const ckks_ctx *ctx, const ckks_ct *a) {
     need(ctx && a, "null handle");
     if (a->ctx != ctx) throw Error(CKKS_E_PARAM_MISMATCH, "ciphertext belongs to another context");
@@ -552,7 +565,7 @@ int ckks_ct_import(ckks_ctx *ctx, const uint64_t *buf, int depth, double scale, 
     });
 }
 
-void ckks_ct_free(ckks_ct *ct) { delete ct; }
+void ckks_ct_free(ckks_ct *ct) { free_locked(ct ? ct->ctx : nullptr, ct); }
 
 #define CT_UNARY(name, expr)                                   \
     int name(ckks_ctx *ctx, const ckks_ct *a, ckks_ct **out) { \
@@ -740,7 +753,7 @@ int gwas_input_from_cts(ckks_ctx *ctx, int n, int k, int m, int kappa, ckks_ct *
     });
 }
 
-void gwas_input_free(gwas_enc_input *in) { delete in; }
+void gwas_input_free(gwas_enc_input *in) { free_locked(in ? in->ctx : nullptr, in); }
 
 int gwas_input_ct(const gwas_enc_input *in, int which, int index, const ckks_ct **ct) {
     return guard([&] {
@@ -911,7 +924,7 @@ int gwas_output_ct(const gwas_enc_output *out, int which, int index, const ckks_
     });
 }
 
-void gwas_output_free(gwas_enc_output *out) { delete out; }
+void gwas_output_free(gwas_enc_output *out) { free_locked(out ? out->ctx : nullptr, out); }
 
 int gwas_graph_create(ckks_ctx *ctx, const gwas_enc_input *in, int chunk, gwas_graph **out) {
     return guard_ctx(ctx, [&] {

@@ -679,8 +679,19 @@ void chunk_for_jobs(ckks_ctx &c, const std::vector<WorkItem> &items) {
 void run_multi(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std::vector<EncOutput> &outs, int chunk) {
     outs.clear();
     outs.resize(jobs.size());
+    // A job with at least half a chunk of SNP batches fills the device with its own launches: it runs as a
+    // single job (its logistic-regression part on the second stream, beside its own SNP batches).  The
+    // smaller jobs are bucketed by shape and share the fixed-part launches and the SNP-batch chunks (an
+    // input with the M-materialised layout always runs as a single job).
     std::map<std::tuple<int, int, int>, std::vector<int>> buckets;
-    for (size_t i = 0; i < jobs.size(); ++i) buckets[bucket_of(*jobs[i])].push_back((int)i);
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        if (2 * jobs[i]->S->count >= chunk || jobs[i]->S_rep) {
+            outs[i].chunk = chunk;
+            run_circuit(c, *jobs[i], outs[i], chunk);
+            continue;
+        }
+        buckets[bucket_of(*jobs[i])].push_back((int)i);
+    }
     for (auto &kv : buckets) {
         const std::vector<int> &ids = kv.second;
         std::vector<const EncInput *> bj;
@@ -700,29 +711,9 @@ void run_multi(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std::vect
                 fxs.push_back(std::move(f[q]));
             }
         }
-        // a job with at least half a chunk of SNP batches runs them in chunks of its own (its fixed-part
-        // values read cyclically by every batch, outputs written in place: no per-batch gathers or copies);
-        // the batches of smaller jobs share chunks across jobs
         std::vector<WorkItem> work;
-        for (size_t q = 0; q < ids.size(); ++q) {
-            const EncInput &in = *bj[q];
-            const int nbq = in.S->count;
-            if (2 * nbq >= chunk && !in.S_host) {
-                EncOutput &o = outs[ids[q]];
-                o.chunk = chunk;
-                for (int b0 = 0; b0 < nbq; b0 += chunk) {
-                    const int cnt = std::min(chunk, nbq - b0);
-                    Ct S = view(*in.S, b0, cnt);
-                    BatchOut bo = run_batch(c, in.lay.R, in.lay.k, fxs[q], *S);
-                    if (c.keep_s_proj) o.S_proj.push_back(std::move(bo.sp));
-                    o.num.push_back(std::move(bo.num));
-                    o.den_even.push_back(std::move(bo.de));
-                    o.den_odd.push_back(std::move(bo.dodd));
-                }
-                continue;
-            }
-            for (int b = 0; b < nbq; ++b) work.push_back(WorkItem{bj[q], &fxs[q], &outs[ids[q]], b});
-        }
+        for (size_t q = 0; q < ids.size(); ++q)
+            for (int b = 0; b < bj[q]->S->count; ++b) work.push_back(WorkItem{bj[q], &fxs[q], &outs[ids[q]], b});
         for (size_t w0 = 0; w0 < work.size(); w0 += chunk) {
             const size_t cnt = std::min((size_t)chunk, work.size() - w0);
             chunk_for_jobs(c, std::vector<WorkItem>(work.begin() + w0, work.begin() + w0 + cnt));

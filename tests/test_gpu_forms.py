@@ -247,3 +247,18 @@ def test_inputs_must_match_chain(ctx):
         c2.gwas_pack_encrypt(d.X, d.y, d.S, KAPPA, 1)
     assert e.value.code == -3
     c2.close()
+
+
+def test_server_outputs_freed_while_worker_runs(ctx, oracle_jobs, singles):
+    """Outputs polled and freed on the caller's thread while the server's worker runs the next jobs:
+    freeing returns device buffers to the context's pool under the context's lock (the worker uses the
+    same pool), and every result still matches the oracle."""
+    say("[gpu] server: outputs freed during work")
+    srv = ctx.gwas_server(hbm_budget=0, max_jobs=1, chunk=2)
+    for rnd in range(3):
+        ids = [(q, srv.submit(pack(ctx, oracle_jobs, q))) for q in range(len(JOBS))]
+        for q, jid in ids:
+            out = srv.poll(jid, JOBS[q][2], wait=True)
+            same(outputs(ctx, out, nb(q)), singles[q])
+            del out
+    srv.close()
