@@ -399,9 +399,11 @@ int ckks_ctx_set_streams(ckks_ctx *ctx, int n);
 
 /* Several jobs in one call.  Jobs with the same block size R, covariate count k and kappa share every
  * launch of the fixed part (one batch ciphertext per job) and their SNP batches run through the
- * per-batch part together, `chunk` ciphertexts per launch, each with its own job's values.  out[i]
- * receives job i's output (one batch per output kind, index 0).  Results are bit-identical to running
- * each job alone. */
+ * per-batch part together, `chunk` ciphertexts per launch, each with its own job's values.  A job with
+ * at least chunk / 2 SNP batches, or with the M-materialised layout, runs alone as gwas_semiparallel
+ * runs it (all its batches in one pass when resident and no pool budget is set, else `chunk` at a time).
+ * out[i] receives job i's output (bucketed jobs: one batch per output kind, index 0).  Results are
+ * bit-identical to running each job alone. */
 int gwas_semiparallel_multi(ckks_ctx *ctx, const gwas_enc_input *const *in, int n_jobs, int chunk,
                             gwas_enc_output **out);
 /* Device bytes a job needs while in flight (inputs, outputs and working values). */

@@ -680,14 +680,17 @@ void run_multi(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std::vect
     outs.clear();
     outs.resize(jobs.size());
     // A job with at least half a chunk of SNP batches fills the device with its own launches: it runs as a
-    // single job (its logistic-regression part on the second stream, beside its own SNP batches).  The
-    // smaller jobs are bucketed by shape and share the fixed-part launches and the SNP-batch chunks (an
-    // input with the M-materialised layout always runs as a single job).
+    // single job, as a call for it alone would run it (all its batches in one pass when it is resident and
+    // no pool budget is set, else `chunk` at a time; its logistic-regression part on the second stream,
+    // beside its own SNP batches).  The smaller jobs are bucketed by shape and share the fixed-part
+    // launches and the SNP-batch chunks (an input with the M-materialised layout always runs as a single
+    // job).
     std::map<std::tuple<int, int, int>, std::vector<int>> buckets;
     for (size_t i = 0; i < jobs.size(); ++i) {
         if (2 * jobs[i]->S->count >= chunk || jobs[i]->S_rep) {
-            outs[i].chunk = chunk;
-            run_circuit(c, *jobs[i], outs[i], chunk);
+            const int own = (!jobs[i]->S_host && c.pool->budget == 0) ? std::max(chunk, jobs[i]->S->count) : chunk;
+            outs[i].chunk = own;
+            run_circuit(c, *jobs[i], outs[i], own);
             continue;
         }
         buckets[bucket_of(*jobs[i])].push_back((int)i);
