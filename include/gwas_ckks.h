@@ -187,8 +187,14 @@ int ckks_sub(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out);
 int ckks_mul_int(ckks_ctx *ctx, const ckks_ct *a, int64_t k, ckks_ct **out);
 /* Add the real constant c (the integer round_half_away(c * scale) in the constant coefficient). */
 int ckks_add_const(ckks_ctx *ctx, const ckks_ct *a, double c, ckks_ct **out);
-/* Mult (paper: Mult then Rescale): tensor, relinearise with the s^2 key, rescale
- * by the last prime; result scale (s_a * s_b) / q. */
+/* Mult (paper: Mult then Rescale): tensor (d0, d1, d2), relinearise d2 with the s^2
+ * key and rescale by the last prime q = q_{l-1}, the two divisions (ModDown's by P,
+ * the rescale's by q) taken as one division by P q: with x the key switch's inner
+ * product over q_0..q_{l-1}, p_1..p_alpha and x' = x + P (d0, d1),
+ *   out = (x' - C) / (P q) mod q_0..q_{l-2},  C = sum_b [x' (P q / b)^-1]_b (P q / b)
+ * over b in {q, p_1..p_alpha} (the fast basis conversion: C is x' mod P q plus
+ * e P q with 0 <= e <= alpha, so each coefficient of the result differs from
+ * round(x' / (P q)) by an integer in [0, alpha + 1]).  Result scale (s_a * s_b) / q. */
 int ckks_mul(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct **out);
 /* ckks_mul without any device allocation, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that forbid

@@ -257,6 +257,51 @@ class BigCKKS:
             out.append(((v - C) // self.P) % Ql)
         return out
 
+    def moddown_rescale(self, x: Sequence[int], add: Sequence[int], l: int) -> List[int]:
+        """((x + P add) - C) / B mod Q_{l-1} with B = P q_{l-1}: x mod Q_l P, add mod Q_l, x' = x + P add
+        as an integer in [0, Q_l P), C = sum_{b in {p_1..p_alpha, q_{l-1}}} [x' (B/b)^-1]_b (B/b)."""
+        Ql = self.Q(l)
+        QP = Ql * self.P
+        ql = self.q[l - 1]
+        B = self.P * ql
+        Q1 = Ql // ql
+        out = []
+        for v, a in zip(x, add):
+            xp = (v + self.P * (a % Ql)) % QP
+            C = 0
+            for b in self.p + [ql]:
+                hat = B // b
+                C += (xp * pow(hat % b, -1, b) % b) * hat
+            assert (xp - C) % B == 0
+            # C = x' mod B + e B with 0 <= e <= alpha: the quotient is floor(x' / B) - e
+            assert 0 <= xp // B - (xp - C) // B <= len(self.p)
+            out.append(((xp - C) // B) % Q1)
+        return out
+
+    def accumulate(self, d: Sequence[int], key_list, l: int):
+        """x = sum_i sum_b sigma_{g_i}(D_b) ksk_{i,b} mod Q_l P (both components), before any division."""
+        Ql = self.Q(l)
+        QP = Ql * self.P
+        D = self.digits(d, l)
+        acc0 = [0] * self.N
+        acc1 = [0] * self.N
+        for g, keys in key_list:
+            for b, Db in enumerate(D):
+                db = [v % QP for v in Db]
+                if g:
+                    db = automorph(db, g, QP)
+                kb, ka = keys[b]
+                acc0 = polyadd(acc0, polymul(db, [v % QP for v in kb], QP), QP)
+                acc1 = polyadd(acc1, polymul(db, [v % QP for v in ka], QP), QP)
+        return acc0, acc1
+
+    def mul_rescale(self, a, b, rlk, l: int):
+        """Product with relinearisation and rescale in one division: tensor (d0, d1, d2), x = the key-switch
+        sum of d2 with the s^2 key, out_c = ((x_c + P d_c) - C) / (P q_{l-1}) for c = 0, 1."""
+        d0, d1, d2 = self.tensor(a, b, l)
+        x0, x1 = self.accumulate(d2, [(0, rlk)], l)
+        return self.moddown_rescale(x0, d0, l), self.moddown_rescale(x1, d1, l)
+
     def keyswitch(self, d: Sequence[int], keys, l: int):
         """Key switch of d (an element of Z_{Q_l}[X]) with the key `keys` (keyswitch_galois, no automorphism)."""
         return self.keyswitch_galois(d, [(0, keys)], l)

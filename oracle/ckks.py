@@ -31,8 +31,15 @@ scheme with power-of-two moduli):
 * Alignment to a deeper (depth, scale): mod-drop to one level above the target,
   multiply by the integer round_half_away(((scale * factor) * q) / s), rescale by
   q and declare the target scale (the residual is below 1 / (2 * integer)).
-* Multiplication: tensor product, relinearisation, then rescale by the last
-  prime; the result scale is (s_a * s_b) / q in FP64.
+* Multiplication: tensor product (d0, d1, d2), relinearisation of d2, rescale by
+  the last prime q; the result scale is (s_a * s_b) / q in FP64.  The division by
+  P that ends the relinearisation's key switch and the rescale's division by q
+  are taken as one division by P q of x' = x + P (d0, d1) (x the key switch's
+  sum of digit-key products): (x' - C) / (P q) with
+  C = sum_b [x' (P q / b)^-1]_b (P q / b), b over q and p_1..p_alpha.  It is the
+  same fast conversion as the key switch's own division, with q counted among the
+  special primes; each result coefficient lies within alpha + 1 of the exactly
+  rounded quotient (relin_rescale).
 * Key switching (the paper's non-RNS KeyGen / Mult, in RNS with a hybrid
   decomposition): digit groups of alpha primes, {q_0 .. q_{alpha-2}}, then
   {q_{alpha-1} .. q_{2 alpha-2}}, ... (digit_groups; alpha = 2 gives {q_0},
@@ -100,6 +107,8 @@ def lib():
         L.ref_automorph.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _u64p, ctypes.c_uint64, _u64p]
         L.ref_keyswitch.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64p, ctypes.c_int,
                                     _u64p, ctypes.POINTER(_u64p), ctypes.c_int, _u64p]
+        L.ref_keyswitch_rescale.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64p,
+                                            ctypes.c_int, _u64p, ctypes.POINTER(_u64p), ctypes.c_int, _u64p, _u64p]
         L.ref_gen_ksk.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _i64p, _u64p, ctypes.c_uint64,
                                   ctypes.c_uint64, ctypes.c_int, _u64p]
         L.ref_key_to_eval.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64p, _u64p]
@@ -697,17 +706,35 @@ class Oracle:
         lib().ref_add(self._ctx, 2, d.shape[1], _p(np.ascontiguousarray(d[:2])), _p(ks), _p(out))
         return Ct(out, depth, scale)
 
+    def relin_rescale(self, d: np.ndarray, depth: int) -> Ct:
+        """(d0, d1) + KS(d2) with the relinearisation key, rescaled by q_{l-1} in the same division: one
+        division of x + P (d0, d1) by P q_{l-1} (ref_keyswitch_rescale).  The result is one level deeper;
+        the caller sets its scale."""
+        l = d.shape[1]
+        if l > self._key_l[0]:
+            raise ValueError("relinearisation key was generated for at most %d limbs" % self._key_l[0])
+        if l < 2:
+            raise ValueError("no limb left to rescale")
+        p = self.p
+        out = np.zeros((2, l - 1, p.N), dtype=np.uint64)
+        gal = np.zeros(1, dtype=np.uint64)
+        kevs = (_u64p * 1)(_p(self._kev[0]))
+        lib().ref_keyswitch_rescale(self._ctx, p.L, self.alpha, l, _p(np.ascontiguousarray(d[2])), 1, _p(gal), kevs,
+                                    self.ng, _p(np.ascontiguousarray(d[:2])), _p(out))
+        self.n_keyswitch += 1
+        return Ct(out, depth + 1, 0.0)
+
     def mul_sum(self, pairs: Sequence[Tuple[Ct, Ct]]) -> Ct:
-        """sum_i a_i * b_i with one relinearisation and one rescale; all pairs share depth and product scale."""
+        """sum_i a_i * b_i: the tensors summed, then one relinearisation and rescale in a single division by
+        P q_{l-1} (relin_rescale); all pairs share depth and product scale."""
         a0, b0 = pairs[0]
         s = a0.scale * b0.scale
         for a, b in pairs:
             if a.scale * b.scale != s:
                 raise ValueError("lazy sum of products with different scales")
         d = self.tensor(pairs)
-        c = self.relinearize(d, a0.depth, a0.scale)
+        r = self.relin_rescale(d, a0.depth)
         q = self.p.q_dropped_at_depth(a0.depth)
-        r = self.rescale(c)
         r.scale = (a0.scale * b0.scale) / float(q)
         return r
 

@@ -428,8 +428,10 @@ static void automorph_poly(int n, u64 q, const u64 *a, u64 g, u64 *o) {
     }
 }
 
-void ref_keyswitch(const ref_ctx *c, int L, int alpha, int l, const u64 *d, int n_keys, const u64 *galois,
-                   const u64 *const *kevs, int ng, u64 *out) {
+/* x = sum_i sum_b sigma_i(D_b) ksk_{i,b} in coefficient form, [2][l + alpha][N] (targets q_0..q_{l-1},
+ * p_1..p_alpha); the caller frees it */
+static u64 *ks_accumulate(const ref_ctx *c, int L, int alpha, int l, const u64 *d, int n_keys, const u64 *galois,
+                          const u64 *const *kevs, int ng) {
     int n = c->n, nt = L + 1 + alpha, gl = ref_num_groups(l, alpha), lt = l + alpha;
     size_t kstride_t = (size_t)n, kstride_b = (size_t)nt * n, kstride_c = (size_t)ng * nt * n;
     /* y_i of every limb: d_i times (Q_G / q_i)^-1 modulo q_i */
@@ -483,6 +485,14 @@ void ref_keyswitch(const ref_ctx *c, int L, int alpha, int l, const u64 *d, int 
         }
         free(dig); free(sg); free(fe);
     }
+    free(y);
+    return acc;
+}
+
+void ref_keyswitch(const ref_ctx *c, int L, int alpha, int l, const u64 *d, int n_keys, const u64 *galois,
+                   const u64 *const *kevs, int ng, u64 *out) {
+    int n = c->n, lt = l + alpha;
+    u64 *acc = ks_accumulate(c, L, alpha, l, d, n_keys, galois, kevs, ng);
     /* ModDown: (x - C) / P with C = sum_k [x (P/p_k)^-1]_{p_k} (P/p_k) */
     u64 pk[64], hinv[64];   /* alpha <= 8 */
     for (int k = 0; k < alpha; ++k) pk[k] = c->mods[L + 1 + k].q;
@@ -514,7 +524,63 @@ void ref_keyswitch(const ref_ctx *c, int L, int alpha, int l, const u64 *d, int 
         }
     }
     free(acc);
-    free(y);
+}
+
+/*
+ * Key switch of d followed by the rescale of (add + KS(d)) by q_{l-1}, in one division by B = P q_{l-1}:
+ *   x' = x + P add   (x as in ref_keyswitch; add = [2][l][N] coefficient form, e.g. d0, d1 of a product)
+ *   out = (x' - C) / B mod q_0..q_{l-2},  C = sum_{b in {p_1..p_alpha, q_{l-1}}} [x' (B/b)^-1]_b (B/b),
+ * an exact division since C = x' mod B up to a multiple of B.  out: [2][l-1][N].
+ */
+void ref_keyswitch_rescale(const ref_ctx *c, int L, int alpha, int l, const u64 *d, int n_keys, const u64 *galois,
+                           const u64 *const *kevs, int ng, const u64 *add, u64 *out) {
+    int n = c->n, lt = l + alpha, nb = alpha + 1;
+    u64 *acc = ks_accumulate(c, L, alpha, l, d, n_keys, galois, kevs, ng);
+    u64 bm[16];   /* the moduli of B: p_1 .. p_alpha, q_{l-1} */
+    for (int k = 0; k < alpha; ++k) bm[k] = c->mods[L + 1 + k].q;
+    bm[alpha] = c->mods[l - 1].q;
+    u64 hinv[16];   /* (B/b)^-1 mod b */
+    for (int k = 0; k < nb; ++k) {
+        u64 hat = 1;
+        for (int j = 0; j < nb; ++j) if (j != k) hat = mulmod(hat, bm[j] % bm[k], bm[k]);
+        hinv[k] = invmod(hat, bm[k]);
+    }
+    u64 *yb = (u64 *)malloc(sizeof(u64) * (size_t)nb * n);
+    for (int comp = 0; comp < 2; ++comp) {
+        /* y_b = [x' (B/b)^-1]_b for the moduli of B: x' = x on the special primes, x + P add on q_{l-1} */
+        for (int k = 0; k < nb; ++k) {
+            const u64 *xs = k < alpha ? acc + ((size_t)comp * lt + l + k) * n : acc + ((size_t)comp * lt + l - 1) * n;
+            u64 qb = bm[k], pm = 1;
+            if (k == alpha)
+                for (int j = 0; j < alpha; ++j) pm = mulmod(pm, bm[j] % qb, qb);
+            const u64 *ad = add + ((size_t)comp * l + l - 1) * n;
+            for (int t = 0; t < n; ++t) {
+                u64 v = xs[t];
+                if (k == alpha) v = addmod(v, mulmod(ad[t], pm, qb), qb);
+                yb[(size_t)k * n + t] = mulmod(v, hinv[k], qb);
+            }
+        }
+        for (int i = 0; i < l - 1; ++i) {
+            u64 q = c->mods[i].q, pm = 1, bmq = 1, hq[16];
+            for (int j = 0; j < alpha; ++j) pm = mulmod(pm, bm[j] % q, q);
+            for (int k = 0; k < nb; ++k) {
+                bmq = mulmod(bmq, bm[k] % q, q);
+                hq[k] = 1;   /* (B/b) mod q */
+                for (int j = 0; j < nb; ++j) if (j != k) hq[k] = mulmod(hq[k], bm[j] % q, q);
+            }
+            u64 binv = invmod(bmq, q);
+            const u64 *xi = acc + ((size_t)comp * lt + i) * n, *ai = add + ((size_t)comp * l + i) * n;
+            u64 *o = out + ((size_t)comp * (l - 1) + i) * n;
+            for (int t = 0; t < n; ++t) {
+                u64 cv = 0;
+                for (int k = 0; k < nb; ++k) cv = addmod(cv, mulmod(yb[(size_t)k * n + t] % q, hq[k], q), q);
+                u64 xp = addmod(xi[t], mulmod(ai[t], pm, q), q);
+                o[t] = mulmod(submod(xp, cv, q), binv, q);
+            }
+        }
+    }
+    free(yb);
+    free(acc);
 }
 
 /*

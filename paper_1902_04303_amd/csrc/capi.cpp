@@ -152,6 +152,44 @@ void build_ks_tables(ckks_ctx &c) {
         c.p_inv.v[i] = pm ? invmod_host(pm, q) : 0;
         c.p_inv.sh[i] = shoup_of(c.p_inv.v[i], q);
     }
+    // fused relinearisation and rescale by q_j: B = P q_j with moduli b = (q_j, p_1 .. p_alpha);
+    // C = sum_b [x (B/b)^-1]_b (B/b), the scales (B/b)^-1 and N^-1 folded into the inverse NTT of those
+    // limbs, B/b mod q_i into the conversion to the remaining q_i (i < j), B^-1 mod q_i into the final store
+    std::vector<std::vector<ConvEntry>> rconv(nq);
+    std::vector<std::vector<LimbScale>> rscale(nq);
+    std::vector<u64> binv((size_t)nq * 3 * kMaxMods, 0);   // [j][v, sh, d][kMaxMods]
+    for (int j = 1; j < nq; ++j) {
+        std::vector<u64> bm(1, p.q[j]);
+        bm.insert(bm.end(), p.P.begin(), p.P.end());
+        const int nb = a + 1;
+        for (int k = 0; k < nb; ++k) {
+            u64 hat = 1;
+            for (int m = 0; m < nb; ++m)
+                if (m != k) hat = mulmod_host(hat, bm[m] % bm[k], bm[k]);
+            rscale[j].push_back(
+                limb_scale(mulmod_host(invmod_host((u64)p.n % bm[k], bm[k]), invmod_host(hat, bm[k]), bm[k]), bm[k]));
+        }
+        for (int i = 0; i < j; ++i) {
+            u64 cs[kMaxSpecial] = {};
+            for (int k = 0; k < nb; ++k) {
+                u64 hat = 1;
+                for (int m = 0; m < nb; ++m)
+                    if (m != k) hat = mulmod_host(hat, bm[m] % p.q[i], p.q[i]);
+                cs[k] = hat;
+            }
+            rconv[j].push_back(conv_entry(0, nb, i, cs, p.q[i], bm));
+        }
+        u64 *v = &binv[(size_t)j * 3 * kMaxMods], *sh = v + kMaxMods;
+        double *d = reinterpret_cast<double *>(sh + kMaxMods);
+        for (int i = 0; i < j; ++i) {
+            const u64 q = p.q[i];
+            u64 bq = p.q[j] % q;   // B mod q_i
+            for (int k = 0; k < a; ++k) bq = mulmod_host(bq, p.P[k] % q, q);
+            v[i] = invmod_host(bq, q);
+            sh[i] = shoup_of(v[i], q);
+            d[i] = (double)v[i];
+        }
+    }
     // one device block for everything
     size_t bytes = 0;
     auto room = [&](size_t b) { size_t o = bytes; bytes += (b + 255) / 256 * 256; return o; };
@@ -164,6 +202,12 @@ void build_ks_tables(ckks_ctx &c) {
     const size_t o_down = room(down.size() * sizeof(ConvEntry)), o_dsc = room(dscale.size() * sizeof(LimbScale));
     const size_t o_pinv = room(kMaxMods * 8), o_pinv_sh = room(kMaxMods * 8), o_pinv_d = room(kMaxMods * 8);
     const size_t o_qinv = room((size_t)nq * 3 * kMaxMods * 8);   // [j][v, sh, d][kMaxMods]
+    std::vector<size_t> o_rconv(nq), o_rscale(nq);
+    for (int j = 1; j < nq; ++j) {
+        o_rconv[j] = room(rconv[j].size() * sizeof(ConvEntry));
+        o_rscale[j] = room(rscale[j].size() * sizeof(LimbScale));
+    }
+    const size_t o_binv = room(binv.size() * 8);
     GCK_HIP(hipMalloc(&c.ks_mem, bytes));
     char *base = static_cast<char *>(c.ks_mem);
     c.ks_levels.assign(nq + 1, ckks_ctx::KsLevel{});
@@ -205,6 +249,19 @@ void build_ks_tables(ckks_ctx &c) {
         c.q_inv[j] = ckks_ctx::QInv{dev, dev + kMaxMods, reinterpret_cast<double *>(dev + 2 * kMaxMods)};
     }
     GCK_HIP(hipMemcpy(base + o_qinv, qinv.data(), qinv.size() * 8, hipMemcpyHostToDevice));
+    c.rs_levels.assign(nq, ckks_ctx::RsLevel{});
+    for (int j = 1; j < nq; ++j) {
+        auto &rl = c.rs_levels[j];
+        rl.conv = reinterpret_cast<ConvEntry *>(base + o_rconv[j]);
+        rl.scale = reinterpret_cast<LimbScale *>(base + o_rscale[j]);
+        GCK_HIP(hipMemcpy(rl.conv, rconv[j].data(), rconv[j].size() * sizeof(ConvEntry), hipMemcpyHostToDevice));
+        GCK_HIP(hipMemcpy(rl.scale, rscale[j].data(), rscale[j].size() * sizeof(LimbScale), hipMemcpyHostToDevice));
+        u64 *dev = reinterpret_cast<u64 *>(base + o_binv) + (size_t)j * 3 * kMaxMods;
+        rl.binv = dev;
+        rl.binv_sh = dev + kMaxMods;
+        rl.binv_d = reinterpret_cast<double *>(dev + 2 * kMaxMods);
+    }
+    GCK_HIP(hipMemcpy(base + o_binv, binv.data(), binv.size() * 8, hipMemcpyHostToDevice));
     c.ng = ks_groups(nq, p.alpha);
 }
 
@@ -304,7 +361,7 @@ const char *ckks_last_error(void) { return g_err.c_str(); }
 int ckks_params_ks_alpha(const ckks_params *params) {
     if (!params) return CKKS_E_INVALID_ARG;
     const int a = params->ks_alpha == 0 ? CKKS_DEFAULT_KS_ALPHA : params->ks_alpha;
-    return (a >= 2 && a <= kMaxSpecial) ? a : CKKS_E_INVALID_ARG;
+    return (a >= 2 && a <= kMaxAlpha) ? a : CKKS_E_INVALID_ARG;
 }
 
 int ckks_chain(const ckks_params *params, uint64_t *moduli, double *scales) {

@@ -20,7 +20,8 @@ using i64 = int64_t;
 using u128 = unsigned __int128;
 
 constexpr int kMaxMods = 64;     // q_0..q_L and the special primes
-constexpr int kMaxSpecial = 8;   // special primes p_1 .. p_alpha of the key-switching modulus P (alpha <= 8)
+constexpr int kMaxAlpha = 8;     // special primes p_1 .. p_alpha of the key-switching modulus P (alpha <= 8)
+constexpr int kMaxSpecial = kMaxAlpha + 1;   // sources of one basis conversion (P, or P q_j for a fused rescale)
 
 // ---------------------------------------------------------------- errors
 struct Error : std::runtime_error {
@@ -142,6 +143,7 @@ struct DBuf {
 // period = nq = l; key-switch accumulators [count][2][l + alpha][N] have period l + alpha, nq = l.
 struct ModMap {
     int period, nq, p_idx;
+    int q_off = 0;   // t < nq is q_{q_off + t}
 };
 inline ModMap map_q(int l) { return ModMap{l, l, 0}; }
 
@@ -261,6 +263,13 @@ struct ModDownEpi {
     u64 g[kMaxKeys];
     int acc_mul;           // 1: acc is first multiplied by km[chain] (an integer constant modulo each modulus)
     u64 km[kMaxMods];
+    // a product's relinearisation fused with its rescale: the added term (d0, d1 of the tensor) is read
+    // from [count][3][l][N] (row r = lam / rowlen of the output takes ciphertext r / 2, polynomial r % 2:
+    // add.ptr + ((r / 2) add_ct + (r % 2) add_poly + lam % rowlen) N) and multiplied by addmul[chain]
+    // (q_{l-1}^-1), with pinv = (P q_{l-1})^-1; add_ct == 0: the plain gather of `add`
+    const u64 *addmul = nullptr, *addmul_sh = nullptr;
+    const double *addmul_d = nullptr;
+    int add_ct = 0, add_poly = 0;
 };
 void k_ntt_forward_g(const DevTables &t, u64 *buf, const Gather &in, int n_limbs, ModMap m, hipStream_t st,
                      const ModDownEpi *epi = nullptr);
@@ -272,6 +281,10 @@ void k_add(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs
            hipStream_t st);
 void k_sub(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
            hipStream_t st);
+// acc[row][l-1] += pm add[row / 2][row % 2][l-1] (NTT domain, modulo q_{l-1}) for the 2 count rows of a
+// key switch's accumulators ([count][2][nt][N]) and a tensor add ([count][3][l][N])
+void k_add_scaled_last(const DevTables &t, u64 *acc, const u64 *add, int count, int nt, int l, u64 pm, u64 pm_sh,
+                       u64 q, hipStream_t st);
 void k_tensor_rep_sum(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int cnt, int n_rows, int l,
                       hipStream_t st);
 void k_add_rotated_plain(const DevTables &t, u64 *out, const u64 *a, const u64 *pt, int count, int l, int R,

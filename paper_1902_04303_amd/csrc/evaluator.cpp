@@ -501,6 +501,62 @@ static KsKeys ks_keys(const ckks_ctx &c, const std::vector<u64> &ids, bool permu
     return k;
 }
 
+// Relinearisation of the tensors d ([count][3][l][N], NTT form) fused with the rescale by q_{l-1}: the
+// key switch of d2 up to its inner product x (targets q_0..q_{l-1}, p_1..p_alpha) as in keyswitch, then
+// one division of x' = x + P (d0, d1) by B = P q_{l-1} in place of ModDown's division by P and the
+// rescale's by q_{l-1}:
+//   x' at q_{l-1} formed in place (acc += (P mod q_{l-1}) d; x' = x at the special primes);
+//   y_b = [x' (B/b)^-1]_b for b = q_{l-1}, p_1..p_alpha (the scales folded into one inverse NTT of those
+//   limbs);  C = sum_b y_b (B/b) converted while loading the forward NTT of the l - 1 remaining limbs,
+//   whose final store forms (x - C) B^-1 + (d0, d1) q_{l-1}^-1.
+// Output [count][2][l-1][N] in NTT form, written into out.
+static void keyswitch_rescale(ckks_ctx &c, const u64 *d, int count, int l, u64 *out) {
+    if (l < 2) throw Error(CKKS_E_LEVEL, "no limb left to rescale");
+    const size_t N = (size_t)c.p.n;
+    const ckks_ctx::KsLevel &kl = c.ks_levels.at(l);
+    const ckks_ctx::RsLevel &rl = c.rs_levels.at(l - 1);
+    const ckks_ctx::QInv &qi = c.q_inv.at(l - 1);
+    const int a = c.p.alpha, nt = l + a, P = c.p.p_index(), nb = a + 1, lo = l - 1, rows = count * 2;
+    const KsKeys keys = ks_keys(c, {0}, false);
+    // algorithmic bytes: d2 (l limbs per ciphertext), the key's digit groups below l at every target
+    // (read once per call), d0 and d1 read (2 l) and the two output polynomials written (2 (l - 1))
+    const int groups = 1 + l / a;
+    const double ks_bytes = 8.0 * (double)N *
+                            ((double)count * l + 2.0 * groups * nt + (double)count * 2.0 * l + (double)count * 2.0 * lo);
+    KRegion region_(c.tab.timer, "keyswitch", ks_bytes, c.stream);
+    const Gather d2{d, l, 3 * l, 2 * l, 1, kPlain, 0};
+    DBuf dc(c.pool.get(), (size_t)count * l * N);
+    k_ntt_inverse_g(c.tab, dc.ptr, d2, count * l, map_q(l), c.stream, kl.up_scale, l);
+    DBuf dig(c.pool.get(), (size_t)count * kl.K * N);
+    k_ntt_forward_g(c.tab, dig.ptr, Gather{dc.ptr, 1, 1, 0, 0, kConv, 0, kl.up, kl.K, l}, count * kl.K, map_q(l),
+                    c.stream);
+    dc.release();
+    DBuf acc(c.pool.get(), (size_t)count * 2 * nt * N);
+    k_ks_inner(c.tab, acc.ptr, dig.ptr, kl.K, kl.didx, d2, keys, c.ng, count, l, c.p.levels, a, c.stream);
+    dig.release();
+    const u64 ql = c.p.q[l - 1];
+    u64 pm = 1;   // P mod q_{l-1}
+    for (int k = 0; k < a; ++k) pm = mulmod_host(pm, c.p.P[k] % ql, ql);
+    k_add_scaled_last(c.tab, acc.ptr, d, count, nt, l, pm, (u64)(((unsigned __int128)pm << 64) / ql), ql, c.stream);
+    DBuf yb(c.pool.get(), (size_t)rows * nb * N);
+    k_ntt_inverse_g(c.tab, yb.ptr, Gather{acc.ptr, nb, nt, l - 1, 1, kPlain, 0}, rows * nb, ModMap{nb, 1, P, l - 1},
+                    c.stream, rl.scale, nb);
+    ModDownEpi epi{Gather{acc.ptr, lo, nt, 0, 1, kPlain, 0}, Gather{d, 1, 1, 0, 0, kPlain, 0}, 0, lo, rl.binv,
+                   rl.binv_sh, rl.binv_d, nullptr, 0, 0, {}};
+    epi.addmul = qi.v;
+    epi.addmul_sh = qi.sh;
+    epi.addmul_d = qi.d;
+    epi.add_ct = 3 * l;
+    epi.add_poly = l;
+    k_ntt_forward_g(c.tab, out, Gather{yb.ptr, 1, 1, 0, 0, kConv, 0, rl.conv, lo, nb}, rows * lo, map_q(lo), c.stream,
+                    &epi);
+    c.n_limb_ntt += (uint64_t)count * (l + kl.K) + (uint64_t)rows * (nb + lo);
+    c.n_launch += 10;
+    ++c.n_keyswitch;
+    c.n_keyswitch_ct += (uint64_t)count;
+}
+
+
 Ct mul_sum(ckks_ctx &c, const std::vector<std::pair<const ckks_ct *, const ckks_ct *>> &pairs) {
     if (pairs.empty()) throw Error(CKKS_E_INVALID_ARG, "empty product sum");
     const ckks_ct &a0 = *pairs[0].first, &b0 = *pairs[0].second;
@@ -530,19 +586,9 @@ Ct mul_sum(ckks_ctx &c, const std::vector<std::pair<const ckks_ct *, const ckks_
 // relinearise the tensors d ([count][3][l][N]): (d0, d1) + KS(d2, s^2 key), then rescale; result scale
 // (sa * sb) / q
 Ct relin_rescale(ckks_ctx &c, DBuf d, int count, int depth, int l, double sa, double sb) {
-    DBuf ks = keyswitch(c, Gather{d.ptr, l, 3 * l, 2 * l, 1, kPlain, 0}, count, l, ks_keys(c, {0}, false),
-                        Gather{d.ptr, 2 * l, 3 * l, 0, 1, kPlain, 0}, false);
-    d.release();
-    ckks_ct tmp;
-    tmp.ctx = &c;
-    tmp.count = count;
-    tmp.depth = depth;
-    tmp.limbs = l;
-    tmp.scale = sa;
-    tmp.data = std::move(ks);
     const u64 q = c.p.dropped_at(depth);
-    Ct r = rescale(c, tmp);
-    r->scale = (sa * sb) / (double)q;
+    Ct r = new_ct(c, count, depth + 1, (sa * sb) / (double)q);
+    keyswitch_rescale(c, d.ptr, count, l, r->data.ptr);
     return r;
 }
 

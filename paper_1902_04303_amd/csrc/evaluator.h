@@ -37,6 +37,17 @@ struct ckks_ctx {
         double *d = nullptr;
     };
     std::vector<QInv> q_inv;
+    // a product's relinearisation fused with its rescale by q_j (j = 1..L): the division by B = P q_j, its
+    // moduli ordered q_j, p_1..p_alpha: conversion to each q_i, i < j (j entries), the inverse-NTT scales
+    // N^-1 (B/b)^-1 mod b (alpha + 1 entries) and (P q_j)^-1 mod every chain modulus (value, Shoup
+    // companion, double)
+    struct RsLevel {
+        gck::ConvEntry *conv = nullptr;
+        gck::LimbScale *scale = nullptr;
+        gck::u64 *binv = nullptr, *binv_sh = nullptr;
+        double *binv_d = nullptr;
+    };
+    std::vector<RsLevel> rs_levels;
     int ng = 0;                              // digit groups of a key (at L + 1 limbs)
     // keys: a context made by keygen holds the secret (the client's side); an evaluating context may hold
     // only imported switching keys (and a public key), never the secret

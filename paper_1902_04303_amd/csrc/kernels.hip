@@ -231,6 +231,26 @@ void k_tensor(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int coun
     check_launch();
 }
 
+__global__ void ew_add_scaled_last(u64 *acc, const u64 *add, size_t total, int log_n, int nt, int l, u64 pm,
+                                   u64 pm_sh, u64 q) {
+    const size_t nw = (size_t)1 << log_n;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        const size_t row = idx >> log_n, k = idx & (nw - 1);
+        u64 *a = acc + (row * nt + l - 1) * nw + k;
+        const u64 dv = add[((row >> 1) * 3 * l + (row & 1) * l + l - 1) * nw + k];
+        *a = add_mod(*a, mul_shoup(dv, pm, pm_sh, q), q);
+    }
+}
+void k_add_scaled_last(const DevTables &t, u64 *acc, const u64 *add, int count, int nt, int l, u64 pm, u64 pm_sh,
+                       u64 q, hipStream_t st) {
+    TScope ts_(t, "ew_add_scaled_last", 24.0 * (double)count * 2 * t.n, st);
+    const size_t total = (size_t)count * 2 << t.log_n;
+    if (!total) return;
+    gck_launch(ew_add_scaled_last, ew_grid(total), dim3(kEwThreads), 0, st, acc, add, total, t.log_n, nt, l, pm,
+               pm_sh, q);
+    check_launch();
+}
+
 // CP-REP product sum of the M-materialised layout: for every batch b of the chunk,
 //   d_b = sum_{i < n} a_i (x) b_{b, i}   (tensor: d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1, mod q)
 // with a = the n duplicated columns of M ([n][2][l][N]) and b the REP rows ([cnt][n][2][l][N]); out is

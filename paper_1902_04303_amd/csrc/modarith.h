@@ -50,7 +50,7 @@ __device__ __forceinline__ u64 reduce64(u64 x, const ModInfo &M) {
 // chain index of limb lam: t = lam mod period is q_t below nq, else special prime p_idx + (t - nq)
 __device__ __forceinline__ int chain_of(int lam, ModMap m) {
     int t = lam % m.period;
-    return t < m.nq ? t : m.p_idx + (t - m.nq);
+    return t < m.nq ? m.q_off + t : m.p_idx + (t - m.nq);
 }
 
 // NTT-domain automorphism X -> X^g: word k of the result is word k2 of the input, where the evaluation

@@ -1,10 +1,11 @@
 // The relinearised product without device allocation (ckks_mul_noalloc): the same operation and kernels
-// as ckks_mul, with every intermediate buffer (tensor, ModUp digits, key-switch accumulators, ModDown and
-// rescale rows, the product before it is copied into the caller's ciphertext) carved from one file-scope
-// device array.  Each GPU holds its own copy of the array from module load until the process ends; every
-// call on a GPU shares it, so calls that overlap on one GPU (two host threads, or two contexts on
-// different streams) race and must be serialised by the caller.  No buffer of the product is read before
-// it is written, so nothing in the array has to start at zero and the last call's contents are harmless.
+// as ckks_mul, with every intermediate buffer (tensor, ModUp digits, key-switch accumulators, the limbs of
+// the division by P q_{l-1}, the product before it is copied into the caller's ciphertext) carved from one
+// file-scope device array.  Each GPU holds its own copy of the array from module load until the process
+// ends; every call on a GPU shares it, so calls that overlap on one GPU (two host threads, or two
+// contexts on different streams) race and must be serialised by the caller.  No buffer of the product is
+// read before it is written, so nothing in the array has to start at zero and the last call's contents
+// are harmless.
 #include <map>
 #include <mutex>
 
@@ -46,20 +47,18 @@ void noalloc_init() { (void)scratch_ptr(); }
 
 size_t noalloc_max_bytes() { return kScratchBytes; }
 
-// Bytes the product takes from the arena, in the order mul_sum, keyswitch and rescale take their buffers
-// (the arena gives back only its most recent block, so every one of them counts).
+// Bytes the product takes from the arena, in the order mul_sum and its fused relinearisation and rescale
+// take their buffers (the arena gives back only its most recent block, so every one of them counts).
 size_t mul_noalloc_bytes(const ckks_ctx &c, int count, int l) {
     const size_t N = (size_t)c.p.n;
     const int a = c.p.alpha, nt = l + a, rows = 2 * count;
     const size_t K = (size_t)c.ks_levels.at(l).K;
     return blk((size_t)count * 3 * l * N)        // tensor d0, d1, d2
+           + blk((size_t)rows * (l - 1) * N)     // the product
            + blk((size_t)count * l * N)          // ModUp: coefficient limbs
            + blk((size_t)count * K * N)          // ModUp: digits at every target
            + blk((size_t)count * 2 * nt * N)     // inner-product accumulators
-           + blk((size_t)rows * a * N)           // ModDown: special limbs
-           + blk((size_t)rows * l * N)           // key-switch output
-           + blk((size_t)rows * N)               // rescale: last limb
-           + blk((size_t)rows * (l - 1) * N);    // the product
+           + blk((size_t)rows * (a + 1) * N);    // the division by P q_{l-1}: its alpha + 1 limbs
 }
 
 void mul_noalloc(ckks_ctx &c, const ckks_ct &a, const ckks_ct &b, ckks_ct &out) {

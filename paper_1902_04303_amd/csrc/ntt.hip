@@ -462,7 +462,11 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
             const u64 *xa = E.acc.ptr + gathered(E.acc, limb) * n;
             const bool even = ((limb / E.rowlen) & 1) == 0;
             const bool with_add = E.add.ptr && (!E.add_even || even);
-            const u64 *xd = with_add ? E.add.ptr + gathered(E.add, limb) * n : nullptr;
+            const int arow = limb / E.rowlen;
+            const u64 *xd = !with_add ? nullptr
+                            : E.add_ct ? E.add.ptr + ((size_t)(arow >> 1) * E.add_ct + (size_t)(arow & 1) * E.add_poly +
+                                                      (size_t)(limb % E.rowlen)) * n
+                                       : E.add.ptr + gathered(E.add, limb) * n;
             const u64 *xs = E.aut ? E.aut + (size_t)limb * n : nullptr;
             const int n_aut = (xs && even) ? E.n_g : 0;
             // aut_self 1: the ciphertext itself on every row; 2: on odd rows only (the even rows' term comes
@@ -492,11 +496,12 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
                     }
                     double r[EG];
                     const double kmul = E.acc_mul ? u2d(E.km[chain]) : 0.0;
+                    const double amul = E.addmul_d ? E.addmul_d[chain] : 0.0;
 #pragma unroll
                     for (int j = 0; j < EG; ++j) {
                         const double av = E.acc_mul ? fmul_mod(u2d(va[j]), kmul, fm) : u2d(va[j]);
                         r[j] = fmul_mod(av - u2d(vt[j]), pd, fm);
-                        r[j] += u2d(vd[j]) + u2d(vs[j]);
+                        r[j] += (E.addmul_d ? fmul_mod(u2d(vd[j]), amul, fm) : u2d(vd[j])) + u2d(vs[j]);
 #pragma unroll
                         for (int i = 0; i < AU; ++i) r[j] += u2d(vp[i][j]);
                     }
@@ -528,7 +533,9 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
                     const u64 t = sh[lds_addr<ROWS>(gi, idx, LOGM, log_g)];
                     const u64 av = E.acc_mul ? mul_mod(xa[base + idx], E.km[chain], M) : xa[base + idx];
                     u64 r = mul_shoup(sub_mod(av, t, qm), pv, ps, qm);
-                    if (with_add) r = add_mod(r, xd[base + idx], qm);
+                    if (with_add)
+                        r = add_mod(r, E.addmul ? mul_shoup(xd[base + idx], E.addmul[chain], E.addmul_sh[chain], qm)
+                                                : xd[base + idx], qm);
                     if (aut_self) r = add_mod(r, xs[base + idx], qm);
                     for (int i = 0; i < n_aut; ++i) r = add_mod(r, xs[automorph_src(base + idx, g.log_n, E.g[i])], qm);
                     a[base + idx] = r;

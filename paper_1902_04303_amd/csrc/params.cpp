@@ -77,7 +77,7 @@ i64 round_half_away(double x) {
 Params make_params(int log_n, int levels, int log2_scale, int alpha) {
     if (alpha == 0) alpha = CKKS_DEFAULT_KS_ALPHA;
     if (log_n < 10 || log_n > 17) throw Error(CKKS_E_INVALID_ARG, "log_n must be in [10, 17]");
-    if (alpha < 2 || alpha > kMaxSpecial) throw Error(CKKS_E_INVALID_ARG, "ks_alpha must be 0 or in [2, 8]");
+    if (alpha < 2 || alpha > kMaxAlpha) throw Error(CKKS_E_INVALID_ARG, "ks_alpha must be 0 or in [2, 8]");
     if (levels < 1 || levels + 1 + alpha > kMaxMods) throw Error(CKKS_E_INVALID_ARG, "levels out of range");
     if (log2_scale < 20 || log2_scale > 50) throw Error(CKKS_E_INVALID_ARG, "log2_scale must be in [20, 50]");
     Params p;

@@ -196,6 +196,25 @@ def test_encrypt_tensor_keyswitch_rescale_match_bigint(tiny_keys):
     r = o.rescale(c1)
     br = bc.rescale(b1, l)
     assert _ct_big(r, p, l - 1) == br
+    # the product: relinearisation and rescale in one division by P q_{l-1} (mul / mul_sum), at the top
+    # level and one level down
+    for lev in (l, l - 1):
+        a1 = C.Ct(np.ascontiguousarray(c1.data[:, :lev]), p.L + 1 - lev, c1.scale)
+        a2 = C.Ct(np.ascontiguousarray(c2.data[:, :lev]), p.L + 1 - lev, c2.scale)
+        pr = o.mul(a1, a2)
+        assert pr.limbs == lev - 1
+        want = bc.mul_rescale(_ct_big(a1, p, lev), _ct_big(a2, p, lev), keys, lev)
+        assert _ct_big(pr, p, lev - 1) == want, lev
+        # against the two divisions taken one after the other (ModDown by P, then the centred rescale by
+        # q_{lev-1}): the one division differs by at most alpha + 2 per coefficient
+        bd = bc.tensor(_ct_big(a1, p, lev), _ct_big(a2, p, lev), lev)
+        Ql = bc.Q(lev)
+        kd = bc.keyswitch(bd[2], keys, lev)
+        seq = bc.rescale(tuple([(x + y) % Ql for x, y in zip(bd[c], kd[c])] for c in range(2)), lev)
+        Q1 = Ql // p.q[lev - 1]
+        for c in range(2):
+            diff = [((w - v + Q1 // 2) % Q1) - Q1 // 2 for w, v in zip(want[c], seq[c])]
+            assert max(abs(x) for x in diff) <= o.alpha + 2, (lev, c)
 
 
 def test_rotation_and_grouped_rotation_sum_match_bigint(tiny_keys):
