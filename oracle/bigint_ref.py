@@ -245,21 +245,25 @@ class BigCKKS:
         return out
 
     def moddown(self, x: Sequence[int], l: int) -> List[int]:
-        """(x - C) / P mod Q_l for x mod Q_l P, C = sum_k [x (P/p_k)^-1]_{p_k} (P/p_k)."""
+        """(x - C) / P mod Q_l for x mod Q_l P, C = sum_k [x (P/p_k)^-1]_{p_k} (P/p_k) with each [.]_{p_k}
+        the centred representative in (-p_k/2, p_k/2)."""
         Ql = self.Q(l)
         out = []
         for v in x:
             C = 0
             for pk in self.p:
                 hat = self.P // pk
-                C += (v * pow(hat % pk, -1, pk) % pk) * hat
+                C += centred(v * pow(hat % pk, -1, pk) % pk, pk) * hat
             assert (v - C) % self.P == 0
+            # |C| < alpha P / 2: the quotient lies within alpha / 2 of v / P
+            assert 2 * abs(C) < len(self.p) * self.P
             out.append(((v - C) // self.P) % Ql)
         return out
 
     def moddown_rescale(self, x: Sequence[int], add: Sequence[int], l: int) -> List[int]:
         """((x + P add) - C) / B mod Q_{l-1} with B = P q_{l-1}: x mod Q_l P, add mod Q_l, x' = x + P add
-        as an integer in [0, Q_l P), C = sum_{b in {p_1..p_alpha, q_{l-1}}} [x' (B/b)^-1]_b (B/b)."""
+        as an integer in [0, Q_l P), C = sum_{b in {p_1..p_alpha, q_{l-1}}} [x' (B/b)^-1]_b (B/b) with each
+        [.]_b the centred representative in (-b/2, b/2)."""
         Ql = self.Q(l)
         QP = Ql * self.P
         ql = self.q[l - 1]
@@ -271,10 +275,10 @@ class BigCKKS:
             C = 0
             for b in self.p + [ql]:
                 hat = B // b
-                C += (xp * pow(hat % b, -1, b) % b) * hat
+                C += centred(xp * pow(hat % b, -1, b) % b, b) * hat
             assert (xp - C) % B == 0
-            # C = x' mod B + e B with 0 <= e <= alpha: the quotient is floor(x' / B) - e
-            assert 0 <= xp // B - (xp - C) // B <= len(self.p)
+            # |C| < (alpha + 1) B / 2: the quotient lies within (alpha + 1) / 2 of x' / B
+            assert 2 * abs(C) < (len(self.p) + 1) * B
             out.append(((xp - C) // B) % Q1)
         return out
 

@@ -493,7 +493,8 @@ void ref_keyswitch(const ref_ctx *c, int L, int alpha, int l, const u64 *d, int 
                    const u64 *const *kevs, int ng, u64 *out) {
     int n = c->n, lt = l + alpha;
     u64 *acc = ks_accumulate(c, L, alpha, l, d, n_keys, galois, kevs, ng);
-    /* ModDown: (x - C) / P with C = sum_k [x (P/p_k)^-1]_{p_k} (P/p_k) */
+    /* ModDown: (x - C) / P with C = sum_k [x (P/p_k)^-1]_{p_k} (P/p_k), each [.]_{p_k} the centred
+       representative in (-p_k/2, p_k/2) */
     u64 pk[64], hinv[64];   /* alpha <= 8 */
     for (int k = 0; k < alpha; ++k) pk[k] = c->mods[L + 1 + k].q;
     for (int k = 0; k < alpha; ++k) {   /* (P/p_k)^-1 mod p_k */
@@ -517,7 +518,8 @@ void ref_keyswitch(const ref_ctx *c, int L, int alpha, int l, const u64 *d, int 
                 u64 cv = 0;
                 for (int j = 0; j < alpha; ++j) {
                     u64 yk = mulmod(xs[(size_t)j * n + k], hinv[j], pk[j]);
-                    cv = addmod(cv, mulmod(yk % q, hq[j], q), q);
+                    u64 ykq = yk > pk[j] / 2 ? submod(yk % q, pk[j] % q, q) : yk % q;   /* yk - p_k */
+                    cv = addmod(cv, mulmod(ykq, hq[j], q), q);
                 }
                 o[k] = mulmod(submod(xi[k], cv, q), pinv, q);
             }
@@ -530,7 +532,8 @@ void ref_keyswitch(const ref_ctx *c, int L, int alpha, int l, const u64 *d, int 
  * Key switch of d followed by the rescale of (add + KS(d)) by q_{l-1}, in one division by B = P q_{l-1}:
  *   x' = x + P add   (x as in ref_keyswitch; add = [2][l][N] coefficient form, e.g. d0, d1 of a product)
  *   out = (x' - C) / B mod q_0..q_{l-2},  C = sum_{b in {p_1..p_alpha, q_{l-1}}} [x' (B/b)^-1]_b (B/b),
- * an exact division since C = x' mod B up to a multiple of B.  out: [2][l-1][N].
+ * each [.]_b the centred representative in (-b/2, b/2); an exact division since C = x' mod B up to a
+ * multiple of B.  out: [2][l-1][N].
  */
 void ref_keyswitch_rescale(const ref_ctx *c, int L, int alpha, int l, const u64 *d, int n_keys, const u64 *galois,
                            const u64 *const *kevs, int ng, const u64 *add, u64 *out) {
@@ -573,7 +576,11 @@ void ref_keyswitch_rescale(const ref_ctx *c, int L, int alpha, int l, const u64 
             u64 *o = out + ((size_t)comp * (l - 1) + i) * n;
             for (int t = 0; t < n; ++t) {
                 u64 cv = 0;
-                for (int k = 0; k < nb; ++k) cv = addmod(cv, mulmod(yb[(size_t)k * n + t] % q, hq[k], q), q);
+                for (int k = 0; k < nb; ++k) {
+                    u64 y = yb[(size_t)k * n + t];
+                    u64 yq = y > bm[k] / 2 ? submod(y % q, bm[k] % q, q) : y % q;   /* y - b */
+                    cv = addmod(cv, mulmod(yq, hq[k], q), q);
+                }
                 u64 xp = addmod(xi[t], mulmod(ai[t], pm, q), q);
                 o[t] = mulmod(submod(xp, cv, q), binv, q);
             }

@@ -68,18 +68,24 @@ int bit_reverse(int x, int bits) {
 
 LimbScale limb_scale(u64 w, u64 q) { return LimbScale{w, shoup_of(w, q), (double)w}; }
 
-ConvEntry conv_entry(int src, int nsrc, int chain, const u64 *cs, u64 q, const std::vector<u64> &src_mods) {
+ConvEntry conv_entry(int src, int nsrc, int chain, const u64 *cs, u64 q, const std::vector<u64> &src_mods,
+                     bool centre = false) {
     ConvEntry e{};
     e.src = src;
     e.nsrc = nsrc;
     e.chain = chain;
     e.big = 0;
+    e.centre = centre ? 1 : 0;
     for (int m = 0; m < nsrc; ++m) {
         e.c[m] = cs[m] % q;
         e.c_sh[m] = shoup_of(e.c[m], q);
         e.cd[m] = (double)e.c[m];
         if (src_mods[m] >= (1ULL << 47)) e.big |= 1 << m;   // source m's residues need splitting
+        e.half[m] = src_mods[m] >> 1;
+        e.negsq[m] = (q - src_mods[m] % q) % q;
+        e.sqd[m] = (double)src_mods[m];
     }
+    if (centre && e.big) throw Error(CKKS_E_INVALID_ARG, "centred conversion from a modulus of 2^47 or more");
     return e;
 }
 
@@ -135,7 +141,7 @@ void build_ks_tables(ckks_ctx &c) {
                 if (j != k) hat = mulmod_host(hat, p.P[j] % p.q[i], p.q[i]);
             cs[k] = hat;
         }
-        down[i] = conv_entry(0, a, i, cs, p.q[i], p.P);
+        down[i] = conv_entry(0, a, i, cs, p.q[i], p.P, true);
     }
     std::vector<LimbScale> dscale(a);
     for (int k = 0; k < a; ++k) {
@@ -177,7 +183,7 @@ void build_ks_tables(ckks_ctx &c) {
                     if (m != k) hat = mulmod_host(hat, bm[m] % p.q[i], p.q[i]);
                 cs[k] = hat;
             }
-            rconv[j].push_back(conv_entry(0, nb, i, cs, p.q[i], bm));
+            rconv[j].push_back(conv_entry(0, nb, i, cs, p.q[i], bm, true));
         }
         u64 *v = &binv[(size_t)j * 3 * kMaxMods], *sh = v + kMaxMods;
         double *d = reinterpret_cast<double *>(sh + kMaxMods);

@@ -223,10 +223,16 @@ void k_ntt_inverse(const DevTables &t, u64 *buf, int n_limbs, ModMap m, hipStrea
 // r = lam / conv_period; its modulus is chain e.chain and its word is sum_{m < e.nsrc} y_m c_m mod that
 // modulus, y_m = src limb r * src_stride + e.src + m (a residue of another modulus, below 2^47 unless
 // bit m of e.big is set), c_m = e.c[m] (with its Shoup companion and FP64 copy).
+// basis conversion to the modulus `chain`: sum over nsrc consecutive source limbs from `src` of
+// y_m c[m]; big bit m: source m's residues need splitting (modulus >= 2^47); centre: each y_m is first
+// taken as its centred representative, y_m - s_m when y_m > s_m / 2 (half[m] = s_m >> 1, s_m the source
+// modulus; negsq[m] = -s_m mod the target, sqd[m] = s_m as a double)
 struct ConvEntry {
-    int src, nsrc, chain, big;
+    int src, nsrc, chain, big, centre;
     u64 c[kMaxSpecial], c_sh[kMaxSpecial];
     double cd[kMaxSpecial];
+    u64 half[kMaxSpecial], negsq[kMaxSpecial];
+    double sqd[kMaxSpecial];
 };
 struct Gather {
     const u64 *ptr;

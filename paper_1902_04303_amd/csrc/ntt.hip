@@ -327,7 +327,7 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
         // the next 8 words' loads issued before the current 8 are converted (double buffer); FP64 moduli
         // keep the sum as a double (|sum| < 1.1 q per source, below 2^45 for up to kMaxSpecial sources)
         // and store its bits
-        const int ns = ce->nsrc, big = ce->big;
+        const int ns = ce->nsrc, big = ce->big, centre = ce->centre;
         const FMod fm{M.qd, M.qinv};
         if (M.fp) {
             constexpr int H = kPer / 2;
@@ -345,12 +345,16 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
             auto convert = [&](const u64 (&yb)[H], double *xh, int m) {
                 const double w = ce->cd[m];
                 const bool split = (big >> m) & 1;
+                // centred sources (never split): y - s when y > s / 2, |y - s| < 2^41
+                const u64 half = centre ? ce->half[m] : ~0ULL;
+                const double sqd = ce->sqd[m];
 #pragma unroll
                 for (int e = 0; e < H; ++e) {
                     const u64 y = yb[e];
-                    const double a = split ? fred(fmul_mod((double)(unsigned)(y >> 32), M.c32_d, fm) +
-                                                      (double)(unsigned)(y & 0xFFFFFFFFULL), fm)
-                                           : u2d(y);
+                    double a = split ? fred(fmul_mod((double)(unsigned)(y >> 32), M.c32_d, fm) +
+                                                (double)(unsigned)(y & 0xFFFFFFFFULL), fm)
+                                     : u2d(y);
+                    a = y > half ? a - sqd : a;
                     xh[e] += fmul_mod(a, w, fm);
                 }
             };
@@ -369,6 +373,7 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
             for (int m = 0; m < ns; ++m) {
                 const u64 *src = ain + (size_t)m * n + base;
                 const u64 w = ce->c[m], wsh = ce->c_sh[m];
+                const u64 half = centre ? ce->half[m] : ~0ULL, negsq = ce->negsq[m];   // y - s = y + negsq
 #pragma unroll
                 for (int h = 0; h < kPer; h += kPer / 2) {
                     u64 y[kPer / 2];
@@ -376,7 +381,10 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
                     for (int e = 0; e < kPer / 2; ++e)
                         y[e] = src[(size_t)slot_index<LOGM, Ph<LOGM, FIRST>::S0, Ph<LOGM, FIRST>::R>(h + e, q) * stride];
 #pragma unroll
-                    for (int e = 0; e < kPer / 2; ++e) v[h + e] = add_mod(v[h + e], mul_shoup(y[e], w, wsh, qm), qm);
+                    for (int e = 0; e < kPer / 2; ++e) {
+                        const u64 yc = y[e] > half ? y[e] + negsq : y[e];
+                        v[h + e] = add_mod(v[h + e], mul_shoup(yc, w, wsh, qm), qm);
+                    }
                 }
             }
         }

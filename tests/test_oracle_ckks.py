@@ -206,7 +206,7 @@ def test_encrypt_tensor_keyswitch_rescale_match_bigint(tiny_keys):
         want = bc.mul_rescale(_ct_big(a1, p, lev), _ct_big(a2, p, lev), keys, lev)
         assert _ct_big(pr, p, lev - 1) == want, lev
         # against the two divisions taken one after the other (ModDown by P, then the centred rescale by
-        # q_{lev-1}): the one division differs by at most alpha + 2 per coefficient
+        # q_{lev-1}): the one division differs by at most alpha / 2 + 2 per coefficient
         bd = bc.tensor(_ct_big(a1, p, lev), _ct_big(a2, p, lev), lev)
         Ql = bc.Q(lev)
         kd = bc.keyswitch(bd[2], keys, lev)
@@ -214,7 +214,42 @@ def test_encrypt_tensor_keyswitch_rescale_match_bigint(tiny_keys):
         Q1 = Ql // p.q[lev - 1]
         for c in range(2):
             diff = [((w - v + Q1 // 2) % Q1) - Q1 // 2 for w, v in zip(want[c], seq[c])]
-            assert max(abs(x) for x in diff) <= o.alpha + 2, (lev, c)
+            assert max(abs(x) for x in diff) <= o.alpha // 2 + 2, (lev, c)
+
+
+def test_divisions_by_p_are_unbiased():
+    """The centred fast conversions of ModDown and of the product's one division by P q_{l-1}: their
+    rounding errors have mean near 0 over a ring of 2^10 coefficients (uncentred conversions would shift
+    every coefficient by about alpha / 2 and (alpha + 1) / 2 units, which the slots sum coherently), and
+    stay within alpha / 2 + 1 and (alpha + 1) / 2 + 1 of the exactly rounded quotients.  The exact
+    quotients come from Python integers on the same x (CRT of the oracle's residues)."""
+    p = C.make_params(10, 3, 30, 3)
+    alpha = p.alpha
+    rng = np.random.default_rng(12)
+    l = p.L + 1
+    QP = B.BigCKKS(p.N, p.q, p.P)
+    Ql = QP.Q(l)
+    Pm = QP.P
+    mods = list(p.q[:l]) + list(p.P)
+    # x: uniform residues on q_0..q_{l-1}, p_1..p_alpha; add: uniform residues on q_0..q_{l-1}
+    x = np.stack([rng.integers(0, q, size=p.N, dtype=np.uint64) for q in mods])
+    add = np.stack([rng.integers(0, q, size=p.N, dtype=np.uint64) for q in p.q[:l]])
+    xb = B.crt([x[i].tolist() for i in range(len(mods))], mods)
+    ab = B.crt([add[i].tolist() for i in range(l)], p.q[:l])
+    md = QP.moddown(xb, l)
+    exact = [B.centred(v, Ql * Pm) for v in xb]
+    # round(v / P) = floor((2 v + P) / (2 P)) (P odd: no ties)
+    err = [B.centred(int(m) - (2 * v + Pm) // (2 * Pm), Ql) for m, v in zip(md, exact)]
+    assert max(abs(e) for e in err) <= alpha // 2 + 1
+    assert abs(np.mean(err)) < 0.1
+    ql = p.q[l - 1]
+    Bq = Pm * ql
+    mr = QP.moddown_rescale(xb, ab, l)
+    Q1 = Ql // ql
+    xp = [B.centred((v + Pm * a) % (Ql * Pm), Ql * Pm) for v, a in zip(xb, ab)]
+    err2 = [B.centred(int(m) - ((2 * v + Bq) // (2 * Bq)), Q1) for m, v in zip(mr, xp)]
+    assert max(abs(e) for e in err2) <= (alpha + 1) // 2 + 1
+    assert abs(np.mean(err2)) < 0.1
 
 
 def test_rotation_and_grouped_rotation_sum_match_bigint(tiny_keys):
