@@ -623,7 +623,7 @@ class Context:
 
 class GwasGraph:
     def __init__(self, ctx: Context, inp: "GwasInput", chunk: int):
-        self.ctx, self.m = ctx, inp.m
+        self.ctx, self.m, self.h = ctx, inp.m, None
         h = _vp()
         _check(lib().gwas_graph_create(ctx.h, inp.h, chunk, ctypes.byref(h)))
         self.h = h
@@ -681,7 +681,7 @@ class GwasServer:
     """Serving loop of the library (a native worker thread); submit() hands the input over."""
 
     def __init__(self, ctx: Context, hbm_budget: int, max_jobs: int, chunk: int):
-        self.ctx = ctx
+        self.ctx, self.h = ctx, None
         out = _vp()
         _check(lib().gwas_server_create(ctx.h, hbm_budget, max_jobs, chunk, ctypes.byref(out)))
         self.h = out
