@@ -283,14 +283,15 @@ int gwas_output_ct(const gwas_enc_output *out, int which, int index, const ckks_
 
 /* ---- Autotuner.  gwas_tune times every candidate schedule of the circuit on `in` itself (SNP-batch chunks
  * of all batches up to 64, 32, 16 and 8, each with the logistic-regression part on a second stream and
- * on one stream; HIP events around whole calls, best of `reps` after one untimed call) and records the
- * fastest for in's shape (R, k, kappa, number of SNP batches) in the context.  Every candidate computes the
- * same operations on the same ciphertexts: outputs are bit-identical whichever is chosen.  Returns the
- * chosen chunk and stream count, its time, the default schedule's time (all batches, two streams) and the
- * number of candidates.  With ckks_ctx_use_tuned(ctx, 1), gwas_semiparallel runs a recorded schedule for
- * inputs of a tuned shape. */
+ * on one stream, each with the covariates' per-batch products stacked up to 256 ciphertexts and not (see
+ * ckks_ctx_set_stack); HIP events around whole calls, best of `reps` after one untimed call) and records
+ * the fastest for in's shape (R, k, kappa, number of SNP batches) in the context.  Every candidate computes
+ * the same operations on the same ciphertexts: outputs are bit-identical whichever is chosen.  Returns the
+ * chosen chunk, stream count and stack size, its time, the default schedule's time (all batches, two
+ * streams, no stack) and the number of candidates (any output pointer may be NULL).  With
+ * ckks_ctx_use_tuned(ctx, 1), gwas_semiparallel runs a recorded schedule for inputs of a tuned shape. */
 int gwas_tune(ckks_ctx *ctx, const gwas_enc_input *in, int reps, int *chunk, int *streams, double *ms,
-              double *ms_default, int *candidates);
+              double *ms_default, int *candidates, int *stack);
 int ckks_ctx_use_tuned(ckks_ctx *ctx, int enable);
 /* Whether the circuit's outputs keep S' of every SNP batch (default 1).  With 0 the projected batches are
  * dropped once their numerator and denominators are formed (gwas_output_ct(.., 3, ..) then fails), which
@@ -399,6 +400,11 @@ int ckks_ctx_kernel_report(ckks_ctx *ctx, char *buf, size_t cap);
  * that does not depend on it; 1 runs everything in order on the context's stream.
  * Results are identical either way. */
 int ckks_ctx_set_streams(ckks_ctx *ctx, int n);
+/* The per-batch part of the GWAS circuit stacks the products r_j S of its k
+ * covariates into one batch (one set of launches for all of them) while the
+ * stack holds at most n ciphertexts (0, the default: one covariate at a time).
+ * Results are identical either way. */
+int ckks_ctx_set_stack(ckks_ctx *ctx, int n);
 
 /* ---------------------------------------------------------------- batched and serving forms
  * (additions of this library around the paper's algorithm; the arithmetic of each job is unchanged) */

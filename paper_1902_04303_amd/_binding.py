@@ -77,6 +77,7 @@ _SIGS = [
     ("ckks_ctx_kernel_report", ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     ("ckks_ctx_kernel_timing_only", ctypes.c_int, [_vp, ctypes.c_char_p]),
     ("ckks_ctx_set_streams", ctypes.c_int, [_vp, ctypes.c_int]),
+    ("ckks_ctx_set_stack", ctypes.c_int, [_vp, ctypes.c_int]),
     ("ckks_ctx_counters", ctypes.c_int, [_vp, _u64p, _u64p, _u64p]),
     ("ckks_ctx_keyswitch_ciphertexts", ctypes.c_int, [_vp, _u64p]),
     ("ckks_keygen", ctypes.c_int, [_vp, ctypes.c_uint64, _u64p, ctypes.c_int]),
@@ -135,7 +136,7 @@ _SIGS = [
     ("gwas_finalize", ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]),
     ("gwas_div_levels", ctypes.c_int, []),
     ("gwas_tune", ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                                 _dp, _dp, ctypes.POINTER(ctypes.c_int)]),
+                                 _dp, _dp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     ("ckks_ctx_use_tuned", ctypes.c_int, [_vp, ctypes.c_int]),
     ("gwas_keep_projected", ctypes.c_int, [_vp, ctypes.c_int]),
     ("gwas_graph_create", ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(_vp)]),
@@ -363,6 +364,10 @@ class Context:
         overlaps the independent per-batch work on a second stream."""
         _check(lib().ckks_ctx_set_streams(self.h, int(n)))
 
+    def set_stack(self, n: int):
+        """Ciphertexts up to which the per-batch part stacks its covariates' products (0: one at a time)."""
+        _check(lib().ckks_ctx_set_stack(self.h, int(n)))
+
     def kernel_report(self):
         """{kernel: (launches, total_ms, algorithmic_bytes, algorithmic_fp64_ops, pass_bytes)} from the
         HIP-event timing ("keyswitch": whole key switches, when selected with kernel_timing_only)."""
@@ -555,12 +560,13 @@ class Context:
         return GwasServer(self, hbm_budget, max_jobs, chunk)
 
     def gwas_tune(self, inp: "GwasInput", reps: int = 2):
-        """Time the bit-identical schedules (chunk, streams) on inp and record the fastest for its shape."""
-        ch, st, cand = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        """Time the bit-identical schedules (chunk, streams, stack) on inp and record the fastest for its shape."""
+        ch, st, cand, stk = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         ms, ms0 = ctypes.c_double(), ctypes.c_double()
         _check(lib().gwas_tune(self.h, inp.h, reps, ctypes.byref(ch), ctypes.byref(st), ctypes.byref(ms),
-                               ctypes.byref(ms0), ctypes.byref(cand)))
-        return dict(chunk=ch.value, streams=st.value, ms=ms.value, ms_default=ms0.value, candidates=cand.value)
+                               ctypes.byref(ms0), ctypes.byref(cand), ctypes.byref(stk)))
+        return dict(chunk=ch.value, streams=st.value, stack=stk.value, ms=ms.value, ms_default=ms0.value,
+                    candidates=cand.value)
 
     def keep_projected(self, keep: bool):
         """Whether outputs keep S' of every SNP batch (default True)."""

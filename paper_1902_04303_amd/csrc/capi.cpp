@@ -473,6 +473,13 @@ int ckks_ctx_set_streams(ckks_ctx *ctx, int n) {
     });
 }
 
+int ckks_ctx_set_stack(ckks_ctx *ctx, int n) {
+    return guard_ctx(ctx, [&] {
+        need(ctx && n >= 0, "stack size must be 0 or more");
+        ctx->stack_cts = n;
+    });
+}
+
 int ckks_ctx_kernel_report(ckks_ctx *ctx, char *buf, size_t cap) {
     return guard_ctx(ctx, [&] {
         need(ctx && buf && cap > 0, "bad buffer");
@@ -915,10 +922,12 @@ int gwas_semiparallel(ckks_ctx *ctx, const gwas_enc_input *in, gwas_enc_output *
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         auto it = ctx->tuned.find(schedule_key(*in->in));
         if (it != ctx->tuned.end()) {
-            const int saved = ctx->n_streams;
+            const int saved = ctx->n_streams, saved_stack = ctx->stack_cts;
             ctx->n_streams = it->second.streams;
+            ctx->stack_cts = it->second.stack;
             const int rc = gwas_semiparallel_chunked(ctx, in, it->second.chunk, out);
             ctx->n_streams = saved;
+            ctx->stack_cts = saved_stack;
             return rc;
         }
     }
@@ -926,7 +935,7 @@ int gwas_semiparallel(ckks_ctx *ctx, const gwas_enc_input *in, gwas_enc_output *
 }
 
 int gwas_tune(ckks_ctx *ctx, const gwas_enc_input *in, int reps, int *chunk, int *streams, double *ms,
-              double *ms_default, int *candidates) {
+              double *ms_default, int *candidates, int *stack) {
     return guard_ctx(ctx, [&] {
         need(in && in->ctx == ctx, "bad arguments");
         const TuneResult r = tune_circuit(*ctx, *in->in, reps);
@@ -935,6 +944,7 @@ int gwas_tune(ckks_ctx *ctx, const gwas_enc_input *in, int reps, int *chunk, int
         if (ms) *ms = r.best.ms;
         if (ms_default) *ms_default = r.ms_default;
         if (candidates) *candidates = r.candidates;
+        if (stack) *stack = r.best.stack;
     });
 }
 

@@ -592,6 +592,39 @@ Ct relin_rescale(ckks_ctx &c, DBuf d, int count, int depth, int l, double sa, do
     return r;
 }
 
+// the products a_i * b_i of several pairs (each relinearised and rescaled, as mul) as consecutive
+// ciphertexts of one batch: pair i gives max(a_i.count, b_i.count) ciphertexts.  One tensor launch per pair
+// and one key switch for the whole batch; every pair at one depth and one product scale.
+Ct mul_stack(ckks_ctx &c, const std::vector<std::pair<const ckks_ct *, const ckks_ct *>> &pairs) {
+    if (pairs.empty()) throw Error(CKKS_E_INVALID_ARG, "empty product stack");
+    const ckks_ct &a0 = *pairs[0].first, &b0 = *pairs[0].second;
+    const double s = a0.scale * b0.scale;
+    int total = 0;
+    std::vector<int> cnt;
+    for (auto &pr : pairs) {
+        if (pr.first->depth != a0.depth || pr.second->depth != a0.depth)
+            throw Error(CKKS_E_PARAM_MISMATCH, "product operands at different depths");
+        if (pr.first->scale * pr.second->scale != s)
+            throw Error(CKKS_E_PARAM_MISMATCH, "stacked products with different scales");
+        const int n = std::max(pr.first->count, pr.second->count);
+        if (n % pr.first->count != 0 || n % pr.second->count != 0)
+            throw Error(CKKS_E_PARAM_MISMATCH, "batch counts differ");
+        cnt.push_back(n);
+        total += n;
+    }
+    const int l = a0.limbs;
+    const size_t N = (size_t)c.p.n;
+    DBuf d(c.pool.get(), (size_t)total * 3 * l * N);
+    size_t off = 0;
+    for (size_t i = 0; i < pairs.size(); ++i) {
+        k_tensor(c.tab, d.ptr + off, pairs[i].first->data.ptr, pairs[i].second->data.ptr, cnt[i], l,
+                 pairs[i].first->count, pairs[i].second->count, false, c.stream);
+        ++c.n_launch;
+        off += (size_t)cnt[i] * 3 * l * N;
+    }
+    return relin_rescale(c, std::move(d), total, a0.depth, l, a0.scale, b0.scale);
+}
+
 // sum_i cols_i (x) rep_{b, i} for every batch b (CP-REP-MatMult of the M-materialised layout): one
 // tensor-sum launch, one relinearisation and one rescale for the chunk
 Ct mul_sum_rep(ckks_ctx &c, const ckks_ct &cols, const ckks_ct &rep) {

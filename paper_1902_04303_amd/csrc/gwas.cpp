@@ -334,18 +334,28 @@ void run_fixed(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckk
 
 // ---------------------------------------------------------------- per-batch part
 
-// S' = S - sum_j x_j E_j with E_j = bcast_R(mask(colSum(r_j S))): needs only r_j and x_j of the fixed part
+// S' = S - sum_j x_j E_j with E_j = bcast_R(mask(colSum(r_j S))): needs only r_j and x_j of the fixed part.
+// The products r_j S of several covariates run as one stacked batch through colSum, the mask and bcast while
+// the stack holds at most c.stack_cts ciphertexts (every key switch then reads its keys once for all of
+// them); the same operations on each ciphertext, so the results are those of one covariate at a time.
 Ct batch_front(ckks_ctx &c, int R, int k, const FixedOut &fx, const ckks_ct &S) {
     Layout lay;
     lay.R = R;
     lay.k = k;
     Circ C(c, lay, kBatchRadix);
-    std::vector<Ct> E(k);
-    for (int j = 0; j < k; ++j) {
-        Ct pj = mul(c, *fx.r_s[j], S);
-        Ct cj = C.rot_sum(std::move(pj));     // column sums at block starts (Alg. colSum)
-        cj = mul_mask(c, *cj, R);             // keep the block starts
-        E[j] = C.bcast(std::move(cj));        // (A X^T S)_{j, c} over block c
+    const int cnt = S.count;
+    const int per = std::max(1, std::min(k, c.stack_cts / std::max(1, cnt)));   // covariates per stack
+    std::vector<Ct> stacks, E(k);
+    for (int j0 = 0; j0 < k; j0 += per) {
+        const int j1 = std::min(k, j0 + per);
+        std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pp;
+        for (int j = j0; j < j1; ++j) pp.push_back({fx.r_s[j].get(), &S});
+        Ct P = mul_stack(c, pp);
+        P = C.rot_sum(std::move(P));          // column sums at block starts (Alg. colSum)
+        P = mul_mask(c, *P, R);               // keep the block starts
+        P = C.bcast(std::move(P));            // (A X^T S)_{j, c} over block c
+        for (int j = j0; j < j1; ++j) E[j] = view(*P, (j - j0) * cnt, cnt);
+        stacks.push_back(std::move(P));       // owns the views' memory until the sum below
     }
     std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pe;
     for (int j = 0; j < k; ++j) pe.push_back({fx.x_c[j].get(), E[j].get()});
@@ -998,15 +1008,16 @@ std::tuple<int, int, int, int> schedule_key(const EncInput &in) {
 
 // Times every candidate schedule on the job itself (HIP events on the context's stream around whole calls,
 // after one untimed call per candidate) and keeps the fastest for the job's shape.  Candidates: SNP-batch
-// chunks of all batches (at most 64), 32, 16 and 8, each on two streams and on one; every one computes
-// the same operations on the same ciphertexts, so the outputs are bit-identical (tested).
+// chunks of all batches (at most 64), 32, 16 and 8, each on two streams and on one, each with the
+// covariates' products stacked (up to 256 ciphertexts) and not; every one computes the same operations on
+// the same ciphertexts, so the outputs are bit-identical (tested).
 TuneResult tune_circuit(ckks_ctx &c, const EncInput &in, int reps) {
     if (c.timer.on) throw Error(CKKS_E_INVALID_ARG, "kernel timing is on");
     const int nb = in.S->count;
     std::vector<int> chunks;
     for (int ch : {std::min(64, nb), 32, 16, 8})
         if (ch >= 1 && ch <= nb && std::find(chunks.begin(), chunks.end(), ch) == chunks.end()) chunks.push_back(ch);
-    const int saved_streams = c.n_streams;
+    const int saved_streams = c.n_streams, saved_stack = c.stack_cts;
     hipEvent_t e0, e1;
     GCK_HIP(hipEventCreate(&e0));
     GCK_HIP(hipEventCreate(&e1));
@@ -1014,34 +1025,38 @@ TuneResult tune_circuit(ckks_ctx &c, const EncInput &in, int reps) {
     res.best.ms = 1e300;
     try {
         for (int streams : {2, 1})
-            for (int ch : chunks) {
-                c.n_streams = streams;
-                {
-                    EncOutput warm;
-                    run_circuit(c, in, warm, ch);
+            for (int ch : chunks)
+                for (int stack : {0, 256}) {
+                    c.n_streams = streams;
+                    c.stack_cts = stack;
+                    {
+                        EncOutput warm;
+                        run_circuit(c, in, warm, ch);
+                    }
+                    double best = 1e300;
+                    for (int r = 0; r < std::max(1, reps); ++r) {
+                        EncOutput o;
+                        GCK_HIP(hipEventRecord(e0, c.stream));
+                        run_circuit(c, in, o, ch);
+                        GCK_HIP(hipEventRecord(e1, c.stream));
+                        GCK_HIP(hipEventSynchronize(e1));
+                        float ms = 0;
+                        GCK_HIP(hipEventElapsedTime(&ms, e0, e1));
+                        best = std::min(best, (double)ms);
+                    }
+                    ++res.candidates;
+                    if (streams == 2 && ch == chunks[0] && stack == 0) res.ms_default = best;
+                    if (best < res.best.ms) res.best = ckks_ctx::Schedule{ch, streams, stack, best};
                 }
-                double best = 1e300;
-                for (int r = 0; r < std::max(1, reps); ++r) {
-                    EncOutput o;
-                    GCK_HIP(hipEventRecord(e0, c.stream));
-                    run_circuit(c, in, o, ch);
-                    GCK_HIP(hipEventRecord(e1, c.stream));
-                    GCK_HIP(hipEventSynchronize(e1));
-                    float ms = 0;
-                    GCK_HIP(hipEventElapsedTime(&ms, e0, e1));
-                    best = std::min(best, (double)ms);
-                }
-                ++res.candidates;
-                if (streams == 2 && ch == chunks[0]) res.ms_default = best;
-                if (best < res.best.ms) res.best = ckks_ctx::Schedule{ch, streams, best};
-            }
     } catch (...) {
         c.n_streams = saved_streams;
+        c.stack_cts = saved_stack;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         throw;
     }
     c.n_streams = saved_streams;
+    c.stack_cts = saved_stack;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c.tuned[schedule_key(in)] = res.best;

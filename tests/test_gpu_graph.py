@@ -124,8 +124,8 @@ def test_graph_at_dataset_shape(torch_dev):
 
 
 def test_tuner_schedules_are_bit_identical(torch_dev):
-    """The autotuner's candidates (chunks of all, 32, 16, 8 SNP batches; one or two streams) all give the
-    oracle's ciphertexts, and so does the schedule it records."""
+    """The autotuner's candidates (chunks of all, 32, 16, 8 SNP batches; one or two streams; the covariates'
+    products stacked or not) all give the oracle's ciphertexts, and so does the schedule it records."""
     n, k, m, kappa, log_n, b = 30, 4, 700, 3, 10, 30
     say("[gpu] tuner n=%d m=%d" % (n, m))
     p = C.make_params(log_n, G.circuit_depth(kappa), b)
@@ -150,12 +150,15 @@ def test_tuner_schedules_are_bit_identical(torch_dev):
 
     t = ctx.gwas_tune(gin, 1)
     say("[gpu] tuner: %s" % t)
-    assert t["candidates"] == 6 and t["chunk"] in (22, 16, 8) and t["streams"] in (1, 2)
+    assert t["candidates"] == 12 and t["chunk"] in (22, 16, 8) and t["streams"] in (1, 2) and t["stack"] in (0, 256)
     for streams in (2, 1):
         ctx.set_streams(streams)
-        for ch in (22, 16, 8):
-            check(ctx.gwas_semiparallel(gin, ch), ch)
+        for stack in (0, 256, 40):
+            ctx.set_stack(stack)
+            for ch in (22, 16, 8):
+                check(ctx.gwas_semiparallel(gin, ch), ch)
     ctx.set_streams(2)
+    ctx.set_stack(0)
     ctx.use_tuned(True)
     check(ctx.gwas_semiparallel(gin), t["chunk"])
     ctx.close()
