@@ -412,8 +412,9 @@ int ckks_ctx_set_stack(ckks_ctx *ctx, int n);
 /* Several jobs in one call.  Jobs with the same block size R, covariate count k and kappa share every
  * launch of the fixed part (one batch ciphertext per job) and their SNP batches run through the
  * per-batch part together, `chunk` ciphertexts per launch, each with its own job's values.  A job with
- * at least chunk / 2 SNP batches, or with the M-materialised layout, runs alone as gwas_semiparallel
- * runs it (all its batches in one pass when resident and no pool budget is set, else `chunk` at a time).
+ * at least chunk / 2 SNP batches, or with the M-materialised layout, runs alone, max(chunk, 256) SNP
+ * batches per pass when resident and no pool budget is set (every job's outputs stay resident until the
+ * call returns, so the passes' transient buffers are bounded), else `chunk` at a time.
  * out[i] receives job i's output (bucketed jobs: one batch per output kind, index 0).  Results are
  * bit-identical to running each job alone. */
 int gwas_semiparallel_multi(ckks_ctx *ctx, const gwas_enc_input *const *in, int n_jobs, int chunk,

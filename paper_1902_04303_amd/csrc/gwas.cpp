@@ -690,15 +690,17 @@ void run_multi(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std::vect
     outs.clear();
     outs.resize(jobs.size());
     // A job with at least half a chunk of SNP batches fills the device with its own launches: it runs as a
-    // single job, as a call for it alone would run it (all its batches in one pass when it is resident and
-    // no pool budget is set, else `chunk` at a time; its logistic-regression part on the second stream,
-    // beside its own SNP batches).  The smaller jobs are bucketed by shape and share the fixed-part
-    // launches and the SNP-batch chunks (an input with the M-materialised layout always runs as a single
-    // job).
+    // single job (its logistic-regression part on the second stream, beside its own SNP batches), in chunks
+    // of kMultiChunk batches or `chunk` if larger when it is resident and no pool budget is set (every job's
+    // outputs stay resident here, so a chunk's transient buffers are bounded), else `chunk` at a time.  The
+    // smaller jobs are bucketed by shape and share the fixed-part launches and the SNP-batch chunks (an
+    // input with the M-materialised layout always runs as a single job).
     std::map<std::tuple<int, int, int>, std::vector<int>> buckets;
     for (size_t i = 0; i < jobs.size(); ++i) {
         if (2 * jobs[i]->S->count >= chunk || jobs[i]->S_rep) {
-            const int own = (!jobs[i]->S_host && c.pool->budget == 0) ? std::max(chunk, jobs[i]->S->count) : chunk;
+            const int own = (!jobs[i]->S_host && c.pool->budget == 0)
+                                ? std::min(jobs[i]->S->count, std::max(chunk, kMultiChunk))
+                                : chunk;
             outs[i].chunk = own;
             run_circuit(c, *jobs[i], outs[i], own);
             continue;

@@ -87,6 +87,9 @@ void run_fixed(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckk
 BatchOut run_batch(ckks_ctx &c, int R, int k, const FixedOut &fx, const ckks_ct &S);
 void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk);
 void run_multi(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std::vector<EncOutput> &outs, int chunk);
+// SNP batches per pass of a large job in the batched form (its transient key-switch buffers, about 20 MB per
+// batch at the per-batch part's levels, stay near 5 GB)
+constexpr int kMultiChunk = 256;
 constexpr size_t kMaxFixedJobs = 8;   // jobs whose fixed parts run as one batch in run_multi
 // building blocks shared with the server
 struct WorkItem {
