@@ -529,15 +529,16 @@ def measured_traffic(kernel: str):
 
 
 def measured_valu(kernel: str):
-    """VALU issue of `kernel` from the committed SQ counter run (SQ_INSTS_VALU over its busy CU cycles:
-    wave64 VALU instructions per CU per cycle, the limit being 1), or None (no record, or the device
-    sources changed since)."""
+    """VALU issue of `kernel` from the committed SQ counter run (SQ_INSTS_VALU per launch over 256 CUs times
+    the launch's cycles at 2.4 GHz in the kernel trace: wave64 VALU instructions per CU per cycle, the limit
+    being 1), or None (no record, or the device sources changed since)."""
     rec = _counter_record()
     k = (rec or {}).get("valu", {}).get(kernel)
     if k is None:
         return None
     return {"valu_insts_per_cu_cycle": k["valu_insts_per_cu_cycle"], "frac": k["valu_insts_per_cu_cycle"],
-            "source": "replayed from profiles/hbm_traffic.json (rocprofv3 SQ_INSTS_VALU, SQ_BUSY_CU_CYCLES)"}
+            "source": "replayed from profiles/hbm_traffic.json (rocprofv3 SQ_INSTS_VALU over 256 CUs x the launch's "
+                      "cycles at 2.4 GHz in the kernel trace)"}
 
 
 def roofline(kernels, warm, steps):
