@@ -125,6 +125,28 @@ def test_multi_job_matches_oracle(ctx, oracle_jobs, singles):
             same(outputs(ctx, o, nb(q)), singles[q])
 
 
+def test_back_to_back_calls_match_oracle(ctx, oracle_jobs, singles):
+    """Calls issued back to back without synchronisation: outputs dropped as soon as the next call returns
+    (their blocks go back to both streams' pools while earlier calls may still run), an input imported
+    between two calls, and every kept output compared with the oracle after one final synchronisation."""
+    import torch
+    say("[gpu] back-to-back calls")
+    order = [0, 2, 4, 1, 3, 0, 4, 2]
+    ins = {q: pack(ctx, oracle_jobs, q) for q in (0, 2, 4)}
+    kept = []
+    out = None
+    for i, q in enumerate(order):
+        if q not in ins:
+            ins[q] = pack(ctx, oracle_jobs, q)   # imported between calls, no synchronisation
+        out = ctx.gwas_semiparallel(ins[q])     # the previous output (unless kept) is freed here
+        if i % 3 == 2:
+            kept.append((q, out))
+    kept.append((order[-1], out))
+    torch.cuda.synchronize()
+    for q, o in kept:
+        same(outputs(ctx, o, nb(q)), singles[q])
+
+
 def test_one_and_two_streams_agree(ctx, oracle_jobs, singles):
     """The circuit with the logistic-regression part on a second stream (the default) and in order on one
     stream give the oracle's ciphertexts."""
