@@ -97,19 +97,23 @@ def test_full_size_circuit_bit_exact_against_oracle_digests(torch_dev, name):
     assert [digest(ctx.export(c)) for c in S] == ins["S"]
     say("[gpu] %s: circuit (%d SNP batches)" % (name, lay.n_batches))
     gin = ctx.gwas_input_from_cts(n, k, m, kappa, x, y, A, S)
-    out = ctx.gwas_semiparallel(gin)
     outs = rec["outputs"]
-    assert [digest(ctx.export(out.ct(P.GwasOutput.BETA, j))) for j in range(k)] == outs["beta"]
-    for which, key in ((P.GwasOutput.W, "w"), (P.GwasOutput.W_INV, "w_inv"), (P.GwasOutput.Z_PROJ, "z_proj"),
-                       (P.GwasOutput.U, "u")):
-        assert digest(ctx.export(out.ct(which))) == outs[key], key
     nb = lay.n_batches
-    assert out.ct(P.GwasOutput.NUM, 0).count == nb   # every SNP batch in one chunk of launches
-    for which, key in ((P.GwasOutput.S_PROJ, "S_proj"), (P.GwasOutput.NUM, "num"),
-                       (P.GwasOutput.DEN_EVEN, "den_even"), (P.GwasOutput.DEN_ODD, "den_odd")):
-        ct = out.ct(which, 0)
-        got = [digest(ctx.export(ct, b)) for b in range(nb)]
-        bad = [b for b in range(nb) if got[b] != outs[key][b]]
-        assert not bad, (key, bad)
-    say("[gpu] %s: %d output ciphertexts bit-exact" % (name, k + 4 + 4 * nb))
+    # the launch configuration the benchmark times, then the covariates' products stacked into one batch
+    for stack in (0, 256):
+        ctx.set_stack(stack)
+        out = ctx.gwas_semiparallel(gin)
+        assert [digest(ctx.export(out.ct(P.GwasOutput.BETA, j))) for j in range(k)] == outs["beta"]
+        for which, key in ((P.GwasOutput.W, "w"), (P.GwasOutput.W_INV, "w_inv"), (P.GwasOutput.Z_PROJ, "z_proj"),
+                           (P.GwasOutput.U, "u")):
+            assert digest(ctx.export(out.ct(which))) == outs[key], key
+        assert out.ct(P.GwasOutput.NUM, 0).count == nb   # every SNP batch in one chunk of launches
+        for which, key in ((P.GwasOutput.S_PROJ, "S_proj"), (P.GwasOutput.NUM, "num"),
+                           (P.GwasOutput.DEN_EVEN, "den_even"), (P.GwasOutput.DEN_ODD, "den_odd")):
+            ct = out.ct(which, 0)
+            got = [digest(ctx.export(ct, b)) for b in range(nb)]
+            bad = [b for b in range(nb) if got[b] != outs[key][b]]
+            assert not bad, (key, stack, bad)
+        say("[gpu] %s: stack %d, %d output ciphertexts bit-exact" % (name, stack, k + 4 + 4 * nb))
+    ctx.set_stack(0)
     ctx.close()
