@@ -278,7 +278,11 @@ int gwas_semiparallel_chunked(ckks_ctx *ctx, const gwas_enc_input *in, int chunk
  * index = chunk number, each a batch of up to `chunk` ciphertexts in SNP-batch order;
  * 4 beta_j (index j), 5 w, 6 w^-1 (CKKS_E_INVALID_ARG for kappa = 1, where both are public), 7 z',
  * 8 u = w z', 9 b' and 10 err' after gwas_divide, 11 the n columns Dup(M_i) of the M-materialised layout
- * (at the SNP depth + 2).  The handle stays owned by out. */
+ * (at the SNP depth + 2).  The handle stays owned by out.  The denominators of the even and the odd SNPs
+ * are the real parts of den_even and den_odd at the block starts; both come from one rotate-and-sum of
+ * W = 4 w (a^2 + i b^2) (S' = a + i b per slot), den_even = sum W / 4 and den_odd = -i den_even (the
+ * factor -i as the exact plaintext product with -X^(N/2)), so each carries the other's in its imaginary
+ * part. */
 int gwas_output_ct(const gwas_enc_output *out, int which, int index, const ckks_ct **ct);
 
 /* ---- Autotuner.  gwas_tune times every candidate schedule of the circuit on `in` itself (SNP-batch chunks
@@ -346,12 +350,12 @@ int gwas_div_levels(void);
  * (an upper bound of den_j since w <= 1/4 and S' = M S is the shortest residual of S_j after projecting
  * out X, whose first column is the intercept; 0 for a constant SNP), one ciphertext per SNP batch and
  * parity: a batch of 2 n_batches ciphertexts, the even SNPs of every batch, then the odd, at depth L_c and
- * scale Delta_{L_c} / (2 f), f = 2 (or 8 for kappa = 1) the factor of the denominators' tracked scale.
+ * scale Delta_{L_c} / (2 f), f = 4 (or 16 for kappa = 1) the factor of the denominators' tracked scale.
  * Ciphertext i is encrypted with seed output_{2^20 + i}(SplitMix64(enc_seed)).  S as in gwas_pack_encrypt. */
 int gwas_pack_normalisers(ckks_ctx *ctx, const uint8_t *S, int n, int m, int kappa, uint64_t enc_seed,
                           ckks_ct **out);
-/* Server side: x = Re(den) v (the real part (den + conj(den)) / 2, since the packed denominators carry
- * cross terms in their imaginary parts), g_1 = 2 - x, then g <- g (2 - x g) four times (the pattern of
+/* Server side: x = Re(den) v (the real part (den + conj(den)) / 2, since a denominator carries the other
+ * parity's denominator in its imaginary part), g_1 = 2 - x, then g <- g (2 - x g) four times (the pattern of
  * Alg. inverseSlots), err' = g v and b' = num err', per chunk of SNP batches, stored in `out` (which = 9
  * b', 10 err' of gwas_output_ct, index = chunk: 2 cnt ciphertexts, the even SNPs' then the odd SNPs'; b'
  * of an even SNP is the real part, of an odd SNP the imaginary part).  Needs the conjugation key.  The

@@ -323,24 +323,31 @@ class Circuit:
         return (sp,) + self.num_den(sp, fx)
 
     def num_den(self, sp: C.Ct, fx: "FixedPart"):
-        """numerator and both denominators of a projected batch S' (Alg. Semi Parallel GWAS)."""
+        """numerator and both denominators of a projected batch S' (Alg. Semi Parallel GWAS).  With
+        S' = a + i b per slot (the even SNP in a, the odd one in b) the denominators are sum w a^2 and
+        sum w b^2.  Both come from one rotate-and-sum of W = 4 w (a^2 + i b^2), formed from
+        P = 2 w S' conj(S') = 2 w (a^2 + b^2) and R = w S'^2 + conj(w S'^2) = 2 w (a^2 - b^2):
+        W = (P + R) + i (P - R), the factor i by mul_i; den_even = sum W / 4 and den_odd = -i sum W / 4,
+        whose real parts are the two denominators (reading 20)."""
         o = self.o
         dsp = sp.depth
         num = self.rot_sum(o.mul(self.at(fx.u, dsp), sp), BATCH_RADIX)
+        sc = o.conjugate(sp)
         if fx.w is None:
-            # public w = 1/4: den_even / den_odd = (S' conj(S') +- S' S') / 8, the 1/8 in the tracked scale
-            sc = o.conjugate(sp)
+            # public w = 1/4: the products without w, the 1/4 in the tracked scale
             ss = o.mul(sp, sp)
             ssc = o.mul(sp, sc)
-            de = self.rot_sum(o.set_scale(o.add(ssc, ss), 2.0 / W_KAPPA1), BATCH_RADIX)
-            do = self.rot_sum(o.set_scale(o.sub(ssc, ss), 2.0 / W_KAPPA1), BATCH_RADIX)
-            return num, de, do
-        ws = o.mul(self.at(fx.w, dsp), sp)
-        sc = o.conjugate(sp)
-        wss = o.mul(ws, self.at(sp, ws.depth))
-        wsc = o.mul(ws, self.at(sc, ws.depth))
-        de = self.rot_sum(o.set_scale(o.add(wsc, wss), 2.0), BATCH_RADIX)
-        do = self.rot_sum(o.set_scale(o.sub(wsc, wss), 2.0), BATCH_RADIX)
+            factor = 4.0 / W_KAPPA1
+        else:
+            ws = o.mul(self.at(fx.w, dsp), sp)
+            ss = o.mul(ws, self.at(sp, ws.depth))
+            ssc = o.mul(ws, self.at(sc, ws.depth))
+            factor = 4.0
+        p2 = o.mul_int(ssc, 2)
+        r2 = o.add(ss, o.conjugate(ss))
+        w4 = o.add(o.add(p2, r2), o.mul_i(o.sub(p2, r2)))
+        de = self.rot_sum(o.set_scale(w4, factor), BATCH_RADIX)
+        do = o.mul_i(de, neg=True)
         return num, de, do
 
     # ---- the M-materialised layout (paper: Alg. CP-REP-MatMult; the walk-through of Alg. Semi Parallel
@@ -529,7 +536,7 @@ assert DIV_GUESS == 1.0                 # the first Newton step is then 2 - x, w
 
 def den_scale_factor(kappa: int) -> float:
     """The factor by which a denominator's tracked scale exceeds the canonical scale of its depth."""
-    return 2.0 / W_KAPPA1 if kappa == 1 else 2.0
+    return 4.0 / W_KAPPA1 if kappa == 1 else 4.0
 
 
 def normaliser_scale(params: C.Params, kappa: int) -> float:

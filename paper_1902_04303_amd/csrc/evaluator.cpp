@@ -413,6 +413,51 @@ Ct mul_mask(ckks_ctx &c, const ckks_ct &a, int R) {
     return r;
 }
 
+// a + b X^(N/2) over l limbs in NTT form, kept in the context like the masks.  Slot j of a plaintext is its
+// value at zeta^(5^j) with zeta = exp(i pi / N); X^(N/2) takes the value zeta^(5^j N / 2) = i there because
+// 5^j = 1 mod 4, so a product with this polynomial multiplies every slot by a + b i with no rounding.
+static const u64 *monomial_plain(ckks_ctx &c, int l, i64 a, i64 b) {
+    const auto key = std::make_tuple(l, a, b);
+    auto it = c.mono_cache.find(key);
+    if (it != c.mono_cache.end()) return it->second.ptr;
+    const int n = c.p.n;
+    std::vector<i64> h(n, 0);
+    h[0] = a;
+    h[n / 2] = b;
+    DBuf small(c.pool.get(), (size_t)n);
+    GCK_HIP(hipMemcpyAsync(small.ptr, h.data(), (size_t)n * 8, hipMemcpyHostToDevice, c.stream));
+    DBuf pt(c.pool.get(), (size_t)l * n);
+    k_signed_to_limbs(c.tab, pt.ptr, reinterpret_cast<const i64 *>(small.ptr), l, map_q(l), c.stream);
+    ntt_fwd(c, pt.ptr, l, map_q(l));
+    sync(c);   // the host vector goes out of scope; the entry is complete for every stream
+    const u64 *p = pt.ptr;
+    c.mono_cache.emplace(key, std::move(pt));
+    return p;
+}
+
+Ct mul_i(ckks_ctx &c, const ckks_ct &a, bool neg) {
+    const int l = a.limbs;
+    const u64 *pt = monomial_plain(c, l, 0, neg ? -1 : 1);
+    Ct r = new_ct(c, a.count, a.depth, a.scale);
+    k_mul(c.tab, r->data.ptr, a.data.ptr, pt, a.count * 2 * l, map_q(l), a.count * 2 * l, l, c.stream);
+    ++c.n_launch;
+    return r;
+}
+
+Ct pack_den(ckks_ctx &c, const ckks_ct &p, const ckks_ct &s, const ckks_ct &t) {
+    check_same(p, s);
+    check_same(p, t);
+    if (p.count != s.count || p.count != t.count) throw Error(CKKS_E_PARAM_MISMATCH, "operands of unequal counts");
+    const int l = p.limbs;
+    const u64 *pa = monomial_plain(c, l, 2, 2);
+    const u64 *pb = monomial_plain(c, l, 1, -1);
+    Ct r = new_ct(c, p.count, p.depth, p.scale);
+    k_mul_plain2(c.tab, r->data.ptr, p.data.ptr, s.data.ptr, t.data.ptr, pa, pb, p.count * 2 * l, map_q(l), l,
+                 c.stream);
+    ++c.n_launch;
+    return r;
+}
+
 Ct align(ckks_ctx &c, const ckks_ct &a, int depth, double scale, double factor) {
     if (depth == a.depth && scale == a.scale && factor == 1.0) return clone(c, a);
     if (depth <= a.depth) throw Error(CKKS_E_LEVEL, "align needs a deeper target depth");
@@ -974,6 +1019,7 @@ ckks_ctx::~ckks_ctx() {
     else hipDeviceSynchronize();
     if (aux_stream) hipStreamSynchronize(aux_stream);
     mask_cache.clear();   // entries may come from either pool
+    mono_cache.clear();
     aux_pool.reset();
     ksk.clear();   // every pool-backed member goes back to the pool before the pool is destroyed
     sk_ntt.release();

@@ -85,6 +85,8 @@ struct ckks_ctx {
     bool keep_s_proj = true;   // the circuit's outputs include S' of every SNP batch
     // block-start masks in NTT form by (R, limbs, scale bits), made once and then only read
     std::map<std::tuple<int, int, uint64_t>, gck::DBuf> mask_cache;
+    // the plaintexts a + b X^(N/2) in NTT form by (limbs, a, b), made once and then only read
+    std::map<std::tuple<int, int64_t, int64_t>, gck::DBuf> mono_cache;
     ~ckks_ctx();
 };
 
@@ -122,6 +124,10 @@ Ct rescale(ckks_ctx &c, const ckks_ct &a);
 Ct mod_drop(ckks_ctx &c, const ckks_ct &a, int depth);
 Ct mul_const(ckks_ctx &c, const ckks_ct &a, double v);
 Ct mul_mask(ckks_ctx &c, const ckks_ct &a, int R);
+// a times X^(N/2) (neg: -X^(N/2)): every slot times i (or -i), exact, same depth and scale
+Ct mul_i(ckks_ctx &c, const ckks_ct &a, bool neg);
+// (2 + 2i) p + (1 - i) (s + t) with the factors i as X^(N/2): exact, same depth and scale
+Ct pack_den(ckks_ctx &c, const ckks_ct &p, const ckks_ct &s, const ckks_ct &t);
 Ct align(ckks_ctx &c, const ckks_ct &a, int depth, double scale, double factor);
 Ct set_scale(ckks_ctx &c, Ct a, double factor);
 // sum_i a_i * b_i: one tensor per pair accumulated, one relinearisation, one rescale

@@ -378,21 +378,25 @@ BatchOut batch_back(ckks_ctx &c, int R, int k, const FixedOut &fx, Ct sp) {
     BatchOut o;
     o.sp = std::move(sp);
     o.num = C.rot_sum(mul(c, *fx.u_s, *o.sp));
-    if (!fx.w_s) {
-        // kappa = 1, public w = 1/4: (S' conj(S') +- S' S') / 8, the 1/8 in the tracked scale
-        Ct sc = conjugate(c, *o.sp);
-        Ct ss = mul(c, *o.sp, *o.sp);
-        Ct ssc = mul(c, *o.sp, *sc);
-        o.de = C.rot_sum(set_scale(c, add(c, *ssc, *ss), 2.0 / kWKappa1));
-        o.dodd = C.rot_sum(set_scale(c, sub(c, *ssc, *ss), 2.0 / kWKappa1));
-        return o;
-    }
-    Ct ws = mul(c, *fx.w_s, *o.sp);
+    // with S' = a + i b per slot (even SNP a, odd SNP b) both denominators come from one rotate-and-sum of
+    // W = 4 w (a^2 + i b^2) = (2 + 2i) w S' conj(S') + (1 - i) (w S'^2 + conj(w S'^2)); den_even = sum W / 4
+    // and den_odd = -i sum W / 4 have the two denominators as their real parts
     Ct sc = conjugate(c, *o.sp);
-    Ct wss = mul(c, *ws, *C.at(*o.sp, ws->depth));
-    Ct wsc = mul(c, *ws, *C.at(*sc, ws->depth));
-    o.de = C.rot_sum(set_scale(c, add(c, *wsc, *wss), 2.0));
-    o.dodd = C.rot_sum(set_scale(c, sub(c, *wsc, *wss), 2.0));
+    Ct ss, ssc;
+    double f;
+    if (!fx.w_s) {
+        // kappa = 1, public w = 1/4: the products without w, the 1/4 in the tracked scale
+        ss = mul(c, *o.sp, *o.sp);
+        ssc = mul(c, *o.sp, *sc);
+        f = 4.0 / kWKappa1;
+    } else {
+        Ct ws = mul(c, *fx.w_s, *o.sp);
+        ss = mul(c, *ws, *C.at(*o.sp, ws->depth));
+        ssc = mul(c, *ws, *C.at(*sc, ws->depth));
+        f = 4.0;
+    }
+    o.de = C.rot_sum(set_scale(c, pack_den(c, *ssc, *ss, *conjugate(c, *ss)), f));
+    o.dodd = mul_i(c, *o.de, true);
     return o;
 }
 
@@ -875,13 +879,13 @@ std::unique_ptr<EncInput> pack_encrypt(ckks_ctx &c, const double *X, const doubl
 // bound of den_j: w <= 1/4 and S' = M S is the shortest residual of S_j after projecting out X, whose
 // first column is the intercept) at the block start of SNP j, 0 elsewhere and for SNPs with d_j = 0.
 // One ciphertext per SNP batch and parity (even SNPs of all batches, then odd), at the denominators'
-// depth and at scale Delta / (2 f), f the factor of the denominators' tracked scale (2, or 8 for
+// depth and at scale Delta / (2 f), f the factor of the denominators' tracked scale (4, or 16 for
 // kappa = 1), so that Re(den) v lands on the canonical scale.
 Ct pack_normalisers(ckks_ctx &c, const uint8_t *S, int n, int m, int kappa, u64 enc_seed) {
     const Layout lay = make_layout(c.p.n, n, 1, m);
     const int dd = circuit_levels(kappa);
     if (c.p.levels < dd) throw Error(CKKS_E_LEVEL, "chain shorter than the circuit");
-    const double f = kappa == 1 ? 2.0 / kWKappa1 : 2.0;
+    const double f = kappa == 1 ? 4.0 / kWKappa1 : 4.0;
     const double sc = c.p.scales[dd] / (2.0 * f);
     std::vector<double> inv_d(m, 0.0);
     for (int j = 0; j < m; ++j) {

@@ -352,6 +352,40 @@ def test_rotation_conjugation_and_mult_semantics():
     assert np.max(np.abs(o.decrypt(mk) - zm)) < tol
 
 
+def test_mul_i_is_the_exact_monomial_shift():
+    """mul_i multiplies by X^(N/2): the decryption polynomial is shifted negacyclically by N/2 with no
+    rounding, and every slot (the value at zeta^(5^j), zeta = exp(i pi / N)) is multiplied by i; with
+    neg by -i.  The packed denominators (2 + 2i) P + (1 - i) R then carry 4 w (a^2 + i b^2)."""
+    p = C.make_params(10, 2, 30)
+    o = C.Oracle(p)
+    o.keygen(3, [C.galois_conj(p.N)])
+    rng = np.random.default_rng(21)
+    z = rng.standard_normal(p.slots) + 1j * rng.standard_normal(p.slots)
+    ct = o.encrypt(C.encode(z, p.N, p.scales[0]), 0, p.scales[0], 4)
+    h = p.N // 2
+    m0 = o.decrypt_poly(ct)
+    for neg, unit in ((False, 1j), (True, -1j)):
+        r = o.mul_i(ct, neg)
+        assert r.depth == ct.depth and r.scale == ct.scale
+        m1 = o.decrypt_poly(r)
+        sgn = -1 if neg else 1
+        # X^(N/2) m(X) mod X^N + 1: coefficient t moves to t + N/2, wrapping with a sign change
+        assert all(m1[t + h] == sgn * m0[t] and m1[t] == -sgn * m0[t + h] for t in range(h))
+        assert np.max(np.abs(o.decrypt(r) - unit * z)) < 1e-4
+    # mul_i twice is the negation, bit for bit
+    assert np.array_equal(o.mul_i(o.mul_i(ct)).data, o.neg(ct).data)
+    # the packing of two real squares into one complex slot
+    a = rng.uniform(-1, 1, p.slots)
+    b = rng.uniform(-1, 1, p.slots)
+    cs = o.encrypt(C.encode(a + 1j * b, p.N, p.scales[0]), 0, p.scales[0], 5)
+    ss = o.mul(cs, cs)
+    ssc = o.mul(cs, o.conjugate(cs))
+    p2 = o.mul_int(ssc, 2)
+    r2 = o.add(ss, o.conjugate(ss))
+    w4 = o.add(o.add(p2, r2), o.mul_i(o.sub(p2, r2)))
+    assert np.max(np.abs(o.decrypt(w4) - 4 * (a * a + 1j * b * b))) < 1e-3
+
+
 # ------------------------------------------------------------------ values printed in the paper
 
 def _golden():
