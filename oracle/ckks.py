@@ -647,6 +647,23 @@ class Oracle:
         r.scale = (a.scale * a.scale) / float(q)
         return r
 
+    def mask_sum(self, terms: Sequence[Tuple[Ct, np.ndarray]]) -> Ct:
+        """sum_i a_i pt_i for integer plaintext polynomials pt_i (masks already encoded at the operands'
+        common scale s), then one rescale by q; the result scale is (s * s) / q, as for mul_mask."""
+        a0 = terms[0][0]
+        q = self.p.q_dropped_at_depth(a0.depth)
+        acc = None
+        for a, pt in terms:
+            self._check_same(a, a0)
+            out = np.empty_like(a.data)
+            lib().ref_mul_plain(self._ctx, 2, a.limbs, _p(a.data), _p(np.ascontiguousarray(pt, dtype=np.int64)),
+                                _p(out))
+            t = Ct(out, a.depth, a.scale)
+            acc = t if acc is None else self.add(acc, t)
+        r = self.rescale(acc)
+        r.scale = (a0.scale * a0.scale) / float(q)
+        return r
+
     def align(self, a: Ct, depth: int, scale: float, factor: float = 1.0) -> Ct:
         """Bring a to (depth, scale), multiplying its value by `factor`: mod-drop to depth-1,
         multiply by the integer round_half_away(((scale * factor) * q) / a.scale), rescale by q,

@@ -226,6 +226,34 @@ def rotation_groups(R: int, radix: int = FIXED_RADIX) -> List[List[int]]:
     return out
 
 
+def diag_width(lay: Layout) -> int:
+    """K of the packed projection (reading 21), or 0 where it does not apply: K is the smallest power of two
+    >= k for k >= 2; it must divide m = min(BATCH_RADIX, R), the size of the first rotation group, and
+    n + K - 1 <= R must hold, so that the rows which the products and the stride sums wrap onto are padding
+    rows (zero in x_j, r_j and S)."""
+    k, R = lay.k, lay.R
+    if k < 2:
+        return 0
+    K = 1
+    while K < k:
+        K *= 2
+    m = min(BATCH_RADIX, R)
+    if K > m or m % K or lay.n + K - 1 > R:
+        return 0
+    return K
+
+
+def stride_groups(R: int, K: int, radix: int = BATCH_RADIX) -> List[List[int]]:
+    """The left rotations of sum_{u < R/K} Rot(a, K u), grouped by shared key switch: the multiples of K in
+    the first group of rotation_groups(R, radix) (dropped when there are none), then its other groups
+    unchanged.  Since sum_{j < m} X^j factors into the groups of rotation_groups, keeping only the multiples
+    of K in the first factor (K divides its size m) leaves the sum over the multiples of K below R.  Every
+    rotation is one of rotation_groups(R, radix), so no other key is needed."""
+    g = rotation_groups(R, radix)
+    head = [r for r in g[0] if r % K == 0]
+    return ([head] if head else []) + g[1:]
+
+
 def required_galois(N: int, R: int) -> List[int]:
     """Galois elements of the left and right rotations of rotation_groups(R, FIXED_RADIX) and
     rotation_groups(R, BATCH_RADIX), each once in first-seen order, then conjugation."""
@@ -245,11 +273,14 @@ def required_galois(N: int, R: int) -> List[int]:
 @dataclass
 class FixedPart:
     """What the per-batch part needs from the fixed part: x_j, r_j = (X A)_{:, j}, w and u = w z'
-    (w is None when it is the public 1/4 of kappa = 1)."""
+    (w is None when it is the public 1/4 of kappa = 1); for the packed projection (reading 21) the
+    diagonals Rot(Z_t, -t) at the SNP depth and X_t at the SNP depth + 2, t < K (else None)."""
     x: List[C.Ct]
     rr: List[C.Ct]
     w: Optional[C.Ct]
     u: C.Ct
+    zt: Optional[List[C.Ct]] = None
+    xt: Optional[List[C.Ct]] = None
 
 
 @dataclass
@@ -306,8 +337,50 @@ class Circuit:
         cc = o.add(self.at(a1, d + 3), b)
         return o.add_const(o.mul(self.at(u, d + 3), cc), 0.5)
 
+    def diagonals(self, inp: EncInput, rr: List[C.Ct], ds: int, K: int):
+        """The packed projection's diagonals (reading 21): with comb_c the mask of the slots s = c mod K,
+        Z_t = sum_j comb_{(j - t) mod K} r_j and X_t = sum_j comb_{(j - t) mod K} x_j (slot s of block row r
+        holds r_{(r + t) mod K}[r], or 0 where (r + t) mod K >= k), each one mask_sum; Z_t is brought to the
+        SNP depth ds and rotated right by t, X_t brought to ds + 2."""
+        o = self.o
+        N = self.lay.N
+        k = self.lay.k
+        zt, xt = [], []
+        for t in range(K):
+            z = o.mask_sum([(rr[j], C.slot_class_indicator_poly(N, K, (j - t) % K, rr[j].scale)) for j in range(k)])
+            z = self.at(z, ds)
+            zt.append(o.rotate(z, -t) if t else z)
+            xm = o.mask_sum([(inp.x[j], C.slot_class_indicator_poly(N, K, (j - t) % K, inp.x[j].scale))
+                             for j in range(k)])
+            xt.append(self.at(xm, ds + 2))
+        return zt, xt
+
+    def project_diag(self, S: C.Ct, fx: "FixedPart") -> C.Ct:
+        """S' = S - sum_j x_j (.) E_j by the packed projection (reading 21):
+        D = sum_t Rot(Z_t, -t) (.) Rot(S, -t) = sum_t Rot(Z_t (.) S, -t) (one lazily summed product),
+        W = sum_{u < R/K} Rot(D, K u), whose slot j < k of each block is C_j = colSum(r_j (.) S),
+        Mk = W times the mask of the first k slots of each block,
+        V = sum_{u < R/K} Rot(Mk, -K u), which holds C_{r mod K} at block row r,
+        x E = sum_t X_t (.) Rot(V, t) (one lazily summed product)."""
+        o = self.o
+        lay = self.lay
+        K = len(fx.zt)
+        pairs = [(fx.zt[0], S)] + [(fx.zt[t], o.rotate(S, -t)) for t in range(1, K)]
+        w = o.mul_sum(pairs)
+        for grp in stride_groups(lay.R, K):
+            w = o.rotate_sum(w, grp)
+        mk = o.mask_sum([(w, sum(C.slot_class_indicator_poly(lay.N, lay.R, j, w.scale) for j in range(lay.k)))])
+        v = mk
+        for grp in stride_groups(lay.R, K):
+            v = o.rotate_sum(v, [-r for r in grp])
+        xe = o.mul_sum([(fx.xt[0], v)] + [(fx.xt[t], o.rotate(v, t)) for t in range(1, K)])
+        return o.sub(self.at(S, xe.depth), xe)
+
     def run_batch(self, S: C.Ct, fx: "FixedPart"):
         """Per-batch part (Alg. Semi Parallel GWAS, batch loop): S' = M S, num, denEven, denOdd."""
+        if fx.zt is not None:
+            sp = self.project_diag(S, fx)
+            return (sp,) + self.num_den(sp, fx)
         o = self.o
         k = self.lay.k
         ds = S.depth
@@ -383,6 +456,14 @@ class Circuit:
         xv = o.mul_sum([(self.at(x[j], dv), v[j]) for j in range(k)])
         return o.sub(self.at(z, xv.depth), xv)
 
+    def _fixed(self, inp: EncInput, w: Optional[C.Ct], u: C.Ct) -> FixedPart:
+        rr = self._xa(inp)
+        fx = FixedPart(x=inp.x, rr=rr, w=w, u=u)
+        K = diag_width(self.lay)
+        if K and self.m_in is None:
+            fx.zt, fx.xt = self.diagonals(inp, rr, snp_depth(inp.kappa), K)
+        return fx
+
     def _xa(self, inp: EncInput) -> List[C.Ct]:
         """r_j = (X A)_{:, j} = sum_l A_jl x_l for the projection of the SNP batches."""
         k = self.lay.k
@@ -422,7 +503,7 @@ class Circuit:
         z = o.add(xb, self.at(r, xb.depth, W_INV_KAPPA1))
         z_proj = self._project_z(inp, z)
         u = self.at(z_proj, snp_depth(1) + 3, W_KAPPA1)
-        fixed = FixedPart(x=inp.x, rr=self._xa(inp), w=None, u=u)
+        fixed = self._fixed(inp, None, u)
         return self._batches(inp, fixed, beta, None, None, z_proj, u)
 
     def run(self, inp: EncInput) -> EncOutput:
@@ -465,7 +546,7 @@ class Circuit:
         # ---- z' = M z = z - X (A (X^T z)), u = w z'
         z_proj = self._project_z(inp, z)
         u = o.mul(self.at(w, z_proj.depth), z_proj)
-        fixed = FixedPart(x=x, rr=self._xa(inp), w=w, u=u)
+        fixed = self._fixed(inp, w, u)
         return self._batches(inp, fixed, beta, w, w_inv, z_proj, u)
 
 

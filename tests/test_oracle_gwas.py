@@ -314,3 +314,78 @@ def test_m_materialised_layout_on_oracle(kappa):
     ref = F.modified_gwas(d.X, d.y, d.S, kappa)
     ok = ref.den > 1e-9 * np.max(ref.den)
     assert np.max(np.abs(bb - ref.b)[ok] / np.maximum(np.abs(ref.b), ref.se)[ok]) < 1e-4
+
+
+def test_stride_groups_sum_the_multiples_of_k():
+    """The stride sums of the packed projection: the rotations of stride_groups(R, K), one shared key
+    switch per group, reach every multiple of K below R exactly once (brute force over the products
+    of the groups' exponent sets), and every rotation is one of the per-batch rotate-and-sum's."""
+    for R in (2, 8, 32, 256, 2048):
+        full = {r for grp in G.rotation_groups(R, G.BATCH_RADIX) for r in grp}
+        for K in (1, 2, 4, 8, 16):
+            if K > min(G.BATCH_RADIX, R):
+                continue
+            sums = [0]
+            for grp in G.stride_groups(R, K):
+                sums = [s + r for s in sums for r in [0] + grp]
+            assert sorted(sums) == list(range(0, R, K)), (R, K)
+            assert all(r in full for grp in G.stride_groups(R, K) for r in grp)
+
+
+def test_diag_width_conditions():
+    lay = lambda n, k, R: G.Layout(N=2 * R, n=n, k=k, m=1, R=R)   # noqa: E731
+    assert G.diag_width(lay(245, 4, 256)) == 4
+    assert G.diag_width(lay(253, 4, 256)) == 4 and G.diag_width(lay(254, 4, 256)) == 0   # n + K - 1 <= R
+    assert G.diag_width(lay(245, 3, 256)) == 4 and G.diag_width(lay(245, 5, 256)) == 8
+    assert G.diag_width(lay(200, 16, 256)) == 16 and G.diag_width(lay(200, 17, 256)) == 0   # K <= 16
+    assert G.diag_width(lay(245, 1, 256)) == 0                                             # k = 1
+    assert G.diag_width(lay(5, 4, 8)) == 4 and G.diag_width(lay(5, 5, 8)) == 0             # K <= R
+
+
+@pytest.mark.parametrize("kappa,k", [(3, 4), (2, 3), (1, 2)])
+def test_packed_projection_on_oracle(kappa, k):
+    """The packed projection (reading 21, n = 24 <= R - K + 1 at R = 32): the diagonals decode to
+    Z_t[r] = r_{(r + t) mod K}[r] (rotated right by t) and X_t[r] = x_{(r + t) mod K}[r]; S' decrypts to the
+    FP64 M S of every batch and to the S' of the M-materialised layout (Alg. CP-REP-MatMult, computed
+    without any stride sum); b' matches the FP64 GWAS."""
+    n, m = 24, 70
+    p = C.make_params(10, G.circuit_depth(kappa), 40)
+    d = make_gwas_data(n, k, m, seed=79)
+    lay = G.make_layout(p.N, n, k, m)
+    K = G.diag_width(lay)
+    assert K == (4 if k > 2 else 2) and lay.R == 32 and m % lay.tau != 0
+    o = C.Oracle(p)
+    o.keygen(7, G.required_galois(p.N, lay.R))
+    inp = G.encrypt_inputs(o, G.encode_inputs(p, d.X, d.y, d.S, kappa), n, k, m, kappa, 11)
+    circ = G.Circuit(o, lay)
+    out = circ.run(inp)
+    # the diagonals, from the same r_j and x_j as the circuit
+    rr = circ._xa(inp)
+    zt, xt = circ.diagonals(inp, rr, G.snp_depth(kappa), K)
+    A = F.xtx_inverse(d.X)
+    XA = d.X @ A
+    rows = np.arange(lay.N // 2) % lay.R
+    for t in range(K):
+        want_z = np.zeros(lay.N // 2)
+        want_x = np.zeros(lay.N // 2)
+        for s in range(lay.N // 2):
+            r = rows[s]
+            j = (r + t) % K
+            if r < n and j < k:
+                want_z[s] = XA[r, j]
+                want_x[s] = d.X[r, j]
+        assert np.max(np.abs(o.decrypt(zt[t]) - np.roll(want_z, t))) < 1e-6
+        assert np.max(np.abs(o.decrypt(xt[t]) - want_x)) < 1e-6
+    M = np.eye(n) - d.X @ A @ d.X.T
+    MS = M @ d.S.astype(np.float64)
+    mi = G.encrypt_inputs_m(o, G.encode_inputs_m(p, d.X, d.S, kappa), n, k, 11)
+    out_m = G.Circuit(o, lay, mi).run(inp)
+    for b in range(lay.n_batches):
+        got = o.decrypt(out.S_proj[b])
+        assert np.max(np.abs(got - G.snp_batch_slots(MS, lay, b))) < 1e-6
+        assert out_m.S_proj[b].depth == out.S_proj[b].depth
+        assert np.max(np.abs(got - o.decrypt(out_m.S_proj[b]))) < 1e-6
+    num, den, bb, err, se = G.finalize(o, lay, out)
+    ref = F.modified_gwas(d.X, d.y, d.S, kappa)
+    ok = ref.den > 1e-9 * np.max(ref.den)
+    assert np.max(np.abs(bb - ref.b)[ok] / np.maximum(np.abs(ref.b), ref.se)[ok]) < 1e-4
