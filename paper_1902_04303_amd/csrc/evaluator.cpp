@@ -379,17 +379,31 @@ Ct mul_const(ckks_ctx &c, const ckks_ct &a, double v) {
     return r;
 }
 
-// the mask at a's scale in NTT form over l limbs: encoded once per (R, l, scale) and kept in the context;
-// a new entry is completed (stream synchronised) before it is used, so any stream may read it later
-static const u64 *mask_plain(ckks_ctx &c, int R, int l, double scale) {
+// 1 at the slots s = j mod P for j0 <= j < j1 at `scale`, in NTT form over l limbs: the sum over j of the
+// block-start mask of period P moved by the automorphism X -> X^(5^-j) of a right rotation by j (a signed
+// permutation of its integer coefficients, so the encoding stays exact).  Made once per (P, j0, j1, l,
+// scale) and kept in the context; a new entry is completed (stream synchronised) before it is used, so any
+// stream may read it later
+static const u64 *class_mask_plain(ckks_ctx &c, int P, int j0, int j1, int l, double scale) {
     uint64_t bits;
     std::memcpy(&bits, &scale, sizeof bits);
-    const auto key = std::make_tuple(R, l, bits);
+    const auto key = std::make_tuple(P, j0, j1, l, bits);
     auto it = c.mask_cache.find(key);
     if (it != c.mask_cache.end()) return it->second.ptr;
     const int n = c.p.n;
-    std::vector<i64> h(n);
-    mask_poly(n, R, scale, h.data());
+    if (j0 < 0 || j1 <= j0 || j1 > P) throw Error(CKKS_E_INVALID_ARG, "slot classes out of range");
+    std::vector<i64> m0(n), h(n, 0);
+    mask_poly(n, P, scale, m0.data());
+    const u64 two_n = 2ULL * (u64)n;
+    for (int j = j0; j < j1; ++j) {
+        const u64 g = galois_rotate_n(n, -j);
+        for (int i = 0; i < n; ++i) {
+            if (!m0[i]) continue;
+            const u64 e = ((u64)i * g) % two_n;
+            if (e < (u64)n) h[e] += m0[i];
+            else h[e - n] -= m0[i];
+        }
+    }
     DBuf small(c.pool.get(), (size_t)n);
     GCK_HIP(hipMemcpyAsync(small.ptr, h.data(), (size_t)n * 8, hipMemcpyHostToDevice, c.stream));
     DBuf pt(c.pool.get(), (size_t)l * n);
@@ -399,6 +413,35 @@ static const u64 *mask_plain(ckks_ctx &c, int R, int l, double scale) {
     const u64 *p = pt.ptr;
     c.mask_cache.emplace(key, std::move(pt));
     return p;
+}
+
+static const u64 *mask_plain(ckks_ctx &c, int R, int l, double scale) { return class_mask_plain(c, R, 0, 1, l, scale); }
+
+Ct mask_sum(ckks_ctx &c, const std::vector<MaskTerm> &terms) {
+    if (terms.empty()) throw Error(CKKS_E_INVALID_ARG, "empty mask sum");
+    const ckks_ct &a0 = *terms[0].a;
+    const u64 q = c.p.dropped_at(a0.depth);
+    const int l = a0.limbs, rows = a0.count * 2 * l;
+    Ct acc = new_ct(c, a0.count, a0.depth, a0.scale);
+    Ct tmp;
+    for (size_t i = 0; i < terms.size(); ++i) {
+        const MaskTerm &m = terms[i];
+        check_same(*m.a, a0);
+        if (m.a->count != a0.count) throw Error(CKKS_E_PARAM_MISMATCH, "mask sum operands of unequal counts");
+        const u64 *pt = class_mask_plain(c, m.P, m.j0, m.j1, l, a0.scale);
+        if (i == 0) {
+            k_mul(c.tab, acc->data.ptr, m.a->data.ptr, pt, rows, map_q(l), rows, l, c.stream);
+        } else {
+            if (!tmp) tmp = new_ct(c, a0.count, a0.depth, a0.scale);
+            k_mul(c.tab, tmp->data.ptr, m.a->data.ptr, pt, rows, map_q(l), rows, l, c.stream);
+            k_add(c.tab, acc->data.ptr, acc->data.ptr, tmp->data.ptr, rows, map_q(l), rows, rows, c.stream);
+            ++c.n_launch;
+        }
+        ++c.n_launch;
+    }
+    Ct r = rescale(c, *acc);
+    r->scale = (a0.scale * a0.scale) / (double)q;
+    return r;
 }
 
 Ct mul_mask(ckks_ctx &c, const ckks_ct &a, int R) {

@@ -83,8 +83,9 @@ struct ckks_ctx {
     std::map<std::tuple<int, int, int, int>, Schedule> tuned;
     bool use_tuned = false;
     bool keep_s_proj = true;   // the circuit's outputs include S' of every SNP batch
-    // block-start masks in NTT form by (R, limbs, scale bits), made once and then only read
-    std::map<std::tuple<int, int, uint64_t>, gck::DBuf> mask_cache;
+    // slot-class masks in NTT form by (period, first class, end class, limbs, scale bits), made once and
+    // then only read
+    std::map<std::tuple<int, int, int, int, uint64_t>, gck::DBuf> mask_cache;
     // the plaintexts a + b X^(N/2) in NTT form by (limbs, a, b), made once and then only read
     std::map<std::tuple<int, int64_t, int64_t>, gck::DBuf> mono_cache;
     ~ckks_ctx();
@@ -124,6 +125,13 @@ Ct rescale(ckks_ctx &c, const ckks_ct &a);
 Ct mod_drop(ckks_ctx &c, const ckks_ct &a, int depth);
 Ct mul_const(ckks_ctx &c, const ckks_ct &a, double v);
 Ct mul_mask(ckks_ctx &c, const ckks_ct &a, int R);
+// sum_i a_i * m_i, m_i the exact mask of 1 at the slots s = j mod P_i for j0_i <= j < j1_i encoded at the
+// operands' common scale s, then one rescale; the result scale is (s * s) / q (as mul_mask)
+struct MaskTerm {
+    const ckks_ct *a;
+    int P, j0, j1;
+};
+Ct mask_sum(ckks_ctx &c, const std::vector<MaskTerm> &terms);
 // a times X^(N/2) (neg: -X^(N/2)): every slot times i (or -i), exact, same depth and scale
 Ct mul_i(ckks_ctx &c, const ckks_ct &a, bool neg);
 // (2 + 2i) p + (1 - i) (s + t) with the factors i as X^(N/2): exact, same depth and scale

@@ -66,6 +66,27 @@ std::vector<std::vector<i64>> rotation_groups(int R, int radix) {
     return out;
 }
 
+int diag_width(const Layout &lay) {
+    if (lay.k < 2) return 0;
+    int K = 1;
+    while (K < lay.k) K *= 2;
+    const int m = std::min(kBatchRadix, lay.R);
+    if (K > m || m % K || lay.n + K - 1 > lay.R) return 0;
+    return K;
+}
+
+std::vector<std::vector<i64>> stride_groups(int R, int K, int radix) {
+    const auto g = rotation_groups(R, radix);
+    std::vector<std::vector<i64>> out;
+    if (g.empty()) return out;
+    std::vector<i64> head;
+    for (i64 r : g[0])
+        if (r % K == 0) head.push_back(r);
+    if (!head.empty()) out.push_back(head);
+    for (size_t i = 1; i < g.size(); ++i) out.push_back(g[i]);
+    return out;
+}
+
 std::vector<u64> required_galois(int n, int R) {
     std::vector<u64> g;
     auto put = [&](u64 e) {
@@ -216,7 +237,7 @@ struct Stacked {
 }  // namespace
 
 void fixed_front(ckks_ctx &c, int R, int k, const std::vector<const ckks_ct *> &x, const std::vector<const ckks_ct *> &Ain,
-                 int ds, FixedOut &fx, const StackIn *pre = nullptr, const ckks_ct *xrep = nullptr,
+                 int ds, FixedOut &fx, int K, const StackIn *pre = nullptr, const ckks_ct *xrep = nullptr,
                  EncOutput *rep = nullptr) {
     Stacked st(c, R, k, x, Ain, pre);
     const int J = st.J;
@@ -252,6 +273,26 @@ void fixed_front(ckks_ctx &c, int R, int k, const std::vector<const ckks_ct *> &
     for (int j = 0; j < k; ++j) {
         fx.r_s[j] = view(*RRs, j * J, J);
         fx.x_c[j] = view(*Xc, j * J, J);
+    }
+    if (K) {
+        // packed projection: Z_t = sum_j comb_{(j - t) mod K} r_j and X_t = sum_j comb_{(j - t) mod K} x_j
+        // (comb_c: the slots s = c mod K), block row r of Z_t holding r_{(r + t) mod K}[r]; Z_t at the SNP
+        // depth, rotated right by t, X_t at the SNP depth + 2
+        fx.K = K;
+        const std::vector<Ct> rj = st.parts(*RR), xj = st.parts(st.Xs);
+        for (int t = 0; t < K; ++t) {
+            std::vector<MaskTerm> tz, tx;
+            for (int j = 0; j < k; ++j) {
+                const int cls = ((j - t) % K + K) % K;
+                tz.push_back({rj[j].get(), K, cls, cls + 1});
+                tx.push_back({xj[j].get(), K, cls, cls + 1});
+            }
+            Ct zm = mask_sum(c, tz), xm = mask_sum(c, tx);
+            if (zm->depth >= ds || xm->depth >= ds + 2) throw Error(CKKS_E_LEVEL, "diagonals too deep");
+            Ct z = st.C.at(*zm, ds);
+            fx.z_d.push_back(t ? rotate(c, *z, -t) : std::move(z));
+            fx.x_d.push_back(st.C.at(*xm, ds + 2));
+        }
     }
     // RRs may be a view of RR (at() does not copy)
     fx.hold.push_back(std::move(RRs));
@@ -327,8 +368,8 @@ void fixed_back(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ck
 }
 
 void run_fixed(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckks_ct *> &x, const ckks_ct &y,
-               const std::vector<const ckks_ct *> &Ain, int ds, FixedOut &fx, EncOutput &rep) {
-    fixed_front(c, R, k, x, Ain, ds, fx);
+               const std::vector<const ckks_ct *> &Ain, int ds, FixedOut &fx, EncOutput &rep, int K) {
+    fixed_front(c, R, k, x, Ain, ds, fx, K);
     fixed_back(c, R, k, kappa, x, y, Ain, ds, fx, rep);
 }
 
@@ -343,6 +384,37 @@ Ct batch_front(ckks_ctx &c, int R, int k, const FixedOut &fx, const ckks_ct &S) 
     lay.R = R;
     lay.k = k;
     Circ C(c, lay, kBatchRadix);
+    if (fx.K) {
+        // packed projection: D = sum_t Rot(Z_t, -t) Rot(S, -t) (one lazy product sum); W = sum_{u < R/K}
+        // Rot(D, K u) holds C_j = colSum(r_j S) at slot j < k of each block; the mask of the first k slots;
+        // V = sum_{u < R/K} Rot(., -K u) holds C_{r mod K} at block row r; x E = sum_t X_t Rot(V, t)
+        const int K = fx.K;
+        const auto groups = stride_groups(R, K, kBatchRadix);
+        std::vector<Ct> rs(K);
+        std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pd{{fx.z_d[0].get(), &S}};
+        for (int t = 1; t < K; ++t) {
+            rs[t] = rotate(c, S, -t);
+            pd.push_back({fx.z_d[t].get(), rs[t].get()});
+        }
+        Ct w = mul_sum(c, pd);
+        rs.clear();
+        for (const auto &grp : groups) w = rotate_sum(c, *w, grp);
+        Ct v = mask_sum(c, {{w.get(), R, 0, k}});
+        w.reset();
+        for (const auto &grp : groups) {
+            std::vector<i64> neg;
+            for (i64 r : grp) neg.push_back(-r);
+            v = rotate_sum(c, *v, neg);
+        }
+        std::vector<Ct> rv(K);
+        std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pe{{fx.x_d[0].get(), v.get()}};
+        for (int t = 1; t < K; ++t) {
+            rv[t] = rotate(c, *v, t);
+            pe.push_back({fx.x_d[t].get(), rv[t].get()});
+        }
+        Ct xe = mul_sum(c, pe);
+        return sub(c, *C.at(S, xe->depth), *xe);
+    }
     const int cnt = S.count;
     const int per = std::max(1, std::min(k, c.stack_cts / std::max(1, cnt)));   // covariates per stack
     std::vector<Ct> stacks, E(k);
@@ -459,7 +531,7 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
             OnStream on_aux(c);
             fixed_back(c, lay.R, k, in.kappa, x, *in.y, A, ds, fx, out, &sin);
         }
-        fixed_front(c, lay.R, k, x, A, ds, fx, &sin, in.Xrep.get(), &out);
+        fixed_front(c, lay.R, k, x, A, ds, fx, in.S_rep ? 0 : diag_width(lay), &sin, in.Xrep.get(), &out);
         std::vector<Ct> sps;
         for (int b0 = 0; b0 < nb; b0 += chunk) {
             const int cnt = std::min(chunk, nb - b0);
@@ -488,7 +560,7 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
     }
     if (in.S_rep) {
         // M-materialised layout on one stream (or under a pool budget): device-resident REP rows only
-        fixed_front(c, lay.R, k, x, A, ds, fx, nullptr, in.Xrep.get(), &out);
+        fixed_front(c, lay.R, k, x, A, ds, fx, 0, nullptr, in.Xrep.get(), &out);
         fixed_back(c, lay.R, k, in.kappa, x, *in.y, A, ds, fx, out);
         for (int b0 = 0; b0 < nb; b0 += chunk) {
             const int cnt = std::min(chunk, nb - b0);
@@ -501,7 +573,7 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
         }
         return;
     }
-    run_fixed(c, lay.R, k, in.kappa, x, *in.y, A, ds, fx, out);
+    run_fixed(c, lay.R, k, in.kappa, x, *in.y, A, ds, fx, out, diag_width(lay));
     if (!in.S_host) {
         for (int b0 = 0; b0 < nb; b0 += chunk) {
             const int cnt = std::min(chunk, nb - b0);
@@ -553,7 +625,7 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
 
 // b' = num / den and err' = 1 / den as ciphertexts (an extension: the paper decrypts num and den and
 // divides on the client).  Per chunk, the even and the odd denominators are stacked into one batch; the
-// real part of each (its imaginary parts are cross terms of the complex packing) times the client's
+// real part of each (its imaginary part holds the other parity's denominator) times the client's
 // normaliser 1 / d_j gives x in (0, 1], whose reciprocal is taken by Newton steps from guess 1 (the
 // pattern of Alg. inverseSlots: g_1 = 2 - x, then g <- g (2 - x g)); err' = g / d_j and b' = num err'
 // (num read cyclically: its real part pairs with the even half, its imaginary part with the odd half).
@@ -597,15 +669,19 @@ void run_divide(ckks_ctx &c, EncOutput &out, const ckks_ct &v) {
 
 // ---------------------------------------------------------------- several jobs
 
-std::tuple<int, int, int> bucket_of(const EncInput &in) { return std::make_tuple(in.lay.R, in.lay.k, in.kappa); }
+std::tuple<int, int, int, int> bucket_of(const EncInput &in) {
+    return std::make_tuple(in.lay.R, in.lay.k, in.kappa, diag_width(in.lay));
+}
 
 // Fixed parts of several jobs with one shape (R, k, kappa): one launch sequence over a batch of one
 // ciphertext per job; the results are split back into one FixedOut (batches of one) per job.
 void fixed_for_jobs(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std::vector<FixedOut> &fxs,
                     std::vector<EncOutput> &reps) {
     const EncInput &j0 = *jobs[0];
-    const int R = j0.lay.R, k = j0.lay.k, kappa = j0.kappa, J = (int)jobs.size();
+    const int R = j0.lay.R, k = j0.lay.k, kappa = j0.kappa, J = (int)jobs.size(), K = diag_width(j0.lay);
     if (c.p.levels < circuit_levels(kappa)) throw Error(CKKS_E_LEVEL, "chain too short for kappa");
+    for (auto *in : jobs)
+        if (bucket_of(*in) != bucket_of(j0)) throw Error(CKKS_E_PARAM_MISMATCH, "jobs of different shapes");
     check_keys(c, R);
     std::vector<Ct> xs(k), As(k * (k + 1) / 2);
     for (int j = 0; j < k; ++j) {
@@ -626,7 +702,7 @@ void fixed_for_jobs(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std:
     for (auto &p : As) Ap.push_back(p.get());
     FixedOut fx;
     EncOutput rep;
-    run_fixed(c, R, k, kappa, xp, *ys, Ap, snp_depth(kappa), fx, rep);
+    run_fixed(c, R, k, kappa, xp, *ys, Ap, snp_depth(kappa), fx, rep, K);
     fxs.clear();
     fxs.resize(J);
     reps.clear();
@@ -635,6 +711,9 @@ void fixed_for_jobs(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std:
         FixedOut &f = fxs[q];
         for (int j = 0; j < k; ++j) f.r_s.push_back(gather(c, {{fx.r_s[j].get(), q}}));
         for (int j = 0; j < k; ++j) f.x_c.push_back(gather(c, {{fx.x_c[j].get(), q}}));
+        f.K = fx.K;
+        for (auto &z : fx.z_d) f.z_d.push_back(gather(c, {{z.get(), q}}));
+        for (auto &xd : fx.x_d) f.x_d.push_back(gather(c, {{xd.get(), q}}));
         f.u_s = gather(c, {{fx.u_s.get(), q}});
         if (fx.w_s) f.w_s = gather(c, {{fx.w_s.get(), q}});
         EncOutput &o = reps[q];
@@ -666,6 +745,13 @@ void chunk_for_jobs(ckks_ctx &c, const std::vector<WorkItem> &items) {
     FixedOut fc;
     for (int j = 0; j < k; ++j) fc.r_s.push_back(per_item([&](const FixedOut &f) { return f.r_s[j].get(); }));
     for (int j = 0; j < k; ++j) fc.x_c.push_back(per_item([&](const FixedOut &f) { return f.x_c[j].get(); }));
+    fc.K = items[0].fx->K;
+    for (const WorkItem &w : items)
+        if (w.fx->K != fc.K) throw Error(CKKS_E_PARAM_MISMATCH, "SNP batches of different projection widths");
+    for (int t = 0; t < fc.K; ++t) {
+        fc.z_d.push_back(per_item([&](const FixedOut &f) { return f.z_d[t].get(); }));
+        fc.x_d.push_back(per_item([&](const FixedOut &f) { return f.x_d[t].get(); }));
+    }
     fc.u_s = per_item([](const FixedOut &f) { return f.u_s.get(); });
     if (items[0].fx->w_s) fc.w_s = per_item([](const FixedOut &f) { return f.w_s.get(); });
     BatchOut bo = run_batch(c, R, k, fc, *S);
@@ -699,7 +785,7 @@ void run_multi(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std::vect
     // outputs stay resident here, so a chunk's transient buffers are bounded), else `chunk` at a time.  The
     // smaller jobs are bucketed by shape and share the fixed-part launches and the SNP-batch chunks (an
     // input with the M-materialised layout always runs as a single job).
-    std::map<std::tuple<int, int, int>, std::vector<int>> buckets;
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> buckets;
     for (size_t i = 0; i < jobs.size(); ++i) {
         if (2 * jobs[i]->S->count >= chunk || jobs[i]->S_rep) {
             const int own = (!jobs[i]->S_host && c.pool->budget == 0)

@@ -60,6 +60,9 @@ struct EncOutput {
 struct FixedOut {
     std::vector<Ct> r_s;   // r_j = (X A)_{:, j} at the SNP depth
     std::vector<Ct> x_c;   // x_j at the SNP depth + 2
+    int K = 0;             // width of the packed projection (0: one colSum and broadcast per covariate)
+    std::vector<Ct> z_d;   // packed projection: Rot(Z_t, -t) at the SNP depth, t < K
+    std::vector<Ct> x_d;   // packed projection: X_t at the SNP depth + 2, t < K
     Ct u_s, w_s;           // u = w z' and w at the SNP depth + 3 (w_s empty when w is public: kappa = 1)
     std::vector<Ct> hold;  // batches that r_s and x_c may be views of
     Ct m_cols;             // M-materialised layout: Dup(M_i), i < n, at the SNP depth + 2
@@ -79,11 +82,19 @@ Layout make_layout(int n_ring, int n, int k, int m);
 // ModUp and ModDown weigh most) uses radix 16, 2 key switches for R = 256.
 constexpr int kFixedRadix = 8, kBatchRadix = 16;
 std::vector<std::vector<i64>> rotation_groups(int R, int radix);
+// Packed projection of the SNP batches (all k covariates' column sums in one ciphertext): its width K, the
+// smallest power of two >= k, or 0 where it does not apply (k < 2, K above min(kBatchRadix, R), or
+// n + K - 1 > R: the rows that its products and stride sums wrap onto must be padding rows)
+int diag_width(const Layout &lay);
+// The rotations of sum_{u < R/K} Rot(a, K u) by shared key switch: the multiples of K in the first group of
+// rotation_groups(R, radix), then its other groups (every rotation is one of rotation_groups(R, radix))
+std::vector<std::vector<i64>> stride_groups(int R, int K, int radix);
 // Galois elements of the rotations of rotation_groups(R, 8) and rotation_groups(R, 16) in both
 // directions (each once, in that order), then conjugation
 std::vector<u64> required_galois(int n, int R);
+// K: the packed projection's width (diag_width), 0 for one colSum and broadcast per covariate
 void run_fixed(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckks_ct *> &x, const ckks_ct &y,
-               const std::vector<const ckks_ct *> &A, int ds, FixedOut &fx, EncOutput &rep);
+               const std::vector<const ckks_ct *> &A, int ds, FixedOut &fx, EncOutput &rep, int K);
 BatchOut run_batch(ckks_ctx &c, int R, int k, const FixedOut &fx, const ckks_ct &S);
 void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk);
 void run_multi(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std::vector<EncOutput> &outs, int chunk);
@@ -98,7 +109,8 @@ struct WorkItem {
     EncOutput *out;
     int batch;
 };
-std::tuple<int, int, int> bucket_of(const EncInput &in);
+// jobs that share launches: same R, k, kappa and packed-projection width
+std::tuple<int, int, int, int> bucket_of(const EncInput &in);
 void fixed_for_jobs(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std::vector<FixedOut> &fxs,
                     std::vector<EncOutput> &reps);
 void chunk_for_jobs(ckks_ctx &c, const std::vector<WorkItem> &items);

@@ -106,7 +106,7 @@ struct gwas_server {
             try {
                 std::lock_guard<std::recursive_mutex> ck(ctx->mu);
                 if (!admitted.empty()) {
-                    std::map<std::tuple<int, int, int>, std::vector<Job *>> buckets;
+                    std::map<std::tuple<int, int, int, int>, std::vector<Job *>> buckets;
                     for (Job *j : admitted) buckets[bucket_of(*j->in->in)].push_back(j);
                     for (auto &kv : buckets) {
                         std::vector<const EncInput *> ins;

@@ -342,10 +342,14 @@ def _oracle_circuit(n, k, m, kappa, log_n, b, data_seed):
 
 @pytest.mark.parametrize("n,k,m,log_n,b,chunk,kappa", [(30, 4, 70, 10, 30, 2, 3), (30, 4, 150, 10, 30, None, 3),
                                                          (245, 4, 32, 13, 30, None, 3), (30, 4, 70, 10, 30, 2, 2),
-                                                         (30, 4, 150, 10, 30, None, 1), (245, 4, 32, 13, 30, 1, 1)])
+                                                         (30, 4, 150, 10, 30, None, 1), (245, 4, 32, 13, 30, 1, 1),
+                                                         (24, 4, 70, 10, 30, 2, 3), (24, 3, 70, 10, 30, None, 2),
+                                                         (20, 2, 40, 10, 30, None, 1), (24, 6, 40, 10, 30, None, 2)])
 def test_circuit_bit_exact_against_oracle(torch_dev, n, k, m, log_n, b, chunk, kappa):
     """Every output ciphertext of the circuit bit for bit against the oracle, for kappa = 3, 2 and 1 (the
-    reduced kappa of the paper's Discussion, with public weights)."""
+    reduced kappa of the paper's Discussion, with public weights).  n = 30 at R = 32 takes one colSum and
+    broadcast per covariate; n = 245 at R = 256 and n <= 24 at R = 32 take the packed projection (K = 4,
+    K = 2 for k = 2, K = 8 for k = 6)."""
     say("[gpu] circuit n=%d k=%d m=%d logN=%d kappa=%d" % (n, k, m, log_n, kappa))
     p, d, lay, o, inp, ref = _oracle_circuit(n, k, m, kappa, log_n, b, config_seed(1))
     ctx = P.Context(log_n, p.L, b)
