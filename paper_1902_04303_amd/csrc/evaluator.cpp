@@ -540,11 +540,30 @@ static const u64 *key_of(const ckks_ctx &c, u64 id) {
 //            subtraction, the multiply by P^-1 and the added term into its final store);
 // plus the gathered `add` term (on every row, or on the first polynomial of each ciphertext when
 // add_even).  Output [count][2][l][N] in NTT form.
+// ModUp of a key switch: the digits of the polynomial gathered by `d` at every target ([count][K][N])
+static DBuf mod_up(ckks_ctx &c, const Gather &d, int count, int l) {
+    const size_t N = (size_t)c.p.n;
+    const ckks_ctx::KsLevel &kl = c.ks_levels.at(l);
+    DBuf dc(c.pool.get(), (size_t)count * l * N);
+    k_ntt_inverse_g(c.tab, dc.ptr, d, count * l, map_q(l), c.stream, kl.up_scale, l);
+    DBuf dig(c.pool.get(), (size_t)count * kl.K * N);
+    k_ntt_forward_g(c.tab, dig.ptr, Gather{dc.ptr, 1, 1, 0, 0, kConv, 0, kl.up, kl.K, l}, count * kl.K, map_q(l),
+                    c.stream);
+    c.n_limb_ntt += (uint64_t)count * (l + kl.K);
+    c.n_launch += 2;
+    return dig;
+}
+
+// inner product and ModDown of a key switch whose digits `dig` come from mod_up of `d` (see keyswitch);
+// `own`, when given, holds the digits and is released after the inner product
+static DBuf ks_inner_down(ckks_ctx &c, const u64 *dig, const Gather &d, int count, int l, const KsKeys &keys,
+                          const Gather &add, bool add_even, const u64 *aut, int aut_self, bool aut_gather,
+                          DBuf *own = nullptr);
+
 static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, const KsKeys &keys, const Gather &add,
                       bool add_even, const u64 *aut = nullptr, int aut_self = 0, bool aut_gather = true) {
     const size_t N = (size_t)c.p.n;
-    const ckks_ctx::KsLevel &kl = c.ks_levels.at(l);
-    const int a = c.p.alpha, nt = l + a, P = c.p.p_index();
+    const int a = c.p.alpha, nt = l + a;
     // algorithmic bytes of the key switch: the input polynomial (l limbs per ciphertext), each key's digit
     // groups below l at every target (read once per call, shared by the ciphertexts) and the two output
     // polynomials read and written once (2 x 2 l limbs per ciphertext)
@@ -552,15 +571,19 @@ static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, const KsKe
     const double ks_bytes = 8.0 * (double)N *
                             ((double)count * l + (double)keys.m * 2.0 * groups * nt + (double)count * 4.0 * l);
     KRegion region_(c.tab.timer, "keyswitch", ks_bytes, c.stream);
-    DBuf dc(c.pool.get(), (size_t)count * l * N);
-    k_ntt_inverse_g(c.tab, dc.ptr, d, count * l, map_q(l), c.stream, kl.up_scale, l);
-    DBuf dig(c.pool.get(), (size_t)count * kl.K * N);
-    k_ntt_forward_g(c.tab, dig.ptr, Gather{dc.ptr, 1, 1, 0, 0, kConv, 0, kl.up, kl.K, l}, count * kl.K, map_q(l),
-                    c.stream);
-    dc.release();
+    DBuf dig = mod_up(c, d, count, l);
+    return ks_inner_down(c, dig.ptr, d, count, l, keys, add, add_even, aut, aut_self, aut_gather, &dig);
+}
+
+static DBuf ks_inner_down(ckks_ctx &c, const u64 *dig, const Gather &d, int count, int l, const KsKeys &keys,
+                          const Gather &add, bool add_even, const u64 *aut, int aut_self, bool aut_gather,
+                          DBuf *own) {
+    const size_t N = (size_t)c.p.n;
+    const ckks_ctx::KsLevel &kl = c.ks_levels.at(l);
+    const int a = c.p.alpha, nt = l + a, P = c.p.p_index();
     DBuf acc(c.pool.get(), (size_t)count * 2 * nt * N);
-    k_ks_inner(c.tab, acc.ptr, dig.ptr, kl.K, kl.didx, d, keys, c.ng, count, l, c.p.levels, a, c.stream);
-    dig.release();
+    k_ks_inner(c.tab, acc.ptr, dig, kl.K, kl.didx, d, keys, c.ng, count, l, c.p.levels, a, c.stream);
+    if (own) own->release();
     const int rows = count * 2;
     DBuf ap(c.pool.get(), (size_t)rows * a * N);
     k_ntt_inverse_g(c.tab, ap.ptr, Gather{acc.ptr, a, nt, l, 1, kPlain, 0}, rows * a, ModMap{a, 0, P}, c.stream,
@@ -571,8 +594,8 @@ static DBuf keyswitch(ckks_ctx &c, const Gather &d, int count, int l, const KsKe
     for (int i = 0; i < keys.m; ++i) epi.g[i] = keys.g[i];
     k_ntt_forward_g(c.tab, out.ptr, Gather{ap.ptr, 1, 1, 0, 0, kConv, 0, c.down_conv, l, a}, rows * l, map_q(l),
                     c.stream, &epi);
-    c.n_limb_ntt += (uint64_t)count * (l + kl.K) + (uint64_t)rows * (a + l);
-    c.n_launch += 9;
+    c.n_limb_ntt += (uint64_t)rows * (a + l);
+    c.n_launch += 7;
     ++c.n_keyswitch;
     c.n_keyswitch_ct += (uint64_t)count;
     return out;
@@ -802,6 +825,31 @@ Ct rotate_sum(ckks_ctx &c, const ckks_ct &a, const std::vector<i64> &rots) {
 }
 
 Ct rotate(ckks_ctx &c, const ckks_ct &a, i64 r) { return apply_galois(c, a, galois_rotate(c, r)); }
+
+std::vector<Ct> rotate_many(ckks_ctx &c, const ckks_ct &a, const std::vector<i64> &rots) {
+    const int l = a.limbs;
+    const Gather d{a.data.ptr, l, 2 * l, l, 1, kPlain, 0};
+    std::vector<Ct> out;
+    if (rots.empty()) return out;
+    // algorithmic bytes as for keyswitch: the input once, then per rotation its key and the two outputs
+    const int al = c.p.alpha, nt = l + al, groups = 1 + l / al;
+    const double bytes = 8.0 * (double)c.p.n *
+                         ((double)a.count * l + (double)rots.size() * (2.0 * groups * nt + (double)a.count * 4.0 * l));
+    KRegion region_(c.tab.timer, "keyswitch", bytes, c.stream);
+    DBuf dig = mod_up(c, d, a.count, l);
+    for (i64 rr : rots) {
+        const KsKeys keys = ks_keys(c, {galois_rotate(c, rr)}, true);
+        Ct r(new ckks_ct());
+        r->ctx = &c;
+        r->count = a.count;
+        r->depth = a.depth;
+        r->limbs = l;
+        r->scale = a.scale;
+        r->data = ks_inner_down(c, dig.ptr, d, a.count, l, keys, Gather{}, false, a.data.ptr, false, true);
+        out.push_back(std::move(r));
+    }
+    return out;
+}
 Ct conjugate(ckks_ctx &c, const ckks_ct &a) { return apply_galois(c, a, galois_conj(c)); }
 
 // ---------------------------------------------------------------- keys

@@ -151,6 +151,9 @@ Ct mul_sum_rep(ckks_ctx &c, const ckks_ct &cols, const ckks_ct &rep);
 Ct add_slot_indicators(ckks_ctx &c, const ckks_ct &a, int R);
 Ct apply_galois(ckks_ctx &c, const ckks_ct &a, u64 g);
 Ct rotate(ckks_ctx &c, const ckks_ct &a, i64 r);
+// Rot(a, r) for every r of rots as separate ciphertexts, with one ModUp of a's second polynomial shared by
+// all of them (bit-identical to one rotate per r)
+std::vector<Ct> rotate_many(ckks_ctx &c, const ckks_ct &a, const std::vector<i64> &rots);
 // a + sum_i Rot(a, rots[i]) with one key switch shared by the rotations (at most 16)
 Ct rotate_sum(ckks_ctx &c, const ckks_ct &a, const std::vector<i64> &rots);
 Ct conjugate(ckks_ctx &c, const ckks_ct &a);

@@ -390,12 +390,14 @@ Ct batch_front(ckks_ctx &c, int R, int k, const FixedOut &fx, const ckks_ct &S) 
         // V = sum_{u < R/K} Rot(., -K u) holds C_{r mod K} at block row r; x E = sum_t X_t Rot(V, t)
         const int K = fx.K;
         const auto groups = stride_groups(R, K, kBatchRadix);
-        std::vector<Ct> rs(K);
-        std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pd{{fx.z_d[0].get(), &S}};
+        std::vector<i64> right, left;
         for (int t = 1; t < K; ++t) {
-            rs[t] = rotate(c, S, -t);
-            pd.push_back({fx.z_d[t].get(), rs[t].get()});
+            right.push_back(-t);
+            left.push_back(t);
         }
+        std::vector<Ct> rs = rotate_many(c, S, right);   // one ModUp of S for the K - 1 rotations
+        std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pd{{fx.z_d[0].get(), &S}};
+        for (int t = 1; t < K; ++t) pd.push_back({fx.z_d[t].get(), rs[t - 1].get()});
         Ct w = mul_sum(c, pd);
         rs.clear();
         for (const auto &grp : groups) w = rotate_sum(c, *w, grp);
@@ -406,12 +408,9 @@ Ct batch_front(ckks_ctx &c, int R, int k, const FixedOut &fx, const ckks_ct &S) 
             for (i64 r : grp) neg.push_back(-r);
             v = rotate_sum(c, *v, neg);
         }
-        std::vector<Ct> rv(K);
+        std::vector<Ct> rv = rotate_many(c, *v, left);
         std::vector<std::pair<const ckks_ct *, const ckks_ct *>> pe{{fx.x_d[0].get(), v.get()}};
-        for (int t = 1; t < K; ++t) {
-            rv[t] = rotate(c, *v, t);
-            pe.push_back({fx.x_d[t].get(), rv[t].get()});
-        }
+        for (int t = 1; t < K; ++t) pe.push_back({fx.x_d[t].get(), rv[t - 1].get()});
         Ct xe = mul_sum(c, pe);
         return sub(c, *C.at(S, xe->depth), *xe);
     }
