@@ -302,7 +302,7 @@ void fixed_front(ckks_ctx &c, int R, int k, const std::vector<const ckks_ct *> &
 
 void fixed_back(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ckks_ct *> &x, const ckks_ct &y,
                 const std::vector<const ckks_ct *> &Ain, int ds, FixedOut &fx, EncOutput &rep,
-                const StackIn *pre = nullptr) {
+                const StackIn *pre = nullptr, hipEvent_t w_ready = nullptr) {
     Stacked st(c, R, k, x, Ain, pre);
     Circ &C = st.C;
     const int J = st.J;
@@ -340,6 +340,8 @@ void fixed_back(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ck
     }
     // ---- w = p (1 - p), Alg. inverseSlots: guess 3, the first Newton step is 6 - 9 w
     Ct w = mul(c, *pk, *add_const(c, *neg(c, *pk), 1.0));
+    fx.w_s = C.at(*w, ds + 3);   // may be a view of w, which rep owns from here on
+    if (w_ready) GCK_HIP(hipEventRecord(w_ready, c.stream));
     Ct gi = add_const(c, *mul_int(c, *w, -9), 6.0);
     for (int it = 0; it < 2; ++it) {
         Ct wg = mul(c, *C.at(*w, gi->depth), *gi);
@@ -359,8 +361,7 @@ void fixed_back(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ck
     Ct u = mul(c, *C.at(*w, z_proj->depth), *z_proj);
     // ---- what the per-batch part needs, at the depths it uses them
     for (int j = 0; j < k; ++j) rep.beta.push_back(clone(c, *view(*beta, j * J, J)));
-    fx.u_s = C.at(*u, ds + 3);   // may be views of u and w, which rep owns from here on
-    fx.w_s = C.at(*w, ds + 3);
+    fx.u_s = C.at(*u, ds + 3);   // may be a view of u, which rep owns from here on
     rep.w = std::move(w);
     rep.w_inv = std::move(w_inv);
     rep.z_proj = std::move(z_proj);
@@ -441,14 +442,21 @@ Ct batch_front_m(ckks_ctx &c, const FixedOut &fx, const ckks_ct &S_rep_chunk) {
 }
 
 // numerator and denominators from S' (needs u and w of the fixed part)
-BatchOut batch_back(ckks_ctx &c, int R, int k, const FixedOut &fx, Ct sp) {
+// the numerator of o.sp (needs u of the fixed part)
+void batch_num(ckks_ctx &c, int R, int k, const FixedOut &fx, BatchOut &o) {
     Layout lay;
     lay.R = R;
     lay.k = k;
     Circ C(c, lay, kBatchRadix);
-    BatchOut o;
-    o.sp = std::move(sp);
     o.num = C.rot_sum(mul(c, *fx.u_s, *o.sp));
+}
+
+// both denominators of o.sp (need w of the fixed part, public for kappa = 1)
+void batch_den(ckks_ctx &c, int R, int k, const FixedOut &fx, BatchOut &o) {
+    Layout lay;
+    lay.R = R;
+    lay.k = k;
+    Circ C(c, lay, kBatchRadix);
     // with S' = a + i b per slot (even SNP a, odd SNP b) both denominators come from one rotate-and-sum of
     // W = 4 w (a^2 + i b^2) = (2 + 2i) w S' conj(S') + (1 - i) (w S'^2 + conj(w S'^2)); den_even = sum W / 4
     // and den_odd = -i sum W / 4 have the two denominators as their real parts
@@ -468,6 +476,13 @@ BatchOut batch_back(ckks_ctx &c, int R, int k, const FixedOut &fx, Ct sp) {
     }
     o.de = C.rot_sum(set_scale(c, pack_den(c, *ssc, *ss, *conjugate(c, *ss)), f));
     o.dodd = mul_i(c, *o.de, true);
+}
+
+BatchOut batch_back(ckks_ctx &c, int R, int k, const FixedOut &fx, Ct sp) {
+    BatchOut o;
+    o.sp = std::move(sp);
+    batch_num(c, R, k, fx, o);
+    batch_den(c, R, k, fx, o);
     return o;
 }
 
@@ -521,14 +536,17 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
     const int nb = in.S->count;
     if (!in.S_host && c.pool->budget == 0 && c.n_streams == 2) {
         // The logistic regression (u, w) runs on the auxiliary stream while the main stream computes what
-        // needs only r_j and x_j (their fixed-part products, then S' of every SNP batch).  The numerator and
-        // denominators then wait for it.
+        // needs only r_j and x_j (their fixed-part products, then S' of every SNP batch).  The denominators
+        // then wait for w only (public for kappa = 1), which the regression has before its last steps
+        // (w^-1, z, z', u); the numerators wait for u.
         ensure_aux(c);
         const StackIn sin = stack_inputs(c, k, x, A);   // shared by both parts, read only
         stream_wait(c.aux_stream, c.stream);   // inputs, their stacking and this call's earlier work
+        hipEvent_t w_ready;
+        GCK_HIP(hipEventCreateWithFlags(&w_ready, hipEventDisableTiming));
         {
             OnStream on_aux(c);
-            fixed_back(c, lay.R, k, in.kappa, x, *in.y, A, ds, fx, out, &sin);
+            fixed_back(c, lay.R, k, in.kappa, x, *in.y, A, ds, fx, out, &sin, w_ready);
         }
         fixed_front(c, lay.R, k, x, A, ds, fx, in.S_rep ? 0 : diag_width(lay), &sin, in.Xrep.get(), &out);
         std::vector<Ct> sps;
@@ -543,9 +561,16 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
             Ct S = view(*in.S, b0, cnt);
             sps.push_back(batch_front(c, lay.R, k, fx, *S));
         }
-        stream_wait(c.stream, c.aux_stream);   // u and w
-        for (Ct &sp : sps) {
-            BatchOut o = batch_back(c, lay.R, k, fx, std::move(sp));
+        if (in.kappa != 1) GCK_HIP(hipStreamWaitEvent(c.stream, w_ready, 0));   // w
+        (void)hipEventDestroy(w_ready);
+        std::vector<BatchOut> bos(sps.size());
+        for (size_t i = 0; i < sps.size(); ++i) {
+            bos[i].sp = std::move(sps[i]);
+            batch_den(c, lay.R, k, fx, bos[i]);
+        }
+        stream_wait(c.stream, c.aux_stream);   // u
+        for (BatchOut &o : bos) {
+            batch_num(c, lay.R, k, fx, o);
             if (c.keep_s_proj) out.S_proj.push_back(std::move(o.sp));
             out.num.push_back(std::move(o.num));
             out.den_even.push_back(std::move(o.de));
