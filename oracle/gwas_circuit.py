@@ -340,19 +340,23 @@ class Circuit:
     def diagonals(self, inp: EncInput, rr: List[C.Ct], ds: int, K: int):
         """The packed projection's diagonals (reading 21): with comb_c the mask of the slots s = c mod K,
         Z_t = sum_j comb_{(j - t) mod K} r_j and X_t = sum_j comb_{(j - t) mod K} x_j (slot s of block row r
-        holds r_{(r + t) mod K}[r], or 0 where (r + t) mod K >= k), each one mask_sum; Z_t is brought to the
-        SNP depth ds and rotated right by t, X_t brought to ds + 2."""
+        holds r_{(r + t) mod K}[r], or 0 where (r + t) mod K >= k), each one mask_sum of the r_j brought to
+        depth ds - 1 and of the x_j brought to ds + 1, so that Z_t lands at the SNP depth ds and X_t at ds + 2
+        with their canonical scales (the mask product's s^2 / q is the next depth's canonical scale); Z_t is
+        then rotated right by t."""
         o = self.o
         N = self.lay.N
         k = self.lay.k
+        ra = [self.at(rr[j], ds - 1) for j in range(k)]
+        xa = [self.at(inp.x[j], ds + 1) for j in range(k)]
         zt, xt = [], []
         for t in range(K):
-            z = o.mask_sum([(rr[j], C.slot_class_indicator_poly(N, K, (j - t) % K, rr[j].scale)) for j in range(k)])
-            z = self.at(z, ds)
+            z = o.mask_sum([(ra[j], C.slot_class_indicator_poly(N, K, (j - t) % K, ra[j].scale)) for j in range(k)])
+            assert z.depth == ds and z.scale == self.sc[ds]
             zt.append(o.rotate(z, -t) if t else z)
-            xm = o.mask_sum([(inp.x[j], C.slot_class_indicator_poly(N, K, (j - t) % K, inp.x[j].scale))
-                             for j in range(k)])
-            xt.append(self.at(xm, ds + 2))
+            xm = o.mask_sum([(xa[j], C.slot_class_indicator_poly(N, K, (j - t) % K, xa[j].scale)) for j in range(k)])
+            assert xm.depth == ds + 2 and xm.scale == self.sc[ds + 2]
+            xt.append(xm)
         return zt, xt
 
     def project_diag(self, S: C.Ct, fx: "FixedPart") -> C.Ct:

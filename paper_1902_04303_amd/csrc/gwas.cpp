@@ -265,6 +265,30 @@ void fixed_front(ckks_ctx &c, int R, int k, const std::vector<const ckks_ct *> &
         fx.hold.push_back(std::move(D));
         if (rep) rep->m_cols = clone(c, *fx.m_cols);
     }
+    if (K) {
+        // packed projection: Z_t = sum_j comb_{(j - t) mod K} r_j and X_t = sum_j comb_{(j - t) mod K} x_j
+        // (comb_c: the slots s = c mod K), block row r of Z_t holding r_{(r + t) mod K}[r].  The mask products
+        // take r_j at the SNP depth - 1 and x_j at the SNP depth + 1, so that Z_t lands at the SNP depth and
+        // X_t at the SNP depth + 2 with their canonical scales; Z_t is then rotated right by t.  r_s and x_c
+        // stay empty (the packed projection does not read them).
+        if (RR->depth >= ds - 1 || st.Xs.depth >= ds + 1) throw Error(CKKS_E_LEVEL, "diagonals too deep");
+        fx.K = K;
+        Ct RRa = st.C.at(*RR, ds - 1), Xa = st.C.at(st.Xs, ds + 1);
+        const std::vector<Ct> rj = st.parts(*RRa), xj = st.parts(*Xa);
+        for (int t = 0; t < K; ++t) {
+            std::vector<MaskTerm> tz, tx;
+            for (int j = 0; j < k; ++j) {
+                const int cls = ((j - t) % K + K) % K;
+                tz.push_back({rj[j].get(), K, cls, cls + 1});
+                tx.push_back({xj[j].get(), K, cls, cls + 1});
+            }
+            Ct z = mask_sum(c, tz);
+            fx.z_d.push_back(t ? rotate(c, *z, -t) : std::move(z));
+            fx.x_d.push_back(mask_sum(c, tx));
+        }
+        fx.hold.push_back(std::move(RR));
+        return;
+    }
     Ct RRs = st.C.at(*RR, ds);
     // x_j at ds + 2 owned here (the stacked x may be the caller's, shared with the other part)
     Ct Xc = st.Xs.depth == ds + 2 ? clone(c, st.Xs) : st.C.at(st.Xs, ds + 2);
@@ -273,26 +297,6 @@ void fixed_front(ckks_ctx &c, int R, int k, const std::vector<const ckks_ct *> &
     for (int j = 0; j < k; ++j) {
         fx.r_s[j] = view(*RRs, j * J, J);
         fx.x_c[j] = view(*Xc, j * J, J);
-    }
-    if (K) {
-        // packed projection: Z_t = sum_j comb_{(j - t) mod K} r_j and X_t = sum_j comb_{(j - t) mod K} x_j
-        // (comb_c: the slots s = c mod K), block row r of Z_t holding r_{(r + t) mod K}[r]; Z_t at the SNP
-        // depth, rotated right by t, X_t at the SNP depth + 2
-        fx.K = K;
-        const std::vector<Ct> rj = st.parts(*RR), xj = st.parts(st.Xs);
-        for (int t = 0; t < K; ++t) {
-            std::vector<MaskTerm> tz, tx;
-            for (int j = 0; j < k; ++j) {
-                const int cls = ((j - t) % K + K) % K;
-                tz.push_back({rj[j].get(), K, cls, cls + 1});
-                tx.push_back({xj[j].get(), K, cls, cls + 1});
-            }
-            Ct zm = mask_sum(c, tz), xm = mask_sum(c, tx);
-            if (zm->depth >= ds || xm->depth >= ds + 2) throw Error(CKKS_E_LEVEL, "diagonals too deep");
-            Ct z = st.C.at(*zm, ds);
-            fx.z_d.push_back(t ? rotate(c, *z, -t) : std::move(z));
-            fx.x_d.push_back(st.C.at(*xm, ds + 2));
-        }
     }
     // RRs may be a view of RR (at() does not copy)
     fx.hold.push_back(std::move(RRs));
@@ -733,8 +737,8 @@ void fixed_for_jobs(ckks_ctx &c, const std::vector<const EncInput *> &jobs, std:
     reps.resize(J);
     for (int q = 0; q < J; ++q) {
         FixedOut &f = fxs[q];
-        for (int j = 0; j < k; ++j) f.r_s.push_back(gather(c, {{fx.r_s[j].get(), q}}));
-        for (int j = 0; j < k; ++j) f.x_c.push_back(gather(c, {{fx.x_c[j].get(), q}}));
+        for (auto &r : fx.r_s) f.r_s.push_back(gather(c, {{r.get(), q}}));
+        for (auto &xc : fx.x_c) f.x_c.push_back(gather(c, {{xc.get(), q}}));
         f.K = fx.K;
         for (auto &z : fx.z_d) f.z_d.push_back(gather(c, {{z.get(), q}}));
         for (auto &xd : fx.x_d) f.x_d.push_back(gather(c, {{xd.get(), q}}));
@@ -767,9 +771,11 @@ void chunk_for_jobs(ckks_ctx &c, const std::vector<WorkItem> &items) {
         return gather(c, it);
     };
     FixedOut fc;
-    for (int j = 0; j < k; ++j) fc.r_s.push_back(per_item([&](const FixedOut &f) { return f.r_s[j].get(); }));
-    for (int j = 0; j < k; ++j) fc.x_c.push_back(per_item([&](const FixedOut &f) { return f.x_c[j].get(); }));
     fc.K = items[0].fx->K;
+    if (!fc.K) {
+        for (int j = 0; j < k; ++j) fc.r_s.push_back(per_item([&](const FixedOut &f) { return f.r_s[j].get(); }));
+        for (int j = 0; j < k; ++j) fc.x_c.push_back(per_item([&](const FixedOut &f) { return f.x_c[j].get(); }));
+    }
     for (const WorkItem &w : items)
         if (w.fx->K != fc.K) throw Error(CKKS_E_PARAM_MISMATCH, "SNP batches of different projection widths");
     for (int t = 0; t < fc.K; ++t) {
