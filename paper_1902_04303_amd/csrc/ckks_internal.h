@@ -307,6 +307,16 @@ void k_mul_const(const DevTables &t, u64 *out, const u64 *a, int n_limbs, ModMap
 // ct data [count][2][l][N]: out = a with c[chain] added to the limbs of poly 0 (out may be a)
 void k_add_const_c0(const DevTables &t, u64 *out, const u64 *a, int count, int l, const ChainConst &c, hipStream_t st);
 // tensor of [count][2][l] ciphertexts into [count][3][l]; a / b read at ciphertext (c % na) / (c % nb)
+// sum over up to kMaxTensorPairs pairs of the tensors of k_tensor (pair p read at ciphertexts c % na[p] and
+// c % nb[p]), stored once into out ([count][3][l][N]; added to out when accumulate)
+constexpr int kMaxTensorPairs = 8;
+struct TensorPairs {
+    const u64 *a[kMaxTensorPairs];
+    const u64 *b[kMaxTensorPairs];
+    int na[kMaxTensorPairs], nb[kMaxTensorPairs];
+    int n;
+};
+void k_tensor_sum(const DevTables &t, u64 *out, const TensorPairs &tp, int count, int l, bool accumulate, hipStream_t st);
 void k_tensor(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int count, int l, int na, int nb,
               bool accumulate, hipStream_t st);
 // NTT-domain automorphism X -> X^g on every limb

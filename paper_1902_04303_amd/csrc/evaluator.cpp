@@ -686,10 +686,23 @@ Ct mul_sum(ckks_ctx &c, const std::vector<std::pair<const ckks_ct *, const ckks_
     const int l = a0.limbs;
     const size_t N = (size_t)c.p.n;
     DBuf d(c.pool.get(), (size_t)count * 3 * l * N);
-    for (size_t i = 0; i < pairs.size(); ++i) {
-        k_tensor(c.tab, d.ptr, pairs[i].first->data.ptr, pairs[i].second->data.ptr, count, l, pairs[i].first->count,
-                 pairs[i].second->count, i > 0, c.stream);
+    if (pairs.size() == 1) {
+        k_tensor(c.tab, d.ptr, a0.data.ptr, b0.data.ptr, count, l, a0.count, b0.count, false, c.stream);
         ++c.n_launch;
+    } else {
+        // the pairs' tensors summed in registers, kMaxTensorPairs per launch
+        for (size_t i0 = 0; i0 < pairs.size(); i0 += kMaxTensorPairs) {
+            TensorPairs tp{};
+            tp.n = (int)std::min(pairs.size() - i0, (size_t)kMaxTensorPairs);
+            for (int p = 0; p < tp.n; ++p) {
+                tp.a[p] = pairs[i0 + p].first->data.ptr;
+                tp.b[p] = pairs[i0 + p].second->data.ptr;
+                tp.na[p] = pairs[i0 + p].first->count;
+                tp.nb[p] = pairs[i0 + p].second->count;
+            }
+            k_tensor_sum(c.tab, d.ptr, tp, count, l, i0 > 0, c.stream);
+            ++c.n_launch;
+        }
     }
     return relin_rescale(c, std::move(d), count, a0.depth, l, a0.scale, b0.scale);
 }

@@ -255,6 +255,52 @@ void k_tensor(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int coun
     check_launch();
 }
 
+// sum over the pairs of ew_tensor's products, each as ew_tensor computes it, summed modulo q and stored once
+__global__ void ew_tensor_sum(u64 *out, TensorPairs tp, size_t total, int log_n, int l, const ModInfo *mods,
+                              int accumulate) {
+    const size_t n = (size_t)1 << log_n;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+        int lam = (int)(idx >> log_n);       // over count * l
+        int ci = lam / l, i = lam % l;
+        size_t k = idx & (n - 1);
+        const ModInfo &M = mods[i];
+        u64 s0 = 0, s1 = 0, s2 = 0;
+        for (int p = 0; p < tp.n; ++p) {
+            const u64 *pa = tp.a[p] + (size_t)(ci % tp.na[p]) * 2 * l * n, *pb = tp.b[p] + (size_t)(ci % tp.nb[p]) * 2 * l * n;
+            u64 a0 = pa[(size_t)i * n + k], a1 = pa[(size_t)(l + i) * n + k];
+            u64 b0 = pb[(size_t)i * n + k], b1 = pb[(size_t)(l + i) * n + k];
+            u64 d0 = mul_mod(a0, b0, M);
+            u64 lo1 = a0 * b1, hi1 = __umul64hi(a0, b1);
+            u64 lo2 = a1 * b0, hi2 = __umul64hi(a1, b0);
+            u64 lo = lo1 + lo2, hi = hi1 + hi2 + (lo < lo1 ? 1 : 0);
+            if (hi >= M.q) hi -= M.q;
+            u64 d1 = mul_shoup(redc(hi, lo, M), M.r_mod, M.r_mod_sh, M.q);
+            u64 d2 = mul_mod(a1, b1, M);
+            s0 = add_mod(s0, d0, M.q);
+            s1 = add_mod(s1, d1, M.q);
+            s2 = add_mod(s2, d2, M.q);
+        }
+        u64 *po = out + (size_t)ci * 3 * l * n;
+        size_t o0 = (size_t)i * n + k, o1 = (size_t)(l + i) * n + k, o2 = (size_t)(2 * l + i) * n + k;
+        if (accumulate) {
+            s0 = add_mod(po[o0], s0, M.q);
+            s1 = add_mod(po[o1], s1, M.q);
+            s2 = add_mod(po[o2], s2, M.q);
+        }
+        po[o0] = s0; po[o1] = s1; po[o2] = s2;
+    }
+}
+
+void k_tensor_sum(const DevTables &t, u64 *out, const TensorPairs &tp, int count, int l, bool accumulate, hipStream_t st) {
+    TScope ts_(t, "ew_tensor_sum", 8.0 * (4.0 * tp.n + 3.0) * (double)((size_t)count * l) * t.n, st);
+    size_t total = ((size_t)count * l) << t.log_n;
+    if (!total || tp.n < 1) return;
+    if (tp.n > kMaxTensorPairs) throw Error(CKKS_E_INVALID_ARG, "too many pairs in one tensor sum");
+    gck_launch(ew_tensor_sum, ew_grid(total), dim3(kEwThreads), 0, st, out, tp, total, t.log_n, l, t.mods,
+               accumulate ? 1 : 0);
+    check_launch();
+}
+
 __global__ void ew_add_scaled_last(u64 *acc, const u64 *add, size_t total, int log_n, int nt, int l, u64 pm,
                                    u64 pm_sh, u64 q) {
     const size_t nw = (size_t)1 << log_n;
