@@ -226,6 +226,23 @@ __global__ void ew_tensor(u64 *out, const u64 *a, const u64 *b, size_t total, in
         const u64 *pa = a + (size_t)(ci % na) * 2 * l * n, *pb = b + (size_t)(ci % nb) * 2 * l * n;
         u64 a0 = pa[(size_t)i * n + k], a1 = pa[(size_t)(l + i) * n + k];
         u64 b0 = pb[(size_t)i * n + k], b1 = pb[(size_t)(l + i) * n + k];
+        if (M.fp) {
+            // moduli below 2^41: exact FP64 products (see ew_tensor_sum), made canonical once
+            const FMod fm{M.qd, M.qinv};
+            const double x0 = u2d(a0), x1 = u2d(a1), y0 = u2d(b0), y1 = u2d(b1);
+            double f0 = fmul_mod(x0, y0, fm), f1 = fmul_mod(x0, y1, fm) + fmul_mod(x1, y0, fm), f2 = fmul_mod(x1, y1, fm);
+            u64 *po = out + (size_t)ci * 3 * l * n;
+            size_t o0 = (size_t)i * n + k, o1 = (size_t)(l + i) * n + k, o2 = (size_t)(2 * l + i) * n + k;
+            if (accumulate) {
+                f0 += u2d(po[o0]);
+                f1 += u2d(po[o1]);
+                f2 += u2d(po[o2]);
+            }
+            po[o0] = fcanon(f0, fm);
+            po[o1] = fcanon(f1, fm);
+            po[o2] = fcanon(f2, fm);
+            continue;
+        }
         u64 d0 = mul_mod(a0, b0, M);
         // a0 b1 + a1 b0 as one 128-bit sum (< 2 q^2 < q 2^64), one reduction
         u64 lo1 = a0 * b1, hi1 = __umul64hi(a0, b1);
@@ -264,6 +281,31 @@ __global__ void ew_tensor_sum(u64 *out, TensorPairs tp, size_t total, int log_n,
         int ci = lam / l, i = lam % l;
         size_t k = idx & (n - 1);
         const ModInfo &M = mods[i];
+        u64 *po = out + (size_t)ci * 3 * l * n;
+        size_t o0 = (size_t)i * n + k, o1 = (size_t)(l + i) * n + k, o2 = (size_t)(2 * l + i) * n + k;
+        if (M.fp) {
+            // moduli below 2^41: exact FP64 products, each in (-1.1 q, 1.1 q); the sums over at most 8
+            // pairs (and the accumulated word) stay below 2^46, exact, and are made canonical once
+            const FMod fm{M.qd, M.qinv};
+            double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+            for (int p = 0; p < tp.n; ++p) {
+                const u64 *pa = tp.a[p] + (size_t)(ci % tp.na[p]) * 2 * l * n, *pb = tp.b[p] + (size_t)(ci % tp.nb[p]) * 2 * l * n;
+                const double a0 = u2d(pa[(size_t)i * n + k]), a1 = u2d(pa[(size_t)(l + i) * n + k]);
+                const double b0 = u2d(pb[(size_t)i * n + k]), b1 = u2d(pb[(size_t)(l + i) * n + k]);
+                f0 += fmul_mod(a0, b0, fm);
+                f1 += fmul_mod(a0, b1, fm) + fmul_mod(a1, b0, fm);
+                f2 += fmul_mod(a1, b1, fm);
+            }
+            if (accumulate) {
+                f0 += u2d(po[o0]);
+                f1 += u2d(po[o1]);
+                f2 += u2d(po[o2]);
+            }
+            po[o0] = fcanon(f0, fm);
+            po[o1] = fcanon(f1, fm);
+            po[o2] = fcanon(f2, fm);
+            continue;
+        }
         u64 s0 = 0, s1 = 0, s2 = 0;
         for (int p = 0; p < tp.n; ++p) {
             const u64 *pa = tp.a[p] + (size_t)(ci % tp.na[p]) * 2 * l * n, *pb = tp.b[p] + (size_t)(ci % tp.nb[p]) * 2 * l * n;
@@ -280,8 +322,6 @@ __global__ void ew_tensor_sum(u64 *out, TensorPairs tp, size_t total, int log_n,
             s1 = add_mod(s1, d1, M.q);
             s2 = add_mod(s2, d2, M.q);
         }
-        u64 *po = out + (size_t)ci * 3 * l * n;
-        size_t o0 = (size_t)i * n + k, o1 = (size_t)(l + i) * n + k, o2 = (size_t)(2 * l + i) * n + k;
         if (accumulate) {
             s0 = add_mod(po[o0], s0, M.q);
             s1 = add_mod(po[o1], s1, M.q);
