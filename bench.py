@@ -666,6 +666,22 @@ def cpu_baseline_leg(alpha: int):
     fx = G.FixedPart(x=[enc(d.X[:, j], ds + 2, j) for j in range(K_COV)],
                      rr=[enc(XA[:, j], ds, 10 + j) for j in range(K_COV)],
                      w=enc(ref.w, ds + 3, 20), u=enc(ref.w * ref.z_proj, ds + 3, 21))
+    K = G.diag_width(lay)
+    if K:
+        # the packed projection's diagonals, encrypted directly: Z_t (rotated right by t) at the SNP depth
+        # and X_t at the SNP depth + 2, block row r holding column (r + t) mod K (0 beyond k or n)
+        rows = np.arange(p.N // 2) % lay.R
+
+        def diag(M, t):
+            j = (rows + t) % K
+            keep = (rows < N_SAMPLES) & (j < K_COV)
+            v = np.zeros(p.N // 2)
+            v[keep] = M[rows[keep], j[keep]]
+            return v
+        fx.zt = [o.encrypt(C.encode(np.roll(diag(XA, t), t), p.N, p.scales[ds]), ds, p.scales[ds], 40 + t)
+                 for t in range(K)]
+        fx.xt = [o.encrypt(C.encode(diag(d.X, t), p.N, p.scales[ds + 2]), ds + 2, p.scales[ds + 2], 50 + t)
+                 for t in range(K)]
     # SNP batches in order until the timed oracle work reaches CPU_SAMPLE_S seconds (at most
     # CPU_SAMPLE_MAX_BATCHES); each batch's encryption is outside the timed part
     circ = G.Circuit(o, lay)
