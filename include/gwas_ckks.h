@@ -271,7 +271,14 @@ int gwas_input_ct(const gwas_enc_input *in, int which, int index, const ckks_ct 
 
 /* Server side (the hot path): the encrypted circuit.  Fails with CKKS_E_LEVEL or
  * CKKS_E_KEY_MISSING before any launch when the chain or keys do not fit.  The SNP
- * batches are processed `chunk` ciphertexts at a time (gwas_semiparallel: up to 64). */
+ * batches are processed `chunk` ciphertexts at a time (gwas_semiparallel: up to 64).
+ * The projection S' = S - sum_j x_j E_j (E_j the block sums of r_j S over each block, r_j = (X A)_j)
+ * packs the k covariates into one ciphertext when n + K - 1 <= R (K the smallest power of two >= k,
+ * at most 16): D = sum_t Rot(Z_t, -t) Rot(S, -t) with the diagonals Z_t of the r_j, a stride-K
+ * rotate-and-sum that leaves E_j's sum at slot j of each block, the mask of the first k slots, a
+ * stride-K broadcast V and sum_t X_t Rot(V, t) with the diagonals X_t of the x_j; otherwise one
+ * colSum, mask and broadcast per covariate.  The stride sums use the rotations of the per-batch
+ * rotate-and-sum only (gwas_galois_elements). */
 int gwas_semiparallel(ckks_ctx *ctx, const gwas_enc_input *in, gwas_enc_output **out);
 int gwas_semiparallel_chunked(ckks_ctx *ctx, const gwas_enc_input *in, int chunk, gwas_enc_output **out);
 /* Output ciphertexts: which = 0 num, 1 den_even, 2 den_odd, 3 S' (projected batches):
