@@ -469,9 +469,12 @@ class Circuit:
         return fx
 
     def _xa(self, inp: EncInput) -> List[C.Ct]:
-        """r_j = (X A)_{:, j} = sum_l A_jl x_l for the projection of the SNP batches."""
+        """r_j = (X A)_{:, j} = sum_l A_jl x_l for the projection of the SNP batches, from A and x brought to
+        the SNP depth - 2 first (r_j is used no higher than the SNP depth - 1), so that the products run on
+        the few limbs left there."""
         k = self.lay.k
-        return [self.o.mul_sum([(self.at(inp.a(j, l), 1), self.at(inp.x[l], 1)) for l in range(k)])
+        d = snp_depth(inp.kappa) - 2
+        return [self.o.mul_sum([(self.at(inp.a(j, l), d), self.at(inp.x[l], d)) for l in range(k)])
                 for j in range(k)]
 
     def _batches(self, inp: EncInput, fixed: FixedPart, beta, w, w_inv, z_proj, u) -> EncOutput:

@@ -241,9 +241,11 @@ void fixed_front(ckks_ctx &c, int R, int k, const std::vector<const ckks_ct *> &
                  EncOutput *rep = nullptr) {
     Stacked st(c, R, k, x, Ain, pre);
     const int J = st.J;
-    // ---- r_j = (X A)_{:, j}, and x_j at the depth the per-batch part uses it
+    // ---- r_j = (X A)_{:, j} from A and x brought to the SNP depth - 2 first (r_j is used no higher than
+    // the SNP depth - 1, so the products run on the few limbs left there), and x_j at the depth the
+    // per-batch part uses it
     std::vector<Ct> x1(k);
-    for (int l = 0; l < k; ++l) x1[l] = st.C.at(*x[l], 1);
+    for (int l = 0; l < k; ++l) x1[l] = st.C.at(*x[l], ds - 2);
     Ct RR = st.a_times(x1);
     if (xrep) {
         // M-materialised layout (Alg. CP-REP-MatMult of X A with the REP X^T, one column of M at a time):
@@ -271,7 +273,7 @@ void fixed_front(ckks_ctx &c, int R, int k, const std::vector<const ckks_ct *> &
         // take r_j at the SNP depth - 1 and x_j at the SNP depth + 1, so that Z_t lands at the SNP depth and
         // X_t at the SNP depth + 2 with their canonical scales; Z_t is then rotated right by t.  r_s and x_c
         // stay empty (the packed projection does not read them).
-        if (RR->depth >= ds - 1 || st.Xs.depth >= ds + 1) throw Error(CKKS_E_LEVEL, "diagonals too deep");
+        if (RR->depth > ds - 1 || st.Xs.depth >= ds + 1) throw Error(CKKS_E_LEVEL, "diagonals too deep");
         fx.K = K;
         Ct RRa = st.C.at(*RR, ds - 1), Xa = st.C.at(st.Xs, ds + 1);
         const std::vector<Ct> rj = st.parts(*RRa), xj = st.parts(*Xa);
