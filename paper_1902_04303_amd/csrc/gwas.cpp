@@ -11,8 +11,10 @@
 // with r_j = sum_l A_jl x_l, all SNP batches of a chunk in one batched ciphertext.
 #include <algorithm>
 #include <cmath>
+#include <memory>
 #include <mutex>
 #include <thread>
+#include <type_traits>
 
 #include "gwas.h"
 
@@ -550,6 +552,8 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
         stream_wait(c.aux_stream, c.stream);   // inputs, their stacking and this call's earlier work
         hipEvent_t w_ready;
         GCK_HIP(hipEventCreateWithFlags(&w_ready, hipEventDisableTiming));
+        const std::unique_ptr<std::remove_pointer<hipEvent_t>::type, hipError_t (*)(hipEvent_t)> w_ready_owner(
+            w_ready, hipEventDestroy);
         {
             OnStream on_aux(c);
             fixed_back(c, lay.R, k, in.kappa, x, *in.y, A, ds, fx, out, &sin, w_ready);
@@ -568,7 +572,6 @@ void run_circuit(ckks_ctx &c, const EncInput &in, EncOutput &out, int chunk) {
             sps.push_back(batch_front(c, lay.R, k, fx, *S));
         }
         if (in.kappa != 1) GCK_HIP(hipStreamWaitEvent(c.stream, w_ready, 0));   // w
-        (void)hipEventDestroy(w_ready);
         std::vector<BatchOut> bos(sps.size());
         for (size_t i = 0; i < sps.size(); ++i) {
             bos[i].sp = std::move(sps[i]);
