@@ -44,9 +44,10 @@ def same(a, b):
     return len(a) == len(b) and all(np.array_equal(x, y) for x, y in zip(a, b))
 
 
-def test_graph_replays_match_oracle_and_eager(torch_dev):
+@pytest.mark.parametrize("n", [30, 24])   # one colSum and broadcast per covariate; packed projection
+def test_graph_replays_match_oracle_and_eager(torch_dev, n):
     torch = torch_dev
-    n, k, m, kappa, log_n, b = 30, 4, 70, 3, 10, 30
+    k, m, kappa, log_n, b = 4, 70, 3, 10, 30
     say("[gpu] graph n=%d m=%d" % (n, m))
     p = C.make_params(log_n, G.circuit_depth(kappa), b)
     d = make_gwas_data(n, k, m, seed=config_seed(1, 5))
