@@ -222,7 +222,7 @@ def config5_leg(args):
     resident, jobs that arrive while others run share launches) against the one-job-at-a-time FIFO
     server on the same trace.  Two regimes: (a) 256 jobs with m scaled by 0.25, so that every job can be
     encrypted before the run (inputs resident) and the server is not saturated; (b) 64 jobs at full m,
-    whose inputs (about 110 GB encrypted) stay resident for the whole trace."""
+    whose encrypted inputs stay resident for the whole trace."""
     import torch
 
     import paper_1902_04303_amd as P
