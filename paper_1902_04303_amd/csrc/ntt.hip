@@ -496,8 +496,8 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
                     for (int j = 0; j < EG; ++j) {
                         const size_t w = base + slot_index<LOGM, 0, Ph<LOGM, 0>::R>(e0 + j, q);
                         vt[j] = sh[lds_addr<ROWS>(gi, slot_index<LOGM, 0, Ph<LOGM, 0>::R>(e0 + j, q), LOGM, log_g)];
-                        va[j] = xa[w];
-                        vd[j] = with_add ? xd[w] : 0;
+                        va[j] = __builtin_nontemporal_load(xa + w);   // read once: kept out of the caches
+                        vd[j] = with_add ? __builtin_nontemporal_load(xd + w) : 0;
                         vs[j] = aut_self ? xs[w] : 0;
 #pragma unroll
                         for (int i = 0; i < AU; ++i) vp[i][j] = i < n_aut ? xs[automorph_src(w, g.log_n, E.g[i])] : 0;
@@ -530,7 +530,7 @@ __global__ void __launch_bounds__((1 << (ROWS ? kLogTileRows : kLogTileCols)) / 
 #pragma unroll
                     for (int j = 0; j < EG; ++j) {
                         const size_t w = base + slot_index<LOGM, 0, Ph<LOGM, 0>::R>(e0 + j, q);
-                        a[w] = fcanon(r[j], fm);
+                        __builtin_nontemporal_store(fcanon(r[j], fm), a + w);
                     }
                 }
             } else {
