@@ -683,16 +683,21 @@ class Oracle:
     def set_scale(self, a: Ct, factor: float) -> Ct:
         return Ct(a.data, a.depth, a.scale * factor)
 
-    def mul_i(self, a: Ct, neg: bool = False) -> Ct:
-        """a times the monomial X^(N/2) (or -X^(N/2)), a plaintext product with no rounding: slot j is the
-        evaluation at zeta^(5^j) (zeta = exp(i pi / N)), where X^(N/2) takes the value zeta^(5^j N/2) = i
-        because 5^j = 1 mod 4, so every slot is multiplied by i (or -i).  Same depth and scale."""
+    def mul_gauss(self, a: Ct, re: int, im: int) -> Ct:
+        """a times the plaintext re + im X^(N/2), a product with no rounding: slot j is the evaluation at
+        zeta^(5^j) (zeta = exp(i pi / N)), where X^(N/2) takes the value zeta^(5^j N/2) = i because
+        5^j = 1 mod 4, so every slot is multiplied by the Gaussian integer re + im i.  Same depth and scale."""
         N = self.p.N
         pt = np.zeros(N, dtype=np.int64)
-        pt[N // 2] = -1 if neg else 1
+        pt[0] = re
+        pt[N // 2] = im
         out = np.empty_like(a.data)
         lib().ref_mul_plain(self._ctx, 2, a.limbs, _p(a.data), _p(pt), _p(out))
         return Ct(out, a.depth, a.scale)
+
+    def mul_i(self, a: Ct, neg: bool = False) -> Ct:
+        """a times X^(N/2) (or -X^(N/2)): every slot times i (or -i), exactly (see mul_gauss)."""
+        return self.mul_gauss(a, 0, -1 if neg else 1)
 
     def keyswitch(self, d: np.ndarray, K: int) -> np.ndarray:
         """Key switch of d ([l][N], coefficient form) with the key of id K (keyswitch_galois, no automorphism)."""

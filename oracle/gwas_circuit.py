@@ -402,27 +402,21 @@ class Circuit:
     def num_den(self, sp: C.Ct, fx: "FixedPart"):
         """numerator and both denominators of a projected batch S' (Alg. Semi Parallel GWAS).  With
         S' = a + i b per slot (the even SNP in a, the odd one in b) the denominators are sum w a^2 and
-        sum w b^2.  Both come from one rotate-and-sum of W = 4 w (a^2 + i b^2), formed from
-        P = 2 w S' conj(S') = 2 w (a^2 + b^2) and R = w S'^2 + conj(w S'^2) = 2 w (a^2 - b^2):
-        W = (P + R) + i (P - R), the factor i by mul_i; den_even = sum W / 4 and den_odd = -i sum W / 4,
-        whose real parts are the two denominators (reading 20)."""
+        sum w b^2.  Both come from one rotate-and-sum of W = 4 w (a^2 + i b^2) = w T with
+        T = (2 + 2i) S' conj(S') + (1 - i) (S'^2 + conj(S')^2) (one lazily summed product, the Gaussian
+        integer factors as exact products with re + im X^(N/2)); den_even = sum W / 4 and
+        den_odd = -i sum W / 4, whose real parts are the two denominators (reading 20)."""
         o = self.o
         dsp = sp.depth
         num = self.rot_sum(o.mul(self.at(fx.u, dsp), sp), BATCH_RADIX)
         sc = o.conjugate(sp)
+        t = o.mul_sum([(o.mul_gauss(sp, 2, 2), sc), (o.mul_gauss(sp, 1, -1), sp), (o.mul_gauss(sc, 1, -1), sc)])
         if fx.w is None:
-            # public w = 1/4: the products without w, the 1/4 in the tracked scale
-            ss = o.mul(sp, sp)
-            ssc = o.mul(sp, sc)
+            w4 = t                        # public w = 1/4, in the tracked scale
             factor = 4.0 / W_KAPPA1
         else:
-            ws = o.mul(self.at(fx.w, dsp), sp)
-            ss = o.mul(ws, self.at(sp, ws.depth))
-            ssc = o.mul(ws, self.at(sc, ws.depth))
+            w4 = o.mul(self.at(fx.w, t.depth), t)
             factor = 4.0
-        p2 = o.mul_int(ssc, 2)
-        r2 = o.add(ss, o.conjugate(ss))
-        w4 = o.add(o.add(p2, r2), o.mul_i(o.sub(p2, r2)))
         de = self.rot_sum(o.set_scale(w4, factor), BATCH_RADIX)
         do = o.mul_i(de, neg=True)
         return num, de, do

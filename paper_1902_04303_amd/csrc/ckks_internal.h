@@ -297,10 +297,6 @@ void k_add_rotated_plain(const DevTables &t, u64 *out, const u64 *a, const u64 *
                          hipStream_t st);
 void k_mul(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs, ModMap m, int na, int nb,
            hipStream_t st);
-// out = x * px + (y + z) * py with x, y, z of n_limbs rows and the plaintexts px, py of np rows, read at
-// row (row mod np)
-void k_mul_plain2(const DevTables &t, u64 *out, const u64 *x, const u64 *y, const u64 *z, const u64 *px,
-                  const u64 *py, int n_limbs, ModMap m, int np, hipStream_t st);
 // out = a * c[chain]
 void k_mul_const(const DevTables &t, u64 *out, const u64 *a, int n_limbs, ModMap m, const ChainConst &c,
                  hipStream_t st);

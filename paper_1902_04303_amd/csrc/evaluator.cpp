@@ -478,28 +478,16 @@ static const u64 *monomial_plain(ckks_ctx &c, int l, i64 a, i64 b) {
     return p;
 }
 
-Ct mul_i(ckks_ctx &c, const ckks_ct &a, bool neg) {
+Ct mul_gauss(ckks_ctx &c, const ckks_ct &a, i64 re, i64 im) {
     const int l = a.limbs;
-    const u64 *pt = monomial_plain(c, l, 0, neg ? -1 : 1);
+    const u64 *pt = monomial_plain(c, l, re, im);
     Ct r = new_ct(c, a.count, a.depth, a.scale);
     k_mul(c.tab, r->data.ptr, a.data.ptr, pt, a.count * 2 * l, map_q(l), a.count * 2 * l, l, c.stream);
     ++c.n_launch;
     return r;
 }
 
-Ct pack_den(ckks_ctx &c, const ckks_ct &p, const ckks_ct &s, const ckks_ct &t) {
-    check_same(p, s);
-    check_same(p, t);
-    if (p.count != s.count || p.count != t.count) throw Error(CKKS_E_PARAM_MISMATCH, "operands of unequal counts");
-    const int l = p.limbs;
-    const u64 *pa = monomial_plain(c, l, 2, 2);
-    const u64 *pb = monomial_plain(c, l, 1, -1);
-    Ct r = new_ct(c, p.count, p.depth, p.scale);
-    k_mul_plain2(c.tab, r->data.ptr, p.data.ptr, s.data.ptr, t.data.ptr, pa, pb, p.count * 2 * l, map_q(l), l,
-                 c.stream);
-    ++c.n_launch;
-    return r;
-}
+Ct mul_i(ckks_ctx &c, const ckks_ct &a, bool neg) { return mul_gauss(c, a, 0, neg ? -1 : 1); }
 
 Ct align(ckks_ctx &c, const ckks_ct &a, int depth, double scale, double factor) {
     if (depth == a.depth && scale == a.scale && factor == 1.0) return clone(c, a);

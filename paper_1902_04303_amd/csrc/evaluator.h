@@ -132,10 +132,10 @@ struct MaskTerm {
     int P, j0, j1;
 };
 Ct mask_sum(ckks_ctx &c, const std::vector<MaskTerm> &terms);
-// a times X^(N/2) (neg: -X^(N/2)): every slot times i (or -i), exact, same depth and scale
+// a times re + im X^(N/2): every slot times the Gaussian integer re + im i, exact, same depth and scale
+Ct mul_gauss(ckks_ctx &c, const ckks_ct &a, i64 re, i64 im);
+// a times X^(N/2) (neg: -X^(N/2)): every slot times i (or -i)
 Ct mul_i(ckks_ctx &c, const ckks_ct &a, bool neg);
-// (2 + 2i) p + (1 - i) (s + t) with the factors i as X^(N/2): exact, same depth and scale
-Ct pack_den(ckks_ctx &c, const ckks_ct &p, const ckks_ct &s, const ckks_ct &t);
 Ct align(ckks_ctx &c, const ckks_ct &a, int depth, double scale, double factor);
 Ct set_scale(ckks_ctx &c, Ct a, double factor);
 // sum_i a_i * b_i: one tensor per pair accumulated, one relinearisation, one rescale

@@ -348,7 +348,7 @@ void fixed_back(ckks_ctx &c, int R, int k, int kappa, const std::vector<const ck
     }
     // ---- w = p (1 - p), Alg. inverseSlots: guess 3, the first Newton step is 6 - 9 w
     Ct w = mul(c, *pk, *add_const(c, *neg(c, *pk), 1.0));
-    fx.w_s = C.at(*w, ds + 3);   // may be a view of w, which rep owns from here on
+    fx.w_s = C.at(*w, ds + 4);   // at the depth of the denominators' product T (may be a view of w)
     if (w_ready) GCK_HIP(hipEventRecord(w_ready, c.stream));
     Ct gi = add_const(c, *mul_int(c, *w, -9), 6.0);
     for (int it = 0; it < 2; ++it) {
@@ -466,23 +466,21 @@ void batch_den(ckks_ctx &c, int R, int k, const FixedOut &fx, BatchOut &o) {
     lay.k = k;
     Circ C(c, lay, kBatchRadix);
     // with S' = a + i b per slot (even SNP a, odd SNP b) both denominators come from one rotate-and-sum of
-    // W = 4 w (a^2 + i b^2) = (2 + 2i) w S' conj(S') + (1 - i) (w S'^2 + conj(w S'^2)); den_even = sum W / 4
-    // and den_odd = -i sum W / 4 have the two denominators as their real parts
+    // W = 4 w (a^2 + i b^2) = w T, T = (2 + 2i) S' conj(S') + (1 - i) (S'^2 + conj(S')^2) as one lazy
+    // product sum (the Gaussian integer factors exact, as products with re + im X^(N/2)); den_even =
+    // sum W / 4 and den_odd = -i sum W / 4 have the two denominators as their real parts
     Ct sc = conjugate(c, *o.sp);
-    Ct ss, ssc;
-    double f;
-    if (!fx.w_s) {
-        // kappa = 1, public w = 1/4: the products without w, the 1/4 in the tracked scale
-        ss = mul(c, *o.sp, *o.sp);
-        ssc = mul(c, *o.sp, *sc);
-        f = 4.0 / kWKappa1;
-    } else {
-        Ct ws = mul(c, *fx.w_s, *o.sp);
-        ss = mul(c, *ws, *C.at(*o.sp, ws->depth));
-        ssc = mul(c, *ws, *C.at(*sc, ws->depth));
+    Ct p22 = mul_gauss(c, *o.sp, 2, 2), p1s = mul_gauss(c, *o.sp, 1, -1), p1c = mul_gauss(c, *sc, 1, -1);
+    Ct t = mul_sum(c, {{p22.get(), sc.get()}, {p1s.get(), o.sp.get()}, {p1c.get(), sc.get()}});
+    p22.reset();
+    p1s.reset();
+    p1c.reset();
+    double f = 4.0 / kWKappa1;   // kappa = 1: public w = 1/4, in the tracked scale
+    if (fx.w_s) {
+        t = mul(c, *fx.w_s, *t);
         f = 4.0;
     }
-    o.de = C.rot_sum(set_scale(c, pack_den(c, *ssc, *ss, *conjugate(c, *ss)), f));
+    o.de = C.rot_sum(set_scale(c, std::move(t), f));
     o.dodd = mul_i(c, *o.de, true);
 }
 

@@ -63,7 +63,7 @@ struct FixedOut {
     int K = 0;             // width of the packed projection (0: one colSum and broadcast per covariate)
     std::vector<Ct> z_d;   // packed projection: Rot(Z_t, -t) at the SNP depth, t < K
     std::vector<Ct> x_d;   // packed projection: X_t at the SNP depth + 2, t < K
-    Ct u_s, w_s;           // u = w z' and w at the SNP depth + 3 (w_s empty when w is public: kappa = 1)
+    Ct u_s, w_s;           // u = w z' at the SNP depth + 3, w at + 4 (w_s empty when w is public: kappa = 1)
     std::vector<Ct> hold;  // batches that r_s and x_c may be views of
     Ct m_cols;             // M-materialised layout: Dup(M_i), i < n, at the SNP depth + 2
 };

@@ -155,30 +155,6 @@ void k_mul(const DevTables &t, u64 *out, const u64 *a, const u64 *b, int n_limbs
     check_launch();
 }
 
-__global__ void ew_mul_plain2(u64 *out, const u64 *x, const u64 *y, const u64 *z, const u64 *px, const u64 *py,
-                              size_t total, int log_n, ModMap mm, const ModInfo *mods, int np) {
-    const size_t n = (size_t)1 << log_n;
-    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
-        int lam = (int)(idx >> log_n);
-        size_t k = idx & (n - 1);
-        const ModInfo &M = mods[chain_of(lam, mm)];
-        const size_t pi = (size_t)(lam % np) * n + k;
-        const u64 a = mul_mod(x[idx], px[pi], M);
-        const u64 b = mul_mod(add_mod(y[idx], z[idx], M.q), py[pi], M);
-        out[idx] = add_mod(a, b, M.q);
-    }
-}
-
-void k_mul_plain2(const DevTables &t, u64 *out, const u64 *x, const u64 *y, const u64 *z, const u64 *px,
-                  const u64 *py, int n_limbs, ModMap m, int np, hipStream_t st) {
-    TScope ts_(t, "ew_mul_plain2", 32.0 * (double)n_limbs * t.n, st);
-    size_t total = (size_t)n_limbs << t.log_n;
-    if (!total) return;
-    gck_launch(ew_mul_plain2, ew_grid(total), dim3(kEwThreads), 0, st, out, x, y, z, px, py, total, t.log_n, m,
-               t.mods, np);
-    check_launch();
-}
-
 __global__ void ew_mul_const(u64 *out, const u64 *a, size_t total, int log_n, ModMap mm, const ModInfo *mods,
                              ChainConst c) {
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {

@@ -355,7 +355,7 @@ def test_rotation_conjugation_and_mult_semantics():
 def test_mul_i_is_the_exact_monomial_shift():
     """mul_i multiplies by X^(N/2): the decryption polynomial is shifted negacyclically by N/2 with no
     rounding, and every slot (the value at zeta^(5^j), zeta = exp(i pi / N)) is multiplied by i; with
-    neg by -i.  The packed denominators (2 + 2i) P + (1 - i) R then carry 4 w (a^2 + i b^2)."""
+    neg by -i.  The packed denominators' (2 + 2i) S conj(S) + (1 - i) (S^2 + conj(S)^2) is 4 (a^2 + i b^2)."""
     p = C.make_params(10, 2, 30)
     o = C.Oracle(p)
     o.keygen(3, [C.galois_conj(p.N)])
@@ -374,16 +374,17 @@ def test_mul_i_is_the_exact_monomial_shift():
         assert np.max(np.abs(o.decrypt(r) - unit * z)) < 1e-4
     # mul_i twice is the negation, bit for bit
     assert np.array_equal(o.mul_i(o.mul_i(ct)).data, o.neg(ct).data)
-    # the packing of two real squares into one complex slot
+    # Gaussian-integer factors: (2 + 2i) and (1 - i) per slot, exactly (2 + 2X^(N/2), 1 - X^(N/2))
+    assert np.max(np.abs(o.decrypt(o.mul_gauss(ct, 2, 2)) - (2 + 2j) * z)) < 1e-3
+    assert np.array_equal(o.mul_gauss(ct, 1, -1).data, o.sub(ct, o.mul_i(ct)).data)
+    # the packing of two real squares into one complex slot:
+    # (2 + 2i) S conj(S) + (1 - i) (S^2 + conj(S)^2) = 4 (a^2 + i b^2) for S = a + i b
     a = rng.uniform(-1, 1, p.slots)
     b = rng.uniform(-1, 1, p.slots)
     cs = o.encrypt(C.encode(a + 1j * b, p.N, p.scales[0]), 0, p.scales[0], 5)
-    ss = o.mul(cs, cs)
-    ssc = o.mul(cs, o.conjugate(cs))
-    p2 = o.mul_int(ssc, 2)
-    r2 = o.add(ss, o.conjugate(ss))
-    w4 = o.add(o.add(p2, r2), o.mul_i(o.sub(p2, r2)))
-    assert np.max(np.abs(o.decrypt(w4) - 4 * (a * a + 1j * b * b))) < 1e-3
+    cc = o.conjugate(cs)
+    t = o.mul_sum([(o.mul_gauss(cs, 2, 2), cc), (o.mul_gauss(cs, 1, -1), cs), (o.mul_gauss(cc, 1, -1), cc)])
+    assert np.max(np.abs(o.decrypt(t) - 4 * (a * a + 1j * b * b))) < 1e-3
 
 
 # ------------------------------------------------------------------ values printed in the paper
